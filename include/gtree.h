@@ -1,0 +1,179 @@
+/*
+ * gtree.h -- C ABI of the MI355X batched B+-tree library (libgtree.so).
+ *
+ * The library keeps a B+-tree (paper Section III: order m, data only in the
+ * leaves, leaves linked left to right) resident in device memory and runs
+ * batches of operations on it with hand-written gfx950 kernels:
+ *
+ *   tree_build         bulk load from (key, value) pairs      (Section V-B: the
+ *                      one-time build and transfer of the tree)
+ *   tree_lookup_batch  root-to-leaf search of a key batch     (Section IV-A,
+ *                      IV-E, IV-F: batch search, "key <= node entry" routing,
+ *                      -1 for a key that is not found)
+ *   tree_insert_batch  sort / merge / split insert of a batch with parent
+ *                      split propagation (keeps the Section III invariants)
+ *   tree_range_batch   range scans over the linked leaves (Section III)
+ *
+ * Conventions shared by every call:
+ *  - Pointers are DEVICE pointers unless the comment says "host".
+ *  - Keys and values have the same width, key_bytes = 4 or 8; keys compare
+ *    as unsigned integers.  A NOT-FOUND value is all ones at that width (the
+ *    paper's -1) and the matching found flag is 0; the flag is authoritative
+ *    because all ones is also a legal value.
+ *  - Every call is asynchronous on `stream`.  Errors that the host can see
+ *    (null pointers, bad sizes, a batch above the tree's max_batch, an arena
+ *    that is too small) are returned synchronously and nothing is enqueued.
+ *    Errors found on the device set bits of the tree's device error word;
+ *    tree_device_error() synchronises the stream and reports them.
+ *  - Results are written in caller order.  B = 0 is a no-op returning GT_OK.
+ *  - Calls that modify a tree must be ordered on one stream by the caller;
+ *    reads may run on several streams only while no write is in flight.
+ *
+ * Ownership: the caller owns every input and output buffer and the arena.
+ * The library places all tree state (header, node pools, a copy of the top
+ * tree levels, per-batch scratch) inside the arena and allocates no device
+ * memory on the lookup, range or insert paths.  tree_build alone allocates
+ * temporary sort buffers, released before it returns.  The arena must stay
+ * allocated until tree_destroy.
+ */
+#ifndef GTREE_H
+#define GTREE_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gt_tree gt_tree; /* opaque handle, host memory */
+
+typedef enum {
+    GT_OK = 0,
+    GT_ERR_INVALID = 1,   /* bad argument                                     */
+    GT_ERR_DUPLICATE = 2, /* tree_build input holds a key twice               */
+    GT_ERR_CAPACITY = 3,  /* arena or node pool too small for the request     */
+    GT_ERR_ADMISSION = 4, /* serving runtime refused a request                */
+    GT_ERR_HIP = 5,       /* a HIP runtime call failed                        */
+    GT_ERR_DEVICE = 6     /* device error word set (other than capacity)      */
+} gt_status;
+
+/* Tree parameters (host struct).  Zero fields take the default. */
+typedef struct {
+    uint32_t key_bytes;       /* 4 or 8 (no default)                          */
+    uint32_t fanout;          /* inner order m; only 16 is supported          */
+    uint32_t leaf_cap;        /* keys per leaf; only 16 is supported          */
+    float fill;               /* bulk-load fill in [0.5, 1]; default 1.0      */
+    uint32_t lanes_per_query; /* lookup lanes per query: 4, 8 or 16 (def. 8)  */
+    uint32_t lds_levels;      /* top inner levels read from an LDS copy: 1..3,
+                                 4 = none; 0 = default (2)                    */
+    uint32_t sorted_mode;     /* reserved, must be 0                          */
+    uint32_t queries_per_group; /* queries a lane group walks at once: 1, 2
+                                   or 4; 0 = default (2)                      */
+    uint64_t max_batch;       /* largest insert batch; default 2^20           */
+} gt_params;
+
+typedef struct {
+    uint64_t n_keys;
+    uint32_t height;          /* levels including the leaf level              */
+    uint32_t root;            /* node reference of the root                   */
+    uint64_t inner_used, inner_cap;
+    uint64_t leaf_used, leaf_cap;
+    uint64_t arena_bytes;     /* bytes of the arena the tree uses             */
+    uint64_t max_batch;
+    uint32_t error_word;      /* device error bits (see GT_DEVERR_*)          */
+    uint32_t key_bytes;
+} gt_tree_stats;
+
+/* device error word bits */
+#define GT_DEVERR_CAPACITY 0x1u  /* an insert batch did not fit; it was not applied */
+#define GT_DEVERR_INTERNAL 0x2u  /* an internal consistency check failed          */
+
+/* Bytes of arena needed for n keys plus `leaf_slack` extra leaves of
+ * headroom for inserts, with the given params (host).  Returns 0 for bad
+ * params. */
+uint64_t tree_arena_bytes(const gt_params* p /*host*/, uint64_t n, uint64_t leaf_slack);
+
+/*
+ * Bulk load (Section V-B's one-time build, done on the device).
+ * keys[n], values[n]: any order; duplicate keys give GT_ERR_DUPLICATE.
+ * Leaves are filled evenly to `fill` (at least half full when there are two
+ * or more), inner levels are built bottom-up with the same rule, and the
+ * leaves are chained in key order.  n = 0 builds an empty tree.
+ * This call synchronises `stream` before it returns.  On success *out
+ * receives a new handle.
+ */
+gt_status tree_build(const gt_params* p /*host*/, const void* keys, const void* values, uint64_t n,
+                     void* arena, uint64_t arena_bytes, hipStream_t stream, gt_tree** out /*host*/);
+
+/*
+ * Lookup batch (Sections IV-A to IV-F).  For each i < B: if keys[i] is in
+ * the tree, values_out[i] = its value and found_out[i] = 1; otherwise
+ * values_out[i] = all ones and found_out[i] = 0.  keys: B entries of
+ * key_bytes; values_out: B entries of key_bytes; found_out: B bytes.
+ */
+gt_status tree_lookup_batch(gt_tree* t, const void* keys, uint64_t B, void* values_out,
+                            uint8_t* found_out, hipStream_t stream);
+
+/*
+ * Insert batch.  Equivalent to inserting (keys[i], values[i]) one at a time
+ * for i = 0..B-1: a present key gets its value overwritten.  status_out[i]
+ * = 0 (INSERTED) when keys[i] was absent before the batch and not earlier in
+ * the batch, else 1 (UPDATED).  Leaves that overflow split evenly into
+ * ceil(t/16) leaves, inner nodes that overflow split the same way, and the
+ * root grows when it splits; every node but the root stays at least half
+ * full (Section III).  B <= max_batch.  The batch is applied whole or not
+ * at all: if the node pools cannot hold it, the device error word gets
+ * GT_DEVERR_CAPACITY, the tree is left unchanged and status_out is
+ * unspecified.
+ */
+gt_status tree_insert_batch(gt_tree* t, const void* keys, const void* values, uint64_t B,
+                            uint8_t* status_out, hipStream_t stream);
+
+/*
+ * Range batch over the linked leaves (Section III).  For each i < B, the
+ * pairs with lo[i] <= key <= hi[i], ascending, cut to the first max_out[i],
+ * are written to out_keys/out_values starting at out_offsets[i];
+ * count_out[i] receives how many.  The caller sizes the outputs so that
+ * out_offsets[i] + max_out[i] entries fit.  lo > hi yields no pairs.
+ * lo, hi: B keys; max_out: B u32; out_offsets: B u64.
+ */
+gt_status tree_range_batch(gt_tree* t, const void* lo, const void* hi, const uint32_t* max_out,
+                           const uint64_t* out_offsets, uint64_t B, void* out_keys,
+                           void* out_values, uint32_t* count_out, hipStream_t stream);
+
+/* Release the handle (host memory only; the arena stays the caller's). */
+gt_status tree_destroy(gt_tree* t);
+
+/* Synchronise `stream` and fill *out (host) from the device header. */
+gt_status tree_stats(gt_tree* t, gt_tree_stats* out /*host*/, hipStream_t stream);
+
+/*
+ * Synchronise `stream`, read and clear the device error word.  Returns
+ * GT_OK, GT_ERR_CAPACITY (an insert batch was refused) or GT_ERR_DEVICE.
+ */
+gt_status tree_device_error(gt_tree* t, hipStream_t stream);
+
+/*
+ * Copy the tree into host memory in the flat export format (synchronises):
+ *   header, 48 bytes little endian:
+ *     u32 magic 0x58455447, key_bytes, fanout, leaf_cap, height, root,
+ *     first_leaf, n_inner, n_leaves, reserved;  u64 n_keys
+ *   n_inner inner records:  key[16] (key_bytes each), child[16] (u32)
+ *   n_leaves leaf records:  key[16], value[16] (key_bytes each),
+ *                           u32 count, u32 next
+ * A node reference with bit 31 set is a leaf (index in the low bits),
+ * otherwise an inner node index; 0xFFFFFFFF is "none".  Inner entry i < c-1
+ * is the largest key below child i; entries from c-1 on hold the largest
+ * key and child slots from c on hold "none".  Leaf key slots from count on
+ * repeat the last key (the largest key in an empty leaf).
+ * With host_buf = NULL, *bytes (host) receives the size needed.
+ */
+gt_status tree_export(gt_tree* t, void* host_buf, uint64_t* bytes /*host*/, hipStream_t stream);
+
+const char* gt_status_str(gt_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GTREE_H */

@@ -1,0 +1,25 @@
+// Insert path (sort, merge, split, parent-split propagation).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "common.h"
+#include "kernels.h"
+
+namespace gt {
+
+struct InsertCtx {
+    uint8_t* scratch;
+    uint64_t scratch_bytes;
+    uint64_t max_batch;
+    uint64_t inner_cap, leaf_cap;
+    LaunchCfg cfg;
+};
+
+// Arena scratch bytes the insert path needs for batches up to max_batch.
+uint64_t insert_scratch_bytes(uint64_t max_batch, int key_bytes);
+
+template <class K>
+void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, const K* vals, uint64_t B,
+                   uint8_t* status, hipStream_t s);
+
+}  // namespace gt

@@ -1,0 +1,40 @@
+// Internal launch functions of the library (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "common.h"
+
+namespace gt {
+
+struct LaunchCfg {
+    int lanes;              // lanes per query: 4, 8, 16
+    int queries_per_group;  // queries interleaved per lane group: 1, 2, 4
+    int lds_levels;         // top inner levels read from LDS: 0..3
+};
+
+template <class K>
+void launch_lookup(const TreeView<K>& t, const LaunchCfg& cfg, const K* q, uint64_t B, K* vout, uint8_t* fout,
+                   hipStream_t s);
+
+template <class K>
+void launch_range(const TreeView<K>& t, const LaunchCfg& cfg, const K* lo, const K* hi, const uint32_t* mx,
+                  const uint64_t* off, uint64_t B, K* ok, K* ov, uint32_t* cnt, hipStream_t s);
+
+// Bulk build from sorted distinct keys (sk, sv): writes leaves, inner levels,
+// header and mirror.  level_sizes[0] = leaves, level_sizes[i] = nodes of the
+// i-th inner level above the leaves; `levels` entries, the last being 1.
+// maxbuf needs room for max(level_sizes) keys, twice.
+template <class K>
+void launch_build(const TreeView<K>& t, const K* sk, const K* sv, uint64_t n, const uint64_t* level_sizes,
+                  int levels, K* maxbuf, hipStream_t s);
+
+template <class K>
+void launch_gather(const K* src, const uint32_t* idx, K* dst, uint64_t n, hipStream_t s);
+
+template <class K>
+void launch_dup_check(const K* sk, uint64_t n, uint32_t* flag, hipStream_t s);
+
+template <class K>
+void launch_mirror_refresh(const TreeView<K>& t, hipStream_t s);
+
+}  // namespace gt

@@ -1,0 +1,263 @@
+// Lookup and range batches.
+//
+// Lookup (paper Sections IV-A, IV-E, IV-F): every query descends from the
+// root with a group of G lanes (see traverse.h), the top inner levels read
+// from the LDS copy of the mirror, the rest from HBM; at the leaf an
+// equality ballot over the key line gives the slot, and one lane reads the
+// value.  A key that is not found returns all ones with found = 0 (the
+// paper's -1 result, Section IV-D).  Results go to the caller's order.
+//
+// Range (spec addition over the linked leaves of Section III): the
+// group descends to the leaf of `lo`, then walks the leaf chain; per leaf a
+// ballot marks the slots with lo <= key <= hi and the group writes them in
+// slot order at out[offset + running count], until `max` pairs are written,
+// a key above `hi` is seen or the chain ends.
+//
+// Both kernels are persistent: a grid of at most a few thousand
+// workgroups walks tiles of queries, so the mirror is staged once per
+// workgroup.
+#include "common.h"
+#include "traverse.h"
+#include "kernels.h"
+
+namespace gt {
+
+constexpr int kLookupBlock = 256;
+
+template <class K, int G, int QPG, int LV>
+__global__ __launch_bounds__(kLookupBlock) void k_lookup(TreeView<K> t, const K* __restrict__ q, uint64_t B,
+                                                          K* __restrict__ vout, uint8_t* __restrict__ fout,
+                                                          uint64_t ntiles) {
+    using T = Trav<K, G>;
+    extern __shared__ __align__(16) uint8_t lds[];
+    const uint8_t* mir = t.mirror;
+    uint32_t mnodes = kMirrorMaxNodes;
+    if constexpr (LV > 0) {
+        mnodes = mirror_nodes_for_levels(LV);
+        stage_mirror<K>(t.mirror, lds, mnodes);
+        __syncthreads();
+        mir = lds;
+    }
+    const MirrorHeader* mh = reinterpret_cast<const MirrorHeader*>(mir);
+    const bool empty = mh->n_keys == 0;
+    const int lane = lane_id();
+    const int gl = lane % G, gbase = lane - gl;
+    const uint64_t group = threadIdx.x / G;
+    const uint64_t tile_q = static_cast<uint64_t>(kLookupBlock / G) * QPG;
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        K key[QPG];
+        uint64_t qi[QPG];
+#pragma unroll
+        for (int j = 0; j < QPG; ++j) {
+            qi[j] = tile * tile_q + group * QPG + j;
+            key[j] = qi[j] < B ? q[qi[j]] : K(0);
+        }
+        uint32_t leaf[QPG];
+        descend<K, G, QPG, false>(t, mir, mnodes, LV, key, leaf, gl, gbase);
+        typename T::KV kv[QPG];
+#pragma unroll
+        for (int j = 0; j < QPG; ++j) kv[j] = T::load_keys(t.lkeys + static_cast<uint64_t>(leaf[j]) * kSlots, gl);
+        uint32_t slot[QPG];
+#pragma unroll
+        for (int j = 0; j < QPG; ++j) slot[j] = T::match_slot(kv[j], key[j], gbase);
+        K val[QPG];
+        bool hit[QPG];
+#pragma unroll
+        for (int j = 0; j < QPG; ++j) {
+            hit[j] = slot[j] < kSlots && !empty;
+            val[j] = kmax<K>();
+            if (gl == (j % G) && qi[j] < B && hit[j]) val[j] = t.lvals[static_cast<uint64_t>(leaf[j]) * kSlots + slot[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < QPG; ++j) {
+            if (gl == (j % G) && qi[j] < B) {
+                vout[qi[j]] = val[j];
+                fout[qi[j]] = hit[j] ? 1 : 0;
+            }
+        }
+    }
+}
+
+template <class K, int G, int LV>
+__global__ __launch_bounds__(kLookupBlock) void k_range(TreeView<K> t, const K* __restrict__ lo,
+                                                         const K* __restrict__ hi,
+                                                         const uint32_t* __restrict__ maxc,
+                                                         const uint64_t* __restrict__ off, uint64_t B,
+                                                         K* __restrict__ okeys, K* __restrict__ ovals,
+                                                         uint32_t* __restrict__ cnt_out, uint64_t ntiles) {
+    using T = Trav<K, G>;
+    constexpr int KPL = T::KPL;
+    extern __shared__ __align__(16) uint8_t lds[];
+    const uint8_t* mir = t.mirror;
+    uint32_t mnodes = kMirrorMaxNodes;
+    if constexpr (LV > 0) {
+        mnodes = mirror_nodes_for_levels(LV);
+        stage_mirror<K>(t.mirror, lds, mnodes);
+        __syncthreads();
+        mir = lds;
+    }
+    const MirrorHeader* mh = reinterpret_cast<const MirrorHeader*>(mir);
+    const bool empty = mh->n_keys == 0;
+    const int lane = lane_id();
+    const int gl = lane % G, gbase = lane - gl;
+    const uint64_t below_lanes = (1ull << gl) - 1ull;
+    const uint64_t group = threadIdx.x / G;
+    const uint64_t tile_q = kLookupBlock / G;
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t qi = tile * tile_q + group;
+        const bool live = qi < B;
+        K key[1] = {live ? lo[qi] : K(0)};
+        const K h = live ? hi[qi] : K(0);
+        const uint32_t mx = live ? maxc[qi] : 0u;
+        const uint64_t base = live ? off[qi] : 0ull;
+        uint32_t leaf[1];
+        descend<K, G, 1, false>(t, mir, mnodes, LV, key, leaf, gl, gbase);
+        uint32_t c = 0;
+        bool done = !live || empty || mx == 0 || key[0] > h;
+        uint32_t cur = leaf[0];
+        while (!done) {
+            typename T::KV kv = T::load_keys(t.lkeys + static_cast<uint64_t>(cur) * kSlots, gl);
+            typename T::KV vv = T::load_keys(t.lvals + static_cast<uint64_t>(cur) * kSlots, gl);
+            const uint2 meta = t.lmeta[cur];
+            bool ok[KPL];
+            uint32_t within = 0, lanes_below = 0, total = 0;
+            bool beyond = false;
+            uint32_t pre[KPL];
+#pragma unroll
+            for (int e = 0; e < KPL; ++e) {
+                const uint32_t slot = static_cast<uint32_t>(gl * KPL + e);
+                const bool inl = slot < meta.x;
+                ok[e] = inl && kv.v[e] >= key[0] && kv.v[e] <= h;
+                const uint64_t bits = group_bits<G>(__ballot(ok[e]), gbase);
+                const uint64_t over = group_bits<G>(__ballot(inl && kv.v[e] > h), gbase);
+                beyond = beyond || over != 0;
+                lanes_below += static_cast<uint32_t>(__popcll(bits & below_lanes));
+                total += static_cast<uint32_t>(__popcll(bits));
+                pre[e] = within;
+                within += ok[e] ? 1u : 0u;
+            }
+#pragma unroll
+            for (int e = 0; e < KPL; ++e) {
+                if (ok[e]) {
+                    const uint32_t p = c + lanes_below + pre[e];
+                    if (p < mx) {
+                        okeys[base + p] = kv.v[e];
+                        ovals[base + p] = vv.v[e];
+                    }
+                }
+            }
+            c += total;
+            done = c >= mx || beyond || meta.y == kNone || meta.x == 0;
+            cur = meta.y;
+        }
+        if (live && gl == 0) cnt_out[qi] = c < mx ? c : mx;
+    }
+}
+
+// ---------------------------------------------------------------- launch
+
+static uint32_t lds_bytes_for(int lv, int key_bytes) {
+    if (lv <= 0) return 0;
+    uint32_t n = mirror_nodes_for_levels(lv);
+    return key_bytes == 8 ? MirrorLayout<uint64_t>::bytes(n) : MirrorLayout<uint32_t>::bytes(n);
+}
+
+static uint64_t grid_for(uint64_t ntiles, int lv, int key_bytes) {
+    // resident workgroups: 8 per CU when the mirror copy is small, fewer
+    // when it takes a large share of the 160 KiB of LDS per CU
+    uint32_t lds = lds_bytes_for(lv, key_bytes);
+    uint64_t per_cu = 8;
+    if (lds > 0) {
+        uint64_t fit = (160u * 1024u) / lds;
+        if (fit < per_cu) per_cu = fit < 1 ? 1 : fit;
+    }
+    uint64_t cap = 256 * per_cu;
+    return ntiles < cap ? (ntiles < 1 ? 1 : ntiles) : cap;
+}
+
+template <class K, int G, int QPG, int LV>
+static void launch_lookup_t(const TreeView<K>& t, const K* q, uint64_t B, K* vout, uint8_t* fout, hipStream_t s) {
+    const uint64_t tile_q = static_cast<uint64_t>(kLookupBlock / G) * QPG;
+    const uint64_t ntiles = (B + tile_q - 1) / tile_q;
+    const uint64_t grid = grid_for(ntiles, LV, sizeof(K));
+    hipLaunchKernelGGL((k_lookup<K, G, QPG, LV>), dim3(static_cast<uint32_t>(grid)), dim3(kLookupBlock),
+                       lds_bytes_for(LV, sizeof(K)), s, t, q, B, vout, fout, ntiles);
+}
+
+template <class K, int G, int QPG>
+static void launch_lookup_lv(const TreeView<K>& t, int lv, const K* q, uint64_t B, K* vout, uint8_t* fout,
+                             hipStream_t s) {
+    switch (lv) {
+        case 0: launch_lookup_t<K, G, QPG, 0>(t, q, B, vout, fout, s); break;
+        case 1: launch_lookup_t<K, G, QPG, 1>(t, q, B, vout, fout, s); break;
+        case 2: launch_lookup_t<K, G, QPG, 2>(t, q, B, vout, fout, s); break;
+        default: launch_lookup_t<K, G, QPG, 3>(t, q, B, vout, fout, s); break;
+    }
+}
+
+template <class K>
+void launch_lookup(const TreeView<K>& t, const LaunchCfg& cfg, const K* q, uint64_t B, K* vout, uint8_t* fout,
+                   hipStream_t s) {
+    const int qpg = cfg.queries_per_group;
+    switch (cfg.lanes) {
+        case 4:
+            if (qpg >= 4) launch_lookup_lv<K, 4, 4>(t, cfg.lds_levels, q, B, vout, fout, s);
+            else if (qpg == 2) launch_lookup_lv<K, 4, 2>(t, cfg.lds_levels, q, B, vout, fout, s);
+            else launch_lookup_lv<K, 4, 1>(t, cfg.lds_levels, q, B, vout, fout, s);
+            break;
+        case 16:
+            if (qpg >= 4) launch_lookup_lv<K, 16, 4>(t, cfg.lds_levels, q, B, vout, fout, s);
+            else if (qpg == 2) launch_lookup_lv<K, 16, 2>(t, cfg.lds_levels, q, B, vout, fout, s);
+            else launch_lookup_lv<K, 16, 1>(t, cfg.lds_levels, q, B, vout, fout, s);
+            break;
+        default:
+            if (qpg >= 4) launch_lookup_lv<K, 8, 4>(t, cfg.lds_levels, q, B, vout, fout, s);
+            else if (qpg == 2) launch_lookup_lv<K, 8, 2>(t, cfg.lds_levels, q, B, vout, fout, s);
+            else launch_lookup_lv<K, 8, 1>(t, cfg.lds_levels, q, B, vout, fout, s);
+            break;
+    }
+}
+
+template <class K, int G, int LV>
+static void launch_range_t(const TreeView<K>& t, const K* lo, const K* hi, const uint32_t* mx, const uint64_t* off,
+                           uint64_t B, K* ok, K* ov, uint32_t* cnt, hipStream_t s) {
+    const uint64_t tile_q = kLookupBlock / G;
+    const uint64_t ntiles = (B + tile_q - 1) / tile_q;
+    const uint64_t grid = grid_for(ntiles, LV, sizeof(K));
+    hipLaunchKernelGGL((k_range<K, G, LV>), dim3(static_cast<uint32_t>(grid)), dim3(kLookupBlock),
+                       lds_bytes_for(LV, sizeof(K)), s, t, lo, hi, mx, off, B, ok, ov, cnt, ntiles);
+}
+
+template <class K, int G>
+static void launch_range_lv(const TreeView<K>& t, int lv, const K* lo, const K* hi, const uint32_t* mx,
+                            const uint64_t* off, uint64_t B, K* ok, K* ov, uint32_t* cnt, hipStream_t s) {
+    switch (lv) {
+        case 0: launch_range_t<K, G, 0>(t, lo, hi, mx, off, B, ok, ov, cnt, s); break;
+        case 1: launch_range_t<K, G, 1>(t, lo, hi, mx, off, B, ok, ov, cnt, s); break;
+        case 2: launch_range_t<K, G, 2>(t, lo, hi, mx, off, B, ok, ov, cnt, s); break;
+        default: launch_range_t<K, G, 3>(t, lo, hi, mx, off, B, ok, ov, cnt, s); break;
+    }
+}
+
+template <class K>
+void launch_range(const TreeView<K>& t, const LaunchCfg& cfg, const K* lo, const K* hi, const uint32_t* mx,
+                  const uint64_t* off, uint64_t B, K* ok, K* ov, uint32_t* cnt, hipStream_t s) {
+    switch (cfg.lanes) {
+        case 4: launch_range_lv<K, 4>(t, cfg.lds_levels, lo, hi, mx, off, B, ok, ov, cnt, s); break;
+        case 16: launch_range_lv<K, 16>(t, cfg.lds_levels, lo, hi, mx, off, B, ok, ov, cnt, s); break;
+        default: launch_range_lv<K, 8>(t, cfg.lds_levels, lo, hi, mx, off, B, ok, ov, cnt, s); break;
+    }
+}
+
+template void launch_lookup<uint32_t>(const TreeView<uint32_t>&, const LaunchCfg&, const uint32_t*, uint64_t,
+                                      uint32_t*, uint8_t*, hipStream_t);
+template void launch_lookup<uint64_t>(const TreeView<uint64_t>&, const LaunchCfg&, const uint64_t*, uint64_t,
+                                      uint64_t*, uint8_t*, hipStream_t);
+template void launch_range<uint32_t>(const TreeView<uint32_t>&, const LaunchCfg&, const uint32_t*,
+                                     const uint32_t*, const uint32_t*, const uint64_t*, uint64_t, uint32_t*,
+                                     uint32_t*, uint32_t*, hipStream_t);
+template void launch_range<uint64_t>(const TreeView<uint64_t>&, const LaunchCfg&, const uint64_t*,
+                                     const uint64_t*, const uint32_t*, const uint64_t*, uint64_t, uint64_t*,
+                                     uint64_t*, uint32_t*, hipStream_t);
+
+}  // namespace gt

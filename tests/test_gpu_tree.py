@@ -1,0 +1,103 @@
+"""GPU parity of build, lookup and range against the oracle (bit-exact),
+through the C ABI.  Tree shapes span one leaf, ragged leaf/inner tails,
+several tiles of queries, both key widths and every launch configuration."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import mk_tree, assert_lookup_parity, assert_export_parity, assert_range_parity, key_set
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _dev():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2604_21117_amd as g
+    g.lib()
+
+
+@pytest.mark.parametrize("width", [32, 64])
+@pytest.mark.parametrize("n", [0, 1, 2, 15, 16, 17, 255, 256, 257, 4109, 65536])
+def test_build_lookup_sizes(width, n):
+    seed = 100 + n
+    keys = key_set(n, width, seed, edges=(n % 2 == 1))
+    vals = synth.values_for(keys, seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, width // 8, max_batch=4096)
+    st = t.stats()
+    assert st["n_keys"] == n
+    assert_export_parity(t, sa)
+    B = 1000
+    q = np.concatenate([synth.present_queries(keys, B // 2, seed) if n else np.zeros(0, keys.dtype),
+                        synth.absent_queries(keys, B // 2, seed, width),
+                        np.array([0, np.iinfo(keys.dtype).max, 1], dtype=keys.dtype)])
+    q = synth.shuffle(q, seed)
+    assert_lookup_parity(t, sa, q)
+
+
+def test_c1_closed_form_node_count():
+    """2^16 keys at fill 1.0: 4096 leaves, 273 inner nodes, height 4
+    (Section III: sum_{i<h} 16^i = 4369 nodes)."""
+    keys = synth.uniform_keys(1 << 16, 1, 32)
+    vals = synth.values_for(keys, 1, 32)
+    t = mk_tree(keys, vals, 4, max_batch=4096)
+    st = t.stats()
+    assert st["height"] == 4 and st["leaf_used"] == 4096 and st["inner_used"] == 273
+
+
+@pytest.mark.parametrize("lanes", [4, 8, 16])
+@pytest.mark.parametrize("qpg", [1, 2, 4])
+@pytest.mark.parametrize("lds", [1, 2, 3, 4])
+def test_launch_configs_agree(lanes, qpg, lds):
+    width, seed = 64, 7
+    keys = key_set(70000, width, seed, edges=True)
+    vals = synth.values_for(keys, seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, 8, max_batch=4096, lanes_per_query=lanes, queries_per_group=qpg, lds_levels=lds)
+    q = synth.mixed_queries(keys, 5003, seed, width)
+    q[:2] = [0, np.iinfo(np.uint64).max]
+    assert_lookup_parity(t, sa, q)
+    lo, hi, mc = synth.range_starts_and_lengths(keys, 777, seed, 60)
+    hi = np.minimum(lo.astype(np.uint64) + np.uint64(1 << 52), np.iinfo(np.uint64).max).astype(np.uint64)
+    assert_range_parity(t, sa, lo, hi, mc)
+
+
+@pytest.mark.parametrize("width", [32, 64])
+def test_range_edge_cases(width):
+    seed = 9
+    keys = key_set(3000, width, seed, edges=True)
+    vals = synth.values_for(keys, seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, width // 8, max_batch=4096)
+    top = np.iinfo(keys.dtype).max
+    sk = np.sort(keys)
+    lo = np.array([0, 0, top, sk[5], sk[100], sk[100], 7, sk[-1], sk[50] + 1], dtype=keys.dtype)
+    hi = np.array([top, 0, top, sk[5], sk[99], sk[400], 6, top, sk[60]], dtype=keys.dtype)
+    mc = np.array([100, 3, 3, 1, 10, 500, 4, 2, 0], dtype=np.uint32)
+    assert_range_parity(t, sa, lo, hi, mc)
+    lo2, hi2, mc2 = synth.range_starts_and_lengths(keys, 4000, seed, 100)
+    assert_range_parity(t, sa, lo2, hi2, mc2)
+
+
+def test_duplicate_build_keys_rejected():
+    import paper_2604_21117_amd as g
+    keys = np.array([5, 9, 5, 11], dtype=np.uint64)
+    with pytest.raises(g.GtError) as e:
+        mk_tree(keys, keys, 8, max_batch=1024)
+    assert e.value.status == g.GT_ERR_DUPLICATE
+
+
+def test_duplicate_queries_and_all_present():
+    width, seed = 64, 11
+    keys = key_set(50000, width, seed)
+    vals = synth.values_for(keys, seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, 8, max_batch=4096)
+    q = np.repeat(keys[:100], 7)
+    assert_lookup_parity(t, sa, q)
+    assert_lookup_parity(t, sa, keys)          # every key once
+    gv, gf = t.lookup(keys)
+    assert gf.all() and np.array_equal(gv, synth.values_for(keys, seed, width))
