@@ -15,8 +15,9 @@ struct InsertCtx {
     LaunchCfg cfg;
 };
 
-// Arena scratch bytes the insert path needs for batches up to max_batch.
-uint64_t insert_scratch_bytes(uint64_t max_batch, int key_bytes);
+// Arena scratch bytes the insert path needs for batches up to max_batch on
+// node pools of the given capacities.
+uint64_t insert_scratch_bytes(uint64_t max_batch, int key_bytes, uint64_t leaf_cap, uint64_t inner_cap);
 
 template <class K>
 void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, const K* vals, uint64_t B,

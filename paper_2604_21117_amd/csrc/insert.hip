@@ -1,17 +1,705 @@
-// Insert path: placeholder until the sort-merge-split kernels land.
+// Insert batches: sort, deduplicate, locate, plan, check, apply.
+//
+// The paper searches a static tree (Section V-A); inserts are the dynamic
+// counterpart that keeps Section III's invariants: sorted leaves, equal
+// leaf depth, every non-root node at least half full.  The batch behaves
+// like inserting its pairs one at a time in batch order: a present key is
+// overwritten, and the last occurrence of a key in the batch supplies its
+// value.
+//
+//  1. Sort (key, batch index) stably; run heads are the distinct keys; the
+//     last element of each run holds the final value.  Every non-head is
+//     UPDATED.
+//  2. Locate: each distinct key descends the tree (the lookup traversal of
+//     traverse.h) recording the inner node and child slot per level; a key
+//     found in its leaf is an update, the others are new.
+//  3. Plan, read-only, level by level from the leaves up.  Touched leaves
+//     are the runs of new keys with the same leaf; a leaf with c old and r
+//     new keys gets t = c + r entries and splits into ceil(t/16) pieces when
+//     t > 16 (even sizes, so every piece holds >= 8).  Touched parents are
+//     the runs of touched children with the same parent; a parent whose
+//     children split gains sum(k-1) entries and splits the same way.  Piece
+//     counts are scanned into allocation offsets, so new node ids follow key
+//     order and repeated runs give the same tree.
+//  4. Check: if the node pools cannot hold every new node the device error
+//     word gets the capacity bit and nothing below runs (the batch is
+//     applied whole or not at all).
+//  5. Apply: updates in place; one wave per touched leaf merges its old keys
+//     (held in registers) with its new keys and writes the pieces, the first
+//     in place, the others to new leaves linked into the chain; then one wave
+//     per changed parent, level by level, rebuilds its entry list (old
+//     entries shifted, split children replaced by their pieces and piece
+//     separators) and writes its own pieces.  A root that splits grows new
+//     levels above it, packed with the same even rule.
+//  6. Commit the header (key count, pool cursors, height, root) and refresh
+//     the top-levels mirror.
 #include "insert.h"
+#include "prims.h"
+#include "traverse.h"
 
 namespace gt {
 
-uint64_t insert_scratch_bytes(uint64_t max_batch, int key_bytes) { return 256; }
+constexpr int kBlk = 256;
 
-__global__ void k_insert_unavailable(DevHeader* h) {
-    if (threadIdx.x == 0) atomicOr(&h->error, kErrInternal);
+struct InsState {
+    uint32_t U, R;
+    uint32_t ok;
+    uint32_t height;       // tree height when the batch started
+    uint32_t overflow;     // item pool would overflow (internal error)
+    uint32_t grow_nodes, grow_levels, new_root;
+    uint32_t lvl_count[kMaxLevels];  // items per level (0 = leaves)
+    uint32_t lvl_base[kMaxLevels];   // first item of the level in the pool
+    uint32_t lvl_new[kMaxLevels];    // new nodes the level's items create
+    uint32_t lvl_alloc[kMaxLevels];  // first new id of the level
+    uint32_t lvl_psep[kMaxLevels];   // first piece separator of the level
+    uint32_t pad[8];
+};
+
+template <class K>
+struct Ins {
+    InsState* st;
+    K* sk; K* sk2; uint32_t* si; uint32_t* si2; void* sort_tmp;
+    uint32_t* f0; uint32_t* f1; void* scan_tmp;
+    K* uk; K* uv; uint32_t* upos; uint32_t* uleaf; uint8_t* uslot; uint8_t* ufound;
+    uint32_t* pn; uint8_t* pi;
+    K* nk; K* nv; uint32_t* nleaf; uint32_t* nu;
+    uint32_t* it_node; uint32_t* it_rep; uint32_t* it_first; uint32_t* it_end;
+    uint32_t* it_cold; uint32_t* it_k; uint32_t* it_off;
+    K* psep;
+    K* gsep0; K* gsep1; uint32_t* gid0; uint32_t* gid1;
+    uint64_t Bm, ip_cap, ps_cap;
+};
+
+// ------------------------------------------------------------ scratch sizing
+
+static uint64_t al(uint64_t x) { return (x + 255) / 256 * 256; }
+
+static uint64_t item_pool_cap(uint64_t Bm, uint64_t leaf_cap) {
+    uint64_t total = 0, lv = leaf_cap;
+    for (int d = 0; d < kMaxLevels; ++d) {
+        uint64_t bound = lv + 2;
+        total += bound < Bm ? bound : Bm;
+        lv = lv / 8;
+    }
+    return total;
+}
+
+static uint64_t psep_cap(uint64_t leaf_cap, uint64_t inner_cap) { return leaf_cap + inner_cap + 64; }
+
+template <class K>
+static uint64_t carve(Ins<K>* v, uint8_t* base, uint64_t Bm, uint64_t leaf_cap, uint64_t inner_cap) {
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        uint8_t* p = base ? base + off : nullptr;
+        off += al(bytes);
+        return p;
+    };
+    const uint64_t ip = item_pool_cap(Bm, leaf_cap), ps = psep_cap(leaf_cap, inner_cap);
+    Ins<K> x;
+    x.Bm = Bm; x.ip_cap = ip; x.ps_cap = ps;
+    x.st = reinterpret_cast<InsState*>(take(sizeof(InsState)));
+    x.sk = reinterpret_cast<K*>(take(Bm * sizeof(K)));
+    x.sk2 = reinterpret_cast<K*>(take(Bm * sizeof(K)));
+    x.si = reinterpret_cast<uint32_t*>(take(Bm * 4));
+    x.si2 = reinterpret_cast<uint32_t*>(take(Bm * 4));
+    x.sort_tmp = take(sort_tmp_bytes(Bm, sizeof(K)));
+    x.f0 = reinterpret_cast<uint32_t*>(take((Bm + 1) * 4));
+    x.f1 = reinterpret_cast<uint32_t*>(take((Bm + 1) * 4));
+    x.scan_tmp = take(scan_tmp_bytes(Bm + 1));
+    x.uk = reinterpret_cast<K*>(take(Bm * sizeof(K)));
+    x.uv = reinterpret_cast<K*>(take(Bm * sizeof(K)));
+    x.upos = reinterpret_cast<uint32_t*>(take(Bm * 4));
+    x.uleaf = reinterpret_cast<uint32_t*>(take(Bm * 4));
+    x.uslot = take(Bm);
+    x.ufound = take(Bm);
+    x.pn = reinterpret_cast<uint32_t*>(take(static_cast<uint64_t>(kMaxLevels) * Bm * 4));
+    x.pi = take(static_cast<uint64_t>(kMaxLevels) * Bm);
+    x.nk = reinterpret_cast<K*>(take(Bm * sizeof(K)));
+    x.nv = reinterpret_cast<K*>(take(Bm * sizeof(K)));
+    x.nleaf = reinterpret_cast<uint32_t*>(take(Bm * 4));
+    x.nu = reinterpret_cast<uint32_t*>(take(Bm * 4));
+    x.it_node = reinterpret_cast<uint32_t*>(take(ip * 4));
+    x.it_rep = reinterpret_cast<uint32_t*>(take(ip * 4));
+    x.it_first = reinterpret_cast<uint32_t*>(take(ip * 4));
+    x.it_end = reinterpret_cast<uint32_t*>(take(ip * 4));
+    x.it_cold = reinterpret_cast<uint32_t*>(take(ip * 4));
+    x.it_k = reinterpret_cast<uint32_t*>(take(ip * 4));
+    x.it_off = reinterpret_cast<uint32_t*>(take(ip * 4));
+    x.psep = reinterpret_cast<K*>(take(ps * sizeof(K)));
+    x.gsep0 = reinterpret_cast<K*>(take(ps * sizeof(K)));
+    x.gsep1 = reinterpret_cast<K*>(take(ps * sizeof(K)));
+    x.gid0 = reinterpret_cast<uint32_t*>(take(ps * 4));
+    x.gid1 = reinterpret_cast<uint32_t*>(take(ps * 4));
+    if (v) *v = x;
+    return off;
+}
+
+uint64_t insert_scratch_bytes(uint64_t max_batch, int key_bytes, uint64_t leaf_cap, uint64_t inner_cap) {
+    if (key_bytes == 8) return carve<uint64_t>(nullptr, nullptr, max_batch, leaf_cap, inner_cap);
+    return carve<uint32_t>(nullptr, nullptr, max_batch, leaf_cap, inner_cap);
+}
+
+// ------------------------------------------------------------------ kernels
+
+__device__ __forceinline__ uint64_t gtid() { return blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; }
+__device__ __forceinline__ uint64_t gstride() { return static_cast<uint64_t>(gridDim.x) * blockDim.x; }
+
+template <class K>
+__global__ void k_init(Ins<K> v, const DevHeader* hdr, const K* __restrict__ keys, uint64_t B) {
+    if (blockIdx.x == 0) {
+        uint32_t* s = reinterpret_cast<uint32_t*>(v.st);
+        for (uint32_t i = threadIdx.x; i < sizeof(InsState) / 4; i += blockDim.x) s[i] = 0;
+        __syncthreads();
+        if (threadIdx.x == 0) v.st->height = hdr->height;
+    }
+    for (uint64_t i = gtid(); i < B; i += gstride()) {
+        v.sk[i] = keys[i];
+        v.si[i] = static_cast<uint32_t>(i);
+    }
 }
 
 template <class K>
-void launch_insert(const TreeView<K>& t, const InsertCtx&, const K*, const K*, uint64_t, uint8_t*, hipStream_t s) {
-    hipLaunchKernelGGL(k_insert_unavailable, dim3(1), dim3(64), 0, s, t.hdr);
+__global__ void k_heads(Ins<K> v, uint64_t B, uint8_t* __restrict__ status) {
+    for (uint64_t p = gtid(); p < B; p += gstride()) {
+        const bool head = p == 0 || v.sk[p] != v.sk[p - 1];
+        v.f0[p] = head ? 1u : 0u;
+        if (!head) status[v.si[p]] = 1;  // UPDATED: an earlier occurrence exists
+    }
+}
+
+template <class K>
+__global__ void k_unique(Ins<K> v, uint64_t B, const K* __restrict__ vals) {
+    for (uint64_t p = gtid(); p < B; p += gstride()) {
+        const uint32_t f = v.f0[p], e = v.f1[p];
+        if (f) {
+            v.uk[e] = v.sk[p];
+            v.upos[e] = static_cast<uint32_t>(p);
+        }
+        const bool last = p + 1 == B || v.sk[p + 1] != v.sk[p];
+        if (last) v.uv[e + f - 1] = vals[v.si[p]];  // the run's last writer
+    }
+}
+
+// Locate every distinct key; G lanes per key, the top levels from LDS.
+template <class K, int G, int LV>
+__global__ __launch_bounds__(kBlk) void k_locate(TreeView<K> t, Ins<K> v, uint8_t* __restrict__ status) {
+    using T = Trav<K, G>;
+    extern __shared__ __align__(16) uint8_t lds[];
+    const uint8_t* mir = t.mirror;
+    uint32_t mnodes = kMirrorMaxNodes;
+    if constexpr (LV > 0) {
+        mnodes = mirror_nodes_for_levels(LV);
+        stage_mirror<K>(t.mirror, lds, mnodes);
+        __syncthreads();
+        mir = lds;
+    }
+    const MirrorHeader* mh = reinterpret_cast<const MirrorHeader*>(mir);
+    const bool empty = mh->n_keys == 0;
+    const uint64_t U = v.st->U;
+    const int lane = lane_id();
+    const int gl = lane % G, gbase = lane - gl;
+    const uint64_t per_block = kBlk / G;
+    const uint64_t ntiles = (U + per_block - 1) / per_block;
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t u = tile * per_block + threadIdx.x / G;
+        const bool live = u < U;
+        K key[1] = {live ? v.uk[u] : K(0)};
+        uint64_t qi[1] = {live ? u : ~0ull};
+        uint32_t leaf[1];
+        descend<K, G, 1, true>(t, mir, mnodes, LV, key, leaf, gl, gbase, v.pn, v.pi, v.Bm, qi);
+        typename T::KV kv = T::load_keys(t.lkeys + static_cast<uint64_t>(leaf[0]) * kSlots, gl);
+        const uint32_t slot = T::match_slot(kv, key[0], gbase);
+        const bool found = slot < kSlots && !empty;
+        if (live && gl == 0) {
+            v.ufound[u] = found ? 1 : 0;
+            v.uleaf[u] = leaf[0];
+            v.uslot[u] = static_cast<uint8_t>(found ? slot : 0);
+            v.f0[u] = found ? 0u : 1u;
+            status[v.si[v.upos[u]]] = found ? 1 : 0;
+        }
+    }
+}
+
+template <class K>
+__global__ void k_compact_new(Ins<K> v) {
+    const uint64_t U = v.st->U;
+    for (uint64_t u = gtid(); u < U; u += gstride()) {
+        if (!v.ufound[u]) {
+            const uint32_t r = v.f1[u];
+            v.nk[r] = v.uk[u];
+            v.nv[r] = v.uv[u];
+            v.nleaf[r] = v.uleaf[u];
+            v.nu[r] = static_cast<uint32_t>(u);
+        }
+    }
+}
+
+template <class K>
+__global__ void k_leaf_heads(Ins<K> v) {
+    const uint64_t R = v.st->R;
+    for (uint64_t r = gtid(); r < R; r += gstride())
+        v.f0[r] = (r == 0 || v.nleaf[r] != v.nleaf[r - 1]) ? 1u : 0u;
+}
+
+template <class K>
+__global__ void k_leaf_items(Ins<K> v) {
+    const uint64_t R = v.st->R;
+    for (uint64_t r = gtid(); r < R; r += gstride()) {
+        const uint32_t f = v.f0[r], e = v.f1[r];
+        if (f) {
+            if (e >= v.ip_cap) { v.st->overflow = 1; continue; }
+            v.it_node[e] = v.nleaf[r];
+            v.it_rep[e] = v.nu[r];
+            v.it_first[e] = static_cast<uint32_t>(r);
+        }
+        if (r + 1 == R || v.f0[r + 1]) {
+            const uint32_t seg = e + f - 1;
+            if (seg < v.ip_cap) v.it_end[seg] = static_cast<uint32_t>(r + 1);
+        }
+    }
+}
+
+template <class K>
+__global__ void k_leaf_plan(TreeView<K> t, Ins<K> v) {
+    const uint64_t T0 = v.st->lvl_count[0];
+    for (uint64_t i = gtid(); i < T0; i += gstride()) {
+        const uint32_t c = t.lmeta[v.it_node[i]].x;
+        const uint64_t total = static_cast<uint64_t>(c) + (v.it_end[i] - v.it_first[i]);
+        const uint32_t k = split_pieces(total);
+        v.it_cold[i] = c;
+        v.it_k[i] = k;
+        v.f0[i] = k - 1;
+    }
+}
+
+// heads of the level-d items: runs of level-(d-1) items with the same parent
+template <class K>
+__global__ void k_par_heads(Ins<K> v, int d) {
+    const int h = static_cast<int>(v.st->height);
+    const int l = h - 1 - d;  // parent level, 0 = root level
+    const uint64_t n = v.st->lvl_count[d - 1];
+    const uint32_t b = v.st->lvl_base[d - 1];
+    if (gtid() == 0) {
+        v.st->lvl_base[d] = b + v.st->lvl_count[d - 1];
+        v.st->lvl_psep[d] = v.st->lvl_psep[d - 1] + v.st->lvl_new[d - 1];
+    }
+    for (uint64_t i = gtid(); i < n; i += gstride()) {
+        uint32_t f = 0;
+        if (l >= 0) {
+            const uint32_t p = v.pn[static_cast<uint64_t>(l) * v.Bm + v.it_rep[b + i]];
+            f = (i == 0 || p != v.pn[static_cast<uint64_t>(l) * v.Bm + v.it_rep[b + i - 1]]) ? 1u : 0u;
+        }
+        v.f0[i] = f;
+    }
+}
+
+template <class K>
+__global__ void k_par_items(Ins<K> v, int d) {
+    const int h = static_cast<int>(v.st->height);
+    const int l = h - 1 - d;
+    if (l < 0) return;
+    const uint64_t n = v.st->lvl_count[d - 1];
+    const uint32_t b = v.st->lvl_base[d - 1];
+    const uint32_t bd = v.st->lvl_base[d];
+    for (uint64_t i = gtid(); i < n; i += gstride()) {
+        const uint32_t f = v.f0[i], e = v.f1[i];
+        if (f) {
+            if (bd + e >= v.ip_cap) { v.st->overflow = 1; continue; }
+            v.it_node[bd + e] = v.pn[static_cast<uint64_t>(l) * v.Bm + v.it_rep[b + i]];
+            v.it_rep[bd + e] = v.it_rep[b + i];
+            v.it_first[bd + e] = static_cast<uint32_t>(i);
+        }
+        if (i + 1 == n || v.f0[i + 1]) {
+            const uint32_t seg = e + f - 1;
+            if (bd + seg < v.ip_cap) v.it_end[bd + seg] = static_cast<uint32_t>(i + 1);
+        }
+    }
+}
+
+template <class K>
+__global__ void k_par_plan(TreeView<K> t, Ins<K> v, int d) {
+    const uint64_t n = v.st->lvl_count[d];
+    const uint32_t bd = v.st->lvl_base[d];
+    const uint32_t bc = v.st->lvl_base[d - 1];
+    for (uint64_t j = gtid(); j < n; j += gstride()) {
+        const uint32_t node = v.it_node[bd + j];
+        uint32_t C = 0;
+        const uint32_t* ch = t.ichild + static_cast<uint64_t>(node) * kSlots;
+        for (int s = 0; s < kSlots; ++s) C += ch[s] != kNone ? 1u : 0u;
+        uint64_t a = 0;
+        for (uint32_t i = v.it_first[bd + j]; i < v.it_end[bd + j]; ++i) a += v.it_k[bc + i] - 1;
+        const uint32_t k = split_pieces(C + a);
+        v.it_cold[bd + j] = C;
+        v.it_k[bd + j] = k;
+        v.f0[j] = k - 1;
+    }
+}
+
+// this level's allocation offsets, moved to the level's slice of the pool
+template <class K>
+__global__ void k_par_off(Ins<K> v, int d) {
+    const uint64_t n = v.st->lvl_count[d];
+    const uint32_t bd = v.st->lvl_base[d];
+    for (uint64_t j = gtid(); j < n; j += gstride()) v.it_off[bd + j] = v.f1[j];
+}
+
+// Capacity check and allocation bases (one thread).
+template <class K>
+__global__ void k_check(TreeView<K> t, Ins<K> v) {
+    if (gtid() != 0) return;
+    InsState* st = v.st;
+    DevHeader* hdr = t.hdr;
+    const int h = static_cast<int>(st->height);
+    // root growth: the root is the level-(h-1) item, if touched
+    uint32_t gn = 0, gl = 0;
+    const int dr = h - 1;
+    if (st->lvl_count[dr] > 0) {
+        uint64_t cnt = v.it_k[st->lvl_base[dr]];
+        while (cnt > 1) {
+            const uint64_t nodes = cnt <= kSlots ? 1 : (cnt + kSlots - 1) / kSlots;
+            gn += static_cast<uint32_t>(nodes);
+            gl += 1;
+            cnt = nodes;
+        }
+    }
+    const uint64_t leaf_new = st->lvl_new[0];
+    uint64_t inner_new = gn, sep_total = 0;
+    for (int d = 0; d < h; ++d) sep_total += st->lvl_new[d];
+    for (int d = 1; d < h; ++d) inner_new += st->lvl_new[d];
+    bool ok = !st->overflow;
+    if (hdr->leaf_used + leaf_new > t.leaf_cap) ok = false;
+    if (hdr->inner_used + inner_new > t.inner_cap) ok = false;
+    if (sep_total + 1 > v.ps_cap) ok = false;
+    if (h + gl > kMaxLevels) ok = false;
+    if (!ok) atomicOr(&hdr->error, st->overflow ? kErrInternal : kErrCapacity);
+    st->ok = ok ? 1u : 0u;
+    st->grow_nodes = gn;
+    st->grow_levels = gl;
+    st->lvl_alloc[0] = hdr->leaf_used;
+    uint32_t cur = hdr->inner_used;
+    for (int d = 1; d < h; ++d) {
+        st->lvl_alloc[d] = cur;
+        cur += st->lvl_new[d];
+    }
+    st->new_root = cur;  // first growth node id
+}
+
+template <class K>
+__global__ void k_apply_updates(TreeView<K> t, Ins<K> v) {
+    if (!v.st->ok) return;
+    const uint64_t U = v.st->U;
+    for (uint64_t u = gtid(); u < U; u += gstride())
+        if (v.ufound[u]) t.lvals[static_cast<uint64_t>(v.uleaf[u]) * kSlots + v.uslot[u]] = v.uv[u];
+}
+
+// first index in a[0..n) whose key is >= k
+template <class K>
+__device__ __forceinline__ uint32_t lower_bound_dev(const K* a, uint32_t n, K k) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Merge-split of the touched leaves: one wave per leaf.
+template <class K>
+__global__ __launch_bounds__(kBlk) void k_apply_leaves(TreeView<K> t, Ins<K> v) {
+    if (!v.st->ok) return;
+    const uint64_t T0 = v.st->lvl_count[0];
+    const int lane = lane_id();
+    const uint64_t wave = gtid() / 64, nwaves = gstride() / 64;
+    const uint32_t alloc = v.st->lvl_alloc[0];
+    for (uint64_t it = wave; it < T0; it += nwaves) {
+        const uint32_t leaf = v.it_node[it];
+        const uint32_t first = v.it_first[it];
+        const uint32_t r = v.it_end[it] - first;
+        const uint32_t c = v.it_cold[it];
+        const uint32_t k = v.it_k[it];
+        const uint32_t off = v.it_off[it];
+        const uint64_t total = static_cast<uint64_t>(c) + r;
+        const uint32_t base_new = alloc + off;
+        K okey = K(0), oval = K(0);
+        if (lane < kSlots) {
+            okey = t.lkeys[static_cast<uint64_t>(leaf) * kSlots + lane];
+            oval = t.lvals[static_cast<uint64_t>(leaf) * kSlots + lane];
+        }
+        const uint2 meta = t.lmeta[leaf];
+        __threadfence_block();  // the old leaf is in registers before any write
+        const K* nk = v.nk + first;
+        const K* nv = v.nv + first;
+        auto place = [&](uint64_t pos, K key, K val) {
+            const uint64_t j = part_of(pos, total, k);
+            const uint64_t s0 = part_start(j, total, k), s1 = part_start(j + 1, total, k);
+            const uint64_t slot = pos - s0;
+            const uint64_t dest = j == 0 ? leaf : base_new + j - 1;
+            t.lkeys[dest * kSlots + slot] = key;
+            t.lvals[dest * kSlots + slot] = val;
+            if (pos + 1 == s1) {
+                const uint32_t cnt = static_cast<uint32_t>(s1 - s0);
+                for (uint32_t s = cnt; s < kSlots; ++s) {
+                    t.lkeys[dest * kSlots + s] = key;
+                    t.lvals[dest * kSlots + s] = kmax<K>();
+                }
+                const uint32_t nxt = (j + 1 < k) ? static_cast<uint32_t>(base_new + j) : meta.y;
+                t.lmeta[dest] = make_uint2(cnt, nxt);
+                if (j + 1 < k) v.psep[off + j] = key;
+            }
+        };
+        if (lane < static_cast<int>(c)) place(lane + lower_bound_dev(nk, r, okey), okey, oval);
+        for (uint32_t q0 = 0; q0 < r; q0 += 64) {
+            const uint32_t q = q0 + lane;
+            const bool act = q < r;
+            const K key = act ? nk[q] : K(0);
+            uint32_t rank = 0;
+            for (uint32_t s = 0; s < c; ++s) {
+                const K ks = __shfl(okey, static_cast<int>(s), 64);
+                rank += ks < key ? 1u : 0u;
+            }
+            if (act) place(q + rank, key, nv[q]);
+        }
+    }
+}
+
+// Rebuild the changed parents of level d: one wave per parent.
+template <class K>
+__global__ __launch_bounds__(kBlk) void k_apply_inner(TreeView<K> t, Ins<K> v, int d) {
+    if (!v.st->ok) return;
+    const int h = static_cast<int>(v.st->height);
+    const int l = h - 1 - d;
+    if (l < 0) return;
+    const uint64_t n = v.st->lvl_count[d];
+    const uint32_t bd = v.st->lvl_base[d], bc = v.st->lvl_base[d - 1];
+    const uint32_t alloc = v.st->lvl_alloc[d], alloc_c = v.st->lvl_alloc[d - 1];
+    const uint32_t psep_d = v.st->lvl_psep[d], psep_c = v.st->lvl_psep[d - 1];
+    const bool child_leaf = d == 1;
+    const int lane = lane_id();
+    const uint64_t wave = gtid() / 64, nwaves = gstride() / 64;
+    for (uint64_t j = wave; j < n; j += nwaves) {
+        const uint32_t node = v.it_node[bd + j];
+        const uint32_t first = v.it_first[bd + j], end = v.it_end[bd + j];
+        const uint32_t C = v.it_cold[bd + j];
+        const uint32_t P = v.it_k[bd + j];
+        const uint32_t off = v.it_off[bd + j];
+        K osep = kmax<K>();
+        uint32_t ochild = kNone;
+        if (lane < kSlots) {
+            osep = t.ikeys[static_cast<uint64_t>(node) * kSlots + lane];
+            ochild = t.ichild[static_cast<uint64_t>(node) * kSlots + lane];
+        }
+        // per old slot: shift from split children before it, and its own item
+        uint32_t shift = 0, myk = 1, myitem = kNone;
+        uint64_t a = 0;
+        for (uint32_t i = first; i < end; ++i) {
+            const uint32_t cs = v.pi[static_cast<uint64_t>(l) * v.Bm + v.it_rep[bc + i]];
+            const uint32_t ki = v.it_k[bc + i];
+            a += ki - 1;
+            if (cs < static_cast<uint32_t>(lane)) shift += ki - 1;
+            if (cs == static_cast<uint32_t>(lane)) { myk = ki; myitem = i; }
+        }
+        __threadfence_block();  // the old node is in registers before any write
+        if (a == 0) continue;   // no child split: the parent is unchanged
+        const uint32_t myoff = myitem != kNone ? v.it_off[bc + myitem] : 0u;
+        const uint32_t newpos = static_cast<uint32_t>(lane) + shift;
+        const uint64_t Cp = C + a;
+        const uint32_t base_new = alloc + off;
+        for (uint64_t e0 = 0; e0 < Cp; e0 += 64) {
+            const uint64_t e = e0 + lane;
+            const bool act = e < Cp;
+            // old slot whose entries cover e: the last slot with newpos <= e
+            uint32_t sf = 0;
+            for (uint32_t s = 0; s < C; ++s) {
+                const uint32_t np = shfl_u32(newpos, static_cast<int>(s));
+                if (np <= e) sf = s;
+            }
+            const uint32_t np = shfl_u32(newpos, static_cast<int>(sf));
+            const uint32_t ks = shfl_u32(myk, static_cast<int>(sf));
+            const uint32_t ko = shfl_u32(myoff, static_cast<int>(sf));
+            const K os = __shfl(osep, static_cast<int>(sf), 64);
+            const uint32_t oc = shfl_u32(ochild, static_cast<int>(sf));
+            const uint64_t jj = e - np;
+            const K last_sep = (sf + 1 < C) ? os : kmax<K>();
+            K sep;
+            uint32_t ch;
+            if (ks <= 1) {
+                sep = last_sep;
+                ch = oc;
+            } else {
+                sep = (jj + 1 < ks) ? v.psep[psep_c + ko + jj] : last_sep;
+                if (jj == 0) ch = oc;
+                else {
+                    const uint32_t id = alloc_c + ko + static_cast<uint32_t>(jj) - 1;
+                    ch = child_leaf ? (kLeafTag | id) : id;
+                }
+            }
+            if (act) {
+                const uint64_t pj = part_of(e, Cp, P);
+                const uint64_t s0 = part_start(pj, Cp, P), s1 = part_start(pj + 1, Cp, P);
+                const uint64_t slot = e - s0;
+                const uint64_t cnt = s1 - s0;
+                const uint64_t dest = pj == 0 ? node : base_new + pj - 1;
+                t.ikeys[dest * kSlots + slot] = (slot + 1 < cnt) ? sep : kmax<K>();
+                t.ichild[dest * kSlots + slot] = ch;
+                if (e + 1 == s1) {
+                    for (uint64_t s = cnt; s < kSlots; ++s) {
+                        t.ikeys[dest * kSlots + s] = kmax<K>();
+                        t.ichild[dest * kSlots + s] = kNone;
+                    }
+                    if (pj + 1 < P) v.psep[psep_d + off + pj] = sep;
+                }
+            }
+        }
+    }
+}
+
+// Root growth: pack the root's pieces into new levels (one workgroup).
+template <class K>
+__global__ __launch_bounds__(1024) void k_grow(TreeView<K> t, Ins<K> v) {
+    if (!v.st->ok || v.st->grow_levels == 0) return;
+    const int h = static_cast<int>(v.st->height);
+    const int dr = h - 1;
+    const uint32_t item = v.st->lvl_base[dr];
+    const uint32_t k0 = v.it_k[item];
+    const uint32_t off = v.it_off[item];
+    const uint32_t alloc = v.st->lvl_alloc[dr];
+    const uint32_t psep0 = v.st->lvl_psep[dr];
+    const bool leaf = dr == 0;
+    for (uint32_t e = threadIdx.x; e < k0; e += blockDim.x) {
+        const uint32_t id = e == 0 ? v.it_node[item] : alloc + off + e - 1;
+        v.gid0[e] = leaf ? (kLeafTag | id) : id;
+        v.gsep0[e] = (e + 1 < k0) ? v.psep[psep0 + off + e] : kmax<K>();
+    }
+    __syncthreads();
+    K* sa = v.gsep0; K* sb = v.gsep1;
+    uint32_t* ia = v.gid0; uint32_t* ib = v.gid1;
+    uint64_t cnt = k0;
+    uint32_t cursor = v.st->new_root;
+    while (cnt > 1) {
+        const uint64_t nodes = cnt <= kSlots ? 1 : (cnt + kSlots - 1) / kSlots;
+        for (uint64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
+            const uint64_t n = part_of(e, cnt, nodes);
+            const uint64_t s0 = part_start(n, cnt, nodes), s1 = part_start(n + 1, cnt, nodes);
+            const uint64_t slot = e - s0, c = s1 - s0;
+            const uint64_t dest = cursor + n;
+            t.ikeys[dest * kSlots + slot] = (slot + 1 < c) ? sa[e] : kmax<K>();
+            t.ichild[dest * kSlots + slot] = ia[e];
+            if (e + 1 == s1) {
+                for (uint64_t s = c; s < kSlots; ++s) {
+                    t.ikeys[dest * kSlots + s] = kmax<K>();
+                    t.ichild[dest * kSlots + s] = kNone;
+                }
+                sb[n] = sa[e];  // the node's bound is its last entry's separator
+                ib[n] = static_cast<uint32_t>(dest);
+            }
+        }
+        __syncthreads();
+        cursor += static_cast<uint32_t>(nodes);
+        cnt = nodes;
+        K* ts = sa; sa = sb; sb = ts;
+        uint32_t* ti = ia; ia = ib; ib = ti;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) v.st->new_root = cursor - 1;
+}
+
+template <class K>
+__global__ void k_commit(TreeView<K> t, Ins<K> v) {
+    if (gtid() != 0 || !v.st->ok) return;
+    InsState* st = v.st;
+    DevHeader* hdr = t.hdr;
+    const int h = static_cast<int>(st->height);
+    uint32_t inner_new = st->grow_nodes;
+    for (int d = 1; d < h; ++d) inner_new += st->lvl_new[d];
+    hdr->n_keys += st->R;
+    hdr->leaf_used += st->lvl_new[0];
+    hdr->inner_used += inner_new;
+    if (st->grow_levels) {
+        hdr->height = h + st->grow_levels;
+        hdr->root = st->new_root;
+    }
+    hdr->epoch += 1;
+}
+
+// ------------------------------------------------------------------ launch
+
+static uint32_t grid_for(uint64_t n, uint32_t per_block) {
+    uint64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > 8192) g = 8192;
+    return static_cast<uint32_t>(g);
+}
+
+template <class K, int G, int LV>
+static void launch_locate_t(const TreeView<K>& t, const Ins<K>& v, uint64_t B, uint8_t* status, hipStream_t s) {
+    const uint32_t lds = LV > 0 ? MirrorLayout<K>::bytes(mirror_nodes_for_levels(LV)) : 0;
+    uint32_t grid = grid_for(B, kBlk / G);
+    if (grid > 2048) grid = 2048;
+    hipLaunchKernelGGL((k_locate<K, G, LV>), dim3(grid), dim3(kBlk), lds, s, t, v, status);
+}
+
+template <class K>
+static void launch_locate(const TreeView<K>& t, const Ins<K>& v, const LaunchCfg& cfg, uint64_t B, uint8_t* status,
+                          hipStream_t s) {
+    // 16 lanes per key: one 128-byte (or 64-byte) line per group load
+    switch (cfg.lds_levels) {
+        case 0: launch_locate_t<K, 16, 0>(t, v, B, status, s); break;
+        case 1: launch_locate_t<K, 16, 1>(t, v, B, status, s); break;
+        case 3: launch_locate_t<K, 16, 3>(t, v, B, status, s); break;
+        default: launch_locate_t<K, 16, 2>(t, v, B, status, s); break;
+    }
+}
+
+// highest tree height the pools allow (non-root inner nodes have >= 8
+// children, the root >= 2)
+static int height_bound(uint64_t leaf_cap) {
+    int h = 1;
+    uint64_t cover = 2;  // leaves a tree of height h+1 can have at least
+    while (cover <= leaf_cap && h < kMaxLevels - 1) {
+        ++h;
+        cover *= 8;
+    }
+    return h + 1 < kMaxLevels ? h + 1 : kMaxLevels;
+}
+
+template <class K>
+void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, const K* vals, uint64_t B,
+                   uint8_t* status, hipStream_t s) {
+    Ins<K> v;
+    carve<K>(&v, c.scratch, c.max_batch, c.leaf_cap, c.inner_cap);
+    InsState* st = v.st;
+    const uint32_t gB = grid_for(B, kBlk);
+    const int H = height_bound(c.leaf_cap);
+
+    hipLaunchKernelGGL(k_init<K>, dim3(gB), dim3(kBlk), 0, s, v, t.hdr, keys, B);
+    sort_pairs<K>(v.sk, v.si, v.sk2, v.si2, B, v.sort_tmp, s);
+    hipLaunchKernelGGL(k_heads<K>, dim3(gB), dim3(kBlk), 0, s, v, B, status);
+    scan_exclusive<uint32_t>(v.f0, v.f1, &st->U, nullptr, B, v.scan_tmp, s);
+    hipLaunchKernelGGL(k_unique<K>, dim3(gB), dim3(kBlk), 0, s, v, B, vals);
+    launch_locate<K>(t, v, c.cfg, B, status, s);
+    scan_exclusive<uint32_t>(v.f0, v.f1, &st->R, &st->U, B, v.scan_tmp, s);
+    hipLaunchKernelGGL(k_compact_new<K>, dim3(gB), dim3(kBlk), 0, s, v);
+    hipLaunchKernelGGL(k_leaf_heads<K>, dim3(gB), dim3(kBlk), 0, s, v);
+    scan_exclusive<uint32_t>(v.f0, v.f1, &st->lvl_count[0], &st->R, B, v.scan_tmp, s);
+    hipLaunchKernelGGL(k_leaf_items<K>, dim3(gB), dim3(kBlk), 0, s, v);
+    hipLaunchKernelGGL(k_leaf_plan<K>, dim3(gB), dim3(kBlk), 0, s, t, v);
+    scan_exclusive<uint32_t>(v.f0, v.it_off, &st->lvl_new[0], &st->lvl_count[0], B, v.scan_tmp, s);
+    for (int d = 1; d < H; ++d) {
+        hipLaunchKernelGGL(k_par_heads<K>, dim3(gB), dim3(kBlk), 0, s, v, d);
+        scan_exclusive<uint32_t>(v.f0, v.f1, &st->lvl_count[d], &st->lvl_count[d - 1], B, v.scan_tmp, s);
+        hipLaunchKernelGGL(k_par_items<K>, dim3(gB), dim3(kBlk), 0, s, v, d);
+        hipLaunchKernelGGL(k_par_plan<K>, dim3(gB), dim3(kBlk), 0, s, t, v, d);
+        scan_exclusive<uint32_t>(v.f0, v.f1, &st->lvl_new[d], &st->lvl_count[d], B, v.scan_tmp, s);
+        hipLaunchKernelGGL(k_par_off<K>, dim3(gB), dim3(kBlk), 0, s, v, d);
+    }
+    hipLaunchKernelGGL(k_check<K>, dim3(1), dim3(64), 0, s, t, v);
+    hipLaunchKernelGGL(k_apply_updates<K>, dim3(gB), dim3(kBlk), 0, s, t, v);
+    hipLaunchKernelGGL(k_apply_leaves<K>, dim3(grid_for(B, kBlk / 64)), dim3(kBlk), 0, s, t, v);
+    for (int d = 1; d < H; ++d)
+        hipLaunchKernelGGL(k_apply_inner<K>, dim3(grid_for(B, kBlk / 64)), dim3(kBlk), 0, s, t, v, d);
+    hipLaunchKernelGGL(k_grow<K>, dim3(1), dim3(1024), 0, s, t, v);
+    hipLaunchKernelGGL(k_commit<K>, dim3(1), dim3(64), 0, s, t, v);
+    launch_mirror_refresh<K>(t, s);
 }
 
 template void launch_insert<uint32_t>(const TreeView<uint32_t>&, const InsertCtx&, const uint32_t*,

@@ -92,13 +92,14 @@ std::vector<uint64_t> level_sizes_for(uint64_t n, double fill) {
     return v;
 }
 
-uint64_t fixed_bytes(int kb, uint64_t max_batch) {
-    return align_up(sizeof(DevHeader)) + mirror_bytes(kb) + align_up(insert_scratch_bytes(max_batch, kb));
-}
-
 // inner nodes needed for `leaves` leaves when every non-root inner node has
 // at least 8 children
 uint64_t inner_cap_for(uint64_t leaves) { return leaves / 7 + 2 * kMaxLevels; }
+
+uint64_t fixed_bytes(int kb, uint64_t max_batch, uint64_t leaf_cap) {
+    return align_up(sizeof(DevHeader)) + mirror_bytes(kb) +
+           align_up(insert_scratch_bytes(max_batch, kb, leaf_cap, inner_cap_for(leaf_cap)));
+}
 
 void layout(gt_tree* t, uint8_t* arena, uint64_t leaf_cap) {
     const int kb = t->kb;
@@ -109,7 +110,7 @@ void layout(gt_tree* t, uint8_t* arena, uint64_t leaf_cap) {
     t->mirror = arena + off;
     off += mirror_bytes(kb);
     t->scratch = arena + off;
-    t->scratch_bytes = align_up(insert_scratch_bytes(t->max_batch, kb));
+    t->scratch_bytes = align_up(insert_scratch_bytes(t->max_batch, kb, leaf_cap, inner_cap_for(leaf_cap)));
     off += t->scratch_bytes;
     t->leaf_cap = leaf_cap;
     t->inner_cap = inner_cap_for(leaf_cap);
@@ -128,7 +129,7 @@ void layout(gt_tree* t, uint8_t* arena, uint64_t leaf_cap) {
 
 uint64_t bytes_for_leaf_cap(int kb, uint64_t max_batch, uint64_t leaf_cap) {
     uint64_t ic = inner_cap_for(leaf_cap);
-    return fixed_bytes(kb, max_batch) + align_up(ic * kSlots * kb) + align_up(ic * kSlots * 4) +
+    return fixed_bytes(kb, max_batch, leaf_cap) + align_up(ic * kSlots * kb) + align_up(ic * kSlots * 4) +
            2 * align_up(leaf_cap * kSlots * kb) + align_up(leaf_cap * 8);
 }
 
