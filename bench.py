@@ -94,6 +94,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--log2n", type=int, default=N_LOG2)
+    ap.add_argument("--profile", action="store_true",
+                    help="counter-collection mode: a 1 GiB device copy (calibration) and 2^20-key lookup "
+                         "batches, three each, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the tree runs on a single MI355X "
@@ -112,6 +115,24 @@ def main():
     tree = g.Tree(keys, vals, 8, leaf_slack=1 << 18, max_batch=1 << 20)
     st = tree.stats()
     stream = torch.cuda.Stream()
+
+    if args.profile:
+        # calibration: a plain copy of exactly 1 GiB (reads 1 GiB, writes 1 GiB)
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        src.fill_(3)
+        BL = 1 << 20
+        qld = tree.dev(synth.present_queries(keys, BL, SEED, purpose=5000))
+        vl = torch.empty(BL, dtype=torch.int64, device=dev)
+        fl = torch.empty(BL, dtype=torch.uint8, device=dev)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            g.tree_lookup_batch(tree.h, qld, vl, fl)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": "done", "copy_bytes": 1 << 30, "lookup_batch": BL}), flush=True)
+        return
 
     B = 1024
     nbatch = 64

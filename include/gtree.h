@@ -71,6 +71,18 @@ typedef struct {
     uint32_t queries_per_group; /* queries a lane group walks at once: 1, 2
                                    or 4; 0 = default (2)                      */
     uint64_t max_batch;       /* largest insert batch; default 2^20           */
+    uint32_t value_coload;    /* 1: a lookup reads the leaf's value line with
+                                 its key line (one dependent load fewer);
+                                 2: it reads the one value after the match;
+                                 0 = default (1)                              */
+    uint32_t xcd_split;       /* 1: large lookup batches are split by key
+                                 range over the 8 XCDs so that each XCD's L2
+                                 holds the inner nodes of its own subtrees;
+                                 2: off; 0 = default (off)                  */
+    uint32_t leaf_stream;     /* 1: leaf lines are read with non-temporal
+                                 loads (they stream and should not evict
+                                 inner nodes); 2: off; 0 = default (off)    */
+    uint32_t reserved;        /* must be 0                                    */
 } gt_params;
 
 typedef struct {

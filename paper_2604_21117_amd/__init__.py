@@ -34,7 +34,9 @@ class GtError(RuntimeError):
 class gt_params(C.Structure):
     _fields_ = [("key_bytes", C.c_uint32), ("fanout", C.c_uint32), ("leaf_cap", C.c_uint32),
                 ("fill", C.c_float), ("lanes_per_query", C.c_uint32), ("lds_levels", C.c_uint32),
-                ("sorted_mode", C.c_uint32), ("queries_per_group", C.c_uint32), ("max_batch", C.c_uint64)]
+                ("sorted_mode", C.c_uint32), ("queries_per_group", C.c_uint32), ("max_batch", C.c_uint64),
+                ("value_coload", C.c_uint32), ("xcd_split", C.c_uint32), ("leaf_stream", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
 
 class gt_tree_stats(C.Structure):
@@ -126,10 +128,12 @@ def key_dtype(key_bytes: int):
 # ------------------------------------------------------------------ C names
 
 def make_params(key_bytes: int, fill: float = 1.0, lanes_per_query: int = 0, lds_levels: int = 0,
-                queries_per_group: int = 0, max_batch: int = 0) -> gt_params:
+                queries_per_group: int = 0, max_batch: int = 0, value_coload: int = 0, xcd_split: int = 0,
+                leaf_stream: int = 0) -> gt_params:
     return gt_params(key_bytes=key_bytes, fanout=16, leaf_cap=16, fill=fill, lanes_per_query=lanes_per_query,
                      lds_levels=lds_levels, sorted_mode=0, queries_per_group=queries_per_group,
-                     max_batch=max_batch)
+                     max_batch=max_batch, value_coload=value_coload, xcd_split=xcd_split,
+                     leaf_stream=leaf_stream, reserved=0)
 
 
 def tree_arena_bytes(params: gt_params, n: int, leaf_slack: int = 0) -> int:

@@ -152,13 +152,41 @@ __global__ __launch_bounds__(256) void k_mirror_refresh(TreeView<K> t) {
             mfirst[m] = f;
         }
     }
+    // XCD splitters: the key space is cut into kXcds ranges of (nearly) equal
+    // numbers of level-2 subtrees (level-1 subtrees for a 3-level tree); the
+    // cut after subtree e is that subtree's upper bound, read from its
+    // parent's separator or, for a last child, from the grandparent's.
+    uint32_t nsplit = 0;
     if (tid == 0) {
+        K* sp = reinterpret_cast<K*>(t.mirror + ML::split_off());
+        const K* rsep = t.ikeys + static_cast<uint64_t>(root) * kSlots;
+        if (levels >= 3 && n2 >= static_cast<uint32_t>(kXcds)) {
+            nsplit = kXcds - 1;
+            for (int x = 0; x < kXcds - 1; ++x) {
+                const uint32_t e = static_cast<uint32_t>((x + 1) * n2 / kXcds - 1);
+                uint32_t p = 0;
+                while (p + 1 < n1 && pre1[p + 1] <= e) ++p;
+                const uint32_t i = e - pre1[p];
+                const uint32_t cnt = pre1[p + 1] - pre1[p];
+                K ub;
+                if (i + 1 < cnt) ub = t.ikeys[static_cast<uint64_t>(ids[1 + p]) * kSlots + i];
+                else ub = (p + 1 < n1) ? rsep[p] : kmax<K>();
+                sp[x] = ub;
+            }
+        } else if (levels >= 2 && n1 >= static_cast<uint32_t>(kXcds)) {
+            nsplit = kXcds - 1;
+            for (int x = 0; x < kXcds - 1; ++x) {
+                const uint32_t e = static_cast<uint32_t>((x + 1) * n1 / kXcds - 1);
+                sp[x] = (e + 1 < n1) ? rsep[e] : kmax<K>();
+            }
+        }
         MirrorHeader* mh = reinterpret_cast<MirrorHeader*>(t.mirror);
         mh->height = height;
         mh->root = root;
         mh->n_keys = n_keys;
         mh->levels = levels;
         mh->nodes = nodes;
+        mh->nsplit = nsplit;
     }
 }
 

@@ -36,6 +36,7 @@ constexpr int kMirrorMaxNodes = 1 + 16 + 256;
 constexpr int kMaxLevels = 16;             // height bound (>= 8 children per inner node)
 constexpr uint32_t kErrCapacity = 0x1u;
 constexpr uint32_t kErrInternal = 0x2u;
+constexpr int kXcds = 8;                   // MI355X: 8 XCDs of 32 CUs, each with its own L2
 
 template <class K>
 __host__ __device__ constexpr K kmax() { return static_cast<K>(~static_cast<K>(0)); }
@@ -60,7 +61,8 @@ struct MirrorHeader {
     uint64_t n_keys;
     uint32_t levels;     // inner levels held (0..3)
     uint32_t nodes;      // nodes held
-    uint32_t pad[10];
+    uint32_t nsplit;     // XCD splitter keys held (7, or 0 for a small tree)
+    uint32_t pad[9];
 };
 static_assert(sizeof(MirrorHeader) == 64, "MirrorHeader size");
 
@@ -71,6 +73,9 @@ struct MirrorLayout {
     static __host__ __device__ constexpr uint32_t child_off(uint32_t n) { return keys_off() + n * kSlots * sizeof(K); }
     static __host__ __device__ constexpr uint32_t first_off(uint32_t n) { return child_off(n) + n * kSlots * 4; }
     static __host__ __device__ constexpr uint32_t bytes(uint32_t n) { return first_off(n) + ((n * 4 + 15) / 16) * 16; }
+    // splitter keys live after the full-size arrays of the global mirror only
+    static __host__ __device__ constexpr uint32_t split_off() { return bytes(kMirrorMaxNodes); }
+    static __host__ __device__ constexpr uint32_t global_bytes() { return split_off() + 8 * sizeof(K); }
 };
 
 // nodes held by the first s levels of a full mirror (1, 17, 273)

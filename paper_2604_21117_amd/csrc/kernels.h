@@ -10,7 +10,12 @@ struct LaunchCfg {
     int lanes;              // lanes per query: 4, 8, 16
     int queries_per_group;  // queries interleaved per lane group: 1, 2, 4
     int lds_levels;         // top inner levels read from LDS: 0..3
+    int value_coload;       // read a leaf's value line together with its key line
+    int xcd_split;          // 0 off, 1 on from kXcdMinBatch queries, 2 always
+    int leaf_stream;        // non-temporal leaf loads
 };
+
+constexpr uint64_t kXcdMinBatch = 1u << 15;
 
 template <class K>
 void launch_lookup(const TreeView<K>& t, const LaunchCfg& cfg, const K* q, uint64_t B, K* vout, uint8_t* fout,

@@ -24,11 +24,58 @@ namespace gt {
 
 constexpr int kLookupBlock = 256;
 
-template <class K, int G, int QPG, int LV>
+// Leaf stage shared by the lookup kernels: match the key line, take the
+// value (from the co-loaded value line, or by one dependent read), write the
+// result of every live query.
+template <class K, int G, int QPG, bool VC, bool NT>
+__device__ __forceinline__ void finish_lookups(const TreeView<K>& t, const K (&key)[QPG], const uint32_t (&leaf)[QPG],
+                                               const uint64_t (&qi)[QPG], bool empty, int gl, int gbase,
+                                               K* __restrict__ vout, uint8_t* __restrict__ fout) {
+    using T = Trav<K, G>;
+    typename T::KV kv[QPG];
+    typename T::KV vv[QPG];
+#pragma unroll
+    for (int j = 0; j < QPG; ++j) {
+        const K* kl = t.lkeys + static_cast<uint64_t>(leaf[j]) * kSlots;
+        const K* vl = t.lvals + static_cast<uint64_t>(leaf[j]) * kSlots;
+        if constexpr (NT) {
+            kv[j] = T::load_keys_nt(kl, gl);
+            if constexpr (VC) vv[j] = T::load_keys_nt(vl, gl);
+        } else {
+            kv[j] = T::load_keys(kl, gl);
+            if constexpr (VC) vv[j] = T::load_keys(vl, gl);
+        }
+    }
+    uint32_t slot[QPG];
+#pragma unroll
+    for (int j = 0; j < QPG; ++j) slot[j] = T::match_slot(kv[j], key[j], gbase);
+    K val[QPG];
+    bool hit[QPG];
+#pragma unroll
+    for (int j = 0; j < QPG; ++j) {
+        hit[j] = slot[j] < kSlots && !empty;
+        val[j] = kmax<K>();
+        if constexpr (VC) {
+            const K x = T::pick_value(vv[j], hit[j] ? slot[j] : 0u, gbase);
+            if (hit[j]) val[j] = x;
+        } else {
+            if (gl == (j % G) && qi[j] != ~0ull && hit[j])
+                val[j] = t.lvals[static_cast<uint64_t>(leaf[j]) * kSlots + slot[j]];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < QPG; ++j) {
+        if (gl == (j % G) && qi[j] != ~0ull) {
+            vout[qi[j]] = val[j];
+            fout[qi[j]] = hit[j] ? 1 : 0;
+        }
+    }
+}
+
+template <class K, int G, int QPG, int LV, bool VC, bool NT>
 __global__ __launch_bounds__(kLookupBlock) void k_lookup(TreeView<K> t, const K* __restrict__ q, uint64_t B,
                                                           K* __restrict__ vout, uint8_t* __restrict__ fout,
                                                           uint64_t ntiles) {
-    using T = Trav<K, G>;
     extern __shared__ __align__(16) uint8_t lds[];
     const uint8_t* mir = t.mirror;
     uint32_t mnodes = kMirrorMaxNodes;
@@ -49,32 +96,89 @@ __global__ __launch_bounds__(kLookupBlock) void k_lookup(TreeView<K> t, const K*
         uint64_t qi[QPG];
 #pragma unroll
         for (int j = 0; j < QPG; ++j) {
-            qi[j] = tile * tile_q + group * QPG + j;
-            key[j] = qi[j] < B ? q[qi[j]] : K(0);
+            const uint64_t x = tile * tile_q + group * QPG + j;
+            key[j] = x < B ? q[x] : K(0);
+            qi[j] = x < B ? x : ~0ull;
         }
         uint32_t leaf[QPG];
         descend<K, G, QPG, false>(t, mir, mnodes, LV, key, leaf, gl, gbase);
-        typename T::KV kv[QPG];
+        finish_lookups<K, G, QPG, VC, NT>(t, key, leaf, qi, empty, gl, gbase, vout, fout);
+    }
+}
+
+// XCD-split lookup for large batches.  Workgroup w runs on XCD w % 8 (the
+// dispatcher deals workgroups to XCDs round-robin).  Each workgroup reads
+// a chunk of the batch, keeps the queries whose key lies in its XCD's key
+// range (seven splitter keys cut the tree into eight runs of level-2
+// subtrees) and walks only those, so the inner nodes an XCD touches are
+// one eighth of the tree and stay in its own L2.  Every chunk is read by
+// eight workgroups; results are written by query index, so the output is
+// the same as the plain kernel's.
+constexpr uint32_t kXcdChunk = 1024;
+
+template <class K, int G, int QPG, bool VC, bool NT>
+__global__ __launch_bounds__(kLookupBlock) void k_lookup_xcd(TreeView<K> t, const K* __restrict__ q, uint64_t B,
+                                                              K* __restrict__ vout, uint8_t* __restrict__ fout,
+                                                              uint64_t nchunks) {
+    constexpr int LV = 2;
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ K ck[kXcdChunk];
+    __shared__ uint32_t ci[kXcdChunk];
+    __shared__ uint32_t ccount;
+    const uint32_t mnodes = mirror_nodes_for_levels(LV);
+    stage_mirror<K>(t.mirror, lds, mnodes);
+    const MirrorHeader* gmh = reinterpret_cast<const MirrorHeader*>(t.mirror);
+    const K* sp = reinterpret_cast<const K*>(t.mirror + MirrorLayout<K>::split_off());
+    const uint32_t nsplit = gmh->nsplit;
+    K split[kXcds - 1];
 #pragma unroll
-        for (int j = 0; j < QPG; ++j) kv[j] = T::load_keys(t.lkeys + static_cast<uint64_t>(leaf[j]) * kSlots, gl);
-        uint32_t slot[QPG];
+    for (int x = 0; x < kXcds - 1; ++x) split[x] = sp[x];
+    __syncthreads();
+    const MirrorHeader* mh = reinterpret_cast<const MirrorHeader*>(lds);
+    const bool empty = mh->n_keys == 0;
+    const uint32_t xcd = blockIdx.x % kXcds;
+    const uint64_t slot0 = blockIdx.x / kXcds, nslots = gridDim.x / kXcds;
+    const int lane = lane_id();
+    const int gl = lane % G, gbase = lane - gl;
+    const uint32_t group = threadIdx.x / G;
+    constexpr uint32_t tile_q = (kLookupBlock / G) * QPG;
+    for (uint64_t c = slot0; c < nchunks; c += nslots) {
+        if (threadIdx.x == 0) ccount = 0;
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < kXcdChunk; i += kLookupBlock) {
+            const uint64_t qi = c * kXcdChunk + i;
+            if (qi < B) {
+                const K key = q[qi];
+                uint32_t b = 0;
+                if (nsplit) {
 #pragma unroll
-        for (int j = 0; j < QPG; ++j) slot[j] = T::match_slot(kv[j], key[j], gbase);
-        K val[QPG];
-        bool hit[QPG];
-#pragma unroll
-        for (int j = 0; j < QPG; ++j) {
-            hit[j] = slot[j] < kSlots && !empty;
-            val[j] = kmax<K>();
-            if (gl == (j % G) && qi[j] < B && hit[j]) val[j] = t.lvals[static_cast<uint64_t>(leaf[j]) * kSlots + slot[j]];
-        }
-#pragma unroll
-        for (int j = 0; j < QPG; ++j) {
-            if (gl == (j % G) && qi[j] < B) {
-                vout[qi[j]] = val[j];
-                fout[qi[j]] = hit[j] ? 1 : 0;
+                    for (int x = 0; x < kXcds - 1; ++x) b += split[x] < key ? 1u : 0u;
+                } else {
+                    b = static_cast<uint32_t>(qi % kXcds);
+                }
+                if (b == xcd) {
+                    const uint32_t pos = atomicAdd(&ccount, 1u);
+                    ck[pos] = key;
+                    ci[pos] = static_cast<uint32_t>(i);
+                }
             }
         }
+        __syncthreads();
+        const uint32_t n = ccount;
+        for (uint32_t t0 = 0; t0 < n; t0 += tile_q) {
+            K key[QPG];
+            uint64_t qi[QPG];
+#pragma unroll
+            for (int j = 0; j < QPG; ++j) {
+                const uint32_t e = t0 + group * QPG + j;
+                key[j] = e < n ? ck[e] : K(0);
+                qi[j] = e < n ? c * kXcdChunk + ci[e] : ~0ull;
+            }
+            uint32_t leaf[QPG];
+            descend<K, G, QPG, false>(t, lds, mnodes, LV, key, leaf, gl, gbase);
+            finish_lookups<K, G, QPG, VC, NT>(t, key, leaf, qi, empty, gl, gbase, vout, fout);
+        }
+        __syncthreads();
     }
 }
 
@@ -175,23 +279,55 @@ static uint64_t grid_for(uint64_t ntiles, int lv, int key_bytes) {
     return ntiles < cap ? (ntiles < 1 ? 1 : ntiles) : cap;
 }
 
-template <class K, int G, int QPG, int LV>
+template <class K, int G, int QPG, int LV, bool VC, bool NT>
 static void launch_lookup_t(const TreeView<K>& t, const K* q, uint64_t B, K* vout, uint8_t* fout, hipStream_t s) {
     const uint64_t tile_q = static_cast<uint64_t>(kLookupBlock / G) * QPG;
     const uint64_t ntiles = (B + tile_q - 1) / tile_q;
     const uint64_t grid = grid_for(ntiles, LV, sizeof(K));
-    hipLaunchKernelGGL((k_lookup<K, G, QPG, LV>), dim3(static_cast<uint32_t>(grid)), dim3(kLookupBlock),
+    hipLaunchKernelGGL((k_lookup<K, G, QPG, LV, VC, NT>), dim3(static_cast<uint32_t>(grid)), dim3(kLookupBlock),
                        lds_bytes_for(LV, sizeof(K)), s, t, q, B, vout, fout, ntiles);
 }
 
+template <class K, int G, int QPG, bool VC, bool NT>
+static void launch_lookup_xcd(const TreeView<K>& t, const K* q, uint64_t B, K* vout, uint8_t* fout, hipStream_t s) {
+    const uint64_t nchunks = (B + kXcdChunk - 1) / kXcdChunk;
+    // eight resident workgroups per CU, 32 CUs per XCD
+    const uint64_t slots = nchunks < 256 ? nchunks : 256;
+    hipLaunchKernelGGL((k_lookup_xcd<K, G, QPG, VC, NT>), dim3(static_cast<uint32_t>(slots * kXcds)),
+                       dim3(kLookupBlock), lds_bytes_for(2, sizeof(K)), s, t, q, B, vout, fout, nchunks);
+}
+
+template <class K, int G, int QPG, int LV>
+static void launch_lookup_v(const TreeView<K>& t, const LaunchCfg& cfg, const K* q, uint64_t B, K* vout,
+                            uint8_t* fout, hipStream_t s) {
+    const bool xcd = cfg.xcd_split == 2 || (cfg.xcd_split == 1 && B >= kXcdMinBatch);
+    if (xcd) {
+        if (cfg.value_coload) {
+            if (cfg.leaf_stream) launch_lookup_xcd<K, G, QPG, true, true>(t, q, B, vout, fout, s);
+            else launch_lookup_xcd<K, G, QPG, true, false>(t, q, B, vout, fout, s);
+        } else {
+            if (cfg.leaf_stream) launch_lookup_xcd<K, G, QPG, false, true>(t, q, B, vout, fout, s);
+            else launch_lookup_xcd<K, G, QPG, false, false>(t, q, B, vout, fout, s);
+        }
+        return;
+    }
+    if (cfg.value_coload) {
+        if (cfg.leaf_stream) launch_lookup_t<K, G, QPG, LV, true, true>(t, q, B, vout, fout, s);
+        else launch_lookup_t<K, G, QPG, LV, true, false>(t, q, B, vout, fout, s);
+    } else {
+        if (cfg.leaf_stream) launch_lookup_t<K, G, QPG, LV, false, true>(t, q, B, vout, fout, s);
+        else launch_lookup_t<K, G, QPG, LV, false, false>(t, q, B, vout, fout, s);
+    }
+}
+
 template <class K, int G, int QPG>
-static void launch_lookup_lv(const TreeView<K>& t, int lv, const K* q, uint64_t B, K* vout, uint8_t* fout,
-                             hipStream_t s) {
-    switch (lv) {
-        case 0: launch_lookup_t<K, G, QPG, 0>(t, q, B, vout, fout, s); break;
-        case 1: launch_lookup_t<K, G, QPG, 1>(t, q, B, vout, fout, s); break;
-        case 2: launch_lookup_t<K, G, QPG, 2>(t, q, B, vout, fout, s); break;
-        default: launch_lookup_t<K, G, QPG, 3>(t, q, B, vout, fout, s); break;
+static void launch_lookup_lv(const TreeView<K>& t, const LaunchCfg& cfg, const K* q, uint64_t B, K* vout,
+                             uint8_t* fout, hipStream_t s) {
+    switch (cfg.lds_levels) {
+        case 0: launch_lookup_v<K, G, QPG, 0>(t, cfg, q, B, vout, fout, s); break;
+        case 1: launch_lookup_v<K, G, QPG, 1>(t, cfg, q, B, vout, fout, s); break;
+        case 2: launch_lookup_v<K, G, QPG, 2>(t, cfg, q, B, vout, fout, s); break;
+        default: launch_lookup_v<K, G, QPG, 3>(t, cfg, q, B, vout, fout, s); break;
     }
 }
 
@@ -201,19 +337,19 @@ void launch_lookup(const TreeView<K>& t, const LaunchCfg& cfg, const K* q, uint6
     const int qpg = cfg.queries_per_group;
     switch (cfg.lanes) {
         case 4:
-            if (qpg >= 4) launch_lookup_lv<K, 4, 4>(t, cfg.lds_levels, q, B, vout, fout, s);
-            else if (qpg == 2) launch_lookup_lv<K, 4, 2>(t, cfg.lds_levels, q, B, vout, fout, s);
-            else launch_lookup_lv<K, 4, 1>(t, cfg.lds_levels, q, B, vout, fout, s);
+            if (qpg >= 4) launch_lookup_lv<K, 4, 4>(t, cfg, q, B, vout, fout, s);
+            else if (qpg == 2) launch_lookup_lv<K, 4, 2>(t, cfg, q, B, vout, fout, s);
+            else launch_lookup_lv<K, 4, 1>(t, cfg, q, B, vout, fout, s);
             break;
         case 16:
-            if (qpg >= 4) launch_lookup_lv<K, 16, 4>(t, cfg.lds_levels, q, B, vout, fout, s);
-            else if (qpg == 2) launch_lookup_lv<K, 16, 2>(t, cfg.lds_levels, q, B, vout, fout, s);
-            else launch_lookup_lv<K, 16, 1>(t, cfg.lds_levels, q, B, vout, fout, s);
+            if (qpg >= 4) launch_lookup_lv<K, 16, 4>(t, cfg, q, B, vout, fout, s);
+            else if (qpg == 2) launch_lookup_lv<K, 16, 2>(t, cfg, q, B, vout, fout, s);
+            else launch_lookup_lv<K, 16, 1>(t, cfg, q, B, vout, fout, s);
             break;
         default:
-            if (qpg >= 4) launch_lookup_lv<K, 8, 4>(t, cfg.lds_levels, q, B, vout, fout, s);
-            else if (qpg == 2) launch_lookup_lv<K, 8, 2>(t, cfg.lds_levels, q, B, vout, fout, s);
-            else launch_lookup_lv<K, 8, 1>(t, cfg.lds_levels, q, B, vout, fout, s);
+            if (qpg >= 4) launch_lookup_lv<K, 8, 4>(t, cfg, q, B, vout, fout, s);
+            else if (qpg == 2) launch_lookup_lv<K, 8, 2>(t, cfg, q, B, vout, fout, s);
+            else launch_lookup_lv<K, 8, 1>(t, cfg, q, B, vout, fout, s);
             break;
     }
 }

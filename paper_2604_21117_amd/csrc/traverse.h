@@ -21,11 +21,48 @@
 
 namespace gt {
 
+// Load n elements of T (n * sizeof(T) = 4, 8, 16 or 32 bytes, naturally
+// aligned) with 4/8/16-byte vector loads into registers.
+template <class T, int N>
+__device__ __forceinline__ void load_vec(const T* p, T (&out)[N]) {
+    constexpr int bytes = N * static_cast<int>(sizeof(T));
+    if constexpr (bytes >= 16) {
+#pragma unroll
+        for (int c = 0; c < bytes / 16; ++c) {
+            const uint4 x = reinterpret_cast<const uint4*>(p)[c];
+            __builtin_memcpy(&out[c * (16 / sizeof(T))], &x, 16);
+        }
+    } else if constexpr (bytes == 8) {
+        const uint2 x = *reinterpret_cast<const uint2*>(p);
+        __builtin_memcpy(&out[0], &x, 8);
+    } else {
+        const uint32_t x = *reinterpret_cast<const uint32_t*>(p);
+        __builtin_memcpy(&out[0], &x, 4);
+    }
+}
+
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+// As load_vec, with non-temporal loads (streamed lines, low cache priority).
+template <class T, int N>
+__device__ __forceinline__ void load_vec_nt(const T* p, T (&out)[N]) {
+    constexpr int bytes = N * static_cast<int>(sizeof(T));
+    if constexpr (bytes >= 16) {
+#pragma unroll
+        for (int c = 0; c < bytes / 16; ++c) {
+            const u32x4_t x = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(p) + c);
+            __builtin_memcpy(&out[c * (16 / sizeof(T))], &x, 16);
+        }
+    } else {
+        load_vec<T, N>(p, out);
+    }
+}
+
 template <class K, int G>
 struct Trav {
     static constexpr int KPL = kSlots / G;
-    using KV = VecN<K, KPL>;
-    using CV = VecN<uint32_t, KPL>;
+    struct KV { K v[KPL]; };
+    struct CV { uint32_t v[KPL]; };
 
     // child index = number of separators below `key` in the group's line
     static __device__ __forceinline__ uint32_t child_index(const KV& kv, K key, int gbase) {
@@ -48,6 +85,16 @@ struct Trav {
         return shfl_u32(mine, gbase + static_cast<int>(idx / KPL));
     }
 
+    // value in slot `slot` of a line held KPL-per-lane by the group
+    static __device__ __forceinline__ K pick_value(const KV& vv, uint32_t slot, int gbase) {
+        uint32_t e = slot % KPL;
+        K mine = vv.v[0];
+#pragma unroll
+        for (int j = 1; j < KPL; ++j)
+            if (e == static_cast<uint32_t>(j)) mine = vv.v[j];
+        return __shfl(mine, gbase + static_cast<int>(slot / KPL), 64);
+    }
+
     // first slot whose key equals `key`, or 16 if none
     static __device__ __forceinline__ uint32_t match_slot(const KV& kv, K key, int gbase) {
         uint32_t best = kSlots;
@@ -63,10 +110,19 @@ struct Trav {
     }
 
     static __device__ __forceinline__ KV load_keys(const K* line, int gl) {
-        return *reinterpret_cast<const KV*>(line + gl * KPL);
+        KV r;
+        load_vec<K, KPL>(line + gl * KPL, r.v);
+        return r;
+    }
+    static __device__ __forceinline__ KV load_keys_nt(const K* line, int gl) {
+        KV r;
+        load_vec_nt<K, KPL>(line + gl * KPL, r.v);
+        return r;
     }
     static __device__ __forceinline__ CV load_child(const uint32_t* line, int gl) {
-        return *reinterpret_cast<const CV*>(line + gl * KPL);
+        CV r;
+        load_vec<uint32_t, KPL>(line + gl * KPL, r.v);
+        return r;
     }
 };
 

@@ -56,6 +56,7 @@ bool params_ok(const gt_params* p) {
         p->queries_per_group != 4)
         return false;
     if (p->sorted_mode != 0) return false;
+    if (p->value_coload > 2 || p->xcd_split > 2 || p->leaf_stream > 2 || p->reserved != 0) return false;
     return true;
 }
 
@@ -66,7 +67,7 @@ uint64_t leaf_rec_bytes(int kb) { return 2ull * kSlots * kb + 8; }
 uint64_t inner_rec_bytes(int kb) { return static_cast<uint64_t>(kSlots) * (kb + 4); }
 
 uint64_t mirror_bytes(int kb) {
-    return align_up(kb == 8 ? MirrorLayout<uint64_t>::bytes(kMirrorMaxNodes) : MirrorLayout<uint32_t>::bytes(kMirrorMaxNodes));
+    return align_up(kb == 8 ? MirrorLayout<uint64_t>::global_bytes() : MirrorLayout<uint32_t>::global_bytes());
 }
 
 // nodes a level of `items` entries packs into (cap per node after fill, at
@@ -261,6 +262,9 @@ gt_status tree_build(const gt_params* p, const void* keys, const void* values, u
     t->cfg.lanes = p->lanes_per_query ? static_cast<int>(p->lanes_per_query) : 8;
     t->cfg.queries_per_group = p->queries_per_group ? static_cast<int>(p->queries_per_group) : 2;
     t->cfg.lds_levels = p->lds_levels == 0 ? 2 : (p->lds_levels == 4 ? 0 : static_cast<int>(p->lds_levels));
+    t->cfg.value_coload = p->value_coload == 2 ? 0 : 1;
+    t->cfg.xcd_split = p->xcd_split == 1 ? 1 : 0;
+    t->cfg.leaf_stream = p->leaf_stream == 1 ? 1 : 0;
     layout(t, reinterpret_cast<uint8_t*>(arena), lo);
     gt_status st = kb == 8 ? build_t<uint64_t>(t, keys, values, n, stream)
                            : build_t<uint32_t>(t, keys, values, n, stream);

@@ -69,7 +69,8 @@ def test_insert_sequences(width, n, batches):
     sk = np.sort(sa.keys).astype(keys.dtype)
     if len(sk):
         lo = sk[rng.integers(0, len(sk), 200)]
-        hi = np.minimum(lo.astype(np.float64) * 1.01 + 1000, float(top)).astype(keys.dtype)
+        span = (rng.integers(0, 1 << 20, 200).astype(np.uint64) << np.uint64(width - 24)).astype(keys.dtype)
+        hi = np.where(lo > top - span, top, lo + span).astype(keys.dtype)
         mc = rng.integers(1, 80, 200).astype(np.uint32)
         assert_range_parity(t, sa, lo, hi, mc)
 

@@ -51,12 +51,14 @@ def test_c1_closed_form_node_count():
 @pytest.mark.parametrize("lanes", [4, 8, 16])
 @pytest.mark.parametrize("qpg", [1, 2, 4])
 @pytest.mark.parametrize("lds", [1, 2, 3, 4])
-def test_launch_configs_agree(lanes, qpg, lds):
+@pytest.mark.parametrize("vc", [1, 2])
+def test_launch_configs_agree(lanes, qpg, lds, vc):
     width, seed = 64, 7
     keys = key_set(70000, width, seed, edges=True)
     vals = synth.values_for(keys, seed, width)
     sa = oracle.SortedArray(keys, vals, width)
-    t = mk_tree(keys, vals, 8, max_batch=4096, lanes_per_query=lanes, queries_per_group=qpg, lds_levels=lds)
+    t = mk_tree(keys, vals, 8, max_batch=4096, lanes_per_query=lanes, queries_per_group=qpg, lds_levels=lds,
+                value_coload=vc)
     q = synth.mixed_queries(keys, 5003, seed, width)
     q[:2] = [0, np.iinfo(np.uint64).max]
     assert_lookup_parity(t, sa, q)
@@ -101,3 +103,20 @@ def test_duplicate_queries_and_all_present():
     assert_lookup_parity(t, sa, keys)          # every key once
     gv, gf = t.lookup(keys)
     assert gf.all() and np.array_equal(gv, synth.values_for(keys, seed, width))
+
+
+@pytest.mark.parametrize("width", [32, 64])
+@pytest.mark.parametrize("n", [5, 300, 3000, 200000])
+@pytest.mark.parametrize("xcd,stream", [(1, 2), (1, 1), (2, 2)])
+def test_large_batch_paths(width, n, xcd, stream):
+    """Batches above the XCD-split threshold (2^15): the split kernel, with
+    and without streaming leaf loads, agrees bit for bit with the oracle,
+    for trees with and without splitter keys."""
+    seed = 50 + n
+    keys = key_set(n, width, seed, edges=True)
+    vals = synth.values_for(keys, seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, width // 8, max_batch=4096, xcd_split=xcd, leaf_stream=stream)
+    q = synth.mixed_queries(keys, 70001, seed, width)
+    q[:3] = [0, np.iinfo(keys.dtype).max, keys[0]]
+    assert_lookup_parity(t, sa, q)
