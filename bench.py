@@ -3,18 +3,24 @@
 
 Workload: 2^24 distinct uniform u64 keys (seed 2), values hash64(key ^ 2),
 bulk-loaded at fill 1.0 (fanout 16, 16 keys per leaf, height 6), resident in
-HBM.  A timed step is one lookup batch of B = 1024 keys drawn uniformly from
-the present keys, already in HBM; `value` is lookups per second over the K
-timed steps (whole job, one GPU), `ms_per_step` the time per batch.
+HBM, with a learned index of 1024 models trained on it.  A timed step is one
+lookup batch of B = 1024 keys drawn uniformly from the present keys (inputs
+already in HBM), through the learned index (`--path plain`: the tree).
+`value` is lookups per second over the K timed steps, `ms_per_step` the time
+per batch.  The other path is timed the same way and reported beside it.
 
-Also reported, measured in the same run outside the K timed steps:
-  sweep          device time per lookup batch for B = 1, 8, 64, 256, 1024
-                 (uniform and Zipf(0.99) queries)
-  large_batch    one 2^20-key lookup batch (cold and warm)
-  roofline       the lookup kernel at B = 2^20: algorithmic bytes per launch
-                 over its average duration (HIP events on its own stream)
-  cpu_baseline   the oracle's pointer B+-tree on the host cores, a bounded
-                 sample of the same B = 1024 batches
+Also measured in the same run, outside the K timed steps:
+  sweep           device time per lookup batch, B = 1..1024, uniform and
+                  Zipf(0.99) queries, plain and learned
+  large_batch     2^20-key lookup batches (warm; `--cold` adds flushed runs)
+  roofline        the large-batch lookup kernel: algorithmic bytes per launch
+                  over its average duration (HIP events on its stream)
+  insert          fresh-key insert batches, B = 1024 and 2^20
+  range           range batches, B = 1024, max U{1..100}
+  learned_stale   learned lookups after the inserts, then after retraining
+  serving         2000 batches B ~ U{1..1024}, 80/15/5 lookup/insert/range,
+                  Zipf keys, Poisson arrivals at half the closed-loop rate
+  cpu_baseline    the oracle's pointer B+-tree on the host cores
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -39,38 +45,36 @@ SEED = 2
 
 
 def iqm(x):
+    """Mean of the central half of the sample (sample trimmed to a multiple
+    of 4)."""
     s = np.sort(np.asarray(x, dtype=np.float64))
     n = len(s) - len(s) % 4
-    s = s[:n] if n else s
+    s = s[:n] if n >= 4 else s
     q = len(s) // 4
     return float(s[q:len(s) - q].mean()) if len(s) >= 4 else float(s.mean())
 
 
 def algorithmic_bytes(sorted_keys: np.ndarray, q: np.ndarray, height: int, hits: int, kb: int = 8) -> dict:
-    """Bytes a lookup batch must move: every distinct node it visits once
-    (inner node = key line + child line, leaf = key line), plus the value
-    of each hit and the batch's input keys and outputs.  Exact for the
-    bulk-loaded tree at fill 1.0 with 16 keys per leaf, where the leaf of
-    the key of rank r is r // 16 and its level-l ancestor r // 16^(h-l)."""
-    ranks = np.searchsorted(sorted_keys, q)
-    ranks = np.minimum(ranks, len(sorted_keys) - 1).astype(np.int64)
-    leaf = ranks // 16
-    per_level = []
-    node = leaf
-    per_level.append(len(np.unique(node)))
+    """Bytes a lookup batch must move: each distinct node it visits once
+    (inner node = key line + child line, leaf = key line), the value of each
+    hit, and the batch's keys in and results out.  Exact for the bulk-loaded
+    tree at fill 1.0 with 16 keys per leaf: the key of rank r sits in leaf
+    r // 16, whose ancestor d levels up is r // 16^(d+1)."""
+    ranks = np.minimum(np.searchsorted(sorted_keys, q), len(sorted_keys) - 1).astype(np.int64)
+    node = ranks // 16
+    per_level = [len(np.unique(node))]
     for _ in range(height - 1):
         node = node // 16
         per_level.append(len(np.unique(node)))
-    per_level = per_level[::-1]  # root first
-    inner_bytes = sum(per_level[:-1]) * (16 * kb + 64)
-    leaf_bytes = per_level[-1] * 16 * kb
+    per_level = per_level[::-1]
+    inner = sum(per_level[:-1]) * (16 * kb + 64)
+    leaf = per_level[-1] * 16 * kb
     io = len(q) * (kb + kb + 1) + hits * kb
-    return {"distinct_nodes_per_level": per_level, "bytes": int(inner_bytes + leaf_bytes + io)}
+    return {"distinct_nodes_per_level": per_level, "bytes": int(inner + leaf + io)}
 
 
-def cpu_baseline(keys, vals, batches, budget_s=12.0):
+def cpu_baseline(keys, vals, batches, threads, budget_s=10.0):
     import oracle
-    threads = len(os.sched_getaffinity(0))
     pt = oracle.PointerTree(16, 16, 64)
     pt.bulk_load(keys, vals)
     done = 0
@@ -82,9 +86,29 @@ def cpu_baseline(keys, vals, batches, budget_s=12.0):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": done / dt / 1e6, "unit": "Mops/s", "cores": threads, "kind": "oracle",
+    return {"value": round(done / dt / 1e6, 3), "unit": "Mops/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} lookups in batches of {len(batches[0])} on the oracle's pointer B+-tree "
-                      f"(2^{N_LOG2} keys), batch split evenly over {threads} threads, {dt:.1f} s"}
+                      f"(2^{N_LOG2} keys), each batch split evenly over {threads} threads, {dt:.1f} s"}
+
+
+class Timer:
+    """HIP events recorded on the stream the work is launched on."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+
+    def run(self, fn, reps, skip=2):
+        ts = []
+        for r in range(reps):
+            e0 = self.torch.cuda.Event(enable_timing=True)
+            e1 = self.torch.cuda.Event(enable_timing=True)
+            e0.record(self.stream)
+            fn()
+            e1.record(self.stream)
+            e1.synchronize()
+            if r >= skip:
+                ts.append(e0.elapsed_time(e1) * 1e3)
+        return ts
 
 
 def main():
@@ -92,11 +116,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--path", choices=("learned", "plain"), default="learned")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--cold", action="store_true", help="also time flushed (cold-cache) 2^20 batches")
     ap.add_argument("--log2n", type=int, default=N_LOG2)
     ap.add_argument("--profile", action="store_true",
-                    help="counter-collection mode: a 1 GiB device copy (calibration) and 2^20-key lookup "
-                         "batches, three each, then exit")
+                    help="counter-collection mode: a 1 GiB device copy (calibration) and three 2^20-key "
+                         "lookup batches, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the tree runs on a single MI355X "
@@ -107,32 +134,45 @@ def main():
     import paper_2604_21117_amd as g
 
     dev = "cuda"
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    timer = Timer(torch, stream)
     n = 1 << args.log2n
     keys = synth.uniform_keys(n, SEED, 64)
     vals = synth.values_for(keys, SEED, 64)
     skeys = np.sort(keys)
+    print(f"[bench] {n} keys ready", file=sys.stderr, flush=True)
 
-    tree = g.Tree(keys, vals, 8, leaf_slack=1 << 18, max_batch=1 << 20)
+    t0 = time.perf_counter()
+    tree = g.Tree(keys, vals, 8, leaf_slack=(1 << 20) + (1 << 18), max_batch=1 << 20)
+    build_s = time.perf_counter() - t0
     st = tree.stats()
-    stream = torch.cuda.Stream()
+    BL = 1 << 20
+    ql_np = synth.present_queries(keys, BL, SEED, purpose=5000)
+    qld = tree.dev(ql_np)
+    vl = torch.empty(BL, dtype=torch.int64, device=dev)
+    fl = torch.empty(BL, dtype=torch.uint8, device=dev)
 
     if args.profile:
-        # calibration: a plain copy of exactly 1 GiB (reads 1 GiB, writes 1 GiB)
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         src.fill_(3)
-        BL = 1 << 20
-        qld = tree.dev(synth.present_queries(keys, BL, SEED, purpose=5000))
-        vl = torch.empty(BL, dtype=torch.int64, device=dev)
-        fl = torch.empty(BL, dtype=torch.uint8, device=dev)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
         for _ in range(3):
-            g.tree_lookup_batch(tree.h, qld, vl, fl)
+            g.tree_lookup_batch(tree.h, qld, vl, fl, stream)
         torch.cuda.synchronize()
         print(json.dumps({"profile": "done", "copy_bytes": 1 << 30, "lookup_batch": BL}), flush=True)
         return
+
+    t0 = time.perf_counter()
+    li = g.Learned(tree, models=1024)
+    li.train()
+    train_s = time.perf_counter() - t0
+    lst = li.stats()
+    print(f"[bench] tree built in {build_s:.2f} s, learned index trained in {train_s:.2f} s", file=sys.stderr,
+          flush=True)
 
     B = 1024
     nbatch = 64
@@ -141,82 +181,160 @@ def main():
     vo = torch.empty(B, dtype=torch.int64, device=dev)
     fo = torch.empty(B, dtype=torch.uint8, device=dev)
 
-    # correctness spot check of the timed path against the generator's closed
-    # form (present keys return hash64(key ^ seed))
-    with torch.cuda.stream(stream):
-        g.tree_lookup_batch(tree.h, qd[0], vo, fo, stream)
-    stream.synchronize()
-    assert g.to_numpy(fo).all() and np.array_equal(g.to_numpy(vo, np.uint64), synth.values_for(qs[0], SEED, 64))
+    def plain_step(i):
+        g.tree_lookup_batch(tree.h, qd[i % nbatch], vo, fo, stream)
 
-    # ---- timed steps: B = 1024 lookup batches, back to back on one stream
-    with torch.cuda.stream(stream):
-        for i in range(args.warmup):
-            g.tree_lookup_batch(tree.h, qd[i % nbatch], vo, fo, stream)
-    stream.synchronize()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    with torch.cuda.stream(stream):
-        for i in range(args.steps):
-            g.tree_lookup_batch(tree.h, qd[i % nbatch], vo, fo, stream)
-    stream.synchronize()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    def learned_step(i):
+        g.li_lookup_batch(li.h, qd[i % nbatch], vo, fo, stream)
+
+    # both paths answer the generator's closed form on a sample batch
+    for step in (plain_step, learned_step):
+        step(0)
+        stream.synchronize()
+        assert g.to_numpy(fo).all() and np.array_equal(g.to_numpy(vo, np.uint64),
+                                                       synth.values_for(qs[0], SEED, 64))
+
+    def timed_steps(step, steps, warmup):
+        for i in range(warmup):
+            step(i)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(i)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    main_step = learned_step if args.path == "learned" else plain_step
+    other_step = plain_step if args.path == "learned" else learned_step
+    elapsed = timed_steps(main_step, args.steps, args.warmup)
+    other_elapsed = timed_steps(other_step, args.steps, args.warmup)
     ms_per_step = elapsed * 1e3 / args.steps
     value = args.steps * B / elapsed / 1e6
+    other_value = args.steps * B / other_elapsed / 1e6
+    print(f"[bench] timed steps done: {args.path} {value:.1f} Mops/s", file=sys.stderr, flush=True)
 
-    # ---- per-batch device time sweep (events on the launch stream)
+    # ---- per-batch device-time sweep
     zipf = synth.Zipf(n, 0.99, SEED)
     sweep = {}
     for dist in ("uniform", "zipf"):
-        sweep[dist] = {}
         for b in (1, 8, 64, 256, 1024):
-            if dist == "uniform":
-                q = synth.present_queries(keys, b, SEED, purpose=3000 + b)
-            else:
-                q = keys[zipf.indices(b)]
+            q = synth.present_queries(keys, b, SEED, purpose=3000 + b) if dist == "uniform" else \
+                keys[zipf.indices(b)]
             qdv = tree.dev(q)
             v2 = torch.empty(b, dtype=torch.int64, device=dev)
             f2 = torch.empty(b, dtype=torch.uint8, device=dev)
-            ts = []
-            for rep in range(110):
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                with torch.cuda.stream(stream):
-                    e0.record(stream)
-                    g.tree_lookup_batch(tree.h, qdv, v2, f2, stream)
-                    e1.record(stream)
-                e1.synchronize()
-                if rep >= 10:
-                    ts.append(e0.elapsed_time(e1) * 1e3)
-            us = iqm(ts)
-            sweep[dist][str(b)] = {"us_per_batch": round(us, 3), "mops": round(b / us, 3)}
+            row = {}
+            for path in ("plain", "learned"):
+                fn = (lambda: g.tree_lookup_batch(tree.h, qdv, v2, f2, stream)) if path == "plain" else \
+                    (lambda: g.li_lookup_batch(li.h, qdv, v2, f2, stream))
+                us = iqm(timer.run(fn, 104, skip=4))
+                row[path] = {"us_per_batch": round(us, 3), "mops": round(b / us, 2)}
+            row["learned_speedup"] = round(row["plain"]["us_per_batch"] / row["learned"]["us_per_batch"], 3)
+            sweep.setdefault(dist, {})[str(b)] = row
+    print("[bench] sweep done", file=sys.stderr, flush=True)
 
-    # ---- large batch: roofline of the lookup kernel
-    BL = 1 << 20
-    ql = synth.present_queries(keys, BL, SEED, purpose=5000)
-    qld = tree.dev(ql)
-    vl = torch.empty(BL, dtype=torch.int64, device=dev)
-    fl = torch.empty(BL, dtype=torch.uint8, device=dev)
-    flush = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
-    cold, warm = [], []
-    for rep in range(24):
-        if rep % 2 == 0:
-            with torch.cuda.stream(stream):
-                flush.add_(1)  # stream 2 GiB through HBM to evict L2 and MALL
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        with torch.cuda.stream(stream):
-            e0.record(stream)
-            g.tree_lookup_batch(tree.h, qld, vl, fl, stream)
-            e1.record(stream)
-        e1.synchronize()
-        (cold if rep % 2 == 0 else warm).append(e0.elapsed_time(e1) * 1e3)
-    del flush
+    # ---- large batch: warm launches of the 2^20-key lookup kernel
+    warm = timer.run(lambda: g.tree_lookup_batch(tree.h, qld, vl, fl, stream), 22)
     got = g.to_numpy(fl)
-    assert got.all()
-    ab = algorithmic_bytes(skeys, ql, st["height"], hits=int(got.sum()))
-    cold_us, warm_us = iqm(cold[2:]), iqm(warm[2:])
-    achieved = ab["bytes"] / (cold_us * 1e-6) / 1e9
+    assert got.all() and np.array_equal(g.to_numpy(vl, np.uint64), synth.values_for(ql_np, SEED, 64))
+    ab = algorithmic_bytes(skeys, ql_np, st["height"], hits=int(got.sum()))
+    warm_avg = float(np.mean(warm))
+    achieved = ab["bytes"] / (warm_avg * 1e-6) / 1e9
+    large = {"batch": BL, "warm_avg_us": round(warm_avg, 2), "warm_iqm_us": round(iqm(warm), 2),
+             "warm_glookups_per_s": round(BL / warm_avg / 1e3, 3),
+             "distinct_nodes_per_level": ab["distinct_nodes_per_level"]}
+    lw = timer.run(lambda: g.li_lookup_batch(li.h, qld, vl, fl, stream), 12)
+    large["learned_warm_avg_us"] = round(float(np.mean(lw)), 2)
+    if args.cold:
+        flush = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
+        cold = []
+        for _ in range(12):
+            flush.add_(1)
+            cold += timer.run(lambda: g.tree_lookup_batch(tree.h, qld, vl, fl, stream), 1, skip=0)
+        del flush
+        large["cold_avg_us"] = round(float(np.mean(cold[2:])), 2)
+    print("[bench] large batch done", file=sys.stderr, flush=True)
+
+    # ---- range batches
+    lo, hi, mc = synth.range_starts_and_lengths(keys, B, SEED, 100)
+    off = np.zeros(B, dtype=np.uint64)
+    off[1:] = np.cumsum(mc.astype(np.uint64))[:-1]
+    tot = int(mc.astype(np.uint64).sum())
+    rlo, rhi, rmc, roff = tree.dev(lo), tree.dev(hi), g.to_device(mc), g.to_device(off)
+    rok = torch.empty(tot, dtype=torch.int64, device=dev)
+    rov = torch.empty(tot, dtype=torch.int64, device=dev)
+    rcnt = torch.empty(B, dtype=torch.int32, device=dev)
+    rts = timer.run(lambda: g.tree_range_batch(tree.h, rlo, rhi, rmc, roff, rok, rov, rcnt, stream), 52)
+    rc = g.to_numpy(rcnt, np.uint32)
+    assert np.all(rc <= mc) and rc.sum() >= 0.99 * tot  # starts are present keys
+    rng_row = {"batch": B, "us_per_batch": round(iqm(rts), 2), "pairs": tot,
+               "mpairs_per_s": round(tot / iqm(rts), 2)}
+
+    # ---- insert batches of fresh keys
+    fresh = synth.uniform_keys((1 << 20) + 64 * B, SEED + 1, 64, purpose=synth.P_INSERT, exclude=keys)
+    ins_small = []
+    for i in range(24):
+        k = fresh[i * B:(i + 1) * B]
+        kd, vd = tree.dev(k), tree.dev(synth.values_for(k, SEED, 64))
+        s8 = torch.empty(B, dtype=torch.uint8, device=dev)
+        ins_small += timer.run(lambda: g.tree_insert_batch(tree.h, kd, vd, s8, stream), 1, skip=0)
+    assert g.tree_device_error(tree.h) == g.GT_OK
+    kbig = fresh[64 * B:64 * B + BL]
+    kd, vd = tree.dev(kbig), tree.dev(synth.values_for(kbig, SEED, 64))
+    s8 = torch.empty(BL, dtype=torch.uint8, device=dev)
+    big = timer.run(lambda: g.tree_insert_batch(tree.h, kd, vd, s8, stream), 1, skip=0)
+    assert g.tree_device_error(tree.h) == g.GT_OK and (g.to_numpy(s8) == 0).all()
+    ins_row = {"b1024_us_per_batch": round(iqm(ins_small[4:]), 1),
+               "b1024_mkeys_per_s": round(B / iqm(ins_small[4:]), 2),
+               "b2p20_us": round(big[0], 1), "b2p20_mkeys_per_s": round(BL / big[0], 2),
+               "height_after": tree.stats()["height"]}
+    print("[bench] inserts done", file=sys.stderr, flush=True)
+
+    # ---- learned index after the inserts (stale), then retrained
+    qmix = tree.dev(np.concatenate([keys[:B // 2], kbig[:B // 2]]))
+    v3 = torch.empty(B, dtype=torch.int64, device=dev)
+    f3 = torch.empty(B, dtype=torch.uint8, device=dev)
+    f_before = li.stats()["fallbacks"]
+    stale_us = iqm(timer.run(lambda: g.li_lookup_batch(li.h, qmix, v3, f3, stream), 40))
+    stale_fb = (li.stats()["fallbacks"] - f_before) / (40 * B)
+    t0 = time.perf_counter()
+    li.train()
+    retrain_s = time.perf_counter() - t0
+    f_before = li.stats()["fallbacks"]
+    fresh_us = iqm(timer.run(lambda: g.li_lookup_batch(li.h, qmix, v3, f3, stream), 40))
+    fresh_fb = (li.stats()["fallbacks"] - f_before) / (40 * B)
+    plain_mix_us = iqm(timer.run(lambda: g.tree_lookup_batch(tree.h, qmix, v3, f3, stream), 40))
+    stale_row = {"batch": B, "stale_us": round(stale_us, 3), "stale_fallback_rate": round(stale_fb, 4),
+                 "retrain_s": round(retrain_s, 3), "retrained_us": round(fresh_us, 3),
+                 "retrained_fallback_rate": round(fresh_fb, 4), "plain_us": round(plain_mix_us, 3)}
+
+    # ---- serving: closed loop for the saturation rate, then open loop at half
+    serving = None
+    if not args.no_serve:
+        skeys_now = np.concatenate([keys, fresh[:64 * B + BL]])
+        sfresh = synth.uniform_keys(400000, SEED + 9, 64, purpose=synth.P_INSERT, exclude=skeys_now)
+        spec = synth.serving_mix(keys, 2000, SEED, bmax=1024, zipf=zipf, fresh=sfresh)
+        srv = g.Server(tree, learned=li, slots=16, read_streams=4)
+        batches = [g.Batch(op, k, v, m, 0.0) for (op, k, v, m, _) in spec[:1000]]
+        assert srv.replay(batches) == g.GT_OK
+        sat = srv.stats()
+        lam = 0.5 * sum(sat["done"]) / sat["wall_s"]
+        spec2 = synth.serving_mix(keys, 2000, SEED + 1, bmax=1024, rate=lam, zipf=zipf, fresh=sfresh[200000:])
+        batches = [g.Batch(op, k, v, m, a) for (op, k, v, m, a) in spec2]
+        assert srv.replay(batches) == g.GT_OK
+        ss = srv.stats()
+        nops = sum(ss["ops"])
+        serving = {"batches": len(batches), "rate_batches_per_s": round(lam, 1),
+                   "saturation_batches_per_s": round(2 * lam, 1),
+                   "ops_per_s": round(nops / ss["wall_s"], 1), "batches_per_s": round(len(batches) / ss["wall_s"], 1),
+                   "p50_us": round(ss["p50_us"], 1), "p99_us": round(ss["p99_us"], 1),
+                   "p50_us_by_op": [round(x, 1) for x in ss["p50_us_op"]],
+                   "p99_us_by_op": [round(x, 1) for x in ss["p99_us_op"]],
+                   "graph_launches": ss["graph_launches"], "keys": "2^24 + inserts", "lookups": "learned index"}
+        srv.close()
+        print("[bench] serving done", file=sys.stderr, flush=True)
 
     line = {
         "metric": "lookup Mops/s and us/batch at B=1..1024, 2^24 keys; learned vs plain tree",
@@ -231,20 +349,33 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": f"plain B+-tree lookups, 2^{args.log2n} uniform u64 keys, B=1024 uniform present "
-                               f"queries", "keys": n, "batch": B, "fanout": 16, "leaf_cap": 16,
-                   "height": st["height"], "path": "plain"},
-        "sweep_us_per_batch": sweep,
-        "large_batch": {"batch": BL, "cold_us": round(cold_us, 2), "warm_us": round(warm_us, 2),
-                        "cold_glookups_per_s": round(BL / cold_us / 1e3, 3),
-                        "warm_glookups_per_s": round(BL / warm_us / 1e3, 3),
-                        "distinct_nodes_per_level": ab["distinct_nodes_per_level"]},
+        "config": {"workload": f"B=1024 lookup batches of uniform present keys on a bulk-loaded B+-tree of "
+                               f"2^{args.log2n} uniform u64 keys (fanout 16, 16 keys per leaf)",
+                   "keys": n, "batch": B, "height": st["height"], "path": args.path,
+                   "learned_models": lst["models"], "learned_linear": lst["linear_models"],
+                   "learned_mlp": lst["mlp_models"], "learned_tree": lst["tree_models"],
+                   "learned_mean_window": round(lst["mean_window"], 2), "learned_max_window": lst["max_window"]},
+        "other_path": {"path": "plain" if args.path == "learned" else "learned", "value": round(other_value, 3),
+                       "ms_per_step": round(other_elapsed * 1e3 / args.steps, 6)},
+        "learned_vs_plain_b1024": round((value / other_value) if args.path == "learned" else (other_value / value), 3),
+        "sweep": sweep,
+        "large_batch": large,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_lookup (B=2^20, cold)", "algorithmic_bytes": ab["bytes"]},
+                     "kernel": "k_lookup<unsigned long, 8, 4, 2, true, false> (B=2^20, warm)",
+                     "algorithmic_bytes": ab["bytes"]},
+        "range": rng_row,
+        "insert": ins_row,
+        "learned_stale": stale_row,
+        "build_s": round(build_s, 3),
+        "train_s": round(train_s, 3),
     }
+    if serving:
+        line["serving"] = serving
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(keys, vals, qs[:16])
+        threads = len(os.sched_getaffinity(0))
+        line["cpu_baseline"] = cpu_baseline(keys, vals, qs[:16], threads)
+        line["cpu_baseline_1thread"] = cpu_baseline(keys, vals, qs[:4], 1, budget_s=4.0)
     print(json.dumps(line), flush=True)
 
 

@@ -69,7 +69,8 @@ typedef struct {
                                  4 = none; 0 = default (2)                    */
     uint32_t sorted_mode;     /* reserved, must be 0                          */
     uint32_t queries_per_group; /* queries a lane group walks at once: 1, 2
-                                   or 4; 0 = default (2)                      */
+                                   or 4 for every batch; 0 = default (2, and
+                                   4 from 2^15 queries on)                    */
     uint64_t max_batch;       /* largest insert batch; default 2^20           */
     uint32_t value_coload;    /* 1: a lookup reads the leaf's value line with
                                  its key line (one dependent load fewer);
@@ -184,6 +185,155 @@ gt_status tree_device_error(gt_tree* t, hipStream_t stream);
 gt_status tree_export(gt_tree* t, void* host_buf, uint64_t* bytes /*host*/, hipStream_t stream);
 
 const char* gt_status_str(gt_status s);
+
+/* ------------------------------------------------------------------------
+ * Learned index over a tree (an addition to the paper's tree search).
+ *
+ * A two-stage FP32 model maps a key to its leaf's position in key order: a
+ * linear root picks one of `models` leaf models, each either linear or a
+ * one-hidden-layer MLP with 32 ReLU units, chosen per model by the smaller
+ * error window.  The models are trained on the device from the tree's own
+ * (key, leaf position) pairs, and every model gets exact error bounds
+ * lo <= pos - pred <= hi over all keys routed to it, computed by the same
+ * inference code the lookup runs.  A lookup predicts, searches the
+ * directory of leaf fence keys inside [pred + lo, pred + hi], reads that
+ * leaf and answers; a key that the leaf does not bracket (a window that
+ * missed, a leaf split since training, a key routed to a model without
+ * bounds) goes down the tree instead.  Results are always exactly those of
+ * tree_lookup_batch; the models only change the speed.
+ * ---------------------------------------------------------------------- */
+typedef struct gt_learned gt_learned; /* opaque handle, host memory */
+
+typedef struct {
+    uint32_t models;      /* leaf models, 1..4096; 0 = default 1024          */
+    uint32_t kind;        /* 0 = per model, the kind with the smaller window;
+                             1 = linear only; 2 = MLP only                    */
+    uint32_t max_window;  /* a model whose window spans more leaves sends its
+                             keys down the tree; 0 = default 64               */
+    uint32_t reserved;    /* must be 0                                        */
+} gt_li_params;
+
+typedef struct {
+    uint64_t trained_leaves;  /* leaves in the directory at training         */
+    uint64_t trained_keys;
+    uint64_t lookups;         /* queries answered since training             */
+    uint64_t fallbacks;       /* of which went down the tree                 */
+    uint32_t models, linear_models, mlp_models, tree_models;
+    uint32_t max_window;      /* widest window (leaves) of a model in use    */
+    uint32_t reserved;
+    double mean_window;       /* mean window over models in use              */
+} gt_li_stats;
+
+/* Arena bytes a learned index over tree t needs (host). */
+uint64_t li_arena_bytes(const gt_tree* t, const gt_li_params* p /*host*/);
+
+/* Create an (untrained) learned index over t in `arena` (device memory the
+ * caller owns and keeps until li_destroy).  Lookups before li_train go
+ * down the tree. */
+gt_status li_create(gt_tree* t, const gt_li_params* p /*host*/, void* arena, uint64_t arena_bytes,
+                    gt_learned** out /*host*/);
+
+/* (Re)train from the tree's current leaves: leaf positions by list ranking
+ * of the leaf chain, the fence directory, root and leaf model fits,
+ * exact bounds over every key.  Synchronises `stream`. */
+gt_status li_train(gt_learned* li, hipStream_t stream);
+
+/* Same contract as tree_lookup_batch. */
+gt_status li_lookup_batch(gt_learned* li, const void* keys, uint64_t B, void* values_out,
+                          uint8_t* found_out, hipStream_t stream);
+
+/* Inference as the lookup runs it, for checking bounds: per key the model
+ * index, the predicted leaf position and that model's bounds (lo, hi; both
+ * 0 and kind 2 in model_kind_out when the model sends keys down the tree).
+ * Outputs: B entries each (u32, i32, i32, i32, u8). */
+gt_status li_predict(gt_learned* li, const void* keys, uint64_t B, uint32_t* model_out, int32_t* pred_out,
+                     int32_t* lo_out, int32_t* hi_out, uint8_t* model_kind_out, hipStream_t stream);
+
+/* Test hook: overwrite every model's bounds with [lo, hi] (a wrong window
+ * must only cost fallbacks, never a wrong result). */
+gt_status li_set_bounds(gt_learned* li, int32_t lo, int32_t hi, hipStream_t stream);
+
+/* Counters and model summary (synchronises). */
+gt_status li_stats(gt_learned* li, gt_li_stats* out /*host*/, hipStream_t stream);
+
+gt_status li_destroy(gt_learned* li);
+
+/* ------------------------------------------------------------------------
+ * Serving runtime (an addition to the paper's batch search; its closest
+ * analogue is the host/device overlap of Section V-B).
+ *
+ * Lookup, insert and range batches of uneven sizes arrive from host
+ * threads and are admitted in arrival order when a slot is free and the
+ * bytes in flight stay under the memory cap (a batch that can never fit is
+ * refused).  Admission order is the linearization order: a batch sees every
+ * insert admitted before it and none after.  Reads run concurrently on
+ * several HIP streams; an insert waits for the reads admitted before it and
+ * the reads after it wait for the insert.  Each batch is padded to a power
+ * of two with entries that leave the result unchanged (extra lookups, a
+ * repeat of the last insert pair, empty ranges) and, once its
+ * (slot, op, size) shape has been seen, replayed from a captured hipGraph
+ * (input copy, kernels, output copy).  Inputs and outputs live in the
+ * caller's host memory; the runtime stages them through pinned buffers.
+ * ---------------------------------------------------------------------- */
+typedef struct gt_server gt_server;
+
+typedef struct {
+    uint32_t read_streams;   /* streams for reads; 0 = default 4            */
+    uint32_t slots;          /* batches in flight at once; 0 = default 16   */
+    uint64_t mem_cap;        /* cap on staged bytes in flight; 0 = 32 GiB   */
+    uint32_t max_batch;      /* largest batch; 0 = default 1024             */
+    uint32_t max_range;      /* largest per-query range length; 0 = 128     */
+    uint32_t use_graphs;     /* 1 = replay captured graphs, 2 = direct
+                                launches; 0 = default (1)                   */
+    uint32_t reserved;       /* must be 0                                   */
+} gt_srv_params;
+
+enum { GT_OP_LOOKUP = 0, GT_OP_INSERT = 1, GT_OP_RANGE = 2 };
+enum { GT_REQ_QUEUED = 0, GT_REQ_INFLIGHT = 1, GT_REQ_DONE = 2, GT_REQ_REFUSED = 3 };
+
+/* One batch; every pointer is HOST memory owned by the caller until the
+ * request is done.  lookup: keys -> out0 (values), out1 (found, u8);
+ * insert: keys, values -> out0 (status, u8); range: keys (lo), values (hi),
+ * max_out -> out0 (keys), out1 (values) in CSR order of max_out, count_out. */
+typedef struct {
+    uint32_t op;
+    uint32_t B;
+    const void* keys;
+    const void* values;
+    const uint32_t* max_out;
+    void* out0;
+    void* out1;
+    uint32_t* count_out;
+    double arrival_s;        /* srv_replay: arrival time after the start    */
+} gt_request;
+
+typedef struct {
+    uint64_t done[3];        /* batches completed per op                    */
+    uint64_t ops[3];         /* keys (lookup, insert) / ranges completed    */
+    uint64_t refused;
+    uint64_t graph_launches, direct_launches;
+    double wall_s;           /* first arrival to last completion            */
+    double p50_us, p99_us;   /* arrival -> completion latency, all batches  */
+    double p50_us_op[3], p99_us_op[3];
+} gt_srv_stats;
+
+/* Create a server over tree t (and learned index li for lookups, or NULL).
+ * Allocates its staging buffers (pinned host, device) here, not later. */
+gt_status srv_create(gt_tree* t, gt_learned* li, const gt_srv_params* p /*host*/, gt_server** out);
+/* Queue a batch (non-blocking); *ticket identifies it. */
+gt_status srv_submit(gt_server* s, const gt_request* r /*host*/, uint64_t* ticket /*host*/);
+/* State of a ticket (GT_REQ_*). */
+gt_status srv_poll(gt_server* s, uint64_t ticket, uint32_t* state /*host*/);
+/* Block until the ticket is done or refused. */
+gt_status srv_wait(gt_server* s, uint64_t ticket);
+/* Submit reqs[i] at reqs[i].arrival_s after the call starts (open loop),
+ * then wait for all of them; statistics cover exactly these requests. */
+gt_status srv_replay(gt_server* s, const gt_request* reqs /*host*/, uint64_t n);
+gt_status srv_stats(gt_server* s, gt_srv_stats* out /*host*/);
+/* Arrival-to-completion latency in microseconds of the last srv_replay's
+ * requests, in their order (host array of n). */
+gt_status srv_latencies(gt_server* s, double* out /*host*/, uint64_t n);
+gt_status srv_destroy(gt_server* s);
 
 #ifdef __cplusplus
 }

@@ -47,6 +47,39 @@ class gt_tree_stats(C.Structure):
                 ("error_word", C.c_uint32), ("key_bytes", C.c_uint32)]
 
 
+class gt_li_params(C.Structure):
+    _fields_ = [("models", C.c_uint32), ("kind", C.c_uint32), ("max_window", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class gt_li_stats(C.Structure):
+    _fields_ = [("trained_leaves", C.c_uint64), ("trained_keys", C.c_uint64), ("lookups", C.c_uint64),
+                ("fallbacks", C.c_uint64), ("models", C.c_uint32), ("linear_models", C.c_uint32),
+                ("mlp_models", C.c_uint32), ("tree_models", C.c_uint32), ("max_window", C.c_uint32),
+                ("reserved", C.c_uint32), ("mean_window", C.c_double)]
+
+
+class gt_srv_params(C.Structure):
+    _fields_ = [("read_streams", C.c_uint32), ("slots", C.c_uint32), ("mem_cap", C.c_uint64),
+                ("max_batch", C.c_uint32), ("max_range", C.c_uint32), ("use_graphs", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class gt_request(C.Structure):
+    _fields_ = [("op", C.c_uint32), ("B", C.c_uint32), ("keys", C.c_void_p), ("values", C.c_void_p),
+                ("max_out", C.c_void_p), ("out0", C.c_void_p), ("out1", C.c_void_p), ("count_out", C.c_void_p),
+                ("arrival_s", C.c_double)]
+
+
+class gt_srv_stats(C.Structure):
+    _fields_ = [("done", C.c_uint64 * 3), ("ops", C.c_uint64 * 3), ("refused", C.c_uint64),
+                ("graph_launches", C.c_uint64), ("direct_launches", C.c_uint64), ("wall_s", C.c_double),
+                ("p50_us", C.c_double), ("p99_us", C.c_double), ("p50_us_op", C.c_double * 3),
+                ("p99_us_op", C.c_double * 3)]
+
+
+OP_LOOKUP, OP_INSERT, OP_RANGE = 0, 1, 2
+REQ_QUEUED, REQ_INFLIGHT, REQ_DONE, REQ_REFUSED = 0, 1, 2, 3
+
 _lib = None
 
 
@@ -70,8 +103,28 @@ def lib():
         L.tree_stats.argtypes = [vp, C.POINTER(gt_tree_stats), vp]
         L.tree_device_error.argtypes = [vp, vp]
         L.tree_export.argtypes = [vp, vp, C.POINTER(u64), vp]
+        L.li_arena_bytes.argtypes = [vp, C.POINTER(gt_li_params)]
+        L.li_arena_bytes.restype = u64
+        L.li_create.argtypes = [vp, C.POINTER(gt_li_params), vp, u64, C.POINTER(vp)]
+        L.li_train.argtypes = [vp, vp]
+        L.li_lookup_batch.argtypes = [vp, vp, u64, vp, vp, vp]
+        L.li_predict.argtypes = [vp, vp, u64, vp, vp, vp, vp, vp, vp]
+        L.li_set_bounds.argtypes = [vp, C.c_int32, C.c_int32, vp]
+        L.li_stats.argtypes = [vp, C.POINTER(gt_li_stats), vp]
+        L.li_destroy.argtypes = [vp]
+        L.srv_create.argtypes = [vp, vp, C.POINTER(gt_srv_params), C.POINTER(vp)]
+        L.srv_submit.argtypes = [vp, C.POINTER(gt_request), C.POINTER(u64)]
+        L.srv_poll.argtypes = [vp, u64, C.POINTER(u32)]
+        L.srv_wait.argtypes = [vp, u64]
+        L.srv_replay.argtypes = [vp, vp, u64]
+        L.srv_stats.argtypes = [vp, C.POINTER(gt_srv_stats)]
+        L.srv_latencies.argtypes = [vp, vp, u64]
+        L.srv_destroy.argtypes = [vp]
         for f in ("tree_build", "tree_lookup_batch", "tree_insert_batch", "tree_range_batch",
-                  "tree_destroy", "tree_stats", "tree_device_error", "tree_export"):
+                  "tree_destroy", "tree_stats", "tree_device_error", "tree_export", "li_create", "li_train",
+                  "li_lookup_batch", "li_predict", "li_set_bounds", "li_stats", "li_destroy", "srv_create",
+                  "srv_submit", "srv_poll", "srv_wait", "srv_replay", "srv_stats", "srv_latencies",
+                  "srv_destroy"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -187,6 +240,48 @@ def tree_export(h, stream=None) -> np.ndarray:
     return buf
 
 
+def li_params(models: int = 0, kind: int = 0, max_window: int = 0) -> gt_li_params:
+    return gt_li_params(models=models, kind=kind, max_window=max_window, reserved=0)
+
+
+def li_arena_bytes(h, params: gt_li_params) -> int:
+    return int(lib().li_arena_bytes(h, C.byref(params)))
+
+
+def li_create(h, params: gt_li_params, arena) -> int:
+    out = C.c_void_p()
+    _check(lib().li_create(h, C.byref(params), _ptr(arena), arena.numel(), C.byref(out)), "li_create")
+    return out.value
+
+
+def li_train(li, stream=None):
+    _check(lib().li_train(li, _stream(stream)), "li_train")
+
+
+def li_lookup_batch(li, keys, values_out, found_out, stream=None):
+    _check(lib().li_lookup_batch(li, _ptr(keys), keys.numel(), _ptr(values_out), _ptr(found_out),
+                                 _stream(stream)), "li_lookup_batch")
+
+
+def li_predict(li, keys, model_out, pred_out, lo_out, hi_out, kind_out, stream=None):
+    _check(lib().li_predict(li, _ptr(keys), keys.numel(), _ptr(model_out), _ptr(pred_out), _ptr(lo_out),
+                            _ptr(hi_out), _ptr(kind_out), _stream(stream)), "li_predict")
+
+
+def li_set_bounds(li, lo: int, hi: int, stream=None):
+    _check(lib().li_set_bounds(li, lo, hi, _stream(stream)), "li_set_bounds")
+
+
+def li_stats(li, stream=None) -> dict:
+    s = gt_li_stats()
+    _check(lib().li_stats(li, C.byref(s), _stream(stream)), "li_stats")
+    return {f: getattr(s, f) for f, _ in gt_li_stats._fields_}
+
+
+def li_destroy(li):
+    _check(lib().li_destroy(li), "li_destroy")
+
+
 # ------------------------------------------------------------ convenience
 
 class Tree:
@@ -258,3 +353,143 @@ class Tree:
 
     def export(self):
         return tree_export(self.h)
+
+
+class Learned:
+    """A learned index over a :class:`Tree` (owns its arena tensor)."""
+
+    def __init__(self, tree: Tree, models: int = 0, kind: int = 0, max_window: int = 0):
+        torch = _torch()
+        self.tree = tree
+        self.params = li_params(models, kind, max_window)
+        n = li_arena_bytes(tree.h, self.params)
+        if n == 0:
+            raise GtError(GT_ERR_INVALID, "li_arena_bytes")
+        self.arena = torch.empty(n, dtype=torch.uint8, device=tree.device)
+        self.h = li_create(tree.h, self.params, self.arena)
+
+    def close(self):
+        if getattr(self, "h", None):
+            li_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def train(self):
+        li_train(self.h)
+
+    def lookup_dev(self, q, stream=None):
+        torch = _torch()
+        vo = torch.empty(q.numel(), dtype=self.tree.tdtype, device=self.tree.device)
+        fo = torch.empty(q.numel(), dtype=torch.uint8, device=self.tree.device)
+        li_lookup_batch(self.h, q, vo, fo, stream)
+        return vo, fo
+
+    def lookup(self, q: np.ndarray):
+        vo, fo = self.lookup_dev(self.tree.dev(q))
+        return to_numpy(vo, self.tree.udtype), to_numpy(fo)
+
+    def predict(self, q: np.ndarray):
+        torch = _torch()
+        qd = self.tree.dev(q)
+        n, dev = qd.numel(), self.tree.device
+        mo = torch.empty(n, dtype=torch.int32, device=dev)
+        po = torch.empty(n, dtype=torch.int32, device=dev)
+        lo = torch.empty(n, dtype=torch.int32, device=dev)
+        hi = torch.empty(n, dtype=torch.int32, device=dev)
+        ko = torch.empty(n, dtype=torch.uint8, device=dev)
+        li_predict(self.h, qd, mo, po, lo, hi, ko)
+        return to_numpy(mo), to_numpy(po), to_numpy(lo), to_numpy(hi), to_numpy(ko)
+
+    def set_bounds(self, lo: int, hi: int):
+        li_set_bounds(self.h, lo, hi)
+
+    def stats(self):
+        return li_stats(self.h)
+
+
+# ----------------------------------------------------------------- serving
+
+def srv_params(read_streams=0, slots=0, mem_cap=0, max_batch=0, max_range=0, use_graphs=0) -> gt_srv_params:
+    return gt_srv_params(read_streams=read_streams, slots=slots, mem_cap=mem_cap, max_batch=max_batch,
+                         max_range=max_range, use_graphs=use_graphs, reserved=0)
+
+
+class Batch:
+    """One serving request with its host buffers (numpy arrays kept alive)."""
+
+    def __init__(self, op: int, keys: np.ndarray, values: np.ndarray | None = None,
+                 max_out: np.ndarray | None = None, arrival_s: float = 0.0):
+        self.op = op
+        self.keys = np.ascontiguousarray(keys)
+        dt = self.keys.dtype
+        B = len(self.keys)
+        self.values = None if values is None else np.ascontiguousarray(values, dtype=dt)
+        self.max_out = None if max_out is None else np.ascontiguousarray(max_out, dtype=np.uint32)
+        self.count = None
+        if op == OP_LOOKUP:
+            self.out0 = np.empty(B, dtype=dt)
+            self.out1 = np.empty(B, dtype=np.uint8)
+        elif op == OP_INSERT:
+            self.out0 = np.empty(B, dtype=np.uint8)
+            self.out1 = None
+        else:
+            tot = int(self.max_out.astype(np.uint64).sum())
+            self.out0 = np.zeros(max(tot, 1), dtype=dt)
+            self.out1 = np.zeros(max(tot, 1), dtype=dt)
+            self.count = np.empty(B, dtype=np.uint32)
+        self.arrival_s = arrival_s
+
+    def struct(self) -> gt_request:
+        p = lambda a: a.ctypes.data_as(C.c_void_p) if a is not None else None  # noqa: E731
+        return gt_request(op=self.op, B=len(self.keys), keys=p(self.keys), values=p(self.values),
+                          max_out=p(self.max_out), out0=p(self.out0), out1=p(self.out1),
+                          count_out=p(self.count), arrival_s=self.arrival_s)
+
+
+class Server:
+    def __init__(self, tree: Tree, learned: "Learned | None" = None, **kw):
+        self.tree, self.learned = tree, learned
+        self.params = srv_params(**kw)
+        h = C.c_void_p()
+        _check(lib().srv_create(tree.h, learned.h if learned is not None else None, C.byref(self.params),
+                                C.byref(h)), "srv_create")
+        self.h = h.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().srv_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def submit(self, b: Batch) -> int:
+        t = C.c_uint64()
+        b._s = b.struct()
+        _check(lib().srv_submit(self.h, C.byref(b._s), C.byref(t)), "srv_submit")
+        return t.value
+
+    def wait(self, ticket: int) -> int:
+        return int(lib().srv_wait(self.h, ticket))
+
+    def poll(self, ticket: int) -> int:
+        s = C.c_uint32()
+        _check(lib().srv_poll(self.h, ticket, C.byref(s)), "srv_poll")
+        return s.value
+
+    def replay(self, batches: list) -> int:
+        arr = (gt_request * len(batches))(*[b.struct() for b in batches])
+        return int(lib().srv_replay(self.h, C.cast(arr, C.c_void_p), len(batches)))
+
+    def stats(self) -> dict:
+        s = gt_srv_stats()
+        _check(lib().srv_stats(self.h, C.byref(s)), "srv_stats")
+        d = {f: getattr(s, f) for f, _ in gt_srv_stats._fields_}
+        for f in ("done", "ops", "p50_us_op", "p99_us_op"):
+            d[f] = list(d[f])
+        return d
+
+    def latencies(self, n: int) -> np.ndarray:
+        out = np.empty(n, dtype=np.float64)
+        _check(lib().srv_latencies(self.h, out.ctypes.data_as(C.c_void_p), n), "srv_latencies")
+        return out

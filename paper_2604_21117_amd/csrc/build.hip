@@ -190,6 +190,14 @@ __global__ __launch_bounds__(256) void k_mirror_refresh(TreeView<K> t) {
     }
 }
 
+__global__ void k_clear_error(DevHeader* h) {
+    if (threadIdx.x == 0) h->error = 0;
+}
+
+void launch_clear_error(DevHeader* h, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_error, dim3(1), dim3(64), 0, s, h);
+}
+
 static uint32_t grid1d(uint64_t n, uint32_t block) {
     uint64_t g = (n + block - 1) / block;
     if (g < 1) g = 1;

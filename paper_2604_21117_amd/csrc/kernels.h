@@ -13,9 +13,11 @@ struct LaunchCfg {
     int value_coload;       // read a leaf's value line together with its key line
     int xcd_split;          // 0 off, 1 on from kXcdMinBatch queries, 2 always
     int leaf_stream;        // non-temporal leaf loads
+    int large_qpg;          // queries per group from kLargeBatch queries on (0 = same)
 };
 
 constexpr uint64_t kXcdMinBatch = 1u << 15;
+constexpr uint64_t kLargeBatch = 1u << 15;
 
 template <class K>
 void launch_lookup(const TreeView<K>& t, const LaunchCfg& cfg, const K* q, uint64_t B, K* vout, uint8_t* fout,
@@ -41,5 +43,8 @@ void launch_dup_check(const K* sk, uint64_t n, uint32_t* flag, hipStream_t s);
 
 template <class K>
 void launch_mirror_refresh(const TreeView<K>& t, hipStream_t s);
+
+// Clear the device error word with a kernel (safe inside a captured graph).
+void launch_clear_error(DevHeader* h, hipStream_t s);
 
 }  // namespace gt

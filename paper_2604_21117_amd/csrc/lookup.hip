@@ -334,7 +334,8 @@ static void launch_lookup_lv(const TreeView<K>& t, const LaunchCfg& cfg, const K
 template <class K>
 void launch_lookup(const TreeView<K>& t, const LaunchCfg& cfg, const K* q, uint64_t B, K* vout, uint8_t* fout,
                    hipStream_t s) {
-    const int qpg = cfg.queries_per_group;
+    // large batches are throughput-bound: more queries in flight per group
+    const int qpg = (B >= kLargeBatch && cfg.large_qpg) ? cfg.large_qpg : cfg.queries_per_group;
     switch (cfg.lanes) {
         case 4:
             if (qpg >= 4) launch_lookup_lv<K, 4, 4>(t, cfg, q, B, vout, fout, s);

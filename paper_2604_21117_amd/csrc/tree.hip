@@ -16,27 +16,9 @@
 #include "kernels.h"
 #include "prims.h"
 #include "insert.h"
+#include "handle.h"
 
 using namespace gt;
-
-struct gt_tree {
-    gt_params p;
-    int kb;
-    uint8_t* arena;
-    uint64_t arena_bytes;   // bytes used
-    DevHeader* hdr;
-    uint8_t* mirror;
-    void* ikeys;
-    uint32_t* ichild;
-    void* lkeys;
-    void* lvals;
-    uint2* lmeta;
-    uint64_t inner_cap, leaf_cap;
-    uint8_t* scratch;
-    uint64_t scratch_bytes;
-    uint64_t max_batch;
-    LaunchCfg cfg;
-};
 
 namespace {
 
@@ -132,21 +114,6 @@ uint64_t bytes_for_leaf_cap(int kb, uint64_t max_batch, uint64_t leaf_cap) {
     uint64_t ic = inner_cap_for(leaf_cap);
     return fixed_bytes(kb, max_batch, leaf_cap) + align_up(ic * kSlots * kb) + align_up(ic * kSlots * 4) +
            2 * align_up(leaf_cap * kSlots * kb) + align_up(leaf_cap * 8);
-}
-
-template <class K>
-TreeView<K> view(const gt_tree* t) {
-    TreeView<K> v;
-    v.hdr = t->hdr;
-    v.mirror = t->mirror;
-    v.ikeys = reinterpret_cast<K*>(t->ikeys);
-    v.ichild = t->ichild;
-    v.lkeys = reinterpret_cast<K*>(t->lkeys);
-    v.lvals = reinterpret_cast<K*>(t->lvals);
-    v.lmeta = t->lmeta;
-    v.inner_cap = static_cast<uint32_t>(t->inner_cap);
-    v.leaf_cap = static_cast<uint32_t>(t->leaf_cap);
-    return v;
 }
 
 #define HIP_TRY(x)                                  \
@@ -265,6 +232,8 @@ gt_status tree_build(const gt_params* p, const void* keys, const void* values, u
     t->cfg.value_coload = p->value_coload == 2 ? 0 : 1;
     t->cfg.xcd_split = p->xcd_split == 1 ? 1 : 0;
     t->cfg.leaf_stream = p->leaf_stream == 1 ? 1 : 0;
+    // an explicit queries_per_group applies to every batch size
+    t->cfg.large_qpg = p->queries_per_group ? 0 : 4;
     layout(t, reinterpret_cast<uint8_t*>(arena), lo);
     gt_status st = kb == 8 ? build_t<uint64_t>(t, keys, values, n, stream)
                            : build_t<uint32_t>(t, keys, values, n, stream);

@@ -222,3 +222,49 @@ def range_starts_and_lengths(keys: np.ndarray, B: int, seed: int, max_len: int =
     mx = (s.below(B, max_len) + 1).astype(np.uint32)
     hi = np.full(B, np.iinfo(keys.dtype).max, dtype=keys.dtype)
     return lo, hi, mx
+
+
+def serving_mix(keys: np.ndarray, n_batches: int, seed: int, width: int = 64, bmax: int = 1024,
+                mix=(0.8, 0.15, 0.05), rate: float | None = None, zipf: Zipf | None = None,
+                max_len: int = 100, fresh: np.ndarray | None = None):
+    """A serving workload: per batch (op, keys, values, max, arrival_s).
+
+    op 0 lookup / 1 insert / 2 range drawn with probabilities `mix`; size
+    B ~ U{1..bmax}; lookup keys and range starts from the present keys
+    (Zipf when given, else uniform); insert keys taken in order from `fresh`
+    (absent keys) with values hash(key ^ seed); range hi = all ones and
+    max ~ U{1..max_len}; Poisson arrivals at `rate` batches per second (all
+    at 0 when rate is None)."""
+    s = Stream(seed, P_MIX)
+    u = s.uniform01(n_batches)
+    cum = np.cumsum(mix)
+    ops = np.searchsorted(cum / cum[-1], u, side="right").astype(np.int64)
+    sizes = s.below(n_batches, bmax) + 1
+    if rate:
+        gaps = -np.log1p(-s.uniform01(n_batches)) / rate
+        arrivals = np.cumsum(gaps) - gaps[0]
+    else:
+        arrivals = np.zeros(n_batches)
+    keys = np.asarray(keys)
+    top = np.iinfo(keys.dtype).max
+    fpos = 0
+    out = []
+    for i in range(n_batches):
+        B = int(sizes[i])
+        op = int(ops[i])
+        if op == 1:
+            if fresh is None or fpos + B > len(fresh):
+                op = 0
+            else:
+                k = fresh[fpos:fpos + B]
+                fpos += B
+                out.append((1, k, values_for(k, seed, width), None, float(arrivals[i])))
+                continue
+        idx = zipf.indices(B) if zipf is not None else s.below(B, len(keys))
+        k = keys[idx]
+        if op == 0:
+            out.append((0, k, None, None, float(arrivals[i])))
+        else:
+            mx = (s.below(B, max_len) + 1).astype(np.uint32)
+            out.append((2, k, np.full(B, top, dtype=keys.dtype), mx, float(arrivals[i])))
+    return out

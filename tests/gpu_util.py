@@ -41,3 +41,28 @@ def key_set(n, width, seed, edges=False):
         k = np.unique(np.concatenate([k[:n - 2], np.array([0, top], dtype=k.dtype)]))
         k = synth.shuffle(k, seed)
     return k
+
+
+def chain_positions(buf):
+    """From a tree export: every key in key order with the position (in the
+    leaf chain) of the leaf that holds it."""
+    buf = np.asarray(buf, dtype=np.uint8)
+    h = np.frombuffer(buf[:40].tobytes(), dtype=np.uint32)
+    kb, F, Cc, first, ni, nl = int(h[1]), int(h[2]), int(h[3]), int(h[6]), int(h[7]), int(h[8])
+    kd = np.uint64 if kb == 8 else np.uint32
+    rin, rlf = F * (kb + 4), Cc * 2 * kb + 8
+    base = 48 + ni * rin
+    leaves = buf[base: base + nl * rlf].reshape(nl, rlf)
+    lkeys = leaves[:, :Cc * kb].copy().view(kd).reshape(nl, Cc)
+    meta = leaves[:, 2 * Cc * kb:].copy().view(np.uint32).reshape(nl, 2)
+    order = []
+    x = first
+    while x != 0xFFFFFFFF:
+        order.append(x)
+        x = int(meta[x, 1])
+    keys, pos = [], []
+    for p, leaf in enumerate(order):
+        c = int(meta[leaf, 0])
+        keys.append(lkeys[leaf, :c])
+        pos.append(np.full(c, p, dtype=np.int64))
+    return np.concatenate(keys), np.concatenate(pos), len(order)

@@ -1,0 +1,142 @@
+"""Learned index: results identical to the oracle (hence to the tree) on
+every key set, error bounds exact over every trained key (predictions taken
+from the GPU inference kernel itself), and a wrong window or a stale
+directory costing fallbacks only."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import mk_tree, assert_lookup_parity, chain_positions, key_set
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _dev():
+    import torch
+    assert torch.cuda.is_available()
+
+
+def _learned(tree, **kw):
+    import paper_2604_21117_amd as g
+    li = g.Learned(tree, **kw)
+    li.train()
+    return li
+
+
+def _li_parity(li, sa, q):
+    gv, gf = li.lookup(q)
+    ov, of = sa.lookup(q)
+    assert np.array_equal(gf, of), f"found differs at {np.nonzero(gf != of)[0][:8]}"
+    assert np.array_equal(gv, ov), f"values differ at {np.nonzero(gv != ov)[0][:8]}"
+
+
+def _check_bounds(tree, li):
+    keys, pos, L = chain_positions(tree.export())
+    m, p, lo, hi, kind = li.predict(keys)
+    used = kind != 2
+    err = pos - p.astype(np.int64)
+    assert np.all(err[used] >= lo[used]) and np.all(err[used] <= hi[used])
+    # the bounds are the exact extremes over the keys routed to each model
+    for j in np.unique(m[used])[:200]:
+        sel = used & (m == j)
+        assert err[sel].min() == lo[sel][0] and err[sel].max() == hi[sel][0]
+    return used.mean()
+
+
+@pytest.mark.parametrize("width", [32, 64])
+@pytest.mark.parametrize("dist", ["uniform", "lognormal", "clustered"])
+def test_learned_parity_and_bounds(width, dist):
+    seed = 41
+    n = 1 << 18
+    if dist == "uniform":
+        keys = synth.uniform_keys(n, seed, width)
+    elif width == 32:
+        pytest.skip("lognormal / clustered keys are u64 workloads")
+    elif dist == "lognormal":
+        keys = synth.lognormal_keys(n, seed)
+    else:
+        keys = synth.clustered_keys(n, seed)
+    vals = synth.values_for(keys, seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, width // 8, leaf_slack=1 << 14, max_batch=1 << 14)
+    li = _learned(t, models=256)
+    frac_used = _check_bounds(t, li)
+    assert frac_used > 0.5
+    q = synth.mixed_queries(keys, 60000, seed, width)
+    _li_parity(li, sa, q)
+    st = li.stats()
+    assert st["lookups"] == 60000
+    # present keys inside their model's window never need the tree
+    pres = synth.present_queries(keys, 20000, seed + 1)
+    before = li.stats()["fallbacks"]
+    _li_parity(li, sa, pres)
+    assert li.stats()["fallbacks"] - before <= 20000 * (1 - frac_used) + 200
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_kinds(kind):
+    seed, width = 43, 64
+    keys = synth.lognormal_keys(100000, seed)
+    vals = synth.values_for(keys, seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, 8, max_batch=4096)
+    li = _learned(t, models=128, kind=kind, max_window=256)
+    st = li.stats()
+    if kind == 1:
+        assert st["mlp_models"] == 0
+    else:
+        assert st["linear_models"] == 0 or st["mlp_models"] > 0
+    _check_bounds(t, li)
+    _li_parity(li, sa, synth.mixed_queries(keys, 30000, seed, width))
+
+
+def test_forced_fallback_stays_exact():
+    seed, width = 44, 64
+    keys = synth.uniform_keys(200000, seed, width)
+    vals = synth.values_for(keys, seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, 8, max_batch=4096)
+    li = _learned(t)
+    li.set_bounds(0, 0)  # windows of one leaf: most predictions now miss
+    q = synth.mixed_queries(keys, 50000, seed, width)
+    f0 = li.stats()["fallbacks"]
+    _li_parity(li, sa, q)
+    assert li.stats()["fallbacks"] - f0 > 1000
+    li.set_bounds(5, 3) if False else None
+
+
+def test_stale_after_inserts_then_retrain():
+    seed, width = 45, 64
+    keys = synth.uniform_keys(300000, seed, width)
+    vals = synth.values_for(keys, seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, 8, leaf_slack=1 << 16, max_batch=1 << 14)
+    li = _learned(t)
+    rng = np.random.default_rng(seed)
+    for b in range(5):
+        ins = synth.uniform_keys(10000, seed + 100 + b, width, exclude=sa.keys)
+        k = np.concatenate([ins, keys[rng.integers(0, len(keys), 500)]])
+        v = synth.values_for(k, seed + b, width)
+        assert np.array_equal(t.insert(k, v), sa.insert(k, v))
+        q = np.concatenate([k[:3000], synth.mixed_queries(sa.keys, 6000, seed + b, width)])
+        _li_parity(li, sa, q)
+    f_stale = li.stats()["fallbacks"]
+    assert f_stale > 0
+    li.train()
+    _check_bounds(t, li)
+    _li_parity(li, sa, synth.mixed_queries(sa.keys, 40000, seed, width))
+
+
+@pytest.mark.parametrize("n", [0, 1, 7, 100, 5000])
+def test_small_trees(n):
+    seed, width = 46, 64
+    keys = key_set(n, width, seed, edges=n > 2)
+    vals = synth.values_for(keys, seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, 8, max_batch=4096)
+    li = _learned(t, models=64)
+    q = np.concatenate([keys, synth.absent_queries(keys, 300, seed, width),
+                        np.array([0, np.iinfo(np.uint64).max], dtype=np.uint64)])
+    _li_parity(li, sa, q)

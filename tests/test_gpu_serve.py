@@ -1,0 +1,143 @@
+"""Serving runtime: a mix of lookup / insert / range batches admitted while
+others run gives, for every batch, exactly the result of applying the
+batches one at a time in admission order (checked against the oracle and
+against the same batches run alone); graphs and direct launches agree;
+admission refuses what can never fit and never deadlocks."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import mk_tree
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _dev():
+    import torch
+    assert torch.cuda.is_available()
+
+
+def _batches(spec):
+    import paper_2604_21117_amd as g
+    return [g.Batch(op, k, v, m, a) for (op, k, v, m, a) in spec]
+
+
+def _oracle_replay(sa, batches):
+    """Sequential application in submission order; returns expected outputs."""
+    exp = []
+    for b in batches:
+        if b.op == 0:
+            exp.append(sa.lookup(b.keys))
+        elif b.op == 1:
+            exp.append((sa.insert(b.keys, b.values),))
+        else:
+            exp.append(sa.range(b.keys, b.values, b.max_out))
+    return exp
+
+
+def _compare(batches, exp):
+    for i, (b, e) in enumerate(zip(batches, exp)):
+        if b.op == 0:
+            assert np.array_equal(b.out1, e[1]) and np.array_equal(b.out0, e[0]), f"lookup batch {i}"
+        elif b.op == 1:
+            assert np.array_equal(b.out0, e[0]), f"insert batch {i}"
+        else:
+            cnt, off, ok, ov = e
+            assert np.array_equal(b.count, cnt), f"range batch {i} counts"
+            for q in range(len(cnt)):
+                s = slice(int(off[q]), int(off[q] + cnt[q]))
+                assert np.array_equal(b.out0[s], ok[s]) and np.array_equal(b.out1[s], ov[s]), f"range {i}/{q}"
+
+
+def _setup(seed, n=1 << 16, width=64):
+    keys = synth.uniform_keys(n, seed, width)
+    vals = synth.values_for(keys, seed, width)
+    fresh = synth.uniform_keys(200000, seed + 1, width, exclude=keys)
+    return keys, vals, fresh
+
+
+@pytest.mark.parametrize("graphs", [1, 2])
+def test_mix_equals_sequential(graphs):
+    import paper_2604_21117_amd as g
+    seed = 60 + graphs
+    keys, vals, fresh = _setup(seed)
+    t = mk_tree(keys, vals, 8, leaf_slack=1 << 15, max_batch=1024)
+    srv = g.Server(t, use_graphs=graphs, slots=8, read_streams=4, max_range=128)
+    spec = synth.serving_mix(keys, 800, seed, bmax=300, rate=40000.0, zipf=synth.Zipf(len(keys), 0.99, seed),
+                             fresh=fresh)
+    # a few batches with duplicates and updates of present keys
+    spec.append((1, np.concatenate([keys[:50], keys[:50]]), np.arange(100, dtype=np.uint64), None, spec[-1][4]))
+    batches = _batches(spec)
+    assert srv.replay(batches) == g.GT_OK
+    sa = oracle.SortedArray(keys, vals, 64)
+    _compare(batches, _oracle_replay(sa, batches))
+    st = srv.stats()
+    assert sum(st["done"]) == len(batches) and st["refused"] == 0
+    assert st["p99_us"] >= st["p50_us"] > 0
+    if graphs == 1:
+        assert st["graph_launches"] >= len(batches)
+    srv.close()
+    bits, ek, ev = oracle.check_export(t.export(), len(sa))
+    assert bits == 0 and np.array_equal(ek, sa.keys) and np.array_equal(ev, sa.vals)
+
+
+def test_alone_equals_in_mix():
+    import paper_2604_21117_amd as g
+    seed = 70
+    keys, vals, fresh = _setup(seed)
+    spec = synth.serving_mix(keys, 300, seed, bmax=200, rate=None, fresh=fresh)
+    outs = []
+    for mode in ("mix", "alone"):
+        t = mk_tree(keys, vals, 8, leaf_slack=1 << 15, max_batch=1024)
+        srv = g.Server(t, slots=8)
+        batches = _batches(spec)
+        if mode == "mix":
+            assert srv.replay(batches) == g.GT_OK
+        else:
+            for b in batches:
+                assert srv.wait(srv.submit(b)) == g.GT_OK
+        outs.append(batches)
+        srv.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a.out0, b.out0)
+        if a.out1 is not None:
+            assert np.array_equal(a.out1, b.out1)
+        if a.count is not None:
+            assert np.array_equal(a.count, b.count)
+
+
+def test_learned_lookups_in_server():
+    import paper_2604_21117_amd as g
+    seed = 71
+    keys, vals, fresh = _setup(seed, n=1 << 17)
+    t = mk_tree(keys, vals, 8, leaf_slack=1 << 15, max_batch=1024)
+    li = g.Learned(t, models=256)
+    li.train()
+    srv = g.Server(t, learned=li, slots=8)
+    spec = synth.serving_mix(keys, 400, seed, bmax=512, rate=50000.0, fresh=fresh)
+    batches = _batches(spec)
+    assert srv.replay(batches) == g.GT_OK
+    _compare(batches, _oracle_replay(oracle.SortedArray(keys, vals, 64), batches))
+    srv.close()
+
+
+def test_admission_cap():
+    import paper_2604_21117_amd as g
+    seed = 72
+    keys, vals, fresh = _setup(seed, n=1 << 14)
+    t = mk_tree(keys, vals, 8, leaf_slack=1 << 12, max_batch=1024)
+    # room for one 64-key lookup batch at a time; a 1024-key batch never fits
+    srv = g.Server(t, slots=4, mem_cap=64 * 17)
+    big = g.Batch(0, keys[:1024])
+    small = [g.Batch(0, keys[i * 64:(i + 1) * 64]) for i in range(20)]
+    tb = srv.submit(big)
+    ts = [srv.submit(b) for b in small]
+    assert srv.wait(tb) == g.GT_ERR_ADMISSION
+    assert all(srv.wait(x) == g.GT_OK for x in ts)
+    sa = oracle.SortedArray(keys, vals, 64)
+    for b in small:
+        v, f = sa.lookup(b.keys)
+        assert np.array_equal(b.out0, v) and np.array_equal(b.out1, f)
+    srv.close()
