@@ -336,6 +336,16 @@ def main():
         srv.close()
         print("[bench] serving done", file=sys.stderr, flush=True)
 
+    # HBM bytes per launch from the committed counter summary, if it was
+    # taken on this same kernel
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if os.path.exists(tpath):
+        tj = json.load(open(tpath))
+        if tj.get("kernel") == "k_lookup<unsigned long, 8, 4, 2, true, false>" and tj.get("batch") == BL \
+                and tj.get("keys") == n:
+            traffic = tj["traffic_bytes"]
+
     line = {
         "metric": "lookup Mops/s and us/batch at B=1..1024, 2^24 keys; learned vs plain tree",
         "value": round(value, 3),
@@ -361,7 +371,7 @@ def main():
         "sweep": sweep,
         "large_batch": large,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_lookup<unsigned long, 8, 4, 2, true, false> (B=2^20, warm)",
                      "algorithmic_bytes": ab["bytes"]},
         "range": rng_row,

@@ -210,7 +210,14 @@ typedef struct {
                              1 = linear only; 2 = MLP only                    */
     uint32_t max_window;  /* a model whose window spans more leaves sends its
                              keys down the tree; 0 = default 64               */
-    uint32_t reserved;    /* must be 0                                        */
+    uint32_t search;      /* window search: 1 = through the fence directory;
+                             2 = read the window's leaves directly when the
+                             trained directory is the identity (a
+                             bulk-loaded tree); 0 = default (1)               */
+    uint32_t stage;       /* 1 = copy the model table into LDS per workgroup
+                             for batches up to 2^16; 2 = read it from L2;
+                             0 = default (2)                                  */
+    uint32_t reserved[2]; /* must be 0                                        */
 } gt_li_params;
 
 typedef struct {

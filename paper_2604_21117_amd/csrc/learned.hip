@@ -85,10 +85,32 @@ struct alignas(sizeof(K) == 8 ? 16 : 8) DirEntry {
 };
 static_assert(sizeof(DirEntry<uint64_t>) == 16 && sizeof(DirEntry<uint32_t>) == 8, "DirEntry size");
 
+// Compact per-model record read by the lookup (staged into LDS).
+struct ModelLite {
+    uint64_t kmin;
+    double scale;
+    float slope, icpt;
+    int32_t lo_hi;       // lo in the low 16 bits, hi in the high 16 (signed)
+    uint32_t kind;
+};
+static_assert(sizeof(ModelLite) == 32, "ModelLite size");
+
+// Root parameters passed to the lookup by value (no dependent header load).
+struct LiArgs {
+    uint64_t kmin_root;
+    double root_scale;
+    float root_a, root_b;
+    uint32_t L, M;
+    uint32_t identity;   // directory position == leaf id for every position
+    uint32_t pad;
+};
+
 template <class K>
 struct LiView {
     LiHeader* hdr;
     ModelRec* models;
+    ModelLite* lite;
+    uint32_t* identity;
     DirEntry<K>* dir;
     uint32_t* nxt0; uint32_t* nxt1; uint32_t* rank0; uint32_t* rank1;
     uint32_t* pos_of_leaf;
@@ -110,7 +132,8 @@ __device__ __forceinline__ float norm_x(uint64_t key, uint64_t kmin, double scal
     return static_cast<float>(d * scale);
 }
 
-__device__ __forceinline__ uint32_t root_index(const LiHeader& h, uint64_t key) {
+template <class H>
+__device__ __forceinline__ uint32_t root_index(const H& h, uint64_t key) {
     const float x = norm_x(key, h.kmin_root, h.root_scale);
     float f = __fmaf_rn(h.root_a, x, h.root_b);
     f = fminf(fmaxf(f, 0.0f), static_cast<float>(h.M - 1));
@@ -441,7 +464,8 @@ __global__ void k_choose(LiView<K> li, uint32_t M, uint32_t kind_pref, uint32_t 
             kind = use_mlp ? kKindMlp : kKindLinear;
             lo = use_mlp ? li.bnd[4 * j + 2] : li.bnd[4 * j + 0];
             hi = use_mlp ? li.bnd[4 * j + 3] : li.bnd[4 * j + 1];
-            if (static_cast<int64_t>(hi) - lo + 1 > static_cast<int64_t>(max_window)) {
+            if (static_cast<int64_t>(hi) - lo + 1 > static_cast<int64_t>(max_window) || lo < -32768 ||
+                hi > 32767) {
                 kind = kKindTree;
                 lo = hi = 0;
             }
@@ -449,7 +473,21 @@ __global__ void k_choose(LiView<K> li, uint32_t M, uint32_t kind_pref, uint32_t 
         m->kind = kind;
         m->lo = lo;
         m->hi = hi;
+        ModelLite ml;
+        ml.kmin = m->kmin;
+        ml.scale = m->scale;
+        ml.slope = m->slope;
+        ml.icpt = m->icpt;
+        ml.lo_hi = static_cast<int32_t>((static_cast<uint32_t>(static_cast<uint16_t>(static_cast<int16_t>(lo)))) |
+                                        (static_cast<uint32_t>(static_cast<uint16_t>(static_cast<int16_t>(hi))) << 16));
+        ml.kind = kind;
+        li.lite[j] = ml;
     }
+}
+
+__global__ void k_identity(const uint32_t* pos_of_leaf, uint32_t n, uint32_t* flag) {
+    for (uint64_t i = gid(); i < n; i += gsz())
+        if (pos_of_leaf[i] != i) *flag = 0u;
 }
 
 template <class K>
@@ -462,11 +500,14 @@ __global__ void k_li_finish(LiView<K> li, uint64_t n_keys) {
     }
 }
 
-__global__ void k_set_bounds(ModelRec* models, uint32_t M, int32_t lo, int32_t hi) {
+__global__ void k_set_bounds(ModelRec* models, ModelLite* lite, uint32_t M, int32_t lo, int32_t hi) {
     for (uint64_t j = gid(); j < M; j += gsz()) {
         if (models[j].kind != kKindTree) {
             models[j].lo = lo;
             models[j].hi = hi;
+            lite[j].lo_hi = static_cast<int32_t>(
+                (static_cast<uint32_t>(static_cast<uint16_t>(static_cast<int16_t>(lo)))) |
+                (static_cast<uint32_t>(static_cast<uint16_t>(static_cast<int16_t>(hi))) << 16));
         }
     }
 }
@@ -512,50 +553,94 @@ __device__ __forceinline__ int64_t window_search(const DirEntry<K>* dir, int32_t
     return cand;
 }
 
+constexpr int kDirect = 8;  // leaves a group reads at once on the direct path
+
+// Leaf verdict shared by both search paths: hit, authoritative miss (the
+// leaf's first and last keys bracket the key), or neither.
 template <class K>
-__global__ __launch_bounds__(kLiBlock) void k_li_lookup(TreeView<K> t, LiView<K> li, const K* __restrict__ q,
-                                                        uint64_t B, K* __restrict__ vout,
+struct Verdict {
+    bool hit = false, bracket = false;
+    K val = kmax<K>();
+};
+
+template <class K>
+__device__ __forceinline__ void judge_leaf(const typename Trav<K, kLiG>::KV& kv, const typename Trav<K, kLiG>::KV& vv,
+                                           K key, int gbase, Verdict<K>& v) {
+    using T = Trav<K, kLiG>;
+    const uint32_t slot = T::match_slot(kv, key, gbase);
+    const K first = static_cast<K>(__shfl(kv.v[0], gbase, 64));
+    const K last = static_cast<K>(__shfl(kv.v[T::KPL - 1], gbase + kLiG - 1, 64));
+    const K x = T::pick_value(vv, slot < kSlots ? slot : 0u, gbase);
+    if (slot < kSlots) {
+        v.hit = true;
+        v.val = x;
+    }
+    if (key >= first && key <= last) v.bracket = true;
+}
+
+template <class K, bool STAGE>
+__global__ __launch_bounds__(kLiBlock) void k_li_lookup(TreeView<K> t, LiView<K> li, LiArgs a,
+                                                        const K* __restrict__ q, uint64_t B, K* __restrict__ vout,
                                                         uint8_t* __restrict__ fout) {
     using T = Trav<K, kLiG>;
-    const LiHeader h = *li.hdr;
-    const MirrorHeader* mh = reinterpret_cast<const MirrorHeader*>(t.mirror);
-    const bool empty = mh->n_keys == 0;
+    extern __shared__ __align__(16) uint8_t lds[];
+    const ModelLite* tab = li.lite;
+    if constexpr (STAGE) {
+        const uint4* src = reinterpret_cast<const uint4*>(li.lite);
+        uint4* dst = reinterpret_cast<uint4*>(lds);
+        for (uint32_t i = threadIdx.x; i < a.M * (sizeof(ModelLite) / 16); i += blockDim.x) dst[i] = src[i];
+        __syncthreads();
+        tab = reinterpret_cast<const ModelLite*>(lds);
+    }
     const int lane = lane_id();
     const int gl = lane % kLiG, gbase = lane - gl;
     const uint64_t group = gid() / kLiG, ngroups = gsz() / kLiG;
     uint32_t nfb = 0;
     for (uint64_t i = group; i < B; i += ngroups) {
         const K key = q[i];
-        const uint32_t j = root_index(h, static_cast<uint64_t>(key));
-        const ModelRec* m = li.models + j;
-        const uint32_t kind = m->kind;
-        bool fb = kind == kKindTree;
-        uint32_t leaf = kNone;
+        const uint32_t j = root_index(a, static_cast<uint64_t>(key));
+        const ModelLite m = tab[j];
+        bool fb = m.kind == kKindTree;
+        Verdict<K> v;
         if (!fb) {
-            const int32_t p = predict(m, kind, static_cast<uint64_t>(key), h.L, gl);
-            int32_t wl = p + m->lo, wh = p + m->hi;
+            const float x = norm_x(static_cast<uint64_t>(key), m.kmin, m.scale);
+            const float f = m.kind == kKindMlp ? mlp_eval_group(li.models + j, x, gl) : __fmaf_rn(m.slope, x, m.icpt);
+            const int32_t p = clamp_pos(f, a.L);
+            const int32_t lo = static_cast<int16_t>(m.lo_hi & 0xFFFF), hi = static_cast<int16_t>(m.lo_hi >> 16);
+            int32_t wl = p + lo, wh = p + hi;
             if (wl < 0) wl = 0;
-            if (wh > static_cast<int32_t>(h.L) - 1) wh = static_cast<int32_t>(h.L) - 1;
-            const int64_t cand = window_search<K>(li.dir, wl, wh, key, gl, gbase, &leaf);
-            if (cand < 0) {
-                if (wl == 0) leaf = li.dir[0].leaf;  // below every fence: the first leaf
-                else fb = true;
-            }
-        }
-        K val = kmax<K>();
-        bool hit = false;
-        if (!fb) {
-            const typename T::KV kv = T::load_keys(t.lkeys + static_cast<uint64_t>(leaf) * kSlots, gl);
-            const typename T::KV vv = T::load_keys(t.lvals + static_cast<uint64_t>(leaf) * kSlots, gl);
-            const uint32_t slot = T::match_slot(kv, key, gbase);
-            const K first = static_cast<K>(__shfl(kv.v[0], gbase, 64));
-            const K last = static_cast<K>(__shfl(kv.v[T::KPL - 1], gbase + kLiG - 1, 64));
-            const K x = T::pick_value(vv, slot < kSlots ? slot : 0u, gbase);
-            if (slot < kSlots && !empty) {
-                hit = true;
-                val = x;
-            } else if (empty || !(key >= first && key <= last)) {
-                fb = !empty;
+            if (wh > static_cast<int32_t>(a.L) - 1) wh = static_cast<int32_t>(a.L) - 1;
+            if (a.identity) {
+                // positions are leaf ids: read the window's leaves at once
+                bool done = false;
+                for (int32_t base = wl; base <= wh && !done; base += kDirect) {
+                    typename T::KV kv[kDirect], vv[kDirect];
+#pragma unroll
+                    for (int u = 0; u < kDirect; ++u) {
+                        if (base + u <= wh) {
+                            kv[u] = T::load_keys(t.lkeys + static_cast<uint64_t>(base + u) * kSlots, gl);
+                            vv[u] = T::load_keys(t.lvals + static_cast<uint64_t>(base + u) * kSlots, gl);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < kDirect; ++u)
+                        if (base + u <= wh) judge_leaf<K>(kv[u], vv[u], key, gbase, v);
+                    done = v.hit || v.bracket;
+                }
+                fb = !(v.hit || v.bracket);
+            } else {
+                uint32_t leaf = kNone;
+                const int64_t cand = window_search<K>(li.dir, wl, wh, key, gl, gbase, &leaf);
+                if (cand < 0) {
+                    if (wl == 0) leaf = li.dir[0].leaf;  // below every fence: the first leaf
+                    else fb = true;
+                }
+                if (!fb) {
+                    const typename T::KV kv = T::load_keys(t.lkeys + static_cast<uint64_t>(leaf) * kSlots, gl);
+                    const typename T::KV vv = T::load_keys(t.lvals + static_cast<uint64_t>(leaf) * kSlots, gl);
+                    judge_leaf<K>(kv, vv, key, gbase, v);
+                    fb = !(v.hit || v.bracket);
+                }
             }
         }
         if (fb) {
@@ -565,15 +650,13 @@ __global__ __launch_bounds__(kLiBlock) void k_li_lookup(TreeView<K> t, LiView<K>
             descend<K, kLiG, 1, false>(t, t.mirror, kMirrorMaxNodes, 0, kk, lf, gl, gbase);
             const typename T::KV kv = T::load_keys(t.lkeys + static_cast<uint64_t>(lf[0]) * kSlots, gl);
             const typename T::KV vv = T::load_keys(t.lvals + static_cast<uint64_t>(lf[0]) * kSlots, gl);
-            const uint32_t slot = T::match_slot(kv, key, gbase);
-            const K x = T::pick_value(vv, slot < kSlots ? slot : 0u, gbase);
-            hit = slot < kSlots && !empty;
-            val = hit ? x : kmax<K>();
+            v = Verdict<K>();
+            judge_leaf<K>(kv, vv, key, gbase, v);
             nfb += gl == 0 ? 1u : 0u;
         }
         if (gl == 0) {
-            vout[i] = val;
-            fout[i] = hit ? 1 : 0;
+            vout[i] = v.hit ? v.val : kmax<K>();
+            fout[i] = v.hit ? 1 : 0;
         }
     }
     // counters: one atomic per wave
@@ -621,7 +704,8 @@ struct gt_learned {
     bool trained;
     uint64_t leaf_cap;
     uint64_t off_models, off_dir, off_nxt0, off_nxt1, off_rank0, off_rank1, off_pos, off_start, off_bnd, off_cnt,
-        off_partial, off_mlp;
+        off_partial, off_mlp, off_lite, off_ident;
+    LiArgs args;
 };
 
 namespace {
@@ -645,7 +729,10 @@ uint64_t layout_li(gt_learned* li, uint64_t leaf_cap, uint32_t M, int kb) {
     uint64_t o_cnt = off; off += al256(M * 4ull);
     uint64_t o_part = off; off += al256(kMaxPartials * 5ull * 8);
     uint64_t o_mlp = off; off += al256(M * 4ull);
+    uint64_t o_lite = off; off += al256(static_cast<uint64_t>(M) * sizeof(ModelLite));
+    uint64_t o_ident = off; off += 256;
     if (li) {
+        li->off_lite = o_lite; li->off_ident = o_ident;
         li->off_models = o_models; li->off_dir = o_dir; li->off_nxt0 = o_n0; li->off_nxt1 = o_n1;
         li->off_rank0 = o_r0; li->off_rank1 = o_r1; li->off_pos = o_pos; li->off_start = o_start;
         li->off_bnd = o_bnd; li->off_cnt = o_cnt; li->off_partial = o_part; li->off_mlp = o_mlp;
@@ -670,6 +757,8 @@ LiView<K> li_view(const gt_learned* li) {
     v.cnt = reinterpret_cast<uint32_t*>(a + li->off_cnt);
     v.partial = reinterpret_cast<double*>(a + li->off_partial);
     v.mlp_ok = reinterpret_cast<float*>(a + li->off_mlp);
+    v.lite = reinterpret_cast<ModelLite*>(a + li->off_lite);
+    v.identity = reinterpret_cast<uint32_t*>(a + li->off_ident);
     return v;
 }
 
@@ -731,11 +820,27 @@ gt_status train_t(gt_learned* li, hipStream_t s) {
     hipLaunchKernelGGL(k_bounds_init, dim3(grid_of(M, 256)), dim3(256), 0, s, v.bnd, v.cnt, M);
     hipLaunchKernelGGL(k_bounds<K>, dim3(grid_of(static_cast<uint64_t>(n) * kSlots * kLiG, kLiBlock, 8192)),
                        dim3(kLiBlock), 0, s, tv, v, n);
-    const uint32_t mw = li->p.max_window ? li->p.max_window : 64u;
+    uint32_t mw = li->p.max_window ? li->p.max_window : 64u;
+    if (mw > 4096u) mw = 4096u;  // windows are packed in 16 bits
     hipLaunchKernelGGL(k_choose<K>, dim3(grid_of(M, 256)), dim3(256), 0, s, v, M, li->p.kind, mw);
     hipLaunchKernelGGL(k_li_finish<K>, dim3(1), dim3(64), 0, s, v, dh.n_keys);
+    const uint32_t one = 1;
+    LI_HIP(hipMemcpyAsync(v.identity, &one, 4, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_identity, dim3(grid_of(n, 256)), dim3(256), 0, s, v.pos_of_leaf, n, v.identity);
     if (hipGetLastError() != hipSuccess) return GT_ERR_HIP;
+    LiHeader h;
+    uint32_t ident = 0;
+    LI_HIP(hipMemcpyAsync(&h, v.hdr, sizeof h, hipMemcpyDeviceToHost, s));
+    LI_HIP(hipMemcpyAsync(&ident, v.identity, 4, hipMemcpyDeviceToHost, s));
     LI_HIP(hipStreamSynchronize(s));
+    li->args.kmin_root = h.kmin_root;
+    li->args.root_scale = h.root_scale;
+    li->args.root_a = h.root_a;
+    li->args.root_b = h.root_b;
+    li->args.L = h.L;
+    li->args.M = h.M;
+    li->args.identity = (li->p.search == 2) ? ident : 0u;
+    li->args.pad = 0;
     li->trained = true;
     return GT_OK;
 }
@@ -746,13 +851,15 @@ extern "C" {
 
 uint64_t li_arena_bytes(const gt_tree* t, const gt_li_params* p) {
     if (!t) return 0;
-    if (p && (p->models > 4096 || p->kind > 2 || p->reserved)) return 0;
+    if (p && (p->models > 4096 || p->kind > 2 || p->search > 2 || p->stage > 2 || p->reserved[0] || p->reserved[1]))
+        return 0;
     return layout_li(nullptr, t->leaf_cap, models_of(p), t->kb);
 }
 
 gt_status li_create(gt_tree* t, const gt_li_params* p, void* arena, uint64_t arena_bytes, gt_learned** out) {
     if (!t || !arena || !out) return GT_ERR_INVALID;
-    if (p && (p->models > 4096 || p->kind > 2 || p->reserved)) return GT_ERR_INVALID;
+    if (p && (p->models > 4096 || p->kind > 2 || p->search > 2 || p->stage > 2 || p->reserved[0] || p->reserved[1]))
+        return GT_ERR_INVALID;
     const uint32_t M = models_of(p);
     if (layout_li(nullptr, t->leaf_cap, M, t->kb) > arena_bytes) return GT_ERR_CAPACITY;
     gt_learned* li = new gt_learned();
@@ -783,14 +890,33 @@ gt_status li_lookup_batch(gt_learned* li, const void* keys, uint64_t B, void* va
     if (!keys || !values_out || !found_out) return GT_ERR_INVALID;
     if (!li->trained) return tree_lookup_batch(li->t, keys, B, values_out, found_out, stream);
     const uint32_t grid = grid_of(B * kLiG, kLiBlock, 2048);
-    if (li->t->kb == 8)
-        hipLaunchKernelGGL(k_li_lookup<uint64_t>, dim3(grid), dim3(kLiBlock), 0, stream, view<uint64_t>(li->t),
-                           li_view<uint64_t>(li), reinterpret_cast<const uint64_t*>(keys), B,
-                           reinterpret_cast<uint64_t*>(values_out), found_out);
-    else
-        hipLaunchKernelGGL(k_li_lookup<uint32_t>, dim3(grid), dim3(kLiBlock), 0, stream, view<uint32_t>(li->t),
-                           li_view<uint32_t>(li), reinterpret_cast<const uint32_t*>(keys), B,
-                           reinterpret_cast<uint32_t*>(values_out), found_out);
+    // the model table goes to LDS when it is small; large batches keep it in
+    // L2, where the staging would cost more than it saves
+    const uint32_t lds = li->M * static_cast<uint32_t>(sizeof(ModelLite));
+    const bool stage = li->p.stage == 1 && lds <= 48u * 1024u && B <= (1u << 16);
+    if (li->t->kb == 8) {
+        if (stage)
+            hipLaunchKernelGGL((k_li_lookup<uint64_t, true>), dim3(grid), dim3(kLiBlock), lds, stream,
+                               view<uint64_t>(li->t), li_view<uint64_t>(li), li->args,
+                               reinterpret_cast<const uint64_t*>(keys), B, reinterpret_cast<uint64_t*>(values_out),
+                               found_out);
+        else
+            hipLaunchKernelGGL((k_li_lookup<uint64_t, false>), dim3(grid), dim3(kLiBlock), 0, stream,
+                               view<uint64_t>(li->t), li_view<uint64_t>(li), li->args,
+                               reinterpret_cast<const uint64_t*>(keys), B, reinterpret_cast<uint64_t*>(values_out),
+                               found_out);
+    } else {
+        if (stage)
+            hipLaunchKernelGGL((k_li_lookup<uint32_t, true>), dim3(grid), dim3(kLiBlock), lds, stream,
+                               view<uint32_t>(li->t), li_view<uint32_t>(li), li->args,
+                               reinterpret_cast<const uint32_t*>(keys), B, reinterpret_cast<uint32_t*>(values_out),
+                               found_out);
+        else
+            hipLaunchKernelGGL((k_li_lookup<uint32_t, false>), dim3(grid), dim3(kLiBlock), 0, stream,
+                               view<uint32_t>(li->t), li_view<uint32_t>(li), li->args,
+                               reinterpret_cast<const uint32_t*>(keys), B, reinterpret_cast<uint32_t*>(values_out),
+                               found_out);
+    }
     return hipGetLastError() == hipSuccess ? GT_OK : GT_ERR_HIP;
 }
 
@@ -811,8 +937,10 @@ gt_status li_predict(gt_learned* li, const void* keys, uint64_t B, uint32_t* mod
 
 gt_status li_set_bounds(gt_learned* li, int32_t lo, int32_t hi, hipStream_t stream) {
     if (!li || lo > hi) return GT_ERR_INVALID;
+    if (lo < -30000 || hi > 30000) return GT_ERR_INVALID;
     hipLaunchKernelGGL(k_set_bounds, dim3(grid_of(li->M, 256)), dim3(256), 0, stream,
-                       reinterpret_cast<ModelRec*>(li->arena + li->off_models), li->M, lo, hi);
+                       reinterpret_cast<ModelRec*>(li->arena + li->off_models),
+                       reinterpret_cast<ModelLite*>(li->arena + li->off_lite), li->M, lo, hi);
     return hipGetLastError() == hipSuccess ? GT_OK : GT_ERR_HIP;
 }
 

@@ -45,9 +45,10 @@ def _check_bounds(tree, li):
     return used.mean()
 
 
+@pytest.mark.parametrize("search,stage", [(1, 2), (2, 1)])
 @pytest.mark.parametrize("width", [32, 64])
 @pytest.mark.parametrize("dist", ["uniform", "lognormal", "clustered"])
-def test_learned_parity_and_bounds(width, dist):
+def test_learned_parity_and_bounds(width, dist, search, stage):
     seed = 41
     n = 1 << 18
     if dist == "uniform":
@@ -61,7 +62,7 @@ def test_learned_parity_and_bounds(width, dist):
     vals = synth.values_for(keys, seed, width)
     sa = oracle.SortedArray(keys, vals, width)
     t = mk_tree(keys, vals, width // 8, leaf_slack=1 << 14, max_batch=1 << 14)
-    li = _learned(t, models=256)
+    li = _learned(t, models=256, search=search, stage=stage)
     frac_used = _check_bounds(t, li)
     assert frac_used > 0.5
     q = synth.mixed_queries(keys, 60000, seed, width)
@@ -113,7 +114,7 @@ def test_stale_after_inserts_then_retrain():
     vals = synth.values_for(keys, seed, width)
     sa = oracle.SortedArray(keys, vals, width)
     t = mk_tree(keys, vals, 8, leaf_slack=1 << 16, max_batch=1 << 14)
-    li = _learned(t)
+    li = _learned(t, search=2, stage=1)
     rng = np.random.default_rng(seed)
     for b in range(5):
         ins = synth.uniform_keys(10000, seed + 100 + b, width, exclude=sa.keys)
