@@ -85,9 +85,11 @@ __global__ void k_set_header(DevHeader* h, uint32_t root, uint32_t height, uint6
     }
 }
 
-// One workgroup of 256 threads.
+// One workgroup of 256 threads.  With `dirty` given, nothing happens unless
+// *dirty is set.
 template <class K>
-__global__ __launch_bounds__(256) void k_mirror_refresh(TreeView<K> t) {
+__global__ __launch_bounds__(256) void k_mirror_refresh(TreeView<K> t, const uint32_t* dirty) {
+    if (dirty && *dirty == 0) return;
     using ML = MirrorLayout<K>;
     constexpr uint32_t full = kMirrorMaxNodes;
     __shared__ uint32_t ids[kMirrorMaxNodes];
@@ -219,7 +221,12 @@ void launch_dup_check(const K* sk, uint64_t n, uint32_t* flag, hipStream_t s) {
 
 template <class K>
 void launch_mirror_refresh(const TreeView<K>& t, hipStream_t s) {
-    hipLaunchKernelGGL(k_mirror_refresh<K>, dim3(1), dim3(256), 0, s, t);
+    hipLaunchKernelGGL(k_mirror_refresh<K>, dim3(1), dim3(256), 0, s, t, nullptr);
+}
+
+template <class K>
+void launch_mirror_refresh_if(const TreeView<K>& t, const uint32_t* dirty, hipStream_t s) {
+    hipLaunchKernelGGL(k_mirror_refresh<K>, dim3(1), dim3(256), 0, s, t, dirty);
 }
 
 template <class K>
@@ -259,6 +266,8 @@ template void launch_dup_check<uint32_t>(const uint32_t*, uint64_t, uint32_t*, h
 template void launch_dup_check<uint64_t>(const uint64_t*, uint64_t, uint32_t*, hipStream_t);
 template void launch_mirror_refresh<uint32_t>(const TreeView<uint32_t>&, hipStream_t);
 template void launch_mirror_refresh<uint64_t>(const TreeView<uint64_t>&, hipStream_t);
+template void launch_mirror_refresh_if<uint32_t>(const TreeView<uint32_t>&, const uint32_t*, hipStream_t);
+template void launch_mirror_refresh_if<uint64_t>(const TreeView<uint64_t>&, const uint32_t*, hipStream_t);
 template void launch_build<uint32_t>(const TreeView<uint32_t>&, const uint32_t*, const uint32_t*, uint64_t,
                                      const uint64_t*, int, uint32_t*, hipStream_t);
 template void launch_build<uint64_t>(const TreeView<uint64_t>&, const uint64_t*, const uint64_t*, uint64_t,

@@ -47,12 +47,13 @@ struct InsState {
     uint32_t height;       // tree height when the batch started
     uint32_t overflow;     // item pool would overflow (internal error)
     uint32_t grow_nodes, grow_levels, new_root;
+    uint32_t mirror_dirty;
     uint32_t lvl_count[kMaxLevels];  // items per level (0 = leaves)
     uint32_t lvl_base[kMaxLevels];   // first item of the level in the pool
     uint32_t lvl_new[kMaxLevels];    // new nodes the level's items create
     uint32_t lvl_alloc[kMaxLevels];  // first new id of the level
     uint32_t lvl_psep[kMaxLevels];   // first piece separator of the level
-    uint32_t pad[8];
+    uint32_t pad[7];
 };
 
 template <class K>
@@ -221,9 +222,9 @@ __global__ __launch_bounds__(kBlk) void k_locate(TreeView<K> t, Ins<K> v, uint8_
 }
 
 template <class K>
-__global__ void k_compact_new(Ins<K> v) {
+__device__ __forceinline__ void ph_compact_new(Ins<K> v, uint64_t tid, uint64_t nth) {
     const uint64_t U = v.st->U;
-    for (uint64_t u = gtid(); u < U; u += gstride()) {
+    for (uint64_t u = tid; u < U; u += nth) {
         if (!v.ufound[u]) {
             const uint32_t r = v.f1[u];
             v.nk[r] = v.uk[u];
@@ -235,16 +236,26 @@ __global__ void k_compact_new(Ins<K> v) {
 }
 
 template <class K>
-__global__ void k_leaf_heads(Ins<K> v) {
+__global__ void k_compact_new(Ins<K> v) {
+    ph_compact_new<K>(v, gtid(), gstride());
+}
+
+template <class K>
+__device__ __forceinline__ void ph_leaf_heads(Ins<K> v, uint64_t tid, uint64_t nth) {
     const uint64_t R = v.st->R;
-    for (uint64_t r = gtid(); r < R; r += gstride())
+    for (uint64_t r = tid; r < R; r += nth)
         v.f0[r] = (r == 0 || v.nleaf[r] != v.nleaf[r - 1]) ? 1u : 0u;
 }
 
 template <class K>
-__global__ void k_leaf_items(Ins<K> v) {
+__global__ void k_leaf_heads(Ins<K> v) {
+    ph_leaf_heads<K>(v, gtid(), gstride());
+}
+
+template <class K>
+__device__ __forceinline__ void ph_leaf_items(Ins<K> v, uint64_t tid, uint64_t nth) {
     const uint64_t R = v.st->R;
-    for (uint64_t r = gtid(); r < R; r += gstride()) {
+    for (uint64_t r = tid; r < R; r += nth) {
         const uint32_t f = v.f0[r], e = v.f1[r];
         if (f) {
             if (e >= v.ip_cap) { v.st->overflow = 1; continue; }
@@ -260,9 +271,14 @@ __global__ void k_leaf_items(Ins<K> v) {
 }
 
 template <class K>
-__global__ void k_leaf_plan(TreeView<K> t, Ins<K> v) {
+__global__ void k_leaf_items(Ins<K> v) {
+    ph_leaf_items<K>(v, gtid(), gstride());
+}
+
+template <class K>
+__device__ __forceinline__ void ph_leaf_plan(TreeView<K> t, Ins<K> v, uint64_t tid, uint64_t nth) {
     const uint64_t T0 = v.st->lvl_count[0];
-    for (uint64_t i = gtid(); i < T0; i += gstride()) {
+    for (uint64_t i = tid; i < T0; i += nth) {
         const uint32_t c = t.lmeta[v.it_node[i]].x;
         const uint64_t total = static_cast<uint64_t>(c) + (v.it_end[i] - v.it_first[i]);
         const uint32_t k = split_pieces(total);
@@ -272,18 +288,23 @@ __global__ void k_leaf_plan(TreeView<K> t, Ins<K> v) {
     }
 }
 
+template <class K>
+__global__ void k_leaf_plan(TreeView<K> t, Ins<K> v) {
+    ph_leaf_plan<K>(t, v, gtid(), gstride());
+}
+
 // heads of the level-d items: runs of level-(d-1) items with the same parent
 template <class K>
-__global__ void k_par_heads(Ins<K> v, int d) {
+__device__ __forceinline__ void ph_par_heads(Ins<K> v, int d, uint64_t tid, uint64_t nth) {
     const int h = static_cast<int>(v.st->height);
     const int l = h - 1 - d;  // parent level, 0 = root level
     const uint64_t n = v.st->lvl_count[d - 1];
     const uint32_t b = v.st->lvl_base[d - 1];
-    if (gtid() == 0) {
+    if (tid == 0) {
         v.st->lvl_base[d] = b + v.st->lvl_count[d - 1];
         v.st->lvl_psep[d] = v.st->lvl_psep[d - 1] + v.st->lvl_new[d - 1];
     }
-    for (uint64_t i = gtid(); i < n; i += gstride()) {
+    for (uint64_t i = tid; i < n; i += nth) {
         uint32_t f = 0;
         if (l >= 0) {
             const uint32_t p = v.pn[static_cast<uint64_t>(l) * v.Bm + v.it_rep[b + i]];
@@ -294,14 +315,19 @@ __global__ void k_par_heads(Ins<K> v, int d) {
 }
 
 template <class K>
-__global__ void k_par_items(Ins<K> v, int d) {
+__global__ void k_par_heads(Ins<K> v, int d) {
+    ph_par_heads<K>(v, d, gtid(), gstride());
+}
+
+template <class K>
+__device__ __forceinline__ void ph_par_items(Ins<K> v, int d, uint64_t tid, uint64_t nth) {
     const int h = static_cast<int>(v.st->height);
     const int l = h - 1 - d;
     if (l < 0) return;
     const uint64_t n = v.st->lvl_count[d - 1];
     const uint32_t b = v.st->lvl_base[d - 1];
     const uint32_t bd = v.st->lvl_base[d];
-    for (uint64_t i = gtid(); i < n; i += gstride()) {
+    for (uint64_t i = tid; i < n; i += nth) {
         const uint32_t f = v.f0[i], e = v.f1[i];
         if (f) {
             if (bd + e >= v.ip_cap) { v.st->overflow = 1; continue; }
@@ -317,11 +343,16 @@ __global__ void k_par_items(Ins<K> v, int d) {
 }
 
 template <class K>
-__global__ void k_par_plan(TreeView<K> t, Ins<K> v, int d) {
+__global__ void k_par_items(Ins<K> v, int d) {
+    ph_par_items<K>(v, d, gtid(), gstride());
+}
+
+template <class K>
+__device__ __forceinline__ void ph_par_plan(TreeView<K> t, Ins<K> v, int d, uint64_t tid, uint64_t nth) {
     const uint64_t n = v.st->lvl_count[d];
     const uint32_t bd = v.st->lvl_base[d];
     const uint32_t bc = v.st->lvl_base[d - 1];
-    for (uint64_t j = gtid(); j < n; j += gstride()) {
+    for (uint64_t j = tid; j < n; j += nth) {
         const uint32_t node = v.it_node[bd + j];
         uint32_t C = 0;
         const uint32_t* ch = t.ichild + static_cast<uint64_t>(node) * kSlots;
@@ -335,18 +366,28 @@ __global__ void k_par_plan(TreeView<K> t, Ins<K> v, int d) {
     }
 }
 
+template <class K>
+__global__ void k_par_plan(TreeView<K> t, Ins<K> v, int d) {
+    ph_par_plan<K>(t, v, d, gtid(), gstride());
+}
+
 // this level's allocation offsets, moved to the level's slice of the pool
 template <class K>
-__global__ void k_par_off(Ins<K> v, int d) {
+__device__ __forceinline__ void ph_par_off(Ins<K> v, int d, uint64_t tid, uint64_t nth) {
     const uint64_t n = v.st->lvl_count[d];
     const uint32_t bd = v.st->lvl_base[d];
-    for (uint64_t j = gtid(); j < n; j += gstride()) v.it_off[bd + j] = v.f1[j];
+    for (uint64_t j = tid; j < n; j += nth) v.it_off[bd + j] = v.f1[j];
+}
+
+template <class K>
+__global__ void k_par_off(Ins<K> v, int d) {
+    ph_par_off<K>(v, d, gtid(), gstride());
 }
 
 // Capacity check and allocation bases (one thread).
 template <class K>
-__global__ void k_check(TreeView<K> t, Ins<K> v) {
-    if (gtid() != 0) return;
+__device__ __forceinline__ void ph_check(TreeView<K> t, Ins<K> v, uint64_t tid, uint64_t nth) {
+    if (tid != 0) return;
     InsState* st = v.st;
     DevHeader* hdr = t.hdr;
     const int h = static_cast<int>(st->height);
@@ -382,6 +423,11 @@ __global__ void k_check(TreeView<K> t, Ins<K> v) {
         cur += st->lvl_new[d];
     }
     st->new_root = cur;  // first growth node id
+}
+
+template <class K>
+__global__ void k_check(TreeView<K> t, Ins<K> v) {
+    ph_check<K>(t, v, gtid(), gstride());
 }
 
 template <class K>
@@ -555,7 +601,7 @@ __global__ __launch_bounds__(kBlk) void k_apply_inner(TreeView<K> t, Ins<K> v, i
 
 // Root growth: pack the root's pieces into new levels (one workgroup).
 template <class K>
-__global__ __launch_bounds__(1024) void k_grow(TreeView<K> t, Ins<K> v) {
+__device__ __forceinline__ void grow_body(TreeView<K> t, Ins<K> v) {
     if (!v.st->ok || v.st->grow_levels == 0) return;
     const int h = static_cast<int>(v.st->height);
     const int dr = h - 1;
@@ -603,9 +649,10 @@ __global__ __launch_bounds__(1024) void k_grow(TreeView<K> t, Ins<K> v) {
     if (threadIdx.x == 0) v.st->new_root = cursor - 1;
 }
 
+
 template <class K>
-__global__ void k_commit(TreeView<K> t, Ins<K> v) {
-    if (gtid() != 0 || !v.st->ok) return;
+__device__ __forceinline__ void ph_commit(TreeView<K> t, Ins<K> v) {
+    if (!v.st->ok) return;
     InsState* st = v.st;
     DevHeader* hdr = t.hdr;
     const int h = static_cast<int>(st->height);
@@ -619,6 +666,108 @@ __global__ void k_commit(TreeView<K> t, Ins<K> v) {
         hdr->root = st->new_root;
     }
     hdr->epoch += 1;
+    // the mirror (three top inner levels, key count) needs a refresh when the
+    // root grew, the tree was empty, or a node of the top three levels was
+    // rewritten: parents at tree level l change when their children (item
+    // level h-2-l) split
+    bool dirty = st->grow_levels > 0 || hdr->n_keys == st->R;
+    for (int l = 0; l < 3; ++l) {
+        const int dc = h - 2 - l;
+        if (dc >= 0 && st->lvl_new[dc] > 0) dirty = true;
+    }
+    st->mirror_dirty = dirty ? 1u : 0u;
+    reinterpret_cast<MirrorHeader*>(t.mirror)->n_keys = hdr->n_keys;
+}
+
+// growth then commit, one workgroup
+template <class K>
+__global__ __launch_bounds__(1024) void k_grow_commit(TreeView<K> t, Ins<K> v) {
+    grow_body<K>(t, v);
+    __syncthreads();
+    if (threadIdx.x == 0) ph_commit<K>(t, v);
+}
+
+// ------------------------------------------------- small batches (B <= 2048)
+//
+// One workgroup sorts, deduplicates and plans every level, with barriers
+// where the general path has kernel boundaries and block scans where it has
+// device-wide scans; the phase bodies are the same functions.
+
+constexpr uint32_t kSmallInsert = 2048;
+constexpr int kSmallBlock = 1024;
+
+template <class K>
+__global__ __launch_bounds__(kSmallBlock) void k_small_prefix(Ins<K> v, const DevHeader* hdr,
+                                                               const K* __restrict__ keys, const K* __restrict__ vals,
+                                                               uint32_t B, uint32_t n2, uint8_t* __restrict__ status) {
+    __shared__ K sk[kSmallInsert];
+    __shared__ uint32_t si[kSmallInsert];
+    __shared__ uint32_t sh[33];
+    const uint32_t tid = threadIdx.x;
+    uint32_t* s = reinterpret_cast<uint32_t*>(v.st);
+    for (uint32_t i = tid; i < sizeof(InsState) / 4; i += blockDim.x) s[i] = 0;
+    for (uint32_t i = tid; i < n2; i += blockDim.x) {
+        sk[i] = i < B ? keys[i] : kmax<K>();
+        si[i] = i < B ? i : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    if (tid == 0) v.st->height = hdr->height;
+    bitonic_lds<K>(sk, si, n2);
+    uint32_t f[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const uint32_t p = 2 * tid + e;
+        f[e] = (p < B && (p == 0 || sk[p] != sk[p - 1])) ? 1u : 0u;
+    }
+    uint32_t tot;
+    const uint32_t off = block_excl_scan<uint32_t>(f[0] + f[1], sh, &tot);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const uint32_t p = 2 * tid + e;
+        if (p >= B) continue;
+        const uint32_t pos = off + (e ? f[0] : 0u);
+        v.sk[p] = sk[p];
+        v.si[p] = si[p];
+        if (f[e]) {
+            v.uk[pos] = sk[p];
+            v.upos[pos] = p;
+        } else {
+            status[si[p]] = 1;  // UPDATED: an earlier occurrence exists
+        }
+        if (p + 1 == B || sk[p + 1] != sk[p]) v.uv[pos + f[e] - 1] = vals[si[p]];
+    }
+    if (tid == 0) v.st->U = tot;
+}
+
+template <class K>
+__global__ __launch_bounds__(kSmallBlock) void k_small_plan(TreeView<K> t, Ins<K> v, int H) {
+    __shared__ uint32_t sh[33];
+    const uint64_t tid = threadIdx.x, nth = blockDim.x;
+    block_scan_small(v.f0, v.f1, v.st->U, &v.st->R, sh);
+    ph_compact_new<K>(v, tid, nth);
+    __syncthreads();
+    ph_leaf_heads<K>(v, tid, nth);
+    __syncthreads();
+    block_scan_small(v.f0, v.f1, v.st->R, &v.st->lvl_count[0], sh);
+    ph_leaf_items<K>(v, tid, nth);
+    __syncthreads();
+    ph_leaf_plan<K>(t, v, tid, nth);
+    __syncthreads();
+    block_scan_small(v.f0, v.it_off, v.st->lvl_count[0], &v.st->lvl_new[0], sh);
+    const int h = static_cast<int>(v.st->height);
+    for (int d = 1; d < H && d < h; ++d) {
+        ph_par_heads<K>(v, d, tid, nth);
+        __syncthreads();
+        block_scan_small(v.f0, v.f1, v.st->lvl_count[d - 1], &v.st->lvl_count[d], sh);
+        ph_par_items<K>(v, d, tid, nth);
+        __syncthreads();
+        ph_par_plan<K>(t, v, d, tid, nth);
+        __syncthreads();
+        block_scan_small(v.f0, v.f1, v.st->lvl_count[d], &v.st->lvl_new[d], sh);
+        ph_par_off<K>(v, d, tid, nth);
+        __syncthreads();
+    }
+    ph_check<K>(t, v, tid, nth);
 }
 
 // ------------------------------------------------------------------ launch
@@ -662,6 +811,18 @@ static int height_bound(uint64_t leaf_cap) {
     return h + 1 < kMaxLevels ? h + 1 : kMaxLevels;
 }
 
+// apply, grow, commit, mirror: shared by both paths
+template <class K>
+static void launch_apply(const TreeView<K>& t, const Ins<K>& v, uint64_t B, int H, hipStream_t s) {
+    const uint32_t gB = grid_for(B, kBlk);
+    hipLaunchKernelGGL(k_apply_updates<K>, dim3(gB), dim3(kBlk), 0, s, t, v);
+    hipLaunchKernelGGL(k_apply_leaves<K>, dim3(grid_for(B, kBlk / 64)), dim3(kBlk), 0, s, t, v);
+    for (int d = 1; d < H; ++d)
+        hipLaunchKernelGGL(k_apply_inner<K>, dim3(grid_for(B, kBlk / 64)), dim3(kBlk), 0, s, t, v, d);
+    hipLaunchKernelGGL(k_grow_commit<K>, dim3(1), dim3(1024), 0, s, t, v);
+    launch_mirror_refresh_if<K>(t, &v.st->mirror_dirty, s);
+}
+
 template <class K>
 void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, const K* vals, uint64_t B,
                    uint8_t* status, hipStream_t s) {
@@ -671,6 +832,16 @@ void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, cons
     const uint32_t gB = grid_for(B, kBlk);
     const int H = height_bound(c.leaf_cap);
 
+    if (B <= kSmallInsert) {
+        uint32_t n2 = 2;
+        while (n2 < B) n2 <<= 1;
+        hipLaunchKernelGGL(k_small_prefix<K>, dim3(1), dim3(kSmallBlock), 0, s, v, t.hdr, keys, vals,
+                           static_cast<uint32_t>(B), n2, status);
+        launch_locate<K>(t, v, c.cfg, B, status, s);
+        hipLaunchKernelGGL(k_small_plan<K>, dim3(1), dim3(kSmallBlock), 0, s, t, v, H);
+        launch_apply<K>(t, v, B, H, s);
+        return;
+    }
     hipLaunchKernelGGL(k_init<K>, dim3(gB), dim3(kBlk), 0, s, v, t.hdr, keys, B);
     sort_pairs<K>(v.sk, v.si, v.sk2, v.si2, B, v.sort_tmp, s);
     hipLaunchKernelGGL(k_heads<K>, dim3(gB), dim3(kBlk), 0, s, v, B, status);
@@ -693,13 +864,7 @@ void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, cons
         hipLaunchKernelGGL(k_par_off<K>, dim3(gB), dim3(kBlk), 0, s, v, d);
     }
     hipLaunchKernelGGL(k_check<K>, dim3(1), dim3(64), 0, s, t, v);
-    hipLaunchKernelGGL(k_apply_updates<K>, dim3(gB), dim3(kBlk), 0, s, t, v);
-    hipLaunchKernelGGL(k_apply_leaves<K>, dim3(grid_for(B, kBlk / 64)), dim3(kBlk), 0, s, t, v);
-    for (int d = 1; d < H; ++d)
-        hipLaunchKernelGGL(k_apply_inner<K>, dim3(grid_for(B, kBlk / 64)), dim3(kBlk), 0, s, t, v, d);
-    hipLaunchKernelGGL(k_grow<K>, dim3(1), dim3(1024), 0, s, t, v);
-    hipLaunchKernelGGL(k_commit<K>, dim3(1), dim3(64), 0, s, t, v);
-    launch_mirror_refresh<K>(t, s);
+    launch_apply<K>(t, v, B, H, s);
 }
 
 template void launch_insert<uint32_t>(const TreeView<uint32_t>&, const InsertCtx&, const uint32_t*,

@@ -39,6 +39,47 @@ __device__ __forceinline__ T block_excl_scan(T v, T* sh, T* total) {
     return res;
 }
 
+// Bitonic sort of (key, index) pairs held in LDS, n2 a power of two, by the
+// whole workgroup; pairs compare by key then index, so equal keys keep their
+// index order.
+template <class K>
+__device__ __forceinline__ void bitonic_lds(K* sk, uint32_t* si, uint32_t n2) {
+    const uint32_t half = n2 >> 1;
+    for (uint32_t k = 2; k <= n2; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            // pair q compares slots t and t + j, where t has bit j clear
+            for (uint32_t q = threadIdx.x; q < half; q += blockDim.x) {
+                const uint32_t t = ((q & ~(j - 1)) << 1) | (q & (j - 1));
+                const uint32_t p = t | j;
+                const K a = sk[t], b = sk[p];
+                const uint32_t ia = si[t], ib = si[p];
+                const bool gt = (a > b) || (a == b && ia > ib);
+                const bool up = (t & k) == 0;
+                if (gt == up) {
+                    sk[t] = b; sk[p] = a;
+                    si[t] = ib; si[p] = ia;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Exclusive scan of in[0..n) into out[0..n) (global memory, may alias) by
+// one workgroup, n <= 2 * blockDim.x; the total goes to *tot.  All threads
+// call it; it ends with a barrier.
+__device__ __forceinline__ void block_scan_small(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tot,
+                                                 uint32_t* sh) {
+    const uint32_t i0 = 2 * threadIdx.x, i1 = i0 + 1;
+    const uint32_t a = i0 < n ? in[i0] : 0u, b = i1 < n ? in[i1] : 0u;
+    uint32_t total;
+    const uint32_t off = block_excl_scan<uint32_t>(a + b, sh, &total);
+    if (i0 < n) out[i0] = off;
+    if (i1 < n) out[i1] = off + a;
+    if (tot && threadIdx.x == 0) *tot = total;
+    __syncthreads();
+}
+
 // ------------------------------------------------------------ host side
 
 // Scratch bytes needed by scan_exclusive for up to n elements.

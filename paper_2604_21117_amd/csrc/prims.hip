@@ -153,24 +153,7 @@ __global__ __launch_bounds__(kSortBlock) void k_bitonic(K* keys, uint32_t* idx, 
         si[t] = t < n ? idx[t] : 0xFFFFFFFFu;
     }
     __syncthreads();
-    for (uint32_t k = 2; k <= n2; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t t = threadIdx.x; t < n2; t += kSortBlock) {
-                uint32_t p = t ^ j;
-                if (p > t) {
-                    K a = sk[t], b = sk[p];
-                    uint32_t ia = si[t], ib = si[p];
-                    bool gt = (a > b) || (a == b && ia > ib);
-                    bool up = (t & k) == 0;
-                    if (gt == up) {
-                        sk[t] = b; sk[p] = a;
-                        si[t] = ib; si[p] = ia;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
+    bitonic_lds<K>(sk, si, n2);
     for (uint32_t t = threadIdx.x; t < n; t += kSortBlock) {
         keys[t] = sk[t];
         idx[t] = si[t];

@@ -148,3 +148,36 @@ def test_large_batch_radix_path():
     assert np.array_equal(st, sa.insert(k, v))
     assert_export_parity(t, sa)
     assert_lookup_parity(t, sa, k[:200000])
+
+
+@pytest.mark.parametrize("xcd", [0, 1])
+def test_mirror_follows_top_levels(xcd):
+    """Height-5 tree (2^20 u64 keys), three mirrored inner levels staged in
+    LDS.  Sparse batches split leaves only, so the mirrored levels stay as
+    they are; clustered batches split level-3 nodes and rewrite mirrored
+    level-2 nodes.  Lookups through the mirror (and the XCD splitters taken
+    from it) match the oracle after every batch."""
+    width, seed = 64, 41
+    keys = synth.uniform_keys(1 << 20, seed, width)
+    vals = synth.values_for(keys, seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, 8, leaf_slack=1 << 15, max_batch=4096, lds_levels=3, xcd_split=xcd)
+    assert t.stats()["height"] == 5
+    rng = np.random.default_rng(seed)
+    sk = np.sort(keys)
+    fresh = synth.uniform_keys(1 << 15, seed + 3, width, exclude=keys)
+    for bi in range(8):
+        if bi % 2 == 0:
+            k = fresh[bi * 1024:(bi + 1) * 1024]
+        else:
+            j = int(rng.integers(0, len(sk) - 5000))
+            lo, hi = int(sk[j]), int(sk[j + 4000])
+            k = np.unique(rng.integers(lo, hi, 3000, dtype=np.uint64))
+            k = synth.shuffle(k, seed + bi)
+        v = synth.values_for(k, seed + 100 + bi, width)
+        st = t.insert(k, v)
+        assert np.array_equal(st, sa.insert(k, v)), f"status differs in batch {bi}"
+        q = np.concatenate([k, keys[rng.integers(0, len(keys), (1 << 15) - len(k) - 4096)],
+                            fresh[-4096:]])
+        assert_lookup_parity(t, sa, q)
+    assert_export_parity(t, sa)
