@@ -6,12 +6,18 @@ bulk-loaded at fill 1.0 (fanout 16, 16 keys per leaf, height 6), resident in
 HBM, with a learned index of 1024 models trained on it.  A timed step is one
 lookup batch of B = 1024 keys drawn uniformly from the present keys (inputs
 already in HBM), through the learned index (`--path plain`: the tree).
+The steps cycle over 2048 distinct query batches (2^21 queries) and are
+submitted as HIP graph replays, each graph holding 64 consecutive steps:
+a single eager launch costs the host about as long as a B = 1024 lookup
+takes on the device, so per-call submission would time the host.  The same
+K steps submitted one call at a time are reported as `eager`.
 `value` is lookups per second over the K timed steps, `ms_per_step` the time
 per batch.  The other path is timed the same way and reported beside it.
 
 Also measured in the same run, outside the K timed steps:
-  sweep           device time per lookup batch, B = 1..1024, uniform and
-                  Zipf(0.99) queries, plain and learned
+  sweep           B = 1..1024, uniform and Zipf(0.99) queries, plain and
+                  learned: steady-state time per batch (graph replays over
+                  2048 distinct batches) and single-launch latency (events)
   large_batch     2^20-key lookup batches (warm; `--cold` adds flushed runs)
   roofline        the large-batch lookup kernel: algorithmic bytes per launch
                   over its average duration (HIP events on its stream)
@@ -27,6 +33,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -71,6 +78,16 @@ def algorithmic_bytes(sorted_keys: np.ndarray, q: np.ndarray, height: int, hits:
     leaf = per_level[-1] * 16 * kb
     io = len(q) * (kb + kb + 1) + hits * kb
     return {"distinct_nodes_per_level": per_level, "bytes": int(inner + leaf + io)}
+
+
+def lookup_sources_hash() -> str:
+    """Hash of the sources the large-batch lookup kernel is built from (a
+    stored HBM traffic figure only applies to the kernel it was taken on)."""
+    h = hashlib.sha256()
+    for f in ("common.h", "traverse.h", "lookup.hip", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_2604_21117_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def cpu_baseline(keys, vals, batches, threads, budget_s=10.0):
@@ -175,11 +192,18 @@ def main():
           flush=True)
 
     B = 1024
-    nbatch = 64
-    qs = [synth.present_queries(keys, B, SEED, purpose=1000 + i) for i in range(nbatch)]
-    qd = [tree.dev(q) for q in qs]
+    # distinct query batches (2^21 queries): no batch repeats within the
+    # timed steps, so leaf lines are not kept warm by repetition
+    nbatch = 2048
+    allq = synth.present_queries(keys, nbatch * B, SEED, purpose=1000)
+    qdev = tree.dev(allq)
+    qd = [qdev[i * B:(i + 1) * B] for i in range(nbatch)]
     vo = torch.empty(B, dtype=torch.int64, device=dev)
     fo = torch.empty(B, dtype=torch.uint8, device=dev)
+
+    def expect(i):
+        j = i % nbatch
+        return synth.values_for(allq[j * B:(j + 1) * B], SEED, 64)
 
     def plain_step(i):
         g.tree_lookup_batch(tree.h, qd[i % nbatch], vo, fo, stream)
@@ -191,8 +215,7 @@ def main():
     for step in (plain_step, learned_step):
         step(0)
         stream.synchronize()
-        assert g.to_numpy(fo).all() and np.array_equal(g.to_numpy(vo, np.uint64),
-                                                       synth.values_for(qs[0], SEED, 64))
+        assert g.to_numpy(fo).all() and np.array_equal(g.to_numpy(vo, np.uint64), expect(0))
 
     def timed_steps(step, steps, warmup):
         for i in range(warmup):
@@ -206,33 +229,81 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
+    GR = 64  # steps per captured graph
+
+    def capture(step, first, count):
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr, stream=stream):
+            for i in range(first, first + count):
+                step(i)
+        return gr
+
+    def timed_graph_steps(step, steps, warmup):
+        graphs = [capture(step, c, min(GR, steps - c)) for c in range(0, steps, GR)]
+        for gr in graphs[:max(1, warmup // GR)]:
+            gr.replay()
+        stream.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for gr in graphs:
+            gr.replay()
+        stream.synchronize()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        # the replayed graphs answer like the eager calls: the last step's batch
+        assert g.to_numpy(fo).all() and np.array_equal(g.to_numpy(vo, np.uint64), expect(steps - 1))
+        return dt
+
     main_step = learned_step if args.path == "learned" else plain_step
     other_step = plain_step if args.path == "learned" else learned_step
-    elapsed = timed_steps(main_step, args.steps, args.warmup)
-    other_elapsed = timed_steps(other_step, args.steps, args.warmup)
+    elapsed = timed_graph_steps(main_step, args.steps, args.warmup)
+    other_elapsed = timed_graph_steps(other_step, args.steps, args.warmup)
+    eager = timed_steps(main_step, args.steps, args.warmup)
+    other_eager = timed_steps(other_step, args.steps, args.warmup)
     ms_per_step = elapsed * 1e3 / args.steps
     value = args.steps * B / elapsed / 1e6
     other_value = args.steps * B / other_elapsed / 1e6
     print(f"[bench] timed steps done: {args.path} {value:.1f} Mops/s", file=sys.stderr, flush=True)
 
-    # ---- per-batch device-time sweep
+    # ---- per-batch sweep: steady-state time per batch (graph replays over
+    # 2048 distinct batches) and single-launch latency (HIP events)
     zipf = synth.Zipf(n, 0.99, SEED)
     sweep = {}
+    nb = 2048
     for dist in ("uniform", "zipf"):
         for b in (1, 8, 64, 256, 1024):
-            q = synth.present_queries(keys, b, SEED, purpose=3000 + b) if dist == "uniform" else \
-                keys[zipf.indices(b)]
-            qdv = tree.dev(q)
+            qn = synth.present_queries(keys, nb * b, SEED, purpose=3000 + b) if dist == "uniform" else \
+                keys[zipf.indices(nb * b)]
+            qall = tree.dev(qn)
+            qb = [qall[i * b:(i + 1) * b] for i in range(nb)]
             v2 = torch.empty(b, dtype=torch.int64, device=dev)
             f2 = torch.empty(b, dtype=torch.uint8, device=dev)
             row = {}
             for path in ("plain", "learned"):
-                fn = (lambda: g.tree_lookup_batch(tree.h, qdv, v2, f2, stream)) if path == "plain" else \
-                    (lambda: g.li_lookup_batch(li.h, qdv, v2, f2, stream))
-                us = iqm(timer.run(fn, 104, skip=4))
-                row[path] = {"us_per_batch": round(us, 3), "mops": round(b / us, 2)}
+                if path == "plain":
+                    fn = lambda i: g.tree_lookup_batch(tree.h, qb[i], v2, f2, stream)
+                else:
+                    fn = lambda i: g.li_lookup_batch(li.h, qb[i], v2, f2, stream)
+                graphs = [capture(fn, c, GR) for c in range(0, nb, GR)]
+                graphs[0].replay()
+                stream.synchronize()
+                best = None
+                for _ in range(2):
+                    t0 = time.perf_counter()
+                    for gr in graphs:
+                        gr.replay()
+                    stream.synchronize()
+                    dt = (time.perf_counter() - t0) / nb * 1e6
+                    best = dt if best is None else min(best, dt)
+                assert g.to_numpy(f2).all() and np.array_equal(
+                    g.to_numpy(v2, np.uint64), synth.values_for(qn[(nb - 1) * b:], SEED, 64))
+                del graphs
+                lat = iqm(timer.run(lambda: fn(0), 104, skip=4))
+                row[path] = {"us_per_batch": round(best, 3), "mops": round(b / best, 2),
+                             "latency_us": round(lat, 3)}
             row["learned_speedup"] = round(row["plain"]["us_per_batch"] / row["learned"]["us_per_batch"], 3)
             sweep.setdefault(dist, {})[str(b)] = row
+            del qall, qb
     print("[bench] sweep done", file=sys.stderr, flush=True)
 
     # ---- large batch: warm launches of the 2^20-key lookup kernel
@@ -337,13 +408,13 @@ def main():
         print("[bench] serving done", file=sys.stderr, flush=True)
 
     # HBM bytes per launch from the committed counter summary, if it was
-    # taken on this same kernel
+    # taken on this same kernel (same sources, batch and tree)
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if os.path.exists(tpath):
         tj = json.load(open(tpath))
         if tj.get("kernel") == "k_lookup<unsigned long, 8, 4, 2, true, false>" and tj.get("batch") == BL \
-                and tj.get("keys") == n:
+                and tj.get("keys") == n and tj.get("sources_sha256") == lookup_sources_hash():
             traffic = tj["traffic_bytes"]
 
     line = {
@@ -365,8 +436,15 @@ def main():
                    "learned_models": lst["models"], "learned_linear": lst["linear_models"],
                    "learned_mlp": lst["mlp_models"], "learned_tree": lst["tree_models"],
                    "learned_mean_window": round(lst["mean_window"], 2), "learned_max_window": lst["max_window"]},
+        "submission": f"HIP graph replays of {GR} steps over {nbatch} distinct batches",
         "other_path": {"path": "plain" if args.path == "learned" else "learned", "value": round(other_value, 3),
                        "ms_per_step": round(other_elapsed * 1e3 / args.steps, 6)},
+        "eager": {"submission": "one library call per step",
+                  args.path: {"value": round(args.steps * B / eager / 1e6, 3),
+                              "ms_per_step": round(eager * 1e3 / args.steps, 6)},
+                  ("plain" if args.path == "learned" else "learned"): {
+                      "value": round(args.steps * B / other_eager / 1e6, 3),
+                      "ms_per_step": round(other_eager * 1e3 / args.steps, 6)}},
         "learned_vs_plain_b1024": round((value / other_value) if args.path == "learned" else (other_value / value), 3),
         "sweep": sweep,
         "large_batch": large,
@@ -384,8 +462,9 @@ def main():
         line["serving"] = serving
     if not args.no_cpu:
         threads = len(os.sched_getaffinity(0))
-        line["cpu_baseline"] = cpu_baseline(keys, vals, qs[:16], threads)
-        line["cpu_baseline_1thread"] = cpu_baseline(keys, vals, qs[:4], 1, budget_s=4.0)
+        cq = [allq[i * B:(i + 1) * B] for i in range(16)]
+        line["cpu_baseline"] = cpu_baseline(keys, vals, cq, threads)
+        line["cpu_baseline_1thread"] = cpu_baseline(keys, vals, cq[:4], 1, budget_s=4.0)
     print(json.dumps(line), flush=True)
 
 

@@ -64,13 +64,17 @@ typedef struct {
     uint32_t fanout;          /* inner order m; only 16 is supported          */
     uint32_t leaf_cap;        /* keys per leaf; only 16 is supported          */
     float fill;               /* bulk-load fill in [0.5, 1]; default 1.0      */
-    uint32_t lanes_per_query; /* lookup lanes per query: 4, 8 or 16 (def. 8)  */
+    uint32_t lanes_per_query; /* lookup lanes per query: 4, 8 or 16; 0 = by
+                                 batch size (16 below 2^13 queries, else 8);
+                                 ranges and insert location use 8            */
     uint32_t lds_levels;      /* top inner levels read from an LDS copy: 1..3,
-                                 4 = none; 0 = default (2)                    */
+                                 4 = none; 0 = by batch size (none below 2^15
+                                 queries, else 2; ranges and insert location
+                                 use 2)                                       */
     uint32_t sorted_mode;     /* reserved, must be 0                          */
     uint32_t queries_per_group; /* queries a lane group walks at once: 1, 2
-                                   or 4 for every batch; 0 = default (2, and
-                                   4 from 2^15 queries on)                    */
+                                   or 4 for every batch; 0 = by batch size
+                                   (1 below 2^15 queries, else 4)             */
     uint64_t max_batch;       /* largest insert batch; default 2^20           */
     uint32_t value_coload;    /* 1: a lookup reads the leaf's value line with
                                  its key line (one dependent load fewer);
@@ -189,35 +193,37 @@ const char* gt_status_str(gt_status s);
 /* ------------------------------------------------------------------------
  * Learned index over a tree (an addition to the paper's tree search).
  *
- * A two-stage FP32 model maps a key to its leaf's position in key order: a
- * linear root picks one of `models` leaf models, each either linear or a
- * one-hidden-layer MLP with 32 ReLU units, chosen per model by the smaller
- * error window.  The models are trained on the device from the tree's own
- * (key, leaf position) pairs, and every model gets exact error bounds
- * lo <= pos - pred <= hi over all keys routed to it, computed by the same
- * inference code the lookup runs.  A lookup predicts, searches the
- * directory of leaf fence keys inside [pred + lo, pred + hi], reads that
- * leaf and answers; a key that the leaf does not bracket (a window that
- * missed, a leaf split since training, a key routed to a model without
- * bounds) goes down the tree instead.  Results are always exactly those of
- * tree_lookup_batch; the models only change the speed.
+ * A two-stage model maps a key to its leaf's position in key order.  The
+ * root is linear (evaluated in FP64); its output picks one of `models`
+ * leaf models and its fractional part is that model's input.  Each leaf
+ * model is FP32: a line, or a one-hidden-layer ReLU network with 32 units
+ * whose knots sit on a uniform grid, which makes it linear on 32 pieces;
+ * it is stored as 32 (slope, intercept) pieces, chosen per model by the
+ * smaller error window.  The models are trained on the device from the
+ * tree's own (key, leaf position) pairs, and every piece gets exact error
+ * bounds lo <= pos - pred <= hi over all keys routed to it, computed by the
+ * same evaluation the lookup runs.  A lookup predicts, reads the leaves of
+ * [pred + lo, pred + hi] (directly on a bulk-loaded tree, else through the
+ * directory of leaf fence keys), and answers when a leaf holds the key or
+ * proves it absent; anything else (a window that missed, a leaf split
+ * since training, a piece without bounds) goes down the tree.  Results are
+ * always exactly those of tree_lookup_batch; the models only change the
+ * speed.
  * ---------------------------------------------------------------------- */
 typedef struct gt_learned gt_learned; /* opaque handle, host memory */
 
 typedef struct {
     uint32_t models;      /* leaf models, 1..4096; 0 = default 1024          */
     uint32_t kind;        /* 0 = per model, the kind with the smaller window;
-                             1 = linear only; 2 = MLP only                    */
-    uint32_t max_window;  /* a model whose window spans more leaves sends its
+                             1 = linear only; 2 = network only                */
+    uint32_t max_window;  /* a piece whose window spans more leaves sends its
                              keys down the tree; 0 = default 64               */
     uint32_t search;      /* window search: 1 = through the fence directory;
                              2 = read the window's leaves directly when the
-                             trained directory is the identity (a
-                             bulk-loaded tree); 0 = default (1)               */
-    uint32_t stage;       /* 1 = copy the model table into LDS per workgroup
-                             for batches up to 2^16; 2 = read it from L2;
-                             0 = default (2)                                  */
-    uint32_t reserved[2]; /* must be 0                                        */
+                             trained directory is the identity (a bulk-loaded
+                             tree); 0 = default: direct for batches up to
+                             2^13 keys on such a tree, else the directory     */
+    uint32_t reserved[3]; /* must be 0                                        */
 } gt_li_params;
 
 typedef struct {
@@ -226,9 +232,10 @@ typedef struct {
     uint64_t lookups;         /* queries answered since training             */
     uint64_t fallbacks;       /* of which went down the tree                 */
     uint32_t models, linear_models, mlp_models, tree_models;
-    uint32_t max_window;      /* widest window (leaves) of a model in use    */
+                              /* tree_models: every key goes down the tree   */
+    uint32_t max_window;      /* widest window (leaves) of a piece in use    */
     uint32_t reserved;
-    double mean_window;       /* mean window over models in use              */
+    double mean_window;       /* window per trained key, averaged over keys  */
 } gt_li_stats;
 
 /* Arena bytes a learned index over tree t needs (host). */
@@ -249,14 +256,15 @@ gt_status li_train(gt_learned* li, hipStream_t stream);
 gt_status li_lookup_batch(gt_learned* li, const void* keys, uint64_t B, void* values_out,
                           uint8_t* found_out, hipStream_t stream);
 
-/* Inference as the lookup runs it, for checking bounds: per key the model
- * index, the predicted leaf position and that model's bounds (lo, hi; both
- * 0 and kind 2 in model_kind_out when the model sends keys down the tree).
- * Outputs: B entries each (u32, i32, i32, i32, u8). */
+/* Inference as the lookup runs it, for checking bounds: per key the piece
+ * (model * 32 + piece, the unit that owns bounds), the predicted leaf
+ * position and that piece's bounds (lo, hi), and the kind in use (0 line,
+ * 1 network; 2, with pred, lo and hi 0, when the piece sends keys down the
+ * tree).  Outputs: B entries each (u32, i32, i32, i32, u8). */
 gt_status li_predict(gt_learned* li, const void* keys, uint64_t B, uint32_t* model_out, int32_t* pred_out,
                      int32_t* lo_out, int32_t* hi_out, uint8_t* model_kind_out, hipStream_t stream);
 
-/* Test hook: overwrite every model's bounds with [lo, hi] (a wrong window
+/* Test hook: overwrite every piece's bounds with [lo, hi] (a wrong window
  * must only cost fallbacks, never a wrong result). */
 gt_status li_set_bounds(gt_learned* li, int32_t lo, int32_t hi, hipStream_t stream);
 

@@ -49,7 +49,7 @@ class gt_tree_stats(C.Structure):
 
 class gt_li_params(C.Structure):
     _fields_ = [("models", C.c_uint32), ("kind", C.c_uint32), ("max_window", C.c_uint32), ("search", C.c_uint32),
-                ("stage", C.c_uint32), ("reserved", C.c_uint32 * 2)]
+                ("reserved", C.c_uint32 * 3)]
 
 
 class gt_li_stats(C.Structure):
@@ -241,8 +241,8 @@ def tree_export(h, stream=None) -> np.ndarray:
     return buf
 
 
-def li_params(models: int = 0, kind: int = 0, max_window: int = 0, search: int = 0, stage: int = 0) -> gt_li_params:
-    return gt_li_params(models=models, kind=kind, max_window=max_window, search=search, stage=stage)
+def li_params(models: int = 0, kind: int = 0, max_window: int = 0, search: int = 0) -> gt_li_params:
+    return gt_li_params(models=models, kind=kind, max_window=max_window, search=search)
 
 
 def li_arena_bytes(h, params: gt_li_params) -> int:
@@ -359,11 +359,10 @@ class Tree:
 class Learned:
     """A learned index over a :class:`Tree` (owns its arena tensor)."""
 
-    def __init__(self, tree: Tree, models: int = 0, kind: int = 0, max_window: int = 0, search: int = 0,
-                 stage: int = 0):
+    def __init__(self, tree: Tree, models: int = 0, kind: int = 0, max_window: int = 0, search: int = 0):
         torch = _torch()
         self.tree = tree
-        self.params = li_params(models, kind, max_window, search, stage)
+        self.params = li_params(models, kind, max_window, search)
         n = li_arena_bytes(tree.h, self.params)
         if n == 0:
             raise GtError(GT_ERR_INVALID, "li_arena_bytes")

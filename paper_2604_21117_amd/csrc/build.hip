@@ -63,7 +63,10 @@ __global__ void k_build_inner(TreeView<K> t, const K* __restrict__ cmax, uint64_
         const uint64_t c = e - b;
         uint32_t ref = kNone;
         if (s < c) ref = child_is_leaf ? (kLeafTag | static_cast<uint32_t>(b + s)) : child_base + static_cast<uint32_t>(b + s);
-        const K sep = (s + 1 < c) ? cmax[b + s] : kmax<K>();
+        K sep = (s + 1 < c) ? cmax[b + s] : kmax<K>();
+        // slot 15: the first child reference (children are consecutive)
+        if (s == kFirstSlot) sep = static_cast<K>(child_is_leaf ? (kLeafTag | static_cast<uint32_t>(b))
+                                                                : child_base + static_cast<uint32_t>(b));
         const uint64_t node = node_base + j;
         t.ikeys[node * kSlots + s] = sep;
         t.ichild[node * kSlots + s] = ref;

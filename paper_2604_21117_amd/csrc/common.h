@@ -13,6 +13,13 @@
 //                                  a key goes to the first child whose entry
 //                                  is >= the key, so the child index is the
 //                                  number of entries below the key)
+//                                  -- except slot 15, which is never a
+//                                  separator (at most 16 children): it holds
+//                                  the first child reference when the node's
+//                                  children have consecutive references (a
+//                                  bulk-loaded node), so a search needs no
+//                                  child line; a node an insert rewrites
+//                                  gets the largest key there
 //                ichild[cap][16]   child references, "none" from c on
 //   leaf pool    lkeys[cap][16]    keys ascending; slots from count on repeat
 //                                  the last key, so an equality ballot finds
@@ -30,6 +37,7 @@
 namespace gt {
 
 constexpr int kSlots = 16;                 // fanout = leaf capacity = entries per line
+constexpr int kFirstSlot = kSlots - 1;     // inner key slot holding the first child reference
 constexpr uint32_t kNone = 0xFFFFFFFFu;    // "no node"
 constexpr uint32_t kLeafTag = 0x80000000u; // bit 31 marks a leaf reference
 constexpr int kMirrorMaxNodes = 1 + 16 + 256;

@@ -14,10 +14,12 @@ struct LaunchCfg {
     int xcd_split;          // 0 off, 1 on from kXcdMinBatch queries, 2 always
     int leaf_stream;        // non-temporal leaf loads
     int large_qpg;          // queries per group from kLargeBatch queries on (0 = same)
+    int shape_auto;         // lookup shape chosen by batch size: bit 0 lanes, 1 queries per group, 2 LDS levels
 };
 
 constexpr uint64_t kXcdMinBatch = 1u << 15;
 constexpr uint64_t kLargeBatch = 1u << 15;
+constexpr uint64_t kMidBatch = 1u << 13;
 
 template <class K>
 void launch_lookup(const TreeView<K>& t, const LaunchCfg& cfg, const K* q, uint64_t B, K* vout, uint8_t* fout,

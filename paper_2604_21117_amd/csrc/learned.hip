@@ -1,36 +1,49 @@
 // Learned index over the tree: training and lookup kernels.
 //
-// Stage 1 (root): x = (key - kmin) * scale in FP64, rounded to FP32;
-// j = clamp(floor(a x + b), 0, M-1).  Stage 2 (model j): a linear model
-// p = slope x_j + icpt, or an MLP p = b2 + sum_u w2_u relu(w1_u x_j + b1_u)
-// with 32 hidden units, on the model's own normalised key x_j.  The
-// prediction is the leaf's position in key order (the leaf chain order at
-// training time).
+// Model.  Stage 1 (root): f = a (key - kmin) + c, evaluated in FP64;
+// j = clamp(floor(f), 0, M-1) picks the leaf model and x = f - j, rounded to
+// FP32, is that model's input: the key's place inside the model's share of
+// the key range.  Stage 2 (leaf model j), FP32: either a line p = s x + t or
+// a one-hidden-layer ReLU network with 32 units,
+//     p = w_b + w_0 x + sum_{u=1..31} w_u relu(x - u/32)
+// (unit 0's knot sits at the left end of the model's range, where relu(x)
+// and x agree).  With its knots on the uniform grid u/32 the network is
+// linear on every piece [m/32, (m+1)/32), so it is stored and evaluated as
+// 32 (slope, intercept) pairs selected by m = clamp(floor(32 x), 0, 31):
+// the same function, one fused multiply-add per query, and one 16-byte
+// record per piece that also carries the piece's exact error bounds.  A
+// linear model fills its 32 pieces with the same line.  The prediction is
+// a leaf position in key order (the leaf chain at training time).
 //
 // Training (all on the device, deterministic reduction orders):
 //   leaf positions   list ranking of the leaf chain by pointer jumping
 //   directory        dir[pos] = (first key of the leaf, leaf id)
 //   root             least squares of pos*M/L on the fences (FP64 sums)
 //   model ranges     the root is monotone, so model j owns a contiguous run
-//                    of fences
-//   leaf models      least squares per model on its fences; the MLP uses
-//                    hinge units relu(x - t_u) with knots t_u at the run's
-//                    quantiles and output weights from the normal equations
-//                    (FP64 Cholesky) -- a one-hidden-layer ReLU network whose
-//                    output layer is fitted in closed form
-//   bounds           every key of the tree is pushed through the same
-//                    inference functions the lookup uses; lo_j / hi_j are
-//                    the exact min / max of (true position - prediction)
-//                    over the keys routed to model j, per model kind; the
-//                    kind with the smaller window is kept
+//                    of fences; one fence on either side anchors its fit
+//   leaf models      least squares on those fences in FP64: the line, and
+//                    the network's output layer from the normal equations
+//                    (Cholesky)
+//   bounds           every key of the tree goes through the same piece
+//                    evaluation the lookup runs; per piece and model kind,
+//                    lo / hi are the exact min / max of (true position -
+//                    prediction) over the keys routed there
+//   choice           per model, the kind with the smaller key-weighted
+//                    window; a piece whose window exceeds the limit sends
+//                    its keys down the tree
 //
-// Lookup: predict, clamp the window [p + lo, p + hi] to the directory,
-// find the last fence <= key in it, read that leaf's key and value lines.
-// A match is a hit.  No match is an authoritative miss only when the leaf's
-// first and last keys bracket the key (the tree routes every key in that
-// interval to this leaf); otherwise -- the window missed, the leaf split
-// since training, the model has no bounds -- the query walks the tree in
-// the same kernel.  So results equal the tree's for any model state.
+// Lookup: route, read the piece, clamp the window [p + lo, p + hi].  On a
+// bulk-loaded tree (directory = identity: position i is leaf i) small
+// batches read the window's leaves at once (latency: one dependent access
+// after the piece); otherwise, and for large batches (bound by the rate of
+// line requests, where reading 3-4 leaves per query costs more than a fence
+// search), the last fence <= key in the window picks the leaf.  A match is a hit.  While the tree is unchanged since
+// training and the bounds are the trained ones, every present key lies in
+// its window, so a window without the key proves it absent.  After inserts
+// a miss is authoritative only when a window leaf brackets the key (first
+// <= key <= last) or the key lies below the first leaf; anything else (a
+// leaf split since training, a piece without bounds) walks the tree in the
+// same kernel.  Results equal the tree's for any model state.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -44,39 +57,50 @@
 
 namespace gt {
 
-constexpr int kHidden = 32;
-constexpr int kLiG = 8;             // lanes per query
+constexpr int kSeg = 32;                          // hidden units = pieces per leaf model
+constexpr int kLiG = 8;                           // lanes per query
 constexpr int kLiBlock = 256;
 constexpr uint32_t kKindLinear = 0, kKindMlp = 1, kKindTree = 2;
-constexpr int kFitPoints = 4096;    // points per model used for the MLP fit
+constexpr int kFitPoints = 4096;                  // points per model for the network fit
+constexpr int kDirect = 4;                        // leaves a group reads at once on the direct path
+constexpr uint64_t kDirectMaxBatch = 1ull << 13;   // default: direct window reads up to this batch
+constexpr uint64_t kSmallLookup = 1ull << 13;      // batches up to this size use 64-thread workgroups
 
 struct LiHeader {
     uint64_t kmin_root;
-    double root_scale;
-    float root_a, root_b;
+    double root_a, root_c;
     uint32_t L;          // leaves in the directory
     uint32_t M;
     uint64_t n_keys;
     unsigned long long lookups, fallbacks;
     uint32_t trained;
-    uint32_t pad[49];
+    uint32_t epoch;      // tree epoch at training
+    uint32_t pad[48];
 };
 static_assert(sizeof(LiHeader) == 256, "LiHeader size");
 
-struct ModelRec {
-    uint64_t kmin;
-    double scale;
-    uint32_t kind;
-    int32_t lo, hi;
-    float slope, icpt, b2;
-    uint32_t n_keys;     // keys routed here at training
-    uint32_t pad[5];
-    float w1[kHidden];
-    float b1[kHidden];
-    float w2[kHidden];
-    uint32_t pad2[16];
+// One piece of a leaf model as the lookup reads it.  Prediction:
+// base + floor(slope * x + icpt), clamped to the directory; lo > hi marks a
+// piece whose keys go down the tree.
+struct alignas(16) Piece {
+    float slope, icpt;
+    int16_t lo, hi;
+    uint32_t base;
 };
-static_assert(sizeof(ModelRec) == 512, "ModelRec size");
+static_assert(sizeof(Piece) == 16, "Piece size");
+
+// Training record of one leaf model: both candidate kinds.
+struct ModelFit {
+    float lin_s, lin_t;   // the line, relative to base
+    uint32_t base;        // position offset of the model's predictions
+    uint32_t kind;        // kind in use after the choice
+    uint32_t n_keys;      // keys routed here
+    uint32_t mlp_ok;      // network fitted
+    uint32_t pad[2];
+    float A[kSeg];        // network pieces: slopes
+    float C[kSeg];        // and intercepts, relative to base
+};
+static_assert(sizeof(ModelFit) == 288, "ModelFit size");
 
 template <class K>
 struct alignas(sizeof(K) == 8 ? 16 : 8) DirEntry {
@@ -85,93 +109,95 @@ struct alignas(sizeof(K) == 8 ? 16 : 8) DirEntry {
 };
 static_assert(sizeof(DirEntry<uint64_t>) == 16 && sizeof(DirEntry<uint32_t>) == 8, "DirEntry size");
 
-// Compact per-model record read by the lookup (staged into LDS).
-struct ModelLite {
-    uint64_t kmin;
-    double scale;
-    float slope, icpt;
-    int32_t lo_hi;       // lo in the low 16 bits, hi in the high 16 (signed)
-    uint32_t kind;
-};
-static_assert(sizeof(ModelLite) == 32, "ModelLite size");
-
-// Root parameters passed to the lookup by value (no dependent header load).
+// Root parameters, passed to the lookup by value (no dependent header load).
 struct LiArgs {
-    uint64_t kmin_root;
-    double root_scale;
-    float root_a, root_b;
+    uint64_t kmin;
+    double a, c;
     uint32_t L, M;
+    uint32_t epoch;      // tree epoch at training
     uint32_t identity;   // directory position == leaf id for every position
+    uint32_t exact;      // bounds are the trained ones (not overwritten)
     uint32_t pad;
 };
 
 template <class K>
 struct LiView {
     LiHeader* hdr;
-    ModelRec* models;
-    ModelLite* lite;
+    ModelFit* fit;         // M
+    Piece* piece;          // M * kSeg
     uint32_t* identity;
-    DirEntry<K>* dir;
+    DirEntry<K>* dir;      // L + 1 (the last entry: largest key, no leaf)
     uint32_t* nxt0; uint32_t* nxt1; uint32_t* rank0; uint32_t* rank1;
     uint32_t* pos_of_leaf;
     uint32_t* start;       // M + 1
-    int32_t* bnd;          // 4 * M: lo_lin, hi_lin, lo_mlp, hi_mlp
-    uint32_t* cnt;         // M
+    int32_t* bnd;          // 4 per piece: lo, hi of the line; lo, hi of the network
+    uint32_t* cnt;         // keys per piece
     double* partial;       // kMaxPartials * 5
-    float* mlp_ok;         // M (1 = MLP fitted)
 };
 
 constexpr int kMaxPartials = 4096;
 
 // ------------------------------------------------------------ inference
 
-// (key - kmin) * scale with the difference taken in FP64 on either side of
-// kmin (u64 differences can exceed the int64 range)
-__device__ __forceinline__ float norm_x(uint64_t key, uint64_t kmin, double scale) {
-    const double d = key >= kmin ? static_cast<double>(key - kmin) : -static_cast<double>(kmin - key);
-    return static_cast<float>(d * scale);
+// key - kmin in FP64 on either side of kmin (u64 differences can exceed the
+// int64 range)
+__device__ __forceinline__ double key_diff(uint64_t key, uint64_t kmin) {
+    return key >= kmin ? static_cast<double>(key - kmin) : -static_cast<double>(kmin - key);
 }
 
-template <class H>
-__device__ __forceinline__ uint32_t root_index(const H& h, uint64_t key) {
-    const float x = norm_x(key, h.kmin_root, h.root_scale);
-    float f = __fmaf_rn(h.root_a, x, h.root_b);
-    f = fminf(fmaxf(f, 0.0f), static_cast<float>(h.M - 1));
-    return static_cast<uint32_t>(floorf(f));
+struct Route {
+    uint32_t j, m;
+    float x;
+};
+
+__device__ __forceinline__ uint32_t piece_of(float x) {
+    const float s = floorf(x * static_cast<float>(kSeg));
+    return static_cast<uint32_t>(fminf(fmaxf(s, 0.0f), static_cast<float>(kSeg - 1)));
 }
 
-__device__ __forceinline__ int32_t clamp_pos(float f, uint32_t L) {
+__device__ __forceinline__ Route route(const LiArgs& a, uint64_t key) {
+    const double f = fma(a.a, key_diff(key, a.kmin), a.c);
+    const double fj = fmin(fmax(floor(f), 0.0), static_cast<double>(a.M - 1));
+    Route r;
+    r.j = static_cast<uint32_t>(fj);
+    r.x = static_cast<float>(f - fj);
+    r.m = piece_of(r.x);
+    return r;
+}
+
+// model j's input for any key (equal to route().x for the keys routed to j)
+__device__ __forceinline__ float x_in(const LiArgs& a, uint32_t j, uint64_t key) {
+    return static_cast<float>(fma(a.a, key_diff(key, a.kmin), a.c) - static_cast<double>(j));
+}
+
+__device__ __forceinline__ int32_t piece_pos(float slope, float icpt, uint32_t base, float x, uint32_t L) {
+    float f = __fmaf_rn(slope, x, icpt);
     f = fminf(fmaxf(f, -1.0e9f), 1.0e9f);
-    int32_t p = static_cast<int32_t>(floorf(f));
+    int64_t p = static_cast<int64_t>(base) + static_cast<int64_t>(floorf(f));
     if (p < 0) p = 0;
-    if (p > static_cast<int32_t>(L) - 1) p = static_cast<int32_t>(L) - 1;
-    return p;
+    if (p > static_cast<int64_t>(L) - 1) p = static_cast<int64_t>(L) - 1;
+    return static_cast<int32_t>(p);
 }
 
-__device__ __forceinline__ float linear_eval(const ModelRec& m, float x) { return __fmaf_rn(m.slope, x, m.icpt); }
-
-// MLP output evaluated by a group of 8 lanes (4 hidden units each), summed
-// with an xor tree so every lane of the group holds the same bits.
-__device__ __forceinline__ float mlp_eval_group(const ModelRec* m, float x, int gl) {
-    const float4 w1 = reinterpret_cast<const float4*>(m->w1)[gl];
-    const float4 b1 = reinterpret_cast<const float4*>(m->b1)[gl];
-    const float4 w2 = reinterpret_cast<const float4*>(m->w2)[gl];
-    float part = 0.0f;
-    part = __fmaf_rn(w2.x, fmaxf(0.0f, __fmaf_rn(w1.x, x, b1.x)), part);
-    part = __fmaf_rn(w2.y, fmaxf(0.0f, __fmaf_rn(w1.y, x, b1.y)), part);
-    part = __fmaf_rn(w2.z, fmaxf(0.0f, __fmaf_rn(w1.z, x, b1.z)), part);
-    part = __fmaf_rn(w2.w, fmaxf(0.0f, __fmaf_rn(w1.w, x, b1.w)), part);
-    part += __shfl_xor(part, 1, 64);
-    part += __shfl_xor(part, 2, 64);
-    part += __shfl_xor(part, 4, 64);
-    return part + m->b2;
+__device__ __forceinline__ Piece load_piece(const Piece* tab, uint32_t j, uint32_t m) {
+    const uint4 raw = *reinterpret_cast<const uint4*>(tab + (static_cast<uint64_t>(j) * kSeg + m));
+    Piece e;
+    __builtin_memcpy(&e, &raw, sizeof e);
+    return e;
 }
 
-// Predicted position of `key` under model m of the given kind.
-__device__ __forceinline__ int32_t predict(const ModelRec* m, uint32_t kind, uint64_t key, uint32_t L, int gl) {
-    const float x = norm_x(key, m->kmin, m->scale);
-    const float f = kind == kKindMlp ? mlp_eval_group(m, x, gl) : linear_eval(*m, x);
-    return clamp_pos(f, L);
+__device__ __forceinline__ LiArgs args_of(const LiHeader* h) {
+    LiArgs a;
+    a.kmin = h->kmin_root;
+    a.a = h->root_a;
+    a.c = h->root_c;
+    a.L = h->L;
+    a.M = h->M;
+    a.epoch = h->epoch;
+    a.identity = 0;
+    a.exact = 0;
+    a.pad = 0;
+    return a;
 }
 
 // ------------------------------------------------------------- training
@@ -231,7 +257,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return r;
 }
 
-// root sums: block b covers fences [b*n/nb, (b+1)*n/nb)
+// root sums: block b covers fences [b*n/nb, (b+1)*n/nb); x = (fence - kmin) * scale
 template <class K>
 __global__ __launch_bounds__(256) void k_root_partial(LiView<K> li, uint32_t L, uint32_t M, uint64_t kmin,
                                                       double scale) {
@@ -239,7 +265,7 @@ __global__ __launch_bounds__(256) void k_root_partial(LiView<K> li, uint32_t L, 
     const uint64_t b0 = part_start(blockIdx.x, L, gridDim.x), b1 = part_start(blockIdx.x + 1, L, gridDim.x);
     double s[5] = {0, 0, 0, 0, 0};
     for (uint64_t p = b0 + threadIdx.x; p < b1; p += blockDim.x) {
-        const double x = norm_x(static_cast<uint64_t>(li.dir[p].fence), kmin, scale);
+        const double x = key_diff(static_cast<uint64_t>(li.dir[p].fence), kmin) * scale;
         const double y = static_cast<double>(p) * M / L;
         s[0] += 1.0; s[1] += x; s[2] += y; s[3] += x * x; s[4] += x * y;
     }
@@ -249,33 +275,37 @@ __global__ __launch_bounds__(256) void k_root_partial(LiView<K> li, uint32_t L, 
     }
 }
 
+// f = a' x + c with x = (key - kmin) * scale, stored as a = a' * scale.
+// One workgroup of 256: strided partial sums, then the fixed-order tree.
 template <class K>
 __global__ __launch_bounds__(256) void k_root_final(LiView<K> li, uint32_t nb, uint64_t kmin, double scale,
-                                                    uint32_t L, uint32_t M) {
-    if (threadIdx.x != 0) return;
+                                                    uint32_t L, uint32_t M, uint32_t epoch) {
+    __shared__ double sh[256];
     double s[5] = {0, 0, 0, 0, 0};
-    for (uint32_t b = 0; b < nb; ++b)
+    for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x)
         for (int k = 0; k < 5; ++k) s[k] += li.partial[b * 5 + k];
+    for (int k = 0; k < 5; ++k) s[k] = block_sum(s[k], sh);
+    if (threadIdx.x != 0) return;
     const double n = s[0], den = n * s[3] - s[1] * s[1];
     double a = den > 0 ? (n * s[4] - s[1] * s[2]) / den : 0.0;
     if (!(a > 0)) a = 0.0;
-    const double b = n > 0 ? (s[2] - a * s[1]) / n : 0.0;
+    const double c = n > 0 ? (s[2] - a * s[1]) / n : 0.0;
     LiHeader* h = li.hdr;
     h->kmin_root = kmin;
-    h->root_scale = scale;
-    h->root_a = static_cast<float>(a);
-    h->root_b = static_cast<float>(b);
+    h->root_a = a * scale;
+    h->root_c = c;
     h->L = L;
     h->M = M;
+    h->epoch = epoch;
 }
 
 // model j owns fences [start[j], start[j+1])
 template <class K>
 __global__ void k_ranges(LiView<K> li, uint32_t L, uint32_t M) {
-    const LiHeader h = *li.hdr;
+    const LiArgs a = args_of(li.hdr);
     for (uint64_t p = gid(); p < L; p += gsz()) {
-        const uint32_t j = root_index(h, static_cast<uint64_t>(li.dir[p].fence));
-        const int64_t jp = p ? static_cast<int64_t>(root_index(h, static_cast<uint64_t>(li.dir[p - 1].fence))) : -1;
+        const uint32_t j = route(a, static_cast<uint64_t>(li.dir[p].fence)).j;
+        const int64_t jp = p ? static_cast<int64_t>(route(a, static_cast<uint64_t>(li.dir[p - 1].fence)).j) : -1;
         for (int64_t jj = jp + 1; jj <= static_cast<int64_t>(j); ++jj) li.start[jj] = static_cast<uint32_t>(p);
         if (p + 1 == L)
             for (uint32_t jj = j + 1; jj <= M; ++jj) li.start[jj] = L;
@@ -313,175 +343,225 @@ __device__ bool cholesky_solve(double* G, double* r, int n) {
     return true;
 }
 
-// One workgroup per model: linear and MLP fits on the model's fences.
+// feature u of the network at x: unit 0 is x, units 1..31 relu(x - u/32),
+// feature 32 the bias
+__device__ __forceinline__ double feature(int u, double x) {
+    if (u == 0) return x;
+    if (u < kSeg) return fmax(0.0, x - static_cast<double>(u) / kSeg);
+    return 1.0;
+}
+
+// One workgroup per model: the line and the network, fitted to the fences
+// of the model's run and its two neighbours, targets relative to `base`.
 template <class K>
-__global__ __launch_bounds__(256) void k_fit(LiView<K> li, uint32_t M) {
-    constexpr int NF = kHidden + 1;
+__global__ __launch_bounds__(256) void k_fit(LiView<K> li, uint32_t L, uint32_t M) {
+    constexpr int NF = kSeg + 1;
     __shared__ double sh[256];
     __shared__ float xs[kFitPoints];
     __shared__ float ys[kFitPoints];
-    __shared__ float knot[kHidden];
     __shared__ double G[NF * NF];
     __shared__ double rr[NF];
+    __shared__ int solved;
     const uint32_t j = blockIdx.x;
     if (j >= M) return;
-    ModelRec* m = li.models + j;
+    const LiArgs a = args_of(li.hdr);
+    ModelFit* mf = li.fit + j;
     const uint32_t b = li.start[j], e = li.start[j + 1];
-    const uint32_t n = e - b;
-    if (threadIdx.x == 0) {
-        m->kind = n ? kKindLinear : kKindTree;
-        m->lo = 0;
-        m->hi = 0;
-        m->n_keys = 0;
-    }
-    if (n == 0) {
-        if (threadIdx.x == 0) { m->kmin = 0; m->scale = 1.0; m->slope = 0; m->icpt = 0; m->b2 = 0; li.mlp_ok[j] = 0; }
-        return;
-    }
-    const uint64_t kmin = static_cast<uint64_t>(li.dir[b].fence);
-    const uint64_t klast = static_cast<uint64_t>(li.dir[e - 1].fence);
-    const double scale = klast > kmin ? 1.0 / static_cast<double>(klast - kmin) : 1.0;
-    // linear least squares on all fences of the run
+    const uint32_t p0 = b > 0 ? b - 1 : 0;
+    const uint32_t p1 = e < L ? e : L - 1;  // inclusive, >= p0
+    const uint32_t np = p1 - p0 + 1;
+    // line: least squares over every point
     double s[5] = {0, 0, 0, 0, 0};
-    for (uint32_t p = b + threadIdx.x; p < e; p += blockDim.x) {
-        const double x = norm_x(static_cast<uint64_t>(li.dir[p].fence), kmin, scale);
-        const double y = static_cast<double>(p);
+    for (uint32_t p = p0 + threadIdx.x; p <= p1; p += blockDim.x) {
+        const double x = x_in(a, j, static_cast<uint64_t>(li.dir[p].fence));
+        const double y = static_cast<double>(p - p0);
         s[0] += 1.0; s[1] += x; s[2] += y; s[3] += x * x; s[4] += x * y;
     }
     for (int k = 0; k < 5; ++k) s[k] = block_sum(s[k], sh);
     const double den = s[0] * s[3] - s[1] * s[1];
-    const double a = den > 1e-300 ? (s[0] * s[4] - s[1] * s[2]) / den : 0.0;
-    const double c = (s[2] - a * s[1]) / s[0];
-    // MLP: up to kFitPoints evenly spaced fences of the run
-    const uint32_t np = n < static_cast<uint32_t>(kFitPoints) ? n : static_cast<uint32_t>(kFitPoints);
-    for (uint32_t i = threadIdx.x; i < np; i += blockDim.x) {
-        const uint32_t p = b + static_cast<uint32_t>(part_start(i, n, np));
-        xs[i] = norm_x(static_cast<uint64_t>(li.dir[p].fence), kmin, scale);
-        ys[i] = static_cast<float>(p);
+    const double slope = den > 1e-12 * s[0] * s[3] ? (s[0] * s[4] - s[1] * s[2]) / den : 0.0;
+    const double icpt = (s[2] - slope * s[1]) / s[0];
+    // network: up to kFitPoints evenly spaced points
+    const uint32_t nq = np < static_cast<uint32_t>(kFitPoints) ? np : static_cast<uint32_t>(kFitPoints);
+    for (uint32_t i = threadIdx.x; i < nq; i += blockDim.x) {
+        const uint32_t p = p0 + static_cast<uint32_t>(part_start(i, np, nq));
+        xs[i] = x_in(a, j, static_cast<uint64_t>(li.dir[p].fence));
+        ys[i] = static_cast<float>(p - p0);
     }
+    if (threadIdx.x == 0) solved = 0;
     __syncthreads();
-    if (threadIdx.x < kHidden) knot[threadIdx.x] = xs[part_start(threadIdx.x, np, kHidden)];
-    __syncthreads();
-    bool ok = false;
-    if (np >= static_cast<uint32_t>(4 * NF)) {
-        // Gram matrix of the features relu(x - t_u) (u < 32) and 1
-        for (int q = threadIdx.x; q < NF * NF + NF; q += blockDim.x) {
+    if (nq >= 8) {
+        // normal equations, upper triangle and right-hand side
+        constexpr int NT = NF * (NF + 1) / 2;
+        for (int q = threadIdx.x; q < NT + NF; q += blockDim.x) {
             double acc = 0.0;
-            if (q < NF * NF) {
-                const int ua = q / NF, ub = q % NF;
-                for (uint32_t i = 0; i < np; ++i) {
-                    const double fa = ua < kHidden ? fmax(0.0, static_cast<double>(xs[i]) - knot[ua]) : 1.0;
-                    const double fb = ub < kHidden ? fmax(0.0, static_cast<double>(xs[i]) - knot[ub]) : 1.0;
-                    acc += fa * fb;
-                }
-                G[q] = acc;
+            if (q < NT) {
+                int ua = 0, rem = q;
+                while (rem >= NF - ua) { rem -= NF - ua; ++ua; }
+                const int ub = ua + rem;
+                for (uint32_t i = 0; i < nq; ++i) acc += feature(ua, xs[i]) * feature(ub, xs[i]);
+                G[ua * NF + ub] = acc;
+                G[ub * NF + ua] = acc;
             } else {
-                const int ua = q - NF * NF;
-                for (uint32_t i = 0; i < np; ++i) {
-                    const double fa = ua < kHidden ? fmax(0.0, static_cast<double>(xs[i]) - knot[ua]) : 1.0;
-                    acc += fa * ys[i];
-                }
+                const int ua = q - NT;
+                for (uint32_t i = 0; i < nq; ++i) acc += feature(ua, xs[i]) * static_cast<double>(ys[i]);
                 rr[ua] = acc;
             }
         }
         __syncthreads();
-        if (threadIdx.x == 0) ok = cholesky_solve(G, rr, NF);
+        if (threadIdx.x == 0) solved = cholesky_solve(G, rr, NF) ? 1 : 0;
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        m->kmin = kmin;
-        m->scale = scale;
-        m->slope = static_cast<float>(a);
-        m->icpt = static_cast<float>(c);
-        li.mlp_ok[j] = ok ? 1.0f : 0.0f;
-        if (ok) {
-            for (int u = 0; u < kHidden; ++u) {
-                m->w1[u] = 1.0f;
-                m->b1[u] = -knot[u];
-                m->w2[u] = static_cast<float>(rr[u]);
+    // pieces of the network: slope_m = sum_{u<=m} w_u,
+    // intercept_m = w_b - sum_{1<=u<=m} w_u u/32
+    if (threadIdx.x < static_cast<unsigned>(kSeg)) {
+        const int m = threadIdx.x;
+        double A = 0.0, C = solved ? rr[kSeg] : 0.0;
+        if (solved)
+            for (int u = 0; u <= m; ++u) {
+                A += rr[u];
+                if (u > 0) C -= rr[u] * static_cast<double>(u) / kSeg;
             }
-            m->b2 = static_cast<float>(rr[kHidden]);
-        } else {
-            for (int u = 0; u < kHidden; ++u) { m->w1[u] = 0; m->b1[u] = 0; m->w2[u] = 0; }
-            m->b2 = 0;
-        }
+        mf->A[m] = static_cast<float>(A);
+        mf->C[m] = static_cast<float>(C);
+    }
+    if (threadIdx.x == 0) {
+        mf->lin_s = static_cast<float>(slope);
+        mf->lin_t = static_cast<float>(icpt);
+        mf->base = p0;
+        mf->mlp_ok = solved;
+        mf->kind = kKindLinear;
+        mf->n_keys = 0;
     }
 }
 
-__global__ void k_bounds_init(int32_t* bnd, uint32_t* cnt, uint32_t M) {
-    for (uint64_t j = gid(); j < M; j += gsz()) {
+__global__ void k_bounds_init(int32_t* bnd, uint32_t* cnt, uint32_t cells) {
+    for (uint64_t j = gid(); j < cells; j += gsz()) {
         bnd[4 * j + 0] = INT32_MAX; bnd[4 * j + 1] = INT32_MIN;
         bnd[4 * j + 2] = INT32_MAX; bnd[4 * j + 3] = INT32_MIN;
         cnt[j] = 0;
     }
 }
 
-// Every key of the tree, one 8-lane group per key, through both model kinds.
+// Every key of the tree, one lane per key slot, through both kinds of its
+// model.  Neighbouring slots almost always share a piece: a wave whose keys
+// all do reduces in registers and issues one set of atomics.
 template <class K>
 __global__ __launch_bounds__(kLiBlock) void k_bounds(TreeView<K> t, LiView<K> li, uint32_t nleaves) {
-    const LiHeader h = *li.hdr;
-    const int gl = lane_id() % kLiG;
-    const uint64_t group = gid() / kLiG, ngroups = gsz() / kLiG;
+    const LiArgs a = args_of(li.hdr);
     const uint64_t total = static_cast<uint64_t>(nleaves) * kSlots;
-    for (uint64_t x = group; x < total; x += ngroups) {
-        const uint32_t leaf = static_cast<uint32_t>(x / kSlots), slot = static_cast<uint32_t>(x % kSlots);
-        if (slot >= t.lmeta[leaf].x) continue;  // group-uniform
-        const uint64_t key = static_cast<uint64_t>(t.lkeys[x]);
-        const int32_t pos = static_cast<int32_t>(li.pos_of_leaf[leaf]);
-        const uint32_t j = root_index(h, key);
-        const ModelRec* m = li.models + j;
-        const int32_t plin = predict(m, kKindLinear, key, h.L, gl);
-        const bool mlp = li.mlp_ok[j] != 0.0f;
-        const int32_t pmlp = mlp ? predict(m, kKindMlp, key, h.L, gl) : 0;
-        if (gl == 0) {
-            atomicMin(&li.bnd[4 * j + 0], pos - plin);
-            atomicMax(&li.bnd[4 * j + 1], pos - plin);
-            if (mlp) {
-                atomicMin(&li.bnd[4 * j + 2], pos - pmlp);
-                atomicMax(&li.bnd[4 * j + 3], pos - pmlp);
+    const int lane = lane_id();
+    const uint64_t w0 = gid() - static_cast<uint64_t>(lane);
+    for (uint64_t base = w0; base < total; base += gsz()) {
+        const uint64_t x = base + static_cast<uint64_t>(lane);
+        bool valid = false;
+        uint32_t cell = 0;
+        int32_t rl = 0, rm = 0;
+        bool mok = false;
+        if (x < total) {
+            const uint32_t leaf = static_cast<uint32_t>(x / kSlots), slot = static_cast<uint32_t>(x % kSlots);
+            if (slot < t.lmeta[leaf].x) {
+                valid = true;
+                const uint64_t key = static_cast<uint64_t>(t.lkeys[x]);
+                const int32_t pos = static_cast<int32_t>(li.pos_of_leaf[leaf]);
+                const Route r = route(a, key);
+                const ModelFit* f = li.fit + r.j;
+                cell = r.j * kSeg + r.m;
+                rl = pos - piece_pos(f->lin_s, f->lin_t, f->base, r.x, a.L);
+                mok = f->mlp_ok != 0;
+                if (mok) rm = pos - piece_pos(f->A[r.m], f->C[r.m], f->base, r.x, a.L);
             }
-            atomicAdd(&li.cnt[j], 1u);
+        }
+        const uint64_t vmask = __ballot(valid);
+        if (vmask == 0) continue;
+        const int first = __builtin_ctzll(vmask);
+        const uint32_t c0 = static_cast<uint32_t>(__shfl(static_cast<int>(cell), first, 64));
+        if (__ballot(valid && cell != c0) == 0) {
+            int32_t lmin = valid ? rl : INT32_MAX, lmax = valid ? rl : INT32_MIN;
+            int32_t mmin = valid && mok ? rm : INT32_MAX, mmax = valid && mok ? rm : INT32_MIN;
+            for (int d = 32; d > 0; d >>= 1) {
+                lmin = min(lmin, __shfl_xor(lmin, d, 64));
+                lmax = max(lmax, __shfl_xor(lmax, d, 64));
+                mmin = min(mmin, __shfl_xor(mmin, d, 64));
+                mmax = max(mmax, __shfl_xor(mmax, d, 64));
+            }
+            if (lane == first) {
+                atomicMin(&li.bnd[4 * c0 + 0], lmin);
+                atomicMax(&li.bnd[4 * c0 + 1], lmax);
+                if (mmin <= mmax) {
+                    atomicMin(&li.bnd[4 * c0 + 2], mmin);
+                    atomicMax(&li.bnd[4 * c0 + 3], mmax);
+                }
+                atomicAdd(&li.cnt[c0], static_cast<uint32_t>(__popcll(vmask)));
+            }
+        } else if (valid) {
+            atomicMin(&li.bnd[4 * cell + 0], rl);
+            atomicMax(&li.bnd[4 * cell + 1], rl);
+            if (mok) {
+                atomicMin(&li.bnd[4 * cell + 2], rm);
+                atomicMax(&li.bnd[4 * cell + 3], rm);
+            }
+            atomicAdd(&li.cnt[cell], 1u);
         }
     }
 }
 
+// One wave per model, lane m < 32 per piece: pick the kind with the smaller
+// key-weighted window (a key sent down the tree counts 2 * max_window) and
+// write the pieces the lookup reads.
 template <class K>
-__global__ void k_choose(LiView<K> li, uint32_t M, uint32_t kind_pref, uint32_t max_window) {
-    for (uint64_t j = gid(); j < M; j += gsz()) {
-        ModelRec* m = li.models + j;
-        const uint32_t c = li.cnt[j];
-        m->n_keys = c;
-        uint32_t kind = kKindTree;
-        int32_t lo = 0, hi = 0;
-        if (c > 0) {
-            const int64_t wl = static_cast<int64_t>(li.bnd[4 * j + 1]) - li.bnd[4 * j + 0];
-            const bool mlp = li.mlp_ok[j] != 0.0f;
-            const int64_t wm = mlp ? static_cast<int64_t>(li.bnd[4 * j + 3]) - li.bnd[4 * j + 2] : INT64_MAX;
-            bool use_mlp;
-            if (kind_pref == 1) use_mlp = false;
-            else if (kind_pref == 2) use_mlp = mlp;
-            else use_mlp = wm < wl;
-            kind = use_mlp ? kKindMlp : kKindLinear;
-            lo = use_mlp ? li.bnd[4 * j + 2] : li.bnd[4 * j + 0];
-            hi = use_mlp ? li.bnd[4 * j + 3] : li.bnd[4 * j + 1];
-            if (static_cast<int64_t>(hi) - lo + 1 > static_cast<int64_t>(max_window) || lo < -32768 ||
-                hi > 32767) {
-                kind = kKindTree;
-                lo = hi = 0;
-            }
-        }
-        m->kind = kind;
-        m->lo = lo;
-        m->hi = hi;
-        ModelLite ml;
-        ml.kmin = m->kmin;
-        ml.scale = m->scale;
-        ml.slope = m->slope;
-        ml.icpt = m->icpt;
-        ml.lo_hi = static_cast<int32_t>((static_cast<uint32_t>(static_cast<uint16_t>(static_cast<int16_t>(lo)))) |
-                                        (static_cast<uint32_t>(static_cast<uint16_t>(static_cast<int16_t>(hi))) << 16));
-        ml.kind = kind;
-        li.lite[j] = ml;
+__global__ __launch_bounds__(256) void k_choose(LiView<K> li, uint32_t M, uint32_t kind_pref, uint32_t max_window) {
+    const uint32_t j = static_cast<uint32_t>(gid() / 64);
+    const int lane = lane_id();
+    if (j >= M) return;
+    const ModelFit* f = li.fit + j;
+    const bool mok = f->mlp_ok != 0;
+    const uint64_t cell = static_cast<uint64_t>(j) * kSeg + lane;
+    uint32_t c = 0;
+    int32_t ll = 0, lh = 0, ml = 0, mh = 0;
+    if (lane < kSeg) {
+        c = li.cnt[cell];
+        ll = li.bnd[4 * cell + 0]; lh = li.bnd[4 * cell + 1];
+        ml = li.bnd[4 * cell + 2]; mh = li.bnd[4 * cell + 3];
+    }
+    auto fits = [&](int32_t lo, int32_t hi) {
+        return lo <= hi && static_cast<int64_t>(hi) - lo + 1 <= static_cast<int64_t>(max_window) && lo >= -32768 &&
+               hi <= 32767;
+    };
+    const double pen = 2.0 * max_window;
+    double cl = 0.0, cm = 0.0;
+    if (c) {
+        cl = c * (fits(ll, lh) ? static_cast<double>(lh - ll + 1) : pen);
+        cm = c * (mok && fits(ml, mh) ? static_cast<double>(mh - ml + 1) : pen);
+    }
+    uint32_t total = c;
+    for (int d = 32; d > 0; d >>= 1) {
+        cl += __shfl_xor(cl, d, 64);
+        cm += __shfl_xor(cm, d, 64);
+        total += __shfl_xor(total, d, 64);
+    }
+    bool use_mlp;
+    if (kind_pref == 1) use_mlp = false;
+    else if (kind_pref == 2) use_mlp = mok;
+    else use_mlp = mok && cm < cl;
+    const int32_t lo0 = use_mlp ? ml : ll, hi0 = use_mlp ? mh : lh;
+    const bool keyed_out = c > 0 && !fits(lo0, hi0);
+    const bool all_out = __ballot(c > 0 && !keyed_out) == 0 && total > 0;
+    if (lane < kSeg) {
+        Piece p;
+        p.slope = use_mlp ? f->A[lane] : f->lin_s;
+        p.icpt = use_mlp ? f->C[lane] : f->lin_t;
+        p.base = f->base;
+        int32_t lo = lo0, hi = hi0;
+        if (c == 0) lo = hi = 0;          // no key here: the prediction alone
+        else if (keyed_out) { lo = 1; hi = 0; }
+        p.lo = static_cast<int16_t>(lo);
+        p.hi = static_cast<int16_t>(hi);
+        li.piece[cell] = p;
+    }
+    if (lane == 0) {
+        li.fit[j].kind = all_out ? kKindTree : (use_mlp ? kKindMlp : kKindLinear);
+        li.fit[j].n_keys = total;
     }
 }
 
@@ -500,14 +580,11 @@ __global__ void k_li_finish(LiView<K> li, uint64_t n_keys) {
     }
 }
 
-__global__ void k_set_bounds(ModelRec* models, ModelLite* lite, uint32_t M, int32_t lo, int32_t hi) {
-    for (uint64_t j = gid(); j < M; j += gsz()) {
-        if (models[j].kind != kKindTree) {
-            models[j].lo = lo;
-            models[j].hi = hi;
-            lite[j].lo_hi = static_cast<int32_t>(
-                (static_cast<uint32_t>(static_cast<uint16_t>(static_cast<int16_t>(lo)))) |
-                (static_cast<uint32_t>(static_cast<uint16_t>(static_cast<int16_t>(hi))) << 16));
+__global__ void k_set_bounds(Piece* piece, uint64_t cells, int32_t lo, int32_t hi) {
+    for (uint64_t j = gid(); j < cells; j += gsz()) {
+        if (piece[j].lo <= piece[j].hi) {
+            piece[j].lo = static_cast<int16_t>(lo);
+            piece[j].hi = static_cast<int16_t>(hi);
         }
     }
 }
@@ -553,19 +630,18 @@ __device__ __forceinline__ int64_t window_search(const DirEntry<K>* dir, int32_t
     return cand;
 }
 
-constexpr int kDirect = 8;  // leaves a group reads at once on the direct path
-
-// Leaf verdict shared by both search paths: hit, authoritative miss (the
-// leaf's first and last keys bracket the key), or neither.
+// What one window leaf says about the key: a hit, or (after inserts) an
+// authoritative miss -- the leaf brackets the key, or it is the first leaf
+// and the key lies below it.
 template <class K>
 struct Verdict {
-    bool hit = false, bracket = false;
+    bool hit = false, sure = false;
     K val = kmax<K>();
 };
 
 template <class K>
 __device__ __forceinline__ void judge_leaf(const typename Trav<K, kLiG>::KV& kv, const typename Trav<K, kLiG>::KV& vv,
-                                           K key, int gbase, Verdict<K>& v) {
+                                           K key, bool first_leaf, int gbase, Verdict<K>& v) {
     using T = Trav<K, kLiG>;
     const uint32_t slot = T::match_slot(kv, key, gbase);
     const K first = static_cast<K>(__shfl(kv.v[0], gbase, 64));
@@ -575,72 +651,95 @@ __device__ __forceinline__ void judge_leaf(const typename Trav<K, kLiG>::KV& kv,
         v.hit = true;
         v.val = x;
     }
-    if (key >= first && key <= last) v.bracket = true;
+    if ((key >= first && key <= last) || (first_leaf && key < first)) v.sure = true;
 }
 
-template <class K, bool STAGE>
-__global__ __launch_bounds__(kLiBlock) void k_li_lookup(TreeView<K> t, LiView<K> li, LiArgs a,
-                                                        const K* __restrict__ q, uint64_t B, K* __restrict__ vout,
-                                                        uint8_t* __restrict__ fout) {
+template <class K, bool DIRECT, int BLK>
+__global__ __launch_bounds__(BLK) void k_li_lookup(TreeView<K> t, LiView<K> li, LiArgs a, const K* __restrict__ q,
+                                                   uint64_t B, K* __restrict__ vout, uint8_t* __restrict__ fout) {
     using T = Trav<K, kLiG>;
-    extern __shared__ __align__(16) uint8_t lds[];
-    const ModelLite* tab = li.lite;
-    if constexpr (STAGE) {
-        const uint4* src = reinterpret_cast<const uint4*>(li.lite);
-        uint4* dst = reinterpret_cast<uint4*>(lds);
-        for (uint32_t i = threadIdx.x; i < a.M * (sizeof(ModelLite) / 16); i += blockDim.x) dst[i] = src[i];
-        __syncthreads();
-        tab = reinterpret_cast<const ModelLite*>(lds);
-    }
+    // issued first, so the kernel's end does not wait for it
+    if (gid() == 0) atomicAdd(&li.hdr->lookups, static_cast<unsigned long long>(B));
     const int lane = lane_id();
     const int gl = lane % kLiG, gbase = lane - gl;
     const uint64_t group = gid() / kLiG, ngroups = gsz() / kLiG;
+    const int32_t last_pos = static_cast<int32_t>(a.L) - 1;
+    // unchanged tree and trained bounds: the window holds every present key.
+    // Read only when a miss needs it (-1: not read yet).
+    int fresh = a.exact ? -1 : 0;
     uint32_t nfb = 0;
     for (uint64_t i = group; i < B; i += ngroups) {
         const K key = q[i];
-        const uint32_t j = root_index(a, static_cast<uint64_t>(key));
-        const ModelLite m = tab[j];
-        bool fb = m.kind == kKindTree;
+        const Route r = route(a, static_cast<uint64_t>(key));
+        const Piece e = load_piece(li.piece, r.j, r.m);
         Verdict<K> v;
+        bool fb = e.lo > e.hi;
         if (!fb) {
-            const float x = norm_x(static_cast<uint64_t>(key), m.kmin, m.scale);
-            const float f = m.kind == kKindMlp ? mlp_eval_group(li.models + j, x, gl) : __fmaf_rn(m.slope, x, m.icpt);
-            const int32_t p = clamp_pos(f, a.L);
-            const int32_t lo = static_cast<int16_t>(m.lo_hi & 0xFFFF), hi = static_cast<int16_t>(m.lo_hi >> 16);
-            int32_t wl = p + lo, wh = p + hi;
-            if (wl < 0) wl = 0;
-            if (wh > static_cast<int32_t>(a.L) - 1) wh = static_cast<int32_t>(a.L) - 1;
-            if (a.identity) {
-                // positions are leaf ids: read the window's leaves at once
-                bool done = false;
-                for (int32_t base = wl; base <= wh && !done; base += kDirect) {
+            const int32_t p = piece_pos(e.slope, e.icpt, e.base, r.x, a.L);
+            const int32_t wl = max(p + e.lo, 0), wh = min(p + e.hi, last_pos);
+            if constexpr (DIRECT) {
+                // positions are leaf ids: read kDirect of the window's leaves at
+                // once; each lane checks its own slots (no cross-lane work
+                // unless the key is found or a miss needs proof)
+                for (int32_t b0 = wl; b0 <= wh && !(v.hit || v.sure); b0 += kDirect) {
                     typename T::KV kv[kDirect], vv[kDirect];
 #pragma unroll
                     for (int u = 0; u < kDirect; ++u) {
-                        if (base + u <= wh) {
-                            kv[u] = T::load_keys(t.lkeys + static_cast<uint64_t>(base + u) * kSlots, gl);
-                            vv[u] = T::load_keys(t.lvals + static_cast<uint64_t>(base + u) * kSlots, gl);
+                        if (b0 + u <= wh) {
+                            kv[u] = T::load_keys(t.lkeys + static_cast<uint64_t>(b0 + u) * kSlots, gl);
+                            vv[u] = T::load_keys(t.lvals + static_cast<uint64_t>(b0 + u) * kSlots, gl);
                         }
                     }
+                    // this lane's first slot holding the key (padding slots repeat
+                    // a leaf's last key, so the first one is the real slot)
+                    bool mine = false;
+                    K mval = K(0);
 #pragma unroll
-                    for (int u = 0; u < kDirect; ++u)
-                        if (base + u <= wh) judge_leaf<K>(kv[u], vv[u], key, gbase, v);
-                    done = v.hit || v.bracket;
+                    for (int u = 0; u < kDirect; ++u) {
+                        const bool in = b0 + u <= wh;
+#pragma unroll
+                        for (int x = 0; x < T::KPL; ++x) {
+                            const bool m = in && !mine && kv[u].v[x] == key;
+                            mval = m ? vv[u].v[x] : mval;
+                            mine = mine || m;
+                        }
+                    }
+                    const uint64_t hm = group_bits<kLiG>(__ballot(mine), gbase);
+                    if (hm) {
+                        v.hit = true;
+                        v.val = static_cast<K>(__shfl(mval, gbase + __builtin_ctzll(hm), 64));
+                    } else {
+                        if (fresh < 0) fresh = t.hdr->epoch == a.epoch ? 1 : 0;
+                        if (fresh == 0) {
+                            // after inserts: a leaf that brackets the key, or the first leaf
+#pragma unroll
+                            for (int u = 0; u < kDirect; ++u) {
+                                if (b0 + u <= wh) {
+                                    const K first = static_cast<K>(__shfl(kv[u].v[0], gbase, 64));
+                                    const K last =
+                                        static_cast<K>(__shfl(kv[u].v[T::KPL - 1], gbase + kLiG - 1, 64));
+                                    if ((key >= first && key <= last) || (b0 + u == 0 && key < first)) v.sure = true;
+                                }
+                            }
+                        }
+                    }
                 }
-                fb = !(v.hit || v.bracket);
             } else {
                 uint32_t leaf = kNone;
-                const int64_t cand = window_search<K>(li.dir, wl, wh, key, gl, gbase, &leaf);
-                if (cand < 0) {
-                    if (wl == 0) leaf = li.dir[0].leaf;  // below every fence: the first leaf
-                    else fb = true;
+                int64_t c = window_search<K>(li.dir, wl, wh, key, gl, gbase, &leaf);
+                if (c < 0 && wl == 0) {
+                    leaf = li.dir[0].leaf;  // below every fence: the first leaf
+                    c = 0;
                 }
-                if (!fb) {
+                if (c >= 0) {
                     const typename T::KV kv = T::load_keys(t.lkeys + static_cast<uint64_t>(leaf) * kSlots, gl);
                     const typename T::KV vv = T::load_keys(t.lvals + static_cast<uint64_t>(leaf) * kSlots, gl);
-                    judge_leaf<K>(kv, vv, key, gbase, v);
-                    fb = !(v.hit || v.bracket);
+                    judge_leaf<K>(kv, vv, key, c == 0, gbase, v);
                 }
+            }
+            if (!(v.hit || v.sure)) {
+                if (fresh < 0) fresh = t.hdr->epoch == a.epoch ? 1 : 0;
+                fb = fresh == 0;
             }
         }
         if (fb) {
@@ -651,7 +750,7 @@ __global__ __launch_bounds__(kLiBlock) void k_li_lookup(TreeView<K> t, LiView<K>
             const typename T::KV kv = T::load_keys(t.lkeys + static_cast<uint64_t>(lf[0]) * kSlots, gl);
             const typename T::KV vv = T::load_keys(t.lvals + static_cast<uint64_t>(lf[0]) * kSlots, gl);
             v = Verdict<K>();
-            judge_leaf<K>(kv, vv, key, gbase, v);
+            judge_leaf<K>(kv, vv, key, false, gbase, v);
             nfb += gl == 0 ? 1u : 0u;
         }
         if (gl == 0) {
@@ -659,33 +758,28 @@ __global__ __launch_bounds__(kLiBlock) void k_li_lookup(TreeView<K> t, LiView<K>
             fout[i] = v.hit ? 1 : 0;
         }
     }
-    // counters: one atomic per wave
+    // fallback counter: one atomic per wave that had any
     uint64_t wsum = nfb;
     for (int d = 32; d > 0; d >>= 1) wsum += __shfl_xor(wsum, d, 64);
     if (lane == 0 && wsum) atomicAdd(&li.hdr->fallbacks, static_cast<unsigned long long>(wsum));
-    if (gid() == 0) atomicAdd(&li.hdr->lookups, static_cast<unsigned long long>(B));
 }
 
+// Inference as the lookup runs it: piece id (model * 32 + piece), predicted
+// position, the piece's bounds and the kind in use (2: down the tree).
 template <class K>
-__global__ __launch_bounds__(kLiBlock) void k_li_predict(LiView<K> li, const K* __restrict__ q, uint64_t B,
-                                                         uint32_t* mo, int32_t* po, int32_t* lo, int32_t* hi,
-                                                         uint8_t* ko) {
-    const LiHeader h = *li.hdr;
-    const int gl = lane_id() % kLiG;
-    const uint64_t group = gid() / kLiG, ngroups = gsz() / kLiG;
-    for (uint64_t i = group; i < B; i += ngroups) {
-        const uint64_t key = static_cast<uint64_t>(q[i]);
-        const uint32_t j = root_index(h, key);
-        const ModelRec* m = li.models + j;
-        const uint32_t kind = m->kind;
-        const int32_t p = kind == kKindTree ? 0 : predict(m, kind, key, h.L, gl);
-        if (gl == 0) {
-            mo[i] = j;
-            po[i] = p;
-            lo[i] = m->lo;
-            hi[i] = m->hi;
-            ko[i] = static_cast<uint8_t>(kind);
-        }
+__global__ __launch_bounds__(kLiBlock) void k_li_predict(LiView<K> li, LiArgs a, const K* __restrict__ q,
+                                                         uint64_t B, uint32_t* mo, int32_t* po, int32_t* lo,
+                                                         int32_t* hi, uint8_t* ko) {
+    for (uint64_t i = gid(); i < B; i += gsz()) {
+        const Route r = route(a, static_cast<uint64_t>(q[i]));
+        const Piece e = load_piece(li.piece, r.j, r.m);
+        const bool tree = e.lo > e.hi;
+        mo[i] = r.j * kSeg + r.m;
+        po[i] = tree ? 0 : piece_pos(e.slope, e.icpt, e.base, r.x, a.L);
+        lo[i] = tree ? 0 : e.lo;
+        hi[i] = tree ? 0 : e.hi;
+        ko[i] = tree ? static_cast<uint8_t>(kKindTree)
+                     : static_cast<uint8_t>(li.fit[r.j].kind == kKindMlp ? kKindMlp : kKindLinear);
     }
 }
 
@@ -703,8 +797,8 @@ struct gt_learned {
     uint64_t arena_bytes;
     bool trained;
     uint64_t leaf_cap;
-    uint64_t off_models, off_dir, off_nxt0, off_nxt1, off_rank0, off_rank1, off_pos, off_start, off_bnd, off_cnt,
-        off_partial, off_mlp, off_lite, off_ident;
+    uint64_t off_fit, off_piece, off_dir, off_nxt0, off_nxt1, off_rank0, off_rank1, off_pos, off_start, off_bnd,
+        off_cnt, off_partial, off_ident;
     LiArgs args;
 };
 
@@ -714,10 +808,17 @@ uint64_t al256(uint64_t x) { return (x + 255) / 256 * 256; }
 
 uint32_t models_of(const gt_li_params* p) { return p && p->models ? p->models : 1024u; }
 
+bool params_bad(const gt_li_params* p) {
+    return p && (p->models > 4096 || p->kind > 2 || p->search > 2 || p->reserved[0] || p->reserved[1] ||
+                 p->reserved[2]);
+}
+
 uint64_t layout_li(gt_learned* li, uint64_t leaf_cap, uint32_t M, int kb) {
+    const uint64_t cells = static_cast<uint64_t>(M) * kSeg;
     uint64_t off = al256(sizeof(LiHeader));
     const uint64_t de = kb == 8 ? sizeof(DirEntry<uint64_t>) : sizeof(DirEntry<uint32_t>);
-    uint64_t o_models = off; off += al256(static_cast<uint64_t>(M) * sizeof(ModelRec));
+    uint64_t o_fit = off; off += al256(static_cast<uint64_t>(M) * sizeof(ModelFit));
+    uint64_t o_piece = off; off += al256(cells * sizeof(Piece));
     uint64_t o_dir = off; off += al256((leaf_cap + 1) * de);
     uint64_t o_n0 = off; off += al256(leaf_cap * 4);
     uint64_t o_n1 = off; off += al256(leaf_cap * 4);
@@ -725,17 +826,15 @@ uint64_t layout_li(gt_learned* li, uint64_t leaf_cap, uint32_t M, int kb) {
     uint64_t o_r1 = off; off += al256(leaf_cap * 4);
     uint64_t o_pos = off; off += al256(leaf_cap * 4);
     uint64_t o_start = off; off += al256((M + 1ull) * 4);
-    uint64_t o_bnd = off; off += al256(4ull * M * 4);
-    uint64_t o_cnt = off; off += al256(M * 4ull);
+    uint64_t o_bnd = off; off += al256(4ull * cells * 4);
+    uint64_t o_cnt = off; off += al256(cells * 4);
     uint64_t o_part = off; off += al256(kMaxPartials * 5ull * 8);
-    uint64_t o_mlp = off; off += al256(M * 4ull);
-    uint64_t o_lite = off; off += al256(static_cast<uint64_t>(M) * sizeof(ModelLite));
     uint64_t o_ident = off; off += 256;
     if (li) {
-        li->off_lite = o_lite; li->off_ident = o_ident;
-        li->off_models = o_models; li->off_dir = o_dir; li->off_nxt0 = o_n0; li->off_nxt1 = o_n1;
-        li->off_rank0 = o_r0; li->off_rank1 = o_r1; li->off_pos = o_pos; li->off_start = o_start;
-        li->off_bnd = o_bnd; li->off_cnt = o_cnt; li->off_partial = o_part; li->off_mlp = o_mlp;
+        li->off_fit = o_fit; li->off_piece = o_piece; li->off_dir = o_dir; li->off_nxt0 = o_n0;
+        li->off_nxt1 = o_n1; li->off_rank0 = o_r0; li->off_rank1 = o_r1; li->off_pos = o_pos;
+        li->off_start = o_start; li->off_bnd = o_bnd; li->off_cnt = o_cnt; li->off_partial = o_part;
+        li->off_ident = o_ident;
     }
     return off;
 }
@@ -745,7 +844,8 @@ LiView<K> li_view(const gt_learned* li) {
     LiView<K> v;
     uint8_t* a = li->arena;
     v.hdr = reinterpret_cast<LiHeader*>(a);
-    v.models = reinterpret_cast<ModelRec*>(a + li->off_models);
+    v.fit = reinterpret_cast<ModelFit*>(a + li->off_fit);
+    v.piece = reinterpret_cast<Piece*>(a + li->off_piece);
     v.dir = reinterpret_cast<DirEntry<K>*>(a + li->off_dir);
     v.nxt0 = reinterpret_cast<uint32_t*>(a + li->off_nxt0);
     v.nxt1 = reinterpret_cast<uint32_t*>(a + li->off_nxt1);
@@ -756,8 +856,6 @@ LiView<K> li_view(const gt_learned* li) {
     v.bnd = reinterpret_cast<int32_t*>(a + li->off_bnd);
     v.cnt = reinterpret_cast<uint32_t*>(a + li->off_cnt);
     v.partial = reinterpret_cast<double*>(a + li->off_partial);
-    v.mlp_ok = reinterpret_cast<float*>(a + li->off_mlp);
-    v.lite = reinterpret_cast<ModelLite*>(a + li->off_lite);
     v.identity = reinterpret_cast<uint32_t*>(a + li->off_ident);
     return v;
 }
@@ -800,11 +898,9 @@ gt_status train_t(gt_learned* li, hipStream_t s) {
     }
     hipLaunchKernelGGL(k_directory<K>, dim3(grid_of(n, 256)), dim3(256), 0, s, tv, v, ri, n);
     // root normalisation: smallest first key .. largest key of the tree
-    DirEntry<K> d0;
+    DirEntry<K> d0, dl;
     LI_HIP(hipMemcpyAsync(&d0, v.dir, sizeof d0, hipMemcpyDeviceToHost, s));
-    uint32_t last_leaf_pos = n - 1;
-    DirEntry<K> dl;
-    LI_HIP(hipMemcpyAsync(&dl, v.dir + last_leaf_pos, sizeof dl, hipMemcpyDeviceToHost, s));
+    LI_HIP(hipMemcpyAsync(&dl, v.dir + (n - 1), sizeof dl, hipMemcpyDeviceToHost, s));
     LI_HIP(hipStreamSynchronize(s));
     K kmaxkey;
     LI_HIP(hipMemcpyAsync(&kmaxkey, tv.lkeys + static_cast<uint64_t>(dl.leaf) * kSlots + kSlots - 1, sizeof(K),
@@ -812,17 +908,20 @@ gt_status train_t(gt_learned* li, hipStream_t s) {
     LI_HIP(hipStreamSynchronize(s));
     const uint64_t kmin = static_cast<uint64_t>(d0.fence), kmx = static_cast<uint64_t>(kmaxkey);
     const double scale = kmx > kmin ? 1.0 / static_cast<double>(kmx - kmin) : 1.0;
-    const uint32_t nb = n < static_cast<uint32_t>(kMaxPartials) ? (n < 1 ? 1 : n) : kMaxPartials;
+    const uint32_t nb = n < static_cast<uint32_t>(kMaxPartials) ? n : kMaxPartials;
+    const uint64_t cells = static_cast<uint64_t>(M) * kSeg;
     hipLaunchKernelGGL(k_root_partial<K>, dim3(nb), dim3(256), 0, s, v, n, M, kmin, scale);
-    hipLaunchKernelGGL(k_root_final<K>, dim3(1), dim3(64), 0, s, v, nb, kmin, scale, n, M);
+    hipLaunchKernelGGL(k_root_final<K>, dim3(1), dim3(256), 0, s, v, nb, kmin, scale, n, M, dh.epoch);
     hipLaunchKernelGGL(k_ranges<K>, dim3(grid_of(n, 256)), dim3(256), 0, s, v, n, M);
-    hipLaunchKernelGGL(k_fit<K>, dim3(M), dim3(256), 0, s, v, M);
-    hipLaunchKernelGGL(k_bounds_init, dim3(grid_of(M, 256)), dim3(256), 0, s, v.bnd, v.cnt, M);
-    hipLaunchKernelGGL(k_bounds<K>, dim3(grid_of(static_cast<uint64_t>(n) * kSlots * kLiG, kLiBlock, 8192)),
+    hipLaunchKernelGGL(k_fit<K>, dim3(M), dim3(256), 0, s, v, n, M);
+    hipLaunchKernelGGL(k_bounds_init, dim3(grid_of(cells, 256)), dim3(256), 0, s, v.bnd, v.cnt,
+                       static_cast<uint32_t>(cells));
+    hipLaunchKernelGGL(k_bounds<K>, dim3(grid_of(static_cast<uint64_t>(n) * kSlots, kLiBlock, 8192)),
                        dim3(kLiBlock), 0, s, tv, v, n);
     uint32_t mw = li->p.max_window ? li->p.max_window : 64u;
-    if (mw > 4096u) mw = 4096u;  // windows are packed in 16 bits
-    hipLaunchKernelGGL(k_choose<K>, dim3(grid_of(M, 256)), dim3(256), 0, s, v, M, li->p.kind, mw);
+    if (mw > 4096u) mw = 4096u;
+    hipLaunchKernelGGL(k_choose<K>, dim3(grid_of(static_cast<uint64_t>(M) * 64, 256)), dim3(256), 0, s, v, M,
+                       li->p.kind, mw);
     hipLaunchKernelGGL(k_li_finish<K>, dim3(1), dim3(64), 0, s, v, dh.n_keys);
     const uint32_t one = 1;
     LI_HIP(hipMemcpyAsync(v.identity, &one, 4, hipMemcpyHostToDevice, s));
@@ -833,16 +932,43 @@ gt_status train_t(gt_learned* li, hipStream_t s) {
     LI_HIP(hipMemcpyAsync(&h, v.hdr, sizeof h, hipMemcpyDeviceToHost, s));
     LI_HIP(hipMemcpyAsync(&ident, v.identity, 4, hipMemcpyDeviceToHost, s));
     LI_HIP(hipStreamSynchronize(s));
-    li->args.kmin_root = h.kmin_root;
-    li->args.root_scale = h.root_scale;
-    li->args.root_a = h.root_a;
-    li->args.root_b = h.root_b;
+    li->args.kmin = h.kmin_root;
+    li->args.a = h.root_a;
+    li->args.c = h.root_c;
     li->args.L = h.L;
     li->args.M = h.M;
-    li->args.identity = (li->p.search == 2) ? ident : 0u;
+    li->args.epoch = h.epoch;
+    li->args.identity = ident;
+    li->args.exact = 1;
     li->args.pad = 0;
     li->trained = true;
     return GT_OK;
+}
+
+template <class K, bool DIRECT, int BLK>
+void launch_li_lookup_t(gt_learned* li, const K* q, uint64_t B, K* vo, uint8_t* fo, hipStream_t stream) {
+    const uint32_t grid = grid_of(B * kLiG, BLK, 8192);
+    hipLaunchKernelGGL((k_li_lookup<K, DIRECT, BLK>), dim3(grid), dim3(BLK), 0, stream, view<K>(li->t),
+                       li_view<K>(li), li->args, q, B, vo, fo);
+}
+
+// Small batches are latency-bound: 64-thread workgroups spread them over
+// more CUs (fewer outstanding misses per CU).
+template <class K>
+void launch_li_lookup(gt_learned* li, const void* keys, uint64_t B, void* values_out, uint8_t* found_out,
+                      hipStream_t stream) {
+    const uint32_t mode = li->p.search;
+    const bool direct = li->args.identity && (mode == 2 || (mode == 0 && B <= kDirectMaxBatch));
+    const bool small = B <= kSmallLookup;
+    const K* q = reinterpret_cast<const K*>(keys);
+    K* vo = reinterpret_cast<K*>(values_out);
+    if (direct) {
+        if (small) launch_li_lookup_t<K, true, 64>(li, q, B, vo, found_out, stream);
+        else launch_li_lookup_t<K, true, kLiBlock>(li, q, B, vo, found_out, stream);
+    } else {
+        if (small) launch_li_lookup_t<K, false, 64>(li, q, B, vo, found_out, stream);
+        else launch_li_lookup_t<K, false, kLiBlock>(li, q, B, vo, found_out, stream);
+    }
 }
 
 }  // namespace
@@ -850,16 +976,12 @@ gt_status train_t(gt_learned* li, hipStream_t s) {
 extern "C" {
 
 uint64_t li_arena_bytes(const gt_tree* t, const gt_li_params* p) {
-    if (!t) return 0;
-    if (p && (p->models > 4096 || p->kind > 2 || p->search > 2 || p->stage > 2 || p->reserved[0] || p->reserved[1]))
-        return 0;
+    if (!t || params_bad(p)) return 0;
     return layout_li(nullptr, t->leaf_cap, models_of(p), t->kb);
 }
 
 gt_status li_create(gt_tree* t, const gt_li_params* p, void* arena, uint64_t arena_bytes, gt_learned** out) {
-    if (!t || !arena || !out) return GT_ERR_INVALID;
-    if (p && (p->models > 4096 || p->kind > 2 || p->search > 2 || p->stage > 2 || p->reserved[0] || p->reserved[1]))
-        return GT_ERR_INVALID;
+    if (!t || !arena || !out || params_bad(p)) return GT_ERR_INVALID;
     const uint32_t M = models_of(p);
     if (layout_li(nullptr, t->leaf_cap, M, t->kb) > arena_bytes) return GT_ERR_CAPACITY;
     gt_learned* li = new gt_learned();
@@ -889,34 +1011,8 @@ gt_status li_lookup_batch(gt_learned* li, const void* keys, uint64_t B, void* va
     if (B == 0) return GT_OK;
     if (!keys || !values_out || !found_out) return GT_ERR_INVALID;
     if (!li->trained) return tree_lookup_batch(li->t, keys, B, values_out, found_out, stream);
-    const uint32_t grid = grid_of(B * kLiG, kLiBlock, 2048);
-    // the model table goes to LDS when it is small; large batches keep it in
-    // L2, where the staging would cost more than it saves
-    const uint32_t lds = li->M * static_cast<uint32_t>(sizeof(ModelLite));
-    const bool stage = li->p.stage == 1 && lds <= 48u * 1024u && B <= (1u << 16);
-    if (li->t->kb == 8) {
-        if (stage)
-            hipLaunchKernelGGL((k_li_lookup<uint64_t, true>), dim3(grid), dim3(kLiBlock), lds, stream,
-                               view<uint64_t>(li->t), li_view<uint64_t>(li), li->args,
-                               reinterpret_cast<const uint64_t*>(keys), B, reinterpret_cast<uint64_t*>(values_out),
-                               found_out);
-        else
-            hipLaunchKernelGGL((k_li_lookup<uint64_t, false>), dim3(grid), dim3(kLiBlock), 0, stream,
-                               view<uint64_t>(li->t), li_view<uint64_t>(li), li->args,
-                               reinterpret_cast<const uint64_t*>(keys), B, reinterpret_cast<uint64_t*>(values_out),
-                               found_out);
-    } else {
-        if (stage)
-            hipLaunchKernelGGL((k_li_lookup<uint32_t, true>), dim3(grid), dim3(kLiBlock), lds, stream,
-                               view<uint32_t>(li->t), li_view<uint32_t>(li), li->args,
-                               reinterpret_cast<const uint32_t*>(keys), B, reinterpret_cast<uint32_t*>(values_out),
-                               found_out);
-        else
-            hipLaunchKernelGGL((k_li_lookup<uint32_t, false>), dim3(grid), dim3(kLiBlock), 0, stream,
-                               view<uint32_t>(li->t), li_view<uint32_t>(li), li->args,
-                               reinterpret_cast<const uint32_t*>(keys), B, reinterpret_cast<uint32_t*>(values_out),
-                               found_out);
-    }
+    if (li->t->kb == 8) launch_li_lookup<uint64_t>(li, keys, B, values_out, found_out, stream);
+    else launch_li_lookup<uint32_t>(li, keys, B, values_out, found_out, stream);
     return hipGetLastError() == hipSuccess ? GT_OK : GT_ERR_HIP;
 }
 
@@ -925,54 +1021,63 @@ gt_status li_predict(gt_learned* li, const void* keys, uint64_t B, uint32_t* mod
     if (!li || (B && (!keys || !model_out || !pred_out || !lo_out || !hi_out || !kind_out))) return GT_ERR_INVALID;
     if (!li->trained) return GT_ERR_INVALID;
     if (B == 0) return GT_OK;
-    const uint32_t grid = grid_of(B * kLiG, kLiBlock, 2048);
+    const uint32_t grid = grid_of(B, kLiBlock, 4096);
     if (li->t->kb == 8)
         hipLaunchKernelGGL(k_li_predict<uint64_t>, dim3(grid), dim3(kLiBlock), 0, stream, li_view<uint64_t>(li),
-                           reinterpret_cast<const uint64_t*>(keys), B, model_out, pred_out, lo_out, hi_out, kind_out);
+                           li->args, reinterpret_cast<const uint64_t*>(keys), B, model_out, pred_out, lo_out, hi_out,
+                           kind_out);
     else
         hipLaunchKernelGGL(k_li_predict<uint32_t>, dim3(grid), dim3(kLiBlock), 0, stream, li_view<uint32_t>(li),
-                           reinterpret_cast<const uint32_t*>(keys), B, model_out, pred_out, lo_out, hi_out, kind_out);
+                           li->args, reinterpret_cast<const uint32_t*>(keys), B, model_out, pred_out, lo_out, hi_out,
+                           kind_out);
     return hipGetLastError() == hipSuccess ? GT_OK : GT_ERR_HIP;
 }
 
 gt_status li_set_bounds(gt_learned* li, int32_t lo, int32_t hi, hipStream_t stream) {
     if (!li || lo > hi) return GT_ERR_INVALID;
     if (lo < -30000 || hi > 30000) return GT_ERR_INVALID;
-    hipLaunchKernelGGL(k_set_bounds, dim3(grid_of(li->M, 256)), dim3(256), 0, stream,
-                       reinterpret_cast<ModelRec*>(li->arena + li->off_models),
-                       reinterpret_cast<ModelLite*>(li->arena + li->off_lite), li->M, lo, hi);
+    const uint64_t cells = static_cast<uint64_t>(li->M) * kSeg;
+    li->args.exact = 0;  // windows no longer cover every key: misses need proof
+    hipLaunchKernelGGL(k_set_bounds, dim3(grid_of(cells, 256)), dim3(256), 0, stream,
+                       reinterpret_cast<Piece*>(li->arena + li->off_piece), cells, lo, hi);
     return hipGetLastError() == hipSuccess ? GT_OK : GT_ERR_HIP;
 }
 
 gt_status li_stats(gt_learned* li, gt_li_stats* out, hipStream_t stream) {
     if (!li || !out) return GT_ERR_INVALID;
+    const uint64_t cells = static_cast<uint64_t>(li->M) * kSeg;
     LiHeader h;
-    std::vector<ModelRec> ms(li->M);
+    std::vector<ModelFit> fs(li->M);
+    std::vector<Piece> ps(cells);
+    std::vector<uint32_t> cs(cells);
     LI_HIP(hipMemcpyAsync(&h, li->arena, sizeof h, hipMemcpyDeviceToHost, stream));
-    LI_HIP(hipMemcpyAsync(ms.data(), li->arena + li->off_models, ms.size() * sizeof(ModelRec), hipMemcpyDeviceToHost,
+    LI_HIP(hipMemcpyAsync(fs.data(), li->arena + li->off_fit, fs.size() * sizeof(ModelFit), hipMemcpyDeviceToHost,
                           stream));
+    LI_HIP(hipMemcpyAsync(ps.data(), li->arena + li->off_piece, ps.size() * sizeof(Piece), hipMemcpyDeviceToHost,
+                          stream));
+    LI_HIP(hipMemcpyAsync(cs.data(), li->arena + li->off_cnt, cs.size() * 4, hipMemcpyDeviceToHost, stream));
     LI_HIP(hipStreamSynchronize(stream));
     memset(out, 0, sizeof *out);
-    out->trained_leaves = li->trained ? h.L : 0;
-    out->trained_keys = li->trained ? h.n_keys : 0;
+    out->models = li->M;
+    if (!li->trained) return GT_OK;
+    out->trained_leaves = h.L;
+    out->trained_keys = h.n_keys;
     out->lookups = h.lookups;
     out->fallbacks = h.fallbacks;
-    out->models = li->M;
-    double wsum = 0;
-    uint32_t used = 0;
-    for (const ModelRec& m : ms) {
-        if (!li->trained) break;
-        if (m.kind == kKindLinear) out->linear_models++;
-        else if (m.kind == kKindMlp) out->mlp_models++;
+    for (const ModelFit& f : fs) {
+        if (f.kind == kKindLinear) out->linear_models++;
+        else if (f.kind == kKindMlp) out->mlp_models++;
         else out->tree_models++;
-        if (m.kind != kKindTree) {
-            const uint32_t w = static_cast<uint32_t>(m.hi - m.lo + 1);
-            wsum += w;
-            used++;
-            if (w > out->max_window) out->max_window = w;
-        }
     }
-    out->mean_window = used ? wsum / used : 0.0;
+    double wsum = 0, ksum = 0;
+    for (uint64_t c = 0; c < cells; ++c) {
+        if (!cs[c] || ps[c].lo > ps[c].hi) continue;
+        const uint32_t w = static_cast<uint32_t>(ps[c].hi - ps[c].lo + 1);
+        wsum += static_cast<double>(w) * cs[c];
+        ksum += cs[c];
+        if (w > out->max_window) out->max_window = w;
+    }
+    out->mean_window = ksum > 0 ? wsum / ksum : 0.0;
     return GT_OK;
 }
 

@@ -331,11 +331,30 @@ static void launch_lookup_lv(const TreeView<K>& t, const LaunchCfg& cfg, const K
     }
 }
 
+// Lookup shape by batch size, for the fields the caller did not fix
+// (measured on 2^24 u64 keys): small batches are latency-bound and want
+// 16 lanes per query, one query per group and no LDS staging (the top
+// levels are L2 hits, the staging a barrier on the critical path); large
+// batches are bound by the rate of L2 misses and want 8 lanes, four queries
+// in flight per group and the top two levels in LDS.
+static LaunchCfg shape_for(const LaunchCfg& cfg, uint64_t B) {
+    LaunchCfg c = cfg;
+    int lanes, qpg, lds;
+    if (B < kMidBatch) { lanes = 16; qpg = 1; lds = 0; }
+    else if (B < kLargeBatch) { lanes = 8; qpg = 1; lds = 0; }
+    else { lanes = 8; qpg = cfg.large_qpg ? cfg.large_qpg : 4; lds = 2; }
+    if (cfg.shape_auto & 1) c.lanes = lanes;
+    if (cfg.shape_auto & 2) c.queries_per_group = qpg;
+    else if (B >= kLargeBatch && cfg.large_qpg) c.queries_per_group = cfg.large_qpg;
+    if (cfg.shape_auto & 4) c.lds_levels = lds;
+    return c;
+}
+
 template <class K>
-void launch_lookup(const TreeView<K>& t, const LaunchCfg& cfg, const K* q, uint64_t B, K* vout, uint8_t* fout,
+void launch_lookup(const TreeView<K>& t, const LaunchCfg& cfg0, const K* q, uint64_t B, K* vout, uint8_t* fout,
                    hipStream_t s) {
-    // large batches are throughput-bound: more queries in flight per group
-    const int qpg = (B >= kLargeBatch && cfg.large_qpg) ? cfg.large_qpg : cfg.queries_per_group;
+    const LaunchCfg cfg = shape_for(cfg0, B);
+    const int qpg = cfg.queries_per_group;
     switch (cfg.lanes) {
         case 4:
             if (qpg >= 4) launch_lookup_lv<K, 4, 4>(t, cfg, q, B, vout, fout, s);

@@ -65,14 +65,22 @@ struct Trav {
     struct CV { uint32_t v[KPL]; };
 
     // child index = number of separators below `key` in the group's line
+    // (slots 0..14; slot 15 is never a separator, see kFirstSlot)
     static __device__ __forceinline__ uint32_t child_index(const KV& kv, K key, int gbase) {
         uint32_t idx = 0;
 #pragma unroll
         for (int e = 0; e < KPL; ++e) {
             uint64_t m = __ballot(kv.v[e] < key);
+            if (e == KPL - 1) m &= ~(1ull << (gbase + G - 1));
             idx += static_cast<uint32_t>(__popcll(group_bits<G>(m, gbase)));
         }
         return idx;
+    }
+
+    // slot 15 of the group's line: the first child reference when the node's
+    // children have consecutive references, else the largest key
+    static __device__ __forceinline__ K first_slot(const KV& kv, int gbase) {
+        return static_cast<K>(__shfl(kv.v[KPL - 1], gbase + G - 1, 64));
     }
 
     // child reference for slot idx, read from the lane that holds it
@@ -203,18 +211,24 @@ __device__ __forceinline__ void descend(const TreeView<K>& t, const uint8_t* mir
             }
         }
     }
+    // HBM levels: a node whose children are consecutive gives its child
+    // reference from the key line alone; only other nodes (rewritten by an
+    // insert) cost a dependent read of the child line
     for (; level < inner_levels; ++level) {
         typename T::KV kv[QPG];
-        typename T::CV cv[QPG];
+#pragma unroll
+        for (int j = 0; j < QPG; ++j) kv[j] = T::load_keys(t.ikeys + static_cast<uint64_t>(node[j]) * kSlots, gl);
 #pragma unroll
         for (int j = 0; j < QPG; ++j) {
-            kv[j] = T::load_keys(t.ikeys + static_cast<uint64_t>(node[j]) * kSlots, gl);
-            cv[j] = T::load_child(t.ichild + static_cast<uint64_t>(node[j]) * kSlots, gl);
-        }
-#pragma unroll
-        for (int j = 0; j < QPG; ++j) {
-            uint32_t idx = T::child_index(kv[j], key[j], gbase);
-            uint32_t c = T::pick_child(cv[j], idx, gbase);
+            const uint32_t idx = T::child_index(kv[j], key[j], gbase);
+            const K f = T::first_slot(kv[j], gbase);
+            uint32_t c;
+            if (f != kmax<K>()) {
+                c = static_cast<uint32_t>(f) + idx;
+            } else {
+                const typename T::CV cv = T::load_child(t.ichild + static_cast<uint64_t>(node[j]) * kSlots, gl);
+                c = T::pick_child(cv, idx, gbase);
+            }
             if constexpr (REC) {
                 if (gl == 0 && qidx[j] != ~0ull) {
                     path_node[level * path_stride + qidx[j]] = node[j];

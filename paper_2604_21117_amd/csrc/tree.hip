@@ -234,6 +234,8 @@ gt_status tree_build(const gt_params* p, const void* keys, const void* values, u
     t->cfg.leaf_stream = p->leaf_stream == 1 ? 1 : 0;
     // an explicit queries_per_group applies to every batch size
     t->cfg.large_qpg = p->queries_per_group ? 0 : 4;
+    // lookup shape fields the caller left at 0 follow the batch size
+    t->cfg.shape_auto = (p->lanes_per_query ? 0 : 1) | (p->queries_per_group ? 0 : 2) | (p->lds_levels ? 0 : 4);
     layout(t, reinterpret_cast<uint8_t*>(arena), lo);
     gt_status st = kb == 8 ? build_t<uint64_t>(t, keys, values, n, stream)
                            : build_t<uint32_t>(t, keys, values, n, stream);
@@ -373,6 +375,7 @@ gt_status tree_export(gt_tree* t, void* host_buf, uint64_t* bytes, hipStream_t s
     o += 48;
     for (uint64_t i = 0; i < ni; ++i) {
         memcpy(o, ik.data() + i * kSlots * kb, kSlots * kb);
+        memset(o + kFirstSlot * kb, 0xFF, kb);  // the first-child slot is padding in the exported format
         memcpy(o + kSlots * kb, ic.data() + i * kSlots * 4, kSlots * 4);
         o += inner_rec_bytes(kb);
     }
