@@ -18,6 +18,8 @@ Also measured in the same run, outside the K timed steps:
   sweep           B = 1..1024, uniform and Zipf(0.99) queries, plain and
                   learned: steady-state time per batch (graph replays over
                   2048 distinct batches) and single-launch latency (events)
+  size_sweep      B = 1024 on trees of 2^4 .. 2^24 keys (prefixes of the same
+                  key sequence), plain and learned
   large_batch     2^20-key lookup batches (warm; `--cold` adds flushed runs)
   roofline        the large-batch lookup kernel: algorithmic bytes per launch
                   over its average duration (HIP events on its stream)
@@ -63,10 +65,11 @@ def iqm(x):
 
 def algorithmic_bytes(sorted_keys: np.ndarray, q: np.ndarray, height: int, hits: int, kb: int = 8) -> dict:
     """Bytes a lookup batch must move: each distinct node it visits once
-    (inner node = key line + child line, leaf = key line), the value of each
-    hit, and the batch's keys in and results out.  Exact for the bulk-loaded
-    tree at fill 1.0 with 16 keys per leaf: the key of rank r sits in leaf
-    r // 16, whose ancestor d levels up is r // 16^(d+1)."""
+    (one key line per node: a bulk-loaded inner node carries its first child
+    reference in that line), the value of each hit, and the batch's keys in
+    and results out.  Exact for the bulk-loaded tree at fill 1.0 with 16 keys
+    per leaf: the key of rank r sits in leaf r // 16, whose ancestor d levels
+    up is r // 16^(d+1)."""
     ranks = np.minimum(np.searchsorted(sorted_keys, q), len(sorted_keys) - 1).astype(np.int64)
     node = ranks // 16
     per_level = [len(np.unique(node))]
@@ -74,7 +77,7 @@ def algorithmic_bytes(sorted_keys: np.ndarray, q: np.ndarray, height: int, hits:
         node = node // 16
         per_level.append(len(np.unique(node)))
     per_level = per_level[::-1]
-    inner = sum(per_level[:-1]) * (16 * kb + 64)
+    inner = sum(per_level[:-1]) * 16 * kb
     leaf = per_level[-1] * 16 * kb
     io = len(q) * (kb + kb + 1) + hits * kb
     return {"distinct_nodes_per_level": per_level, "bytes": int(inner + leaf + io)}
@@ -306,6 +309,46 @@ def main():
             del qall, qb
     print("[bench] sweep done", file=sys.stderr, flush=True)
 
+    # ---- tree-size sweep: B = 1024 uniform present keys, trees of the first
+    # 2^k keys of the same generator sequence, k = 4..log2n
+    size_sweep = {}
+    vz = torch.empty(B, dtype=torch.int64, device=dev)
+    fz = torch.empty(B, dtype=torch.uint8, device=dev)
+    for lg in range(4, args.log2n + 1):
+        m = 1 << lg
+        tz = g.Tree(keys[:m], vals[:m], 8, max_batch=1024)
+        lz = g.Learned(tz, models=1024)
+        lz.train()
+        qz_np = synth.present_queries(keys[:m], 256 * B, SEED, purpose=6000 + lg)
+        qz = tz.dev(qz_np)
+        qzb = [qz[i * B:(i + 1) * B] for i in range(256)]
+        row = {"height": tz.stats()["height"]}
+        for path in ("plain", "learned"):
+            if path == "plain":
+                fn = lambda i: g.tree_lookup_batch(tz.h, qzb[i], vz, fz, stream)
+            else:
+                fn = lambda i: g.li_lookup_batch(lz.h, qzb[i], vz, fz, stream)
+            graphs = [capture(fn, c, GR) for c in range(0, 256, GR)]
+            graphs[0].replay()
+            stream.synchronize()
+            best = None
+            for _ in range(3):
+                t0 = time.perf_counter()
+                for gr in graphs:
+                    gr.replay()
+                stream.synchronize()
+                dt = (time.perf_counter() - t0) / 256 * 1e6
+                best = dt if best is None else min(best, dt)
+            assert g.to_numpy(fz).all() and np.array_equal(g.to_numpy(vz, np.uint64),
+                                                           synth.values_for(qz_np[255 * B:], SEED, 64))
+            del graphs
+            row[f"{path}_us_per_batch"] = round(best, 3)
+        size_sweep[str(lg)] = row
+        lz.close()
+        tz.close()
+        del qz, qzb
+    print("[bench] size sweep done", file=sys.stderr, flush=True)
+
     # ---- large batch: warm launches of the 2^20-key lookup kernel
     warm = timer.run(lambda: g.tree_lookup_batch(tree.h, qld, vl, fl, stream), 22)
     got = g.to_numpy(fl)
@@ -447,6 +490,7 @@ def main():
                       "ms_per_step": round(other_eager * 1e3 / args.steps, 6)}},
         "learned_vs_plain_b1024": round((value / other_value) if args.path == "learned" else (other_value / value), 3),
         "sweep": sweep,
+        "size_sweep_b1024": size_sweep,
         "large_batch": large,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

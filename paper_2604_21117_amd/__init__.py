@@ -306,11 +306,16 @@ class Tree:
         self.h = tree_build(self.params, k, v, self.arena)
 
     def close(self):
-        if getattr(self, "h", None):
-            tree_destroy(self.h)
+        h = getattr(self, "h", None)
+        if h:
             self.h = None
+            tree_destroy(h)
 
-    __del__ = close
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: module globals may be gone
+            pass
 
     def dev(self, a: np.ndarray):
         return to_device(np.asarray(a, dtype=self.udtype), self.device)
@@ -370,11 +375,16 @@ class Learned:
         self.h = li_create(tree.h, self.params, self.arena)
 
     def close(self):
-        if getattr(self, "h", None):
-            li_destroy(self.h)
+        h = getattr(self, "h", None)
+        if h:
             self.h = None
+            li_destroy(h)
 
-    __del__ = close
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: module globals may be gone
+            pass
 
     def train(self):
         li_train(self.h)
@@ -458,11 +468,16 @@ class Server:
         self.h = h.value
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().srv_destroy(self.h)
+        h = getattr(self, "h", None)
+        if h:
             self.h = None
+            lib().srv_destroy(h)
 
-    __del__ = close
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: module globals may be gone
+            pass
 
     def submit(self, b: Batch) -> int:
         t = C.c_uint64()

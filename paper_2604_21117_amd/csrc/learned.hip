@@ -667,7 +667,6 @@ __global__ __launch_bounds__(BLK) void k_li_lookup(TreeView<K> t, LiView<K> li, 
     // unchanged tree and trained bounds: the window holds every present key.
     // Read only when a miss needs it (-1: not read yet).
     int fresh = a.exact ? -1 : 0;
-    uint32_t nfb = 0;
     for (uint64_t i = group; i < B; i += ngroups) {
         const K key = q[i];
         const Route r = route(a, static_cast<uint64_t>(key));
@@ -751,17 +750,14 @@ __global__ __launch_bounds__(BLK) void k_li_lookup(TreeView<K> t, LiView<K> li, 
             const typename T::KV vv = T::load_keys(t.lvals + static_cast<uint64_t>(lf[0]) * kSlots, gl);
             v = Verdict<K>();
             judge_leaf<K>(kv, vv, key, false, gbase, v);
-            nfb += gl == 0 ? 1u : 0u;
+            // counted where it happens (rare): no reduction on the common path
+            if (gl == 0) atomicAdd(&li.hdr->fallbacks, 1ull);
         }
         if (gl == 0) {
             vout[i] = v.hit ? v.val : kmax<K>();
             fout[i] = v.hit ? 1 : 0;
         }
     }
-    // fallback counter: one atomic per wave that had any
-    uint64_t wsum = nfb;
-    for (int d = 32; d > 0; d >>= 1) wsum += __shfl_xor(wsum, d, 64);
-    if (lane == 0 && wsum) atomicAdd(&li.hdr->fallbacks, static_cast<unsigned long long>(wsum));
 }
 
 // Inference as the lookup runs it: piece id (model * 32 + piece), predicted
