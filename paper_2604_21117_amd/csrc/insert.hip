@@ -696,23 +696,65 @@ __global__ __launch_bounds__(1024) void k_grow_commit(TreeView<K> t, Ins<K> v) {
 constexpr uint32_t kSmallInsert = 2048;
 constexpr int kSmallBlock = 1024;
 
+// Stable sort of B <= kSmallInsert (key, batch index) pairs by rank: the
+// rank of (k_i, i) is the number of pairs (k_j, j) before it in (key, index)
+// order.  Every workgroup holds all keys in LDS and 16 lanes share one
+// element's count, so the B^2 comparisons spread over B / 16 CUs instead of
+// the one CU a workgroup-local sort would use.
+constexpr uint32_t kRankLanes = 16;  // lanes sharing one element's count
+
+template <class K>
+__global__ __launch_bounds__(256) void k_small_rank(Ins<K> v, const K* __restrict__ keys, uint32_t B) {
+    __shared__ K sk[kSmallInsert];
+    for (uint32_t i = threadIdx.x; i < B; i += blockDim.x) sk[i] = keys[i];
+    __syncthreads();
+    const uint32_t e = (blockIdx.x * blockDim.x + threadIdx.x) / kRankLanes, l = threadIdx.x % kRankLanes;
+    if (e >= B) return;  // whole groups of lanes leave together
+    const K ke = sk[e];
+    uint32_t c = 0;
+    // lane l takes keys l, l + 16, ...: neighbouring lanes read neighbouring
+    // LDS words (no bank conflicts); eight reads in flight per batch
+    constexpr uint32_t R = 8;
+    uint32_t j = l;
+    for (; j + kRankLanes * (R - 1) < B; j += kRankLanes * R) {
+        K kj[R];
+#pragma unroll
+        for (uint32_t u = 0; u < R; ++u) kj[u] = sk[j + kRankLanes * u];
+#pragma unroll
+        for (uint32_t u = 0; u < R; ++u) {
+            const uint32_t jj = j + kRankLanes * u;
+            c += (kj[u] < ke || (kj[u] == ke && jj < e)) ? 1u : 0u;
+        }
+    }
+    for (; j < B; j += kRankLanes) {
+        const K kj = sk[j];
+        c += (kj < ke || (kj == ke && j < e)) ? 1u : 0u;
+    }
+#pragma unroll
+    for (uint32_t m = 1; m < kRankLanes; m <<= 1) c += __shfl_xor(c, static_cast<int>(m), 64);
+    if (l == 0) {
+        v.sk[c] = ke;
+        v.si[c] = e;
+    }
+}
+
 template <class K>
 __global__ __launch_bounds__(kSmallBlock) void k_small_prefix(Ins<K> v, const DevHeader* hdr,
                                                                const K* __restrict__ keys, const K* __restrict__ vals,
-                                                               uint32_t B, uint32_t n2, uint8_t* __restrict__ status) {
+                                                               uint32_t B, uint8_t* __restrict__ status) {
     __shared__ K sk[kSmallInsert];
     __shared__ uint32_t si[kSmallInsert];
     __shared__ uint32_t sh[33];
     const uint32_t tid = threadIdx.x;
     uint32_t* s = reinterpret_cast<uint32_t*>(v.st);
     for (uint32_t i = tid; i < sizeof(InsState) / 4; i += blockDim.x) s[i] = 0;
-    for (uint32_t i = tid; i < n2; i += blockDim.x) {
-        sk[i] = i < B ? keys[i] : kmax<K>();
-        si[i] = i < B ? i : 0xFFFFFFFFu;
+    // the pairs in (key, index) order, from k_small_rank
+    for (uint32_t i = tid; i < B; i += blockDim.x) {
+        sk[i] = v.sk[i];
+        si[i] = v.si[i];
     }
     __syncthreads();
     if (tid == 0) v.st->height = hdr->height;
-    bitonic_lds<K>(sk, si, n2);
     uint32_t f[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -726,8 +768,6 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_prefix(Ins<K> v, const De
         const uint32_t p = 2 * tid + e;
         if (p >= B) continue;
         const uint32_t pos = off + (e ? f[0] : 0u);
-        v.sk[p] = sk[p];
-        v.si[p] = si[p];
         if (f[e]) {
             v.uk[pos] = sk[p];
             v.upos[pos] = p;
@@ -740,9 +780,17 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_prefix(Ins<K> v, const De
 }
 
 template <class K>
-__global__ __launch_bounds__(kSmallBlock) void k_small_plan(TreeView<K> t, Ins<K> v, int H) {
+__global__ __launch_bounds__(kSmallBlock) void k_small_plan(TreeView<K> t, Ins<K> v0, int H) {
     __shared__ uint32_t sh[33];
+    __shared__ uint32_t sf0[kSmallInsert + 1], sf1[kSmallInsert + 1];
     const uint64_t tid = threadIdx.x, nth = blockDim.x;
+    // the flag and scan arrays live in LDS here (every phase reads what the
+    // previous one wrote); the locate kernel left the new-key flags in f0
+    for (uint32_t i = static_cast<uint32_t>(tid); i < v0.st->U; i += static_cast<uint32_t>(nth)) sf0[i] = v0.f0[i];
+    Ins<K> v = v0;
+    v.f0 = sf0;
+    v.f1 = sf1;
+    __syncthreads();
     block_scan_small(v.f0, v.f1, v.st->U, &v.st->R, sh);
     ph_compact_new<K>(v, tid, nth);
     __syncthreads();
@@ -833,10 +881,10 @@ void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, cons
     const int H = height_bound(c.leaf_cap);
 
     if (B <= kSmallInsert) {
-        uint32_t n2 = 2;
-        while (n2 < B) n2 <<= 1;
+        const uint32_t grank = static_cast<uint32_t>((B * kRankLanes + 255) / 256);
+        hipLaunchKernelGGL(k_small_rank<K>, dim3(grank), dim3(256), 0, s, v, keys, static_cast<uint32_t>(B));
         hipLaunchKernelGGL(k_small_prefix<K>, dim3(1), dim3(kSmallBlock), 0, s, v, t.hdr, keys, vals,
-                           static_cast<uint32_t>(B), n2, status);
+                           static_cast<uint32_t>(B), status);
         launch_locate<K>(t, v, c.cfg, B, status, s);
         hipLaunchKernelGGL(k_small_plan<K>, dim3(1), dim3(kSmallBlock), 0, s, t, v, H);
         launch_apply<K>(t, v, B, H, s);

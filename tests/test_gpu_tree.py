@@ -120,3 +120,25 @@ def test_large_batch_paths(width, n, xcd, stream):
     q = synth.mixed_queries(keys, 70001, seed, width)
     q[:3] = [0, np.iinfo(keys.dtype).max, keys[0]]
     assert_lookup_parity(t, sa, q)
+
+
+@pytest.mark.parametrize("width", [32, 64])
+def test_default_shapes_across_batch_sizes(width):
+    """With the shape left to the library, lookups switch lanes per query,
+    queries per group and LDS staging at 2^13 and 2^15 queries; batches on
+    both sides of each switch (and ragged tails) match the oracle, present
+    and absent keys, learned index included."""
+    import paper_2604_21117_amd as g
+    seed = 71
+    keys = key_set(1 << 18, width, seed, edges=True)
+    vals = synth.values_for(keys, seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, width // 8, max_batch=4096)
+    li = g.Learned(t, models=256)
+    li.train()
+    for B in (1, 63, (1 << 13) - 1, 1 << 13, (1 << 13) + 1, (1 << 15) - 1, 1 << 15, (1 << 15) + 17):
+        q = synth.mixed_queries(keys, B, seed + B, width)
+        assert_lookup_parity(t, sa, q)
+        gv, gf = li.lookup(q)
+        ov, of = sa.lookup(q)
+        assert np.array_equal(gf, of) and np.array_equal(gv, ov), f"learned, B={B}"
