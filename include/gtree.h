@@ -204,11 +204,11 @@ const char* gt_status_str(gt_status s);
  * bounds lo <= pos - pred <= hi over all keys routed to it, computed by the
  * same evaluation the lookup runs.  A lookup predicts, reads the leaves of
  * [pred + lo, pred + hi] (directly on a bulk-loaded tree, else through the
- * directory of leaf fence keys), and answers when a leaf holds the key or
- * proves it absent; anything else (a window that missed, a leaf split
- * since training, a piece without bounds) goes down the tree.  Results are
- * always exactly those of tree_lookup_batch; the models only change the
- * speed.
+ * directory of leaf fence keys) and answers when a leaf holds the key; while
+ * the tree is unchanged since training a window without the key proves it
+ * absent, and otherwise (inserts since training, overwritten bounds, a piece
+ * without bounds) such a query goes down the tree.  Results are always
+ * exactly those of tree_lookup_batch; the models only change the speed.
  * ---------------------------------------------------------------------- */
 typedef struct gt_learned gt_learned; /* opaque handle, host memory */
 

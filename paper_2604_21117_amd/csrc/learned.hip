@@ -36,14 +36,14 @@
 // bulk-loaded tree (directory = identity: position i is leaf i) small
 // batches read the window's leaves at once (latency: one dependent access
 // after the piece); otherwise, and for large batches (bound by the rate of
-// line requests, where reading 3-4 leaves per query costs more than a fence
-// search), the last fence <= key in the window picks the leaf.  A match is a hit.  While the tree is unchanged since
-// training and the bounds are the trained ones, every present key lies in
-// its window, so a window without the key proves it absent.  After inserts
-// a miss is authoritative only when a window leaf brackets the key (first
-// <= key <= last) or the key lies below the first leaf; anything else (a
-// leaf split since training, a piece without bounds) walks the tree in the
-// same kernel.  Results equal the tree's for any model state.
+// line requests, where reading 3-4 leaves per query costs more than a
+// fence search), the last fence <= key in the window picks the leaf.  A
+// match is a hit.  While the tree is unchanged since training and the
+// bounds are the trained ones, every present key lies in its window, so a
+// window without the key proves it absent.  Otherwise (after inserts, after
+// the bounds were overwritten, in a piece without bounds) a query whose
+// window does not hold it walks the tree in the same kernel.  Results equal
+// the tree's for any model state.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -630,28 +630,23 @@ __device__ __forceinline__ int64_t window_search(const DirEntry<K>* dir, int32_t
     return cand;
 }
 
-// What one window leaf says about the key: a hit, or (after inserts) an
-// authoritative miss -- the leaf brackets the key, or it is the first leaf
-// and the key lies below it.
+// A leaf's answer for one key: its value when the leaf holds it.
 template <class K>
-struct Verdict {
-    bool hit = false, sure = false;
+struct Hit {
+    bool hit = false;
     K val = kmax<K>();
 };
 
 template <class K>
-__device__ __forceinline__ void judge_leaf(const typename Trav<K, kLiG>::KV& kv, const typename Trav<K, kLiG>::KV& vv,
-                                           K key, bool first_leaf, int gbase, Verdict<K>& v) {
+__device__ __forceinline__ void match_leaf(const typename Trav<K, kLiG>::KV& kv, const typename Trav<K, kLiG>::KV& vv,
+                                           K key, int gbase, Hit<K>& v) {
     using T = Trav<K, kLiG>;
     const uint32_t slot = T::match_slot(kv, key, gbase);
-    const K first = static_cast<K>(__shfl(kv.v[0], gbase, 64));
-    const K last = static_cast<K>(__shfl(kv.v[T::KPL - 1], gbase + kLiG - 1, 64));
     const K x = T::pick_value(vv, slot < kSlots ? slot : 0u, gbase);
     if (slot < kSlots) {
         v.hit = true;
         v.val = x;
     }
-    if ((key >= first && key <= last) || (first_leaf && key < first)) v.sure = true;
 }
 
 template <class K, bool DIRECT, int BLK>
@@ -671,7 +666,7 @@ __global__ __launch_bounds__(BLK) void k_li_lookup(TreeView<K> t, LiView<K> li, 
         const K key = q[i];
         const Route r = route(a, static_cast<uint64_t>(key));
         const Piece e = load_piece(li.piece, r.j, r.m);
-        Verdict<K> v;
+        Hit<K> v;
         bool fb = e.lo > e.hi;
         if (!fb) {
             const int32_t p = piece_pos(e.slope, e.icpt, e.base, r.x, a.L);
@@ -679,8 +674,8 @@ __global__ __launch_bounds__(BLK) void k_li_lookup(TreeView<K> t, LiView<K> li, 
             if constexpr (DIRECT) {
                 // positions are leaf ids: read kDirect of the window's leaves at
                 // once; each lane checks its own slots (no cross-lane work
-                // unless the key is found or a miss needs proof)
-                for (int32_t b0 = wl; b0 <= wh && !(v.hit || v.sure); b0 += kDirect) {
+                // until one lane holds the key)
+                for (int32_t b0 = wl; b0 <= wh && !v.hit; b0 += kDirect) {
                     typename T::KV kv[kDirect], vv[kDirect];
 #pragma unroll
                     for (int u = 0; u < kDirect; ++u) {
@@ -707,36 +702,21 @@ __global__ __launch_bounds__(BLK) void k_li_lookup(TreeView<K> t, LiView<K> li, 
                     if (hm) {
                         v.hit = true;
                         v.val = static_cast<K>(__shfl(mval, gbase + __builtin_ctzll(hm), 64));
-                    } else {
-                        if (fresh < 0) fresh = t.hdr->epoch == a.epoch ? 1 : 0;
-                        if (fresh == 0) {
-                            // after inserts: a leaf that brackets the key, or the first leaf
-#pragma unroll
-                            for (int u = 0; u < kDirect; ++u) {
-                                if (b0 + u <= wh) {
-                                    const K first = static_cast<K>(__shfl(kv[u].v[0], gbase, 64));
-                                    const K last =
-                                        static_cast<K>(__shfl(kv[u].v[T::KPL - 1], gbase + kLiG - 1, 64));
-                                    if ((key >= first && key <= last) || (b0 + u == 0 && key < first)) v.sure = true;
-                                }
-                            }
-                        }
                     }
                 }
             } else {
+                // the last fence <= key in the window picks the leaf; none: the
+                // key lies before the window (absent while the tree is unchanged)
                 uint32_t leaf = kNone;
-                int64_t c = window_search<K>(li.dir, wl, wh, key, gl, gbase, &leaf);
-                if (c < 0 && wl == 0) {
-                    leaf = li.dir[0].leaf;  // below every fence: the first leaf
-                    c = 0;
-                }
+                const int64_t c = window_search<K>(li.dir, wl, wh, key, gl, gbase, &leaf);
                 if (c >= 0) {
                     const typename T::KV kv = T::load_keys(t.lkeys + static_cast<uint64_t>(leaf) * kSlots, gl);
                     const typename T::KV vv = T::load_keys(t.lvals + static_cast<uint64_t>(leaf) * kSlots, gl);
-                    judge_leaf<K>(kv, vv, key, c == 0, gbase, v);
+                    match_leaf<K>(kv, vv, key, gbase, v);
                 }
             }
-            if (!(v.hit || v.sure)) {
+            // no hit: proof of absence on an unchanged tree, else the tree decides
+            if (!v.hit) {
                 if (fresh < 0) fresh = t.hdr->epoch == a.epoch ? 1 : 0;
                 fb = fresh == 0;
             }
@@ -748,8 +728,8 @@ __global__ __launch_bounds__(BLK) void k_li_lookup(TreeView<K> t, LiView<K> li, 
             descend<K, kLiG, 1, false>(t, t.mirror, kMirrorMaxNodes, 0, kk, lf, gl, gbase);
             const typename T::KV kv = T::load_keys(t.lkeys + static_cast<uint64_t>(lf[0]) * kSlots, gl);
             const typename T::KV vv = T::load_keys(t.lvals + static_cast<uint64_t>(lf[0]) * kSlots, gl);
-            v = Verdict<K>();
-            judge_leaf<K>(kv, vv, key, false, gbase, v);
+            v = Hit<K>();
+            match_leaf<K>(kv, vv, key, gbase, v);
             // counted where it happens (rare): no reduction on the common path
             if (gl == 0) atomicAdd(&li.hdr->fallbacks, 1ull);
         }
