@@ -449,15 +449,19 @@ __device__ __forceinline__ uint32_t lower_bound_dev(const K* a, uint32_t n, K k)
     return lo;
 }
 
-// Merge-split of the touched leaves: one wave per leaf.
+// Lanes that rebuild one node (a leaf or an inner node): one per slot, four
+// nodes per wave, so a wave keeps four nodes' reads in flight.
+constexpr int kNodeLanes = 16;
+
+// Merge-split of the touched leaves: kNodeLanes lanes per leaf.
 template <class K>
 __global__ __launch_bounds__(kBlk) void k_apply_leaves(TreeView<K> t, Ins<K> v) {
     if (!v.st->ok) return;
     const uint64_t T0 = v.st->lvl_count[0];
-    const int lane = lane_id();
-    const uint64_t wave = gtid() / 64, nwaves = gstride() / 64;
+    const int gl = lane_id() % kNodeLanes, gbase = lane_id() - gl;
+    const uint64_t grp = gtid() / kNodeLanes, ngrp = gstride() / kNodeLanes;
     const uint32_t alloc = v.st->lvl_alloc[0];
-    for (uint64_t it = wave; it < T0; it += nwaves) {
+    for (uint64_t it = grp; it < T0; it += ngrp) {
         const uint32_t leaf = v.it_node[it];
         const uint32_t first = v.it_first[it];
         const uint32_t r = v.it_end[it] - first;
@@ -466,11 +470,8 @@ __global__ __launch_bounds__(kBlk) void k_apply_leaves(TreeView<K> t, Ins<K> v) 
         const uint32_t off = v.it_off[it];
         const uint64_t total = static_cast<uint64_t>(c) + r;
         const uint32_t base_new = alloc + off;
-        K okey = K(0), oval = K(0);
-        if (lane < kSlots) {
-            okey = t.lkeys[static_cast<uint64_t>(leaf) * kSlots + lane];
-            oval = t.lvals[static_cast<uint64_t>(leaf) * kSlots + lane];
-        }
+        const K okey = t.lkeys[static_cast<uint64_t>(leaf) * kSlots + gl];
+        const K oval = t.lvals[static_cast<uint64_t>(leaf) * kSlots + gl];
         const uint2 meta = t.lmeta[leaf];
         __threadfence_block();  // the old leaf is in registers before any write
         const K* nk = v.nk + first;
@@ -493,14 +494,14 @@ __global__ __launch_bounds__(kBlk) void k_apply_leaves(TreeView<K> t, Ins<K> v) 
                 if (j + 1 < k) v.psep[off + j] = key;
             }
         };
-        if (lane < static_cast<int>(c)) place(lane + lower_bound_dev(nk, r, okey), okey, oval);
-        for (uint32_t q0 = 0; q0 < r; q0 += 64) {
-            const uint32_t q = q0 + lane;
+        if (gl < static_cast<int>(c)) place(gl + lower_bound_dev(nk, r, okey), okey, oval);
+        for (uint32_t q0 = 0; q0 < r; q0 += kNodeLanes) {
+            const uint32_t q = q0 + gl;
             const bool act = q < r;
             const K key = act ? nk[q] : K(0);
             uint32_t rank = 0;
             for (uint32_t s = 0; s < c; ++s) {
-                const K ks = __shfl(okey, static_cast<int>(s), 64);
+                const K ks = __shfl(okey, gbase + static_cast<int>(s), 64);
                 rank += ks < key ? 1u : 0u;
             }
             if (act) place(q + rank, key, nv[q]);
@@ -508,7 +509,7 @@ __global__ __launch_bounds__(kBlk) void k_apply_leaves(TreeView<K> t, Ins<K> v) 
     }
 }
 
-// Rebuild the changed parents of level d: one wave per parent.
+// Rebuild the changed parents of level d: kNodeLanes lanes per parent.
 template <class K>
 __global__ __launch_bounds__(kBlk) void k_apply_inner(TreeView<K> t, Ins<K> v, int d) {
     if (!v.st->ok) return;
@@ -520,20 +521,17 @@ __global__ __launch_bounds__(kBlk) void k_apply_inner(TreeView<K> t, Ins<K> v, i
     const uint32_t alloc = v.st->lvl_alloc[d], alloc_c = v.st->lvl_alloc[d - 1];
     const uint32_t psep_d = v.st->lvl_psep[d], psep_c = v.st->lvl_psep[d - 1];
     const bool child_leaf = d == 1;
-    const int lane = lane_id();
-    const uint64_t wave = gtid() / 64, nwaves = gstride() / 64;
-    for (uint64_t j = wave; j < n; j += nwaves) {
+    const int gl = lane_id() % kNodeLanes, gbase = lane_id() - gl;
+    const uint32_t lane = static_cast<uint32_t>(gl);  // this lane's old slot
+    const uint64_t grp = gtid() / kNodeLanes, ngrp = gstride() / kNodeLanes;
+    for (uint64_t j = grp; j < n; j += ngrp) {
         const uint32_t node = v.it_node[bd + j];
         const uint32_t first = v.it_first[bd + j], end = v.it_end[bd + j];
         const uint32_t C = v.it_cold[bd + j];
         const uint32_t P = v.it_k[bd + j];
         const uint32_t off = v.it_off[bd + j];
-        K osep = kmax<K>();
-        uint32_t ochild = kNone;
-        if (lane < kSlots) {
-            osep = t.ikeys[static_cast<uint64_t>(node) * kSlots + lane];
-            ochild = t.ichild[static_cast<uint64_t>(node) * kSlots + lane];
-        }
+        const K osep = t.ikeys[static_cast<uint64_t>(node) * kSlots + lane];
+        const uint32_t ochild = t.ichild[static_cast<uint64_t>(node) * kSlots + lane];
         // per old slot: shift from split children before it, and its own item
         uint32_t shift = 0, myk = 1, myitem = kNone;
         uint64_t a = 0;
@@ -541,29 +539,30 @@ __global__ __launch_bounds__(kBlk) void k_apply_inner(TreeView<K> t, Ins<K> v, i
             const uint32_t cs = v.pi[static_cast<uint64_t>(l) * v.Bm + v.it_rep[bc + i]];
             const uint32_t ki = v.it_k[bc + i];
             a += ki - 1;
-            if (cs < static_cast<uint32_t>(lane)) shift += ki - 1;
-            if (cs == static_cast<uint32_t>(lane)) { myk = ki; myitem = i; }
+            if (cs < lane) shift += ki - 1;
+            if (cs == lane) { myk = ki; myitem = i; }
         }
         __threadfence_block();  // the old node is in registers before any write
         if (a == 0) continue;   // no child split: the parent is unchanged
         const uint32_t myoff = myitem != kNone ? v.it_off[bc + myitem] : 0u;
-        const uint32_t newpos = static_cast<uint32_t>(lane) + shift;
+        const uint32_t newpos = lane + shift;
         const uint64_t Cp = C + a;
         const uint32_t base_new = alloc + off;
-        for (uint64_t e0 = 0; e0 < Cp; e0 += 64) {
+        for (uint64_t e0 = 0; e0 < Cp; e0 += kNodeLanes) {
             const uint64_t e = e0 + lane;
             const bool act = e < Cp;
             // old slot whose entries cover e: the last slot with newpos <= e
             uint32_t sf = 0;
             for (uint32_t s = 0; s < C; ++s) {
-                const uint32_t np = shfl_u32(newpos, static_cast<int>(s));
+                const uint32_t np = shfl_u32(newpos, gbase + static_cast<int>(s));
                 if (np <= e) sf = s;
             }
-            const uint32_t np = shfl_u32(newpos, static_cast<int>(sf));
-            const uint32_t ks = shfl_u32(myk, static_cast<int>(sf));
-            const uint32_t ko = shfl_u32(myoff, static_cast<int>(sf));
-            const K os = __shfl(osep, static_cast<int>(sf), 64);
-            const uint32_t oc = shfl_u32(ochild, static_cast<int>(sf));
+            const int src = gbase + static_cast<int>(sf);
+            const uint32_t np = shfl_u32(newpos, src);
+            const uint32_t ks = shfl_u32(myk, src);
+            const uint32_t ko = shfl_u32(myoff, src);
+            const K os = __shfl(osep, src, 64);
+            const uint32_t oc = shfl_u32(ochild, src);
             const uint64_t jj = e - np;
             const K last_sep = (sf + 1 < C) ? os : kmax<K>();
             K sep;
@@ -864,9 +863,9 @@ template <class K>
 static void launch_apply(const TreeView<K>& t, const Ins<K>& v, uint64_t B, int H, hipStream_t s) {
     const uint32_t gB = grid_for(B, kBlk);
     hipLaunchKernelGGL(k_apply_updates<K>, dim3(gB), dim3(kBlk), 0, s, t, v);
-    hipLaunchKernelGGL(k_apply_leaves<K>, dim3(grid_for(B, kBlk / 64)), dim3(kBlk), 0, s, t, v);
+    hipLaunchKernelGGL(k_apply_leaves<K>, dim3(grid_for(B, kBlk / kNodeLanes)), dim3(kBlk), 0, s, t, v);
     for (int d = 1; d < H; ++d)
-        hipLaunchKernelGGL(k_apply_inner<K>, dim3(grid_for(B, kBlk / 64)), dim3(kBlk), 0, s, t, v, d);
+        hipLaunchKernelGGL(k_apply_inner<K>, dim3(grid_for(B, kBlk / kNodeLanes)), dim3(kBlk), 0, s, t, v, d);
     hipLaunchKernelGGL(k_grow_commit<K>, dim3(1), dim3(1024), 0, s, t, v);
     launch_mirror_refresh_if<K>(t, &v.st->mirror_dirty, s);
 }

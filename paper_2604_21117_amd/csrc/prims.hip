@@ -1,6 +1,6 @@
 // Scans and the stable key sort (hand-written for gfx950, wave64).
 //
-// scan_exclusive: one workgroup of 1024 threads for up to 64 Ki elements
+// scan_exclusive: one workgroup of 1024 threads for up to 16 Ki elements
 // (it walks the input in 4096-element rounds with a running carry), else
 // reduce-then-scan over 4096-element tiles (tile sums, one-workgroup scan of
 // the sums, tile scans plus offsets).
@@ -20,7 +20,7 @@ namespace gt {
 constexpr int kScanBlock = 1024;
 constexpr int kScanItems = 4;
 constexpr uint64_t kScanTile = kScanBlock * kScanItems;  // 4096
-constexpr uint64_t kScanSmallMax = 1 << 16;
+constexpr uint64_t kScanSmallMax = 1 << 14;  // one workgroup up to four tiles
 
 static uint32_t ntiles_for(uint64_t n) { return static_cast<uint32_t>((n + kScanTile - 1) / kScanTile); }
 
