@@ -20,7 +20,8 @@ Also measured in the same run, outside the K timed steps:
                   2048 distinct batches) and single-launch latency (events)
   size_sweep      B = 1024 on trees of 2^4 .. 2^24 keys (prefixes of the same
                   key sequence), plain and learned
-  large_batch     2^20-key lookup batches (warm; `--cold` adds flushed runs)
+  large_batch     2^20-key lookup batches, warm and cold (a 2 GiB flush before
+                  each cold launch; `--no-cold` skips them)
   roofline        the large-batch lookup kernel: algorithmic bytes per launch
                   over its average duration (HIP events on its stream)
   insert          fresh-key insert batches, B = 1024 and 2^20
@@ -139,7 +140,7 @@ def main():
     ap.add_argument("--path", choices=("learned", "plain"), default="learned")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--cold", action="store_true", help="also time flushed (cold-cache) 2^20 batches")
+    ap.add_argument("--no-cold", action="store_true", help="skip the flushed (cold-cache) 2^20 batches")
     ap.add_argument("--log2n", type=int, default=N_LOG2)
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection mode: a 1 GiB device copy (calibration) and three 2^20-key "
@@ -361,7 +362,9 @@ def main():
              "distinct_nodes_per_level": ab["distinct_nodes_per_level"]}
     lw = timer.run(lambda: g.li_lookup_batch(li.h, qld, vl, fl, stream), 12)
     large["learned_warm_avg_us"] = round(float(np.mean(lw)), 2)
-    if args.cold:
+    if not args.no_cold:
+        # cold: an untimed 2 GiB read-modify-write evicts the 256 MB Infinity
+        # Cache and the L2s before each timed launch
         flush = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
         cold = []
         for _ in range(12):
@@ -369,6 +372,7 @@ def main():
             cold += timer.run(lambda: g.tree_lookup_batch(tree.h, qld, vl, fl, stream), 1, skip=0)
         del flush
         large["cold_avg_us"] = round(float(np.mean(cold[2:])), 2)
+        large["cold_frac_of_roofline"] = round(ab["bytes"] / (large["cold_avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
     print("[bench] large batch done", file=sys.stderr, flush=True)
 
     # ---- range batches

@@ -181,8 +181,9 @@ __global__ void k_unique(Ins<K> v, uint64_t B, const K* __restrict__ vals) {
     }
 }
 
-// Locate every distinct key; G lanes per key, the top levels from LDS.
-template <class K, int G, int LV>
+// Locate every distinct key; G lanes per key, QPG keys in flight per group,
+// the top levels from LDS.
+template <class K, int G, int QPG, int LV>
 __global__ __launch_bounds__(kBlk) void k_locate(TreeView<K> t, Ins<K> v, uint8_t* __restrict__ status) {
     using T = Trav<K, G>;
     extern __shared__ __align__(16) uint8_t lds[];
@@ -199,24 +200,35 @@ __global__ __launch_bounds__(kBlk) void k_locate(TreeView<K> t, Ins<K> v, uint8_
     const uint64_t U = v.st->U;
     const int lane = lane_id();
     const int gl = lane % G, gbase = lane - gl;
-    const uint64_t per_block = kBlk / G;
+    const uint64_t group = threadIdx.x / G;
+    const uint64_t per_block = static_cast<uint64_t>(kBlk / G) * QPG;
     const uint64_t ntiles = (U + per_block - 1) / per_block;
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint64_t u = tile * per_block + threadIdx.x / G;
-        const bool live = u < U;
-        K key[1] = {live ? v.uk[u] : K(0)};
-        uint64_t qi[1] = {live ? u : ~0ull};
-        uint32_t leaf[1];
-        descend<K, G, 1, true>(t, mir, mnodes, LV, key, leaf, gl, gbase, v.pn, v.pi, v.Bm, qi);
-        typename T::KV kv = T::load_keys(t.lkeys + static_cast<uint64_t>(leaf[0]) * kSlots, gl);
-        const uint32_t slot = T::match_slot(kv, key[0], gbase);
-        const bool found = slot < kSlots && !empty;
-        if (live && gl == 0) {
-            v.ufound[u] = found ? 1 : 0;
-            v.uleaf[u] = leaf[0];
-            v.uslot[u] = static_cast<uint8_t>(found ? slot : 0);
-            v.f0[u] = found ? 0u : 1u;
-            status[v.si[v.upos[u]]] = found ? 1 : 0;
+        K key[QPG];
+        uint64_t qi[QPG];
+#pragma unroll
+        for (int j = 0; j < QPG; ++j) {
+            const uint64_t u = tile * per_block + group * QPG + j;
+            key[j] = u < U ? v.uk[u] : K(0);
+            qi[j] = u < U ? u : ~0ull;
+        }
+        uint32_t leaf[QPG];
+        descend<K, G, QPG, true>(t, mir, mnodes, LV, key, leaf, gl, gbase, v.pn, v.pi, v.Bm, qi);
+        typename T::KV kv[QPG];
+#pragma unroll
+        for (int j = 0; j < QPG; ++j) kv[j] = T::load_keys(t.lkeys + static_cast<uint64_t>(leaf[j]) * kSlots, gl);
+#pragma unroll
+        for (int j = 0; j < QPG; ++j) {
+            const uint32_t slot = T::match_slot(kv[j], key[j], gbase);
+            const bool found = slot < kSlots && !empty;
+            if (qi[j] != ~0ull && gl == 0) {
+                const uint64_t u = qi[j];
+                v.ufound[u] = found ? 1 : 0;
+                v.uleaf[u] = leaf[j];
+                v.uslot[u] = static_cast<uint8_t>(found ? slot : 0);
+                v.f0[u] = found ? 0u : 1u;
+                status[v.si[v.upos[u]]] = found ? 1 : 0;
+            }
         }
     }
 }
@@ -826,24 +838,33 @@ static uint32_t grid_for(uint64_t n, uint32_t per_block) {
     return static_cast<uint32_t>(g);
 }
 
-template <class K, int G, int LV>
+template <class K, int G, int QPG, int LV>
 static void launch_locate_t(const TreeView<K>& t, const Ins<K>& v, uint64_t B, uint8_t* status, hipStream_t s) {
     const uint32_t lds = LV > 0 ? MirrorLayout<K>::bytes(mirror_nodes_for_levels(LV)) : 0;
-    uint32_t grid = grid_for(B, kBlk / G);
+    uint32_t grid = grid_for((B + QPG - 1) / QPG, kBlk / G);
     if (grid > 2048) grid = 2048;
-    hipLaunchKernelGGL((k_locate<K, G, LV>), dim3(grid), dim3(kBlk), lds, s, t, v, status);
+    hipLaunchKernelGGL((k_locate<K, G, QPG, LV>), dim3(grid), dim3(kBlk), lds, s, t, v, status);
+}
+
+// Shape by batch size, as for lookups: small batches are latency-bound (16
+// lanes, one key per group); large ones are bound by the rate of line
+// requests (8 lanes, four keys in flight per group).
+template <class K, int G, int QPG>
+static void launch_locate_lv(const TreeView<K>& t, const Ins<K>& v, const LaunchCfg& cfg, uint64_t B,
+                             uint8_t* status, hipStream_t s) {
+    switch (cfg.lds_levels) {
+        case 0: launch_locate_t<K, G, QPG, 0>(t, v, B, status, s); break;
+        case 1: launch_locate_t<K, G, QPG, 1>(t, v, B, status, s); break;
+        case 3: launch_locate_t<K, G, QPG, 3>(t, v, B, status, s); break;
+        default: launch_locate_t<K, G, QPG, 2>(t, v, B, status, s); break;
+    }
 }
 
 template <class K>
 static void launch_locate(const TreeView<K>& t, const Ins<K>& v, const LaunchCfg& cfg, uint64_t B, uint8_t* status,
                           hipStream_t s) {
-    // 16 lanes per key: one 128-byte (or 64-byte) line per group load
-    switch (cfg.lds_levels) {
-        case 0: launch_locate_t<K, 16, 0>(t, v, B, status, s); break;
-        case 1: launch_locate_t<K, 16, 1>(t, v, B, status, s); break;
-        case 3: launch_locate_t<K, 16, 3>(t, v, B, status, s); break;
-        default: launch_locate_t<K, 16, 2>(t, v, B, status, s); break;
-    }
+    if (B >= kLargeBatch) launch_locate_lv<K, 8, 4>(t, v, cfg, B, status, s);
+    else launch_locate_lv<K, 16, 1>(t, v, cfg, B, status, s);
 }
 
 // highest tree height the pools allow (non-root inner nodes have >= 8
