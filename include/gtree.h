@@ -333,7 +333,9 @@ typedef struct {
 } gt_srv_stats;
 
 /* Create a server over tree t (and learned index li for lookups, or NULL).
- * Allocates its staging buffers (pinned host, device) here, not later. */
+ * Allocates its staging buffers (pinned host, device) here, not later.
+ * li_train / li_set_bounds on li are allowed while no request is in flight;
+ * the server then captures its lookup graphs again. */
 gt_status srv_create(gt_tree* t, gt_learned* li, const gt_srv_params* p /*host*/, gt_server** out);
 /* Queue a batch (non-blocking); *ticket identifies it. */
 gt_status srv_submit(gt_server* s, const gt_request* r /*host*/, uint64_t* ticket /*host*/);

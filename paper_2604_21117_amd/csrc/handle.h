@@ -6,6 +6,11 @@
 #include "common.h"
 #include "kernels.h"
 
+// Changes whenever li_train or li_set_bounds changes what a learned lookup
+// launch captures (kernel arguments, tables); a cached graph of an older
+// generation must be captured again.
+uint64_t gt_li_generation(const gt_learned* li);
+
 struct gt_tree {
     gt_params p;
     int kb;

@@ -776,7 +776,10 @@ struct gt_learned {
     uint64_t off_fit, off_piece, off_dir, off_nxt0, off_nxt1, off_rank0, off_rank1, off_pos, off_start, off_bnd,
         off_cnt, off_partial, off_ident;
     LiArgs args;
+    uint64_t generation = 0;  // bumped whenever the lookup's arguments or tables change
 };
+
+uint64_t gt_li_generation(const gt_learned* li) { return li->generation; }
 
 namespace {
 
@@ -861,6 +864,7 @@ gt_status train_t(gt_learned* li, hipStream_t s) {
         LI_HIP(hipMemsetAsync(v.hdr, 0, sizeof(LiHeader), s));
         LI_HIP(hipStreamSynchronize(s));
         li->trained = false;
+        li->generation++;
         return GT_OK;
     }
     const uint32_t n = dh.leaf_used;
@@ -918,6 +922,7 @@ gt_status train_t(gt_learned* li, hipStream_t s) {
     li->args.exact = 1;
     li->args.pad = 0;
     li->trained = true;
+    li->generation++;
     return GT_OK;
 }
 
@@ -1014,6 +1019,7 @@ gt_status li_set_bounds(gt_learned* li, int32_t lo, int32_t hi, hipStream_t stre
     if (lo < -30000 || hi > 30000) return GT_ERR_INVALID;
     const uint64_t cells = static_cast<uint64_t>(li->M) * kSeg;
     li->args.exact = 0;  // windows no longer cover every key: misses need proof
+    li->generation++;
     hipLaunchKernelGGL(k_set_bounds, dim3(grid_of(cells, 256)), dim3(256), 0, stream,
                        reinterpret_cast<Piece*>(li->arena + li->off_piece), cells, lo, hi);
     return hipGetLastError() == hipSuccess ? GT_OK : GT_ERR_HIP;

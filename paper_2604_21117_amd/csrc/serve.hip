@@ -71,6 +71,7 @@ struct Slot {
     uint8_t* h_out0 = nullptr; uint8_t* h_out1 = nullptr; uint32_t* h_cnt = nullptr; uint8_t* h_flag = nullptr;
     uint32_t* h_err = nullptr;
     std::map<uint64_t, hipGraphExec_t> graphs;
+    uint64_t li_gen = 0;   // learned-index generation the lookup graphs were captured at
     uint32_t bucket = 0;
     uint64_t out_len = 0;  // staged range output entries
 };
@@ -192,6 +193,21 @@ hipError_t launch(gt_server* s, Slot& sl, uint32_t op, uint32_t bucket, uint64_t
     if (!graphs) {
         s->direct_launches++;
         return enqueue_ops(s, sl, op, bucket, outn, st);
+    }
+    if (op == GT_OP_LOOKUP && s->li) {
+        // a retrained (or re-bounded) learned index: its lookup graphs are stale
+        const uint64_t gen = gt_li_generation(s->li);
+        if (gen != sl.li_gen) {
+            for (auto g = sl.graphs.begin(); g != sl.graphs.end();) {
+                if ((g->first >> 56) == GT_OP_LOOKUP) {
+                    hipGraphExecDestroy(g->second);
+                    g = sl.graphs.erase(g);
+                } else {
+                    ++g;
+                }
+            }
+            sl.li_gen = gen;
+        }
     }
     const uint64_t key = (static_cast<uint64_t>(op) << 56) | (static_cast<uint64_t>(bucket) << 28) | outn;
     auto it = sl.graphs.find(key);

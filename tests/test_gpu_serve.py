@@ -130,6 +130,37 @@ def test_learned_lookups_in_server():
     srv.close()
 
 
+def test_server_recaptures_after_learned_changes():
+    """The server caches a graph per lookup bucket; overwriting the learned
+    index's bounds (the tree unchanged) or retraining it changes what a
+    lookup launch must be, so the same bucket afterwards still matches the
+    oracle (a stale graph would take the narrowed windows as exact and report
+    present keys absent)."""
+    import paper_2604_21117_amd as g
+    seed = 73
+    keys, vals, fresh = _setup(seed, n=1 << 16)
+    sa = oracle.SortedArray(keys, vals, 64)
+    t = mk_tree(keys, vals, 8, leaf_slack=1 << 14, max_batch=1024)
+    li = g.Learned(t, models=128)
+    li.train()
+    srv = g.Server(t, learned=li, slots=2)
+    q = synth.present_queries(keys, 512, seed)
+
+    def run():
+        b = g.Batch(0, q)
+        assert srv.wait(srv.submit(b)) == g.GT_OK
+        v, f = sa.lookup(q)
+        assert np.array_equal(b.out1, f) and np.array_equal(b.out0, v)
+
+    run()
+    li.set_bounds(0, 0)
+    run()
+    li.train()
+    run()
+    assert srv.stats()["graph_launches"] >= 3
+    srv.close()
+
+
 def test_admission_cap():
     import paper_2604_21117_amd as g
     seed = 72
