@@ -252,7 +252,9 @@ gt_status li_create(gt_tree* t, const gt_li_params* p /*host*/, void* arena, uin
  * exact bounds over every key.  Synchronises `stream`. */
 gt_status li_train(gt_learned* li, hipStream_t stream);
 
-/* Same contract as tree_lookup_batch. */
+/* Same contract as tree_lookup_batch.  The launch passes the index's current
+ * parameters by value: a graph that captured it must be captured again after
+ * li_train or li_set_bounds. */
 gt_status li_lookup_batch(gt_learned* li, const void* keys, uint64_t B, void* values_out,
                           uint8_t* found_out, hipStream_t stream);
 

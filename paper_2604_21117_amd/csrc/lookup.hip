@@ -7,7 +7,7 @@
 // value.  A key that is not found returns all ones with found = 0 (the
 // paper's -1 result, Section IV-D).  Results go to the caller's order.
 //
-// Range (spec addition over the linked leaves of Section III): the
+// Range (an addition over the linked leaves of Section III): the
 // group descends to the leaf of `lo`, then walks the leaf chain; per leaf a
 // ballot marks the slots with lo <= key <= hi and the group writes them in
 // slot order at out[offset + running count], until `max` pairs are written,
