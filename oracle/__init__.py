@@ -13,6 +13,8 @@ Parts (each cited in ``oracle.c``):
   -1 "not found" result).
 * :class:`PointerTree` -- a textbook pointer B+-tree (Section III), the
   timed CPU baseline; lookup batches split evenly over threads (Section V-F).
+  Its ``lookup_levelwise`` is the paper's level-by-level search of a sorted
+  batch with a FIFO of (node, count) entries (Sections IV-A, IV-F).
 * :func:`check_export` -- invariant checker over the flat tree export
   format (sorted leaves, equal depth, fill of at least half, separator
   bounds, leaf chain, reachability, padding).
@@ -76,6 +78,8 @@ def lib():
         L.bpt_lookup_batch.argtypes = [vp, _u64p, u64, _u64p, _u8p, i32]
         L.bpt_range_batch.argtypes = [vp, _u64p, _u64p, _u32p, _u64p, u64, _u64p, _u64p, _u32p]
         L.bpt_stats.argtypes = [vp, _u64p]
+        L.bpt_levelwise.argtypes = [vp, _u64p, u64, _u64p, _u8p, _u32p, _u64p, _u64p, _u64p, u64]
+        L.bpt_levelwise.restype = C.c_longlong
         L.bpt_export_bytes.argtypes = [vp]
         L.bpt_export_bytes.restype = u64
         L.bpt_export.argtypes = [vp, _u8p, u64]
@@ -185,6 +189,25 @@ class PointerTree:
         fo = np.empty(len(q), dtype=np.uint8)
         lib().bpt_lookup_batch(self.h, q, len(q), vo, fo, threads)
         return _narrow(vo, self.width), fo
+
+    def lookup_levelwise(self, sorted_q):
+        """Level-wise search of an ascending batch (Sections IV-A, IV-F).
+
+        Returns (values, found, runs): results in processing order, and the
+        FIFO entries as a dict of arrays level / first / count / node.
+        """
+        q = _w(sorted_q)
+        B = len(q)
+        vo = np.empty(max(B, 1), dtype=np.uint64)
+        fo = np.empty(max(B, 1), dtype=np.uint8)
+        cap = max(1, B * int(self.stats()["height"]))
+        lv = np.empty(cap, dtype=np.uint32)
+        fi, co, no = (np.empty(cap, dtype=np.uint64) for _ in range(3))
+        w = lib().bpt_levelwise(self.h, q, B, vo, fo, lv, fi, co, no, cap)
+        if w < 0:
+            raise ValueError("batch not in ascending order")
+        runs = {"level": lv[:w].copy(), "first": fi[:w].copy(), "count": co[:w].copy(), "node": no[:w].copy()}
+        return _narrow(vo[:B], self.width), fo[:B], runs
 
     def range(self, lo, hi, maxc):
         lo, hi = _w(lo), _w(hi)

@@ -372,6 +372,65 @@ void bpt_range_batch(const bptree* t, const u64* lo, const u64* hi, const u32* m
     }
 }
 
+/*
+ * Level-wise batch search (Sections IV-A and IV-F), the paper's traversal
+ * written out on the pointer tree.  The batch sq[0..B) must be ascending.
+ * A FIFO holds one tree level as entries (node, number of keys); the keys
+ * are taken in order by one running key index.  For each entry the node is
+ * taken once and its keys are compared with it one after another: at an
+ * inner node each key yields a child, and a key whose child equals that of
+ * the entry written last to the next FIFO increments that entry's count,
+ * otherwise it opens a new entry with count 1.  At the leaves each key's
+ * result (its value, or -1 with found = 0, Section IV-D) is written in
+ * processing order.
+ *
+ * Each entry is reported as a run: (level, first key index, count, node
+ * identity), levels in order.  Returns the number of runs, or -1 if the
+ * batch is not ascending or more than run_cap runs would be written.
+ */
+long long bpt_levelwise(const bptree* t, const u64* sq, u64 B, u64* vout, uint8_t* fout, u32* run_level,
+                        u64* run_first, u64* run_count, u64* run_node, u64 run_cap) {
+    for (u64 i = 1; i < B; i++)
+        if (sq[i] < sq[i - 1]) return -1;
+    typedef struct { const bnode* x; u64 n; } entry;
+    entry* cur = malloc(sizeof(entry) * (B ? B : 1));
+    entry* nxt = malloc(sizeof(entry) * (B ? B : 1));
+    u64 ncur = 0, w = 0;
+    long long ret = 0;
+    const u64 miss = ones(t->width);
+    if (B) cur[ncur++] = (entry){ t->root, B };
+    for (int level = 0; level < t->height && ret == 0; level++) {
+        u64 idx = 0, nn = 0;
+        for (u64 e = 0; e < ncur; e++) {
+            const bnode* x = cur[e].x;
+            if (w >= run_cap) { ret = -1; break; }
+            run_level[w] = (u32)level;
+            run_first[w] = idx;
+            run_count[w] = cur[e].n;
+            run_node[w] = (u64)(uintptr_t)x;
+            w++;
+            for (u64 j = 0; j < cur[e].n; j++, idx++) {
+                const u64 k = sq[idx];
+                if (x->leaf) {
+                    int p = 0;
+                    while (p < x->n && x->key[p] != k) p++;
+                    if (p < x->n) { vout[idx] = x->val[p]; fout[idx] = 1; }
+                    else { vout[idx] = miss; fout[idx] = 0; }
+                } else {
+                    const bnode* c = x->child[route(x, k)];
+                    if (nn > 0 && nxt[nn - 1].x == c) nxt[nn - 1].n++;
+                    else nxt[nn++] = (entry){ c, 1 };
+                }
+            }
+        }
+        entry* tmp = cur; cur = nxt; nxt = tmp;
+        ncur = nn;
+    }
+    free(cur);
+    free(nxt);
+    return ret == 0 ? (long long)w : -1;
+}
+
 void bpt_stats(const bptree* t, u64* out /* height, n_keys, n_inner, n_leaves */) {
     out[0] = (u64)t->height; out[1] = t->n_keys; out[2] = t->n_inner; out[3] = t->n_leaves;
 }
