@@ -22,6 +22,9 @@ Also measured in the same run, outside the K timed steps:
                   key sequence), plain and learned
   large_batch     2^20-key lookup batches, warm and cold (a 2 GiB flush before
                   each cold launch; `--no-cold` skips them)
+  levelwise       the paper's level-by-level walk of a sorted batch against
+                  the per-query descent, B = 1024, 2^15, 2^20, uniform and
+                  Zipf keys, in random order and sorted
   roofline        the large-batch lookup kernel: algorithmic bytes per launch
                   over its average duration (HIP events on its stream)
   insert          fresh-key insert batches, B = 1024 and 2^20
@@ -375,6 +378,51 @@ def main():
         large["cold_frac_of_roofline"] = round(ab["bytes"] / (large["cold_avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
     print("[bench] large batch done", file=sys.stderr, flush=True)
 
+    # ---- level-wise traversal (the paper's sorted, level-by-level walk)
+    # against the per-query descent: batches in random order and sorted,
+    # uniform and Zipf keys; time per batch from graph replays
+    levelwise = {}
+    for dist in ("uniform", "zipf"):
+        for b in (1024, 1 << 15, 1 << 20):
+            qn = synth.present_queries(keys, b, SEED, purpose=7000 + b.bit_length()) if dist == "uniform" \
+                else keys[zipf.indices(b)]
+            qsort = np.sort(qn)
+            qdn, qds = tree.dev(qn), tree.dev(qsort)
+            v4 = torch.empty(b, dtype=torch.int64, device=dev)
+            f4 = torch.empty(b, dtype=torch.uint8, device=dev)
+            ws = tree.levelwise_workspace(b, False)
+            wsp = tree.levelwise_workspace(b, True)
+            cases = {
+                "per_query": (lambda: g.tree_lookup_batch(tree.h, qdn, v4, f4, stream), qn),
+                "per_query_sorted_input": (lambda: g.tree_lookup_batch(tree.h, qds, v4, f4, stream), qsort),
+                "levelwise": (lambda: g.tree_lookup_levelwise(tree.h, qdn, 0, v4, f4, ws, stream), qn),
+                "levelwise_presorted": (lambda: g.tree_lookup_levelwise(tree.h, qds, g.GT_LW_PRESORTED, v4, f4,
+                                                                        wsp, stream), qsort),
+            }
+            reps = 32 if b <= (1 << 15) else 8
+            row = {}
+            for name, (fn, qref) in cases.items():
+                gr = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(gr, stream=stream):
+                    for _ in range(reps):
+                        fn()
+                gr.replay()
+                stream.synchronize()
+                assert g.to_numpy(f4).all() and np.array_equal(g.to_numpy(v4, np.uint64),
+                                                               synth.values_for(qref, SEED, 64)), (dist, b, name)
+                best = None
+                for _ in range(3):
+                    t0 = time.perf_counter()
+                    gr.replay()
+                    stream.synchronize()
+                    dt = (time.perf_counter() - t0) / reps * 1e6
+                    best = dt if best is None else min(best, dt)
+                del gr
+                row[name + "_us"] = round(best, 2)
+            levelwise.setdefault(dist, {})[str(b)] = row
+            del ws, wsp, qdn, qds
+    print("[bench] level-wise done", file=sys.stderr, flush=True)
+
     # ---- range batches
     lo, hi, mc = synth.range_starts_and_lengths(keys, B, SEED, 100)
     off = np.zeros(B, dtype=np.uint64)
@@ -496,6 +544,7 @@ def main():
         "sweep": sweep,
         "size_sweep_b1024": size_sweep,
         "large_batch": large,
+        "levelwise": levelwise,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_lookup<unsigned long, 8, 4, 2, true, false> (B=2^20, warm)",

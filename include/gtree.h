@@ -10,6 +10,8 @@
  *   tree_lookup_batch  root-to-leaf search of a key batch     (Section IV-A,
  *                      IV-E, IV-F: batch search, "key <= node entry" routing,
  *                      -1 for a key that is not found)
+ *   tree_lookup_levelwise  the same results by the paper's level-by-level
+ *                      walk of a sorted batch (Sections IV-A, IV-F)
  *   tree_insert_batch  sort / merge / split insert of a batch with parent
  *                      split propagation (keeps the Section III invariants)
  *   tree_range_batch   range scans over the linked leaves (Section III)
@@ -131,6 +133,34 @@ gt_status tree_build(const gt_params* p /*host*/, const void* keys, const void* 
  */
 gt_status tree_lookup_batch(gt_tree* t, const void* keys, uint64_t B, void* values_out,
                             uint8_t* found_out, hipStream_t stream);
+
+/*
+ * Level-wise lookup batch: the paper's own traversal (Sections IV-A and
+ * IV-F).  The batch is sorted, then walks the tree one level at a time: a
+ * FIFO of (node, first query, count) entries, each node read once and
+ * compared with the whole run of sorted queries that passes through it,
+ * the run cut into the next level's entries where the child changes.  The
+ * results are those of tree_lookup_batch, in caller order.
+ *
+ * flags: 0, or GT_LW_PRESORTED when the caller's keys are already in
+ * ascending order: no sort is made and the runs come straight from the
+ * caller's order.  Keys that are not in order still get correct results
+ * (the runs are only shorter).
+ *
+ * workspace: device memory of at least
+ * tree_lookup_levelwise_workspace_bytes(t, B, flags) bytes, owned by the
+ * caller; its contents on entry are ignored.  A call uses it until the call
+ * completes on `stream`, so calls that may overlap need separate
+ * workspaces.  B < 2^31.  Errors: GT_ERR_INVALID for null pointers, unknown
+ * flags or B too large; GT_ERR_CAPACITY when workspace_bytes is too small.
+ * Nothing is enqueued on an error.  No memory is allocated; the call is
+ * graph-capturable.
+ */
+#define GT_LW_PRESORTED 1u
+uint64_t tree_lookup_levelwise_workspace_bytes(const gt_tree* t, uint64_t B, uint32_t flags);
+gt_status tree_lookup_levelwise(gt_tree* t, const void* keys, uint64_t B, uint32_t flags, void* values_out,
+                                uint8_t* found_out, void* workspace, uint64_t workspace_bytes,
+                                hipStream_t stream);
 
 /*
  * Insert batch.  Equivalent to inserting (keys[i], values[i]) one at a time

@@ -98,6 +98,9 @@ def lib():
         L.tree_arena_bytes.restype = u64
         L.tree_build.argtypes = [C.POINTER(gt_params), vp, vp, u64, vp, u64, vp, C.POINTER(vp)]
         L.tree_lookup_batch.argtypes = [vp, vp, u64, vp, vp, vp]
+        L.tree_lookup_levelwise_workspace_bytes.argtypes = [vp, u64, u32]
+        L.tree_lookup_levelwise_workspace_bytes.restype = u64
+        L.tree_lookup_levelwise.argtypes = [vp, vp, u64, u32, vp, vp, vp, u64, vp]
         L.tree_insert_batch.argtypes = [vp, vp, vp, u64, vp, vp]
         L.tree_range_batch.argtypes = [vp, vp, vp, vp, vp, u64, vp, vp, vp, vp]
         L.tree_destroy.argtypes = [vp]
@@ -206,6 +209,19 @@ def tree_build(params: gt_params, keys, values, arena, stream=None) -> int:
 def tree_lookup_batch(h, keys, values_out, found_out, stream=None):
     _check(lib().tree_lookup_batch(h, _ptr(keys), keys.numel(), _ptr(values_out), _ptr(found_out),
                                    _stream(stream)), "tree_lookup_batch")
+
+
+GT_LW_PRESORTED = 1
+
+
+def tree_lookup_levelwise_workspace_bytes(h, B: int, flags: int = 0) -> int:
+    return lib().tree_lookup_levelwise_workspace_bytes(h, B, flags)
+
+
+def tree_lookup_levelwise(h, keys, flags, values_out, found_out, workspace, stream=None):
+    _check(lib().tree_lookup_levelwise(h, _ptr(keys), keys.numel(), flags, _ptr(values_out), _ptr(found_out),
+                                       _ptr(workspace), workspace.numel(), _stream(stream)),
+           "tree_lookup_levelwise")
 
 
 def tree_insert_batch(h, keys, values, status_out, stream=None):
@@ -329,6 +345,24 @@ class Tree:
 
     def lookup(self, q: np.ndarray):
         vo, fo = self.lookup_dev(self.dev(q))
+        return to_numpy(vo, self.udtype), to_numpy(fo)
+
+    def levelwise_workspace(self, B: int, presorted: bool = False):
+        torch = _torch()
+        flags = GT_LW_PRESORTED if presorted else 0
+        n = tree_lookup_levelwise_workspace_bytes(self.h, B, flags)
+        return torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
+
+    def lookup_levelwise_dev(self, q, presorted: bool = False, workspace=None, stream=None):
+        torch = _torch()
+        vo = torch.empty(q.numel(), dtype=self.tdtype, device=self.device)
+        fo = torch.empty(q.numel(), dtype=torch.uint8, device=self.device)
+        ws = workspace if workspace is not None else self.levelwise_workspace(q.numel(), presorted)
+        tree_lookup_levelwise(self.h, q, GT_LW_PRESORTED if presorted else 0, vo, fo, ws, stream)
+        return vo, fo
+
+    def lookup_levelwise(self, q: np.ndarray, presorted: bool = False):
+        vo, fo = self.lookup_levelwise_dev(self.dev(q), presorted)
         return to_numpy(vo, self.udtype), to_numpy(fo)
 
     def insert(self, k: np.ndarray, v: np.ndarray, check: bool = True):

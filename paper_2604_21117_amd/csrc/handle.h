@@ -28,6 +28,8 @@ struct gt_tree {
     uint64_t scratch_bytes;
     uint64_t max_batch;
     gt::LaunchCfg cfg;
+    uint32_t h_bound;       // the tree's height or more (exact after the build;
+                            // after an insert, the most the pool sizes allow)
 };
 
 

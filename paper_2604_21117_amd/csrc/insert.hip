@@ -700,54 +700,14 @@ __global__ __launch_bounds__(1024) void k_grow_commit(TreeView<K> t, Ins<K> v) {
 
 // ------------------------------------------------- small batches (B <= 2048)
 //
-// One workgroup sorts, deduplicates and plans every level, with barriers
-// where the general path has kernel boundaries and block scans where it has
-// device-wide scans; the phase bodies are the same functions.
+// A rank sort over many workgroups orders the batch; then one workgroup
+// deduplicates and plans every level, with barriers where the general path
+// has kernel boundaries and block scans where it has device-wide scans; the
+// phase bodies are the same functions.
 
 constexpr uint32_t kSmallInsert = 2048;
+static_assert(kSmallInsert <= kRankSortMax, "the small path sorts with rank_sort_small");
 constexpr int kSmallBlock = 1024;
-
-// Stable sort of B <= kSmallInsert (key, batch index) pairs by rank: the
-// rank of (k_i, i) is the number of pairs (k_j, j) before it in (key, index)
-// order.  Every workgroup holds all keys in LDS and 16 lanes share one
-// element's count, so the B^2 comparisons spread over B / 16 CUs instead of
-// the one CU a workgroup-local sort would use.
-constexpr uint32_t kRankLanes = 16;  // lanes sharing one element's count
-
-template <class K>
-__global__ __launch_bounds__(256) void k_small_rank(Ins<K> v, const K* __restrict__ keys, uint32_t B) {
-    __shared__ K sk[kSmallInsert];
-    for (uint32_t i = threadIdx.x; i < B; i += blockDim.x) sk[i] = keys[i];
-    __syncthreads();
-    const uint32_t e = (blockIdx.x * blockDim.x + threadIdx.x) / kRankLanes, l = threadIdx.x % kRankLanes;
-    if (e >= B) return;  // whole groups of lanes leave together
-    const K ke = sk[e];
-    uint32_t c = 0;
-    // lane l takes keys l, l + 16, ...: neighbouring lanes read neighbouring
-    // LDS words (no bank conflicts); eight reads in flight per batch
-    constexpr uint32_t R = 8;
-    uint32_t j = l;
-    for (; j + kRankLanes * (R - 1) < B; j += kRankLanes * R) {
-        K kj[R];
-#pragma unroll
-        for (uint32_t u = 0; u < R; ++u) kj[u] = sk[j + kRankLanes * u];
-#pragma unroll
-        for (uint32_t u = 0; u < R; ++u) {
-            const uint32_t jj = j + kRankLanes * u;
-            c += (kj[u] < ke || (kj[u] == ke && jj < e)) ? 1u : 0u;
-        }
-    }
-    for (; j < B; j += kRankLanes) {
-        const K kj = sk[j];
-        c += (kj < ke || (kj == ke && j < e)) ? 1u : 0u;
-    }
-#pragma unroll
-    for (uint32_t m = 1; m < kRankLanes; m <<= 1) c += __shfl_xor(c, static_cast<int>(m), 64);
-    if (l == 0) {
-        v.sk[c] = ke;
-        v.si[c] = e;
-    }
-}
 
 template <class K>
 __global__ __launch_bounds__(kSmallBlock) void k_small_prefix(Ins<K> v, const DevHeader* hdr,
@@ -759,7 +719,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_prefix(Ins<K> v, const De
     const uint32_t tid = threadIdx.x;
     uint32_t* s = reinterpret_cast<uint32_t*>(v.st);
     for (uint32_t i = tid; i < sizeof(InsState) / 4; i += blockDim.x) s[i] = 0;
-    // the pairs in (key, index) order, from k_small_rank
+    // the pairs in (key, index) order, from rank_sort_small
     for (uint32_t i = tid; i < B; i += blockDim.x) {
         sk[i] = v.sk[i];
         si[i] = v.si[i];
@@ -901,8 +861,7 @@ void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, cons
     const int H = height_bound(c.leaf_cap);
 
     if (B <= kSmallInsert) {
-        const uint32_t grank = static_cast<uint32_t>((B * kRankLanes + 255) / 256);
-        hipLaunchKernelGGL(k_small_rank<K>, dim3(grank), dim3(256), 0, s, v, keys, static_cast<uint32_t>(B));
+        rank_sort_small<K>(keys, static_cast<uint32_t>(B), v.sk, v.si, nullptr, 0, s);
         hipLaunchKernelGGL(k_small_prefix<K>, dim3(1), dim3(kSmallBlock), 0, s, v, t.hdr, keys, vals,
                            static_cast<uint32_t>(B), status);
         launch_locate<K>(t, v, c.cfg, B, status, s);

@@ -53,4 +53,18 @@ void launch_mirror_refresh_if(const TreeView<K>& t, const uint32_t* dirty, hipSt
 // Clear the device error word with a kernel (safe inside a captured graph).
 void launch_clear_error(DevHeader* h, hipStream_t s);
 
+// Workspace of a level-wise lookup batch: byte offsets of the two FIFOs
+// (per 64-query window a run-start mask, per query a node reference) and,
+// unless the batch arrives sorted, the sort buffers.
+struct LwLayout {
+    uint64_t ha, hb, ra, rb, sk, si, sk2, si2, tmp, total;
+};
+LwLayout lw_layout(uint64_t B, int key_bytes, bool presorted);
+
+// Level-wise lookup: sort the batch (unless presorted), then one kernel per
+// level for `levels` levels (at least the tree's height).
+template <class K>
+void launch_lookup_levelwise(const TreeView<K>& t, const K* keys, uint64_t B, bool presorted, uint32_t levels,
+                             K* vout, uint8_t* fout, void* ws, hipStream_t s);
+
 }  // namespace gt

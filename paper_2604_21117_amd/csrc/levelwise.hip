@@ -1,0 +1,212 @@
+// Level-wise batch lookup (paper Sections IV-A and IV-F).
+//
+// The paper walks a sorted batch through the tree one level at a time.  A
+// FIFO holds (node, number of queries) entries; each node is read once and
+// compared with the run of consecutive sorted queries that passes through
+// it, and the queries of that run that go to the same child form one entry
+// of the next level.  Here the batch is sorted by the library (or arrives
+// sorted from the caller), and each tree level is one kernel.
+//
+// The FIFO of a level is kept per window of 64 consecutive sorted queries.
+// A run never crosses a window boundary (the root's run is cut at every
+// window, and a child's run is a piece of its parent's), so each window's
+// entries are described by a 64-bit mask with bit p set where a run starts
+// at query p of the window, plus the node reference of each run stored at
+// its first query's position.  No counter, scan or atomic is needed to
+// append entries, and the order of the entries is the order of the keys.
+//
+//   * A wave serves a window, one lane per query.  The lane finds its run
+//     (the nearest run start at or below it), reads the run's node
+//     reference, and reads the node's key line with 16-byte loads.  All
+//     lanes of a run load the same addresses in the same instructions, so
+//     the memory system fetches the line once per run: the node is read
+//     once and compared with every query of its run, the queries in
+//     parallel rather than one after another as on the FPGA.
+//   * Where the child differs from the previous query's, a new run starts;
+//     its child reference and start bit go to the next level's FIFO.
+//   * At the leaf level each lane matches its query in the leaf's key line
+//     (read with the value line, once per run) and writes the result to the
+//     query's position in the caller's order.
+//
+// What differs from the FPGA design: the root's run is cut at every window
+// (so 256 CUs share the work); the root and the nodes near it are then read
+// once per window, from HBM once and from L2 after.  Unsorted queries still
+// get correct answers: runs are only cut more often.  The host launches one
+// kernel per level up to a bound on the height; a kernel whose level lies
+// below the leaves (per the device header) returns at once.
+#include "common.h"
+#include "kernels.h"
+#include "prims.h"
+#include "traverse.h"
+
+namespace gt {
+
+constexpr int kLwBlock = 256;
+constexpr int kLwWaves = kLwBlock / 64;
+constexpr uint32_t kLwWin = 64;                 // queries per window (one wave)
+constexpr uint32_t kLwGridMax = 2048;           // 8 resident workgroups per CU
+
+// One tree level over every window of the batch.  ROOT: each window is one
+// run through the root.  Otherwise the runs of window w start at the set bits
+// of hm_in[w], with their node references in ref_in at the runs' first
+// positions.  Every lane of a wave stays active through the level (the
+// cross-lane reads need their source lanes).
+template <class K, bool ROOT>
+__global__ __launch_bounds__(kLwBlock) void k_lw_level(TreeView<K> t, const K* __restrict__ qs,
+                                                        const uint32_t* __restrict__ qi, uint32_t B, uint32_t level,
+                                                        const uint64_t* __restrict__ hm_in,
+                                                        const uint32_t* __restrict__ ref_in,
+                                                        uint64_t* __restrict__ hm_out, uint32_t* __restrict__ ref_out,
+                                                        K* __restrict__ vout, uint8_t* __restrict__ fout) {
+    const uint32_t height = t.hdr->height;
+    if (level >= height) return;  // the whole grid: the tree has no such level
+    const bool leaves = level + 1 == height;
+    const bool empty = t.hdr->n_keys == 0;
+    const uint32_t root = t.hdr->root;
+    const int lane = lane_id();
+    const uint32_t nwin = (B + kLwWin - 1) / kLwWin;
+    const uint32_t waves = gridDim.x * kLwWaves;
+    for (uint32_t w = blockIdx.x * kLwWaves + threadIdx.x / 64; w < nwin; w += waves) {
+        const uint64_t w0 = static_cast<uint64_t>(w) * kLwWin;
+        const uint32_t nq = B - static_cast<uint32_t>(w0) < kLwWin ? B - static_cast<uint32_t>(w0) : kLwWin;
+        const bool valid = static_cast<uint32_t>(lane) < nq;
+        const K key = valid ? qs[w0 + lane] : K(0);
+        uint32_t ref = root;
+        if (!ROOT) {
+            // this query's run starts at the highest run start <= lane (a
+            // lane past the window's end takes the last run: every lane
+            // reads a real node of this level)
+            const uint64_t H = hm_in[w];
+            const uint64_t upto = lane < 63 ? (H & ((2ull << lane) - 1ull)) : H;
+            const uint32_t start = 63u - static_cast<uint32_t>(__builtin_clzll(upto | 1ull));
+            ref = ref_in[w0 + start];
+        }
+        if (leaves) {
+            const uint64_t line = static_cast<uint64_t>(ref & ~kLeafTag) * kSlots;
+            K lk[kSlots], lv[kSlots];
+            load_vec<K, kSlots>(t.lkeys + line, lk);
+            load_vec<K, kSlots>(t.lvals + line, lv);
+            // slots past the leaf's count repeat its last key, so the first
+            // equal slot is the key's own
+            uint32_t slot = kSlots;
+#pragma unroll
+            for (int j = kSlots - 1; j >= 0; --j)
+                if (lk[j] == key) slot = static_cast<uint32_t>(j);
+            K v = kmax<K>();
+#pragma unroll
+            for (int j = 0; j < kSlots; ++j)
+                if (slot == static_cast<uint32_t>(j)) v = lv[j];
+            const bool hit = slot < kSlots && !empty;
+            if (valid) {
+                const uint32_t o = qi ? qi[w0 + lane] : static_cast<uint32_t>(w0) + static_cast<uint32_t>(lane);
+                vout[o] = hit ? v : kmax<K>();
+                fout[o] = hit ? 1 : 0;  // a miss is all ones with found = 0 (Section IV-D)
+            }
+        } else {
+            K sep[kSlots];
+            load_vec<K, kSlots>(t.ikeys + static_cast<uint64_t>(ref) * kSlots, sep);
+            // child index = separators below the key ("key <= entry"
+            // routing); slot 15 is never a separator: it holds the first
+            // child reference of a node with consecutive children, else the
+            // largest key
+            uint32_t ci = 0;
+#pragma unroll
+            for (int j = 0; j < kFirstSlot; ++j) ci += sep[j] < key ? 1u : 0u;
+            const K first = sep[kFirstSlot];
+            uint32_t r;
+            if (first != kmax<K>()) r = static_cast<uint32_t>(first) + ci;
+            else r = t.ichild[static_cast<uint64_t>(ref) * kSlots + ci];
+            const uint32_t prev = shfl_u32(r, lane > 0 ? lane - 1 : 0);
+            const bool head = valid && (lane == 0 || r != prev);
+            const uint64_t Hn = __ballot(head);
+            if (head) ref_out[w0 + lane] = r;
+            if (lane == 0) hm_out[w] = Hn;
+        }
+    }
+}
+
+// Copy the batch into the sort buffers (key, position).
+template <class K>
+__global__ __launch_bounds__(256) void k_lw_stage(const K* __restrict__ keys, uint32_t B, K* __restrict__ sk,
+                                                  uint32_t* __restrict__ si) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < B) {
+        sk[i] = keys[i];
+        si[i] = i;
+    }
+}
+
+// ------------------------------------------------------------ host side
+
+static uint64_t lw_align(uint64_t x) { return (x + 255) / 256 * 256; }
+
+LwLayout lw_layout(uint64_t B, int key_bytes, bool presorted) {
+    LwLayout L{};
+    const uint64_t n = B ? B : 1;
+    const uint64_t nw = (n + kLwWin - 1) / kLwWin;
+    uint64_t o = 0;
+    L.ha = o;  o += lw_align(nw * 8);
+    L.hb = o;  o += lw_align(nw * 8);
+    L.ra = o;  o += lw_align(n * 4);
+    L.rb = o;  o += lw_align(n * 4);
+    if (!presorted) {
+        L.sk = o;  o += lw_align(n * key_bytes);
+        L.si = o;  o += lw_align(n * 4);
+        if (n > kRankSortMax) {
+            L.sk2 = o;  o += lw_align(n * key_bytes);
+            L.si2 = o;  o += lw_align(n * 4);
+            L.tmp = o;  o += lw_align(sort_tmp_bytes(n, key_bytes));
+        }
+    }
+    L.total = o;
+    return L;
+}
+
+template <class K>
+void launch_lookup_levelwise(const TreeView<K>& t, const K* keys, uint64_t B, bool presorted, uint32_t levels,
+                             K* vout, uint8_t* fout, void* ws, hipStream_t s) {
+    const LwLayout L = lw_layout(B, sizeof(K), presorted);
+    uint8_t* w = reinterpret_cast<uint8_t*>(ws);
+    uint64_t* ha = reinterpret_cast<uint64_t*>(w + L.ha);
+    uint64_t* hb = reinterpret_cast<uint64_t*>(w + L.hb);
+    uint32_t* ra = reinterpret_cast<uint32_t*>(w + L.ra);
+    uint32_t* rb = reinterpret_cast<uint32_t*>(w + L.rb);
+    const uint32_t b = static_cast<uint32_t>(B);
+    const K* qs = keys;
+    const uint32_t* qi = nullptr;
+    if (!presorted) {
+        K* sk = reinterpret_cast<K*>(w + L.sk);
+        uint32_t* si = reinterpret_cast<uint32_t*>(w + L.si);
+        if (B <= kRankSortMax) {
+            rank_sort_small<K>(keys, b, sk, si, nullptr, 0, s);
+        } else {
+            hipLaunchKernelGGL(k_lw_stage<K>, dim3((b + 255) / 256), dim3(256), 0, s, keys, b, sk, si);
+            sort_pairs<K>(sk, si, reinterpret_cast<K*>(w + L.sk2), reinterpret_cast<uint32_t*>(w + L.si2), B,
+                          w + L.tmp, s);
+        }
+        qs = sk;
+        qi = si;
+    }
+    const uint64_t nwin = (B + kLwWin - 1) / kLwWin;
+    const uint64_t wgs = (nwin + kLwBlock / 64 - 1) / (kLwBlock / 64);
+    const uint32_t grid = static_cast<uint32_t>(wgs < kLwGridMax ? wgs : kLwGridMax);
+    for (uint32_t l = 0; l < levels; ++l) {
+        const uint64_t* hin = (l & 1) ? ha : hb;
+        const uint32_t* rin = (l & 1) ? ra : rb;
+        uint64_t* hout = (l & 1) ? hb : ha;
+        uint32_t* rout = (l & 1) ? rb : ra;
+        if (l == 0)
+            hipLaunchKernelGGL((k_lw_level<K, true>), dim3(grid), dim3(kLwBlock), 0, s, t, qs, qi, b, l, hin, rin,
+                               hout, rout, vout, fout);
+        else
+            hipLaunchKernelGGL((k_lw_level<K, false>), dim3(grid), dim3(kLwBlock), 0, s, t, qs, qi, b, l, hin,
+                               rin, hout, rout, vout, fout);
+    }
+}
+
+template void launch_lookup_levelwise<uint32_t>(const TreeView<uint32_t>&, const uint32_t*, uint64_t, bool,
+                                                uint32_t, uint32_t*, uint8_t*, void*, hipStream_t);
+template void launch_lookup_levelwise<uint64_t>(const TreeView<uint64_t>&, const uint64_t*, uint64_t, bool,
+                                                uint32_t, uint64_t*, uint8_t*, void*, hipStream_t);
+
+}  // namespace gt

@@ -82,6 +82,17 @@ __device__ __forceinline__ void block_scan_small(const uint32_t* in, uint32_t* o
 
 // ------------------------------------------------------------ host side
 
+// Largest batch rank_sort_small takes (all keys sit in each workgroup's LDS).
+constexpr uint32_t kRankSortMax = 2048;
+
+// Stable sort of B <= kRankSortMax keys by rank: sk[r] = keys[i] and
+// si[r] = i, where r is the number of pairs (keys[j], j) before (keys[i], i)
+// in (key, index) order.  If `zero` is given, its first `zero_words` words
+// are cleared by the first workgroup (a free ride for the caller's counters).
+template <class K>
+void rank_sort_small(const K* keys, uint32_t B, K* sk, uint32_t* si, uint32_t* zero, uint32_t zero_words,
+                     hipStream_t s);
+
 // Scratch bytes needed by scan_exclusive for up to n elements.
 uint64_t scan_tmp_bytes(uint64_t n);
 

@@ -251,6 +251,64 @@ void sort_pairs(K* keys, uint32_t* idx, K* keys_alt, uint32_t* idx_alt, uint64_t
     // sizeof(K) passes is even, so the result is back in keys/idx
 }
 
+// ------------------------------------------------------------ rank sort
+//
+// Every workgroup holds all B keys in LDS and 16 lanes share one element's
+// count, so the B^2 comparisons spread over B / 16 CUs instead of the one
+// CU a workgroup-local sort would use.
+constexpr uint32_t kRankLanes = 16;  // lanes sharing one element's count
+
+template <class K>
+__global__ __launch_bounds__(256) void k_rank_sort(const K* __restrict__ keys, uint32_t B, K* __restrict__ osk,
+                                                   uint32_t* __restrict__ osi, uint32_t* zero, uint32_t zero_words) {
+    __shared__ K sk[kRankSortMax];
+    if (zero && blockIdx.x == 0)
+        for (uint32_t i = threadIdx.x; i < zero_words; i += blockDim.x) zero[i] = 0;
+    for (uint32_t i = threadIdx.x; i < B; i += blockDim.x) sk[i] = keys[i];
+    __syncthreads();
+    const uint32_t e = (blockIdx.x * blockDim.x + threadIdx.x) / kRankLanes, l = threadIdx.x % kRankLanes;
+    if (e >= B) return;  // whole groups of lanes leave together
+    const K ke = sk[e];
+    uint32_t c = 0;
+    // lane l takes keys l, l + 16, ...: neighbouring lanes read neighbouring
+    // LDS words (no bank conflicts); eight reads in flight per batch
+    constexpr uint32_t R = 8;
+    uint32_t j = l;
+    for (; j + kRankLanes * (R - 1) < B; j += kRankLanes * R) {
+        K kj[R];
+#pragma unroll
+        for (uint32_t u = 0; u < R; ++u) kj[u] = sk[j + kRankLanes * u];
+#pragma unroll
+        for (uint32_t u = 0; u < R; ++u) {
+            const uint32_t jj = j + kRankLanes * u;
+            c += (kj[u] < ke || (kj[u] == ke && jj < e)) ? 1u : 0u;
+        }
+    }
+    for (; j < B; j += kRankLanes) {
+        const K kj = sk[j];
+        c += (kj < ke || (kj == ke && j < e)) ? 1u : 0u;
+    }
+#pragma unroll
+    for (uint32_t m = 1; m < kRankLanes; m <<= 1) c += __shfl_xor(c, static_cast<int>(m), 64);
+    if (l == 0) {
+        osk[c] = ke;
+        osi[c] = e;
+    }
+}
+
+template <class K>
+void rank_sort_small(const K* keys, uint32_t B, K* sk, uint32_t* si, uint32_t* zero, uint32_t zero_words,
+                     hipStream_t s) {
+    const uint32_t grid = (B * kRankLanes + 255) / 256;
+    hipLaunchKernelGGL(k_rank_sort<K>, dim3(grid < 1 ? 1 : grid), dim3(256), 0, s, keys, B, sk, si, zero,
+                       zero_words);
+}
+
+template void rank_sort_small<uint32_t>(const uint32_t*, uint32_t, uint32_t*, uint32_t*, uint32_t*, uint32_t,
+                                        hipStream_t);
+template void rank_sort_small<uint64_t>(const uint64_t*, uint32_t, uint64_t*, uint32_t*, uint32_t*, uint32_t,
+                                        hipStream_t);
+
 template void sort_pairs<uint32_t>(uint32_t*, uint32_t*, uint32_t*, uint32_t*, uint64_t, void*, hipStream_t);
 template void sort_pairs<uint64_t>(uint64_t*, uint32_t*, uint64_t*, uint32_t*, uint64_t, void*, hipStream_t);
 

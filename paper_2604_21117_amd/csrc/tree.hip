@@ -79,6 +79,19 @@ std::vector<uint64_t> level_sizes_for(uint64_t n, double fill) {
 // at least 8 children
 uint64_t inner_cap_for(uint64_t leaves) { return leaves / 7 + 2 * kMaxLevels; }
 
+// Largest height a tree with at most `leaf_cap` leaves can have: a non-root
+// inner node has at least 8 children and an inner root at least 2, so a tree
+// of height h >= 2 has at least 2 * 8^(h-2) leaves.
+uint32_t height_cap(uint64_t leaf_cap) {
+    uint32_t h = 1;
+    uint64_t need = 2;  // leaves a tree of height h + 1 needs at least
+    while (need <= leaf_cap && h < static_cast<uint32_t>(kMaxLevels)) {
+        ++h;
+        need *= 8;
+    }
+    return h;
+}
+
 uint64_t fixed_bytes(int kb, uint64_t max_batch, uint64_t leaf_cap) {
     return align_up(sizeof(DevHeader)) + mirror_bytes(kb) +
            align_up(insert_scratch_bytes(max_batch, kb, leaf_cap, inner_cap_for(leaf_cap)));
@@ -178,6 +191,7 @@ gt_status build_t(gt_tree* t, const void* keys, const void* values, uint64_t n, 
         TreeView<K> v = view<K>(t);
         launch_build<K>(v, sk, sv, n, sizes.data(), static_cast<int>(sizes.size()), maxbuf, s);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) st = GT_ERR_HIP;
+        t->h_bound = static_cast<uint32_t>(sizes.size());
     } while (0);
     hipStreamSynchronize(s);
     hipFree(tmp);
@@ -261,6 +275,31 @@ gt_status tree_lookup_batch(gt_tree* t, const void* keys, uint64_t B, void* valu
     return hipGetLastError() == hipSuccess ? GT_OK : GT_ERR_HIP;
 }
 
+uint64_t tree_lookup_levelwise_workspace_bytes(const gt_tree* t, uint64_t B, uint32_t flags) {
+    if (!t || (flags & ~GT_LW_PRESORTED) != 0) return 0;
+    return lw_layout(B, t->kb, (flags & GT_LW_PRESORTED) != 0).total;
+}
+
+gt_status tree_lookup_levelwise(gt_tree* t, const void* keys, uint64_t B, uint32_t flags, void* values_out,
+                                uint8_t* found_out, void* workspace, uint64_t workspace_bytes, hipStream_t stream) {
+    if (!t) return GT_ERR_INVALID;
+    if ((flags & ~GT_LW_PRESORTED) != 0) return GT_ERR_INVALID;
+    if (B == 0) return GT_OK;
+    if (!keys || !values_out || !found_out || !workspace) return GT_ERR_INVALID;
+    if (B >= (1ull << 31)) return GT_ERR_INVALID;
+    const bool presorted = (flags & GT_LW_PRESORTED) != 0;
+    if (workspace_bytes < lw_layout(B, t->kb, presorted).total) return GT_ERR_CAPACITY;
+    if (t->kb == 8)
+        launch_lookup_levelwise<uint64_t>(view<uint64_t>(t), reinterpret_cast<const uint64_t*>(keys), B,
+                                          presorted, t->h_bound, reinterpret_cast<uint64_t*>(values_out),
+                                          found_out, workspace, stream);
+    else
+        launch_lookup_levelwise<uint32_t>(view<uint32_t>(t), reinterpret_cast<const uint32_t*>(keys), B,
+                                          presorted, t->h_bound, reinterpret_cast<uint32_t*>(values_out),
+                                          found_out, workspace, stream);
+    return hipGetLastError() == hipSuccess ? GT_OK : GT_ERR_HIP;
+}
+
 gt_status tree_range_batch(gt_tree* t, const void* lo, const void* hi, const uint32_t* max_out,
                            const uint64_t* out_offsets, uint64_t B, void* out_keys, void* out_values,
                            uint32_t* count_out, hipStream_t stream) {
@@ -299,6 +338,9 @@ gt_status tree_insert_batch(gt_tree* t, const void* keys, const void* values, ui
     else
         launch_insert<uint32_t>(view<uint32_t>(t), c, reinterpret_cast<const uint32_t*>(keys),
                                 reinterpret_cast<const uint32_t*>(values), B, status_out, stream);
+    // the batch may grow the tree on the device; the host keeps a bound
+    const uint32_t hc = height_cap(t->leaf_cap);
+    if (hc > t->h_bound) t->h_bound = hc;
     return hipGetLastError() == hipSuccess ? GT_OK : GT_ERR_HIP;
 }
 
