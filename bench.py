@@ -22,6 +22,10 @@ Also measured in the same run, outside the K timed steps:
                   key sequence), plain and learned
   large_batch     2^20-key lookup batches, warm and cold (a 2 GiB flush before
                   each cold launch; `--no-cold` skips them)
+  latency_regime  lognormal and clustered keys (2^16, 2^24), half absent:
+                  single-launch latency at B = 1..1024 on the full GPU and on
+                  a stream masked to 8 CUs (one per XCD); `--no-latency`
+                  skips it
   levelwise       the paper's level-by-level walk of a sorted batch against
                   the per-query descent, B = 1024, 2^15, 2^20, uniform and
                   Zipf keys, in random order and sorted
@@ -115,6 +119,22 @@ def cpu_baseline(keys, vals, batches, threads, budget_s=10.0):
                       f"(2^{N_LOG2} keys), each batch split evenly over {threads} threads, {dt:.1f} s"}
 
 
+def cu_masked_stream(cus):
+    """A HIP stream restricted to the CUs whose mask bits are given (bit i
+    of the mask selects a CU of XCD i mod 8 on MI355X).  Default priority."""
+    import ctypes as C
+    hip = C.CDLL("libamdhip64.so")
+    hip.hipExtStreamCreateWithCUMask.argtypes = [C.POINTER(C.c_void_p), C.c_uint32, C.POINTER(C.c_uint32)]
+    mask = (C.c_uint32 * 8)()
+    for b in cus:
+        mask[b // 32] |= 1 << (b % 32)
+    h = C.c_void_p()
+    rc = hip.hipExtStreamCreateWithCUMask(C.byref(h), 8, mask)
+    if rc != 0:
+        raise RuntimeError(f"hipExtStreamCreateWithCUMask returned {rc}")
+    return h
+
+
 class Timer:
     """HIP events recorded on the stream the work is launched on."""
 
@@ -144,6 +164,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cold", action="store_true", help="skip the flushed (cold-cache) 2^20 batches")
+    ap.add_argument("--no-latency", action="store_true",
+                    help="skip the latency regime (lognormal / clustered keys, full GPU and 8 CUs)")
     ap.add_argument("--log2n", type=int, default=N_LOG2)
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection mode: a 1 GiB device copy (calibration) and three 2^20-key "
@@ -423,6 +445,63 @@ def main():
             del ws, wsp, qdn, qds
     print("[bench] level-wise done", file=sys.stderr, flush=True)
 
+    # ---- latency regime: lognormal and clustered keys (2^16 and 2^24), half
+    # present and half absent queries, B = 1, 2, 4, ..., 1024 and 1000;
+    # single-launch latency (HIP events, IQM of 100) on the full GPU and on a
+    # stream masked to 8 CUs, one per XCD (the runtime refuses a mask that
+    # leaves an XCD without CUs, so 8 CUs of one XCD cannot be asked for)
+    latency = None
+    if not args.no_latency:
+        cu8_handle = cu_masked_stream(range(8))
+        cu8 = torch.cuda.ExternalStream(cu8_handle.value)
+        contexts = {"full": stream, "cu8": cu8}
+        latency = {"contexts": {"full": "all 256 CUs", "cu8": "CU-mask bits 0-7: one CU on each of the 8 XCDs"},
+                   "queries": "50 % present, 50 % absent", "reps": 100, "stat": "IQM of single-launch HIP-event time"}
+        for lg in (16, 24):
+            for dist in ("lognormal", "clustered"):
+                kk = synth.lognormal_keys(1 << lg, 3) if dist == "lognormal" else synth.clustered_keys(1 << lg, 3)
+                vv = synth.values_for(kk, 3, 64)
+                kset = np.sort(kk)
+                tl = g.Tree(kk, vv, 8, max_batch=1024)
+                ll = g.Learned(tl, models=1024 if lg == 24 else 256)
+                ll.train()
+                rows = {}
+                for b in [1 << i for i in range(11)] + [1000]:
+                    q = synth.mixed_queries(kk, b, 3 + b, 64)
+                    present = np.isin(q, kset)
+                    qd3 = tl.dev(q)
+                    v5 = torch.empty(b, dtype=torch.int64, device=dev)
+                    f5 = torch.empty(b, dtype=torch.uint8, device=dev)
+                    row = {}
+                    for cname, cs in contexts.items():
+                        tm = Timer(torch, cs)
+                        cell = {}
+                        for path in ("plain", "learned"):
+                            if path == "plain":
+                                fn = lambda: g.tree_lookup_batch(tl.h, qd3, v5, f5, cs)
+                            else:
+                                fn = lambda: g.li_lookup_batch(ll.h, qd3, v5, f5, cs)
+                            ts = tm.run(fn, 104, skip=4)
+                            got_f = g.to_numpy(f5).astype(bool)
+                            got_v = g.to_numpy(v5, np.uint64)
+                            assert np.array_equal(got_f, present) and np.array_equal(
+                                got_v[present], synth.values_for(q[present], 3, 64)), (dist, lg, b, cname, path)
+                            cell[path] = round(iqm(ts), 3)
+                        row[cname] = cell
+                    rows[str(b)] = row
+                ls = ll.stats()
+                latency[f"{dist}_2^{lg}"] = {
+                    "height": tl.stats()["height"], "by_batch_us": rows,
+                    "learned": {"models": ls["models"], "tree_models": ls["tree_models"], "declined": ls["declined"],
+                                "mean_window": round(ls["mean_window"], 2), "max_window": ls["max_window"],
+                                "fallback_rate": round(ls["fallbacks"] / max(1, ls["lookups"]), 4)}}
+                ll.close()
+                tl.close()
+        cu8.synchronize()
+        import ctypes as C
+        C.CDLL("libamdhip64.so").hipStreamDestroy(cu8_handle)
+        print("[bench] latency regime done", file=sys.stderr, flush=True)
+
     # ---- range batches
     lo, hi, mc = synth.range_starts_and_lengths(keys, B, SEED, 100)
     off = np.zeros(B, dtype=np.uint64)
@@ -530,7 +609,8 @@ def main():
                    "keys": n, "batch": B, "height": st["height"], "path": args.path,
                    "learned_models": lst["models"], "learned_linear": lst["linear_models"],
                    "learned_mlp": lst["mlp_models"], "learned_tree": lst["tree_models"],
-                   "learned_mean_window": round(lst["mean_window"], 2), "learned_max_window": lst["max_window"]},
+                   "learned_mean_window": round(lst["mean_window"], 2), "learned_max_window": lst["max_window"],
+                   "learned_declined": lst["declined"]},
         "submission": f"HIP graph replays of {GR} steps over {nbatch} distinct batches",
         "other_path": {"path": "plain" if args.path == "learned" else "learned", "value": round(other_value, 3),
                        "ms_per_step": round(other_elapsed * 1e3 / args.steps, 6)},
@@ -545,6 +625,7 @@ def main():
         "size_sweep_b1024": size_sweep,
         "large_batch": large,
         "levelwise": levelwise,
+        "latency_regime": latency,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_lookup<unsigned long, 8, 4, 2, true, false> (B=2^20, warm)",

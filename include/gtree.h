@@ -251,9 +251,17 @@ typedef struct {
     uint32_t search;      /* window search: 1 = through the fence directory;
                              2 = read the window's leaves directly when the
                              trained directory is the identity (a bulk-loaded
-                             tree); 0 = default: direct for batches up to
-                             2^13 keys on such a tree, else the directory     */
-    uint32_t reserved[3]; /* must be 0                                        */
+                             tree) and the window spans at most 8 leaves
+                             (wider windows use the directory); 0 = default:
+                             as 2 for batches up to 2^13 keys, else 1         */
+    uint32_t gate;        /* 0 = default: after training, if more than a
+                             quarter of the keys go down the tree or the
+                             key-weighted mean window exceeds 16 leaves, the
+                             models cannot beat the tree's descent and
+                             li_lookup_batch runs tree_lookup_batch instead
+                             (same results; li_stats reports `declined`);
+                             1 = always take the model path                  */
+    uint32_t reserved[2]; /* must be 0                                        */
 } gt_li_params;
 
 typedef struct {
@@ -264,7 +272,8 @@ typedef struct {
     uint32_t models, linear_models, mlp_models, tree_models;
                               /* tree_models: every key goes down the tree   */
     uint32_t max_window;      /* widest window (leaves) of a piece in use    */
-    uint32_t reserved;
+    uint32_t declined;        /* 1: the quality gate sends lookups to the
+                                 tree (see gt_li_params.gate)                */
     double mean_window;       /* window per trained key, averaged over keys  */
 } gt_li_stats;
 

@@ -49,14 +49,14 @@ class gt_tree_stats(C.Structure):
 
 class gt_li_params(C.Structure):
     _fields_ = [("models", C.c_uint32), ("kind", C.c_uint32), ("max_window", C.c_uint32), ("search", C.c_uint32),
-                ("reserved", C.c_uint32 * 3)]
+                ("gate", C.c_uint32), ("reserved", C.c_uint32 * 2)]
 
 
 class gt_li_stats(C.Structure):
     _fields_ = [("trained_leaves", C.c_uint64), ("trained_keys", C.c_uint64), ("lookups", C.c_uint64),
                 ("fallbacks", C.c_uint64), ("models", C.c_uint32), ("linear_models", C.c_uint32),
                 ("mlp_models", C.c_uint32), ("tree_models", C.c_uint32), ("max_window", C.c_uint32),
-                ("reserved", C.c_uint32), ("mean_window", C.c_double)]
+                ("declined", C.c_uint32), ("mean_window", C.c_double)]
 
 
 class gt_srv_params(C.Structure):
@@ -257,8 +257,8 @@ def tree_export(h, stream=None) -> np.ndarray:
     return buf
 
 
-def li_params(models: int = 0, kind: int = 0, max_window: int = 0, search: int = 0) -> gt_li_params:
-    return gt_li_params(models=models, kind=kind, max_window=max_window, search=search)
+def li_params(models: int = 0, kind: int = 0, max_window: int = 0, search: int = 0, gate: int = 0) -> gt_li_params:
+    return gt_li_params(models=models, kind=kind, max_window=max_window, search=search, gate=gate)
 
 
 def li_arena_bytes(h, params: gt_li_params) -> int:
@@ -398,10 +398,11 @@ class Tree:
 class Learned:
     """A learned index over a :class:`Tree` (owns its arena tensor)."""
 
-    def __init__(self, tree: Tree, models: int = 0, kind: int = 0, max_window: int = 0, search: int = 0):
+    def __init__(self, tree: Tree, models: int = 0, kind: int = 0, max_window: int = 0, search: int = 0,
+                 gate: int = 0):
         torch = _torch()
         self.tree = tree
-        self.params = li_params(models, kind, max_window, search)
+        self.params = li_params(models, kind, max_window, search, gate)
         n = li_arena_bytes(tree.h, self.params)
         if n == 0:
             raise GtError(GT_ERR_INVALID, "li_arena_bytes")

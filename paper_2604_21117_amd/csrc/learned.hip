@@ -63,6 +63,9 @@ constexpr int kLiBlock = 256;
 constexpr uint32_t kKindLinear = 0, kKindMlp = 1, kKindTree = 2;
 constexpr int kFitPoints = 4096;                  // points per model for the network fit
 constexpr int kDirect = 4;                        // leaves a group reads at once on the direct path
+constexpr int32_t kDirectMaxWin = 2 * kDirect;    // wider windows take the fence directory instead
+constexpr double kGateTreeShare = 0.25;           // decline: more of the keys go down the tree than this
+constexpr double kGateMeanWindow = 16.0;          // decline: a wider key-weighted mean window (leaves)
 constexpr uint64_t kDirectMaxBatch = 1ull << 13;   // default: direct window reads up to this batch
 constexpr uint64_t kSmallLookup = 1ull << 13;      // batches up to this size use 64-thread workgroups
 
@@ -75,7 +78,9 @@ struct LiHeader {
     unsigned long long lookups, fallbacks;
     uint32_t trained;
     uint32_t epoch;      // tree epoch at training
-    uint32_t pad[48];
+    unsigned long long keys_tree;    // trained keys whose piece sends them down the tree
+    unsigned long long window_sum;   // sum over the other keys of their piece's window (leaves)
+    uint32_t pad[44];
 };
 static_assert(sizeof(LiHeader) == 256, "LiHeader size");
 
@@ -565,6 +570,42 @@ __global__ __launch_bounds__(256) void k_choose(LiView<K> li, uint32_t M, uint32
     }
 }
 
+// Model quality over the trained keys (one workgroup): keys whose piece
+// sends them down the tree, and the key-weighted window of the others.
+constexpr int kQualityBlock = 1024;
+
+template <class K>
+__global__ __launch_bounds__(kQualityBlock) void k_quality(LiView<K> li, uint32_t cells) {
+    __shared__ unsigned long long sh[2][kQualityBlock / 64];
+    unsigned long long tree = 0, wsum = 0;
+    for (uint32_t c = threadIdx.x; c < cells; c += kQualityBlock) {
+        const uint32_t n = li.cnt[c];
+        const Piece p = li.piece[c];
+        if (n == 0) continue;
+        if (p.lo > p.hi) tree += n;
+        else wsum += static_cast<unsigned long long>(n) * static_cast<unsigned long long>(p.hi - p.lo + 1);
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        tree += __shfl_xor(tree, d, 64);
+        wsum += __shfl_xor(wsum, d, 64);
+    }
+    const int w = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][w] = tree;
+        sh[1][w] = wsum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = 0, b = 0;
+        for (int i = 0; i < kQualityBlock / 64; ++i) {
+            a += sh[0][i];
+            b += sh[1][i];
+        }
+        li.hdr->keys_tree = a;
+        li.hdr->window_sum = b;
+    }
+}
+
 __global__ void k_identity(const uint32_t* pos_of_leaf, uint32_t n, uint32_t* flag) {
     for (uint64_t i = gid(); i < n; i += gsz())
         if (pos_of_leaf[i] != i) *flag = 0u;
@@ -671,7 +712,13 @@ __global__ __launch_bounds__(BLK) void k_li_lookup(TreeView<K> t, LiView<K> li, 
         if (!fb) {
             const int32_t p = piece_pos(e.slope, e.icpt, e.base, r.x, a.L);
             const int32_t wl = max(p + e.lo, 0), wh = min(p + e.hi, last_pos);
-            if constexpr (DIRECT) {
+            // a narrow window on a bulk-loaded tree reads its leaves directly
+            // (at most two rounds); a wider one searches the fence directory
+            // (32 fences a round, then one leaf), which costs about as much as
+            // the tree's own descent instead of growing with the window
+            bool direct = false;
+            if constexpr (DIRECT) direct = wh - wl < kDirectMaxWin;
+            if (direct) {
                 // positions are leaf ids: read kDirect of the window's leaves at
                 // once; each lane checks its own slots (no cross-lane work
                 // until one lane holds the key)
@@ -776,6 +823,7 @@ struct gt_learned {
     uint64_t off_fit, off_piece, off_dir, off_nxt0, off_nxt1, off_rank0, off_rank1, off_pos, off_start, off_bnd,
         off_cnt, off_partial, off_ident;
     LiArgs args;
+    bool declined = false;    // the quality gate sends lookups to the tree kernel
     uint64_t generation = 0;  // bumped whenever the lookup's arguments or tables change
 };
 
@@ -788,8 +836,8 @@ uint64_t al256(uint64_t x) { return (x + 255) / 256 * 256; }
 uint32_t models_of(const gt_li_params* p) { return p && p->models ? p->models : 1024u; }
 
 bool params_bad(const gt_li_params* p) {
-    return p && (p->models > 4096 || p->kind > 2 || p->search > 2 || p->reserved[0] || p->reserved[1] ||
-                 p->reserved[2]);
+    return p && (p->models > 4096 || p->kind > 2 || p->search > 2 || p->gate > 1 || p->reserved[0] ||
+                 p->reserved[1]);
 }
 
 uint64_t layout_li(gt_learned* li, uint64_t leaf_cap, uint32_t M, int kb) {
@@ -864,6 +912,7 @@ gt_status train_t(gt_learned* li, hipStream_t s) {
         LI_HIP(hipMemsetAsync(v.hdr, 0, sizeof(LiHeader), s));
         LI_HIP(hipStreamSynchronize(s));
         li->trained = false;
+        li->declined = false;
         li->generation++;
         return GT_OK;
     }
@@ -903,6 +952,7 @@ gt_status train_t(gt_learned* li, hipStream_t s) {
     hipLaunchKernelGGL(k_choose<K>, dim3(grid_of(static_cast<uint64_t>(M) * 64, 256)), dim3(256), 0, s, v, M,
                        li->p.kind, mw);
     hipLaunchKernelGGL(k_li_finish<K>, dim3(1), dim3(64), 0, s, v, dh.n_keys);
+    hipLaunchKernelGGL(k_quality<K>, dim3(1), dim3(kQualityBlock), 0, s, v, static_cast<uint32_t>(cells));
     const uint32_t one = 1;
     LI_HIP(hipMemcpyAsync(v.identity, &one, 4, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_identity, dim3(grid_of(n, 256)), dim3(256), 0, s, v.pos_of_leaf, n, v.identity);
@@ -922,6 +972,14 @@ gt_status train_t(gt_learned* li, hipStream_t s) {
     li->args.exact = 1;
     li->args.pad = 0;
     li->trained = true;
+    // quality gate: when many keys would go down the tree after the model
+    // step, or the windows are wide, the model path costs more than the
+    // tree's own descent; lookups then take the tree (same results)
+    const double keys = static_cast<double>(h.n_keys);
+    const double in_win = keys - static_cast<double>(h.keys_tree);
+    const double mean_win = in_win > 0 ? static_cast<double>(h.window_sum) / in_win : 0.0;
+    li->declined = li->p.gate == 0 &&
+                   (static_cast<double>(h.keys_tree) > kGateTreeShare * keys || mean_win > kGateMeanWindow);
     li->generation++;
     return GT_OK;
 }
@@ -991,7 +1049,7 @@ gt_status li_lookup_batch(gt_learned* li, const void* keys, uint64_t B, void* va
     if (!li) return GT_ERR_INVALID;
     if (B == 0) return GT_OK;
     if (!keys || !values_out || !found_out) return GT_ERR_INVALID;
-    if (!li->trained) return tree_lookup_batch(li->t, keys, B, values_out, found_out, stream);
+    if (!li->trained || li->declined) return tree_lookup_batch(li->t, keys, B, values_out, found_out, stream);
     if (li->t->kb == 8) launch_li_lookup<uint64_t>(li, keys, B, values_out, found_out, stream);
     else launch_li_lookup<uint32_t>(li, keys, B, values_out, found_out, stream);
     return hipGetLastError() == hipSuccess ? GT_OK : GT_ERR_HIP;
@@ -1060,6 +1118,7 @@ gt_status li_stats(gt_learned* li, gt_li_stats* out, hipStream_t stream) {
         if (w > out->max_window) out->max_window = w;
     }
     out->mean_window = ksum > 0 ? wsum / ksum : 0.0;
+    out->declined = li->declined ? 1u : 0u;
     return GT_OK;
 }
 

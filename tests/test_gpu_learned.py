@@ -62,7 +62,9 @@ def test_learned_parity_and_bounds(width, dist, search):
     vals = synth.values_for(keys, seed, width)
     sa = oracle.SortedArray(keys, vals, width)
     t = mk_tree(keys, vals, width // 8, leaf_slack=1 << 14, max_batch=1 << 14)
-    li = _learned(t, models=256, search=search)
+    # gate=1: the model path runs even where the quality gate would decline
+    li = _learned(t, models=256, search=search, gate=1)
+    assert li.stats()["declined"] == 0
     frac_used = _check_bounds(t, li)
     # keys in pieces with bounds (the rest walk the tree): uniform keys are
     # the model's workload; on clustered keys the uniform knot grid cannot
@@ -87,7 +89,7 @@ def test_kinds(kind):
     vals = synth.values_for(keys, seed, width)
     sa = oracle.SortedArray(keys, vals, width)
     t = mk_tree(keys, vals, 8, max_batch=4096)
-    li = _learned(t, models=128, kind=kind, max_window=256)
+    li = _learned(t, models=128, kind=kind, max_window=256, gate=1)
     st = li.stats()
     if kind == 1:
         assert st["mlp_models"] == 0
@@ -95,6 +97,34 @@ def test_kinds(kind):
         assert st["linear_models"] == 0 or st["mlp_models"] > 0
     _check_bounds(t, li)
     _li_parity(li, sa, synth.mixed_queries(keys, 30000, seed, width))
+
+
+@pytest.mark.parametrize("dist", ["uniform", "lognormal", "clustered"])
+def test_quality_gate(dist):
+    """With the default gate an index whose models send many keys down the
+    tree, or have wide windows, declines: lookups run the tree kernel (the
+    model's counters do not move) and stay exact; uniform keys keep the
+    model path.  gate=1 keeps the model path everywhere."""
+    seed, width, n = 49, 64, 1 << 18
+    keys = {"uniform": lambda: synth.uniform_keys(n, seed, width),
+            "lognormal": lambda: synth.lognormal_keys(n, seed),
+            "clustered": lambda: synth.clustered_keys(n, seed)}[dist]()
+    vals = synth.values_for(keys, seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, 8, max_batch=4096)
+    q = synth.mixed_queries(keys, 5000, seed, width)
+    for gate in (0, 1):
+        li = _learned(t, models=1024, gate=gate)
+        st = li.stats()
+        keys_tree_share = 1.0 - _check_bounds(t, li)
+        expect = gate == 0 and (keys_tree_share > 0.25 or st["mean_window"] > 16.0)
+        assert st["declined"] == (1 if expect else 0), (dist, gate, keys_tree_share, st["mean_window"])
+        l0 = st["lookups"]
+        _li_parity(li, sa, q)
+        assert li.stats()["lookups"] - l0 == (0 if expect else len(q))
+        if dist == "uniform":
+            assert st["declined"] == 0
+        li.close()
 
 
 def test_forced_fallback_stays_exact():
