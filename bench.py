@@ -34,8 +34,11 @@ Also measured in the same run, outside the K timed steps:
   insert          fresh-key insert batches, B = 1024 and 2^20
   range           range batches, B = 1024, max U{1..100}
   learned_stale   learned lookups after the inserts, then after retraining
-  serving         2000 batches B ~ U{1..1024}, 80/15/5 lookup/insert/range,
-                  Zipf keys, Poisson arrivals at half the closed-loop rate
+  serving         2^26 resident keys; batches B ~ U{1..1024}, 80/15/5
+                  lookup/insert/range, Zipf keys; closed loop, then Poisson
+                  arrivals at 0.25/0.5/0.75/0.9 of its rate (20,000 batches
+                  each); plain tree and learned index; p50/p99 and the
+                  device-busy fraction
   cpu_baseline    the oracle's pointer B+-tree on the host cores
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -164,6 +167,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cold", action="store_true", help="skip the flushed (cold-cache) 2^20 batches")
+    ap.add_argument("--serve-log2n", type=int, default=26, help="keys of the serving tree (log2)")
+    ap.add_argument("--serve-batches", type=int, default=20000, help="batches per open-loop serving run")
     ap.add_argument("--no-latency", action="store_true",
                     help="skip the latency regime (lognormal / clustered keys, full GPU and 8 CUs)")
     ap.add_argument("--log2n", type=int, default=N_LOG2)
@@ -555,31 +560,80 @@ def main():
                  "retrain_s": round(retrain_s, 3), "retrained_us": round(fresh_us, 3),
                  "retrained_fallback_rate": round(fresh_fb, 4), "plain_us": round(plain_mix_us, 3)}
 
-    # ---- serving: closed loop for the saturation rate, then open loop at half
+    # ---- serving: 2^26 resident uniform keys (seed 5), batches B ~ U{1..1024}
+    # of 80 % lookups / 15 % inserts of fresh keys / 5 % ranges (max
+    # U{1..100}), lookup keys and range starts Zipf(0.99) over the present
+    # keys.  Per path (plain tree, learned index): a closed-loop run gives the
+    # saturation rate, then open-loop Poisson arrivals at 0.25 / 0.5 / 0.75 /
+    # 0.9 of it, `--serve-batches` batches per run, the first 1000 not
+    # counted in the latency percentiles.  The learned index is retrained
+    # before each run (each run inserts about 1.5 M keys).
     serving = None
     if not args.no_serve:
-        skeys_now = np.concatenate([keys, fresh[:64 * B + BL]])
-        sfresh = synth.uniform_keys(400000, SEED + 9, 64, purpose=synth.P_INSERT, exclude=skeys_now)
-        spec = synth.serving_mix(keys, 2000, SEED, bmax=1024, zipf=zipf, fresh=sfresh)
-        srv = g.Server(tree, learned=li, slots=16, read_streams=4)
-        batches = [g.Batch(op, k, v, m, 0.0) for (op, k, v, m, _) in spec[:1000]]
-        assert srv.replay(batches) == g.GT_OK
-        sat = srv.stats()
-        lam = 0.5 * sum(sat["done"]) / sat["wall_s"]
-        spec2 = synth.serving_mix(keys, 2000, SEED + 1, bmax=1024, rate=lam, zipf=zipf, fresh=sfresh[200000:])
-        batches = [g.Batch(op, k, v, m, a) for (op, k, v, m, a) in spec2]
-        assert srv.replay(batches) == g.GT_OK
-        ss = srv.stats()
-        nops = sum(ss["ops"])
-        serving = {"batches": len(batches), "rate_batches_per_s": round(lam, 1),
-                   "saturation_batches_per_s": round(2 * lam, 1),
-                   "ops_per_s": round(nops / ss["wall_s"], 1), "batches_per_s": round(len(batches) / ss["wall_s"], 1),
-                   "p50_us": round(ss["p50_us"], 1), "p99_us": round(ss["p99_us"], 1),
-                   "p50_us_by_op": [round(x, 1) for x in ss["p50_us_op"]],
-                   "p99_us_by_op": [round(x, 1) for x in ss["p99_us_op"]],
-                   "graph_launches": ss["graph_launches"], "keys": "2^24 + inserts", "lookups": "learned index"}
-        srv.close()
-        print("[bench] serving done", file=sys.stderr, flush=True)
+        s5, n5, nbr = 5, 1 << args.serve_log2n, args.serve_batches
+        warm5 = min(1000, nbr // 10)
+        keys5 = synth.uniform_keys(n5, s5, 64)
+        vals5 = synth.values_for(keys5, s5, 64)
+        ins_per_path = int(0.15 * 512.5 * (2000 + 4 * nbr) * 1.2)
+        fresh5 = synth.uniform_keys(2 * ins_per_path, s5 + 1, 64, purpose=synth.P_INSERT, exclude=keys5)
+        zipf5 = synth.Zipf(n5, 0.99, s5)
+        # a full leaf (fill 1.0) splits on its first new key: up to one new
+        # leaf per inserted key
+        tree5 = g.Tree(keys5, vals5, 8, leaf_slack=2 * ins_per_path + (1 << 16), max_batch=1024)
+        li5 = g.Learned(tree5, models=1024)
+        print(f"[bench] serving tree of {n5} keys ready", file=sys.stderr, flush=True)
+        serving = {"keys": n5, "batches_per_run": nbr, "warmup_batches": warm5,
+                   "mix": "80/15/5 lookup/insert/range, B ~ U{1..1024}, Zipf(0.99) keys, ranges max U{1..100}",
+                   "latency": "arrival -> completion, PCIe copies included (host buffers in and out)"}
+        fpos = 0
+        spec_seed = 50
+
+        def run(srv, n_b, rate):
+            nonlocal fpos, spec_seed
+            spec_seed += 1
+            spec = synth.serving_mix(keys5, n_b, s5 + spec_seed, bmax=1024, rate=rate, zipf=zipf5,
+                                     fresh=fresh5[fpos:])
+            fpos += sum(len(k) for (op, k, v, m, a) in spec if op == 1)
+            batches = [g.Batch(op, k, v, m, a) for (op, k, v, m, a) in spec]
+            assert srv.replay(batches) == g.GT_OK
+            st5 = srv.stats()
+            lat = srv.latencies(len(batches))
+            ops5 = np.array([b[0] for b in spec])
+            kept = slice(warm5, None) if rate else slice(0, None)
+            lk, lo = lat[kept], ops5[kept]
+            row = {"ops_per_s": round(sum(st5["ops"]) / st5["wall_s"], 1),
+                   "batches_per_s": round(len(batches) / st5["wall_s"], 1),
+                   "p50_us": round(float(np.percentile(lk, 50)), 1), "p99_us": round(float(np.percentile(lk, 99)), 1),
+                   "p50_us_by_op": [round(float(np.percentile(lk[lo == o], 50)), 1) if np.any(lo == o) else None
+                                    for o in range(3)],
+                   "p99_us_by_op": [round(float(np.percentile(lk[lo == o], 99)), 1) if np.any(lo == o) else None
+                                    for o in range(3)],
+                   "device_busy_frac": round(st5["busy_frac"], 3), "refused": st5["refused"]}
+            return row, len(batches) / st5["wall_s"]
+
+        for path in ("plain", "learned"):
+            srv = g.Server(tree5, learned=li5 if path == "learned" else None, slots=16, read_streams=4)
+            if path == "learned":
+                li5.train()
+            sat_row, lam_sat = run(srv, 2000, None)
+            runs = {"closed_loop": sat_row}
+            for frac in (0.25, 0.5, 0.75, 0.9):
+                if path == "learned":
+                    li5.train()
+                row, _ = run(srv, nbr, frac * lam_sat)
+                row["rate_batches_per_s"] = round(frac * lam_sat, 1)
+                runs[str(frac)] = row
+            if path == "learned":
+                ls5 = li5.stats()
+                runs["learned_index"] = {"declined": ls5["declined"], "mean_window": round(ls5["mean_window"], 2),
+                                         "fallbacks_last_run": ls5["fallbacks"]}
+            serving[path] = runs
+            srv.close()
+            print(f"[bench] serving ({path}) done", file=sys.stderr, flush=True)
+        serving["keys_after"] = tree5.stats()["n_keys"]
+        li5.close()
+        tree5.close()
+        del keys5, vals5, fresh5, zipf5
 
     # HBM bytes per launch from the committed counter summary, if it was
     # taken on this same kernel (same sources, batch and tree)

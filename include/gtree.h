@@ -371,6 +371,9 @@ typedef struct {
     double wall_s;           /* first arrival to last completion            */
     double p50_us, p99_us;   /* arrival -> completion latency, all batches  */
     double p50_us_op[3], p99_us_op[3];
+    double busy_frac;        /* share of wall_s in which the device worked on
+                                at least one batch (copies included), from
+                                timing events around each batch              */
 } gt_srv_stats;
 
 /* Create a server over tree t (and learned index li for lookups, or NULL).

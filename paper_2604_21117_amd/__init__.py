@@ -75,7 +75,7 @@ class gt_srv_stats(C.Structure):
     _fields_ = [("done", C.c_uint64 * 3), ("ops", C.c_uint64 * 3), ("refused", C.c_uint64),
                 ("graph_launches", C.c_uint64), ("direct_launches", C.c_uint64), ("wall_s", C.c_double),
                 ("p50_us", C.c_double), ("p99_us", C.c_double), ("p50_us_op", C.c_double * 3),
-                ("p99_us_op", C.c_double * 3)]
+                ("p99_us_op", C.c_double * 3), ("busy_frac", C.c_double)]
 
 
 OP_LOOKUP, OP_INSERT, OP_RANGE = 0, 1, 2

@@ -57,12 +57,14 @@ struct Req {
     uint32_t slot;
     uint64_t bytes;
     bool failed;
+    float dev0 = -1.0f, dev1 = -1.0f;  // device start / end (ms after the replay's reference event)
 };
 
 struct Slot {
     bool busy = false;
     uint64_t ticket = 0;
-    hipEvent_t ev = nullptr;
+    hipEvent_t ev = nullptr;   // recorded after the batch's work (completion, end time)
+    hipEvent_t ev0 = nullptr;  // recorded before it (start time)
     // device staging
     uint8_t* d_keys = nullptr; uint8_t* d_vals = nullptr; uint32_t* d_max = nullptr; uint64_t* d_off = nullptr;
     uint8_t* d_out0 = nullptr; uint8_t* d_out1 = nullptr; uint32_t* d_cnt = nullptr; uint8_t* d_flag = nullptr;
@@ -87,6 +89,9 @@ struct gt_server {
     std::vector<hipStream_t> rstreams;
     hipStream_t wstream = nullptr, cstream = nullptr;
     hipEvent_t wev = nullptr;
+    hipEvent_t ref_ev = nullptr;          // device time origin of the current replay
+    bool ref_set = false;
+    uint64_t replay_first = UINT64_MAX;   // first ticket of the current replay
     bool have_write = false;
     std::vector<hipEvent_t> reads_since_write;
     uint32_t rr = 0;
@@ -259,6 +264,14 @@ void worker_loop(gt_server* s) {
             if (hipEventQuery(sl.ev) != hipSuccess) continue;
             Req& q = s->reqs[sl.ticket];
             retire(s, sl, q);
+            if (s->ref_set) {
+                float a = 0, b = 0;
+                if (hipEventElapsedTime(&a, s->ref_ev, sl.ev0) == hipSuccess &&
+                    hipEventElapsedTime(&b, s->ref_ev, sl.ev) == hipSuccess) {
+                    q.dev0 = a;
+                    q.dev1 = b;
+                }
+            }
             q.done = now_s();
             q.state = q.failed ? GT_REQ_REFUSED : GT_REQ_DONE;
             s->bytes_inflight -= q.bytes;
@@ -298,7 +311,13 @@ void worker_loop(gt_server* s) {
                 st = s->rstreams[s->rr++ % s->rstreams.size()];
                 if (s->have_write) hipStreamWaitEvent(st, s->wev, 0);
             }
-            hipError_t e = launch(s, sl, q.r.op, bucket, outn, st);
+            hipError_t e = hipSuccess;
+            if (tk == s->replay_first) {
+                e = hipEventRecord(s->ref_ev, st);
+                s->ref_set = e == hipSuccess;
+            }
+            if (e == hipSuccess) e = hipEventRecord(sl.ev0, st);
+            if (e == hipSuccess) e = launch(s, sl, q.r.op, bucket, outn, st);
             if (e == hipSuccess) e = hipEventRecord(sl.ev, st);
             if (e == hipSuccess && q.r.op == GT_OP_INSERT) {
                 e = hipEventRecord(s->wev, st);
@@ -355,7 +374,8 @@ gt_status alloc_slot(gt_server* s, Slot& sl) {
               hm((void**)&sl.h_out0, std::max(B, outn) * kb) && hm((void**)&sl.h_out1, std::max(B, outn) * kb) &&
               hm((void**)&sl.h_cnt, B * 4) && hm((void**)&sl.h_flag, B) && hm((void**)&sl.h_err, 4);
     if (!ok) return GT_ERR_HIP;
-    if (hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess) return GT_ERR_HIP;
+    // timing events: the device-busy fraction is measured from them
+    if (hipEventCreate(&sl.ev) != hipSuccess || hipEventCreate(&sl.ev0) != hipSuccess) return GT_ERR_HIP;
     return GT_OK;
 }
 
@@ -363,6 +383,7 @@ void free_slot(Slot& sl) {
     for (auto& kv : sl.graphs) hipGraphExecDestroy(kv.second);
     sl.graphs.clear();
     if (sl.ev) hipEventDestroy(sl.ev);
+    if (sl.ev0) hipEventDestroy(sl.ev0);
     void* d[] = {sl.d_keys, sl.d_vals, sl.d_max, sl.d_off, sl.d_out0, sl.d_out1, sl.d_cnt, sl.d_flag};
     for (void* p : d)
         if (p) hipFree(p);
@@ -438,7 +459,8 @@ gt_status srv_create(gt_tree* t, gt_learned* li, const gt_srv_params* p, gt_serv
             if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) st = GT_ERR_HIP;
         if (hipStreamCreateWithFlags(&s->wstream, hipStreamNonBlocking) != hipSuccess ||
             hipStreamCreateWithFlags(&s->cstream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&s->wev, hipEventDisableTiming) != hipSuccess)
+            hipEventCreateWithFlags(&s->wev, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreate(&s->ref_ev) != hipSuccess)
             st = GT_ERR_HIP;
     }
     if (st != GT_OK) {
@@ -482,6 +504,13 @@ gt_status srv_wait(gt_server* s, uint64_t ticket) {
 gt_status srv_replay(gt_server* s, const gt_request* reqs, uint64_t n) {
     if (!s || (n && !reqs)) return GT_ERR_INVALID;
     std::vector<uint64_t> tickets(n);
+    {
+        // the worker records the device time origin when it admits this
+        // replay's first request
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->replay_first = s->reqs.size();
+        s->ref_set = false;
+    }
     const double t0 = now_s();
     for (uint64_t i = 0; i < n; ++i) {
         const double at = t0 + reqs[i].arrival_s;
@@ -507,6 +536,7 @@ gt_status srv_stats(gt_server* s, gt_srv_stats* out) {
     std::lock_guard<std::mutex> lk(s->mu);
     memset(out, 0, sizeof *out);
     std::vector<double> all, per[3];
+    std::vector<std::pair<float, float>> busy;
     double first = 1e300, last = 0;
     const std::vector<uint64_t>& ids = s->last_replay;
     for (uint64_t tk : ids) {
@@ -523,6 +553,7 @@ gt_status srv_stats(gt_server* s, gt_srv_stats* out) {
         out->ops[q.r.op] += q.r.B;
         first = std::min(first, q.arrival);
         last = std::max(last, q.done);
+        if (q.dev1 >= q.dev0 && q.dev0 > -1.0f) busy.emplace_back(q.dev0, q.dev1);
     }
     out->graph_launches = s->graph_launches;
     out->direct_launches = s->direct_launches;
@@ -533,6 +564,20 @@ gt_status srv_stats(gt_server* s, gt_srv_stats* out) {
         out->p50_us_op[o] = percentile(per[o], 0.5);
         out->p99_us_op[o] = percentile(per[o], 0.99);
     }
+    // union of the batches' device intervals over the wall time
+    std::sort(busy.begin(), busy.end());
+    double covered_ms = 0, cur0 = 0, cur1 = -1e300;
+    for (const auto& iv : busy) {
+        if (iv.first > cur1) {
+            if (cur1 > cur0) covered_ms += cur1 - cur0;
+            cur0 = iv.first;
+            cur1 = iv.second;
+        } else if (iv.second > cur1) {
+            cur1 = iv.second;
+        }
+    }
+    if (cur1 > cur0) covered_ms += cur1 - cur0;
+    out->busy_frac = out->wall_s > 0 ? covered_ms * 1e-3 / out->wall_s : 0.0;
     return GT_OK;
 }
 
@@ -564,6 +609,7 @@ gt_status srv_destroy(gt_server* s) {
     if (s->wstream) hipStreamDestroy(s->wstream);
     if (s->cstream) hipStreamDestroy(s->cstream);
     if (s->wev) hipEventDestroy(s->wev);
+    if (s->ref_ev) hipEventDestroy(s->ref_ev);
     delete s;
     return GT_OK;
 }

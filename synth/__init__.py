@@ -232,14 +232,16 @@ def serving_mix(keys: np.ndarray, n_batches: int, seed: int, width: int = 64, bm
     op 0 lookup / 1 insert / 2 range drawn with probabilities `mix`; size
     B ~ U{1..bmax}; lookup keys and range starts from the present keys
     (Zipf when given, else uniform); insert keys taken in order from `fresh`
-    (absent keys) with values hash(key ^ seed); range hi = all ones and
+    (absent keys) with values hash(key ^ seed) -- an insert batch beyond the
+    end of `fresh` becomes a lookup batch; range hi = all ones and
     max ~ U{1..max_len}; Poisson arrivals at `rate` batches per second (all
-    at 0 when rate is None)."""
+    at 0 when rate is None).  All draws are made at once and cut into
+    batches."""
     s = Stream(seed, P_MIX)
     u = s.uniform01(n_batches)
     cum = np.cumsum(mix)
     ops = np.searchsorted(cum / cum[-1], u, side="right").astype(np.int64)
-    sizes = s.below(n_batches, bmax) + 1
+    sizes = (s.below(n_batches, bmax) + 1).astype(np.int64)
     if rate:
         gaps = -np.log1p(-s.uniform01(n_batches)) / rate
         arrivals = np.cumsum(gaps) - gaps[0]
@@ -247,24 +249,36 @@ def serving_mix(keys: np.ndarray, n_batches: int, seed: int, width: int = 64, bm
         arrivals = np.zeros(n_batches)
     keys = np.asarray(keys)
     top = np.iinfo(keys.dtype).max
-    fpos = 0
+    ins = ops == 1
+    if fresh is None:
+        ops[ins] = 0
+    else:
+        need = np.cumsum(np.where(ins, sizes, 0))
+        ops[ins & (need > len(fresh))] = 0
+    ins = ops == 1
+    n_ins = int(sizes[ins].sum())
+    ik = fresh[:n_ins] if n_ins else np.zeros(0, dtype=keys.dtype)
+    iv = values_for(ik, seed, width) if n_ins else ik
+    n_read = int(sizes[~ins].sum())
+    ridx = zipf.indices(n_read) if zipf is not None else s.below(n_read, len(keys))
+    rk = keys[ridx]
+    n_rng = int(sizes[ops == 2].sum())
+    rmx = (s.below(n_rng, max_len) + 1).astype(np.uint32)
     out = []
+    pi = pr = pm = 0
     for i in range(n_batches):
         B = int(sizes[i])
         op = int(ops[i])
+        at = float(arrivals[i])
         if op == 1:
-            if fresh is None or fpos + B > len(fresh):
-                op = 0
-            else:
-                k = fresh[fpos:fpos + B]
-                fpos += B
-                out.append((1, k, values_for(k, seed, width), None, float(arrivals[i])))
-                continue
-        idx = zipf.indices(B) if zipf is not None else s.below(B, len(keys))
-        k = keys[idx]
+            out.append((1, ik[pi:pi + B], iv[pi:pi + B], None, at))
+            pi += B
+            continue
+        k = rk[pr:pr + B]
+        pr += B
         if op == 0:
-            out.append((0, k, None, None, float(arrivals[i])))
+            out.append((0, k, None, None, at))
         else:
-            mx = (s.below(B, max_len) + 1).astype(np.uint32)
-            out.append((2, k, np.full(B, top, dtype=keys.dtype), mx, float(arrivals[i])))
+            out.append((2, k, np.full(B, top, dtype=keys.dtype), rmx[pm:pm + B], at))
+            pm += B
     return out

@@ -76,6 +76,9 @@ def test_mix_equals_sequential(graphs):
     st = srv.stats()
     assert sum(st["done"]) == len(batches) and st["refused"] == 0
     assert st["p99_us"] >= st["p50_us"] > 0
+    # device intervals from timing events: some work, and no more than the
+    # wall time (the union of intervals, not their sum)
+    assert 0.0 < st["busy_frac"] <= 1.05
     if graphs == 1:
         assert st["graph_launches"] >= len(batches)
     srv.close()
