@@ -195,7 +195,8 @@ def main():
     print(f"[bench] {n} keys ready", file=sys.stderr, flush=True)
 
     t0 = time.perf_counter()
-    tree = g.Tree(keys, vals, 8, leaf_slack=(1 << 20) + (1 << 18), max_batch=1 << 20)
+    # room for about 2.1 M inserted keys (a full leaf splits on its first new key)
+    tree = g.Tree(keys, vals, 8, leaf_slack=(1 << 21) + (1 << 19), max_batch=1 << 20)
     build_s = time.perf_counter() - t0
     st = tree.stats()
     BL = 1 << 20
@@ -522,24 +523,37 @@ def main():
     rng_row = {"batch": B, "us_per_batch": round(iqm(rts), 2), "pairs": tot,
                "mpairs_per_s": round(tot / iqm(rts), 2)}
 
-    # ---- insert batches of fresh keys
-    fresh = synth.uniform_keys((1 << 20) + 64 * B, SEED + 1, 64, purpose=synth.P_INSERT, exclude=keys)
-    ins_small = []
-    for i in range(24):
-        k = fresh[i * B:(i + 1) * B]
+    # ---- insert batches of fresh keys: B = 1, 8, 64, 256 (32 batches each),
+    # 1024 (24 batches) and 2^20 (one batch), timed with HIP events
+    fresh = synth.uniform_keys((1 << 21) + 128 * B, SEED + 1, 64, purpose=synth.P_INSERT, exclude=keys)
+    fpos = 0
+
+    def insert_batch(k):
         kd, vd = tree.dev(k), tree.dev(synth.values_for(k, SEED, 64))
-        s8 = torch.empty(B, dtype=torch.uint8, device=dev)
-        ins_small += timer.run(lambda: g.tree_insert_batch(tree.h, kd, vd, s8, stream), 1, skip=0)
+        s8 = torch.empty(len(k), dtype=torch.uint8, device=dev)
+        t = timer.run(lambda: g.tree_insert_batch(tree.h, kd, vd, s8, stream), 1, skip=0)
+        return t[0], s8
+
+    ins_row = {"us_per_batch": {}, "mkeys_per_s": {}}
+    for b, reps in ((1, 32), (8, 32), (64, 32), (256, 32), (B, 24)):
+        ts = []
+        for _ in range(reps):
+            t, _s = insert_batch(fresh[fpos:fpos + b])
+            fpos += b
+            ts.append(t)
+        ins_row["us_per_batch"][str(b)] = round(iqm(ts[4:]), 1)
+        ins_row["mkeys_per_s"][str(b)] = round(b / iqm(ts[4:]), 3)
     assert g.tree_device_error(tree.h) == g.GT_OK
-    kbig = fresh[64 * B:64 * B + BL]
-    kd, vd = tree.dev(kbig), tree.dev(synth.values_for(kbig, SEED, 64))
-    s8 = torch.empty(BL, dtype=torch.uint8, device=dev)
-    big = timer.run(lambda: g.tree_insert_batch(tree.h, kd, vd, s8, stream), 1, skip=0)
+    kbig = fresh[fpos:fpos + BL]
+    fpos += BL
+    big, s8 = insert_batch(kbig)
     assert g.tree_device_error(tree.h) == g.GT_OK and (g.to_numpy(s8) == 0).all()
-    ins_row = {"b1024_us_per_batch": round(iqm(ins_small[4:]), 1),
-               "b1024_mkeys_per_s": round(B / iqm(ins_small[4:]), 2),
-               "b2p20_us": round(big[0], 1), "b2p20_mkeys_per_s": round(BL / big[0], 2),
-               "height_after": tree.stats()["height"]}
+    ins_row["us_per_batch"][str(BL)] = round(big, 1)
+    ins_row["mkeys_per_s"][str(BL)] = round(BL / big, 2)
+    ins_row["b1024_us_per_batch"] = ins_row["us_per_batch"][str(B)]
+    ins_row["b2p20_us"] = ins_row["us_per_batch"][str(BL)]
+    ins_row["b2p20_mkeys_per_s"] = ins_row["mkeys_per_s"][str(BL)]
+    ins_row["height_after"] = tree.stats()["height"]
     print("[bench] inserts done", file=sys.stderr, flush=True)
 
     # ---- learned index after the inserts (stale), then retrained
@@ -559,6 +573,34 @@ def main():
     stale_row = {"batch": B, "stale_us": round(stale_us, 3), "stale_fallback_rate": round(stale_fb, 4),
                  "retrain_s": round(retrain_s, 3), "retrained_us": round(fresh_us, 3),
                  "retrained_fallback_rate": round(fresh_fb, 4), "plain_us": round(plain_mix_us, 3)}
+
+    # ---- staleness (the learned-index protocol): from a freshly trained index,
+    # 1024 rounds of one B = 1024 lookup batch of present keys followed by one
+    # insert batch of 1024 fresh keys (2^20 inserts); lookup time (events) and
+    # fallback rate per quarter of the inserts, then the retrain, timed
+    quarters = []
+    rounds = 1024
+    for qtr in range(4):
+        lt, pt = [], []
+        f0, l0 = li.stats()["fallbacks"], li.stats()["lookups"]
+        for r in range(rounds // 4):
+            i = qtr * (rounds // 4) + r
+            lt += timer.run(lambda: g.li_lookup_batch(li.h, qd[i % nbatch], vo, fo, stream), 1, skip=0)
+            pt += timer.run(lambda: g.tree_lookup_batch(tree.h, qd[i % nbatch], vo, fo, stream), 1, skip=0)
+            insert_batch(fresh[fpos:fpos + B])
+            fpos += B
+        ls = li.stats()
+        quarters.append({"learned_us": round(iqm(lt), 3), "plain_us": round(iqm(pt), 3),
+                         "fallback_rate": round((ls["fallbacks"] - f0) / max(1, ls["lookups"] - l0), 4)})
+    assert g.tree_device_error(tree.h) == g.GT_OK
+    t0 = time.perf_counter()
+    li.train()
+    retrain2_s = time.perf_counter() - t0
+    after = iqm(timer.run(lambda: g.li_lookup_batch(li.h, qd[0], vo, fo, stream), 40))
+    stale_row["by_quarter_of_2p20_inserts"] = quarters
+    stale_row["retrain_after_2p20_s"] = round(retrain2_s, 3)
+    stale_row["retrained_after_2p20_us"] = round(after, 3)
+    print("[bench] staleness done", file=sys.stderr, flush=True)
 
     # ---- serving: 2^26 resident uniform keys (seed 5), batches B ~ U{1..1024}
     # of 80 % lookups / 15 % inserts of fresh keys / 5 % ranges (max

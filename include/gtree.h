@@ -251,9 +251,9 @@ typedef struct {
     uint32_t search;      /* window search: 1 = through the fence directory;
                              2 = read the window's leaves directly when the
                              trained directory is the identity (a bulk-loaded
-                             tree) and the window spans at most 8 leaves
-                             (wider windows use the directory); 0 = default:
-                             as 2 for batches up to 2^13 keys, else 1         */
+                             tree); 0 = default: direct for batches up to
+                             2^13 keys on such a tree when no window spans
+                             more than 16 leaves, else the directory          */
     uint32_t gate;        /* 0 = default: after training, if more than a
                              quarter of the keys go down the tree or the
                              key-weighted mean window exceeds 16 leaves, the
@@ -293,7 +293,10 @@ gt_status li_train(gt_learned* li, hipStream_t stream);
 
 /* Same contract as tree_lookup_batch.  The launch passes the index's current
  * parameters by value: a graph that captured it must be captured again after
- * li_train or li_set_bounds. */
+ * li_train or li_set_bounds, and after the first tree_insert_batch on its
+ * tree since training (from then on a miss resumes along the leaf chain,
+ * which another kernel does; a graph captured before still answers
+ * correctly, through the tree). */
 gt_status li_lookup_batch(gt_learned* li, const void* keys, uint64_t B, void* values_out,
                           uint8_t* found_out, hipStream_t stream);
 

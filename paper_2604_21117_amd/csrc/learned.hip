@@ -63,7 +63,8 @@ constexpr int kLiBlock = 256;
 constexpr uint32_t kKindLinear = 0, kKindMlp = 1, kKindTree = 2;
 constexpr int kFitPoints = 4096;                  // points per model for the network fit
 constexpr int kDirect = 4;                        // leaves a group reads at once on the direct path
-constexpr int32_t kDirectMaxWin = 2 * kDirect;    // wider windows take the fence directory instead
+constexpr uint32_t kDirectMaxWin = 16;            // direct reads only while every window is this narrow
+constexpr int kWalkMax = 4;                       // leaves a stale miss may follow along the chain
 constexpr double kGateTreeShare = 0.25;           // decline: more of the keys go down the tree than this
 constexpr double kGateMeanWindow = 16.0;          // decline: a wider key-weighted mean window (leaves)
 constexpr uint64_t kDirectMaxBatch = 1ull << 13;   // default: direct window reads up to this batch
@@ -80,7 +81,8 @@ struct LiHeader {
     uint32_t epoch;      // tree epoch at training
     unsigned long long keys_tree;    // trained keys whose piece sends them down the tree
     unsigned long long window_sum;   // sum over the other keys of their piece's window (leaves)
-    uint32_t pad[44];
+    uint32_t max_win;                // widest window of a piece that holds keys
+    uint32_t pad[43];
 };
 static_assert(sizeof(LiHeader) == 256, "LiHeader size");
 
@@ -576,33 +578,43 @@ constexpr int kQualityBlock = 1024;
 
 template <class K>
 __global__ __launch_bounds__(kQualityBlock) void k_quality(LiView<K> li, uint32_t cells) {
-    __shared__ unsigned long long sh[2][kQualityBlock / 64];
-    unsigned long long tree = 0, wsum = 0;
+    __shared__ unsigned long long sh[3][kQualityBlock / 64];
+    unsigned long long tree = 0, wsum = 0, wmax = 0;
     for (uint32_t c = threadIdx.x; c < cells; c += kQualityBlock) {
         const uint32_t n = li.cnt[c];
         const Piece p = li.piece[c];
         if (n == 0) continue;
-        if (p.lo > p.hi) tree += n;
-        else wsum += static_cast<unsigned long long>(n) * static_cast<unsigned long long>(p.hi - p.lo + 1);
+        if (p.lo > p.hi) {
+            tree += n;
+        } else {
+            const unsigned long long w = static_cast<unsigned long long>(p.hi - p.lo + 1);
+            wsum += static_cast<unsigned long long>(n) * w;
+            wmax = w > wmax ? w : wmax;
+        }
     }
     for (int d = 32; d > 0; d >>= 1) {
         tree += __shfl_xor(tree, d, 64);
         wsum += __shfl_xor(wsum, d, 64);
+        const unsigned long long o = __shfl_xor(wmax, d, 64);
+        wmax = o > wmax ? o : wmax;
     }
     const int w = threadIdx.x / 64;
     if ((threadIdx.x & 63) == 0) {
         sh[0][w] = tree;
         sh[1][w] = wsum;
+        sh[2][w] = wmax;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long a = 0, b = 0;
+        unsigned long long a = 0, b = 0, m = 0;
         for (int i = 0; i < kQualityBlock / 64; ++i) {
             a += sh[0][i];
             b += sh[1][i];
+            m = sh[2][i] > m ? sh[2][i] : m;
         }
         li.hdr->keys_tree = a;
         li.hdr->window_sum = b;
+        li.hdr->max_win = static_cast<uint32_t>(m);
     }
 }
 
@@ -690,7 +702,44 @@ __device__ __forceinline__ void match_leaf(const typename Trav<K, kLiG>::KV& kv,
     }
 }
 
-template <class K, bool DIRECT, int BLK>
+// A miss after the tree changed (or after li_set_bounds) resumes along the
+// leaf chain from a candidate leaf: the last window leaf whose first key is
+// <= key.  Chain order is key order, so the key lies in the candidate or in a
+// leaf chained after it (a split moves the upper part of a leaf to new leaves
+// chained right after it).  The walk goes on while the current leaf ends
+// below the key; a walk longer than kWalkMax leaves, or no candidate, hands
+// over to the root-to-leaf descent.  Trained leaf ids stay valid leaves
+// because the tree never frees a leaf (it has no delete).  Returns false when
+// the walk cannot decide.
+template <class K>
+__device__ __forceinline__ bool chain_walk(const TreeView<K>& t, K key, uint32_t cand, K cand_last, int gl,
+                                           int gbase, Hit<K>& v) {
+    using T = Trav<K, kLiG>;
+    uint32_t cur = cand;
+    K last = cand_last;
+    for (int step = 0; step < kWalkMax; ++step) {
+        if (last >= key) return true;           // the key's leaf was checked: absent
+        const uint32_t nx = t.lmeta[cur].y;
+        if (nx == kNone) return true;           // past the last leaf: absent
+        const typename T::KV kv = T::load_keys(t.lkeys + static_cast<uint64_t>(nx) * kSlots, gl);
+        const typename T::KV vv = T::load_keys(t.lvals + static_cast<uint64_t>(nx) * kSlots, gl);
+        const K first = static_cast<K>(__shfl(kv.v[0], gbase, 64));
+        if (first > key) return true;           // between two leaves: absent
+        match_leaf<K>(kv, vv, key, gbase, v);
+        if (v.hit) return true;
+        last = static_cast<K>(__shfl(kv.v[T::KPL - 1], gbase + kLiG - 1, 64));
+        cur = nx;
+    }
+    return last >= key;
+}
+
+// Learned lookup.  DIRECT: the trained directory is the identity (position
+// = leaf id), so the window's leaves are read directly.  STALE: the tree may
+// have changed since training or the bounds were overwritten; a miss then
+// resumes along the leaf chain (chain_walk) before it falls back to the
+// tree.  The host launches STALE = false while no insert was issued since
+// training, so the common kernel carries none of that code.
+template <class K, bool DIRECT, int BLK, bool STALE>
 __global__ __launch_bounds__(BLK) void k_li_lookup(TreeView<K> t, LiView<K> li, LiArgs a, const K* __restrict__ q,
                                                    uint64_t B, K* __restrict__ vout, uint8_t* __restrict__ fout) {
     using T = Trav<K, kLiG>;
@@ -709,16 +758,13 @@ __global__ __launch_bounds__(BLK) void k_li_lookup(TreeView<K> t, LiView<K> li, 
         const Piece e = load_piece(li.piece, r.j, r.m);
         Hit<K> v;
         bool fb = e.lo > e.hi;
+        // where a stale miss resumes (STALE only)
+        uint32_t cand = kNone;
+        K cand_last = K(0);
         if (!fb) {
             const int32_t p = piece_pos(e.slope, e.icpt, e.base, r.x, a.L);
             const int32_t wl = max(p + e.lo, 0), wh = min(p + e.hi, last_pos);
-            // a narrow window on a bulk-loaded tree reads its leaves directly
-            // (at most two rounds); a wider one searches the fence directory
-            // (32 fences a round, then one leaf), which costs about as much as
-            // the tree's own descent instead of growing with the window
-            bool direct = false;
-            if constexpr (DIRECT) direct = wh - wl < kDirectMaxWin;
-            if (direct) {
+            if constexpr (DIRECT) {
                 // positions are leaf ids: read kDirect of the window's leaves at
                 // once; each lane checks its own slots (no cross-lane work
                 // until one lane holds the key)
@@ -751,6 +797,27 @@ __global__ __launch_bounds__(BLK) void k_li_lookup(TreeView<K> t, LiView<K> li, 
                         v.val = static_cast<K>(__shfl(mval, gbase + __builtin_ctzll(hm), 64));
                     }
                 }
+                if constexpr (STALE) {
+                    if (!v.hit) {
+                        // the candidate from the window leaves' first and last
+                        // keys, kLiG leaves at a time
+                        for (int32_t b0 = wl; b0 <= wh; b0 += kLiG) {
+                            const int32_t pp = b0 + gl;
+                            const bool in = pp <= wh;
+                            K first = K(0), last = K(0);
+                            if (in) {
+                                first = t.lkeys[static_cast<uint64_t>(pp) * kSlots];
+                                last = t.lkeys[static_cast<uint64_t>(pp) * kSlots + kSlots - 1];
+                            }
+                            const uint64_t m = group_bits<kLiG>(__ballot(in && first <= key), gbase);
+                            if (m) {
+                                const int idx = 63 - __builtin_clzll(m);
+                                cand = static_cast<uint32_t>(b0 + idx);
+                                cand_last = static_cast<K>(__shfl(last, gbase + idx, 64));
+                            }
+                        }
+                    }
+                }
             } else {
                 // the last fence <= key in the window picks the leaf; none: the
                 // key lies before the window (absent while the tree is unchanged)
@@ -760,13 +827,21 @@ __global__ __launch_bounds__(BLK) void k_li_lookup(TreeView<K> t, LiView<K> li, 
                     const typename T::KV kv = T::load_keys(t.lkeys + static_cast<uint64_t>(leaf) * kSlots, gl);
                     const typename T::KV vv = T::load_keys(t.lvals + static_cast<uint64_t>(leaf) * kSlots, gl);
                     match_leaf<K>(kv, vv, key, gbase, v);
+                    if constexpr (STALE) {
+                        cand = leaf;
+                        cand_last = static_cast<K>(__shfl(kv.v[T::KPL - 1], gbase + kLiG - 1, 64));
+                    }
                 }
             }
-            // no hit: proof of absence on an unchanged tree, else the tree decides
+            // no hit: proof of absence on an unchanged tree, else the leaf
+            // chain or the tree decides
             if (!v.hit) {
                 if (fresh < 0) fresh = t.hdr->epoch == a.epoch ? 1 : 0;
                 fb = fresh == 0;
             }
+        }
+        if constexpr (STALE) {
+            if (fb && cand != kNone && chain_walk<K>(t, key, cand, cand_last, gl, gbase, v)) fb = false;
         }
         if (fb) {
             // the tree decides: plain root-to-leaf walk
@@ -824,10 +899,19 @@ struct gt_learned {
         off_cnt, off_partial, off_ident;
     LiArgs args;
     bool declined = false;    // the quality gate sends lookups to the tree kernel
+    uint32_t max_win = 0;     // widest window at training (leaves)
+    uint64_t inserts_at_train = 0;  // the tree's insert count when trained
     uint64_t generation = 0;  // bumped whenever the lookup's arguments or tables change
 };
 
-uint64_t gt_li_generation(const gt_learned* li) { return li->generation; }
+// The lookup launches a different kernel once the tree has changed since
+// training (or the bounds were overwritten): that state is part of the
+// generation, so a captured graph of the other state is captured again.
+static bool li_stale(const gt_learned* li) {
+    return !li->args.exact || li->t->inserts != li->inserts_at_train;
+}
+
+uint64_t gt_li_generation(const gt_learned* li) { return 2 * li->generation + (li_stale(li) ? 1 : 0); }
 
 namespace {
 
@@ -913,6 +997,7 @@ gt_status train_t(gt_learned* li, hipStream_t s) {
         LI_HIP(hipStreamSynchronize(s));
         li->trained = false;
         li->declined = false;
+        li->inserts_at_train = t->inserts;
         li->generation++;
         return GT_OK;
     }
@@ -980,33 +1065,43 @@ gt_status train_t(gt_learned* li, hipStream_t s) {
     const double mean_win = in_win > 0 ? static_cast<double>(h.window_sum) / in_win : 0.0;
     li->declined = li->p.gate == 0 &&
                    (static_cast<double>(h.keys_tree) > kGateTreeShare * keys || mean_win > kGateMeanWindow);
+    li->max_win = h.max_win;
+    li->inserts_at_train = t->inserts;
     li->generation++;
     return GT_OK;
 }
 
 template <class K, bool DIRECT, int BLK>
-void launch_li_lookup_t(gt_learned* li, const K* q, uint64_t B, K* vo, uint8_t* fo, hipStream_t stream) {
+void launch_li_lookup_t(gt_learned* li, bool stale, const K* q, uint64_t B, K* vo, uint8_t* fo, hipStream_t stream) {
     const uint32_t grid = grid_of(B * kLiG, BLK, 8192);
-    hipLaunchKernelGGL((k_li_lookup<K, DIRECT, BLK>), dim3(grid), dim3(BLK), 0, stream, view<K>(li->t),
-                       li_view<K>(li), li->args, q, B, vo, fo);
+    if (stale)
+        hipLaunchKernelGGL((k_li_lookup<K, DIRECT, BLK, true>), dim3(grid), dim3(BLK), 0, stream, view<K>(li->t),
+                           li_view<K>(li), li->args, q, B, vo, fo);
+    else
+        hipLaunchKernelGGL((k_li_lookup<K, DIRECT, BLK, false>), dim3(grid), dim3(BLK), 0, stream, view<K>(li->t),
+                           li_view<K>(li), li->args, q, B, vo, fo);
 }
 
 // Small batches are latency-bound: 64-thread workgroups spread them over
-// more CUs (fewer outstanding misses per CU).
+// more CUs (fewer outstanding misses per CU).  Windows are read directly on
+// a bulk-loaded tree (identity directory) for small batches when every
+// window is narrow; otherwise the fence directory is searched.
 template <class K>
 void launch_li_lookup(gt_learned* li, const void* keys, uint64_t B, void* values_out, uint8_t* found_out,
                       hipStream_t stream) {
     const uint32_t mode = li->p.search;
-    const bool direct = li->args.identity && (mode == 2 || (mode == 0 && B <= kDirectMaxBatch));
+    const bool direct = li->args.identity &&
+                        (mode == 2 || (mode == 0 && B <= kDirectMaxBatch && li->max_win <= kDirectMaxWin));
     const bool small = B <= kSmallLookup;
+    const bool stale = li_stale(li);
     const K* q = reinterpret_cast<const K*>(keys);
     K* vo = reinterpret_cast<K*>(values_out);
     if (direct) {
-        if (small) launch_li_lookup_t<K, true, 64>(li, q, B, vo, found_out, stream);
-        else launch_li_lookup_t<K, true, kLiBlock>(li, q, B, vo, found_out, stream);
+        if (small) launch_li_lookup_t<K, true, 64>(li, stale, q, B, vo, found_out, stream);
+        else launch_li_lookup_t<K, true, kLiBlock>(li, stale, q, B, vo, found_out, stream);
     } else {
-        if (small) launch_li_lookup_t<K, false, 64>(li, q, B, vo, found_out, stream);
-        else launch_li_lookup_t<K, false, kLiBlock>(li, q, B, vo, found_out, stream);
+        if (small) launch_li_lookup_t<K, false, 64>(li, stale, q, B, vo, found_out, stream);
+        else launch_li_lookup_t<K, false, kLiBlock>(li, stale, q, B, vo, found_out, stream);
     }
 }
 

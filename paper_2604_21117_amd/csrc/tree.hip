@@ -341,6 +341,7 @@ gt_status tree_insert_batch(gt_tree* t, const void* keys, const void* values, ui
     // the batch may grow the tree on the device; the host keeps a bound
     const uint32_t hc = height_cap(t->leaf_cap);
     if (hc > t->h_bound) t->h_bound = hc;
+    t->inserts++;
     return hipGetLastError() == hipSuccess ? GT_OK : GT_ERR_HIP;
 }
 

@@ -128,18 +128,23 @@ def test_quality_gate(dist):
 
 
 def test_forced_fallback_stays_exact():
+    """Windows of one leaf: most predictions miss the key's leaf, so a miss
+    resumes along the leaf chain from the window or descends from the root;
+    windows past the last leaf are empty, so every query descends from the
+    root.  Every answer stays exact."""
     seed, width = 44, 64
     keys = synth.uniform_keys(200000, seed, width)
     vals = synth.values_for(keys, seed, width)
     sa = oracle.SortedArray(keys, vals, width)
     t = mk_tree(keys, vals, 8, max_batch=4096)
-    li = _learned(t)
-    li.set_bounds(0, 0)  # windows of one leaf: most predictions now miss
+    li = _learned(t, gate=1)
     q = synth.mixed_queries(keys, 50000, seed, width)
-    f0 = li.stats()["fallbacks"]
+    li.set_bounds(0, 0)
     _li_parity(li, sa, q)
-    assert li.stats()["fallbacks"] - f0 > 1000
-    li.set_bounds(5, 3) if False else None
+    f0 = li.stats()["fallbacks"]
+    li.set_bounds(20000, 20000)
+    _li_parity(li, sa, q)
+    assert li.stats()["fallbacks"] - f0 == len(q)
 
 
 @pytest.mark.parametrize("search", [1, 2])
@@ -161,8 +166,10 @@ def test_stale_after_inserts_then_retrain(search):
         assert np.array_equal(t.insert(k, v), sa.insert(k, v))
         q = np.concatenate([k[:3000], synth.mixed_queries(sa.keys, 6000, seed + b, width)])
         _li_parity(li, sa, q)
-    f_stale = li.stats()["fallbacks"]
-    assert f_stale > 0
+    # a miss on the changed tree resumes along the leaf chain from its
+    # window; only keys below every window leaf descend from the root
+    st = li.stats()
+    assert st["fallbacks"] <= st["lookups"] // 10, st
     li.train()
     _check_bounds(t, li)
     _li_parity(li, sa, synth.mixed_queries(sa.keys, 40000, seed, width))
