@@ -488,6 +488,9 @@ __global__ __launch_bounds__(kBlk) void k_apply_leaves(TreeView<K> t, Ins<K> v) 
         __threadfence_block();  // the old leaf is in registers before any write
         const K* nk = v.nk + first;
         const K* nv = v.nv + first;
+        // one run of new keys (the common case): each lane holds at most one
+        // old and one new element, and the group pads the pieces together
+        const bool one_run = r <= static_cast<uint32_t>(kNodeLanes);
         auto place = [&](uint64_t pos, K key, K val) {
             const uint64_t j = part_of(pos, total, k);
             const uint64_t s0 = part_start(j, total, k), s1 = part_start(j + 1, total, k);
@@ -497,16 +500,22 @@ __global__ __launch_bounds__(kBlk) void k_apply_leaves(TreeView<K> t, Ins<K> v) 
             t.lvals[dest * kSlots + slot] = val;
             if (pos + 1 == s1) {
                 const uint32_t cnt = static_cast<uint32_t>(s1 - s0);
-                for (uint32_t s = cnt; s < kSlots; ++s) {
-                    t.lkeys[dest * kSlots + s] = key;
-                    t.lvals[dest * kSlots + s] = kmax<K>();
+                if (!one_run) {
+                    for (uint32_t s = cnt; s < kSlots; ++s) {
+                        t.lkeys[dest * kSlots + s] = key;
+                        t.lvals[dest * kSlots + s] = kmax<K>();
+                    }
                 }
                 const uint32_t nxt = (j + 1 < k) ? static_cast<uint32_t>(base_new + j) : meta.y;
                 t.lmeta[dest] = make_uint2(cnt, nxt);
                 if (j + 1 < k) v.psep[off + j] = key;
             }
         };
-        if (gl < static_cast<int>(c)) place(gl + lower_bound_dev(nk, r, okey), okey, oval);
+        const bool has_old = gl < static_cast<int>(c);
+        const uint64_t opos = has_old ? gl + lower_bound_dev(nk, r, okey) : ~0ull;
+        if (has_old) place(opos, okey, oval);
+        uint64_t npos = ~0ull;
+        K nkey = K(0);
         for (uint32_t q0 = 0; q0 < r; q0 += kNodeLanes) {
             const uint32_t q = q0 + gl;
             const bool act = q < r;
@@ -516,7 +525,31 @@ __global__ __launch_bounds__(kBlk) void k_apply_leaves(TreeView<K> t, Ins<K> v) 
                 const K ks = __shfl(okey, gbase + static_cast<int>(s), 64);
                 rank += ks < key ? 1u : 0u;
             }
-            if (act) place(q + rank, key, nv[q]);
+            if (act) {
+                place(q + rank, key, nv[q]);
+                npos = q + rank;
+                nkey = key;
+            }
+        }
+        if (one_run) {
+            // slots past a piece's count repeat its last key with an all-ones
+            // value: the piece's last element sits on one lane, as an old or
+            // a new element; lanes past the count write one slot each
+            for (uint32_t j = 0; j < k; ++j) {
+                const uint64_t s0 = part_start(j, total, k), s1 = part_start(j + 1, total, k);
+                const uint32_t cnt = static_cast<uint32_t>(s1 - s0);
+                if (cnt >= static_cast<uint32_t>(kSlots)) continue;
+                const uint64_t mo = group_bits<kNodeLanes>(__ballot(opos == s1 - 1), gbase);
+                const uint64_t mn = group_bits<kNodeLanes>(__ballot(npos == s1 - 1), gbase);
+                const K ko = __shfl(okey, gbase + (mo ? __builtin_ctzll(mo) : 0), 64);
+                const K kn = __shfl(nkey, gbase + (mn ? __builtin_ctzll(mn) : 0), 64);
+                const K lastk = mo ? ko : kn;
+                const uint64_t dest = j == 0 ? leaf : base_new + j - 1;
+                if (static_cast<uint32_t>(gl) >= cnt) {
+                    t.lkeys[dest * kSlots + gl] = lastk;
+                    t.lvals[dest * kSlots + gl] = kmax<K>();
+                }
+            }
         }
     }
 }
@@ -598,13 +631,17 @@ __global__ __launch_bounds__(kBlk) void k_apply_inner(TreeView<K> t, Ins<K> v, i
                 const uint64_t dest = pj == 0 ? node : base_new + pj - 1;
                 t.ikeys[dest * kSlots + slot] = (slot + 1 < cnt) ? sep : kmax<K>();
                 t.ichild[dest * kSlots + slot] = ch;
-                if (e + 1 == s1) {
-                    for (uint64_t s = cnt; s < kSlots; ++s) {
-                        t.ikeys[dest * kSlots + s] = kmax<K>();
-                        t.ichild[dest * kSlots + s] = kNone;
-                    }
-                    if (pj + 1 < P) v.psep[psep_d + off + pj] = sep;
-                }
+                if (e + 1 == s1 && pj + 1 < P) v.psep[psep_d + off + pj] = sep;
+            }
+        }
+        // slots past a piece's count: the largest key and no child, one slot
+        // per lane
+        for (uint32_t pj = 0; pj < P; ++pj) {
+            const uint64_t cnt = part_start(pj + 1, Cp, P) - part_start(pj, Cp, P);
+            const uint64_t dest = pj == 0 ? node : base_new + pj - 1;
+            if (lane >= cnt) {
+                t.ikeys[dest * kSlots + lane] = kmax<K>();
+                t.ichild[dest * kSlots + lane] = kNone;
             }
         }
     }
