@@ -218,6 +218,7 @@ gt_status tree_device_error(gt_tree* t, hipStream_t stream);
  */
 gt_status tree_export(gt_tree* t, void* host_buf, uint64_t* bytes /*host*/, hipStream_t stream);
 
+/* A constant, human-readable name for a status code (host). */
 const char* gt_status_str(gt_status s);
 
 /* ------------------------------------------------------------------------
@@ -315,6 +316,8 @@ gt_status li_set_bounds(gt_learned* li, int32_t lo, int32_t hi, hipStream_t stre
 /* Counters and model summary (synchronises). */
 gt_status li_stats(gt_learned* li, gt_li_stats* out /*host*/, hipStream_t stream);
 
+/* Release the handle (host memory only; the caller frees the arena after
+ * work that uses it has completed). */
 gt_status li_destroy(gt_learned* li);
 
 /* ------------------------------------------------------------------------
@@ -393,10 +396,13 @@ gt_status srv_wait(gt_server* s, uint64_t ticket);
 /* Submit reqs[i] at reqs[i].arrival_s after the call starts (open loop),
  * then wait for all of them; statistics cover exactly these requests. */
 gt_status srv_replay(gt_server* s, const gt_request* reqs /*host*/, uint64_t n);
+/* Statistics of the last srv_replay's requests (host). */
 gt_status srv_stats(gt_server* s, gt_srv_stats* out /*host*/);
 /* Arrival-to-completion latency in microseconds of the last srv_replay's
  * requests, in their order (host array of n). */
 gt_status srv_latencies(gt_server* s, double* out /*host*/, uint64_t n);
+/* Drain every admitted request, stop the worker and free the staging
+ * buffers, streams and captured graphs. */
 gt_status srv_destroy(gt_server* s);
 
 #ifdef __cplusplus
