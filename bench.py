@@ -22,6 +22,9 @@ Also measured in the same run, outside the K timed steps:
                   key sequence), plain and learned
   large_batch     2^20-key lookup batches, warm and cold (a 2 GiB flush before
                   each cold launch; `--no-cold` skips them)
+  mixed_90_10     per B in 1..1024 and 2^20, uniform and Zipf: R batches on a
+                  restored snapshot, 90 % lookups / 10 % inserts, each timed
+                  (IQM, IQR, p50, p99); `--no-mixed` skips it
   latency_regime  lognormal and clustered keys (2^16, 2^24), half absent:
                   single-launch latency at B = 1..1024 on the full GPU and on
                   a stream masked to 8 CUs (one per XCD); `--no-latency`
@@ -72,6 +75,13 @@ def iqm(x):
     s = s[:n] if n >= 4 else s
     q = len(s) // 4
     return float(s[q:len(s) - q].mean()) if len(s) >= 4 else float(s.mean())
+
+
+def dist_stats(x):
+    """IQM, IQR, p50 and p99 of a sample (µs)."""
+    a = np.asarray(x, dtype=np.float64)
+    return {"iqm": round(iqm(a), 3), "iqr": round(float(np.percentile(a, 75) - np.percentile(a, 25)), 3),
+            "p50": round(float(np.percentile(a, 50)), 3), "p99": round(float(np.percentile(a, 99)), 3)}
 
 
 def algorithmic_bytes(sorted_keys: np.ndarray, q: np.ndarray, height: int, hits: int, kb: int = 8) -> dict:
@@ -169,6 +179,8 @@ def main():
     ap.add_argument("--no-cold", action="store_true", help="skip the flushed (cold-cache) 2^20 batches")
     ap.add_argument("--serve-log2n", type=int, default=26, help="keys of the serving tree (log2)")
     ap.add_argument("--serve-batches", type=int, default=20000, help="batches per open-loop serving run")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the 90/10 lookup/insert batches on a restored snapshot")
     ap.add_argument("--no-latency", action="store_true",
                     help="skip the latency regime (lognormal / clustered keys, full GPU and 8 CUs)")
     ap.add_argument("--log2n", type=int, default=N_LOG2)
@@ -333,9 +345,20 @@ def main():
                 assert g.to_numpy(f2).all() and np.array_equal(
                     g.to_numpy(v2, np.uint64), synth.values_for(qn[(nb - 1) * b:], SEED, 64))
                 del graphs
-                lat = iqm(timer.run(lambda: fn(0), 104, skip=4))
+                # single launches, 100 after 4 warm-up: device time (HIP events)
+                # and call time (host clock around the library call and a
+                # stream synchronisation)
+                dev_t = timer.run(lambda: fn(0), 104, skip=4)
+                call_t = []
+                for r in range(104):
+                    t0 = time.perf_counter()
+                    fn(r % nb)
+                    stream.synchronize()
+                    if r >= 4:
+                        call_t.append((time.perf_counter() - t0) * 1e6)
                 row[path] = {"us_per_batch": round(best, 3), "mops": round(b / best, 2),
-                             "latency_us": round(lat, 3)}
+                             "latency_us": round(iqm(dev_t), 3), "device_us": dist_stats(dev_t),
+                             "call_us": dist_stats(call_t), "mops_by_call": round(b / iqm(call_t), 2)}
             row["learned_speedup"] = round(row["plain"]["us_per_batch"] / row["learned"]["us_per_batch"], 3)
             sweep.setdefault(dist, {})[str(b)] = row
             del qall, qb
@@ -450,6 +473,57 @@ def main():
             levelwise.setdefault(dist, {})[str(b)] = row
             del ws, wsp, qdn, qds
     print("[bench] level-wise done", file=sys.stderr, flush=True)
+
+    # ---- mixed batches on a restored snapshot: per batch size and query
+    # distribution the bulk-loaded tree is restored (a device copy of its
+    # arena, untimed), then R batches run, each a lookup batch with
+    # probability 0.9, else an insert batch of fresh keys; lookups and inserts
+    # are timed separately (single launches, HIP events)
+    mixed = None
+    if not args.no_mixed:
+        tm = g.Tree(keys, vals, 8, leaf_slack=(1 << 22) + (1 << 20), max_batch=1 << 20)
+        snap = tm.arena.clone()
+        sizes_m = (1, 8, 64, 256, 1024, BL)
+        reps_m = {b: (400 if b <= 1024 else 40) for b in sizes_m}
+        kind = {b: synth.Stream(SEED, 9000 + b).uniform01(reps_m[b]) >= 0.9 for b in sizes_m}
+        n_fresh = 2 * sum(int(kind[b].sum()) * b for b in sizes_m)
+        fresh_m = synth.uniform_keys(n_fresh, SEED + 3, 64, purpose=synth.P_INSERT, exclude=keys)
+        fpos_m = 0
+        vm = torch.empty(BL, dtype=torch.int64, device=dev)
+        fm = torch.empty(BL, dtype=torch.uint8, device=dev)
+        sm = torch.empty(BL, dtype=torch.uint8, device=dev)
+        mixed = {"protocol": "restore the bulk-loaded tree, then R batches (400; 40 at 2^20), each a lookup "
+                             "w.p. 0.9 else an insert of fresh keys; per-launch HIP-event times",
+                 "uniform": {}, "zipf": {}}
+        for dist in ("uniform", "zipf"):
+            for b in sizes_m:
+                tm.arena.copy_(snap)
+                torch.cuda.synchronize()
+                nq = min(reps_m[b], 4 if b == BL else reps_m[b])
+                qn = synth.present_queries(keys, nq * b, SEED, purpose=9500 + b) if dist == "uniform" else \
+                    keys[zipf.indices(nq * b)]
+                qdm = tm.dev(qn)
+                lt, it = [], []
+                for r in range(reps_m[b]):
+                    if kind[b][r]:
+                        k = fresh_m[fpos_m:fpos_m + b]
+                        fpos_m += b
+                        kd, vd = tm.dev(k), tm.dev(synth.values_for(k, SEED, 64))
+                        it += timer.run(lambda: g.tree_insert_batch(tm.h, kd, vd, sm[:b], stream), 1, skip=0)
+                    else:
+                        j = r % nq
+                        qq = qdm[j * b:(j + 1) * b]
+                        lt += timer.run(lambda: g.tree_lookup_batch(tm.h, qq, vm[:b], fm[:b], stream), 1, skip=0)
+                assert g.tree_device_error(tm.h) == g.GT_OK
+                mixed[dist][str(b)] = {"lookups": len(lt), "inserts": len(it),
+                                       "lookup_us": dist_stats(lt) if lt else None,
+                                       "insert_us": dist_stats(it) if it else None,
+                                       "lookup_mops": round(b / iqm(lt), 3) if lt else None,
+                                       "insert_mkeys_per_s": round(b / iqm(it), 3) if it else None}
+                del qdm
+        tm.close()
+        del snap, fresh_m
+        print("[bench] mixed batches done", file=sys.stderr, flush=True)
 
     # ---- latency regime: lognormal and clustered keys (2^16 and 2^24), half
     # present and half absent queries, B = 1, 2, 4, ..., 1024 and 1000;
@@ -722,6 +796,7 @@ def main():
         "large_batch": large,
         "levelwise": levelwise,
         "latency_regime": latency,
+        "mixed_90_10": mixed,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_lookup<unsigned long, 8, 4, 2, true, false> (B=2^20, warm)",
