@@ -347,7 +347,10 @@ typedef struct {
     uint32_t max_range;      /* largest per-query range length; 0 = 128     */
     uint32_t use_graphs;     /* 1 = replay captured graphs, 2 = direct
                                 launches; 0 = default (1)                   */
-    uint32_t reserved;       /* must be 0                                   */
+    uint32_t retrain_log2;   /* with a learned index: after 2^retrain_log2
+                                inserted keys the server pauses admission,
+                                lets in-flight batches finish and retrains
+                                the index (li_train); 0 = never; at most 40 */
 } gt_srv_params;
 
 enum { GT_OP_LOOKUP = 0, GT_OP_INSERT = 1, GT_OP_RANGE = 2 };
@@ -380,6 +383,8 @@ typedef struct {
     double busy_frac;        /* share of wall_s in which the device worked on
                                 at least one batch (copies included), from
                                 timing events around each batch              */
+    uint64_t retrains;       /* learned-index retrainings since creation     */
+    double retrain_s;        /* their total time                             */
 } gt_srv_stats;
 
 /* Create a server over tree t (and learned index li for lookups, or NULL).

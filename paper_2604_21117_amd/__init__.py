@@ -62,7 +62,7 @@ class gt_li_stats(C.Structure):
 class gt_srv_params(C.Structure):
     _fields_ = [("read_streams", C.c_uint32), ("slots", C.c_uint32), ("mem_cap", C.c_uint64),
                 ("max_batch", C.c_uint32), ("max_range", C.c_uint32), ("use_graphs", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("retrain_log2", C.c_uint32)]
 
 
 class gt_request(C.Structure):
@@ -75,7 +75,8 @@ class gt_srv_stats(C.Structure):
     _fields_ = [("done", C.c_uint64 * 3), ("ops", C.c_uint64 * 3), ("refused", C.c_uint64),
                 ("graph_launches", C.c_uint64), ("direct_launches", C.c_uint64), ("wall_s", C.c_double),
                 ("p50_us", C.c_double), ("p99_us", C.c_double), ("p50_us_op", C.c_double * 3),
-                ("p99_us_op", C.c_double * 3), ("busy_frac", C.c_double)]
+                ("p99_us_op", C.c_double * 3), ("busy_frac", C.c_double), ("retrains", C.c_uint64),
+                ("retrain_s", C.c_double)]
 
 
 OP_LOOKUP, OP_INSERT, OP_RANGE = 0, 1, 2
@@ -456,9 +457,10 @@ class Learned:
 
 # ----------------------------------------------------------------- serving
 
-def srv_params(read_streams=0, slots=0, mem_cap=0, max_batch=0, max_range=0, use_graphs=0) -> gt_srv_params:
+def srv_params(read_streams=0, slots=0, mem_cap=0, max_batch=0, max_range=0, use_graphs=0,
+               retrain_log2=0) -> gt_srv_params:
     return gt_srv_params(read_streams=read_streams, slots=slots, mem_cap=mem_cap, max_batch=max_batch,
-                         max_range=max_range, use_graphs=use_graphs, reserved=0)
+                         max_range=max_range, use_graphs=use_graphs, retrain_log2=retrain_log2)
 
 
 class Batch:

@@ -4,6 +4,10 @@
 // One worker thread owns every HIP call of the server.  Each pass it
 //   1. retires finished batches (event query), copies their outputs from
 //      pinned staging to the caller's buffers and frees slot and bytes;
+//  1b. with a learned index and retrain_log2 set: once 2^retrain_log2 keys
+//      were inserted since training, admission pauses, and when no batch is
+//      in flight the index is retrained (its lookup graphs are captured
+//      again on their next use);
 //   2. admits queued batches in arrival order while a slot is free and the
 //      staged bytes in flight stay under the cap (a batch larger than the
 //      cap is refused at once, so admission never deadlocks);
@@ -105,6 +109,11 @@ struct gt_server {
     uint64_t bytes_inflight = 0;
     uint32_t inflight = 0;
     uint64_t graph_launches = 0, direct_launches = 0;
+    uint64_t inserted_since_train = 0;  // keys of completed insert batches since the last retrain
+    bool retrain_pending = false;       // admission paused until in-flight batches drain
+    bool training = false;              // li_train running on the worker
+    uint64_t retrains = 0;
+    double retrain_s = 0.0;
     std::vector<uint64_t> last_replay;
     hipError_t fatal = hipSuccess;
 };
@@ -264,6 +273,10 @@ void worker_loop(gt_server* s) {
             if (hipEventQuery(sl.ev) != hipSuccess) continue;
             Req& q = s->reqs[sl.ticket];
             retire(s, sl, q);
+            if (q.r.op == GT_OP_INSERT && !q.failed && s->li && s->p.retrain_log2) {
+                s->inserted_since_train += q.r.B;
+                if (s->inserted_since_train >= (1ull << s->p.retrain_log2)) s->retrain_pending = true;
+            }
             if (s->ref_set) {
                 float a = 0, b = 0;
                 if (hipEventElapsedTime(&a, s->ref_ev, sl.ev0) == hipSuccess &&
@@ -280,8 +293,27 @@ void worker_loop(gt_server* s) {
             did = true;
         }
         if (did) s->cv_done.notify_all();
+        // 1b. retrain the learned index once enough keys were inserted: no
+        //     batch is admitted meanwhile, and training starts when none is in
+        //     flight
+        if (s->retrain_pending && s->inflight == 0 && s->fatal == hipSuccess) {
+            const double t0 = now_s();
+            s->training = true;
+            lk.unlock();
+            const gt_status st = li_train(s->li, s->cstream);
+            lk.lock();
+            s->training = false;
+            if (st != GT_OK) s->fatal = hipErrorUnknown;
+            s->retrains++;
+            s->retrain_s += now_s() - t0;
+            // every inserted key is in the tree the index was trained on
+            s->inserted_since_train = 0;
+            s->retrain_pending = false;
+            s->cv_done.notify_all();
+            did = true;
+        }
         // 2. admit in arrival order
-        while (!s->queue.empty() && s->fatal == hipSuccess) {
+        while (!s->queue.empty() && s->fatal == hipSuccess && !s->retrain_pending) {
             const uint64_t tk = s->queue.front();
             Req& q = s->reqs[tk];
             const uint32_t bucket = pow2ceil(q.r.B ? q.r.B : 1);
@@ -436,7 +468,7 @@ gt_status srv_create(gt_tree* t, gt_learned* li, const gt_srv_params* p, gt_serv
     if (!t || !out) return GT_ERR_INVALID;
     gt_srv_params q{};
     if (p) q = *p;
-    if (q.reserved || q.use_graphs > 2) return GT_ERR_INVALID;
+    if (q.use_graphs > 2 || q.retrain_log2 > 40) return GT_ERR_INVALID;
     if (!q.read_streams) q.read_streams = 4;
     if (!q.slots) q.slots = 16;
     if (!q.mem_cap) q.mem_cap = 32ull << 30;
@@ -526,7 +558,9 @@ gt_status srv_replay(gt_server* s, const gt_request* reqs, uint64_t n) {
         if (st == GT_ERR_HIP) return st;
         if (st != GT_OK) res = GT_ERR_ADMISSION;
     }
-    std::lock_guard<std::mutex> lk(s->mu);
+    std::unique_lock<std::mutex> lk(s->mu);
+    // a retraining these inserts started is part of the replay
+    s->cv_done.wait(lk, [&] { return (!s->retrain_pending && !s->training) || s->fatal != hipSuccess; });
     s->last_replay = tickets;
     return res;
 }
@@ -557,6 +591,8 @@ gt_status srv_stats(gt_server* s, gt_srv_stats* out) {
     }
     out->graph_launches = s->graph_launches;
     out->direct_launches = s->direct_launches;
+    out->retrains = s->retrains;
+    out->retrain_s = s->retrain_s;
     out->wall_s = all.empty() ? 0.0 : last - first;
     out->p50_us = percentile(all, 0.5);
     out->p99_us = percentile(all, 0.99);

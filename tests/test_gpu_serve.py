@@ -164,6 +164,34 @@ def test_server_recaptures_after_learned_changes():
     srv.close()
 
 
+def test_server_retrains_learned_index():
+    """With retrain_log2 set, the server retrains the learned index after
+    every 2^retrain_log2 inserted keys (admission paused, in-flight batches
+    drained) and recaptures its lookup graphs; every result still equals the
+    sequential replay, and the index ends trained on the inserted keys."""
+    import paper_2604_21117_amd as g
+    seed = 74
+    keys, vals, fresh = _setup(seed, n=1 << 16)
+    sa = oracle.SortedArray(keys, vals, 64)
+    t = mk_tree(keys, vals, 8, leaf_slack=1 << 15, max_batch=1024)
+    li = g.Learned(t, models=128)
+    li.train()
+    n0 = li.stats()["trained_keys"]
+    srv = g.Server(t, learned=li, slots=8, read_streams=4, retrain_log2=13)
+    spec = synth.serving_mix(keys, 400, seed, bmax=512, rate=30000.0, fresh=fresh)
+    batches = _batches(spec)
+    assert srv.replay(batches) == g.GT_OK
+    _compare(batches, _oracle_replay(sa, batches))
+    inserted = sum(len(b.keys) for b in batches if b.op == 1)
+    st = srv.stats()
+    assert 1 <= st["retrains"] <= inserted >> 13, (st["retrains"], inserted)
+    assert st["retrain_s"] > 0
+    assert li.stats()["trained_keys"] > n0
+    srv.close()
+    bits, ek, ev = oracle.check_export(t.export(), len(sa))
+    assert bits == 0 and np.array_equal(ek, sa.keys)
+
+
 def test_admission_cap():
     import paper_2604_21117_amd as g
     seed = 72
