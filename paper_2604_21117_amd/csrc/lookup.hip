@@ -106,25 +106,40 @@ __global__ __launch_bounds__(kLookupBlock) void k_lookup(TreeView<K> t, const K*
     }
 }
 
-// XCD-split lookup for large batches.  Workgroup w runs on XCD w % 8 (the
-// dispatcher deals workgroups to XCDs round-robin).  Each workgroup reads
-// a chunk of the batch, keeps the queries whose key lies in its XCD's key
-// range (seven splitter keys cut the tree into eight runs of level-2
-// subtrees) and walks only those, so the inner nodes an XCD touches are
-// one eighth of the tree and stay in its own L2.  Every chunk is read by
-// eight workgroups; results are written by query index, so the output is
-// the same as the plain kernel's.
-constexpr uint32_t kXcdChunk = 1024;
+// Position of the t-th set bit (t counted from 0) of m; m has more than t.
+__device__ __forceinline__ int nth_set_bit(uint64_t m, uint32_t t) {
+    int pos = 0;
+#pragma unroll
+    for (int w = 32; w > 0; w >>= 1) {
+        const uint32_t c = static_cast<uint32_t>(__popcll(m & ((1ull << w) - 1ull)));
+        if (t >= c) {
+            t -= c;
+            m >>= w;
+            pos += w;
+        }
+    }
+    return pos;
+}
 
-template <class K, int G, int QPG, bool VC, bool NT>
+// XCD-split lookup for large batches.  Workgroup w runs on XCD w % 8 (the
+// dispatcher deals workgroups to XCDs round-robin).  Seven splitter keys cut
+// the key space into eight ranges, and XCD x answers the queries of range x
+// only, so the leaf parents it reads (an eighth of them) stay in its own L2.
+// Every wave of XCD x reads four 64-query chunks of the batch at a time (one
+// coalesced load each), keeps the queries of its range with one ballot per
+// chunk, and deals them to its eight 8-lane groups, four queries per group
+// per round.  Each chunk is read by one wave of every XCD; results go by
+// query index, so the output is the plain kernel's.  All lanes stay active
+// through a round (the groups' cross-lane reads need their source lanes).
+constexpr int kXcdChunks = 4;  // 64-query chunks a wave reads at once
+
+template <class K, bool VC, bool NT>
 __global__ __launch_bounds__(kLookupBlock) void k_lookup_xcd(TreeView<K> t, const K* __restrict__ q, uint64_t B,
                                                               K* __restrict__ vout, uint8_t* __restrict__ fout,
                                                               uint64_t nchunks) {
-    constexpr int LV = 2;
+    constexpr int G = 8, LV = 2, QPG = kXcdChunks;
+    constexpr uint32_t kGroups = 64 / G;
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ K ck[kXcdChunk];
-    __shared__ uint32_t ci[kXcdChunk];
-    __shared__ uint32_t ccount;
     const uint32_t mnodes = mirror_nodes_for_levels(LV);
     stage_mirror<K>(t.mirror, lds, mnodes);
     const MirrorHeader* gmh = reinterpret_cast<const MirrorHeader*>(t.mirror);
@@ -134,51 +149,71 @@ __global__ __launch_bounds__(kLookupBlock) void k_lookup_xcd(TreeView<K> t, cons
 #pragma unroll
     for (int x = 0; x < kXcds - 1; ++x) split[x] = sp[x];
     __syncthreads();
-    const MirrorHeader* mh = reinterpret_cast<const MirrorHeader*>(lds);
-    const bool empty = mh->n_keys == 0;
+    const bool empty = reinterpret_cast<const MirrorHeader*>(lds)->n_keys == 0;
     const uint32_t xcd = blockIdx.x % kXcds;
-    const uint64_t slot0 = blockIdx.x / kXcds, nslots = gridDim.x / kXcds;
     const int lane = lane_id();
     const int gl = lane % G, gbase = lane - gl;
-    const uint32_t group = threadIdx.x / G;
-    constexpr uint32_t tile_q = (kLookupBlock / G) * QPG;
-    for (uint64_t c = slot0; c < nchunks; c += nslots) {
-        if (threadIdx.x == 0) ccount = 0;
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < kXcdChunk; i += kLookupBlock) {
-            const uint64_t qi = c * kXcdChunk + i;
-            if (qi < B) {
-                const K key = q[qi];
-                uint32_t b = 0;
-                if (nsplit) {
+    const uint32_t grp = static_cast<uint32_t>(lane / G);
+    constexpr int kWaves = kLookupBlock / 64;
+    const uint64_t wave_in_xcd = static_cast<uint64_t>(blockIdx.x / kXcds) * kWaves + threadIdx.x / 64;
+    const uint64_t waves_per_xcd = static_cast<uint64_t>(gridDim.x / kXcds) * kWaves;
+    const uint64_t nsets = (nchunks + kXcdChunks - 1) / kXcdChunks;
+    for (uint64_t set = wave_in_xcd; set < nsets; set += waves_per_xcd) {
+        K key[kXcdChunks];
+        uint64_t m[kXcdChunks];
 #pragma unroll
-                    for (int x = 0; x < kXcds - 1; ++x) b += split[x] < key ? 1u : 0u;
-                } else {
-                    b = static_cast<uint32_t>(qi % kXcds);
-                }
-                if (b == xcd) {
-                    const uint32_t pos = atomicAdd(&ccount, 1u);
-                    ck[pos] = key;
-                    ci[pos] = static_cast<uint32_t>(i);
-                }
+        for (int k = 0; k < kXcdChunks; ++k) {
+            const uint64_t qi = (set * kXcdChunks + k) * 64 + static_cast<uint64_t>(lane);
+            const bool valid = qi < B;
+            key[k] = valid ? q[qi] : K(0);
+            uint32_t b = 0;
+            if (nsplit) {
+#pragma unroll
+                for (int x = 0; x < kXcds - 1; ++x) b += split[x] < key[k] ? 1u : 0u;
+            } else {
+                b = static_cast<uint32_t>(qi % kXcds);
             }
+            m[k] = __ballot(valid && b == xcd);
         }
-        __syncthreads();
-        const uint32_t n = ccount;
-        for (uint32_t t0 = 0; t0 < n; t0 += tile_q) {
-            K key[QPG];
-            uint64_t qi[QPG];
+        uint32_t left = 0;
+#pragma unroll
+        for (int k = 0; k < kXcdChunks; ++k) left += static_cast<uint32_t>(__popcll(m[k]));
+        for (uint32_t r0 = 0; r0 < left; r0 += kGroups * QPG) {  // the same for the whole wave
+            // group grp takes the selected queries of rank r0 + grp + 8 j
+            K kk[QPG];
+            uint64_t qq[QPG];
 #pragma unroll
             for (int j = 0; j < QPG; ++j) {
-                const uint32_t e = t0 + group * QPG + j;
-                key[j] = e < n ? ck[e] : K(0);
-                qi[j] = e < n ? c * kXcdChunk + ci[e] : ~0ull;
+                uint32_t rank = r0 + grp + kGroups * static_cast<uint32_t>(j);
+                const bool live = rank < left;
+                int chunk = 0, src = 0;
+                if (live) {
+#pragma unroll
+                    for (int k = 0; k < kXcdChunks; ++k) {
+                        const uint32_t c = static_cast<uint32_t>(__popcll(m[k]));
+                        if (chunk == k && rank >= c) {
+                            rank -= c;
+                            chunk = k + 1;
+                        }
+                    }
+                    src = nth_set_bit(m[chunk], rank);
+                }
+                // a cross-lane read returns the source lane's register, so
+                // read every chunk's key there and keep the wanted one
+                K kx = K(0);
+#pragma unroll
+                for (int k = 0; k < kXcdChunks; ++k) {
+                    const K v = static_cast<K>(__shfl(key[k], src, 64));
+                    if (chunk == k) kx = v;
+                }
+                kk[j] = kx;
+                qq[j] = live ? (set * kXcdChunks + static_cast<uint64_t>(chunk)) * 64 + static_cast<uint64_t>(src)
+                             : ~0ull;
             }
             uint32_t leaf[QPG];
-            descend<K, G, QPG, false>(t, lds, mnodes, LV, key, leaf, gl, gbase);
-            finish_lookups<K, G, QPG, VC, NT>(t, key, leaf, qi, empty, gl, gbase, vout, fout);
+            descend<K, G, QPG, false>(t, lds, mnodes, LV, kk, leaf, gl, gbase);
+            finish_lookups<K, G, QPG, VC, NT>(t, kk, leaf, qq, empty, gl, gbase, vout, fout);
         }
-        __syncthreads();
     }
 }
 
@@ -288,13 +323,16 @@ static void launch_lookup_t(const TreeView<K>& t, const K* q, uint64_t B, K* vou
                        lds_bytes_for(LV, sizeof(K)), s, t, q, B, vout, fout, ntiles);
 }
 
-template <class K, int G, int QPG, bool VC, bool NT>
+template <class K, bool VC, bool NT>
 static void launch_lookup_xcd(const TreeView<K>& t, const K* q, uint64_t B, K* vout, uint8_t* fout, hipStream_t s) {
-    const uint64_t nchunks = (B + kXcdChunk - 1) / kXcdChunk;
-    // eight resident workgroups per CU, 32 CUs per XCD
-    const uint64_t slots = nchunks < 256 ? nchunks : 256;
-    hipLaunchKernelGGL((k_lookup_xcd<K, G, QPG, VC, NT>), dim3(static_cast<uint32_t>(slots * kXcds)),
-                       dim3(kLookupBlock), lds_bytes_for(2, sizeof(K)), s, t, q, B, vout, fout, nchunks);
+    const uint64_t nchunks = (B + 63) / 64;
+    // per XCD up to 256 workgroups (8 per CU) of four waves; every XCD reads
+    // every chunk, four at a time per wave
+    uint64_t per_xcd = (nchunks + 4 * kXcdChunks - 1) / (4 * kXcdChunks);
+    if (per_xcd > 256) per_xcd = 256;
+    if (per_xcd < 1) per_xcd = 1;
+    hipLaunchKernelGGL((k_lookup_xcd<K, VC, NT>), dim3(static_cast<uint32_t>(per_xcd * kXcds)), dim3(kLookupBlock),
+                       lds_bytes_for(2, sizeof(K)), s, t, q, B, vout, fout, nchunks);
 }
 
 template <class K, int G, int QPG, int LV>
@@ -303,11 +341,11 @@ static void launch_lookup_v(const TreeView<K>& t, const LaunchCfg& cfg, const K*
     const bool xcd = cfg.xcd_split == 2 || (cfg.xcd_split == 1 && B >= kXcdMinBatch);
     if (xcd) {
         if (cfg.value_coload) {
-            if (cfg.leaf_stream) launch_lookup_xcd<K, G, QPG, true, true>(t, q, B, vout, fout, s);
-            else launch_lookup_xcd<K, G, QPG, true, false>(t, q, B, vout, fout, s);
+            if (cfg.leaf_stream) launch_lookup_xcd<K, true, true>(t, q, B, vout, fout, s);
+            else launch_lookup_xcd<K, true, false>(t, q, B, vout, fout, s);
         } else {
-            if (cfg.leaf_stream) launch_lookup_xcd<K, G, QPG, false, true>(t, q, B, vout, fout, s);
-            else launch_lookup_xcd<K, G, QPG, false, false>(t, q, B, vout, fout, s);
+            if (cfg.leaf_stream) launch_lookup_xcd<K, false, true>(t, q, B, vout, fout, s);
+            else launch_lookup_xcd<K, false, false>(t, q, B, vout, fout, s);
         }
         return;
     }
