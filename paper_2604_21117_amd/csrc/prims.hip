@@ -176,19 +176,43 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* keys, uint64
     if (threadIdx.x < 256) gh[static_cast<uint64_t>(threadIdx.x) * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
+// Stable scatter of one tile for one digit.  The tile's elements are first
+// placed in LDS in (digit, original order) order, then written out in that
+// order, so consecutive threads store consecutive positions of one digit's
+// run (coalesced lines instead of one line per lane).
 template <class K>
 __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* kin, const uint32_t* iin, K* kout,
                                                                uint32_t* iout, uint64_t n, int shift,
                                                                const uint32_t* gofs, uint32_t ntiles) {
     __shared__ uint32_t wcnt[kSortBlock / 64][256];
     __shared__ uint32_t run[256];
-    __shared__ uint32_t base[256];
+    __shared__ uint32_t base[256];   // global position of this tile's run of digit d
+    __shared__ uint32_t lstart[256]; // position of that run inside the tile
+    __shared__ uint32_t sh[33];
+    __shared__ K tk[kSortTile];
+    __shared__ uint32_t ti[kSortTile];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const uint64_t tbase = static_cast<uint64_t>(blockIdx.x) * kSortTile;
     if (tid < 256) {
         run[tid] = 0;
-        base[tid] = gofs[static_cast<uint64_t>(tid) * ntiles + blockIdx.x];
+        const uint64_t at = static_cast<uint64_t>(tid) * ntiles + blockIdx.x;
+        base[tid] = gofs[at];
     }
-    const uint64_t tbase = static_cast<uint64_t>(blockIdx.x) * kSortTile;
+    __syncthreads();
+    // this tile's count of digit d: the next offset in digit-major order
+    // (the next tile's for d, or the next digit's first tile) minus its own
+    {
+        uint32_t c = 0;
+        if (tid < 256) {
+            const uint64_t at = static_cast<uint64_t>(tid) * ntiles + blockIdx.x;
+            const uint64_t nxt = at + 1 < static_cast<uint64_t>(ntiles) * 256 ? gofs[at + 1] : n;
+            c = static_cast<uint32_t>(nxt - base[tid]);
+        }
+        uint32_t tot;
+        const uint32_t st = block_excl_scan<uint32_t>(c, sh, &tot);
+        if (tid < 256) lstart[tid] = st;
+    }
+    __syncthreads();
     const uint64_t lt = (1ull << lane) - 1ull;
     for (int r = 0; r < kSortRounds; ++r) {
         uint32_t* flat = &wcnt[0][0];
@@ -219,11 +243,19 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* kin, cons
         }
         __syncthreads();
         if (valid) {
-            uint32_t dst = base[d] + wcnt[w][d] + rank;
-            kout[dst] = k;
-            iout[dst] = iin[i];
+            const uint32_t p = lstart[d] + wcnt[w][d] + rank;  // place in the tile
+            tk[p] = k;
+            ti[p] = iin[i];
         }
         __syncthreads();
+    }
+    const uint64_t cnt = n - tbase < kSortTile ? n - tbase : kSortTile;
+    for (uint32_t p = tid; p < cnt; p += kSortBlock) {
+        const K k = tk[p];
+        const uint32_t d = static_cast<uint32_t>(k >> shift) & 255u;
+        const uint64_t dst = static_cast<uint64_t>(base[d]) + (p - lstart[d]);
+        kout[dst] = k;
+        iout[dst] = ti[p];
     }
 }
 
