@@ -66,6 +66,7 @@ struct Ins {
     K* nk; K* nv; uint32_t* nleaf; uint32_t* nu;
     uint32_t* it_node; uint32_t* it_rep; uint32_t* it_first; uint32_t* it_end;
     uint32_t* it_cold; uint32_t* it_k; uint32_t* it_off;
+    uint8_t* it_cs;  // slot of the item's node in its parent
     K* psep;
     K* gsep0; K* gsep1; uint32_t* gid0; uint32_t* gid1;
     uint64_t Bm, ip_cap, ps_cap;
@@ -126,6 +127,7 @@ static uint64_t carve(Ins<K>* v, uint8_t* base, uint64_t Bm, uint64_t leaf_cap, 
     x.it_cold = reinterpret_cast<uint32_t*>(take(ip * 4));
     x.it_k = reinterpret_cast<uint32_t*>(take(ip * 4));
     x.it_off = reinterpret_cast<uint32_t*>(take(ip * 4));
+    x.it_cs = take(ip);
     x.psep = reinterpret_cast<K*>(take(ps * sizeof(K)));
     x.gsep0 = reinterpret_cast<K*>(take(ps * sizeof(K)));
     x.gsep1 = reinterpret_cast<K*>(take(ps * sizeof(K)));
@@ -290,7 +292,9 @@ __global__ void k_leaf_items(Ins<K> v) {
 template <class K>
 __device__ __forceinline__ void ph_leaf_plan(TreeView<K> t, Ins<K> v, uint64_t tid, uint64_t nth) {
     const uint64_t T0 = v.st->lvl_count[0];
+    const int h = static_cast<int>(v.st->height);
     for (uint64_t i = tid; i < T0; i += nth) {
+        if (h >= 2) v.it_cs[i] = v.pi[static_cast<uint64_t>(h - 2) * v.Bm + v.it_rep[i]];
         const uint32_t c = t.lmeta[v.it_node[i]].x;
         const uint64_t total = static_cast<uint64_t>(c) + (v.it_end[i] - v.it_first[i]);
         const uint32_t k = split_pieces(total);
@@ -364,7 +368,9 @@ __device__ __forceinline__ void ph_par_plan(TreeView<K> t, Ins<K> v, int d, uint
     const uint64_t n = v.st->lvl_count[d];
     const uint32_t bd = v.st->lvl_base[d];
     const uint32_t bc = v.st->lvl_base[d - 1];
+    const int lp = static_cast<int>(v.st->height) - 2 - d;  // tree level of the items' parents
     for (uint64_t j = tid; j < n; j += nth) {
+        if (lp >= 0) v.it_cs[bd + j] = v.pi[static_cast<uint64_t>(lp) * v.Bm + v.it_rep[bd + j]];
         const uint32_t node = v.it_node[bd + j];
         uint32_t C = 0;
         const uint32_t* ch = t.ichild + static_cast<uint64_t>(node) * kSlots;
@@ -468,8 +474,9 @@ constexpr int kNodeLanes = 16;
 // Merge-split of the touched leaves: kNodeLanes lanes per leaf.
 template <class K>
 __global__ __launch_bounds__(kBlk) void k_apply_leaves(TreeView<K> t, Ins<K> v) {
-    if (!v.st->ok) return;
+    const uint32_t ok = v.st->ok;
     const uint64_t T0 = v.st->lvl_count[0];
+    if (!ok || T0 == 0) return;
     const int gl = lane_id() % kNodeLanes, gbase = lane_id() - gl;
     const uint64_t grp = gtid() / kNodeLanes, ngrp = gstride() / kNodeLanes;
     const uint32_t alloc = v.st->lvl_alloc[0];
@@ -512,7 +519,19 @@ __global__ __launch_bounds__(kBlk) void k_apply_leaves(TreeView<K> t, Ins<K> v) 
             }
         };
         const bool has_old = gl < static_cast<int>(c);
-        const uint64_t opos = has_old ? gl + lower_bound_dev(nk, r, okey) : ~0ull;
+        uint64_t opos = ~0ull;
+        if (one_run) {
+            // new keys below this lane's old key, from the group's lanes
+            const K mine = static_cast<uint32_t>(gl) < r ? nk[gl] : K(0);
+            uint32_t below = 0;
+            for (uint32_t s = 0; s < r; ++s) {
+                const K ks = __shfl(mine, gbase + static_cast<int>(s), 64);
+                below += ks < okey ? 1u : 0u;
+            }
+            if (has_old) opos = gl + below;
+        } else if (has_old) {
+            opos = gl + lower_bound_dev(nk, r, okey);
+        }
         if (has_old) place(opos, okey, oval);
         uint64_t npos = ~0ull;
         K nkey = K(0);
@@ -557,10 +576,10 @@ __global__ __launch_bounds__(kBlk) void k_apply_leaves(TreeView<K> t, Ins<K> v) 
 // Rebuild the changed parents of level d: kNodeLanes lanes per parent.
 template <class K>
 __global__ __launch_bounds__(kBlk) void k_apply_inner(TreeView<K> t, Ins<K> v, int d) {
-    if (!v.st->ok) return;
+    const uint32_t ok = v.st->ok;
     const int h = static_cast<int>(v.st->height);
     const int l = h - 1 - d;
-    if (l < 0) return;
+    if (!ok || l < 0) return;
     const uint64_t n = v.st->lvl_count[d];
     const uint32_t bd = v.st->lvl_base[d], bc = v.st->lvl_base[d - 1];
     const uint32_t alloc = v.st->lvl_alloc[d], alloc_c = v.st->lvl_alloc[d - 1];
@@ -577,19 +596,27 @@ __global__ __launch_bounds__(kBlk) void k_apply_inner(TreeView<K> t, Ins<K> v, i
         const uint32_t off = v.it_off[bd + j];
         const K osep = t.ikeys[static_cast<uint64_t>(node) * kSlots + lane];
         const uint32_t ochild = t.ichild[static_cast<uint64_t>(node) * kSlots + lane];
+        // the child items (one per changed child node, so at most kSlots),
+        // one per lane: slot in this node, piece count, first new piece
+        const uint32_t nci = end - first < static_cast<uint32_t>(kNodeLanes) ? end - first : kNodeLanes;
+        uint32_t ccs = kNone, cks = 1, cof = 0;
+        if (lane < nci) {
+            ccs = v.it_cs[bc + first + lane];
+            cks = v.it_k[bc + first + lane];
+            cof = v.it_off[bc + first + lane];
+        }
         // per old slot: shift from split children before it, and its own item
-        uint32_t shift = 0, myk = 1, myitem = kNone;
+        uint32_t shift = 0, myk = 1, myoff = 0;
         uint64_t a = 0;
-        for (uint32_t i = first; i < end; ++i) {
-            const uint32_t cs = v.pi[static_cast<uint64_t>(l) * v.Bm + v.it_rep[bc + i]];
-            const uint32_t ki = v.it_k[bc + i];
+        for (uint32_t i = 0; i < nci; ++i) {
+            const int src = gbase + static_cast<int>(i);
+            const uint32_t cs = shfl_u32(ccs, src), ki = shfl_u32(cks, src), oi = shfl_u32(cof, src);
             a += ki - 1;
             if (cs < lane) shift += ki - 1;
-            if (cs == lane) { myk = ki; myitem = i; }
+            if (cs == lane) { myk = ki; myoff = oi; }
         }
         __threadfence_block();  // the old node is in registers before any write
         if (a == 0) continue;   // no child split: the parent is unchanged
-        const uint32_t myoff = myitem != kNone ? v.it_off[bc + myitem] : 0u;
         const uint32_t newpos = lane + shift;
         const uint64_t Cp = C + a;
         const uint32_t base_new = alloc + off;
@@ -787,43 +814,266 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_prefix(Ins<K> v, const De
     if (tid == 0) v.st->U = tot;
 }
 
+// Old entry count of node `node` at level d (0 = leaves): a leaf's count, or
+// the number of child references of an inner node.
 template <class K>
-__global__ __launch_bounds__(kSmallBlock) void k_small_plan(TreeView<K> t, Ins<K> v0, int H) {
+__device__ __forceinline__ uint32_t old_count(const TreeView<K>& t, uint32_t node, bool leaf) {
+    if (leaf) return t.lmeta[node].x;
+    const uint4* ch = reinterpret_cast<const uint4*>(t.ichild + static_cast<uint64_t>(node) * kSlots);
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < kSlots / 4; ++q) {
+        const uint4 x = ch[q];
+        c += (x.x != kNone) + (x.y != kNone) + (x.z != kNone) + (x.w != kNone);
+    }
+    return c;
+}
+
+// Exclusive scan over the plan's workgroup: one wave needs no LDS.
+template <int NT>
+__device__ __forceinline__ uint32_t plan_scan(uint32_t x, uint32_t* sh, uint32_t* total) {
+    if constexpr (NT == 64) {
+        const uint32_t inc = wave_incl_scan(x);
+        *total = __shfl(inc, 63, 64);
+        return inc - x;
+    } else {
+        return block_excl_scan<uint32_t>(x, sh, total);
+    }
+}
+
+// Plan of a small batch, one workgroup of NT threads (NT >= B / 2); thread t
+// owns new keys 2t and 2t+1.  Small NT keeps the barriers cheap (one wave
+// for B <= 128), and the level loops stay rolled so that the kernel's code
+// stays small (a single wave runs it once, so every instruction line it
+// touches is a cache miss).
+//
+// The nodes a new key passes through are known from the locate kernel (its
+// leaf and its parent at every level), so the items of every level (runs of
+// new keys through one node) are cut first, level after level in LDS with
+// block scans.  The old entry counts of all items of all levels are then
+// read in one round of loads, and the piece counts follow level after level:
+// an item gains the new keys of its run (leaves) or sum(k - 1) over its child
+// items (inner nodes), both taken as differences of a prefix sum over the
+// run's keys.  Writes the same item arrays and level counters as the general
+// path, and then the values of keys already present.
+template <class K, int NT>
+__global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int H) {
+    constexpr int kL = kMaxLevels;
+    constexpr uint32_t kCap = 2 * NT;  // new keys, items per level
     __shared__ uint32_t sh[33];
-    __shared__ uint32_t sf0[kSmallInsert + 1], sf1[kSmallInsert + 1];
-    const uint64_t tid = threadIdx.x, nth = blockDim.x;
-    // the flag and scan arrays live in LDS here (every phase reads what the
-    // previous one wrote); the locate kernel left the new-key flags in f0
-    for (uint32_t i = static_cast<uint32_t>(tid); i < v0.st->U; i += static_cast<uint32_t>(nth)) sf0[i] = v0.f0[i];
-    Ins<K> v = v0;
-    v.f0 = sf0;
-    v.f1 = sf1;
-    __syncthreads();
-    block_scan_small(v.f0, v.f1, v.st->U, &v.st->R, sh);
-    ph_compact_new<K>(v, tid, nth);
-    __syncthreads();
-    ph_leaf_heads<K>(v, tid, nth);
-    __syncthreads();
-    block_scan_small(v.f0, v.f1, v.st->R, &v.st->lvl_count[0], sh);
-    ph_leaf_items<K>(v, tid, nth);
-    __syncthreads();
-    ph_leaf_plan<K>(t, v, tid, nth);
-    __syncthreads();
-    block_scan_small(v.f0, v.it_off, v.st->lvl_count[0], &v.st->lvl_new[0], sh);
+    __shared__ uint32_t s_a[kCap], s_b[kCap];  // key -> distinct key, node; later prefix sums at item bounds
+    __shared__ uint16_t s_ix[kL * kCap];       // item index of each key, per level
+    __shared__ uint32_t s_k[kCap];             // piece counts of the previous level's items
+    __shared__ uint8_t s_C[kL * kCap];         // old entry count of every item
+    __shared__ uint32_t s_base[kL + 1];        // first item of each level
+    __shared__ uint32_t s_over;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t U = v.st->U;
     const int h = static_cast<int>(v.st->height);
-    for (int d = 1; d < H && d < h; ++d) {
-        ph_par_heads<K>(v, d, tid, nth);
+    const int hmax = H < h ? H : h;
+    if (tid == 0) s_over = 0;
+
+    // new keys in key order (locate left f0[u] = 1 for a key not in its leaf)
+    uint32_t fl[2];
+    for (int j = 0; j < 2; ++j) {
+        const uint32_t u = 2 * tid + j;
+        fl[j] = u < U ? v.f0[u] : 0u;
+    }
+    uint32_t R;
+    const uint32_t o0 = plan_scan<NT>(fl[0] + fl[1], sh, &R);
+    for (int j = 0; j < 2; ++j) {
+        if (!fl[j]) continue;
+        const uint32_t u = 2 * tid + j, r = o0 + (j ? fl[0] : 0u);
+        const uint32_t leaf = v.uleaf[u];
+        v.nk[r] = v.uk[u];
+        v.nv[r] = v.uv[u];
+        v.nleaf[r] = leaf;
+        v.nu[r] = u;
+        s_a[r] = u;
+        s_b[r] = leaf;
+    }
+    __syncthreads();
+    bool valid[2];
+    uint32_t nu[2], ixp[2], node[2], pnx[2] = {0u, 0u};
+    for (int j = 0; j < 2; ++j) {
+        const uint32_t r = 2 * tid + j;
+        valid[j] = r < R;
+        nu[j] = valid[j] ? s_a[r] : 0u;
+        node[j] = valid[j] ? s_b[r] : 0u;
+        ixp[j] = r;  // at the leaf level an item's range counts keys
+    }
+
+    // items of every level: heads and ends of runs, item index per key
+    uint32_t hbits = 0, lbits = 0, items = 0;
+#pragma unroll 1
+    for (int d = 0; d < hmax; ++d) {
+        if (d > 0) {
+            for (int j = 0; j < 2; ++j) {
+                node[j] = pnx[j];
+                if (valid[j]) s_b[2 * tid + j] = node[j];
+            }
+            __syncthreads();
+        }
+        // the next level's parent references, in flight through this level
+        if (d + 1 < hmax)
+            for (int j = 0; j < 2; ++j)
+                pnx[j] = valid[j] ? v.pn[static_cast<uint64_t>(h - 2 - d) * v.Bm + nu[j]] : 0u;
+        uint32_t hd[2], ls[2];
+        for (int j = 0; j < 2; ++j) {
+            const uint32_t r = 2 * tid + j;
+            hd[j] = valid[j] && (r == 0 || s_b[r - 1] != node[j]) ? 1u : 0u;
+            ls[j] = valid[j] && (r + 1 == R || s_b[r + 1] != node[j]) ? 1u : 0u;
+        }
+        uint32_t n;
+        const uint32_t oh = plan_scan<NT>(hd[0] + hd[1], sh, &n);
+        for (int j = 0; j < 2; ++j) {
+            const uint32_t r = 2 * tid + j;
+            const uint32_t ix = oh + (j ? hd[0] : 0u) + hd[j] - 1u;
+            const uint64_t e = static_cast<uint64_t>(items) + ix;
+            if (valid[j]) s_ix[d * kCap + r] = static_cast<uint16_t>(ix);
+            if (hd[j]) {
+                if (e < v.ip_cap) {
+                    v.it_node[e] = node[j];
+                    v.it_rep[e] = nu[j];
+                    v.it_first[e] = ixp[j];
+                } else {
+                    s_over = 1;
+                }
+            }
+            if (ls[j] && e < v.ip_cap) v.it_end[e] = ixp[j] + 1u;
+            hbits |= hd[j] << (2 * d + j);
+            lbits |= ls[j] << (2 * d + j);
+            ixp[j] = ix;
+        }
+        if (tid == 0) s_base[d] = items;
+        items += n;
+        __syncthreads();  // s_b is rewritten by the next level
+    }
+    if (tid == 0) s_base[hmax] = items;
+    __syncthreads();
+
+    // old entry counts of all items and each item's slot in its parent: leaf
+    // items, then inner items, four in flight per thread (indices clamped so
+    // that every load is issued before any is used)
+    const uint32_t total = items < v.ip_cap ? items : static_cast<uint32_t>(v.ip_cap);
+    const uint32_t nleaf = s_base[hmax > 1 ? 1 : hmax] < total ? s_base[hmax > 1 ? 1 : hmax] : total;
+#pragma unroll 1
+    for (uint32_t x0 = tid; x0 < nleaf; x0 += 4 * NT) {
+        uint32_t nd[4], rp[4], c[4], cs[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t x = x0 + q * NT < nleaf ? x0 + q * NT : nleaf - 1;
+            nd[q] = v.it_node[x];
+            rp[q] = v.it_rep[x];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c[q] = t.lmeta[nd[q]].x;
+            cs[q] = h >= 2 ? v.pi[static_cast<uint64_t>(h - 2) * v.Bm + rp[q]] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t x = x0 + q * NT;
+            if (x < nleaf) {
+                s_C[x] = static_cast<uint8_t>(c[q]);
+                v.it_cold[x] = c[q];
+                v.it_cs[x] = static_cast<uint8_t>(cs[q]);
+            }
+        }
+    }
+#pragma unroll 1
+    for (uint32_t x0 = nleaf + tid; x0 < total; x0 += 4 * NT) {
+        uint32_t nd[4], rp[4], c[4], cs[4];
+        int lp[4];  // tree level of the item's parent (< 0: the item is the root)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t x = x0 + q * NT < total ? x0 + q * NT : total - 1;
+            nd[q] = v.it_node[x];
+            rp[q] = v.it_rep[x];
+            int dx = 1;
+#pragma unroll 1
+            for (int d = 2; d < hmax; ++d)
+                if (x >= s_base[d]) dx = d;
+            lp[q] = h - 2 - dx;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c[q] = old_count<K>(t, nd[q], false);
+            cs[q] = v.pi[static_cast<uint64_t>(lp[q] >= 0 ? lp[q] : 0) * v.Bm + rp[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t x = x0 + q * NT;
+            if (x < total) {
+                s_C[x] = static_cast<uint8_t>(c[q]);
+                v.it_cold[x] = c[q];
+                v.it_cs[x] = static_cast<uint8_t>(lp[q] >= 0 ? cs[q] : 0u);
+            }
+        }
+    }
+    __syncthreads();
+
+    // piece counts, level after level
+    uint32_t psep = 0;
+#pragma unroll 1
+    for (int d = 0; d < hmax; ++d) {
+        const uint32_t bd = s_base[d], nd = s_base[d + 1] - bd;
+        // what each key brings to its item: 1 new entry (leaves), or k - 1
+        // from the child item it heads (inner levels)
+        uint32_t g[2], ixd[2];
+        for (int j = 0; j < 2; ++j) {
+            const uint32_t r = 2 * tid + j;
+            ixd[j] = valid[j] ? s_ix[d * kCap + r] : 0u;
+            if (d == 0) g[j] = valid[j] ? 1u : 0u;
+            else g[j] = (hbits >> (2 * (d - 1) + j)) & 1u ? s_k[s_ix[(d - 1) * kCap + r]] - 1u : 0u;
+        }
+        uint32_t gs;
+        const uint32_t og = plan_scan<NT>(g[0] + g[1], sh, &gs);
+        for (int j = 0; j < 2; ++j) {
+            const uint32_t pg = og + (j ? g[0] : 0u);
+            if ((hbits >> (2 * d + j)) & 1u) s_a[ixd[j]] = pg;
+            if ((lbits >> (2 * d + j)) & 1u) s_b[ixd[j]] = pg + g[j];
+        }
         __syncthreads();
-        block_scan_small(v.f0, v.f1, v.st->lvl_count[d - 1], &v.st->lvl_count[d], sh);
-        ph_par_items<K>(v, d, tid, nth);
-        __syncthreads();
-        ph_par_plan<K>(t, v, d, tid, nth);
-        __syncthreads();
-        block_scan_small(v.f0, v.f1, v.st->lvl_count[d], &v.st->lvl_new[d], sh);
-        ph_par_off<K>(v, d, tid, nth);
+        uint32_t kk[2], f[2];
+        for (int i = 0; i < 2; ++i) {
+            const uint32_t jt = 2 * tid + i;
+            const bool in = jt < nd && bd + jt < total;
+            kk[i] = in ? split_pieces(static_cast<uint64_t>(s_C[bd + jt]) + (s_b[jt] - s_a[jt])) : 1u;
+            f[i] = in ? kk[i] - 1u : 0u;
+        }
+        uint32_t nnew;
+        const uint32_t of = plan_scan<NT>(f[0] + f[1], sh, &nnew);
+        for (int i = 0; i < 2; ++i) {
+            const uint32_t jt = 2 * tid + i;
+            if (jt < nd && bd + jt < total) {
+                s_k[jt] = kk[i];
+                v.it_k[bd + jt] = kk[i];
+                v.it_off[bd + jt] = of + (i ? f[0] : 0u);
+            }
+        }
+        if (tid == 0) {
+            v.st->lvl_count[d] = nd;
+            v.st->lvl_base[d] = bd;
+            v.st->lvl_new[d] = nnew;
+            v.st->lvl_psep[d] = psep;
+        }
+        psep += nnew;
         __syncthreads();
     }
-    ph_check<K>(t, v, tid, nth);
+    if (tid == 0) {
+        v.st->R = R;
+        if (s_over) v.st->overflow = 1;
+    }
+    __syncthreads();
+    ph_check<K>(t, v, tid, NT);
+    __syncthreads();
+    // values of keys already present (the batch passed the capacity check;
+    // the leaf rewrites that follow read these values)
+    if (v.st->ok) {
+        for (uint32_t u = tid; u < U; u += NT)
+            if (v.ufound[u]) t.lvals[static_cast<uint64_t>(v.uleaf[u]) * kSlots + v.uslot[u]] = v.uv[u];
+    }
 }
 
 // ------------------------------------------------------------------ launch
@@ -876,11 +1126,12 @@ static int height_bound(uint64_t leaf_cap) {
     return h + 1 < kMaxLevels ? h + 1 : kMaxLevels;
 }
 
-// apply, grow, commit, mirror: shared by both paths
+// apply, grow, commit, mirror: shared by both paths (the small path's plan
+// kernel writes the updates itself)
 template <class K>
-static void launch_apply(const TreeView<K>& t, const Ins<K>& v, uint64_t B, int H, hipStream_t s) {
+static void launch_apply(const TreeView<K>& t, const Ins<K>& v, uint64_t B, int H, bool updates, hipStream_t s) {
     const uint32_t gB = grid_for(B, kBlk);
-    hipLaunchKernelGGL(k_apply_updates<K>, dim3(gB), dim3(kBlk), 0, s, t, v);
+    if (updates) hipLaunchKernelGGL(k_apply_updates<K>, dim3(gB), dim3(kBlk), 0, s, t, v);
     hipLaunchKernelGGL(k_apply_leaves<K>, dim3(grid_for(B, kBlk / kNodeLanes)), dim3(kBlk), 0, s, t, v);
     for (int d = 1; d < H; ++d)
         hipLaunchKernelGGL(k_apply_inner<K>, dim3(grid_for(B, kBlk / kNodeLanes)), dim3(kBlk), 0, s, t, v, d);
@@ -902,8 +1153,10 @@ void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, cons
         hipLaunchKernelGGL(k_small_prefix<K>, dim3(1), dim3(kSmallBlock), 0, s, v, t.hdr, keys, vals,
                            static_cast<uint32_t>(B), status);
         launch_locate<K>(t, v, c.cfg, B, status, s);
-        hipLaunchKernelGGL(k_small_plan<K>, dim3(1), dim3(kSmallBlock), 0, s, t, v, H);
-        launch_apply<K>(t, v, B, H, s);
+        if (B <= 128) hipLaunchKernelGGL((k_small_plan<K, 64>), dim3(1), dim3(64), 0, s, t, v, H);
+        else if (B <= 512) hipLaunchKernelGGL((k_small_plan<K, 256>), dim3(1), dim3(256), 0, s, t, v, H);
+        else hipLaunchKernelGGL((k_small_plan<K, kSmallBlock>), dim3(1), dim3(kSmallBlock), 0, s, t, v, H);
+        launch_apply<K>(t, v, B, H, false, s);  // the plan wrote the updates
         return;
     }
     hipLaunchKernelGGL(k_init<K>, dim3(gB), dim3(kBlk), 0, s, v, t.hdr, keys, B);
@@ -928,7 +1181,7 @@ void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, cons
         hipLaunchKernelGGL(k_par_off<K>, dim3(gB), dim3(kBlk), 0, s, v, d);
     }
     hipLaunchKernelGGL(k_check<K>, dim3(1), dim3(64), 0, s, t, v);
-    launch_apply<K>(t, v, B, H, s);
+    launch_apply<K>(t, v, B, H, true, s);
 }
 
 template void launch_insert<uint32_t>(const TreeView<uint32_t>&, const InsertCtx&, const uint32_t*,
