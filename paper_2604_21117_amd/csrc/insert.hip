@@ -34,6 +34,7 @@
 //  6. Commit the header (key count, pool cursors, height, root) and refresh
 //     the top-levels mirror.
 #include "insert.h"
+#include "mirror.h"
 #include "prims.h"
 #include "traverse.h"
 
@@ -147,18 +148,13 @@ uint64_t insert_scratch_bytes(uint64_t max_batch, int key_bytes, uint64_t leaf_c
 __device__ __forceinline__ uint64_t gtid() { return blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; }
 __device__ __forceinline__ uint64_t gstride() { return static_cast<uint64_t>(gridDim.x) * blockDim.x; }
 
+// Clear the batch state (one workgroup).
 template <class K>
-__global__ void k_init(Ins<K> v, const DevHeader* hdr, const K* __restrict__ keys, uint64_t B) {
-    if (blockIdx.x == 0) {
-        uint32_t* s = reinterpret_cast<uint32_t*>(v.st);
-        for (uint32_t i = threadIdx.x; i < sizeof(InsState) / 4; i += blockDim.x) s[i] = 0;
-        __syncthreads();
-        if (threadIdx.x == 0) v.st->height = hdr->height;
-    }
-    for (uint64_t i = gtid(); i < B; i += gstride()) {
-        v.sk[i] = keys[i];
-        v.si[i] = static_cast<uint32_t>(i);
-    }
+__global__ void k_init(Ins<K> v, const DevHeader* hdr) {
+    uint32_t* s = reinterpret_cast<uint32_t*>(v.st);
+    for (uint32_t i = threadIdx.x; i < sizeof(InsState) / 4; i += blockDim.x) s[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) v.st->height = hdr->height;
 }
 
 template <class K>
@@ -471,14 +467,14 @@ __device__ __forceinline__ uint32_t lower_bound_dev(const K* a, uint32_t n, K k)
 // nodes per wave, so a wave keeps four nodes' reads in flight.
 constexpr int kNodeLanes = 16;
 
-// Merge-split of the touched leaves: kNodeLanes lanes per leaf.
+// Merge-split of the touched leaves: kNodeLanes lanes per leaf, group grp
+// of ngrp.
 template <class K>
-__global__ __launch_bounds__(kBlk) void k_apply_leaves(TreeView<K> t, Ins<K> v) {
+__device__ __forceinline__ void apply_leaves_body(TreeView<K> t, Ins<K> v, uint64_t grp, uint64_t ngrp) {
     const uint32_t ok = v.st->ok;
     const uint64_t T0 = v.st->lvl_count[0];
     if (!ok || T0 == 0) return;
     const int gl = lane_id() % kNodeLanes, gbase = lane_id() - gl;
-    const uint64_t grp = gtid() / kNodeLanes, ngrp = gstride() / kNodeLanes;
     const uint32_t alloc = v.st->lvl_alloc[0];
     for (uint64_t it = grp; it < T0; it += ngrp) {
         const uint32_t leaf = v.it_node[it];
@@ -573,9 +569,10 @@ __global__ __launch_bounds__(kBlk) void k_apply_leaves(TreeView<K> t, Ins<K> v) 
     }
 }
 
-// Rebuild the changed parents of level d: kNodeLanes lanes per parent.
+// Rebuild the changed parents of level d: kNodeLanes lanes per parent, group
+// grp of ngrp.
 template <class K>
-__global__ __launch_bounds__(kBlk) void k_apply_inner(TreeView<K> t, Ins<K> v, int d) {
+__device__ __forceinline__ void apply_inner_body(TreeView<K> t, Ins<K> v, int d, uint64_t grp, uint64_t ngrp) {
     const uint32_t ok = v.st->ok;
     const int h = static_cast<int>(v.st->height);
     const int l = h - 1 - d;
@@ -587,7 +584,6 @@ __global__ __launch_bounds__(kBlk) void k_apply_inner(TreeView<K> t, Ins<K> v, i
     const bool child_leaf = d == 1;
     const int gl = lane_id() % kNodeLanes, gbase = lane_id() - gl;
     const uint32_t lane = static_cast<uint32_t>(gl);  // this lane's old slot
-    const uint64_t grp = gtid() / kNodeLanes, ngrp = gstride() / kNodeLanes;
     for (uint64_t j = grp; j < n; j += ngrp) {
         const uint32_t node = v.it_node[bd + j];
         const uint32_t first = v.it_first[bd + j], end = v.it_end[bd + j];
@@ -672,6 +668,16 @@ __global__ __launch_bounds__(kBlk) void k_apply_inner(TreeView<K> t, Ins<K> v, i
             }
         }
     }
+}
+
+template <class K>
+__global__ __launch_bounds__(kBlk) void k_apply_leaves(TreeView<K> t, Ins<K> v) {
+    apply_leaves_body<K>(t, v, gtid() / kNodeLanes, gstride() / kNodeLanes);
+}
+
+template <class K>
+__global__ __launch_bounds__(kBlk) void k_apply_inner(TreeView<K> t, Ins<K> v, int d) {
+    apply_inner_body<K>(t, v, d, gtid() / kNodeLanes, gstride() / kNodeLanes);
 }
 
 // Root growth: pack the root's pieces into new levels (one workgroup).
@@ -760,6 +766,29 @@ __global__ __launch_bounds__(1024) void k_grow_commit(TreeView<K> t, Ins<K> v) {
     grow_body<K>(t, v);
     __syncthreads();
     if (threadIdx.x == 0) ph_commit<K>(t, v);
+}
+
+// Everything after the plan for a batch of at most kFusedMax keys, in one
+// workgroup: every level has at most that many touched nodes, one round of
+// kNodeLanes-lane groups, and barriers stand where the general path has
+// kernel boundaries (leaves, each parent level, growth and commit, mirror).
+constexpr int kFusedBlock = 1024;
+constexpr uint32_t kFusedMax = kFusedBlock / kNodeLanes;  // 64
+
+template <class K>
+__global__ __launch_bounds__(kFusedBlock) void k_small_apply(TreeView<K> t, Ins<K> v, int H) {
+    const uint64_t grp = threadIdx.x / kNodeLanes, ngrp = kFusedBlock / kNodeLanes;
+    apply_leaves_body<K>(t, v, grp, ngrp);
+    __syncthreads();
+    for (int d = 1; d < H; ++d) {
+        apply_inner_body<K>(t, v, d, grp, ngrp);
+        __syncthreads();
+    }
+    grow_body<K>(t, v);
+    __syncthreads();
+    if (threadIdx.x == 0) ph_commit<K>(t, v);
+    __syncthreads();
+    if (v.st->mirror_dirty) mirror_refresh_body<K, kFusedBlock>(t);
 }
 
 // ------------------------------------------------- small batches (B <= 2048)
@@ -863,7 +892,7 @@ __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int 
     __shared__ uint32_t sh[33];
     __shared__ uint32_t s_a[kCap], s_b[kCap];  // key -> distinct key, node; later prefix sums at item bounds
     __shared__ uint16_t s_ix[kL * kCap];       // item index of each key, per level
-    __shared__ uint32_t s_k[kCap];             // piece counts of the previous level's items
+    __shared__ uint32_t s_k[kCap + 1];         // piece-offset prefix of the previous level's items
     __shared__ uint8_t s_C[kL * kCap];         // old entry count of every item
     __shared__ uint32_t s_base[kL + 1];        // first item of each level
     __shared__ uint32_t s_over;
@@ -1013,26 +1042,21 @@ __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int 
     }
     __syncthreads();
 
-    // piece counts, level after level
+    // piece counts, level after level.  An item's gain is its run's key
+    // count (leaves) or sum(k - 1) over its child items (inner levels): a
+    // difference of the child level's piece-offset prefix (s_k), taken by
+    // the run's first and last keys.
     uint32_t psep = 0;
 #pragma unroll 1
     for (int d = 0; d < hmax; ++d) {
         const uint32_t bd = s_base[d], nd = s_base[d + 1] - bd;
-        // what each key brings to its item: 1 new entry (leaves), or k - 1
-        // from the child item it heads (inner levels)
-        uint32_t g[2], ixd[2];
         for (int j = 0; j < 2; ++j) {
             const uint32_t r = 2 * tid + j;
-            ixd[j] = valid[j] ? s_ix[d * kCap + r] : 0u;
-            if (d == 0) g[j] = valid[j] ? 1u : 0u;
-            else g[j] = (hbits >> (2 * (d - 1) + j)) & 1u ? s_k[s_ix[(d - 1) * kCap + r]] - 1u : 0u;
-        }
-        uint32_t gs;
-        const uint32_t og = plan_scan<NT>(g[0] + g[1], sh, &gs);
-        for (int j = 0; j < 2; ++j) {
-            const uint32_t pg = og + (j ? g[0] : 0u);
-            if ((hbits >> (2 * d + j)) & 1u) s_a[ixd[j]] = pg;
-            if ((lbits >> (2 * d + j)) & 1u) s_b[ixd[j]] = pg + g[j];
+            if (!valid[j]) continue;
+            const uint32_t ixd = s_ix[d * kCap + r];
+            const uint32_t c = d == 0 ? r : s_k[s_ix[(d - 1) * kCap + r]];
+            if ((hbits >> (2 * d + j)) & 1u) s_a[ixd] = c;
+            if ((lbits >> (2 * d + j)) & 1u) s_b[ixd] = d == 0 ? r + 1 : s_k[s_ix[(d - 1) * kCap + r] + 1];
         }
         __syncthreads();
         uint32_t kk[2], f[2];
@@ -1044,15 +1068,18 @@ __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int 
         }
         uint32_t nnew;
         const uint32_t of = plan_scan<NT>(f[0] + f[1], sh, &nnew);
+        // s_k now holds this level's piece-offset prefix, s_k[nd] its total
         for (int i = 0; i < 2; ++i) {
             const uint32_t jt = 2 * tid + i;
+            const uint32_t o = of + (i ? f[0] : 0u);
+            if (jt < nd) s_k[jt] = o;
             if (jt < nd && bd + jt < total) {
-                s_k[jt] = kk[i];
                 v.it_k[bd + jt] = kk[i];
-                v.it_off[bd + jt] = of + (i ? f[0] : 0u);
+                v.it_off[bd + jt] = o;
             }
         }
         if (tid == 0) {
+            s_k[nd] = nnew;
             v.st->lvl_count[d] = nd;
             v.st->lvl_base[d] = bd;
             v.st->lvl_new[d] = nnew;
@@ -1156,11 +1183,12 @@ void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, cons
         if (B <= 128) hipLaunchKernelGGL((k_small_plan<K, 64>), dim3(1), dim3(64), 0, s, t, v, H);
         else if (B <= 512) hipLaunchKernelGGL((k_small_plan<K, 256>), dim3(1), dim3(256), 0, s, t, v, H);
         else hipLaunchKernelGGL((k_small_plan<K, kSmallBlock>), dim3(1), dim3(kSmallBlock), 0, s, t, v, H);
-        launch_apply<K>(t, v, B, H, false, s);  // the plan wrote the updates
+        if (B <= kFusedMax) hipLaunchKernelGGL(k_small_apply<K>, dim3(1), dim3(kFusedBlock), 0, s, t, v, H);
+        else launch_apply<K>(t, v, B, H, false, s);  // the plan wrote the updates
         return;
     }
-    hipLaunchKernelGGL(k_init<K>, dim3(gB), dim3(kBlk), 0, s, v, t.hdr, keys, B);
-    sort_pairs<K>(v.sk, v.si, v.sk2, v.si2, B, v.sort_tmp, s);
+    hipLaunchKernelGGL(k_init<K>, dim3(1), dim3(kBlk), 0, s, v, t.hdr);
+    sort_from<K>(keys, v.sk, v.si, v.sk2, v.si2, B, v.sort_tmp, s);
     hipLaunchKernelGGL(k_heads<K>, dim3(gB), dim3(kBlk), 0, s, v, B, status);
     scan_exclusive<uint32_t>(v.f0, v.f1, &st->U, nullptr, B, v.scan_tmp, s);
     hipLaunchKernelGGL(k_unique<K>, dim3(gB), dim3(kBlk), 0, s, v, B, vals);

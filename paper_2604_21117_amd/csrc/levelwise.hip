@@ -125,17 +125,6 @@ __global__ __launch_bounds__(kLwBlock) void k_lw_level(TreeView<K> t, const K* _
     }
 }
 
-// Copy the batch into the sort buffers (key, position).
-template <class K>
-__global__ __launch_bounds__(256) void k_lw_stage(const K* __restrict__ keys, uint32_t B, K* __restrict__ sk,
-                                                  uint32_t* __restrict__ si) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < B) {
-        sk[i] = keys[i];
-        si[i] = i;
-    }
-}
-
 // ------------------------------------------------------------ host side
 
 static uint64_t lw_align(uint64_t x) { return (x + 255) / 256 * 256; }
@@ -180,9 +169,8 @@ void launch_lookup_levelwise(const TreeView<K>& t, const K* keys, uint64_t B, bo
         if (B <= kRankSortMax) {
             rank_sort_small<K>(keys, b, sk, si, nullptr, 0, s);
         } else {
-            hipLaunchKernelGGL(k_lw_stage<K>, dim3((b + 255) / 256), dim3(256), 0, s, keys, b, sk, si);
-            sort_pairs<K>(sk, si, reinterpret_cast<K*>(w + L.sk2), reinterpret_cast<uint32_t*>(w + L.si2), B,
-                          w + L.tmp, s);
+            sort_from<K>(keys, sk, si, reinterpret_cast<K*>(w + L.sk2), reinterpret_cast<uint32_t*>(w + L.si2), B,
+                         w + L.tmp, s);
         }
         qs = sk;
         qi = si;

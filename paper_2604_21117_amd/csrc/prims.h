@@ -113,4 +113,10 @@ template <class K>
 void sort_pairs(K* keys, uint32_t* idx, K* keys_alt, uint32_t* idx_alt, uint64_t n, void* tmp,
                 hipStream_t s);
 
+// The same sort of (src[i], i): src is read, keys/idx receive the result,
+// keys_alt/idx_alt are ping-pong buffers.  Saves staging the pairs.
+template <class K>
+void sort_from(const K* src, K* keys, uint32_t* idx, K* keys_alt, uint32_t* idx_alt, uint64_t n, void* tmp,
+               hipStream_t s);
+
 }  // namespace gt

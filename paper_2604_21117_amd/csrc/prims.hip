@@ -7,11 +7,9 @@
 //
 // sort_pairs: up to 2048 elements sort inside one workgroup with a bitonic
 // network on (key, index) pairs, which orders equal keys by index and so is
-// stable.  Larger inputs use LSD radix sort with 8-bit digits: per pass a
-// per-tile digit histogram, an exclusive scan of the histograms in
-// digit-major order, and a stable scatter in which each wave ranks its
-// lanes by digit with eight ballots (lanes whose digit bits all agree are
-// peers) and waves are offset by a per-digit prefix in LDS.
+// stable.  Larger inputs use LSD radix sort with 8-bit digits, one stable
+// scatter kernel per pass whose tiles find their output offsets by
+// decoupled look-back (below).
 #include "prims.h"
 #include "common.h"
 
@@ -130,19 +128,47 @@ template void scan_exclusive<uint64_t>(const uint64_t*, uint64_t*, uint64_t*, co
                                        void*, hipStream_t);
 
 // ------------------------------------------------------------------ sort
+//
+// For n > kBitonicMax: LSD radix sort with 8-bit digits, one scatter kernel
+// per pass (the decoupled look-back scheme of single-pass prefix scans).
+// One kernel clears the pass tickets and tile words, one counts the digits
+// of every pass over the whole input.  In a pass, each workgroup takes the
+// next 4096-element tile from an atomic ticket, ranks its elements by digit
+// (eight ballots per wave, per-digit prefixes over the waves in LDS),
+// publishes its per-digit counts, and sums the counts of earlier tiles by
+// walking back over their published words until one carries an inclusive
+// prefix; it then publishes its own inclusive prefix, reorders the tile in
+// LDS and writes each digit's run contiguously.  A tile waits only on tiles
+// with smaller tickets, which are already running and publish their counts
+// before they wait, so every wait ends; the spin is bounded all the same.
 
 constexpr int kSortBlock = 1024;
 constexpr int kSortRounds = 4;
 constexpr uint64_t kSortTile = kSortBlock * kSortRounds;  // 4096
 constexpr uint64_t kBitonicMax = 2048;
+constexpr uint32_t kSpinMax = 1u << 20;       // a look-back that waits longer gives up
+constexpr uint64_t kNarrowMax = 1ull << 30;   // counts fit the 30 bits of a 32-bit tile word
 
 static uint32_t sort_tiles(uint64_t n) { return static_cast<uint32_t>((n + kSortTile - 1) / kSortTile); }
 
-uint64_t sort_tmp_bytes(uint64_t n, int) {
-    uint64_t nt = sort_tiles(n);
-    uint64_t hist = nt * 256 * 4;
-    return ((hist + 255) / 256) * 256 + scan_tmp_bytes(nt * 256);
+struct SortLayout {
+    uint64_t totals, tickets, err, flags, bytes;
+};
+
+static SortLayout sort_layout(uint64_t n, int key_bytes) {
+    const uint64_t nt = sort_tiles(n), w = n < kNarrowMax ? 4 : 8;
+    auto al = [](uint64_t x) { return (x + 255) / 256 * 256; };
+    SortLayout L{};
+    uint64_t o = 0;
+    L.totals = o;  o += al(static_cast<uint64_t>(key_bytes) * 256 * 4);
+    L.tickets = o; o += al(static_cast<uint64_t>(key_bytes) * 4);
+    L.err = o;     o += al(4);
+    L.flags = o;   o += al(static_cast<uint64_t>(key_bytes) * nt * 256 * w);
+    L.bytes = o;
+    return L;
 }
+
+uint64_t sort_tmp_bytes(uint64_t n, int key_bytes) { return sort_layout(n, key_bytes).bytes; }
 
 template <class K>
 __global__ __launch_bounds__(kSortBlock) void k_bitonic(K* keys, uint32_t* idx, uint32_t n, uint32_t n2) {
@@ -161,71 +187,84 @@ __global__ __launch_bounds__(kSortBlock) void k_bitonic(K* keys, uint32_t* idx, 
 }
 
 template <class K>
-__global__ __launch_bounds__(kSortBlock) void k_radix_hist(const K* keys, uint64_t n, int shift, uint32_t* gh,
-                                                            uint32_t ntiles) {
-    __shared__ uint32_t h[256];
-    if (threadIdx.x < 256) h[threadIdx.x] = 0;
-    __syncthreads();
-    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kSortTile;
-#pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
-        uint64_t i = base + r * kSortBlock + threadIdx.x;
-        if (i < n) atomicAdd(&h[static_cast<uint32_t>(keys[i] >> shift) & 255u], 1u);
+__global__ __launch_bounds__(256) void k_sort_stage(const K* __restrict__ src, uint64_t n, K* __restrict__ keys,
+                                                    uint32_t* __restrict__ idx) {
+    const uint64_t i = blockIdx.x * 256ull + threadIdx.x;
+    if (i < n) {
+        keys[i] = src[i];
+        idx[i] = static_cast<uint32_t>(i);
     }
-    __syncthreads();
-    if (threadIdx.x < 256) gh[static_cast<uint64_t>(threadIdx.x) * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter of one tile for one digit.  The tile's elements are first
-// placed in LDS in (digit, original order) order, then written out in that
-// order, so consecutive threads store consecutive positions of one digit's
-// run (coalesced lines instead of one line per lane).
+__global__ __launch_bounds__(256) void k_sort_clear(uint32_t* w, uint64_t words) {
+    for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < words; i += gridDim.x * 256ull) w[i] = 0;
+}
+
+// Digit counts of every pass over the whole input.
 template <class K>
-__global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* kin, const uint32_t* iin, K* kout,
-                                                               uint32_t* iout, uint64_t n, int shift,
-                                                               const uint32_t* gofs, uint32_t ntiles) {
+__global__ __launch_bounds__(kSortBlock) void k_sort_hist(const K* __restrict__ keys, uint64_t n,
+                                                           uint32_t* __restrict__ totals) {
+    constexpr int P = sizeof(K);
+    __shared__ uint32_t h[P * 256];
+    for (int i = threadIdx.x; i < P * 256; i += kSortBlock) h[i] = 0;
+    __syncthreads();
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(kSortBlock) + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * kSortBlock) {
+        const K k = keys[i];
+#pragma unroll
+        for (int p = 0; p < P; ++p) atomicAdd(&h[p * 256 + (static_cast<uint32_t>(k >> (8 * p)) & 255u)], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < P * 256; i += kSortBlock)
+        if (h[i]) atomicAdd(&totals[i], h[i]);
+}
+
+// One pass over the digit at `shift`; `totals` are this pass's digit counts,
+// `flags` its tile words (2 flag bits: 1 = tile count, 2 = inclusive prefix).
+// Without `iin` the element at position i carries index i.
+template <class K, class W>
+__global__ __launch_bounds__(kSortBlock) void k_sort_pass(const K* __restrict__ kin, const uint32_t* __restrict__ iin,
+                                                           K* __restrict__ kout, uint32_t* __restrict__ iout, uint64_t n,
+                                                           int shift, const uint32_t* __restrict__ totals,
+                                                           uint32_t* ticket, W* flags, uint32_t* err) {
+    constexpr int kSh = static_cast<int>(sizeof(W)) * 8 - 2;
+    constexpr W kAgg = W(1) << kSh, kIncl = W(2) << kSh, kVal = (W(1) << kSh) - 1;
     __shared__ uint32_t wcnt[kSortBlock / 64][256];
     __shared__ uint32_t run[256];
-    __shared__ uint32_t base[256];   // global position of this tile's run of digit d
-    __shared__ uint32_t lstart[256]; // position of that run inside the tile
+    __shared__ uint32_t lstart[256];  // this tile's run of digit d inside the tile
+    __shared__ uint64_t gbase[256];   // and in the output
     __shared__ uint32_t sh[33];
+    __shared__ uint32_t s_tile;
     __shared__ K tk[kSortTile];
     __shared__ uint32_t ti[kSortTile];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    const uint64_t tbase = static_cast<uint64_t>(blockIdx.x) * kSortTile;
-    if (tid < 256) {
-        run[tid] = 0;
-        const uint64_t at = static_cast<uint64_t>(tid) * ntiles + blockIdx.x;
-        base[tid] = gofs[at];
-    }
+    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+    if (tid < 256) run[tid] = 0;
     __syncthreads();
-    // this tile's count of digit d: the next offset in digit-major order
-    // (the next tile's for d, or the next digit's first tile) minus its own
-    {
-        uint32_t c = 0;
-        if (tid < 256) {
-            const uint64_t at = static_cast<uint64_t>(tid) * ntiles + blockIdx.x;
-            const uint64_t nxt = at + 1 < static_cast<uint64_t>(ntiles) * 256 ? gofs[at + 1] : n;
-            c = static_cast<uint32_t>(nxt - base[tid]);
-        }
-        uint32_t tot;
-        const uint32_t st = block_excl_scan<uint32_t>(c, sh, &tot);
-        if (tid < 256) lstart[tid] = st;
-    }
-    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint64_t tbase = static_cast<uint64_t>(tile) * kSortTile;
+    // where each digit starts in the output: scan of the pass's totals
+    uint32_t tot;
+    const uint32_t dstart = block_excl_scan<uint32_t>(tid < 256 ? totals[tid] : 0u, sh, &tot);
+
+    // rank the tile's elements by digit, in input order
     const uint64_t lt = (1ull << lane) - 1ull;
+    K kr[kSortRounds];
+    uint32_t dr[kSortRounds], rr[kSortRounds], ir[kSortRounds];
+    bool vr[kSortRounds];
+#pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
         uint32_t* flat = &wcnt[0][0];
         for (int j = tid; j < (kSortBlock / 64) * 256; j += kSortBlock) flat[j] = 0;
         __syncthreads();
         const uint64_t i = tbase + r * kSortBlock + tid;
         const bool valid = i < n;
-        K k = valid ? kin[i] : K(0);
-        uint32_t d = static_cast<uint32_t>(k >> shift) & 255u;
+        const K k = valid ? kin[i] : K(0);
+        const uint32_t d = static_cast<uint32_t>(k >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            uint64_t m = __ballot((d >> b) & 1u);
+            const uint64_t m = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
         const uint32_t rank = static_cast<uint32_t>(__popcll(peers & lt));
@@ -235,27 +274,97 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const K* kin, cons
             uint32_t acc = run[tid];
 #pragma unroll
             for (int ww = 0; ww < kSortBlock / 64; ++ww) {
-                uint32_t c = wcnt[ww][tid];
+                const uint32_t c = wcnt[ww][tid];
                 wcnt[ww][tid] = acc;
                 acc += c;
             }
             run[tid] = acc;
         }
         __syncthreads();
-        if (valid) {
-            const uint32_t p = lstart[d] + wcnt[w][d] + rank;  // place in the tile
-            tk[p] = k;
-            ti[p] = iin[i];
-        }
+        kr[r] = k;
+        dr[r] = d;
+        vr[r] = valid;
+        rr[r] = valid ? wcnt[w][d] + rank : 0u;
+        ir[r] = valid ? (iin ? iin[i] : static_cast<uint32_t>(i)) : 0u;
         __syncthreads();
     }
+
+    // publish this tile's counts, look back for the earlier tiles' sums
+    if (tid < 256) {
+        const uint32_t cnt = run[tid];
+        W* mine = flags + static_cast<uint64_t>(tile) * 256 + tid;
+        uint64_t excl = 0;
+        if (tile == 0) {
+            __hip_atomic_store(mine, kIncl | static_cast<W>(cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(mine, kAgg | static_cast<W>(cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t j = tile - 1, spins = 0;
+            for (;;) {
+                const W x = __hip_atomic_load(flags + static_cast<uint64_t>(j) * 256 + tid, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                const W f = x >> kSh;
+                if (f == 2) { excl += x & kVal; break; }
+                if (f == 1 && j > 0) { excl += x & kVal; --j; continue; }
+                if (f == 1 || ++spins > kSpinMax) { atomicOr(err, 1u); break; }  // tile 0 is never a bare count
+            }
+            __hip_atomic_store(mine, kIncl | static_cast<W>(excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        gbase[tid] = static_cast<uint64_t>(dstart) + excl;
+    }
+    {
+        uint32_t t2;
+        const uint32_t st = block_excl_scan<uint32_t>(tid < 256 ? run[tid] : 0u, sh, &t2);
+        if (tid < 256) lstart[tid] = st;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+        if (vr[r]) {
+            const uint32_t p = lstart[dr[r]] + rr[r];
+            tk[p] = kr[r];
+            ti[p] = ir[r];
+        }
+    }
+    __syncthreads();
     const uint64_t cnt = n - tbase < kSortTile ? n - tbase : kSortTile;
     for (uint32_t p = tid; p < cnt; p += kSortBlock) {
         const K k = tk[p];
         const uint32_t d = static_cast<uint32_t>(k >> shift) & 255u;
-        const uint64_t dst = static_cast<uint64_t>(base[d]) + (p - lstart[d]);
+        const uint64_t dst = gbase[d] + (p - lstart[d]);
         kout[dst] = k;
         iout[dst] = ti[p];
+    }
+}
+
+template <class K, class W>
+static void sort_onesweep(const K* src, K* keys, uint32_t* idx, K* keys_alt, uint32_t* idx_alt, uint64_t n,
+                          void* tmp, hipStream_t s) {
+    constexpr int P = sizeof(K);
+    const uint32_t nt = sort_tiles(n);
+    const SortLayout L = sort_layout(n, P);
+    uint8_t* b = reinterpret_cast<uint8_t*>(tmp);
+    uint32_t* totals = reinterpret_cast<uint32_t*>(b + L.totals);
+    uint32_t* tickets = reinterpret_cast<uint32_t*>(b + L.tickets);
+    uint32_t* err = reinterpret_cast<uint32_t*>(b + L.err);
+    W* flags = reinterpret_cast<W*>(b + L.flags);
+    const uint64_t words = L.bytes / 4;
+    const uint64_t cg = (words + 255) / 256;
+    hipLaunchKernelGGL(k_sort_clear, dim3(static_cast<uint32_t>(cg < 4096 ? cg : 4096)), dim3(256), 0, s,
+                       reinterpret_cast<uint32_t*>(b), words);
+    const uint32_t hg = nt < 512 ? nt : 512;
+    hipLaunchKernelGGL(k_sort_hist<K>, dim3(hg), dim3(kSortBlock), 0, s, src ? src : keys, n, totals);
+    // pass 0 reads the source (indices 0..n-1) or keys/idx and writes the
+    // alternates; sizeof(K) passes is even, so the result ends in keys/idx
+    const K* ka = src ? src : keys;
+    const uint32_t* ia = src ? nullptr : idx;
+    K* kb = keys_alt; uint32_t* ib = idx_alt;
+    for (int p = 0; p < P; ++p) {
+        hipLaunchKernelGGL((k_sort_pass<K, W>), dim3(nt), dim3(kSortBlock), 0, s, ka, ia, kb, ib, n, 8 * p,
+                           totals + p * 256, tickets + p, flags + static_cast<uint64_t>(p) * nt * 256, err);
+        ka = kb;
+        ia = ib;
+        kb = (p & 1) ? keys_alt : keys;
+        ib = (p & 1) ? idx_alt : idx;
     }
 }
 
@@ -268,19 +377,22 @@ void sort_pairs(K* keys, uint32_t* idx, K* keys_alt, uint32_t* idx_alt, uint64_t
         hipLaunchKernelGGL(k_bitonic<K>, dim3(1), dim3(kSortBlock), 0, s, keys, idx, static_cast<uint32_t>(n), n2);
         return;
     }
-    const uint32_t nt = sort_tiles(n);
-    uint32_t* gh = reinterpret_cast<uint32_t*>(tmp);
-    void* stmp = reinterpret_cast<uint8_t*>(tmp) + ((static_cast<uint64_t>(nt) * 256 * 4 + 255) / 256) * 256;
-    K* ka = keys; uint32_t* ia = idx;
-    K* kb = keys_alt; uint32_t* ib = idx_alt;
-    for (int shift = 0; shift < static_cast<int>(sizeof(K) * 8); shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist<K>, dim3(nt), dim3(kSortBlock), 0, s, ka, n, shift, gh, nt);
-        scan_exclusive<uint32_t>(gh, gh, nullptr, nullptr, static_cast<uint64_t>(nt) * 256, stmp, s);
-        hipLaunchKernelGGL(k_radix_scatter<K>, dim3(nt), dim3(kSortBlock), 0, s, ka, ia, kb, ib, n, shift, gh, nt);
-        K* tk = ka; ka = kb; kb = tk;
-        uint32_t* ti = ia; ia = ib; ib = ti;
+    if (n < kNarrowMax) sort_onesweep<K, uint32_t>(nullptr, keys, idx, keys_alt, idx_alt, n, tmp, s);
+    else sort_onesweep<K, uint64_t>(nullptr, keys, idx, keys_alt, idx_alt, n, tmp, s);
+}
+
+template <class K>
+void sort_from(const K* src, K* keys, uint32_t* idx, K* keys_alt, uint32_t* idx_alt, uint64_t n, void* tmp,
+               hipStream_t s) {
+    if (n <= kBitonicMax) {
+        // stage (key, position) pairs, then the in-workgroup sort
+        hipLaunchKernelGGL(k_sort_stage<K>, dim3(static_cast<uint32_t>((n + 255) / 256 ? (n + 255) / 256 : 1)),
+                           dim3(256), 0, s, src, n, keys, idx);
+        sort_pairs<K>(keys, idx, keys_alt, idx_alt, n, tmp, s);
+        return;
     }
-    // sizeof(K) passes is even, so the result is back in keys/idx
+    if (n < kNarrowMax) sort_onesweep<K, uint32_t>(src, keys, idx, keys_alt, idx_alt, n, tmp, s);
+    else sort_onesweep<K, uint64_t>(src, keys, idx, keys_alt, idx_alt, n, tmp, s);
 }
 
 // ------------------------------------------------------------ rank sort
@@ -342,6 +454,10 @@ template void rank_sort_small<uint64_t>(const uint64_t*, uint32_t, uint64_t*, ui
                                         hipStream_t);
 
 template void sort_pairs<uint32_t>(uint32_t*, uint32_t*, uint32_t*, uint32_t*, uint64_t, void*, hipStream_t);
+template void sort_from<uint32_t>(const uint32_t*, uint32_t*, uint32_t*, uint32_t*, uint32_t*, uint64_t, void*,
+                                  hipStream_t);
+template void sort_from<uint64_t>(const uint64_t*, uint64_t*, uint32_t*, uint64_t*, uint32_t*, uint64_t, void*,
+                                  hipStream_t);
 template void sort_pairs<uint64_t>(uint64_t*, uint32_t*, uint64_t*, uint32_t*, uint64_t, void*, hipStream_t);
 
 }  // namespace gt

@@ -150,6 +150,36 @@ def test_large_batch_radix_path():
     assert_lookup_parity(t, sa, k[:200000])
 
 
+@pytest.mark.parametrize("width", [32, 64])
+def test_radix_path_repeats_last_writer_wins(width):
+    """Batches above the rank-sort limit go through the device radix sort,
+    whose tiles find their output offsets by look-back over earlier tiles.
+    Heavy in-batch repeats in shuffled order (a few hundred keys, each dozens
+    of times, half of them already present) make the last occurrence's value
+    win only if the sort keeps equal keys in batch order; small-range keys
+    leave every upper digit zero, so one digit's run spans every tile."""
+    seed = 23
+    keys = synth.uniform_keys(1 << 14, seed, width)
+    vals = synth.values_for(keys, seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, width // 8, leaf_slack=1 << 13, max_batch=1 << 16)
+    rng = np.random.default_rng(seed)
+    dt = keys.dtype
+    for B in (2049, 6151, 40000):
+        fresh = synth.uniform_keys(300, seed + B, width, exclude=keys)
+        k = np.concatenate([fresh[rng.integers(0, 300, B // 2)], keys[rng.integers(0, 300, B - B // 2)]])
+        k = k.astype(dt)
+        v = rng.integers(0, np.iinfo(dt).max, B, dtype=dt, endpoint=True)
+        assert np.array_equal(t.insert(k, v), sa.insert(k, v)), f"statuses, B={B}"
+        assert_export_parity(t, sa)
+    small = np.arange(1, 9000, 3, dtype=dt)
+    k = small[rng.integers(0, len(small), 30000)]
+    v = rng.integers(0, np.iinfo(dt).max, len(k), dtype=dt, endpoint=True)
+    assert np.array_equal(t.insert(k, v), sa.insert(k, v)), "statuses, small-range keys"
+    assert_export_parity(t, sa)
+    assert_lookup_parity(t, sa, np.concatenate([small, keys[:5000]]))
+
+
 @pytest.mark.parametrize("xcd", [0, 1])
 def test_mirror_follows_top_levels(xcd):
     """Height-5 tree (2^20 u64 keys), three mirrored inner levels staged in
