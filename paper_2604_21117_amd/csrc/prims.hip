@@ -230,6 +230,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(const K* __restrict__ 
     constexpr int kSh = static_cast<int>(sizeof(W)) * 8 - 2;
     constexpr W kAgg = W(1) << kSh, kIncl = W(2) << kSh, kVal = (W(1) << kSh) - 1;
     __shared__ uint32_t wcnt[kSortBlock / 64][256];
+    __shared__ uint32_t part[4][256];  // per digit: counts of four waves each
     __shared__ uint32_t run[256];
     __shared__ uint32_t lstart[256];  // this tile's run of digit d inside the tile
     __shared__ uint64_t gbase[256];   // and in the output
@@ -239,55 +240,74 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(const K* __restrict__ 
     __shared__ uint32_t ti[kSortTile];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     if (tid == 0) s_tile = atomicAdd(ticket, 1u);
-    if (tid < 256) run[tid] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
     const uint64_t tbase = static_cast<uint64_t>(tile) * kSortTile;
-    // where each digit starts in the output: scan of the pass's totals
-    uint32_t tot;
-    const uint32_t dstart = block_excl_scan<uint32_t>(tid < 256 ? totals[tid] : 0u, sh, &tot);
-
-    // rank the tile's elements by digit, in input order
+    // rank the tile's elements by digit, in input order.  Wave w ranks the
+    // tile's w-th block of 256 elements, four 64-element chunks in order,
+    // against its own per-digit running count in LDS (one wave's LDS
+    // operations take effect in order, so the chunks need no barrier); a
+    // prefix over the waves then offsets each wave's runs.  Every chunk's
+    // key and index are loaded up front.
+    constexpr int kPerWave = kSortTile / (kSortBlock / 64);  // 256
     const uint64_t lt = (1ull << lane) - 1ull;
     K kr[kSortRounds];
     uint32_t dr[kSortRounds], rr[kSortRounds], ir[kSortRounds];
     bool vr[kSortRounds];
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
+        const uint64_t i = tbase + static_cast<uint64_t>(w) * kPerWave + r * 64 + lane;
+        vr[r] = i < n;
+        kr[r] = vr[r] ? kin[i] : K(0);
+        ir[r] = vr[r] ? (iin ? iin[i] : static_cast<uint32_t>(i)) : 0u;
+    }
+    {
         uint32_t* flat = &wcnt[0][0];
         for (int j = tid; j < (kSortBlock / 64) * 256; j += kSortBlock) flat[j] = 0;
-        __syncthreads();
-        const uint64_t i = tbase + r * kSortBlock + tid;
-        const bool valid = i < n;
-        const K k = valid ? kin[i] : K(0);
-        const uint32_t d = static_cast<uint32_t>(k >> shift) & 255u;
+    }
+    // where each digit starts in the output: scan of the pass's totals (its
+    // barriers also order the clearing above before the counting below)
+    uint32_t tot;
+    const uint32_t dstart = block_excl_scan<uint32_t>(tid < 256 ? totals[tid] : 0u, sh, &tot);
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+        const bool valid = vr[r];
+        const uint32_t d = static_cast<uint32_t>(kr[r] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
             const uint64_t m = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
+        const uint32_t base = wcnt[w][d];
         const uint32_t rank = static_cast<uint32_t>(__popcll(peers & lt));
-        if (valid && rank == 0) wcnt[w][d] = static_cast<uint32_t>(__popcll(peers));
-        __syncthreads();
-        if (tid < 256) {
-            uint32_t acc = run[tid];
-#pragma unroll
-            for (int ww = 0; ww < kSortBlock / 64; ++ww) {
-                const uint32_t c = wcnt[ww][tid];
-                wcnt[ww][tid] = acc;
-                acc += c;
-            }
-            run[tid] = acc;
-        }
-        __syncthreads();
-        kr[r] = k;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rank == 0) wcnt[w][d] = base + static_cast<uint32_t>(__popcll(peers));
+        __builtin_amdgcn_wave_barrier();
         dr[r] = d;
-        vr[r] = valid;
-        rr[r] = valid ? wcnt[w][d] + rank : 0u;
-        ir[r] = valid ? (iin ? iin[i] : static_cast<uint32_t>(i)) : 0u;
+        rr[r] = base + rank;  // rank among this wave's elements of digit d
+    }
+    __syncthreads();
+    // per digit, offsets of the waves' runs: thread (digit, q) sums waves
+    // 4q..4q+3, then adds the earlier quarters
+    {
+        static_assert(kSortBlock == 1024, "four threads per digit, four waves each");
+        const int dd = tid & 255, q = tid >> 8;
+        const uint32_t c0 = wcnt[4 * q][dd], c1 = wcnt[4 * q + 1][dd];
+        const uint32_t c2 = wcnt[4 * q + 2][dd], c3 = wcnt[4 * q + 3][dd];
+        part[q][dd] = c0 + c1 + c2 + c3;
+        __syncthreads();
+        uint32_t b0 = 0;
+        for (int qq = 0; qq < q; ++qq) b0 += part[qq][dd];
+        wcnt[4 * q][dd] = b0;
+        wcnt[4 * q + 1][dd] = b0 + c0;
+        wcnt[4 * q + 2][dd] = b0 + c0 + c1;
+        wcnt[4 * q + 3][dd] = b0 + c0 + c1 + c2;
+        if (q == 3) run[dd] = b0 + c0 + c1 + c2 + c3;
         __syncthreads();
     }
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) rr[r] += vr[r] ? wcnt[w][dr[r]] : 0u;
 
     // publish this tile's counts, look back for the earlier tiles' sums
     if (tid < 256) {
@@ -298,14 +318,32 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(const K* __restrict__ 
             __hip_atomic_store(mine, kIncl | static_cast<W>(cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             __hip_atomic_store(mine, kAgg | static_cast<W>(cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            uint32_t j = tile - 1, spins = 0;
-            for (;;) {
-                const W x = __hip_atomic_load(flags + static_cast<uint64_t>(j) * 256 + tid, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-                const W f = x >> kSh;
-                if (f == 2) { excl += x & kVal; break; }
-                if (f == 1 && j > 0) { excl += x & kVal; --j; continue; }
-                if (f == 1 || ++spins > kSpinMax) { atomicOr(err, 1u); break; }  // tile 0 is never a bare count
+            // eight earlier tiles per step, their words read together; sum
+            // counts until an inclusive prefix, resume at a tile not yet
+            // published
+            constexpr int kLook = 8;
+            int64_t j = static_cast<int64_t>(tile) - 1;
+            uint32_t spins = 0;
+            bool done = false;
+            while (!done) {
+                W x[kLook];
+#pragma unroll
+                for (int q = 0; q < kLook; ++q)
+                    x[q] = j - q >= 0 ? __hip_atomic_load(flags + static_cast<uint64_t>(j - q) * 256 + tid,
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                      : kIncl;  // never reached: tile 0 publishes an inclusive prefix
+                int used = 0;
+#pragma unroll
+                for (int q = 0; q < kLook; ++q) {
+                    if (done || used < q) continue;  // stopped at an earlier word
+                    const W f = x[q] >> kSh;
+                    if (f == 0) continue;  // not yet published
+                    excl += x[q] & kVal;
+                    ++used;
+                    if (f == 2) done = true;
+                }
+                j -= used;
+                if (!done && used == 0 && ++spins > kSpinMax) { atomicOr(err, 1u); break; }
             }
             __hip_atomic_store(mine, kIncl | static_cast<W>(excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
