@@ -793,10 +793,11 @@ __global__ __launch_bounds__(kFusedBlock) void k_small_apply(TreeView<K> t, Ins<
 
 // ------------------------------------------------- small batches (B <= 2048)
 //
-// A rank sort over many workgroups orders the batch; then one workgroup
-// deduplicates and plans every level, with barriers where the general path
-// has kernel boundaries and block scans where it has device-wide scans; the
-// phase bodies are the same functions.
+// A rank sort over many workgroups orders the batch and one workgroup
+// deduplicates it; after locate, one workgroup sized to the batch plans every
+// level (k_small_plan), and up to kFusedMax keys one more workgroup applies
+// the whole batch (k_small_apply).  The results are those of the general
+// path: the same item arrays and level counters, the same apply bodies.
 
 constexpr uint32_t kSmallInsert = 2048;
 static_assert(kSmallInsert <= kRankSortMax, "the small path sorts with rank_sort_small");

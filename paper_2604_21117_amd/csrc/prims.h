@@ -65,21 +65,6 @@ __device__ __forceinline__ void bitonic_lds(K* sk, uint32_t* si, uint32_t n2) {
     }
 }
 
-// Exclusive scan of in[0..n) into out[0..n) (global memory, may alias) by
-// one workgroup, n <= 2 * blockDim.x; the total goes to *tot.  All threads
-// call it; it ends with a barrier.
-__device__ __forceinline__ void block_scan_small(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tot,
-                                                 uint32_t* sh) {
-    const uint32_t i0 = 2 * threadIdx.x, i1 = i0 + 1;
-    const uint32_t a = i0 < n ? in[i0] : 0u, b = i1 < n ? in[i1] : 0u;
-    uint32_t total;
-    const uint32_t off = block_excl_scan<uint32_t>(a + b, sh, &total);
-    if (i0 < n) out[i0] = off;
-    if (i1 < n) out[i1] = off + a;
-    if (tot && threadIdx.x == 0) *tot = total;
-    __syncthreads();
-}
-
 // ------------------------------------------------------------ host side
 
 // Largest batch rank_sort_small takes (all keys sit in each workgroup's LDS).
