@@ -451,16 +451,36 @@ __global__ void k_bounds_init(int32_t* bnd, uint32_t* cnt, uint32_t cells) {
 }
 
 // Every key of the tree, one lane per key slot, through both kinds of its
-// model.  Neighbouring slots almost always share a piece: a wave whose keys
-// all do reduces in registers and issues one set of atomics.
+// model.  Neighbouring slots almost always share a piece: a wave whose 64
+// slots all do reduces them in registers and keeps the piece's bounds until
+// its run of windows reaches another piece, then issues one set of atomics.
 template <class K>
 __global__ __launch_bounds__(kLiBlock) void k_bounds(TreeView<K> t, LiView<K> li, uint32_t nleaves) {
     const LiArgs a = args_of(li.hdr);
     const uint64_t total = static_cast<uint64_t>(nleaves) * kSlots;
     const int lane = lane_id();
-    const uint64_t w0 = gid() - static_cast<uint64_t>(lane);
-    for (uint64_t base = w0; base < total; base += gsz()) {
-        const uint64_t x = base + static_cast<uint64_t>(lane);
+    // each wave takes a contiguous run of 64-slot windows and carries the
+    // bounds of its current piece across windows (consecutive windows mostly
+    // share a piece), so a piece's atomics go out once per run, not once per
+    // window
+    const uint64_t nwin = (total + 63) / 64, nwave = gsz() / 64;
+    const uint64_t per = (nwin + nwave - 1) / nwave;
+    const uint64_t wb = (gid() / 64) * per, we = wb + per < nwin ? wb + per : nwin;
+    uint32_t cur = UINT32_MAX, ccnt = 0;
+    int32_t clmin = INT32_MAX, clmax = INT32_MIN, cmmin = INT32_MAX, cmmax = INT32_MIN;
+    auto flush = [&]() {
+        if (cur != UINT32_MAX && lane == 0) {
+            atomicMin(&li.bnd[4 * cur + 0], clmin);
+            atomicMax(&li.bnd[4 * cur + 1], clmax);
+            if (cmmin <= cmmax) {
+                atomicMin(&li.bnd[4 * cur + 2], cmmin);
+                atomicMax(&li.bnd[4 * cur + 3], cmmax);
+            }
+            atomicAdd(&li.cnt[cur], ccnt);
+        }
+    };
+    for (uint64_t wi = wb; wi < we; ++wi) {
+        const uint64_t x = wi * 64 + static_cast<uint64_t>(lane);
         bool valid = false;
         uint32_t cell = 0;
         int32_t rl = 0, rm = 0;
@@ -492,15 +512,17 @@ __global__ __launch_bounds__(kLiBlock) void k_bounds(TreeView<K> t, LiView<K> li
                 mmin = min(mmin, __shfl_xor(mmin, d, 64));
                 mmax = max(mmax, __shfl_xor(mmax, d, 64));
             }
-            if (lane == first) {
-                atomicMin(&li.bnd[4 * c0 + 0], lmin);
-                atomicMax(&li.bnd[4 * c0 + 1], lmax);
-                if (mmin <= mmax) {
-                    atomicMin(&li.bnd[4 * c0 + 2], mmin);
-                    atomicMax(&li.bnd[4 * c0 + 3], mmax);
-                }
-                atomicAdd(&li.cnt[c0], static_cast<uint32_t>(__popcll(vmask)));
+            if (c0 != cur) {
+                flush();
+                cur = c0;
+                ccnt = 0;
+                clmin = INT32_MAX; clmax = INT32_MIN; cmmin = INT32_MAX; cmmax = INT32_MIN;
             }
+            clmin = min(clmin, lmin);
+            clmax = max(clmax, lmax);
+            cmmin = min(cmmin, mmin);
+            cmmax = max(cmmax, mmax);
+            ccnt += static_cast<uint32_t>(__popcll(vmask));
         } else if (valid) {
             atomicMin(&li.bnd[4 * cell + 0], rl);
             atomicMax(&li.bnd[4 * cell + 1], rl);
@@ -511,6 +533,7 @@ __global__ __launch_bounds__(kLiBlock) void k_bounds(TreeView<K> t, LiView<K> li
             atomicAdd(&li.cnt[cell], 1u);
         }
     }
+    flush();
 }
 
 // One wave per model, lane m < 32 per piece: pick the kind with the smaller
