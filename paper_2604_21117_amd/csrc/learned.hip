@@ -54,6 +54,7 @@
 #include "common.h"
 #include "traverse.h"
 #include "handle.h"
+#include "prims.h"
 
 namespace gt {
 
@@ -398,21 +399,105 @@ __global__ __launch_bounds__(256) void k_fit(LiView<K> li, uint32_t L, uint32_t 
     if (threadIdx.x == 0) solved = 0;
     __syncthreads();
     if (nq >= 8) {
-        // normal equations, upper triangle and right-hand side
         constexpr int NT = NF * (NF + 1) / 2;
-        for (int q = threadIdx.x; q < NT + NF; q += blockDim.x) {
-            double acc = 0.0;
-            if (q < NT) {
-                int ua = 0, rem = q;
-                while (rem >= NF - ua) { rem -= NF - ua; ++ua; }
-                const int ub = ua + rem;
-                for (uint32_t i = 0; i < nq; ++i) acc += feature(ua, xs[i]) * feature(ub, xs[i]);
-                G[ua * NF + ub] = acc;
-                G[ub * NF + ua] = acc;
-            } else {
-                const int ua = q - NT;
-                for (uint32_t i = 0; i < nq; ++i) acc += feature(ua, xs[i]) * static_cast<double>(ys[i]);
-                rr[ua] = acc;
+        // The points come in increasing x (fences in key order through one
+        // monotone map), and the features are x, relu(x - u/32) and 1, so
+        // every normal-equation entry is a polynomial in five suffix sums
+        // over the points beyond a knot b: S0, S1, S2 (powers of x), T0, T1
+        // (y and x y).  For knots a <= b:
+        //   sum x relu(x-b) = S2(b) - b S1(b),  sum relu(x-b) = S1(b) - b S0(b),
+        //   sum relu(x-a) relu(x-b) = S2(b) - (a+b) S1(b) + a b S0(b),
+        //   sum relu(x-b) y = T1(b) - b T0(b).
+        // Each thread sums kPer consecutive points; a block scan of those
+        // sums plus a short run inside one thread's points gives the prefix
+        // at each knot's first point beyond it (fixed order, so repeatable).
+        // Points out of order (never expected) fall back to direct sums.
+        constexpr int kPer = kFitPoints / 256;  // the workgroup is 256 threads
+        static_assert(kFitPoints % 256 == 0, "whole runs per thread");
+        __shared__ double tp[5][257];
+        __shared__ double suf[5][kSeg];
+        const uint32_t t0 = threadIdx.x * kPer;
+        bool unsorted = false;
+        double qs[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < kPer; ++k) {
+            const uint32_t i = t0 + k;
+            if (i < nq) {
+                const double x = xs[i], y = ys[i];
+                qs[0] += 1.0; qs[1] += x; qs[2] += x * x; qs[3] += y; qs[4] += x * y;
+                if (i + 1 < nq && xs[i + 1] < xs[i]) unsorted = true;
+            }
+        }
+        if (__syncthreads_or(unsorted ? 1 : 0) == 0) {
+            for (int c = 0; c < 5; ++c) {
+                double tot;
+                const double ex = block_excl_scan<double>(qs[c], sh, &tot);
+                tp[c][threadIdx.x] = ex;
+                if (threadIdx.x == 0) tp[c][256] = tot;
+            }
+            __syncthreads();
+            if (threadIdx.x < static_cast<unsigned>(kSeg)) {
+                const int u = threadIdx.x;
+                uint32_t idx = 0;  // first point beyond knot u/32 (u = 0: all points)
+                if (u > 0) {
+                    const double b = static_cast<double>(u) / kSeg;
+                    uint32_t lo = 0, hi = nq;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (static_cast<double>(xs[mid]) > b) hi = mid;
+                        else lo = mid + 1;
+                    }
+                    idx = lo;
+                }
+                const uint32_t tr = idx / kPer;
+                double pre[5];
+                for (int c = 0; c < 5; ++c) pre[c] = tp[c][tr];
+                for (uint32_t i = tr * kPer; i < idx; ++i) {
+                    const double x = xs[i], y = ys[i];
+                    pre[0] += 1.0; pre[1] += x; pre[2] += x * x; pre[3] += y; pre[4] += x * y;
+                }
+                for (int c = 0; c < 5; ++c) suf[c][u] = tp[c][256] - pre[c];
+            }
+            __syncthreads();
+            for (int q = threadIdx.x; q < NT + NF; q += blockDim.x) {
+                if (q < NT) {
+                    int ua = 0, rem = q;
+                    while (rem >= NF - ua) { rem -= NF - ua; ++ua; }
+                    const int ub = ua + rem;  // ua <= ub
+                    double acc;
+                    if (ua == kSeg) {
+                        acc = suf[0][0];
+                    } else if (ua == 0) {
+                        const double b = static_cast<double>(ub) / kSeg;
+                        acc = ub == 0 ? suf[2][0] : ub == kSeg ? suf[1][0] : suf[2][ub] - b * suf[1][ub];
+                    } else {
+                        const double a = static_cast<double>(ua) / kSeg, b = static_cast<double>(ub) / kSeg;
+                        acc = ub == kSeg ? suf[1][ua] - a * suf[0][ua]
+                                         : suf[2][ub] - (a + b) * suf[1][ub] + a * b * suf[0][ub];
+                    }
+                    G[ua * NF + ub] = acc;
+                    G[ub * NF + ua] = acc;
+                } else {
+                    const int ua = q - NT;
+                    const double b = static_cast<double>(ua) / kSeg;
+                    rr[ua] = ua == 0 ? suf[4][0] : ua == kSeg ? suf[3][0] : suf[4][ua] - b * suf[3][ua];
+                }
+            }
+        } else {
+            // normal equations by direct sums, upper triangle and right-hand side
+            for (int q = threadIdx.x; q < NT + NF; q += blockDim.x) {
+                double acc = 0.0;
+                if (q < NT) {
+                    int ua = 0, rem = q;
+                    while (rem >= NF - ua) { rem -= NF - ua; ++ua; }
+                    const int ub = ua + rem;
+                    for (uint32_t i = 0; i < nq; ++i) acc += feature(ua, xs[i]) * feature(ub, xs[i]);
+                    G[ua * NF + ub] = acc;
+                    G[ub * NF + ua] = acc;
+                } else {
+                    const int ua = q - NT;
+                    for (uint32_t i = 0; i < nq; ++i) acc += feature(ua, xs[i]) * static_cast<double>(ys[i]);
+                    rr[ua] = acc;
+                }
             }
         }
         __syncthreads();
