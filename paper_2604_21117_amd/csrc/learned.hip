@@ -584,22 +584,26 @@ __global__ __launch_bounds__(kLiBlock) void k_bounds(TreeView<K> t, LiView<K> li
                 if (mok) rm = pos - piece_pos(f->A[r.m], f->C[r.m], f->base, r.x, a.L);
             }
         }
-        const uint64_t vmask = __ballot(valid);
-        if (vmask == 0) continue;
-        const int first = __builtin_ctzll(vmask);
-        const uint32_t c0 = static_cast<uint32_t>(__shfl(static_cast<int>(cell), first, 64));
-        if (__ballot(valid && cell != c0) == 0) {
-            int32_t lmin = valid ? rl : INT32_MAX, lmax = valid ? rl : INT32_MIN;
-            int32_t mmin = valid && mok ? rm : INT32_MAX, mmax = valid && mok ? rm : INT32_MIN;
+        // the window's pieces in lane order (almost always one, at a piece
+        // boundary two): each is reduced over its lanes, then merged into the
+        // running piece or, when it differs, flushes the running one first
+        uint64_t rem = __ballot(valid);
+        while (rem) {
+            const int ld = __builtin_ctzll(rem);
+            const uint32_t cc = static_cast<uint32_t>(__shfl(static_cast<int>(cell), ld, 64));
+            const bool mine = valid && cell == cc;
+            const uint64_t mm = __ballot(mine);
+            int32_t lmin = mine ? rl : INT32_MAX, lmax = mine ? rl : INT32_MIN;
+            int32_t mmin = mine && mok ? rm : INT32_MAX, mmax = mine && mok ? rm : INT32_MIN;
             for (int d = 32; d > 0; d >>= 1) {
                 lmin = min(lmin, __shfl_xor(lmin, d, 64));
                 lmax = max(lmax, __shfl_xor(lmax, d, 64));
                 mmin = min(mmin, __shfl_xor(mmin, d, 64));
                 mmax = max(mmax, __shfl_xor(mmax, d, 64));
             }
-            if (c0 != cur) {
+            if (cc != cur) {
                 flush();
-                cur = c0;
+                cur = cc;
                 ccnt = 0;
                 clmin = INT32_MAX; clmax = INT32_MIN; cmmin = INT32_MAX; cmmax = INT32_MIN;
             }
@@ -607,15 +611,8 @@ __global__ __launch_bounds__(kLiBlock) void k_bounds(TreeView<K> t, LiView<K> li
             clmax = max(clmax, lmax);
             cmmin = min(cmmin, mmin);
             cmmax = max(cmmax, mmax);
-            ccnt += static_cast<uint32_t>(__popcll(vmask));
-        } else if (valid) {
-            atomicMin(&li.bnd[4 * cell + 0], rl);
-            atomicMax(&li.bnd[4 * cell + 1], rl);
-            if (mok) {
-                atomicMin(&li.bnd[4 * cell + 2], rm);
-                atomicMax(&li.bnd[4 * cell + 3], rm);
-            }
-            atomicAdd(&li.cnt[cell], 1u);
+            ccnt += static_cast<uint32_t>(__popcll(mm));
+            rem &= ~mm;
         }
     }
     flush();
