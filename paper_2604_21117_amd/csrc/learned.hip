@@ -135,7 +135,9 @@ struct LiView {
     Piece* piece;          // M * kSeg
     uint32_t* identity;
     DirEntry<K>* dir;      // L + 1 (the last entry: largest key, no leaf)
-    uint32_t* nxt0; uint32_t* nxt1; uint32_t* rank0; uint32_t* rank1;
+    uint32_t* nxt0; uint32_t* nxt1; uint32_t* rank0; uint32_t* rank1;  // training scratch
+    uint32_t* lvl;         // kMaxLevels: nodes per tree level while positions are computed
+    void* scan_tmp;
     uint32_t* pos_of_leaf;
     uint32_t* start;       // M + 1
     int32_t* bnd;          // 4 per piece: lo, hi of the line; lo, hi of the network
@@ -213,36 +215,56 @@ __device__ __forceinline__ LiArgs args_of(const LiHeader* h) {
 __device__ __forceinline__ uint64_t gid() { return blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; }
 __device__ __forceinline__ uint64_t gsz() { return static_cast<uint64_t>(gridDim.x) * blockDim.x; }
 
-__global__ void k_rank_init(const uint2* lmeta, uint32_t n, uint32_t* nxt, uint32_t* rank) {
-    for (uint64_t i = gid(); i < n; i += gsz()) {
-        const uint32_t x = lmeta[i].y;
-        nxt[i] = x;
-        rank[i] = x == kNone ? 0u : 1u;
+// Leaf positions in key order, by expanding the tree from the root one level
+// at a time: a level's nodes are listed in key order, so their children,
+// taken node after node in slot order, are the next level in key order, and
+// the last expansion gives each leaf its position.  Sixteen lanes per node
+// read its child line; the level's size stays on the device.
+__global__ void k_bfs_init(uint32_t* list, uint32_t* m_dev, uint32_t root, uint32_t* pos, uint32_t root_is_leaf) {
+    if (gid() == 0) {
+        list[0] = root;
+        m_dev[0] = 1;
+        if (root_is_leaf) pos[root & ~kLeafTag] = 0;
     }
 }
 
-__global__ void k_rank_jump(const uint32_t* nin, const uint32_t* rin, uint32_t* nout, uint32_t* rout, uint32_t n) {
-    for (uint64_t i = gid(); i < n; i += gsz()) {
-        const uint32_t x = nin[i];
-        if (x == kNone) {
-            nout[i] = kNone;
-            rout[i] = rin[i];
-        } else {
-            nout[i] = nin[x];
-            rout[i] = rin[i] + rin[x];
+__global__ void k_bfs_count(const uint32_t* __restrict__ ichild, const uint32_t* __restrict__ list,
+                            const uint32_t* __restrict__ m_dev, uint32_t* __restrict__ cnt) {
+    const uint64_t m16 = static_cast<uint64_t>(*m_dev) * kSlots;
+    for (uint64_t g = gid(); g < m16; g += gsz()) {
+        const uint64_t i = g / kSlots;
+        const uint32_t sl = static_cast<uint32_t>(g % kSlots);
+        const bool has = ichild[static_cast<uint64_t>(list[i]) * kSlots + sl] != kNone;
+        const uint64_t m = __ballot(has);
+        const int lane = lane_id(), gb = lane & ~(kSlots - 1);
+        if (sl == 0) cnt[i] = static_cast<uint32_t>(__popcll((m >> gb) & 0xFFFFull));
+    }
+}
+
+__global__ void k_bfs_scatter(const uint32_t* __restrict__ ichild, const uint32_t* __restrict__ list,
+                              const uint32_t* __restrict__ m_dev, const uint32_t* __restrict__ cnt,
+                              const uint32_t* __restrict__ off, uint32_t* __restrict__ next,
+                              uint32_t* __restrict__ pos, uint32_t last) {
+    const uint64_t m16 = static_cast<uint64_t>(*m_dev) * kSlots;
+    for (uint64_t g = gid(); g < m16; g += gsz()) {
+        const uint64_t i = g / kSlots;
+        const uint32_t sl = static_cast<uint32_t>(g % kSlots);
+        if (sl < cnt[i]) {
+            const uint32_t ref = ichild[static_cast<uint64_t>(list[i]) * kSlots + sl];
+            if (last) pos[ref & ~kLeafTag] = off[i] + sl;
+            else next[off[i] + sl] = ref;
         }
     }
 }
 
 template <class K>
-__global__ void k_directory(TreeView<K> t, LiView<K> li, const uint32_t* rank, uint32_t n) {
+__global__ void k_directory(TreeView<K> t, LiView<K> li, uint32_t n) {
     for (uint64_t i = gid(); i < n; i += gsz()) {
-        const uint32_t pos = n - 1 - rank[i];
+        const uint32_t pos = li.pos_of_leaf[i];
         DirEntry<K> e;
         e.fence = t.lkeys[i * kSlots];
         e.leaf = static_cast<uint32_t>(i);
         li.dir[pos] = e;
-        li.pos_of_leaf[i] = pos;
     }
     if (gid() == 0) {
         DirEntry<K> e;
@@ -1001,7 +1023,7 @@ struct gt_learned {
     bool trained;
     uint64_t leaf_cap;
     uint64_t off_fit, off_piece, off_dir, off_nxt0, off_nxt1, off_rank0, off_rank1, off_pos, off_start, off_bnd,
-        off_cnt, off_partial, off_ident;
+        off_cnt, off_partial, off_ident, off_lvl, off_scan;
     LiArgs args;
     bool declined = false;    // the quality gate sends lookups to the tree kernel
     uint32_t max_win = 0;     // widest window at training (leaves)
@@ -1046,11 +1068,15 @@ uint64_t layout_li(gt_learned* li, uint64_t leaf_cap, uint32_t M, int kb) {
     uint64_t o_cnt = off; off += al256(cells * 4);
     uint64_t o_part = off; off += al256(kMaxPartials * 5ull * 8);
     uint64_t o_ident = off; off += 256;
+    uint64_t o_lvl = off; off += al256(kMaxLevels * 4);
+    uint64_t o_scan = off; off += al256(scan_tmp_bytes(leaf_cap + 1));
     if (li) {
         li->off_fit = o_fit; li->off_piece = o_piece; li->off_dir = o_dir; li->off_nxt0 = o_n0;
         li->off_nxt1 = o_n1; li->off_rank0 = o_r0; li->off_rank1 = o_r1; li->off_pos = o_pos;
         li->off_start = o_start; li->off_bnd = o_bnd; li->off_cnt = o_cnt; li->off_partial = o_part;
         li->off_ident = o_ident;
+        li->off_lvl = o_lvl;
+        li->off_scan = o_scan;
     }
     return off;
 }
@@ -1073,6 +1099,8 @@ LiView<K> li_view(const gt_learned* li) {
     v.cnt = reinterpret_cast<uint32_t*>(a + li->off_cnt);
     v.partial = reinterpret_cast<double*>(a + li->off_partial);
     v.identity = reinterpret_cast<uint32_t*>(a + li->off_ident);
+    v.lvl = reinterpret_cast<uint32_t*>(a + li->off_lvl);
+    v.scan_tmp = a + li->off_scan;
     return v;
 }
 
@@ -1108,14 +1136,25 @@ gt_status train_t(gt_learned* li, hipStream_t s) {
     }
     const uint32_t n = dh.leaf_used;
     if (n > li->leaf_cap) return GT_ERR_CAPACITY;
-    hipLaunchKernelGGL(k_rank_init, dim3(grid_of(n, 256)), dim3(256), 0, s, t->lmeta, n, v.nxt0, v.rank0);
-    uint32_t* ni = v.nxt0; uint32_t* ri = v.rank0; uint32_t* no = v.nxt1; uint32_t* ro = v.rank1;
-    for (uint64_t span = 1; span < n; span <<= 1) {
-        hipLaunchKernelGGL(k_rank_jump, dim3(grid_of(n, 256)), dim3(256), 0, s, ni, ri, no, ro, n);
-        uint32_t* a = ni; ni = no; no = a;
-        uint32_t* b = ri; ri = ro; ro = b;
+    // leaf positions: expand the levels from the root (lists in nxt0/nxt1,
+    // per-node child counts and their offsets in rank0/rank1)
+    {
+        const uint32_t h = dh.height;
+        uint32_t* la = v.nxt0; uint32_t* lb = v.nxt1;
+        uint32_t* lvl = v.lvl;  // lvl[l] = nodes of level l
+        hipLaunchKernelGGL(k_bfs_init, dim3(1), dim3(64), 0, s, la, lvl, dh.root, v.pos_of_leaf, h <= 1 ? 1u : 0u);
+        uint64_t bound = 1;  // nodes a level can have
+        for (uint32_t l = 0; l + 1 < h; ++l) {
+            const uint64_t g = grid_of(bound * kSlots, 256, 8192);
+            hipLaunchKernelGGL(k_bfs_count, dim3(g), dim3(256), 0, s, t->ichild, la, lvl + l, v.rank0);
+            scan_exclusive<uint32_t>(v.rank0, v.rank1, lvl + l + 1, lvl + l, bound, v.scan_tmp, s);
+            hipLaunchKernelGGL(k_bfs_scatter, dim3(g), dim3(256), 0, s, t->ichild, la, lvl + l, v.rank0, v.rank1, lb,
+                               v.pos_of_leaf, l + 2 == h ? 1u : 0u);
+            uint32_t* x = la; la = lb; lb = x;
+            bound = bound * kSlots < n ? bound * kSlots : n;
+        }
     }
-    hipLaunchKernelGGL(k_directory<K>, dim3(grid_of(n, 256)), dim3(256), 0, s, tv, v, ri, n);
+    hipLaunchKernelGGL(k_directory<K>, dim3(grid_of(n, 256)), dim3(256), 0, s, tv, v, n);
     // root normalisation: smallest first key .. largest key of the tree
     DirEntry<K> d0, dl;
     LI_HIP(hipMemcpyAsync(&d0, v.dir, sizeof d0, hipMemcpyDeviceToHost, s));
