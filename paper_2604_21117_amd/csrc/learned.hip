@@ -342,34 +342,51 @@ __global__ void k_ranges(LiView<K> li, uint32_t L, uint32_t M) {
     }
 }
 
-// Solve (G + ridge) w = r by Cholesky, n <= 33, FP64, one thread.
-__device__ bool cholesky_solve(double* G, double* r, int n) {
-    double tr = 0;
-    for (int i = 0; i < n; ++i) tr += G[i * n + i];
-    const double ridge = 1e-10 * (tr / n) + 1e-12;
-    for (int i = 0; i < n; ++i) G[i * n + i] += ridge;
+// Solve G w = r (G symmetric positive definite, n <= 64, row-major in LDS)
+// by one wave: Cholesky right-looking (step j takes the pivot, scales column
+// j below it and updates the trailing lower triangle, its elements dealt
+// over the lanes), then the two triangular solves with r held one entry per
+// lane.  A small ridge (relative to the mean diagonal) keeps G definite.
+// One wave's LDS accesses take effect in order, so no barrier is needed
+// between the steps.  Returns false (uniformly) when a pivot is not positive.
+__device__ bool cholesky_solve_wave(double* G, double* r, int n) {
+    const int lane = lane_id();
+    double dg = lane < n ? G[lane * n + lane] : 0.0;
+    for (int o = 32; o > 0; o >>= 1) dg += __shfl_xor(dg, o, 64);
+    const double ridge = 1e-10 * (dg / n) + 1e-12;
+    if (lane < n) G[lane * n + lane] += ridge;
+    __builtin_amdgcn_wave_barrier();
     for (int j = 0; j < n; ++j) {
-        double d = G[j * n + j];
-        for (int k = 0; k < j; ++k) d -= G[j * n + k] * G[j * n + k];
-        if (!(d > 0)) return false;
-        d = sqrt(d);
-        G[j * n + j] = d;
-        for (int i = j + 1; i < n; ++i) {
-            double v = G[i * n + j];
-            for (int k = 0; k < j; ++k) v -= G[i * n + k] * G[j * n + k];
-            G[i * n + j] = v / d;
+        const double pv = G[j * n + j];
+        if (!(pv > 0)) return false;
+        const double dj = sqrt(pv);
+        if (lane > j && lane < n) G[lane * n + j] /= dj;
+        if (lane == j) G[j * n + j] = dj;
+        __builtin_amdgcn_wave_barrier();
+        const int m = n - j - 1, cnt = m * (m + 1) / 2;
+        for (int e = lane; e < cnt; e += 64) {
+            // e -> (ii, kk), kk <= ii, row-major over the trailing triangle
+            int ii = static_cast<int>((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+            if ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
+            if (ii * (ii + 1) / 2 > e) --ii;
+            const int kk = e - ii * (ii + 1) / 2;
+            const int i = j + 1 + ii, k = j + 1 + kk;
+            G[i * n + k] -= G[i * n + j] * G[k * n + j];
         }
+        __builtin_amdgcn_wave_barrier();
     }
-    for (int i = 0; i < n; ++i) {  // L y = r
-        double v = r[i];
-        for (int k = 0; k < i; ++k) v -= G[i * n + k] * r[k];
-        r[i] = v / G[i * n + i];
+    double ri = lane < n ? r[lane] : 0.0;
+    for (int k = 0; k < n; ++k) {  // L y = r
+        const double yk = __shfl(ri, k, 64) / G[k * n + k];
+        if (lane == k) ri = yk;
+        else if (lane > k && lane < n) ri -= G[lane * n + k] * yk;
     }
-    for (int i = n - 1; i >= 0; --i) {  // L^T w = y
-        double v = r[i];
-        for (int k = i + 1; k < n; ++k) v -= G[k * n + i] * r[k];
-        r[i] = v / G[i * n + i];
+    for (int k = n - 1; k >= 0; --k) {  // L^T w = y
+        const double wk = __shfl(ri, k, 64) / G[k * n + k];
+        if (lane == k) ri = wk;
+        else if (lane < k) ri -= G[k * n + lane] * wk;
     }
+    if (lane < n) r[lane] = ri;
     return true;
 }
 
@@ -523,7 +540,10 @@ __global__ __launch_bounds__(256) void k_fit(LiView<K> li, uint32_t L, uint32_t 
             }
         }
         __syncthreads();
-        if (threadIdx.x == 0) solved = cholesky_solve(G, rr, NF) ? 1 : 0;
+        if (threadIdx.x < 64) {
+            const bool ok = cholesky_solve_wave(G, rr, NF);
+            if (threadIdx.x == 0) solved = ok ? 1 : 0;
+        }
         __syncthreads();
     }
     // pieces of the network: slope_m = sum_{u<=m} w_u,
