@@ -48,7 +48,8 @@ def _random_batch(rng, pool, B, width):
 
 @pytest.mark.parametrize("width", [32, 64])
 @pytest.mark.parametrize("n,batches", [(0, [1, 5, 16, 17, 300]), (1, [15, 1, 2]), (17, [40, 1000]),
-                                       (5000, [1, 2, 3000, 5000, 700]), (70000, [4096, 1, 2049])])
+                                       (5000, [1, 2, 3000, 5000, 700]), (70000, [4096, 1, 2049]),
+                                       (3000, [64, 65, 100, 128, 129, 512, 513, 2048])])
 def test_insert_sequences(width, n, batches):
     seed = 31 + n
     rng = np.random.default_rng(seed)
