@@ -63,7 +63,8 @@ struct Ins {
     K* sk; K* sk2; uint32_t* si; uint32_t* si2; void* sort_tmp;
     uint32_t* f0; uint32_t* f1; void* scan_tmp;
     K* uk; K* uv; uint32_t* upos; uint32_t* uleaf; uint8_t* uslot; uint8_t* ufound;
-    uint32_t* pn; uint8_t* pi;
+    uint32_t* pn; uint8_t* pi; uint8_t* pc;  // per level: node, child slot taken, node's children
+    uint8_t* ulc;                             // per distinct key: its leaf's key count
     K* nk; K* nv; uint32_t* nleaf; uint32_t* nu;
     uint32_t* it_node; uint32_t* it_rep; uint32_t* it_first; uint32_t* it_end;
     uint32_t* it_cold; uint32_t* it_k; uint32_t* it_off;
@@ -117,6 +118,8 @@ static uint64_t carve(Ins<K>* v, uint8_t* base, uint64_t Bm, uint64_t leaf_cap, 
     x.ufound = take(Bm);
     x.pn = reinterpret_cast<uint32_t*>(take(static_cast<uint64_t>(kMaxLevels) * Bm * 4));
     x.pi = take(static_cast<uint64_t>(kMaxLevels) * Bm);
+    x.pc = take(static_cast<uint64_t>(kMaxLevels) * Bm);
+    x.ulc = take(Bm);
     x.nk = reinterpret_cast<K*>(take(Bm * sizeof(K)));
     x.nv = reinterpret_cast<K*>(take(Bm * sizeof(K)));
     x.nleaf = reinterpret_cast<uint32_t*>(take(Bm * 4));
@@ -211,10 +214,14 @@ __global__ __launch_bounds__(kBlk) void k_locate(TreeView<K> t, Ins<K> v, uint8_
             qi[j] = u < U ? u : ~0ull;
         }
         uint32_t leaf[QPG];
-        descend<K, G, QPG, true>(t, mir, mnodes, LV, key, leaf, gl, gbase, v.pn, v.pi, v.Bm, qi);
+        descend<K, G, QPG, true>(t, mir, mnodes, LV, key, leaf, gl, gbase, v.pn, v.pi, v.Bm, qi, v.pc);
         typename T::KV kv[QPG];
+        uint32_t lcnt[QPG];
 #pragma unroll
-        for (int j = 0; j < QPG; ++j) kv[j] = T::load_keys(t.lkeys + static_cast<uint64_t>(leaf[j]) * kSlots, gl);
+        for (int j = 0; j < QPG; ++j) {
+            kv[j] = T::load_keys(t.lkeys + static_cast<uint64_t>(leaf[j]) * kSlots, gl);
+            lcnt[j] = t.lmeta[leaf[j]].x;
+        }
 #pragma unroll
         for (int j = 0; j < QPG; ++j) {
             const uint32_t slot = T::match_slot(kv[j], key[j], gbase);
@@ -223,6 +230,7 @@ __global__ __launch_bounds__(kBlk) void k_locate(TreeView<K> t, Ins<K> v, uint8_
                 const uint64_t u = qi[j];
                 v.ufound[u] = found ? 1 : 0;
                 v.uleaf[u] = leaf[j];
+                v.ulc[u] = static_cast<uint8_t>(lcnt[j]);
                 v.uslot[u] = static_cast<uint8_t>(found ? slot : 0);
                 v.f0[u] = found ? 0u : 1u;
                 status[v.si[v.upos[u]]] = found ? 1 : 0;
@@ -924,12 +932,16 @@ __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int 
     }
     __syncthreads();
     bool valid[2];
-    uint32_t nu[2], ixp[2], node[2], pnx[2] = {0u, 0u};
+    // per key and level: node, its old entry count and its slot in its
+    // parent (all recorded by locate), the next level's loaded one level ahead
+    uint32_t nu[2], ixp[2], node[2], cnt[2], cs[2], pnx[2] = {0u, 0u}, pcx[2] = {0u, 0u}, pix[2] = {0u, 0u};
     for (int j = 0; j < 2; ++j) {
         const uint32_t r = 2 * tid + j;
         valid[j] = r < R;
         nu[j] = valid[j] ? s_a[r] : 0u;
         node[j] = valid[j] ? s_b[r] : 0u;
+        cnt[j] = valid[j] ? v.ulc[nu[j]] : 0u;
+        cs[j] = valid[j] && h >= 2 ? v.pi[static_cast<uint64_t>(h - 2) * v.Bm + nu[j]] : 0u;
         ixp[j] = r;  // at the leaf level an item's range counts keys
     }
 
@@ -940,14 +952,20 @@ __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int 
         if (d > 0) {
             for (int j = 0; j < 2; ++j) {
                 node[j] = pnx[j];
+                cnt[j] = pcx[j];
+                cs[j] = pix[j];
                 if (valid[j]) s_b[2 * tid + j] = node[j];
             }
             __syncthreads();
         }
-        // the next level's parent references, in flight through this level
+        // the next level's records, in flight through this level
         if (d + 1 < hmax)
-            for (int j = 0; j < 2; ++j)
-                pnx[j] = valid[j] ? v.pn[static_cast<uint64_t>(h - 2 - d) * v.Bm + nu[j]] : 0u;
+            for (int j = 0; j < 2; ++j) {
+                const uint64_t at = static_cast<uint64_t>(h - 2 - d) * v.Bm + nu[j];
+                pnx[j] = valid[j] ? v.pn[at] : 0u;
+                pcx[j] = valid[j] ? v.pc[at] : 0u;
+                pix[j] = valid[j] && h - 3 - d >= 0 ? v.pi[at - v.Bm] : 0u;
+            }
         uint32_t hd[2], ls[2];
         for (int j = 0; j < 2; ++j) {
             const uint32_t r = 2 * tid + j;
@@ -966,6 +984,9 @@ __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int 
                     v.it_node[e] = node[j];
                     v.it_rep[e] = nu[j];
                     v.it_first[e] = ixp[j];
+                    v.it_cold[e] = cnt[j];
+                    v.it_cs[e] = static_cast<uint8_t>(cs[j]);
+                    s_C[e] = static_cast<uint8_t>(cnt[j]);
                 } else {
                     s_over = 1;
                 }
@@ -982,66 +1003,7 @@ __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int 
     if (tid == 0) s_base[hmax] = items;
     __syncthreads();
 
-    // old entry counts of all items and each item's slot in its parent: leaf
-    // items, then inner items, four in flight per thread (indices clamped so
-    // that every load is issued before any is used)
     const uint32_t total = items < v.ip_cap ? items : static_cast<uint32_t>(v.ip_cap);
-    const uint32_t nleaf = s_base[hmax > 1 ? 1 : hmax] < total ? s_base[hmax > 1 ? 1 : hmax] : total;
-#pragma unroll 1
-    for (uint32_t x0 = tid; x0 < nleaf; x0 += 4 * NT) {
-        uint32_t nd[4], rp[4], c[4], cs[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t x = x0 + q * NT < nleaf ? x0 + q * NT : nleaf - 1;
-            nd[q] = v.it_node[x];
-            rp[q] = v.it_rep[x];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            c[q] = t.lmeta[nd[q]].x;
-            cs[q] = h >= 2 ? v.pi[static_cast<uint64_t>(h - 2) * v.Bm + rp[q]] : 0u;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t x = x0 + q * NT;
-            if (x < nleaf) {
-                s_C[x] = static_cast<uint8_t>(c[q]);
-                v.it_cold[x] = c[q];
-                v.it_cs[x] = static_cast<uint8_t>(cs[q]);
-            }
-        }
-    }
-#pragma unroll 1
-    for (uint32_t x0 = nleaf + tid; x0 < total; x0 += 4 * NT) {
-        uint32_t nd[4], rp[4], c[4], cs[4];
-        int lp[4];  // tree level of the item's parent (< 0: the item is the root)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t x = x0 + q * NT < total ? x0 + q * NT : total - 1;
-            nd[q] = v.it_node[x];
-            rp[q] = v.it_rep[x];
-            int dx = 1;
-#pragma unroll 1
-            for (int d = 2; d < hmax; ++d)
-                if (x >= s_base[d]) dx = d;
-            lp[q] = h - 2 - dx;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            c[q] = old_count<K>(t, nd[q], false);
-            cs[q] = v.pi[static_cast<uint64_t>(lp[q] >= 0 ? lp[q] : 0) * v.Bm + rp[q]];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t x = x0 + q * NT;
-            if (x < total) {
-                s_C[x] = static_cast<uint8_t>(c[q]);
-                v.it_cold[x] = c[q];
-                v.it_cs[x] = static_cast<uint8_t>(lp[q] >= 0 ? cs[q] : 0u);
-            }
-        }
-    }
-    __syncthreads();
 
     // piece counts, level after level.  An item's gain is its run's key
     // count (leaves) or sum(k - 1) over its child items (inner levels): a

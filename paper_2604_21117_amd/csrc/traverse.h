@@ -83,6 +83,20 @@ struct Trav {
         return static_cast<K>(__shfl(kv.v[KPL - 1], gbase + G - 1, 64));
     }
 
+    // children of an inner node from its key line: a node with C children
+    // has C - 1 separators in slots 0..C-2 and the largest key in the other
+    // slots below slot 15 (no separator is the largest key: that key can
+    // only lie in the last child)
+    static __device__ __forceinline__ uint32_t child_count(const KV& kv, int gl, int gbase) {
+        uint32_t c = 1;
+#pragma unroll
+        for (int e = 0; e < KPL; ++e) {
+            const bool sep = gl * KPL + e < kFirstSlot && kv.v[e] != kmax<K>();
+            c += static_cast<uint32_t>(__popcll(group_bits<G>(__ballot(sep), gbase)));
+        }
+        return c;
+    }
+
     // child reference for slot idx, read from the lane that holds it
     static __device__ __forceinline__ uint32_t pick_child(const CV& cv, uint32_t idx, int gbase) {
         uint32_t e = idx % KPL;
@@ -161,12 +175,14 @@ __device__ __forceinline__ void stage_mirror(const uint8_t* mirror, uint8_t* lds
 //   use_lv   mirror levels to use (clamped to the levels the mirror holds)
 // On return leaf[j] is the leaf index (tag removed) for key[j].
 // If REC is set, path_node[l][j] / path_idx[l][j] receive the inner node and
-// child slot taken at inner level l (0 = root level) for l < height-1.
+// child slot taken at inner level l (0 = root level) for l < height-1, and
+// path_cnt[l][j] (if given) that node's number of children.
 template <class K, int G, int QPG, bool REC>
 __device__ __forceinline__ void descend(const TreeView<K>& t, const uint8_t* mir, uint32_t mnodes, int use_lv,
                                         const K (&key)[QPG], uint32_t (&leaf)[QPG], int gl, int gbase,
                                         uint32_t* path_node = nullptr, uint8_t* path_idx = nullptr,
-                                        uint64_t path_stride = 0, const uint64_t* qidx = nullptr) {
+                                        uint64_t path_stride = 0, const uint64_t* qidx = nullptr,
+                                        uint8_t* path_cnt = nullptr) {
     using T = Trav<K, G>;
     using ML = MirrorLayout<K>;
     const MirrorHeader* mh = reinterpret_cast<const MirrorHeader*>(mir);
@@ -201,9 +217,11 @@ __device__ __forceinline__ void descend(const TreeView<K>& t, const uint8_t* mir
                 uint32_t idx = T::child_index(kv[j], key[j], gbase);
                 uint32_t c = T::pick_child(cv[j], idx, gbase);
                 if constexpr (REC) {
+                    const uint32_t nc = path_cnt ? T::child_count(kv[j], gl, gbase) : 0u;
                     if (gl == 0 && qidx[j] != ~0ull) {
                         path_node[level * path_stride + qidx[j]] = node[j];
                         path_idx[level * path_stride + qidx[j]] = static_cast<uint8_t>(idx);
+                        if (path_cnt) path_cnt[level * path_stride + qidx[j]] = static_cast<uint8_t>(nc);
                     }
                 }
                 node[j] = c;
@@ -230,9 +248,11 @@ __device__ __forceinline__ void descend(const TreeView<K>& t, const uint8_t* mir
                 c = T::pick_child(cv, idx, gbase);
             }
             if constexpr (REC) {
+                const uint32_t nc = path_cnt ? T::child_count(kv[j], gl, gbase) : 0u;
                 if (gl == 0 && qidx[j] != ~0ull) {
                     path_node[level * path_stride + qidx[j]] = node[j];
                     path_idx[level * path_stride + qidx[j]] = static_cast<uint8_t>(idx);
+                    if (path_cnt) path_cnt[level * path_stride + qidx[j]] = static_cast<uint8_t>(nc);
                 }
             }
             node[j] = c;
