@@ -287,9 +287,10 @@ uint64_t li_arena_bytes(const gt_tree* t, const gt_li_params* p /*host*/);
 gt_status li_create(gt_tree* t, const gt_li_params* p /*host*/, void* arena, uint64_t arena_bytes,
                     gt_learned** out /*host*/);
 
-/* (Re)train from the tree's current leaves: leaf positions by list ranking
- * of the leaf chain, the fence directory, root and leaf model fits,
- * exact bounds over every key.  Synchronises `stream`. */
+/* (Re)train from the tree's current leaves: leaf positions in key order
+ * (the tree expanded level by level from the root), the fence directory,
+ * root and leaf model fits, exact bounds over every key.  Synchronises
+ * `stream`. */
 gt_status li_train(gt_learned* li, hipStream_t stream);
 
 /* Same contract as tree_lookup_batch.  The launch passes the index's current

@@ -16,7 +16,9 @@
 // a leaf position in key order (the leaf chain at training time).
 //
 // Training (all on the device, deterministic reduction orders):
-//   leaf positions   list ranking of the leaf chain by pointer jumping
+//   leaf positions   the tree expanded level by level from the root (each
+//                    level's nodes in key order, so the last level lists
+//                    the leaves in key order, the order of the leaf chain)
 //   directory        dir[pos] = (first key of the leaf, leaf id)
 //   root             least squares of pos*M/L on the fences (FP64 sums)
 //   model ranges     the root is monotone, so model j owns a contiguous run
