@@ -120,7 +120,8 @@ uint64_t tree_arena_bytes(const gt_params* p /*host*/, uint64_t n, uint64_t leaf
  * or more), inner levels are built bottom-up with the same rule, and the
  * leaves are chained in key order.  n = 0 builds an empty tree.
  * This call synchronises `stream` before it returns.  On success *out
- * receives a new handle.
+ * receives a new handle; GT_ERR_DEVICE if the device sort of the keys
+ * failed (a bounded wait between its workgroups gave up: not expected).
  */
 gt_status tree_build(const gt_params* p /*host*/, const void* keys, const void* values, uint64_t n,
                      void* arena, uint64_t arena_bytes, hipStream_t stream, gt_tree** out /*host*/);
@@ -154,7 +155,10 @@ gt_status tree_lookup_batch(gt_tree* t, const void* keys, uint64_t B, void* valu
  * workspaces.  B < 2^31.  Errors: GT_ERR_INVALID for null pointers, unknown
  * flags or B too large; GT_ERR_CAPACITY when workspace_bytes is too small.
  * Nothing is enqueued on an error.  No memory is allocated; the call is
- * graph-capturable.
+ * graph-capturable.  Should the device sort of a batch above 2048 keys fail
+ * (a bounded wait between its workgroups gives up: not expected) the tree's
+ * device error word gets the internal bit (tree_device_error: GT_ERR_DEVICE)
+ * and the results are not valid.
  */
 #define GT_LW_PRESORTED 1u
 uint64_t tree_lookup_levelwise_workspace_bytes(const gt_tree* t, uint64_t B, uint32_t flags);
@@ -172,7 +176,10 @@ gt_status tree_lookup_levelwise(gt_tree* t, const void* keys, uint64_t B, uint32
  * full (Section III).  B <= max_batch.  The batch is applied whole or not
  * at all: if the node pools cannot hold it, the device error word gets
  * GT_DEVERR_CAPACITY, the tree is left unchanged and status_out is
- * unspecified.
+ * unspecified.  A batch is not applied either while the word holds
+ * GT_DEVERR_INTERNAL (set, for one, when the device sort of a batch above
+ * 2048 keys gives up a bounded wait between its workgroups: not expected);
+ * tree_device_error clears the word.
  */
 gt_status tree_insert_batch(gt_tree* t, const void* keys, const void* values, uint64_t B,
                             uint8_t* status_out, hipStream_t stream);

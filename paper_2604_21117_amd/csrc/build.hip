@@ -31,7 +31,7 @@ template <class K>
 __global__ void k_dup_check(const K* __restrict__ sk, uint64_t n, uint32_t* flag) {
     for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i + 1 < n;
          i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
-        if (sk[i] == sk[i + 1]) *flag = 1u;
+        if (sk[i] == sk[i + 1]) atomicOr(flag, 1u);
 }
 
 template <class K>

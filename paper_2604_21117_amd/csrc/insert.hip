@@ -430,11 +430,12 @@ __device__ __forceinline__ void ph_check(TreeView<K> t, Ins<K> v, uint64_t tid, 
     for (int d = 0; d < h; ++d) sep_total += st->lvl_new[d];
     for (int d = 1; d < h; ++d) inner_new += st->lvl_new[d];
     bool ok = !st->overflow;
+    if (hdr->error & kErrInternal) ok = false;  // e.g. the batch's device sort gave up
     if (hdr->leaf_used + leaf_new > t.leaf_cap) ok = false;
     if (hdr->inner_used + inner_new > t.inner_cap) ok = false;
     if (sep_total + 1 > v.ps_cap) ok = false;
     if (h + gl > kMaxLevels) ok = false;
-    if (!ok) atomicOr(&hdr->error, st->overflow ? kErrInternal : kErrCapacity);
+    if (!ok && !(hdr->error & kErrInternal)) atomicOr(&hdr->error, st->overflow ? kErrInternal : kErrCapacity);
     st->ok = ok ? 1u : 0u;
     st->grow_nodes = gn;
     st->grow_levels = gl;
@@ -1151,7 +1152,7 @@ void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, cons
         return;
     }
     hipLaunchKernelGGL(k_init<K>, dim3(1), dim3(kBlk), 0, s, v, t.hdr);
-    sort_from<K>(keys, v.sk, v.si, v.sk2, v.si2, B, v.sort_tmp, s);
+    sort_from<K>(keys, v.sk, v.si, v.sk2, v.si2, B, v.sort_tmp, s, &t.hdr->error, kErrInternal);
     hipLaunchKernelGGL(k_heads<K>, dim3(gB), dim3(kBlk), 0, s, v, B, status);
     scan_exclusive<uint32_t>(v.f0, v.f1, &st->U, nullptr, B, v.scan_tmp, s);
     hipLaunchKernelGGL(k_unique<K>, dim3(gB), dim3(kBlk), 0, s, v, B, vals);

@@ -170,7 +170,7 @@ void launch_lookup_levelwise(const TreeView<K>& t, const K* keys, uint64_t B, bo
             rank_sort_small<K>(keys, b, sk, si, nullptr, 0, s);
         } else {
             sort_from<K>(keys, sk, si, reinterpret_cast<K*>(w + L.sk2), reinterpret_cast<uint32_t*>(w + L.si2), B,
-                         w + L.tmp, s);
+                         w + L.tmp, s, &t.hdr->error, kErrInternal);
         }
         qs = sk;
         qi = si;

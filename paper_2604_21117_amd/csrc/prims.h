@@ -93,15 +93,18 @@ void scan_exclusive(const T* in, T* out, T* total, const uint32_t* n_dev, uint64
 uint64_t sort_tmp_bytes(uint64_t n, int key_bytes);
 
 // Stable sort of (keys[i], idx[i]) by key, n host-known.  keys_alt/idx_alt
-// are ping-pong buffers of n entries.  The result ends in keys/idx.
+// are ping-pong buffers of n entries.  The result ends in keys/idx.  If a
+// tile's look-back wait gives up (never expected: it waits only on running
+// tiles), err_bit is or-ed into *err (a device word; by default one in tmp)
+// and the order is not valid.
 template <class K>
 void sort_pairs(K* keys, uint32_t* idx, K* keys_alt, uint32_t* idx_alt, uint64_t n, void* tmp,
-                hipStream_t s);
+                hipStream_t s, uint32_t* err = nullptr, uint32_t err_bit = 1u);
 
 // The same sort of (src[i], i): src is read, keys/idx receive the result,
 // keys_alt/idx_alt are ping-pong buffers.  Saves staging the pairs.
 template <class K>
 void sort_from(const K* src, K* keys, uint32_t* idx, K* keys_alt, uint32_t* idx_alt, uint64_t n, void* tmp,
-               hipStream_t s);
+               hipStream_t s, uint32_t* err = nullptr, uint32_t err_bit = 1u);
 
 }  // namespace gt

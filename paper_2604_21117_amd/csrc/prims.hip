@@ -226,7 +226,8 @@ template <class K, class W>
 __global__ __launch_bounds__(kSortBlock) void k_sort_pass(const K* __restrict__ kin, const uint32_t* __restrict__ iin,
                                                            K* __restrict__ kout, uint32_t* __restrict__ iout, uint64_t n,
                                                            int shift, const uint32_t* __restrict__ totals,
-                                                           uint32_t* ticket, W* flags, uint32_t* err) {
+                                                           uint32_t* ticket, W* flags, uint32_t* err,
+                                                           uint32_t err_bit) {
     constexpr int kSh = static_cast<int>(sizeof(W)) * 8 - 2;
     constexpr W kAgg = W(1) << kSh, kIncl = W(2) << kSh, kVal = (W(1) << kSh) - 1;
     __shared__ uint32_t wcnt[kSortBlock / 64][256];
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(const K* __restrict__ 
                     if (f == 2) done = true;
                 }
                 j -= used;
-                if (!done && used == 0 && ++spins > kSpinMax) { atomicOr(err, 1u); break; }
+                if (!done && used == 0 && ++spins > kSpinMax) { atomicOr(err, err_bit); break; }
             }
             __hip_atomic_store(mine, kIncl | static_cast<W>(excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -376,14 +377,14 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(const K* __restrict__ 
 
 template <class K, class W>
 static void sort_onesweep(const K* src, K* keys, uint32_t* idx, K* keys_alt, uint32_t* idx_alt, uint64_t n,
-                          void* tmp, hipStream_t s) {
+                          void* tmp, hipStream_t s, uint32_t* err_out, uint32_t err_bit) {
     constexpr int P = sizeof(K);
     const uint32_t nt = sort_tiles(n);
     const SortLayout L = sort_layout(n, P);
     uint8_t* b = reinterpret_cast<uint8_t*>(tmp);
     uint32_t* totals = reinterpret_cast<uint32_t*>(b + L.totals);
     uint32_t* tickets = reinterpret_cast<uint32_t*>(b + L.tickets);
-    uint32_t* err = reinterpret_cast<uint32_t*>(b + L.err);
+    uint32_t* err = err_out ? err_out : reinterpret_cast<uint32_t*>(b + L.err);
     W* flags = reinterpret_cast<W*>(b + L.flags);
     const uint64_t words = L.bytes / 4;
     const uint64_t cg = (words + 255) / 256;
@@ -398,7 +399,8 @@ static void sort_onesweep(const K* src, K* keys, uint32_t* idx, K* keys_alt, uin
     K* kb = keys_alt; uint32_t* ib = idx_alt;
     for (int p = 0; p < P; ++p) {
         hipLaunchKernelGGL((k_sort_pass<K, W>), dim3(nt), dim3(kSortBlock), 0, s, ka, ia, kb, ib, n, 8 * p,
-                           totals + p * 256, tickets + p, flags + static_cast<uint64_t>(p) * nt * 256, err);
+                           totals + p * 256, tickets + p, flags + static_cast<uint64_t>(p) * nt * 256, err,
+                           err_bit);
         ka = kb;
         ia = ib;
         kb = (p & 1) ? keys_alt : keys;
@@ -407,7 +409,8 @@ static void sort_onesweep(const K* src, K* keys, uint32_t* idx, K* keys_alt, uin
 }
 
 template <class K>
-void sort_pairs(K* keys, uint32_t* idx, K* keys_alt, uint32_t* idx_alt, uint64_t n, void* tmp, hipStream_t s) {
+void sort_pairs(K* keys, uint32_t* idx, K* keys_alt, uint32_t* idx_alt, uint64_t n, void* tmp, hipStream_t s,
+                uint32_t* err, uint32_t err_bit) {
     if (n <= 1) return;
     if (n <= kBitonicMax) {
         uint32_t n2 = 2;
@@ -415,22 +418,22 @@ void sort_pairs(K* keys, uint32_t* idx, K* keys_alt, uint32_t* idx_alt, uint64_t
         hipLaunchKernelGGL(k_bitonic<K>, dim3(1), dim3(kSortBlock), 0, s, keys, idx, static_cast<uint32_t>(n), n2);
         return;
     }
-    if (n < kNarrowMax) sort_onesweep<K, uint32_t>(nullptr, keys, idx, keys_alt, idx_alt, n, tmp, s);
-    else sort_onesweep<K, uint64_t>(nullptr, keys, idx, keys_alt, idx_alt, n, tmp, s);
+    if (n < kNarrowMax) sort_onesweep<K, uint32_t>(nullptr, keys, idx, keys_alt, idx_alt, n, tmp, s, err, err_bit);
+    else sort_onesweep<K, uint64_t>(nullptr, keys, idx, keys_alt, idx_alt, n, tmp, s, err, err_bit);
 }
 
 template <class K>
 void sort_from(const K* src, K* keys, uint32_t* idx, K* keys_alt, uint32_t* idx_alt, uint64_t n, void* tmp,
-               hipStream_t s) {
+               hipStream_t s, uint32_t* err, uint32_t err_bit) {
     if (n <= kBitonicMax) {
         // stage (key, position) pairs, then the in-workgroup sort
         hipLaunchKernelGGL(k_sort_stage<K>, dim3(static_cast<uint32_t>((n + 255) / 256 ? (n + 255) / 256 : 1)),
                            dim3(256), 0, s, src, n, keys, idx);
-        sort_pairs<K>(keys, idx, keys_alt, idx_alt, n, tmp, s);
+        sort_pairs<K>(keys, idx, keys_alt, idx_alt, n, tmp, s, err, err_bit);
         return;
     }
-    if (n < kNarrowMax) sort_onesweep<K, uint32_t>(src, keys, idx, keys_alt, idx_alt, n, tmp, s);
-    else sort_onesweep<K, uint64_t>(src, keys, idx, keys_alt, idx_alt, n, tmp, s);
+    if (n < kNarrowMax) sort_onesweep<K, uint32_t>(src, keys, idx, keys_alt, idx_alt, n, tmp, s, err, err_bit);
+    else sort_onesweep<K, uint64_t>(src, keys, idx, keys_alt, idx_alt, n, tmp, s, err, err_bit);
 }
 
 // ------------------------------------------------------------ rank sort
@@ -491,11 +494,13 @@ template void rank_sort_small<uint32_t>(const uint32_t*, uint32_t, uint32_t*, ui
 template void rank_sort_small<uint64_t>(const uint64_t*, uint32_t, uint64_t*, uint32_t*, uint32_t*, uint32_t,
                                         hipStream_t);
 
-template void sort_pairs<uint32_t>(uint32_t*, uint32_t*, uint32_t*, uint32_t*, uint64_t, void*, hipStream_t);
+template void sort_pairs<uint32_t>(uint32_t*, uint32_t*, uint32_t*, uint32_t*, uint64_t, void*, hipStream_t,
+                                   uint32_t*, uint32_t);
 template void sort_from<uint32_t>(const uint32_t*, uint32_t*, uint32_t*, uint32_t*, uint32_t*, uint64_t, void*,
-                                  hipStream_t);
+                                  hipStream_t, uint32_t*, uint32_t);
 template void sort_from<uint64_t>(const uint64_t*, uint64_t*, uint32_t*, uint64_t*, uint32_t*, uint64_t, void*,
-                                  hipStream_t);
-template void sort_pairs<uint64_t>(uint64_t*, uint32_t*, uint64_t*, uint32_t*, uint64_t, void*, hipStream_t);
+                                  hipStream_t, uint32_t*, uint32_t);
+template void sort_pairs<uint64_t>(uint64_t*, uint32_t*, uint64_t*, uint32_t*, uint64_t, void*, hipStream_t,
+                                   uint32_t*, uint32_t);
 
 }  // namespace gt

@@ -178,7 +178,7 @@ gt_status build_t(gt_tree* t, const void* keys, const void* values, uint64_t n, 
                 st = GT_ERR_HIP;
                 break;
             }
-            sort_pairs<K>(sk, si, sk2, si2, n, stmp, s);
+            sort_pairs<K>(sk, si, sk2, si2, n, stmp, s, dflag, 2u);  // bit 0: duplicates (below)
             launch_gather<K>(reinterpret_cast<const K*>(values), si, sv, n, s);
             launch_dup_check<K>(sk, n, dflag, s);
         }
@@ -187,6 +187,7 @@ gt_status build_t(gt_tree* t, const void* keys, const void* values, uint64_t n, 
             st = GT_ERR_HIP;
             break;
         }
+        if (hflag & 2u) { st = GT_ERR_DEVICE; break; }  // the sort gave up
         if (hflag) { st = GT_ERR_DUPLICATE; break; }
         TreeView<K> v = view<K>(t);
         launch_build<K>(v, sk, sv, n, sizes.data(), static_cast<int>(sizes.size()), maxbuf, s);
