@@ -585,7 +585,8 @@ __device__ __forceinline__ void apply_inner_body(TreeView<K> t, Ins<K> v, int d,
     const uint32_t ok = v.st->ok;
     const int h = static_cast<int>(v.st->height);
     const int l = h - 1 - d;
-    if (!ok || l < 0) return;
+    // no child at level d-1 split: no parent at level d changes
+    if (!ok || l < 0 || v.st->lvl_new[d - 1] == 0) return;
     const uint64_t n = v.st->lvl_count[d];
     const uint32_t bd = v.st->lvl_base[d], bc = v.st->lvl_base[d - 1];
     const uint32_t alloc = v.st->lvl_alloc[d], alloc_c = v.st->lvl_alloc[d - 1];
@@ -790,6 +791,7 @@ __global__ __launch_bounds__(kFusedBlock) void k_small_apply(TreeView<K> t, Ins<
     apply_leaves_body<K>(t, v, grp, ngrp);
     __syncthreads();
     for (int d = 1; d < H; ++d) {
+        if (v.st->lvl_new[d - 1] == 0) break;  // nothing split below: no level above changes
         apply_inner_body<K>(t, v, d, grp, ngrp);
         __syncthreads();
     }
