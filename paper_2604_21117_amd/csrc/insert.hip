@@ -90,6 +90,13 @@ static uint64_t item_pool_cap(uint64_t Bm, uint64_t leaf_cap) {
 
 static uint64_t psep_cap(uint64_t leaf_cap, uint64_t inner_cap) { return leaf_cap + inner_cap + 64; }
 
+// items level d can hold (the item pool's per-level bound)
+static uint64_t level_items_bound(uint64_t Bm, uint64_t leaf_cap, int d) {
+    uint64_t lv = leaf_cap;
+    for (int i = 0; i < d; ++i) lv /= 8;
+    return lv + 2 < Bm ? lv + 2 : Bm;
+}
+
 template <class K>
 static uint64_t carve(Ins<K>* v, uint8_t* base, uint64_t Bm, uint64_t leaf_cap, uint64_t inner_cap) {
     uint64_t off = 0;
@@ -778,6 +785,49 @@ __global__ __launch_bounds__(1024) void k_grow_commit(TreeView<K> t, Ins<K> v) {
     if (threadIdx.x == 0) ph_commit<K>(t, v);
 }
 
+// The upper levels of a large batch's plan in one workgroup: from level d0
+// on, every level below holds at most kTailMax items (the pool's per-level
+// bound), so the phases run back to back with block scans in LDS where the
+// lower levels have kernel boundaries and device-wide scans.
+constexpr uint32_t kTailMax = 2048;
+constexpr int kTailBlock = 1024;
+
+// exclusive scan of in[0..n) (n <= 2 * blockDim.x) into out, total to *tot
+__device__ __forceinline__ void tail_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* tot,
+                                          uint32_t* sh) {
+    const uint32_t i0 = 2 * threadIdx.x, i1 = i0 + 1;
+    const uint32_t a = i0 < n ? in[i0] : 0u, b = i1 < n ? in[i1] : 0u;
+    uint32_t total;
+    const uint32_t off = block_excl_scan<uint32_t>(a + b, sh, &total);
+    if (i0 < n) out[i0] = off;
+    if (i1 < n) out[i1] = off + a;
+    if (threadIdx.x == 0) *tot = total;
+    __syncthreads();
+}
+
+template <class K>
+__global__ __launch_bounds__(kTailBlock) void k_plan_tail(TreeView<K> t, Ins<K> v0, int d0, int H) {
+    __shared__ uint32_t sh[33];
+    __shared__ uint32_t sf0[kTailMax + 1], sf1[kTailMax + 1];
+    Ins<K> v = v0;
+    v.f0 = sf0;
+    v.f1 = sf1;
+    const uint64_t tid = threadIdx.x, nth = blockDim.x;
+    const int h = static_cast<int>(v.st->height);
+    for (int d = d0; d < H && d < h; ++d) {
+        ph_par_heads<K>(v, d, tid, nth);
+        __syncthreads();
+        tail_scan(v.f0, v.f1, v.st->lvl_count[d - 1], &v.st->lvl_count[d], sh);
+        ph_par_items<K>(v, d, tid, nth);
+        __syncthreads();
+        ph_par_plan<K>(t, v, d, tid, nth);
+        __syncthreads();
+        tail_scan(v.f0, v.f1, v.st->lvl_count[d], &v.st->lvl_new[d], sh);
+        ph_par_off<K>(v, d, tid, nth);
+        __syncthreads();
+    }
+}
+
 // Everything after the plan for a batch of at most kFusedMax keys, in one
 // workgroup: every level has at most that many touched nodes, one round of
 // kNodeLanes-lane groups, and barriers stand where the general path has
@@ -1166,14 +1216,21 @@ void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, cons
     hipLaunchKernelGGL(k_leaf_items<K>, dim3(gB), dim3(kBlk), 0, s, v);
     hipLaunchKernelGGL(k_leaf_plan<K>, dim3(gB), dim3(kBlk), 0, s, t, v);
     scan_exclusive<uint32_t>(v.f0, v.it_off, &st->lvl_new[0], &st->lvl_count[0], B, v.scan_tmp, s);
-    for (int d = 1; d < H; ++d) {
-        hipLaunchKernelGGL(k_par_heads<K>, dim3(gB), dim3(kBlk), 0, s, v, d);
-        scan_exclusive<uint32_t>(v.f0, v.f1, &st->lvl_count[d], &st->lvl_count[d - 1], B, v.scan_tmp, s);
-        hipLaunchKernelGGL(k_par_items<K>, dim3(gB), dim3(kBlk), 0, s, v, d);
-        hipLaunchKernelGGL(k_par_plan<K>, dim3(gB), dim3(kBlk), 0, s, t, v, d);
-        scan_exclusive<uint32_t>(v.f0, v.f1, &st->lvl_new[d], &st->lvl_count[d], B, v.scan_tmp, s);
-        hipLaunchKernelGGL(k_par_off<K>, dim3(gB), dim3(kBlk), 0, s, v, d);
+    // lower levels: kernels sized by the level's bound; from d0 on (the
+    // level below holds at most kTailMax items) one workgroup plans the rest
+    int d0 = 1;
+    while (d0 < H && level_items_bound(B, c.leaf_cap, d0 - 1) > kTailMax) ++d0;
+    for (int d = 1; d < d0; ++d) {
+        const uint64_t nb = level_items_bound(B, c.leaf_cap, d - 1), nd = level_items_bound(B, c.leaf_cap, d);
+        const uint32_t gb = grid_for(nb, kBlk), gd = grid_for(nd, kBlk);
+        hipLaunchKernelGGL(k_par_heads<K>, dim3(gb), dim3(kBlk), 0, s, v, d);
+        scan_exclusive<uint32_t>(v.f0, v.f1, &st->lvl_count[d], &st->lvl_count[d - 1], nb, v.scan_tmp, s);
+        hipLaunchKernelGGL(k_par_items<K>, dim3(gb), dim3(kBlk), 0, s, v, d);
+        hipLaunchKernelGGL(k_par_plan<K>, dim3(gd), dim3(kBlk), 0, s, t, v, d);
+        scan_exclusive<uint32_t>(v.f0, v.f1, &st->lvl_new[d], &st->lvl_count[d], nd, v.scan_tmp, s);
+        hipLaunchKernelGGL(k_par_off<K>, dim3(gd), dim3(kBlk), 0, s, v, d);
     }
+    if (d0 < H) hipLaunchKernelGGL(k_plan_tail<K>, dim3(1), dim3(kTailBlock), 0, s, t, v, d0, H);
     hipLaunchKernelGGL(k_check<K>, dim3(1), dim3(64), 0, s, t, v);
     launch_apply<K>(t, v, B, H, true, s);
 }
