@@ -30,7 +30,9 @@
 //
 // What differs from the FPGA design: the root's run is cut at every window
 // (so 256 CUs share the work); the root and the nodes near it are then read
-// once per window, from HBM once and from L2 after.  Unsorted queries still
+// once per window, from the top-levels mirror (up to three levels, cached on
+// chip), and the first kernel walks those levels itself, so their FIFOs
+// never go through memory.  Unsorted queries still
 // get correct answers: runs are only cut more often.  The host launches one
 // kernel per level up to a bound on the height; a kernel whose level lies
 // below the leaves (per the device header) returns at once.
@@ -46,20 +48,27 @@ constexpr int kLwWaves = kLwBlock / 64;
 constexpr uint32_t kLwWin = 64;                 // queries per window (one wave)
 constexpr uint32_t kLwGridMax = 2048;           // 8 resident workgroups per CU
 
-// One tree level over every window of the batch.  ROOT: each window is one
-// run through the root.  Otherwise the runs of window w start at the set bits
-// of hm_in[w], with their node references in ref_in at the runs' first
-// positions.  Every lane of a wave stays active through the level (the
-// cross-lane reads need their source lanes).
+// One tree level over every window of the batch.  Otherwise the runs of
+// window w start at the set bits of hm_in[w], with their node references in
+// ref_in at the runs' first positions.  ROOT: each window is one run through
+// the root, and the levels the top-levels mirror holds (the root and up to
+// two below it, cached on chip) are walked by every lane through the mirror
+// in this kernel, which writes the FIFO of the first level below them (in
+// hm_in/ref_in when that level is even, the buffers that level reads);
+// the kernels of the mirrored levels then return at once.  Every lane of a
+// wave stays active through the level (the cross-lane reads need their
+// source lanes).
 template <class K, bool ROOT>
 __global__ __launch_bounds__(kLwBlock) void k_lw_level(TreeView<K> t, const K* __restrict__ qs,
                                                         const uint32_t* __restrict__ qi, uint32_t B, uint32_t level,
-                                                        const uint64_t* __restrict__ hm_in,
-                                                        const uint32_t* __restrict__ ref_in,
+                                                        uint64_t* hm_in, uint32_t* ref_in,
                                                         uint64_t* __restrict__ hm_out, uint32_t* __restrict__ ref_out,
                                                         K* __restrict__ vout, uint8_t* __restrict__ fout) {
     const uint32_t height = t.hdr->height;
     if (level >= height) return;  // the whole grid: the tree has no such level
+    using ML = MirrorLayout<K>;
+    const uint32_t top = reinterpret_cast<const MirrorHeader*>(t.mirror)->levels;  // mirrored inner levels
+    if (!ROOT && level < top) return;  // walked through the mirror by the first kernel
     const bool leaves = level + 1 == height;
     const bool empty = t.hdr->n_keys == 0;
     const uint32_t root = t.hdr->root;
@@ -72,6 +81,31 @@ __global__ __launch_bounds__(kLwBlock) void k_lw_level(TreeView<K> t, const K* _
         const bool valid = static_cast<uint32_t>(lane) < nq;
         const K key = valid ? qs[w0 + lane] : K(0);
         uint32_t ref = root;
+        if (ROOT && top > 0) {
+            // the mirrored levels, one lane per query (a window's lanes
+            // mostly read the same mirror lines)
+            const K* mkeys = reinterpret_cast<const K*>(t.mirror + ML::keys_off());
+            const uint32_t* mchild = reinterpret_cast<const uint32_t*>(t.mirror + ML::child_off(kMirrorMaxNodes));
+            const uint32_t* mfirst = reinterpret_cast<const uint32_t*>(t.mirror + ML::first_off(kMirrorMaxNodes));
+            uint32_t m = 0;
+            for (uint32_t lv = 0; lv < top; ++lv) {
+                K sep[kSlots];
+                load_vec<K, kSlots>(mkeys + static_cast<uint64_t>(m) * kSlots, sep);
+                uint32_t ci = 0;
+#pragma unroll
+                for (int j = 0; j < kFirstSlot; ++j) ci += sep[j] < key ? 1u : 0u;
+                ref = mchild[static_cast<uint64_t>(m) * kSlots + ci];
+                if (lv + 1 < top) m = mfirst[m] + ci;
+            }
+            const uint32_t prev = shfl_u32(ref, lane > 0 ? lane - 1 : 0);
+            const bool head = valid && (lane == 0 || ref != prev);
+            const uint64_t Hn = __ballot(head);
+            uint64_t* ho = (top & 1) ? hm_out : hm_in;
+            uint32_t* ro = (top & 1) ? ref_out : ref_in;
+            if (head) ro[w0 + lane] = ref;
+            if (lane == 0) ho[w] = Hn;
+            continue;
+        }
         if (!ROOT) {
             // this query's run starts at the highest run start <= lane (a
             // lane past the window's end takes the last run: every lane
@@ -179,8 +213,8 @@ void launch_lookup_levelwise(const TreeView<K>& t, const K* keys, uint64_t B, bo
     const uint64_t wgs = (nwin + kLwBlock / 64 - 1) / (kLwBlock / 64);
     const uint32_t grid = static_cast<uint32_t>(wgs < kLwGridMax ? wgs : kLwGridMax);
     for (uint32_t l = 0; l < levels; ++l) {
-        const uint64_t* hin = (l & 1) ? ha : hb;
-        const uint32_t* rin = (l & 1) ? ra : rb;
+        uint64_t* hin = (l & 1) ? ha : hb;
+        uint32_t* rin = (l & 1) ? ra : rb;
         uint64_t* hout = (l & 1) ? hb : ha;
         uint32_t* rout = (l & 1) ? rb : ra;
         if (l == 0)
