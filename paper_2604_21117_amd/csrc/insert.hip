@@ -939,14 +939,15 @@ __device__ __forceinline__ uint32_t plan_scan(uint32_t x, uint32_t* sh, uint32_t
 // touches is a cache miss).
 //
 // The nodes a new key passes through are known from the locate kernel (its
-// leaf and its parent at every level), so the items of every level (runs of
-// new keys through one node) are cut first, level after level in LDS with
-// block scans.  The old entry counts of all items of all levels are then
-// read in one round of loads, and the piece counts follow level after level:
-// an item gains the new keys of its run (leaves) or sum(k - 1) over its child
-// items (inner nodes), both taken as differences of a prefix sum over the
-// run's keys.  Writes the same item arrays and level counters as the general
-// path, and then the values of keys already present.
+// leaf and, at every level, its parent, the parent's size and the slot taken),
+// so the items of every level (runs of new keys through one node) are cut
+// first, level after level in LDS with block scans, each item taking its
+// node's old entry count from those records.  The piece counts then follow
+// level after level: an item gains the new keys of its run (leaves) or
+// sum(k - 1) over its child items (inner nodes), a difference of the child
+// level's piece-offset prefix taken by the run's first and last keys.  Writes
+// the same item arrays and level counters as the general path, and then the
+// values of keys already present.
 template <class K, int NT>
 __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int H) {
     constexpr int kL = kMaxLevels;
