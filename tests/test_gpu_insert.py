@@ -116,6 +116,33 @@ def test_capacity_error_leaves_tree_unchanged():
     assert (st == 1).all()
 
 
+@pytest.mark.parametrize("B", [1, 40, 100])
+def test_capacity_error_small_batches(B):
+    """Small batches are planned and applied by their own kernels (one
+    workgroup applies up to 64 keys).  A refused batch changes nothing, not
+    even the values of the present keys it carries; an update-only batch of
+    the same size then goes through."""
+    import paper_2604_21117_amd as g
+    width, seed = 64, 6
+    keys = synth.uniform_keys(20000, seed, width)
+    vals = synth.values_for(keys, seed, width)
+    p = g.make_params(8, max_batch=2048)
+    arena = g.tree_arena_bytes(p, len(keys), 0)  # full leaves, no room for new ones
+    t = mk_tree(keys, vals, 8, arena_bytes=arena, max_batch=2048)
+    before = t.export()
+    fresh = synth.uniform_keys(B, seed + 1, width, exclude=keys)
+    ins = np.concatenate([fresh[:B - B // 2], keys[:B // 2]])
+    with pytest.raises(g.GtError) as e:
+        t.insert(ins, ins)
+    assert e.value.status == g.GT_ERR_CAPACITY
+    assert np.array_equal(t.export(), before)
+    sa = oracle.SortedArray(keys, vals, width)
+    upd = keys[1000:1000 + B]
+    nv = synth.values_for(upd, seed + 2, width)
+    assert np.array_equal(t.insert(upd, nv), sa.insert(upd, nv))
+    assert_export_parity(t, sa)
+
+
 def test_repeatable_layout():
     """The same build and insert batches give byte-identical trees (node
     allocation follows a scan in key order, not atomics)."""
