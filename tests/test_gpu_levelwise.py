@@ -100,6 +100,29 @@ def test_levelwise_after_inserts(width):
     assert t.stats()["height"] > h0
 
 
+@pytest.mark.parametrize("width", [32, 64])
+def test_levelwise_library_sort_degenerate_digits(width):
+    """Batches above 2048 keys are sorted by the device radix sort; here every
+    key is equal (each pass puts every element in one digit, so every tile's
+    look-back sums one digit over all earlier tiles), or keys differ only in
+    the top byte, or only in the low byte."""
+    seed = 82
+    keys = key_set(20000, width, seed, edges=True)
+    vals = synth.values_for(keys, seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, width // 8, max_batch=4096)
+    dt = keys.dtype
+    rng = np.random.default_rng(seed)
+    B = 40000
+    same = np.full(B, keys[123], dtype=dt)
+    _check(t, sa, same, False, "all keys equal")
+    hi = (rng.integers(0, 256, B).astype(np.uint64) << np.uint64(width - 8)).astype(dt)
+    _check(t, sa, hi, False, "top byte only")
+    lo = np.concatenate([keys[rng.integers(0, len(keys), B // 2)],
+                         (rng.integers(0, 256, B - B // 2)).astype(dt)])
+    _check(t, sa, synth.shuffle(lo, seed), False, "present keys and low-byte keys")
+
+
 def test_levelwise_workspace_and_errors():
     import torch
     import paper_2604_21117_amd as g
