@@ -11,8 +11,10 @@
 //
 // The mirror holds up to three top inner levels in breadth-first order with,
 // per node, its key line, its child line (real references) and the mirror
-// index of its first child.  Search kernels copy it into LDS.  It is rebuilt
-// after every change to the tree.
+// index of its first child.  Search kernels copy it into LDS or read it from
+// L2.  It is rebuilt (mirror.h) after an insert that rewrites a node of its
+// levels or grows the root; inserts of up to 64 keys rebuild it in their own
+// kernel.
 #include "common.h"
 #include "kernels.h"
 #include "mirror.h"
