@@ -108,6 +108,8 @@ def lib():
         L.tree_stats.argtypes = [vp, C.POINTER(gt_tree_stats), vp]
         L.tree_device_error.argtypes = [vp, vp]
         L.tree_export.argtypes = [vp, vp, C.POINTER(u64), vp]
+        L.gt_set_sort_spin_limit.argtypes = [u32]
+        L.gt_set_sort_spin_limit.restype = u32
         L.li_arena_bytes.argtypes = [vp, C.POINTER(gt_li_params)]
         L.li_arena_bytes.restype = u64
         L.li_create.argtypes = [vp, C.POINTER(gt_li_params), vp, u64, C.POINTER(vp)]
@@ -248,6 +250,12 @@ def tree_stats(h, stream=None) -> dict:
 
 def tree_device_error(h, stream=None) -> int:
     return int(lib().tree_device_error(h, _stream(stream)))
+
+
+def set_sort_spin_limit(limit: int) -> int:
+    """Testing hook: the device sort's look-back limit (0 makes every sort
+    of more than 4096 keys fail); returns the previous value."""
+    return int(lib().gt_set_sort_spin_limit(limit))
 
 
 def tree_export(h, stream=None) -> np.ndarray:

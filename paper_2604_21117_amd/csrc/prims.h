@@ -107,4 +107,8 @@ template <class K>
 void sort_from(const K* src, K* keys, uint32_t* idx, K* keys_alt, uint32_t* idx_alt, uint64_t n, void* tmp,
                hipStream_t s, uint32_t* err = nullptr, uint32_t err_bit = 1u);
 
+// Empty look-back steps after which a sort gives up (process-wide; 0 makes
+// every tile after the first give up at once).  Returns the previous value.
+uint32_t set_sort_spin_limit(uint32_t limit);
+
 }  // namespace gt

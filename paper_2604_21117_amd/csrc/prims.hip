@@ -10,6 +10,8 @@
 // stable.  Larger inputs use LSD radix sort with 8-bit digits, one stable
 // scatter kernel per pass whose tiles find their output offsets by
 // decoupled look-back (below).
+#include <atomic>
+
 #include "prims.h"
 #include "common.h"
 
@@ -141,18 +143,26 @@ template void scan_exclusive<uint64_t>(const uint64_t*, uint64_t*, uint64_t*, co
 // LDS and writes each digit's run contiguously.  A tile waits only on tiles
 // with smaller tickets, which are already running and publish their counts
 // before they wait, so every wait ends; the spin is bounded all the same.
+// A tile that gives up sums only part of the earlier counts, so its writes
+// stay inside its digits' ranges; it marks the sort failed, later passes
+// then rank and publish but write nothing, and a last kernel replaces the
+// failed result by a valid sorted one (every key 0, index i at position i)
+// so that whatever consumes it stays in bounds while the error is reported.
 
 constexpr int kSortBlock = 1024;
 constexpr int kSortRounds = 4;
 constexpr uint64_t kSortTile = kSortBlock * kSortRounds;  // 4096
 constexpr uint64_t kBitonicMax = 2048;
 constexpr uint32_t kSpinMax = 1u << 20;       // a look-back that waits longer gives up
+static std::atomic<uint32_t> g_spin_max{kSpinMax};  // set by the testing hook (0: give up at once)
+
+uint32_t set_sort_spin_limit(uint32_t limit) { return g_spin_max.exchange(limit, std::memory_order_relaxed); }
 constexpr uint64_t kNarrowMax = 1ull << 30;   // counts fit the 30 bits of a 32-bit tile word
 
 static uint32_t sort_tiles(uint64_t n) { return static_cast<uint32_t>((n + kSortTile - 1) / kSortTile); }
 
 struct SortLayout {
-    uint64_t totals, tickets, err, flags, bytes;
+    uint64_t totals, tickets, fail, flags, bytes;
 };
 
 static SortLayout sort_layout(uint64_t n, int key_bytes) {
@@ -162,7 +172,7 @@ static SortLayout sort_layout(uint64_t n, int key_bytes) {
     uint64_t o = 0;
     L.totals = o;  o += al(static_cast<uint64_t>(key_bytes) * 256 * 4);
     L.tickets = o; o += al(static_cast<uint64_t>(key_bytes) * 4);
-    L.err = o;     o += al(4);
+    L.fail = o;    o += al(4);
     L.flags = o;   o += al(static_cast<uint64_t>(key_bytes) * nt * 256 * w);
     L.bytes = o;
     return L;
@@ -226,8 +236,8 @@ template <class K, class W>
 __global__ __launch_bounds__(kSortBlock) void k_sort_pass(const K* __restrict__ kin, const uint32_t* __restrict__ iin,
                                                            K* __restrict__ kout, uint32_t* __restrict__ iout, uint64_t n,
                                                            int shift, const uint32_t* __restrict__ totals,
-                                                           uint32_t* ticket, W* flags, uint32_t* err,
-                                                           uint32_t err_bit) {
+                                                           uint32_t* ticket, W* flags, uint32_t* fail,
+                                                           uint32_t* err, uint32_t err_bit, uint32_t spin_max) {
     constexpr int kSh = static_cast<int>(sizeof(W)) * 8 - 2;
     constexpr W kAgg = W(1) << kSh, kIncl = W(2) << kSh, kVal = (W(1) << kSh) - 1;
     __shared__ uint32_t wcnt[kSortBlock / 64][256];
@@ -236,13 +246,17 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(const K* __restrict__ 
     __shared__ uint32_t lstart[256];  // this tile's run of digit d inside the tile
     __shared__ uint64_t gbase[256];   // and in the output
     __shared__ uint32_t sh[33];
-    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_tile, s_failed;
     __shared__ K tk[kSortTile];
     __shared__ uint32_t ti[kSortTile];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    if (tid == 0) s_tile = atomicAdd(ticket, 1u);
+    if (tid == 0) {
+        s_tile = atomicAdd(ticket, 1u);
+        s_failed = __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __syncthreads();
     const uint32_t tile = s_tile;
+    const bool failed = s_failed != 0;  // an earlier tile gave up: write nothing
     const uint64_t tbase = static_cast<uint64_t>(tile) * kSortTile;
     // rank the tile's elements by digit, in input order.  Wave w ranks the
     // tile's w-th block of 256 elements, four 64-element chunks in order,
@@ -317,6 +331,12 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(const K* __restrict__ 
         uint64_t excl = 0;
         if (tile == 0) {
             __hip_atomic_store(mine, kIncl | static_cast<W>(cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (spin_max == 0) {
+            // forced from the host (testing): give up without waiting, still
+            // publishing a prefix so that no later tile waits either
+            atomicOr(fail, 1u);
+            if (err) atomicOr(err, err_bit);
+            __hip_atomic_store(mine, kIncl | static_cast<W>(cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             __hip_atomic_store(mine, kAgg | static_cast<W>(cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             // eight earlier tiles per step, their words read together; sum
@@ -344,7 +364,11 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(const K* __restrict__ 
                     if (f == 2) done = true;
                 }
                 j -= used;
-                if (!done && used == 0 && ++spins > kSpinMax) { atomicOr(err, err_bit); break; }
+                if (!done && used == 0 && ++spins > spin_max) {
+                    atomicOr(fail, 1u);
+                    if (err) atomicOr(err, err_bit);
+                    break;
+                }
             }
             __hip_atomic_store(mine, kIncl | static_cast<W>(excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -365,6 +389,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(const K* __restrict__ 
         }
     }
     __syncthreads();
+    if (failed) return;  // the same for the whole workgroup, after its last barrier
     const uint64_t cnt = n - tbase < kSortTile ? n - tbase : kSortTile;
     for (uint32_t p = tid; p < cnt; p += kSortBlock) {
         const K k = tk[p];
@@ -372,6 +397,18 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(const K* __restrict__ 
         const uint64_t dst = gbase[d] + (p - lstart[d]);
         kout[dst] = k;
         iout[dst] = ti[p];
+    }
+}
+
+// After the passes: a failed sort's result becomes every key 0, index i at
+// position i (sorted, and a valid permutation).
+template <class K>
+__global__ __launch_bounds__(256) void k_sort_fix(K* __restrict__ keys, uint32_t* __restrict__ idx, uint64_t n,
+                                                  const uint32_t* fail) {
+    if (__hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
+    for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull) {
+        keys[i] = K(0);
+        idx[i] = static_cast<uint32_t>(i);
     }
 }
 
@@ -384,7 +421,7 @@ static void sort_onesweep(const K* src, K* keys, uint32_t* idx, K* keys_alt, uin
     uint8_t* b = reinterpret_cast<uint8_t*>(tmp);
     uint32_t* totals = reinterpret_cast<uint32_t*>(b + L.totals);
     uint32_t* tickets = reinterpret_cast<uint32_t*>(b + L.tickets);
-    uint32_t* err = err_out ? err_out : reinterpret_cast<uint32_t*>(b + L.err);
+    uint32_t* fail = reinterpret_cast<uint32_t*>(b + L.fail);
     W* flags = reinterpret_cast<W*>(b + L.flags);
     const uint64_t words = L.bytes / 4;
     const uint64_t cg = (words + 255) / 256;
@@ -399,13 +436,14 @@ static void sort_onesweep(const K* src, K* keys, uint32_t* idx, K* keys_alt, uin
     K* kb = keys_alt; uint32_t* ib = idx_alt;
     for (int p = 0; p < P; ++p) {
         hipLaunchKernelGGL((k_sort_pass<K, W>), dim3(nt), dim3(kSortBlock), 0, s, ka, ia, kb, ib, n, 8 * p,
-                           totals + p * 256, tickets + p, flags + static_cast<uint64_t>(p) * nt * 256, err,
-                           err_bit);
+                           totals + p * 256, tickets + p, flags + static_cast<uint64_t>(p) * nt * 256, fail,
+                           err_out, err_bit, g_spin_max.load(std::memory_order_relaxed));
         ka = kb;
         ia = ib;
         kb = (p & 1) ? keys_alt : keys;
         ib = (p & 1) ? idx_alt : idx;
     }
+    hipLaunchKernelGGL(k_sort_fix<K>, dim3(nt < 256 ? nt : 256), dim3(256), 0, s, keys, idx, n, fail);
 }
 
 template <class K>

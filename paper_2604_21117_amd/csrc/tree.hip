@@ -216,6 +216,8 @@ const char* gt_status_str(gt_status s) {
     return "unknown status";
 }
 
+uint32_t gt_set_sort_spin_limit(uint32_t limit) { return set_sort_spin_limit(limit); }
+
 uint64_t tree_arena_bytes(const gt_params* p, uint64_t n, uint64_t leaf_slack) {
     if (!params_ok(p)) return 0;
     std::vector<uint64_t> sizes = level_sizes_for(n, fill_of(p));
