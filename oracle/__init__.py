@@ -8,8 +8,8 @@ calls it, and the two share no code: the oracle is C compiled with gcc
 Parts (each cited in ``oracle.c``):
 
 * :class:`SortedArray` -- the plain definitions: lookup by binary search,
-  an insert batch as its sequential application in batch order, range as a
-  sorted slice (paper Section III for the structure, Section IV-D for the
+  an insert or delete batch as its sequential application in batch order,
+  range as a sorted slice (paper Section III for the structure, Section IV-D for the
   -1 "not found" result).
 * :class:`PointerTree` -- a textbook pointer B+-tree (Section III), the
   timed CPU baseline; lookup batches split evenly over threads (Section V-F).
@@ -68,6 +68,8 @@ def lib():
         L.ora_lookup.argtypes = [_u64p, _u64p, u64, _u64p, u64, i32, _u64p, _u8p]
         L.ora_insert.argtypes = [_u64p, _u64p, u64, _u64p, _u64p, u64, _u64p, _u64p, _u8p]
         L.ora_insert.restype = u64
+        L.ora_delete.argtypes = [_u64p, _u64p, u64, _u64p, u64, _u64p, _u64p, _u8p]
+        L.ora_delete.restype = u64
         L.ora_range.argtypes = [_u64p, _u64p, u64, _u64p, _u64p, _u32p, _u64p, u64, _u64p, _u64p, _u32p]
         L.bpt_create.argtypes = [i32, i32, i32]
         L.bpt_create.restype = vp
@@ -138,6 +140,17 @@ class SortedArray:
         ov = np.empty(n + B, dtype=np.uint64)
         st = np.empty(B, dtype=np.uint8)
         m = lib().ora_insert(self.keys, self.vals, n, k, v, B, ok, ov, st)
+        self.keys, self.vals = ok[:m].copy(), ov[:m].copy()
+        return st
+
+    def delete(self, k):
+        """Delete batch in batch order; per key 1 (DELETED) or 0 (ABSENT)."""
+        k = _w(k)
+        n, B = len(self.keys), len(k)
+        ok = np.empty(max(n, 1), dtype=np.uint64)
+        ov = np.empty(max(n, 1), dtype=np.uint64)
+        st = np.empty(B, dtype=np.uint8)
+        m = lib().ora_delete(self.keys, self.vals, n, k, B, ok, ov, st)
         self.keys, self.vals = ok[:m].copy(), ov[:m].copy()
         return st
 

@@ -4,7 +4,8 @@ searched by linear scan.  TEST INFRASTRUCTURE ONLY.
 Each function is the plain definition written out with pure-Python loops,
 for n and B up to a few hundred: lookup returns the value or the paper's -1
 (all ones at the key width) with found = 0 (Section IV-D); an insert batch
-applies its pairs one at a time in batch order; a range lists the pairs with
+applies its pairs one at a time in batch order, a delete batch removes its
+keys one at a time (1 for a key found, else 0); a range lists the pairs with
 lo <= key <= hi in ascending key order, cut to the first max of them.
 """
 from __future__ import annotations
@@ -45,6 +46,18 @@ class Brute:
                     break
             else:
                 self.pairs.append([int(k), int(v)])
+                status.append(0)
+        return status
+
+    def delete(self, ks):
+        status = []
+        for k in ks:
+            for i, p in enumerate(self.pairs):
+                if p[0] == int(k):
+                    self.pairs.pop(i)
+                    status.append(1)
+                    break
+            else:
                 status.append(0)
         return status
 

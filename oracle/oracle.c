@@ -10,7 +10,8 @@
  *      keys with their values.  lookup(S,k) is a binary search; an insert
  *      batch is the sequential application of its (key, value) pairs in
  *      batch order, computed as stable sort + last-writer-per-key + merge;
- *      range(S, lo, hi, max) is the ascending slice lo <= key <= hi cut to
+ *      a delete batch removes its keys in batch order (a binary search per
+ *      key marks the hits, one pass keeps the rest); range(S, lo, hi, max) is the ascending slice lo <= key <= hi cut to
  *      its first max pairs.  A search that misses reports the paper's -1
  *      (all ones at the key width) together with found = 0 (Section IV-D).
  *
@@ -108,6 +109,32 @@ u64 ora_insert(const u64* keys, const u64* vals, u64 n, const u64* k, const u64*
         o++;
     }
     free(s); free(uk); free(uv);
+    return o;
+}
+
+/*
+ * Delete the keys k[i], i = 0..B-1, from S in batch order (the B+-tree's
+ * delete of Section III, on the state alone).  status[i] = 1 (DELETED) if
+ * k[i] was in S and not earlier in the batch, else 0 (ABSENT).  Each key of
+ * S is kept unless some k[i] equals it: a binary search of S per batch key
+ * marks the hits, then one pass copies the unmarked pairs.  out_keys and
+ * out_vals need room for n entries.  Returns the new size.
+ */
+u64 ora_delete(const u64* keys, const u64* vals, u64 n, const u64* k, u64 B,
+               u64* out_keys, u64* out_vals, uint8_t* status) {
+    uint8_t* gone = calloc(n ? n : 1, 1);
+    for (u64 i = 0; i < B; i++) {
+        u64 p = lower_bound(keys, n, k[i]);
+        int present = p < n && keys[p] == k[i] && !gone[p];
+        status[i] = present ? 1 : 0;
+        if (present) gone[p] = 1;
+    }
+    u64 o = 0;
+    for (u64 a = 0; a < n; a++) {
+        if (gone[a]) continue;
+        out_keys[o] = keys[a]; out_vals[o] = vals[a]; o++;
+    }
+    free(gone);
     return o;
 }
 

@@ -160,6 +160,62 @@ def test_insert_status_formula():
     assert list(k) == [10, 20, 30, 40] and list(v) == [6, 2, 9, 8]
 
 
+@pytest.mark.parametrize("width", [32, 64])
+@pytest.mark.parametrize("seed", range(10))
+def test_delete_vs_brute(width, seed):
+    """Delete batches (present keys, absent keys, keys repeated in the batch,
+    the edge keys) interleaved with inserts, against the one-at-a-time brute
+    force: statuses, the remaining pairs and lookups after each batch."""
+    rng = np.random.default_rng(500 + seed)
+    top = (1 << width) - 1
+    keys = _small_keys(rng, int(rng.integers(0, 80)), width, 0, 150)
+    if seed % 2 == 0:
+        keys = list(set(keys) | {0, top})
+    vals = [int(x) for x in rng.integers(0, top, len(keys), endpoint=True, dtype=np.uint64)]
+    br = Brute(keys, vals, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    for step in range(6):
+        B = int(rng.integers(0, 70))
+        kb = [int(x) for x in rng.integers(0, 160, B)]
+        if step % 3 == 1:
+            kb += [top, 0, top, 0]
+        stb = br.delete(kb)
+        sts = sa.delete(kb)
+        assert list(sts) == stb
+        bk, bv = br.items()
+        sk, sv = sa.items()
+        assert [int(x) for x in sk] == bk and [int(x) for x in sv] == bv
+        q = [int(x) for x in rng.integers(0, 170, 40)] + [0, top]
+        gv, gf = sa.lookup(q)
+        ev, ef = br.lookup(q)
+        assert list(gf) == ef and [int(x) for x in gv] == ev
+        ki = [int(x) for x in rng.integers(0, 160, int(rng.integers(0, 30)))]
+        vi = [int(x) for x in rng.integers(0, top, len(ki), endpoint=True, dtype=np.uint64)]
+        assert list(sa.insert(ki, vi)) == br.insert(ki, vi)
+
+
+def test_delete_closed_forms():
+    """Deleting every key empties the set with all statuses 1; deleting
+    absent keys changes nothing; a repeated key reports 1 only at its first
+    occurrence; deleting then re-inserting restores the set."""
+    keys = np.arange(5, 5005, 5, dtype=np.uint64)
+    vals = keys * 7
+    sa = oracle.SortedArray(keys, vals, 64)
+    st_ = sa.delete(keys + 1)
+    assert not st_.any() and len(sa) == 1000
+    st_ = sa.delete(np.array([10, 11, 10, 10, 4995, 5000, 5000], dtype=np.uint64))
+    assert list(st_) == [1, 0, 0, 0, 1, 1, 0]
+    k, v = sa.items()
+    assert len(k) == 997 and 10 not in set(k.tolist()) and np.array_equal(v, k * 7)
+    st_ = sa.insert(np.array([10, 4995, 5000], dtype=np.uint64), np.array([70, 4995 * 7, 35000], dtype=np.uint64))
+    assert list(st_) == [0, 0, 0]
+    k, v = sa.items()
+    assert np.array_equal(k, keys) and np.array_equal(v, vals)
+    st_ = sa.delete(synth.shuffle(keys, 3))
+    assert st_.all() and len(sa) == 0
+    assert not sa.delete(keys[:10]).any()
+
+
 def test_range_closed_form():
     keys = np.arange(0, 3000, 3, dtype=np.uint64)
     sa = oracle.SortedArray(keys, keys + 1, 64)
