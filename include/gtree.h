@@ -185,6 +185,26 @@ gt_status tree_insert_batch(gt_tree* t, const void* keys, const void* values, ui
                             uint8_t* status_out, hipStream_t stream);
 
 /*
+ * Delete batch.  Equivalent to deleting keys[i] one at a time for
+ * i = 0..B-1: status_out[i] = 1 (DELETED) when keys[i] was present before
+ * the batch and not earlier in the batch, else 0 (ABSENT).  Every node but
+ * the root stays at least half full (Section III): a leaf left with fewer
+ * than 8 keys is merged with its siblings (the parent's keys are spread
+ * evenly over as few of its leaves as hold them at least half full, at
+ * least 8 of them), a root with two leaves shrinks to one leaf when 16 keys
+ * or fewer remain, and when a parent would itself fall below half full the
+ * tree is rebuilt in place from its keys (as tree_build, bulk load, height
+ * recomputed).  Leaves and inner nodes a merge gives up are not reused by
+ * later inserts (the pools only grow until the next tree_build).  Like an
+ * insert, a batch is not applied while the device error word holds
+ * GT_DEVERR_INTERNAL.  keys: B keys; status_out: B bytes; B <= max_batch.
+ * Synchronises the stream once, to learn whether a rebuild is needed; the
+ * rebuild allocates and frees temporary device memory.  A learned index
+ * over the tree answers through the tree after a delete until li_train.
+ */
+gt_status tree_delete_batch(gt_tree* t, const void* keys, uint64_t B, uint8_t* status_out, hipStream_t stream);
+
+/*
  * Range batch over the linked leaves (Section III).  For each i < B, the
  * pairs with lo[i] <= key <= hi[i], ascending, cut to the first max_out[i],
  * are written to out_keys/out_values starting at out_offsets[i];

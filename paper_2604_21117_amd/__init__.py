@@ -103,6 +103,7 @@ def lib():
         L.tree_lookup_levelwise_workspace_bytes.restype = u64
         L.tree_lookup_levelwise.argtypes = [vp, vp, u64, u32, vp, vp, vp, u64, vp]
         L.tree_insert_batch.argtypes = [vp, vp, vp, u64, vp, vp]
+        L.tree_delete_batch.argtypes = [vp, vp, u64, vp, vp]
         L.tree_range_batch.argtypes = [vp, vp, vp, vp, vp, u64, vp, vp, vp, vp]
         L.tree_destroy.argtypes = [vp]
         L.tree_stats.argtypes = [vp, C.POINTER(gt_tree_stats), vp]
@@ -127,7 +128,7 @@ def lib():
         L.srv_stats.argtypes = [vp, C.POINTER(gt_srv_stats)]
         L.srv_latencies.argtypes = [vp, vp, u64]
         L.srv_destroy.argtypes = [vp]
-        for f in ("tree_build", "tree_lookup_batch", "tree_insert_batch", "tree_range_batch",
+        for f in ("tree_build", "tree_lookup_batch", "tree_insert_batch", "tree_delete_batch", "tree_range_batch",
                   "tree_destroy", "tree_stats", "tree_device_error", "tree_export", "li_create", "li_train",
                   "li_lookup_batch", "li_predict", "li_set_bounds", "li_stats", "li_destroy", "srv_create",
                   "srv_submit", "srv_poll", "srv_wait", "srv_replay", "srv_stats", "srv_latencies",
@@ -230,6 +231,11 @@ def tree_lookup_levelwise(h, keys, flags, values_out, found_out, workspace, stre
 def tree_insert_batch(h, keys, values, status_out, stream=None):
     _check(lib().tree_insert_batch(h, _ptr(keys), _ptr(values), keys.numel(), _ptr(status_out),
                                    _stream(stream)), "tree_insert_batch")
+
+
+def tree_delete_batch(h, keys, status_out, stream=None):
+    _check(lib().tree_delete_batch(h, _ptr(keys), keys.numel(), _ptr(status_out), _stream(stream)),
+           "tree_delete_batch")
 
 
 def tree_range_batch(h, lo, hi, max_out, out_offsets, out_keys, out_values, count_out, stream=None):
@@ -381,6 +387,15 @@ class Tree:
         tree_insert_batch(self.h, kd, vd, st)
         if check:
             _check(tree_device_error(self.h), "tree_insert_batch (device)")
+        return to_numpy(st)
+
+    def delete(self, k: np.ndarray, check: bool = True):
+        torch = _torch()
+        kd = self.dev(k)
+        st = torch.empty(kd.numel(), dtype=torch.uint8, device=self.device)
+        tree_delete_batch(self.h, kd, st)
+        if check:
+            _check(tree_device_error(self.h), "tree_delete_batch (device)")
         return to_numpy(st)
 
     def range(self, lo: np.ndarray, hi: np.ndarray, maxc: np.ndarray):

@@ -31,6 +31,7 @@ struct gt_tree {
     uint32_t h_bound;       // the tree's height or more (exact after the build;
                             // after an insert, the most the pool sizes allow)
     uint64_t inserts = 0;   // insert batches enqueued on this tree
+    uint64_t deletes = 0;   // delete batches applied to this tree
 };
 
 

@@ -23,4 +23,16 @@ template <class K>
 void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, const K* vals, uint64_t B,
                    uint8_t* status, hipStream_t s);
 
+// Delete batch on the same scratch; returns the device word that is nonzero
+// when the tree must be rebuilt from its keys (read after the stream ends).
+template <class K>
+const uint32_t* launch_delete(const TreeView<K>& t, const InsertCtx& c, const K* keys, uint64_t B, uint8_t* status,
+                              hipStream_t s);
+
+// Every pair of the leaves that hold keys, appended at *n (device counter);
+// past `cap` pairs nothing is written, the counter still counts.
+template <class K>
+void launch_delete_collect(const TreeView<K>& t, uint32_t leaves, K* ok, K* ov, uint64_t cap,
+                           unsigned long long* n, hipStream_t s);
+
 }  // namespace gt

@@ -54,7 +54,9 @@ struct InsState {
     uint32_t lvl_new[kMaxLevels];    // new nodes the level's items create
     uint32_t lvl_alloc[kMaxLevels];  // first new id of the level
     uint32_t lvl_psep[kMaxLevels];   // first piece separator of the level
-    uint32_t pad[7];
+    uint32_t deleted;      // delete batch: keys removed
+    uint32_t rebuild;      // delete batch: a parent would fall below half full
+    uint32_t pad[5];
 };
 
 template <class K>
@@ -1240,5 +1242,286 @@ template void launch_insert<uint32_t>(const TreeView<uint32_t>&, const InsertCtx
                                       const uint32_t*, uint64_t, uint8_t*, hipStream_t);
 template void launch_insert<uint64_t>(const TreeView<uint64_t>&, const InsertCtx&, const uint64_t*,
                                       const uint64_t*, uint64_t, uint8_t*, hipStream_t);
+
+// ---------------------------------------------------------------- delete
+//
+// A delete batch (Section III: every node but the root stays at least half
+// full) shares the insert's front end: sort, distinct keys, and a locate
+// that records each key's path.  Then:
+//  1. one thread per touched leaf removes the batch's keys from it in place
+//     (survivors moved down, padding rewritten).  If the leaf's largest key
+//     went and the leaf stays at least half full, it rewrites the separator
+//     that holds that key: on the path, the first node whose child slot is
+//     not its last;
+//  2. one wave per leaf parent with a child left below half full gathers the
+//     parent's keys (at most 16 x 16) and spreads them evenly over
+//     max(8, ceil(T / 16)) of its leaves, which borrows and merges in one
+//     step.  The leaves no longer needed are cleared (count 0) and dropped
+//     from the chain, the parent's line is rewritten, and its new largest
+//     key goes into its own separator further up.  A parent that is the
+//     root keeps at least two leaves, or becomes the single leaf root when
+//     16 keys or fewer remain (the root shrinks);
+//  3. a parent that would keep fewer than 64 keys would itself fall below
+//     half full; the batch flags it and the host rebuilds the tree from its
+//     keys.
+
+constexpr uint32_t kHalf = kSlots / 2;
+
+template <class K>
+__global__ void k_del_heads(Ins<K> v, uint64_t B, uint8_t* __restrict__ status) {
+    for (uint64_t p = gtid(); p < B; p += gstride()) {
+        const bool head = p == 0 || v.sk[p] != v.sk[p - 1];
+        v.f0[p] = head ? 1u : 0u;
+        if (!head) status[v.si[p]] = 0;  // ABSENT: an earlier occurrence deleted it
+    }
+}
+
+template <class K>
+__global__ void k_del_unique(Ins<K> v, uint64_t B) {
+    for (uint64_t p = gtid(); p < B; p += gstride()) {
+        if (v.f0[p]) {
+            v.uk[v.f1[p]] = v.sk[p];
+            v.upos[v.f1[p]] = static_cast<uint32_t>(p);
+        }
+    }
+}
+
+// first distinct key of its leaf's run (keys are sorted, so a leaf's keys
+// are consecutive)
+template <class K>
+__device__ __forceinline__ bool leaf_run_head(const Ins<K>& v, uint64_t u) {
+    return u == 0 || v.uleaf[u - 1] != v.uleaf[u];
+}
+
+template <class K>
+__global__ __launch_bounds__(kBlk) void k_del_leaf(TreeView<K> t, Ins<K> v) {
+    if (t.hdr->error & kErrInternal) return;  // e.g. the batch's device sort gave up
+    const uint64_t U = v.st->U;
+    const int h = static_cast<int>(v.st->height);
+    for (uint64_t u = gtid(); u < U; u += gstride()) {
+        if (!leaf_run_head(v, u)) continue;
+        const uint32_t leaf = v.uleaf[u];
+        uint32_t gone = 0, nd = 0;
+        for (uint64_t e = u; e < U && v.uleaf[e] == leaf; ++e) {
+            if (v.ufound[e]) {
+                gone |= 1u << v.uslot[e];
+                ++nd;
+            }
+        }
+        const uint32_t c = t.lmeta[leaf].x;
+        const uint32_t w = c - nd;
+        const bool under = h > 1 && w < kHalf;
+        v.f0[u] = under ? 1u : 0u;
+        if (nd == 0) continue;
+        K* kl = t.lkeys + static_cast<uint64_t>(leaf) * kSlots;
+        K* vl = t.lvals + static_cast<uint64_t>(leaf) * kSlots;
+        uint32_t o = 0;
+        for (uint32_t i = 0; i < c; ++i) {
+            if ((gone >> i) & 1u) continue;
+            if (o != i) {
+                kl[o] = kl[i];
+                vl[o] = vl[i];
+            }
+            ++o;
+        }
+        const K pk = w ? kl[w - 1] : kmax<K>();
+        for (uint32_t i = w; i < kSlots; ++i) {
+            kl[i] = pk;
+            vl[i] = kmax<K>();
+        }
+        t.lmeta[leaf].x = w;
+        atomicAdd(&v.st->deleted, nd);
+        if (!under && w > 0 && ((gone >> (c - 1)) & 1u)) {
+            for (int l = h - 2; l >= 0; --l) {
+                const uint64_t o2 = static_cast<uint64_t>(l) * v.Bm + u;
+                if (v.pi[o2] + 1u < v.pc[o2]) {
+                    t.ikeys[static_cast<uint64_t>(v.pn[o2]) * kSlots + v.pi[o2]] = pk;
+                    break;
+                }
+            }
+        }
+    }
+}
+
+template <class K>
+__global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v) {
+    if (t.hdr->error & kErrInternal) return;
+    const uint64_t U = v.st->U;
+    const int h = static_cast<int>(v.st->height);
+    if (h < 2) return;
+    __shared__ K mk[kSlots * kSlots];
+    __shared__ K mv[kSlots * kSlots];
+    __shared__ uint32_t kid[kSlots], cnt[kSlots], pre[kSlots + 1];
+    __shared__ uint32_t s_next;
+    const int lane = static_cast<int>(threadIdx.x);
+    const uint64_t lp = static_cast<uint64_t>(h - 2) * v.Bm;  // path level of the leaves' parents
+    for (uint64_t u = blockIdx.x; u < U; u += gridDim.x) {
+        // the first run under its parent that left its leaf below half full
+        if (!leaf_run_head(v, u) || !v.f0[u]) continue;
+        const uint32_t P = v.pn[lp + u];
+        bool first = true;
+        for (uint64_t e = u; e-- > 0 && v.pn[lp + e] == P;) {
+            if (leaf_run_head(v, e) && v.f0[e]) {
+                first = false;
+                break;
+            }
+        }
+        if (!first) continue;
+        const uint32_t nc = v.pc[lp + u];
+        const K fs = t.ikeys[static_cast<uint64_t>(P) * kSlots + kFirstSlot];
+        if (lane < kSlots) {
+            uint32_t ref = kNone;
+            if (static_cast<uint32_t>(lane) < nc)
+                ref = fs != kmax<K>() ? static_cast<uint32_t>(fs) + static_cast<uint32_t>(lane)
+                                      : t.ichild[static_cast<uint64_t>(P) * kSlots + lane];
+            kid[lane] = ref & ~kLeafTag;
+            const uint32_t c = static_cast<uint32_t>(lane) < nc ? t.lmeta[ref & ~kLeafTag].x : 0u;
+            cnt[lane] = c < kSlots ? c : kSlots;
+        }
+        __syncthreads();
+        if (lane == 0) {
+            uint32_t a = 0;
+            for (int i = 0; i < kSlots; ++i) {
+                pre[i] = a;
+                a += cnt[i];
+            }
+            pre[kSlots] = a;
+            s_next = t.lmeta[kid[nc - 1]].y;
+        }
+        __syncthreads();
+        const uint32_t T = pre[kSlots];
+        const bool root = h == 2;
+        if (!root && T < kHalf * kHalf) {
+            if (lane == 0) atomicOr(&v.st->rebuild, 1u);
+            __syncthreads();
+            continue;
+        }
+        if (static_cast<uint32_t>(lane) < nc) {
+            const uint64_t src = static_cast<uint64_t>(kid[lane]) * kSlots;
+            for (uint32_t j = 0; j < cnt[lane]; ++j) {
+                mk[pre[lane] + j] = t.lkeys[src + j];
+                mv[pre[lane] + j] = t.lvals[src + j];
+            }
+        }
+        __syncthreads();
+        const uint32_t want = (T + kSlots - 1) / kSlots;
+        const uint32_t n0 = root ? (T <= kSlots ? 1u : (want > 2u ? want : 2u)) : (want > kHalf ? want : kHalf);
+        if (n0 > nc) {  // cannot happen on a tree whose nodes were at least half full
+            if (lane == 0) atomicOr(&v.st->rebuild, 1u);
+            __syncthreads();
+            continue;
+        }
+        const uint32_t q = T / n0, r = T % n0;
+        // leaf j (lane j < n0) takes pairs [start, start + len)
+        if (static_cast<uint32_t>(lane) < nc) {
+            const uint32_t j = static_cast<uint32_t>(lane);
+            const uint64_t dst = static_cast<uint64_t>(kid[j]) * kSlots;
+            if (j < n0) {
+                const uint32_t len = q + (j < r ? 1u : 0u), start = j * q + (j < r ? j : r);
+                for (uint32_t s = 0; s < kSlots; ++s) {
+                    t.lkeys[dst + s] = s < len ? mk[start + s] : (len ? mk[start + len - 1] : kmax<K>());
+                    t.lvals[dst + s] = s < len ? mv[start + s] : kmax<K>();
+                }
+                t.lmeta[kid[j]] = make_uint2(len, j + 1 < n0 ? kid[j + 1] : s_next);
+            } else {
+                for (uint32_t s = 0; s < kSlots; ++s) {
+                    t.lkeys[dst + s] = kmax<K>();
+                    t.lvals[dst + s] = kmax<K>();
+                }
+                t.lmeta[kid[j]] = make_uint2(0u, kNone);
+            }
+        }
+        if (root && n0 == 1) {
+            // the root shrinks to its first leaf
+            if (lane == 0) {
+                t.hdr->root = kid[0] | kLeafTag;
+                t.hdr->height = 1;
+            }
+        } else {
+            if (lane < kSlots) {
+                const uint32_t s = static_cast<uint32_t>(lane);
+                K sep = kmax<K>();
+                if (s + 1 < n0) {
+                    const uint32_t end = (s + 1) * q + (s + 1 < r ? s + 1 : r);  // start of leaf s + 1
+                    sep = mk[end - 1];
+                }
+                t.ikeys[static_cast<uint64_t>(P) * kSlots + s] = sep;  // slot 15: children from the child line
+                t.ichild[static_cast<uint64_t>(P) * kSlots + s] = s < n0 ? (kid[s] | kLeafTag) : kNone;
+            }
+            if (lane == 0 && !root) {
+                const K top = mk[T - 1];
+                for (int l = h - 3; l >= 0; --l) {
+                    const uint64_t o2 = static_cast<uint64_t>(l) * v.Bm + u;
+                    if (v.pi[o2] + 1u < v.pc[o2]) {
+                        t.ikeys[static_cast<uint64_t>(v.pn[o2]) * kSlots + v.pi[o2]] = top;
+                        break;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <class K>
+__global__ void k_del_commit(TreeView<K> t, Ins<K> v) {
+    if (t.hdr->error & kErrInternal) return;
+    const uint32_t d = v.st->deleted;
+    if (d == 0) return;
+    t.hdr->n_keys -= d;
+    t.hdr->epoch += 1;
+}
+
+// Copy every pair of the leaves that hold keys (cleared leaves hold none).
+template <class K>
+__global__ void k_del_collect(TreeView<K> t, uint32_t leaves, K* __restrict__ ok, K* __restrict__ ov, uint64_t cap,
+                              unsigned long long* __restrict__ n) {
+    for (uint64_t l = gtid(); l < leaves; l += gstride()) {
+        const uint32_t c = t.lmeta[l].x < kSlots ? t.lmeta[l].x : kSlots;
+        if (c == 0) continue;
+        const uint64_t at = atomicAdd(n, static_cast<unsigned long long>(c));
+        if (at + c > cap) continue;  // more pairs than the tree counts: the host reports it
+        for (uint32_t j = 0; j < c; ++j) {
+            ok[at + j] = t.lkeys[l * kSlots + j];
+            ov[at + j] = t.lvals[l * kSlots + j];
+        }
+    }
+}
+
+template <class K>
+const uint32_t* launch_delete(const TreeView<K>& t, const InsertCtx& c, const K* keys, uint64_t B, uint8_t* status,
+                              hipStream_t s) {
+    Ins<K> v;
+    carve<K>(&v, c.scratch, c.max_batch, c.leaf_cap, c.inner_cap);
+    const uint32_t gB = grid_for(B, kBlk);
+    hipLaunchKernelGGL(k_init<K>, dim3(1), dim3(kBlk), 0, s, v, t.hdr);
+    sort_from<K>(keys, v.sk, v.si, v.sk2, v.si2, B, v.sort_tmp, s, &t.hdr->error, kErrInternal);
+    hipLaunchKernelGGL(k_del_heads<K>, dim3(gB), dim3(kBlk), 0, s, v, B, status);
+    scan_exclusive<uint32_t>(v.f0, v.f1, &v.st->U, nullptr, B, v.scan_tmp, s);
+    hipLaunchKernelGGL(k_del_unique<K>, dim3(gB), dim3(kBlk), 0, s, v, B);
+    launch_locate<K>(t, v, c.cfg, B, status, s);
+    hipLaunchKernelGGL(k_del_leaf<K>, dim3(gB), dim3(kBlk), 0, s, t, v);
+    const uint32_t gm = B < 4096 ? static_cast<uint32_t>(B) : 4096u;
+    hipLaunchKernelGGL(k_del_merge<K>, dim3(gm), dim3(64), 0, s, t, v);
+    hipLaunchKernelGGL(k_del_commit<K>, dim3(1), dim3(1), 0, s, t, v);
+    launch_mirror_refresh<K>(t, s);
+    return &v.st->rebuild;
+}
+
+template <class K>
+void launch_delete_collect(const TreeView<K>& t, uint32_t leaves, K* ok, K* ov, uint64_t cap,
+                           unsigned long long* n, hipStream_t s) {
+    const uint32_t g = grid_for(leaves ? leaves : 1, kBlk);
+    hipLaunchKernelGGL(k_del_collect<K>, dim3(g < 4096 ? g : 4096), dim3(kBlk), 0, s, t, leaves, ok, ov, cap, n);
+}
+
+template const uint32_t* launch_delete<uint32_t>(const TreeView<uint32_t>&, const InsertCtx&, const uint32_t*,
+                                                 uint64_t, uint8_t*, hipStream_t);
+template const uint32_t* launch_delete<uint64_t>(const TreeView<uint64_t>&, const InsertCtx&, const uint64_t*,
+                                                 uint64_t, uint8_t*, hipStream_t);
+template void launch_delete_collect<uint32_t>(const TreeView<uint32_t>&, uint32_t, uint32_t*, uint32_t*, uint64_t,
+                                              unsigned long long*, hipStream_t);
+template void launch_delete_collect<uint64_t>(const TreeView<uint64_t>&, uint32_t, uint64_t*, uint64_t*, uint64_t,
+                                              unsigned long long*, hipStream_t);
 
 }  // namespace gt

@@ -259,10 +259,18 @@ __global__ void k_bfs_scatter(const uint32_t* __restrict__ ichild, const uint32_
     }
 }
 
+__global__ void k_pos_clear(uint32_t* pos, uint32_t n) {
+    for (uint64_t i = gid(); i < n; i += gsz()) pos[i] = kNone;
+}
+
+// Directory entry per leaf position.  Leaf ids run to `ids`; the L leaves the
+// walk from the root reached hold positions 0..L-1, the others (leaves a
+// delete's merge gave up) keep "none" and are skipped.
 template <class K>
-__global__ void k_directory(TreeView<K> t, LiView<K> li, uint32_t n) {
-    for (uint64_t i = gid(); i < n; i += gsz()) {
+__global__ void k_directory(TreeView<K> t, LiView<K> li, uint32_t ids, uint32_t L) {
+    for (uint64_t i = gid(); i < ids; i += gsz()) {
         const uint32_t pos = li.pos_of_leaf[i];
+        if (pos >= L) continue;
         DirEntry<K> e;
         e.fence = t.lkeys[i * kSlots];
         e.leaf = static_cast<uint32_t>(i);
@@ -272,7 +280,7 @@ __global__ void k_directory(TreeView<K> t, LiView<K> li, uint32_t n) {
         DirEntry<K> e;
         e.fence = kmax<K>();
         e.leaf = kNone;
-        li.dir[n] = e;
+        li.dir[L] = e;
     }
 }
 
@@ -1050,6 +1058,7 @@ struct gt_learned {
     bool declined = false;    // the quality gate sends lookups to the tree kernel
     uint32_t max_win = 0;     // widest window at training (leaves)
     uint64_t inserts_at_train = 0;  // the tree's insert count when trained
+    uint64_t deletes_at_train = 0;  // and its delete count
     uint64_t generation = 0;  // bumped whenever the lookup's arguments or tables change
 };
 
@@ -1060,7 +1069,13 @@ static bool li_stale(const gt_learned* li) {
     return !li->args.exact || li->t->inserts != li->inserts_at_train;
 }
 
-uint64_t gt_li_generation(const gt_learned* li) { return 2 * li->generation + (li_stale(li) ? 1 : 0); }
+// After a delete batch the directory may name leaves the delete cleared or
+// refilled, so lookups go down the tree until the next training.
+static bool li_deleted(const gt_learned* li) { return li->t->deletes != li->deletes_at_train; }
+
+uint64_t gt_li_generation(const gt_learned* li) {
+    return 4 * li->generation + (li_deleted(li) ? 2 : 0) + (li_stale(li) ? 1 : 0);
+}
 
 namespace {
 
@@ -1153,17 +1168,20 @@ gt_status train_t(gt_learned* li, hipStream_t s) {
         li->trained = false;
         li->declined = false;
         li->inserts_at_train = t->inserts;
+        li->deletes_at_train = t->deletes;
         li->generation++;
         return GT_OK;
     }
-    const uint32_t n = dh.leaf_used;
-    if (n > li->leaf_cap) return GT_ERR_CAPACITY;
+    const uint32_t ids = dh.leaf_used;  // leaf ids in use (a delete's merge can leave some unreached)
+    if (ids > li->leaf_cap) return GT_ERR_CAPACITY;
+    uint32_t n = 1;  // leaves in the tree: positions 0..n-1
     // leaf positions: expand the levels from the root (lists in nxt0/nxt1,
     // per-node child counts and their offsets in rank0/rank1)
     {
         const uint32_t h = dh.height;
         uint32_t* la = v.nxt0; uint32_t* lb = v.nxt1;
         uint32_t* lvl = v.lvl;  // lvl[l] = nodes of level l
+        hipLaunchKernelGGL(k_pos_clear, dim3(grid_of(ids, 256)), dim3(256), 0, s, v.pos_of_leaf, ids);
         hipLaunchKernelGGL(k_bfs_init, dim3(1), dim3(64), 0, s, la, lvl, dh.root, v.pos_of_leaf, h <= 1 ? 1u : 0u);
         uint64_t bound = 1;  // nodes a level can have
         for (uint32_t l = 0; l + 1 < h; ++l) {
@@ -1173,10 +1191,15 @@ gt_status train_t(gt_learned* li, hipStream_t s) {
             hipLaunchKernelGGL(k_bfs_scatter, dim3(g), dim3(256), 0, s, t->ichild, la, lvl + l, v.rank0, v.rank1, lb,
                                v.pos_of_leaf, l + 2 == h ? 1u : 0u);
             uint32_t* x = la; la = lb; lb = x;
-            bound = bound * kSlots < n ? bound * kSlots : n;
+            bound = bound * kSlots < ids ? bound * kSlots : ids;
+        }
+        if (h > 1) {
+            LI_HIP(hipMemcpyAsync(&n, lvl + (h - 1), 4, hipMemcpyDeviceToHost, s));
+            LI_HIP(hipStreamSynchronize(s));
         }
     }
-    hipLaunchKernelGGL(k_directory<K>, dim3(grid_of(n, 256)), dim3(256), 0, s, tv, v, n);
+    if (n == 0 || n > ids) return GT_ERR_DEVICE;
+    hipLaunchKernelGGL(k_directory<K>, dim3(grid_of(ids, 256)), dim3(256), 0, s, tv, v, ids, n);
     // root normalisation: smallest first key .. largest key of the tree
     DirEntry<K> d0, dl;
     LI_HIP(hipMemcpyAsync(&d0, v.dir, sizeof d0, hipMemcpyDeviceToHost, s));
@@ -1196,8 +1219,9 @@ gt_status train_t(gt_learned* li, hipStream_t s) {
     hipLaunchKernelGGL(k_fit<K>, dim3(M), dim3(256), 0, s, v, n, M);
     hipLaunchKernelGGL(k_bounds_init, dim3(grid_of(cells, 256)), dim3(256), 0, s, v.bnd, v.cnt,
                        static_cast<uint32_t>(cells));
-    hipLaunchKernelGGL(k_bounds<K>, dim3(grid_of(static_cast<uint64_t>(n) * kSlots, kLiBlock, 8192)),
-                       dim3(kLiBlock), 0, s, tv, v, n);
+    // over leaf ids: a leaf no longer in the tree holds no keys
+    hipLaunchKernelGGL(k_bounds<K>, dim3(grid_of(static_cast<uint64_t>(ids) * kSlots, kLiBlock, 8192)),
+                       dim3(kLiBlock), 0, s, tv, v, ids);
     uint32_t mw = li->p.max_window ? li->p.max_window : 64u;
     if (mw > 4096u) mw = 4096u;
     hipLaunchKernelGGL(k_choose<K>, dim3(grid_of(static_cast<uint64_t>(M) * 64, 256)), dim3(256), 0, s, v, M,
@@ -1206,7 +1230,7 @@ gt_status train_t(gt_learned* li, hipStream_t s) {
     hipLaunchKernelGGL(k_quality<K>, dim3(1), dim3(kQualityBlock), 0, s, v, static_cast<uint32_t>(cells));
     const uint32_t one = 1;
     LI_HIP(hipMemcpyAsync(v.identity, &one, 4, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_identity, dim3(grid_of(n, 256)), dim3(256), 0, s, v.pos_of_leaf, n, v.identity);
+    hipLaunchKernelGGL(k_identity, dim3(grid_of(ids, 256)), dim3(256), 0, s, v.pos_of_leaf, ids, v.identity);
     if (hipGetLastError() != hipSuccess) return GT_ERR_HIP;
     LiHeader h;
     uint32_t ident = 0;
@@ -1233,6 +1257,7 @@ gt_status train_t(gt_learned* li, hipStream_t s) {
                    (static_cast<double>(h.keys_tree) > kGateTreeShare * keys || mean_win > kGateMeanWindow);
     li->max_win = h.max_win;
     li->inserts_at_train = t->inserts;
+    li->deletes_at_train = t->deletes;
     li->generation++;
     return GT_OK;
 }
@@ -1310,7 +1335,8 @@ gt_status li_lookup_batch(gt_learned* li, const void* keys, uint64_t B, void* va
     if (!li) return GT_ERR_INVALID;
     if (B == 0) return GT_OK;
     if (!keys || !values_out || !found_out) return GT_ERR_INVALID;
-    if (!li->trained || li->declined) return tree_lookup_batch(li->t, keys, B, values_out, found_out, stream);
+    if (!li->trained || li->declined || li_deleted(li))
+        return tree_lookup_batch(li->t, keys, B, values_out, found_out, stream);
     if (li->t->kb == 8) launch_li_lookup<uint64_t>(li, keys, B, values_out, found_out, stream);
     else launch_li_lookup<uint32_t>(li, keys, B, values_out, found_out, stream);
     return hipGetLastError() == hipSuccess ? GT_OK : GT_ERR_HIP;

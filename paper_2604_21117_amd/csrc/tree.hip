@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
+#include <cstddef>
 #include <vector>
 #include <algorithm>
 
@@ -199,6 +200,46 @@ gt_status build_t(gt_tree* t, const void* keys, const void* values, uint64_t n, 
     return st;
 }
 
+// After a delete batch whose merges could not keep a leaf parent at least
+// half full: rebuild the tree in place from the pairs its leaves hold (the
+// bulk load fixes every level and the height), keeping the error word and
+// moving the epoch on.
+template <class K>
+gt_status delete_rebuild_t(gt_tree* t, hipStream_t s) {
+    DevHeader h;
+    HIP_TRY(hipMemcpyAsync(&h, t->hdr, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint64_t n = h.n_keys;
+    uint8_t* buf = nullptr;
+    const uint64_t b_keys = align_up((n ? n : 1) * sizeof(K));
+    HIP_TRY(hipMalloc(&buf, 2 * b_keys + kAlign));
+    K* ok = reinterpret_cast<K*>(buf);
+    K* ov = reinterpret_cast<K*>(buf + b_keys);
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(buf + 2 * b_keys);
+    gt_status st = GT_OK;
+    unsigned long long got = 0;
+    do {
+        if (hipMemsetAsync(cnt, 0, sizeof *cnt, s) != hipSuccess) { st = GT_ERR_HIP; break; }
+        launch_delete_collect<K>(view<K>(t), h.leaf_used, ok, ov, n, cnt, s);
+        if (hipMemcpyAsync(&got, cnt, sizeof got, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            st = GT_ERR_HIP;
+            break;
+        }
+        if (got != n) { st = GT_ERR_DEVICE; break; }
+        st = build_t<K>(t, ok, ov, n, s);
+        if (st != GT_OK) break;
+        const uint32_t keep[2] = {h.error, h.epoch + 1};  // DevHeader: error, then epoch
+        static_assert(offsetof(DevHeader, epoch) == offsetof(DevHeader, error) + 4, "header layout");
+        if (hipMemcpyAsync(&t->hdr->error, keep, sizeof keep, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            st = GT_ERR_HIP;
+    } while (0);
+    hipStreamSynchronize(s);
+    hipFree(buf);
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -301,6 +342,32 @@ gt_status tree_lookup_levelwise(gt_tree* t, const void* keys, uint64_t B, uint32
                                           presorted, t->h_bound, reinterpret_cast<uint32_t*>(values_out),
                                           found_out, workspace, stream);
     return hipGetLastError() == hipSuccess ? GT_OK : GT_ERR_HIP;
+}
+
+gt_status tree_delete_batch(gt_tree* t, const void* keys, uint64_t B, uint8_t* status_out, hipStream_t stream) {
+    if (!t) return GT_ERR_INVALID;
+    if (B == 0) return GT_OK;
+    if (!keys || !status_out) return GT_ERR_INVALID;
+    if (B > t->max_batch) return GT_ERR_CAPACITY;
+    InsertCtx c;
+    c.scratch = t->scratch;
+    c.scratch_bytes = t->scratch_bytes;
+    c.max_batch = t->max_batch;
+    c.inner_cap = t->inner_cap;
+    c.leaf_cap = t->leaf_cap;
+    c.cfg = t->cfg;
+    const uint32_t* flag =
+        t->kb == 8 ? launch_delete<uint64_t>(view<uint64_t>(t), c, reinterpret_cast<const uint64_t*>(keys), B,
+                                             status_out, stream)
+                   : launch_delete<uint32_t>(view<uint32_t>(t), c, reinterpret_cast<const uint32_t*>(keys), B,
+                                             status_out, stream);
+    HIP_TRY(hipGetLastError());
+    t->deletes++;
+    uint32_t rebuild = 0;
+    HIP_TRY(hipMemcpyAsync(&rebuild, flag, 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (!rebuild) return GT_OK;
+    return t->kb == 8 ? delete_rebuild_t<uint64_t>(t, stream) : delete_rebuild_t<uint32_t>(t, stream);
 }
 
 gt_status tree_range_batch(gt_tree* t, const void* lo, const void* hi, const uint32_t* max_out,

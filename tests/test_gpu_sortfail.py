@@ -3,8 +3,8 @@ forced from the host through the testing hook that sets its look-back
 limit: at 0 every workgroup of a pass but the first gives up at once, so
 every kernel still ends normally.  A failed sort must surface as an error,
 never as a wrong answer reported as good: the bulk load returns
-GT_ERR_DEVICE, an insert batch is refused with the tree unchanged, a
-level-wise lookup sets the internal bit of the error word.  Sorts that need
+GT_ERR_DEVICE, an insert or delete batch is refused with the tree
+unchanged, a level-wise lookup sets the internal bit of the error word.  Sorts that need
 no look-back (batches up to 4096 keys, one tile) are unaffected, and with
 the limit restored every path is exact again."""
 import numpy as np
@@ -60,6 +60,11 @@ def test_forced_sort_failure_is_reported_and_harmless(g, width):
         assert e.value.status == g.GT_ERR_DEVICE
         assert np.array_equal(t.export(), before), "a refused batch changed the tree"
         assert g.tree_device_error(t.h) == g.GT_OK, "reading the word clears it"
+        # delete above one tile: refused too
+        with pytest.raises(g.GtError) as e:
+            t.delete(synth.shuffle(keys[:9000], seed))
+        assert e.value.status == g.GT_ERR_DEVICE
+        assert np.array_equal(t.export(), before), "a refused delete changed the tree"
         # level-wise lookup above one tile: the internal bit is set
         q = synth.mixed_queries(keys, 9000, seed + 2, width)
         t.lookup_levelwise(q)
