@@ -37,6 +37,7 @@ Also measured in the same run, outside the K timed steps:
   insert          fresh-key insert batches, B = 1024 and 2^20
   range           range batches, B = 1024, max U{1..100}
   learned_stale   learned lookups after the inserts, then after retraining
+  delete          delete batches of present keys, B = 1, 64, 1024 and 2^20
   serving         2^26 resident keys; batches B ~ U{1..1024}, 80/15/5
                   lookup/insert/range, Zipf keys; closed loop, then Poisson
                   arrivals at 0.25/0.5/0.75/0.9 of its rate (20,000 batches
@@ -676,6 +677,40 @@ def main():
     stale_row["retrained_after_2p20_us"] = round(after, 3)
     print("[bench] staleness done", file=sys.stderr, flush=True)
 
+    # ---- delete batches of present keys: B = 1, 64 and 1024 (24 batches
+    # each), then 2^20 (one batch), on the tree the inserts above grew (the
+    # leaves they split are about half full, so single deletes merge).  The
+    # call synchronises once, to learn whether a rebuild is needed; the
+    # HIP-event span includes that round trip.
+    dorder = synth.shuffle(keys, SEED + 7)
+    dpos = 0
+
+    def delete_batch(k):
+        kd = tree.dev(k)
+        s8 = torch.empty(len(k), dtype=torch.uint8, device=dev)
+        t = timer.run(lambda: g.tree_delete_batch(tree.h, kd, s8, stream), 1, skip=0)
+        return t[0], s8
+
+    del_row = {"us_per_batch": {}, "mkeys_per_s": {}}
+    for b, reps in ((1, 24), (64, 24), (B, 24)):
+        ts = []
+        for _ in range(reps):
+            t, s8 = delete_batch(dorder[dpos:dpos + b])
+            dpos += b
+            ts.append(t)
+            assert (g.to_numpy(s8) == 1).all()
+        del_row["us_per_batch"][str(b)] = round(iqm(ts[4:]), 1)
+        del_row["mkeys_per_s"][str(b)] = round(b / iqm(ts[4:]), 3)
+    big, s8 = delete_batch(dorder[dpos:dpos + BL])
+    dpos += BL
+    assert g.tree_device_error(tree.h) == g.GT_OK and (g.to_numpy(s8) == 1).all()
+    del_row["us_per_batch"][str(BL)] = round(big, 1)
+    del_row["mkeys_per_s"][str(BL)] = round(BL / big, 2)
+    dst = tree.stats()
+    del_row["keys_after"] = dst["n_keys"]
+    del_row["height_after"] = dst["height"]
+    print("[bench] deletes done", file=sys.stderr, flush=True)
+
     # ---- serving: 2^26 resident uniform keys (seed 5), batches B ~ U{1..1024}
     # of 80 % lookups / 15 % inserts of fresh keys / 5 % ranges (max
     # U{1..100}), lookup keys and range starts Zipf(0.99) over the present
@@ -806,6 +841,7 @@ def main():
         "range": rng_row,
         "insert": ins_row,
         "learned_stale": stale_row,
+        "delete": del_row,
         "build_s": round(build_s, 3),
         "train_s": round(train_s, 3),
     }

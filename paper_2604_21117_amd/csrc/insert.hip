@@ -56,7 +56,8 @@ struct InsState {
     uint32_t lvl_psep[kMaxLevels];   // first piece separator of the level
     uint32_t deleted;      // delete batch: keys removed
     uint32_t rebuild;      // delete batch: a parent would fall below half full
-    uint32_t pad[5];
+    uint32_t merges;       // delete batch: leaf runs left below half full (listed in f1)
+    uint32_t pad[4];
 };
 
 template <class K>
@@ -1312,6 +1313,7 @@ __global__ __launch_bounds__(kBlk) void k_del_leaf(TreeView<K> t, Ins<K> v) {
         const uint32_t w = c - nd;
         const bool under = h > 1 && w < kHalf;
         v.f0[u] = under ? 1u : 0u;
+        if (under) v.f1[atomicAdd(&v.st->merges, 1u)] = static_cast<uint32_t>(u);  // list for the merge pass
         if (nd == 0) continue;
         K* kl = t.lkeys + static_cast<uint64_t>(leaf) * kSlots;
         K* vl = t.lvals + static_cast<uint64_t>(leaf) * kSlots;
@@ -1346,7 +1348,6 @@ __global__ __launch_bounds__(kBlk) void k_del_leaf(TreeView<K> t, Ins<K> v) {
 template <class K>
 __global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v) {
     if (t.hdr->error & kErrInternal) return;
-    const uint64_t U = v.st->U;
     const int h = static_cast<int>(v.st->height);
     if (h < 2) return;
     __shared__ K mk[kSlots * kSlots];
@@ -1355,9 +1356,11 @@ __global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v) {
     __shared__ uint32_t s_next;
     const int lane = static_cast<int>(threadIdx.x);
     const uint64_t lp = static_cast<uint64_t>(h - 2) * v.Bm;  // path level of the leaves' parents
-    for (uint64_t u = blockIdx.x; u < U; u += gridDim.x) {
-        // the first run under its parent that left its leaf below half full
-        if (!leaf_run_head(v, u) || !v.f0[u]) continue;
+    const uint32_t nlist = v.st->merges;
+    for (uint32_t li = blockIdx.x; li < nlist; li += gridDim.x) {
+        // a leaf run that left its leaf below half full; the first such run
+        // under its parent merges that parent
+        const uint64_t u = v.f1[li];
         const uint32_t P = v.pn[lp + u];
         bool first = true;
         for (uint64_t e = u; e-- > 0 && v.pn[lp + e] == P;) {

@@ -401,12 +401,13 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_pass(const K* __restrict__ 
 }
 
 // After the passes: a failed sort's result becomes every key 0, index i at
-// position i (sorted, and a valid permutation).
+// position i (sorted, and a valid permutation).  One workgroup: the check
+// costs one small dispatch, and the rewrite happens only after a failure.
 template <class K>
-__global__ __launch_bounds__(256) void k_sort_fix(K* __restrict__ keys, uint32_t* __restrict__ idx, uint64_t n,
-                                                  const uint32_t* fail) {
+__global__ __launch_bounds__(1024) void k_sort_fix(K* __restrict__ keys, uint32_t* __restrict__ idx, uint64_t n,
+                                                   const uint32_t* fail) {
     if (__hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
-    for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull) {
+    for (uint64_t i = threadIdx.x; i < n; i += 1024) {
         keys[i] = K(0);
         idx[i] = static_cast<uint32_t>(i);
     }
@@ -443,7 +444,7 @@ static void sort_onesweep(const K* src, K* keys, uint32_t* idx, K* keys_alt, uin
         kb = (p & 1) ? keys_alt : keys;
         ib = (p & 1) ? idx_alt : idx;
     }
-    hipLaunchKernelGGL(k_sort_fix<K>, dim3(nt < 256 ? nt : 256), dim3(256), 0, s, keys, idx, n, fail);
+    hipLaunchKernelGGL(k_sort_fix<K>, dim3(1), dim3(1024), 0, s, keys, idx, n, fail);
 }
 
 template <class K>

@@ -169,17 +169,11 @@ gt_status build_t(gt_tree* t, const void* keys, const void* values, uint64_t n, 
 
     gt_status st = GT_OK;
     uint32_t hflag = 0;
-    std::vector<uint32_t> iota(nn);
-    for (uint64_t i = 0; i < nn; ++i) iota[i] = static_cast<uint32_t>(i);
     do {
         if (hipMemsetAsync(dflag, 0, 4, s) != hipSuccess) { st = GT_ERR_HIP; break; }
         if (n) {
-            if (hipMemcpyAsync(sk, keys, n * sizeof(K), hipMemcpyDeviceToDevice, s) != hipSuccess ||
-                hipMemcpyAsync(si, iota.data(), n * 4, hipMemcpyHostToDevice, s) != hipSuccess) {
-                st = GT_ERR_HIP;
-                break;
-            }
-            sort_pairs<K>(sk, si, sk2, si2, n, stmp, s, dflag, 2u);  // bit 0: duplicates (below)
+            // (key, position) pairs sorted by key; positions come from the sort
+            sort_from<K>(reinterpret_cast<const K*>(keys), sk, si, sk2, si2, n, stmp, s, dflag, 2u);  // bit 0: duplicates (below)
             launch_gather<K>(reinterpret_cast<const K*>(values), si, sv, n, s);
             launch_dup_check<K>(sk, n, dflag, s);
         }
