@@ -156,6 +156,25 @@ def test_delete_interleaved_with_inserts(width):
     t.close()
 
 
+@pytest.mark.parametrize("width", [32, 64])
+def test_delete_from_half_full_tree(width):
+    """A bulk load at fill 0.5 leaves every leaf with 8 keys and every inner
+    node with about 8 children, so a single delete leaves a leaf below half
+    full whose parent cannot merge without falling below half full itself:
+    every batch takes the in-place rebuild (at the tree's fill)."""
+    seed = 1700 + width
+    keys = key_set(50000, width, seed, edges=True)
+    vals = synth.values_for(keys, seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, width // 8, fill=0.5, max_batch=8192)
+    for i, B in enumerate((1, 2, 16, 300, 3000, 8192)):
+        allk, _ = sa.items()
+        k = _del_batch(allk, B, seed + 10 * i, width, 0.9)
+        assert np.array_equal(t.delete(k), sa.delete(k)), f"B={B}"
+        _check_all(t, sa, width, seed + i, f"half full, B={B}")
+    t.close()
+
+
 def test_delete_argument_errors():
     import torch
     import paper_2604_21117_amd as g

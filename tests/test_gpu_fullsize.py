@@ -75,3 +75,39 @@ def test_mixed_sample_against_the_oracle(full):
                          ("levelwise", tree.lookup_levelwise(q))):
         assert np.array_equal(f, of), f"{name}: found flags differ at {np.nonzero(f != of)[0][:8]}"
         assert np.array_equal(v, ov), f"{name}: values differ at {np.nonzero(v != ov)[0][:8]}"
+
+
+def test_delete_2p20_on_the_full_tree():
+    """A 2^20-key delete batch on its own 2^24-key tree (the benchmark's
+    shape): every deleted key now misses, a sample of the others still hits
+    with hash(key ^ seed), the count and the exported invariants hold, and
+    the learned index answers through the tree, then from its models again
+    after training."""
+    import paper_2604_21117_amd as g
+    n = 1 << LOG2N
+    keys = synth.uniform_keys(n, SEED, 64)
+    vals = synth.values_for(keys, SEED, 64)
+    tree = g.Tree(keys, vals, 8, max_batch=1 << 20)
+    li = g.Learned(tree, models=1024)
+    li.train()
+    gone = synth.shuffle(keys, SEED + 21)[:1 << 20]
+    st = tree.delete(gone)
+    assert st.all()
+    assert tree.stats()["n_keys"] == n - (1 << 20)
+    assert not tree.delete(gone[:4096]).any()
+    v, f = tree.lookup(gone[:1 << 16])
+    assert not f.any()
+    keep = np.setdiff1d(keys, gone, assume_unique=True)
+    q = synth.shuffle(keep, SEED + 22)[:1 << 16]
+    _closed_form(*tree.lookup(q), q)
+    _closed_form(*li.lookup(q), q)
+    _closed_form(*tree.lookup_levelwise(q), q)
+    bits, ek, _ = oracle.check_export(tree.export(), n - (1 << 20))
+    assert bits == 0, oracle.violations(bits)
+    assert np.array_equal(ek, np.sort(keep))
+    li.train()
+    _closed_form(*li.lookup(q), q)
+    v, f = li.lookup(gone[:1 << 16])
+    assert not f.any()
+    li.close()
+    tree.close()
