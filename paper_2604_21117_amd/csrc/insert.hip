@@ -57,7 +57,8 @@ struct InsState {
     uint32_t deleted;      // delete batch: keys removed
     uint32_t rebuild;      // delete batch: a parent would fall below half full
     uint32_t merges;       // delete batch: leaf runs left below half full (listed in f1)
-    uint32_t pad[4];
+    uint32_t gmerges;      // delete batch: parents that would fall below half full (listed in upos)
+    uint32_t pad[3];
 };
 
 template <class K>
@@ -1395,7 +1396,12 @@ __global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v) {
         const uint32_t T = pre[kSlots];
         const bool root = h == 2;
         if (!root && T < kHalf * kHalf) {
-            if (lane == 0) atomicOr(&v.st->rebuild, 1u);
+            // the parent would fall below half full: its grandparent merges
+            // it with its siblings (marked 2, listed for the next kernel)
+            if (lane == 0) {
+                v.f0[u] = 2u;
+                v.upos[atomicAdd(&v.st->gmerges, 1u)] = static_cast<uint32_t>(u);
+            }
             __syncthreads();
             continue;
         }
@@ -1466,6 +1472,159 @@ __global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v) {
     }
 }
 
+// One level up: a leaf parent that would fall below half full (fewer than
+// 64 keys) is merged with its siblings.  One workgroup per grandparent G
+// gathers every pair below G (at most 16 x 16 x 16) in LDS and lays them out
+// again over n1 = max(8, ceil(T / 256)) of G's parents and
+// n0 = max(8 n1, ceil(T / 16)) of its leaves, reusing old ids in key order
+// (a subtree that was at least half full has enough of both).  A root G
+// keeps at least two parents, or the tree loses levels: one parent as root
+// at T <= 256, one leaf at T <= 16.  A G left with fewer than 512 keys would
+// itself fall below half full; the host rebuilds the tree instead.
+constexpr int kBelowG = kSlots * kSlots * kSlots;
+
+template <class K>
+__global__ __launch_bounds__(1024) void k_del_merge2(TreeView<K> t, Ins<K> v) {
+    if (t.hdr->error & kErrInternal) return;
+    const int h = static_cast<int>(v.st->height);
+    if (h < 3) return;
+    __shared__ K mk[kBelowG];
+    __shared__ K mv[kBelowG];
+    __shared__ uint32_t lid[kSlots * kSlots];  // G's leaves in key order
+    __shared__ uint32_t pid[kSlots];           // G's parents in order
+    __shared__ uint32_t sh[33];
+    __shared__ uint32_t s_first, s_next;
+    const int tid = static_cast<int>(threadIdx.x);
+    const uint64_t lg = static_cast<uint64_t>(h - 3) * v.Bm;  // path level of the grandparents
+    const uint32_t nlist = v.st->gmerges;
+    for (uint32_t li = blockIdx.x; li < nlist; li += gridDim.x) {
+        const uint64_t u = v.upos[li];
+        const uint32_t G = v.pn[lg + u];
+        if (tid == 0) {
+            // the first marked run under G merges it
+            uint32_t first = 1;
+            for (uint64_t e = u; e-- > 0 && v.pn[lg + e] == G;) {
+                if (leaf_run_head(v, e) && v.f0[e] == 2u) {
+                    first = 0;
+                    break;
+                }
+            }
+            s_first = first;
+        }
+        __syncthreads();
+        const bool first = s_first != 0;
+        __syncthreads();
+        if (!first) continue;
+        const uint32_t gc = v.pc[lg + u];
+        // thread (p, l), tid < 256: leaf l of parent p, from the child lines
+        uint32_t lref = kNone, lc = 0;
+        if (tid < kSlots * kSlots) {
+            const uint32_t p = static_cast<uint32_t>(tid) / kSlots, l = static_cast<uint32_t>(tid) % kSlots;
+            if (p < gc) {
+                const uint32_t P = t.ichild[static_cast<uint64_t>(G) * kSlots + p];
+                if (l == 0) pid[p] = P;
+                const uint32_t r = t.ichild[static_cast<uint64_t>(P) * kSlots + l];
+                if (r != kNone) {
+                    lref = r & ~kLeafTag;
+                    const uint32_t c = t.lmeta[lref].x;
+                    lc = c < kSlots ? c : kSlots;
+                }
+            }
+        }
+        uint32_t nleaf, T;
+        const uint32_t lpos = block_excl_scan<uint32_t>(lref != kNone ? 1u : 0u, sh, &nleaf);
+        const uint32_t kpos = block_excl_scan<uint32_t>(lc, sh, &T);
+        if (lref != kNone) {
+            lid[lpos] = lref;
+            const uint64_t src = static_cast<uint64_t>(lref) * kSlots;
+            for (uint32_t j = 0; j < lc; ++j) {
+                mk[kpos + j] = t.lkeys[src + j];
+                mv[kpos + j] = t.lvals[src + j];
+            }
+        }
+        __syncthreads();
+        if (tid == 0) s_next = nleaf ? t.lmeta[lid[nleaf - 1]].y : kNone;
+        const bool root = h == 3;
+        uint32_t n1, n0;
+        const uint32_t w0 = (T + kSlots - 1) / kSlots, w1 = (T + kSlots * kSlots - 1) / (kSlots * kSlots);
+        if (root && T <= kSlots) {
+            n1 = 0;
+            n0 = 1;
+        } else if (root && T <= kSlots * kSlots) {
+            n1 = 1;
+            n0 = w0 > 2u ? w0 : 2u;
+        } else {
+            n1 = w1 > (root ? 2u : kHalf) ? w1 : (root ? 2u : kHalf);
+            n0 = w0 > kHalf * n1 ? w0 : kHalf * n1;
+        }
+        const bool fail = (!root && T < kHalf * kHalf * kHalf) || n1 > gc || n0 > nleaf;
+        __syncthreads();
+        if (fail) {
+            if (tid == 0) atomicOr(&v.st->rebuild, 1u);
+            __syncthreads();
+            continue;
+        }
+        // leaves: leaf j (j < n0) takes pairs [j q0 + min(j, r0), + len)
+        const uint32_t q0 = T / n0, r0 = T % n0;
+        auto leaf_end = [&](uint32_t j) { return (j + 1) * q0 + (j + 1 < r0 ? j + 1 : r0); };
+        if (static_cast<uint32_t>(tid) < nleaf) {
+            const uint32_t j = static_cast<uint32_t>(tid);
+            const uint64_t dst = static_cast<uint64_t>(lid[j]) * kSlots;
+            if (j < n0) {
+                const uint32_t start = j * q0 + (j < r0 ? j : r0), len = leaf_end(j) - start;
+                for (uint32_t s2 = 0; s2 < kSlots; ++s2) {
+                    t.lkeys[dst + s2] = s2 < len ? mk[start + s2] : (len ? mk[start + len - 1] : kmax<K>());
+                    t.lvals[dst + s2] = s2 < len ? mv[start + s2] : kmax<K>();
+                }
+                t.lmeta[lid[j]] = make_uint2(len, j + 1 < n0 ? lid[j + 1] : s_next);
+            } else {
+                for (uint32_t s2 = 0; s2 < kSlots; ++s2) {
+                    t.lkeys[dst + s2] = kmax<K>();
+                    t.lvals[dst + s2] = kmax<K>();
+                }
+                t.lmeta[lid[j]] = make_uint2(0u, kNone);
+            }
+        }
+        // parents: parent i (i < n1) takes leaves [i q1 + min(i, r1), + c)
+        const uint32_t q1 = n1 ? n0 / n1 : 0, r1 = n1 ? n0 % n1 : 0;
+        auto par_first = [&](uint32_t i) { return i * q1 + (i < r1 ? i : r1); };
+        if (n1 && tid < kSlots * kSlots) {
+            const uint32_t i = static_cast<uint32_t>(tid) / kSlots, s2 = static_cast<uint32_t>(tid) % kSlots;
+            if (i < n1) {
+                const uint32_t a = par_first(i), c = par_first(i + 1) - a;
+                const uint64_t P = pid[i];
+                t.ichild[P * kSlots + s2] = s2 < c ? (lid[a + s2] | kLeafTag) : kNone;
+                t.ikeys[P * kSlots + s2] = s2 + 1 < c ? mk[leaf_end(a + s2) - 1] : kmax<K>();
+            }
+        }
+        if (n1 >= 2 && tid < kSlots) {
+            const uint32_t s2 = static_cast<uint32_t>(tid);
+            t.ichild[static_cast<uint64_t>(G) * kSlots + s2] = s2 < n1 ? pid[s2] : kNone;
+            t.ikeys[static_cast<uint64_t>(G) * kSlots + s2] =
+                s2 + 1 < n1 ? mk[leaf_end(par_first(s2 + 1) - 1) - 1] : kmax<K>();
+        }
+        if (tid == 0) {
+            if (root && n1 == 0) {
+                t.hdr->root = lid[0] | kLeafTag;
+                t.hdr->height = 1;
+            } else if (root && n1 == 1) {
+                t.hdr->root = pid[0];
+                t.hdr->height = 2;
+            } else if (!root) {
+                const K top = mk[T - 1];
+                for (int l = h - 4; l >= 0; --l) {
+                    const uint64_t o2 = static_cast<uint64_t>(l) * v.Bm + u;
+                    if (v.pi[o2] + 1u < v.pc[o2]) {
+                        t.ikeys[static_cast<uint64_t>(v.pn[o2]) * kSlots + v.pi[o2]] = top;
+                        break;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <class K>
 __global__ void k_del_commit(TreeView<K> t, Ins<K> v) {
     if (t.hdr->error & kErrInternal) return;
@@ -1506,6 +1665,7 @@ const uint32_t* launch_delete(const TreeView<K>& t, const InsertCtx& c, const K*
     hipLaunchKernelGGL(k_del_leaf<K>, dim3(gB), dim3(kBlk), 0, s, t, v);
     const uint32_t gm = B < 4096 ? static_cast<uint32_t>(B) : 4096u;
     hipLaunchKernelGGL(k_del_merge<K>, dim3(gm), dim3(64), 0, s, t, v);
+    hipLaunchKernelGGL(k_del_merge2<K>, dim3(B < 256 ? static_cast<uint32_t>(B) : 256u), dim3(1024), 0, s, t, v);
     hipLaunchKernelGGL(k_del_commit<K>, dim3(1), dim3(1), 0, s, t, v);
     launch_mirror_refresh<K>(t, s);
     return &v.st->rebuild;

@@ -175,6 +175,33 @@ def test_delete_from_half_full_tree(width):
     t.close()
 
 
+@pytest.mark.parametrize("width", [32, 64])
+def test_delete_grandparent_merges_and_root_shrink(width):
+    """A height-3 tree at fill 0.5: a delete leaves a leaf parent below 64
+    keys, so the root (the grandparent) merges its parents.  Deleting down
+    to 200 keys leaves one parent as the root (height 2), down to 10 keys
+    one leaf (height 1)."""
+    seed = 1800 + width
+    keys = key_set(800, width, seed, edges=True)  # 100 leaves of 8, 12 parents, a root
+    vals = synth.values_for(keys, seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, width // 8, fill=0.5, max_batch=4096)
+    assert t.stats()["height"] == 3
+    for i, B in enumerate((1, 5, 40)):
+        allk, _ = sa.items()
+        k = _del_batch(allk, B, seed + 10 * i, width, 1.0)
+        assert np.array_equal(t.delete(k), sa.delete(k)), f"B={B}"
+        _check_all(t, sa, width, seed + i, f"grandparent, B={B}")
+    assert t.stats()["height"] == 3
+    for left, height in ((200, 2), (10, 1)):
+        allk, _ = sa.items()
+        k = synth.shuffle(allk, seed + left)[: len(allk) - left]
+        assert t.delete(k).all() and sa.delete(k).all()
+        _check_all(t, sa, width, seed + left, f"down to {left}")
+        assert t.stats()["height"] == height, f"down to {left}"
+    t.close()
+
+
 def test_delete_argument_errors():
     import torch
     import paper_2604_21117_amd as g
