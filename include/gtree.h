@@ -191,9 +191,12 @@ gt_status tree_insert_batch(gt_tree* t, const void* keys, const void* values, ui
  * the root stays at least half full (Section III): a leaf left with fewer
  * than 8 keys is merged with its siblings (the parent's keys are spread
  * evenly over as few of its leaves as hold them at least half full, at
- * least 8 of them), a root with two leaves shrinks to one leaf when 16 keys
- * or fewer remain, and when a parent would itself fall below half full the
- * tree is rebuilt in place from its keys (as tree_build, bulk load, height
+ * least 8 of them), a parent that would itself fall below half full is
+ * merged with its siblings (the grandparent's keys, at most 4096, laid out
+ * again over as few of its parents and leaves as keep both at least half
+ * full), the root loses levels when few keys remain (one parent, then one
+ * leaf), and when a grandparent would fall below half full the tree is
+ * rebuilt in place from its keys (as tree_build, bulk load, height
  * recomputed).  Leaves and inner nodes a merge gives up are not reused by
  * later inserts (the pools only grow until the next tree_build).  Like an
  * insert, a batch is not applied while the device error word holds
