@@ -1295,55 +1295,89 @@ __device__ __forceinline__ bool leaf_run_head(const Ins<K>& v, uint64_t u) {
     return u == 0 || v.uleaf[u - 1] != v.uleaf[u];
 }
 
+// 16 lanes per touched leaf, lane s on slot s: the lanes read the run's
+// distinct keys 16 at a time for the slots to remove, then move the kept
+// pairs down (new slot = kept slots below) and pad the rest.  The deleted
+// count is added once per wave at the end (one atomic per leaf on a single
+// address would serialise); k_del_list then lists the leaves left below
+// half full, one thread per distinct key.
 template <class K>
 __global__ __launch_bounds__(kBlk) void k_del_leaf(TreeView<K> t, Ins<K> v) {
     if (t.hdr->error & kErrInternal) return;  // e.g. the batch's device sort gave up
     const uint64_t U = v.st->U;
     const int h = static_cast<int>(v.st->height);
-    for (uint64_t u = gtid(); u < U; u += gstride()) {
-        if (!leaf_run_head(v, u)) continue;
-        const uint32_t leaf = v.uleaf[u];
-        uint32_t gone = 0, nd = 0;
-        for (uint64_t e = u; e < U && v.uleaf[e] == leaf; ++e) {
-            if (v.ufound[e]) {
-                gone |= 1u << v.uslot[e];
-                ++nd;
+    const int lane = static_cast<int>(threadIdx.x) & 63, s = lane & (kSlots - 1), gbase = lane - s;
+    const uint64_t g0 = gtid() / kSlots, gs = gstride() / kSlots;
+    uint32_t del = 0;  // keys this group removed (lane 0 of the group)
+    for (uint64_t u = g0;; u += gs) {
+        if (__ballot(u < U) == 0) break;  // the wave's four groups are done
+        const bool head = u < U && leaf_run_head(v, u);  // the same for the group's 16 lanes
+        if (head) {
+            const uint32_t leaf = v.uleaf[u];
+            uint32_t gone = 0, nd = 0;
+            for (uint64_t e0 = u;; e0 += kSlots) {
+                const uint64_t e = e0 + static_cast<uint64_t>(s);
+                const bool in = e < U && v.uleaf[e] == leaf;
+                const bool hit = in && v.ufound[e];
+                uint32_t bit = hit ? (1u << v.uslot[e]) : 0u;
+                bit |= __shfl_xor(bit, 1);
+                bit |= __shfl_xor(bit, 2);
+                bit |= __shfl_xor(bit, 4);
+                bit |= __shfl_xor(bit, 8);
+                gone |= bit;
+                nd += static_cast<uint32_t>(__popcll((__ballot(hit) >> gbase) & 0xFFFFull));
+                if (((__ballot(in) >> gbase) & 0xFFFFull) != 0xFFFFull) break;  // the run ended in this round
             }
-        }
-        const uint32_t c = t.lmeta[leaf].x;
-        const uint32_t w = c - nd;
-        const bool under = h > 1 && w < kHalf;
-        v.f0[u] = under ? 1u : 0u;
-        if (under) v.f1[atomicAdd(&v.st->merges, 1u)] = static_cast<uint32_t>(u);  // list for the merge pass
-        if (nd == 0) continue;
-        K* kl = t.lkeys + static_cast<uint64_t>(leaf) * kSlots;
-        K* vl = t.lvals + static_cast<uint64_t>(leaf) * kSlots;
-        uint32_t o = 0;
-        for (uint32_t i = 0; i < c; ++i) {
-            if ((gone >> i) & 1u) continue;
-            if (o != i) {
-                kl[o] = kl[i];
-                vl[o] = vl[i];
-            }
-            ++o;
-        }
-        const K pk = w ? kl[w - 1] : kmax<K>();
-        for (uint32_t i = w; i < kSlots; ++i) {
-            kl[i] = pk;
-            vl[i] = kmax<K>();
-        }
-        t.lmeta[leaf].x = w;
-        atomicAdd(&v.st->deleted, nd);
-        if (!under && w > 0 && ((gone >> (c - 1)) & 1u)) {
-            for (int l = h - 2; l >= 0; --l) {
-                const uint64_t o2 = static_cast<uint64_t>(l) * v.Bm + u;
-                if (v.pi[o2] + 1u < v.pc[o2]) {
-                    t.ikeys[static_cast<uint64_t>(v.pn[o2]) * kSlots + v.pi[o2]] = pk;
-                    break;
+            const uint32_t c = t.lmeta[leaf].x;
+            const uint32_t w = c - nd;
+            const bool under = h > 1 && w < kHalf;
+            if (s == 0) v.f0[u] = under ? 1u : 0u;
+            if (nd) {
+                K* kl = t.lkeys + static_cast<uint64_t>(leaf) * kSlots;
+                K* vl = t.lvals + static_cast<uint64_t>(leaf) * kSlots;
+                const K key = kl[s], val = vl[s];
+                const bool keep = static_cast<uint32_t>(s) < c && !((gone >> s) & 1u);
+                const uint32_t km = static_cast<uint32_t>((__ballot(keep) >> gbase) & 0xFFFFull);
+                const uint32_t at = static_cast<uint32_t>(__popc(km & ((1u << s) - 1u)));
+                // the new largest key: from the highest kept slot
+                const int top = km ? 31 - __clz(km) : 0;
+                const K pk = km ? static_cast<K>(__shfl(key, gbase + top, 64)) : kmax<K>();
+                if (keep) {
+                    kl[at] = key;
+                    vl[at] = val;
+                }
+                if (static_cast<uint32_t>(s) >= w) {
+                    kl[s] = pk;
+                    vl[s] = kmax<K>();
+                }
+                if (s == 0) {
+                    t.lmeta[leaf].x = w;
+                    del += nd;
+                    if (!under && w > 0 && ((gone >> (c - 1)) & 1u)) {
+                        for (int l = h - 2; l >= 0; --l) {
+                            const uint64_t o2 = static_cast<uint64_t>(l) * v.Bm + u;
+                            if (v.pi[o2] + 1u < v.pc[o2]) {
+                                t.ikeys[static_cast<uint64_t>(v.pn[o2]) * kSlots + v.pi[o2]] = pk;
+                                break;
+                            }
+                        }
+                    }
                 }
             }
         }
     }
+    // one add per wave
+    for (int o = 32; o > 0; o >>= 1) del += static_cast<uint32_t>(__shfl_xor(static_cast<int>(del), o));
+    if (lane == 0 && del) atomicAdd(&v.st->deleted, del);
+}
+
+// The leaf runs left below half full, listed for the merge pass.
+template <class K>
+__global__ void k_del_list(TreeView<K> t, Ins<K> v) {
+    if (t.hdr->error & kErrInternal) return;
+    const uint64_t U = v.st->U;
+    for (uint64_t u = gtid(); u < U; u += gstride())
+        if (leaf_run_head(v, u) && v.f0[u] == 1u) v.f1[atomicAdd(&v.st->merges, 1u)] = static_cast<uint32_t>(u);
 }
 
 template <class K>
@@ -1662,8 +1696,10 @@ const uint32_t* launch_delete(const TreeView<K>& t, const InsertCtx& c, const K*
     scan_exclusive<uint32_t>(v.f0, v.f1, &v.st->U, nullptr, B, v.scan_tmp, s);
     hipLaunchKernelGGL(k_del_unique<K>, dim3(gB), dim3(kBlk), 0, s, v, B);
     launch_locate<K>(t, v, c.cfg, B, status, s);
-    hipLaunchKernelGGL(k_del_leaf<K>, dim3(gB), dim3(kBlk), 0, s, t, v);
-    const uint32_t gm = B < 4096 ? static_cast<uint32_t>(B) : 4096u;
+    const uint64_t gl = grid_for(B * kSlots, kBlk);
+    hipLaunchKernelGGL(k_del_leaf<K>, dim3(gl < 65536 ? static_cast<uint32_t>(gl) : 65536u), dim3(kBlk), 0, s, t, v);
+    hipLaunchKernelGGL(k_del_list<K>, dim3(gB), dim3(kBlk), 0, s, t, v);
+    const uint32_t gm = B < 16384 ? static_cast<uint32_t>(B) : 16384u;
     hipLaunchKernelGGL(k_del_merge<K>, dim3(gm), dim3(64), 0, s, t, v);
     hipLaunchKernelGGL(k_del_merge2<K>, dim3(B < 256 ? static_cast<uint32_t>(B) : 256u), dim3(1024), 0, s, t, v);
     hipLaunchKernelGGL(k_del_commit<K>, dim3(1), dim3(1), 0, s, t, v);
