@@ -401,13 +401,16 @@ typedef struct {
                                 the index (li_train); 0 = never; at most 40 */
 } gt_srv_params;
 
-enum { GT_OP_LOOKUP = 0, GT_OP_INSERT = 1, GT_OP_RANGE = 2 };
+enum { GT_OP_LOOKUP = 0, GT_OP_INSERT = 1, GT_OP_RANGE = 2, GT_OP_DELETE = 3 };
 enum { GT_REQ_QUEUED = 0, GT_REQ_INFLIGHT = 1, GT_REQ_DONE = 2, GT_REQ_REFUSED = 3 };
 
 /* One batch; every pointer is HOST memory owned by the caller until the
  * request is done.  lookup: keys -> out0 (values), out1 (found, u8);
  * insert: keys, values -> out0 (status, u8); range: keys (lo), values (hi),
- * max_out -> out0 (keys), out1 (values) in CSR order of max_out, count_out. */
+ * max_out -> out0 (keys), out1 (values) in CSR order of max_out, count_out;
+ * delete: keys -> out0 (status, u8).  Inserts and deletes are writes: each
+ * sees every batch admitted before it.  A delete batch runs outside the
+ * captured graphs (tree_delete_batch synchronises). */
 typedef struct {
     uint32_t op;
     uint32_t B;
@@ -421,13 +424,13 @@ typedef struct {
 } gt_request;
 
 typedef struct {
-    uint64_t done[3];        /* batches completed per op                    */
-    uint64_t ops[3];         /* keys (lookup, insert) / ranges completed    */
+    uint64_t done[4];        /* batches completed per op (GT_OP_*)          */
+    uint64_t ops[4];         /* keys (lookup, insert, delete) / ranges done */
     uint64_t refused;
     uint64_t graph_launches, direct_launches;
     double wall_s;           /* first arrival to last completion            */
     double p50_us, p99_us;   /* arrival -> completion latency, all batches  */
-    double p50_us_op[3], p99_us_op[3];
+    double p50_us_op[4], p99_us_op[4];  /* per op, indexed by GT_OP_*   */
     double busy_frac;        /* share of wall_s in which the device worked on
                                 at least one batch (copies included), from
                                 timing events around each batch              */

@@ -72,14 +72,14 @@ class gt_request(C.Structure):
 
 
 class gt_srv_stats(C.Structure):
-    _fields_ = [("done", C.c_uint64 * 3), ("ops", C.c_uint64 * 3), ("refused", C.c_uint64),
+    _fields_ = [("done", C.c_uint64 * 4), ("ops", C.c_uint64 * 4), ("refused", C.c_uint64),
                 ("graph_launches", C.c_uint64), ("direct_launches", C.c_uint64), ("wall_s", C.c_double),
-                ("p50_us", C.c_double), ("p99_us", C.c_double), ("p50_us_op", C.c_double * 3),
-                ("p99_us_op", C.c_double * 3), ("busy_frac", C.c_double), ("retrains", C.c_uint64),
+                ("p50_us", C.c_double), ("p99_us", C.c_double), ("p50_us_op", C.c_double * 4),
+                ("p99_us_op", C.c_double * 4), ("busy_frac", C.c_double), ("retrains", C.c_uint64),
                 ("retrain_s", C.c_double)]
 
 
-OP_LOOKUP, OP_INSERT, OP_RANGE = 0, 1, 2
+OP_LOOKUP, OP_INSERT, OP_RANGE, OP_DELETE = 0, 1, 2, 3
 REQ_QUEUED, REQ_INFLIGHT, REQ_DONE, REQ_REFUSED = 0, 1, 2, 3
 
 _lib = None
@@ -501,7 +501,7 @@ class Batch:
         if op == OP_LOOKUP:
             self.out0 = np.empty(B, dtype=dt)
             self.out1 = np.empty(B, dtype=np.uint8)
-        elif op == OP_INSERT:
+        elif op in (OP_INSERT, OP_DELETE):
             self.out0 = np.empty(B, dtype=np.uint8)
             self.out1 = None
         else:

@@ -125,6 +125,7 @@ uint64_t staged_bytes(const gt_server* s, const gt_request& r, uint32_t bucket, 
     switch (r.op) {
         case GT_OP_LOOKUP: return bucket * (2 * kb + 1);
         case GT_OP_INSERT: return bucket * (2 * kb + 1);
+        case GT_OP_DELETE: return bucket * (kb + 1);
         default: return bucket * (2 * kb + 4 + 8 + 4) + outn * 2 * kb;
     }
 }
@@ -148,6 +149,9 @@ void stage_inputs(gt_server* s, Slot& sl, const gt_request& r, uint32_t bucket, 
             memcpy(sl.h_keys + i * kb, sl.h_keys + (r.B - 1) * kb, kb);
             memcpy(sl.h_vals + i * kb, sl.h_vals + (r.B - 1) * kb, kb);
         }
+    } else if (r.op == GT_OP_DELETE) {
+        // padding repeats the last key: deleted once, statuses ignored
+        for (uint32_t i = r.B; i < bucket; ++i) memcpy(sl.h_keys + i * kb, sl.h_keys + (r.B - 1) * kb, kb);
     } else {
         memcpy(sl.h_vals, r.values, r.B * kb);
         uint64_t off = 0;
@@ -186,6 +190,11 @@ hipError_t enqueue_ops(gt_server* s, Slot& sl, uint32_t op, uint32_t bucket, uin
         if (tree_insert_batch(s->t, sl.d_keys, sl.d_vals, bucket, sl.d_flag, st) != GT_OK) return hipErrorUnknown;
         if ((e = hipMemcpyAsync(sl.h_flag, sl.d_flag, bucket, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
         if ((e = hipMemcpyAsync(sl.h_err, &s->t->hdr->error, 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    } else if (op == GT_OP_DELETE) {
+        gt::launch_clear_error(s->t->hdr, st);
+        if (tree_delete_batch(s->t, sl.d_keys, bucket, sl.d_flag, st) != GT_OK) return hipErrorUnknown;
+        if ((e = hipMemcpyAsync(sl.h_flag, sl.d_flag, bucket, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(sl.h_err, &s->t->hdr->error, 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     } else {
         if ((e = hipMemcpyAsync(sl.d_vals, sl.h_vals, bucket * kb, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
         if ((e = hipMemcpyAsync(sl.d_max, sl.h_max, bucket * 4, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
@@ -204,7 +213,7 @@ hipError_t enqueue_ops(gt_server* s, Slot& sl, uint32_t op, uint32_t bucket, uin
 
 hipError_t launch(gt_server* s, Slot& sl, uint32_t op, uint32_t bucket, uint64_t outn, hipStream_t st) {
     const bool graphs = s->p.use_graphs != 2;
-    if (!graphs) {
+    if (!graphs || op == GT_OP_DELETE) {  // a delete synchronises: never captured
         s->direct_launches++;
         return enqueue_ops(s, sl, op, bucket, outn, st);
     }
@@ -250,7 +259,7 @@ void retire(gt_server* s, Slot& sl, Req& q) {
     if (r.op == GT_OP_LOOKUP) {
         memcpy(r.out0, sl.h_out0, r.B * kb);
         memcpy(r.out1, sl.h_flag, r.B);
-    } else if (r.op == GT_OP_INSERT) {
+    } else if (r.op == GT_OP_INSERT || r.op == GT_OP_DELETE) {
         memcpy(r.out0, sl.h_flag, r.B);
         q.failed = *sl.h_err != 0;
     } else {
@@ -273,7 +282,9 @@ void worker_loop(gt_server* s) {
             if (hipEventQuery(sl.ev) != hipSuccess) continue;
             Req& q = s->reqs[sl.ticket];
             retire(s, sl, q);
-            if (q.r.op == GT_OP_INSERT && !q.failed && s->li && s->p.retrain_log2) {
+            // deleted keys count too: after a delete the index answers
+            // through the tree until it is trained again
+            if ((q.r.op == GT_OP_INSERT || q.r.op == GT_OP_DELETE) && !q.failed && s->li && s->p.retrain_log2) {
                 s->inserted_since_train += q.r.B;
                 if (s->inserted_since_train >= (1ull << s->p.retrain_log2)) s->retrain_pending = true;
             }
@@ -335,7 +346,8 @@ void worker_loop(gt_server* s) {
             Slot& sl = s->slots[free_slot];
             stage_inputs(s, sl, q.r, bucket, outn);
             hipStream_t st;
-            if (q.r.op == GT_OP_INSERT) {
+            const bool write = q.r.op == GT_OP_INSERT || q.r.op == GT_OP_DELETE;
+            if (write) {
                 st = s->wstream;
                 for (hipEvent_t e : s->reads_since_write) hipStreamWaitEvent(st, e, 0);
                 s->reads_since_write.clear();
@@ -351,7 +363,7 @@ void worker_loop(gt_server* s) {
             if (e == hipSuccess) e = hipEventRecord(sl.ev0, st);
             if (e == hipSuccess) e = launch(s, sl, q.r.op, bucket, outn, st);
             if (e == hipSuccess) e = hipEventRecord(sl.ev, st);
-            if (e == hipSuccess && q.r.op == GT_OP_INSERT) {
+            if (e == hipSuccess && write) {
                 e = hipEventRecord(s->wev, st);
                 s->have_write = true;
             } else if (e == hipSuccess) {
@@ -435,9 +447,9 @@ double percentile(std::vector<double> v, double q) {
 
 gt_status submit_at(gt_server* s, const gt_request* r, double arrival, uint64_t* ticket) {
     if (!s || !r || !ticket) return GT_ERR_INVALID;
-    if (r->op > GT_OP_RANGE || r->B == 0 || r->B > s->p.max_batch || !r->keys || !r->out0) return GT_ERR_INVALID;
-    if ((r->op != GT_OP_RANGE && r->op == GT_OP_LOOKUP && !r->out1) ||
-        (r->op != GT_OP_LOOKUP && !r->values) || (r->op == GT_OP_RANGE && (!r->max_out || !r->out1 || !r->count_out)))
+    if (r->op > GT_OP_DELETE || r->B == 0 || r->B > s->p.max_batch || !r->keys || !r->out0) return GT_ERR_INVALID;
+    if ((r->op == GT_OP_LOOKUP && !r->out1) || ((r->op == GT_OP_INSERT || r->op == GT_OP_RANGE) && !r->values) ||
+        (r->op == GT_OP_RANGE && (!r->max_out || !r->out1 || !r->count_out)))
         return GT_ERR_INVALID;
     if (r->op == GT_OP_RANGE)
         for (uint32_t i = 0; i < r->B; ++i)
@@ -569,7 +581,7 @@ gt_status srv_stats(gt_server* s, gt_srv_stats* out) {
     if (!s || !out) return GT_ERR_INVALID;
     std::lock_guard<std::mutex> lk(s->mu);
     memset(out, 0, sizeof *out);
-    std::vector<double> all, per[3];
+    std::vector<double> all, per[4];
     std::vector<std::pair<float, float>> busy;
     double first = 1e300, last = 0;
     const std::vector<uint64_t>& ids = s->last_replay;
@@ -596,7 +608,7 @@ gt_status srv_stats(gt_server* s, gt_srv_stats* out) {
     out->wall_s = all.empty() ? 0.0 : last - first;
     out->p50_us = percentile(all, 0.5);
     out->p99_us = percentile(all, 0.99);
-    for (int o = 0; o < 3; ++o) {
+    for (int o = 0; o < 4; ++o) {
         out->p50_us_op[o] = percentile(per[o], 0.5);
         out->p99_us_op[o] = percentile(per[o], 0.99);
     }

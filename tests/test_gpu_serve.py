@@ -1,4 +1,4 @@
-"""Serving runtime: a mix of lookup / insert / range batches admitted while
+"""Serving runtime: a mix of lookup / insert / range / delete batches admitted while
 others run gives, for every batch, exactly the result of applying the
 batches one at a time in admission order (checked against the oracle and
 against the same batches run alone); graphs and direct launches agree;
@@ -32,6 +32,8 @@ def _oracle_replay(sa, batches):
             exp.append(sa.lookup(b.keys))
         elif b.op == 1:
             exp.append((sa.insert(b.keys, b.values),))
+        elif b.op == 3:
+            exp.append((sa.delete(b.keys),))
         else:
             exp.append(sa.range(b.keys, b.values, b.max_out))
     return exp
@@ -41,8 +43,8 @@ def _compare(batches, exp):
     for i, (b, e) in enumerate(zip(batches, exp)):
         if b.op == 0:
             assert np.array_equal(b.out1, e[1]) and np.array_equal(b.out0, e[0]), f"lookup batch {i}"
-        elif b.op == 1:
-            assert np.array_equal(b.out0, e[0]), f"insert batch {i}"
+        elif b.op in (1, 3):
+            assert np.array_equal(b.out0, e[0]), f"{'insert' if b.op == 1 else 'delete'} batch {i}"
         else:
             cnt, off, ok, ov = e
             assert np.array_equal(b.count, cnt), f"range batch {i} counts"
@@ -84,6 +86,52 @@ def test_mix_equals_sequential(graphs):
     srv.close()
     bits, ek, ev = oracle.check_export(t.export(), len(sa))
     assert bits == 0 and np.array_equal(ek, sa.keys) and np.array_equal(ev, sa.vals)
+
+
+@pytest.mark.parametrize("graphs,learned", [(1, False), (2, False), (1, True)])
+def test_mix_with_deletes_equals_sequential(graphs, learned):
+    """Every tenth batch of the mix becomes a delete of present (and some
+    absent, some repeated) keys: reads and writes still see exactly the
+    batches admitted before them; a learned index answers through the tree
+    after a delete until the server retrains it."""
+    import paper_2604_21117_amd as g
+    seed = 70 + graphs + (10 if learned else 0)
+    keys, vals, fresh = _setup(seed)
+    t = mk_tree(keys, vals, 8, leaf_slack=1 << 15, max_batch=1024)
+    li = None
+    if learned:
+        li = g.Learned(t, models=256)
+        li.train()
+    srv = g.Server(t, li, use_graphs=graphs, slots=8, read_streams=4, max_range=128,
+                   retrain_log2=14 if learned else 0)
+    spec = synth.serving_mix(keys, 600, seed, bmax=300, rate=40000.0, zipf=synth.Zipf(len(keys), 0.99, seed),
+                             fresh=fresh)
+    rng = np.random.default_rng(seed)
+    pool = np.concatenate([keys, fresh[:20000]])
+    for i in range(5, len(spec), 10):
+        B = int(rng.integers(1, 300))
+        dk = pool[rng.integers(0, len(pool), B)]
+        if B > 4:
+            dk[:2] = dk[2]  # repeated in the batch
+        spec[i] = (3, dk, None, None, spec[i][4])
+    batches = _batches(spec)
+    assert srv.replay(batches) == g.GT_OK
+    sa = oracle.SortedArray(keys, vals, 64)
+    _compare(batches, _oracle_replay(sa, batches))
+    st = srv.stats()
+    assert sum(st["done"]) == len(batches) and st["refused"] == 0 and st["done"][3] == len(range(5, len(spec), 10))
+    if graphs == 1:
+        assert st["direct_launches"] >= st["done"][3]  # deletes are never captured
+    srv.close()
+    bits, ek, ev = oracle.check_export(t.export(), len(sa))
+    assert bits == 0 and np.array_equal(ek, sa.keys) and np.array_equal(ev, sa.vals)
+    if li is not None:
+        q = synth.mixed_queries(sa.items()[0], 4000, seed, 64)
+        ov, of = sa.lookup(q)
+        lv, lf = li.lookup(q)
+        assert np.array_equal(lf, of) and np.array_equal(lv, ov)
+        li.close()
+    t.close()
 
 
 def test_alone_equals_in_mix():
