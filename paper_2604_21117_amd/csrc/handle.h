@@ -32,6 +32,7 @@ struct gt_tree {
                             // after an insert, the most the pool sizes allow)
     uint64_t inserts = 0;   // insert batches enqueued on this tree
     uint64_t deletes = 0;   // delete batches applied to this tree
+    uint32_t* h_flag = nullptr;  // pinned host word a delete reads its rebuild flag into
 };
 
 

@@ -1268,6 +1268,7 @@ template void launch_insert<uint64_t>(const TreeView<uint64_t>&, const InsertCtx
 //     keys.
 
 constexpr uint32_t kHalf = kSlots / 2;
+constexpr uint64_t kDelListScan = 16384;  // above: the merge list comes from a scan, in key order
 
 template <class K>
 __global__ void k_del_heads(Ins<K> v, uint64_t B, uint8_t* __restrict__ status) {
@@ -1312,6 +1313,7 @@ __global__ __launch_bounds__(kBlk) void k_del_leaf(TreeView<K> t, Ins<K> v) {
     for (uint64_t u = g0;; u += gs) {
         if (__ballot(u < U) == 0) break;  // the wave's four groups are done
         const bool head = u < U && leaf_run_head(v, u);  // the same for the group's 16 lanes
+        if (u < U && s == 0) v.nu[u] = 0u;  // set to 1 below for a run left below half full
         if (head) {
             const uint32_t leaf = v.uleaf[u];
             uint32_t gone = 0, nd = 0;
@@ -1331,7 +1333,10 @@ __global__ __launch_bounds__(kBlk) void k_del_leaf(TreeView<K> t, Ins<K> v) {
             const uint32_t c = t.lmeta[leaf].x;
             const uint32_t w = c - nd;
             const bool under = h > 1 && w < kHalf;
-            if (s == 0) v.f0[u] = under ? 1u : 0u;
+            if (s == 0) {
+                v.f0[u] = under ? 1u : 0u;
+                v.nu[u] = under ? 1u : 0u;
+            }
             if (nd) {
                 K* kl = t.lkeys + static_cast<uint64_t>(leaf) * kSlots;
                 K* vl = t.lvals + static_cast<uint64_t>(leaf) * kSlots;
@@ -1371,17 +1376,27 @@ __global__ __launch_bounds__(kBlk) void k_del_leaf(TreeView<K> t, Ins<K> v) {
     if (lane == 0 && del) atomicAdd(&v.st->deleted, del);
 }
 
-// The leaf runs left below half full, listed for the merge pass.
+// The leaf runs left below half full, listed for the merge pass: small
+// batches append with an atomic (any order); large ones place each run at
+// its prefix-scan position, so the list is in key order.
 template <class K>
 __global__ void k_del_list(TreeView<K> t, Ins<K> v) {
     if (t.hdr->error & kErrInternal) return;
     const uint64_t U = v.st->U;
     for (uint64_t u = gtid(); u < U; u += gstride())
-        if (leaf_run_head(v, u) && v.f0[u] == 1u) v.f1[atomicAdd(&v.st->merges, 1u)] = static_cast<uint32_t>(u);
+        if (v.nu[u]) v.f1[atomicAdd(&v.st->merges, 1u)] = static_cast<uint32_t>(u);
 }
 
 template <class K>
-__global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v) {
+__global__ void k_del_list_ordered(TreeView<K> t, Ins<K> v) {
+    if (t.hdr->error & kErrInternal) return;
+    const uint64_t U = v.st->U;
+    for (uint64_t u = gtid(); u < U; u += gstride())
+        if (v.nu[u]) v.f1[v.nleaf[u]] = static_cast<uint32_t>(u);
+}
+
+template <class K>
+__global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v, bool ordered) {
     if (t.hdr->error & kErrInternal) return;
     const int h = static_cast<int>(v.st->height);
     if (h < 2) return;
@@ -1398,10 +1413,15 @@ __global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v) {
         const uint64_t u = v.f1[li];
         const uint32_t P = v.pn[lp + u];
         bool first = true;
-        for (uint64_t e = u; e-- > 0 && v.pn[lp + e] == P;) {
-            if (leaf_run_head(v, e) && v.f0[e]) {
-                first = false;
-                break;
+        if (ordered) {
+            // the list is in key order, and a parent's runs are consecutive
+            first = li == 0 || v.pn[lp + v.f1[li - 1]] != P;
+        } else {
+            for (uint64_t e = u; e-- > 0 && v.pn[lp + e] == P;) {
+                if (leaf_run_head(v, e) && v.f0[e]) {
+                    first = false;
+                    break;
+                }
             }
         }
         if (!first) continue;
@@ -1698,9 +1718,15 @@ const uint32_t* launch_delete(const TreeView<K>& t, const InsertCtx& c, const K*
     launch_locate<K>(t, v, c.cfg, B, status, s);
     const uint64_t gl = grid_for(B * kSlots, kBlk);
     hipLaunchKernelGGL(k_del_leaf<K>, dim3(gl < 65536 ? static_cast<uint32_t>(gl) : 65536u), dim3(kBlk), 0, s, t, v);
-    hipLaunchKernelGGL(k_del_list<K>, dim3(gB), dim3(kBlk), 0, s, t, v);
+    const bool ordered = B > kDelListScan;
+    if (ordered) {
+        scan_exclusive<uint32_t>(v.nu, v.nleaf, &v.st->merges, &v.st->U, B, v.scan_tmp, s);
+        hipLaunchKernelGGL(k_del_list_ordered<K>, dim3(gB), dim3(kBlk), 0, s, t, v);
+    } else {
+        hipLaunchKernelGGL(k_del_list<K>, dim3(gB), dim3(kBlk), 0, s, t, v);
+    }
     const uint32_t gm = B < 16384 ? static_cast<uint32_t>(B) : 16384u;
-    hipLaunchKernelGGL(k_del_merge<K>, dim3(gm), dim3(64), 0, s, t, v);
+    hipLaunchKernelGGL(k_del_merge<K>, dim3(gm), dim3(64), 0, s, t, v, ordered);
     hipLaunchKernelGGL(k_del_merge2<K>, dim3(B < 256 ? static_cast<uint32_t>(B) : 256u), dim3(1024), 0, s, t, v);
     hipLaunchKernelGGL(k_del_commit<K>, dim3(1), dim3(1), 0, s, t, v);
     launch_mirror_refresh<K>(t, s);

@@ -357,10 +357,11 @@ gt_status tree_delete_batch(gt_tree* t, const void* keys, uint64_t B, uint8_t* s
                                              status_out, stream);
     HIP_TRY(hipGetLastError());
     t->deletes++;
-    uint32_t rebuild = 0;
-    HIP_TRY(hipMemcpyAsync(&rebuild, flag, 4, hipMemcpyDeviceToHost, stream));
+    // pinned, so that the copy goes straight to host memory (first call allocates it)
+    if (!t->h_flag) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&t->h_flag), 64, hipHostMallocDefault));
+    HIP_TRY(hipMemcpyAsync(t->h_flag, flag, 4, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    if (!rebuild) return GT_OK;
+    if (!*t->h_flag) return GT_OK;
     return t->kb == 8 ? delete_rebuild_t<uint64_t>(t, stream) : delete_rebuild_t<uint32_t>(t, stream);
 }
 
@@ -411,6 +412,7 @@ gt_status tree_insert_batch(gt_tree* t, const void* keys, const void* values, ui
 
 gt_status tree_destroy(gt_tree* t) {
     if (!t) return GT_ERR_INVALID;
+    if (t->h_flag) hipHostFree(t->h_flag);
     delete t;
     return GT_OK;
 }

@@ -57,8 +57,9 @@ def test_delete_sizes(width, n):
     keys = key_set(n, width, seed, edges=(n % 2 == 1))
     vals = synth.values_for(keys, seed, width)
     sa = oracle.SortedArray(keys, vals, width)
-    t = mk_tree(keys, vals, width // 8, max_batch=8192)
-    for i, B in enumerate((1, 7, 64, 1000, 2049, 5000)):
+    t = mk_tree(keys, vals, width // 8, max_batch=1 << 15)
+    # above 16384 keys the merge list comes from a scan (key order)
+    for i, B in enumerate((1, 7, 64, 1000, 2049, 5000, 20000)):
         allk, _ = sa.items()
         k = _del_batch(allk, B, seed + 10 * i, width)
         st = t.delete(k)
