@@ -1460,10 +1460,23 @@ __global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v, bool 
             continue;
         }
         if (static_cast<uint32_t>(lane) < nc) {
+            // all of a child's loads in flight at once (fixed trip count)
             const uint64_t src = static_cast<uint64_t>(kid[lane]) * kSlots;
-            for (uint32_t j = 0; j < cnt[lane]; ++j) {
-                mk[pre[lane] + j] = t.lkeys[src + j];
-                mv[pre[lane] + j] = t.lvals[src + j];
+            const uint32_t cn = cnt[lane], at = pre[lane];
+            K kk[kSlots], vv[kSlots];
+#pragma unroll
+            for (uint32_t j = 0; j < kSlots; ++j) {
+                if (j < cn) {
+                    kk[j] = t.lkeys[src + j];
+                    vv[j] = t.lvals[src + j];
+                }
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < kSlots; ++j) {
+                if (j < cn) {
+                    mk[at + j] = kk[j];
+                    mv[at + j] = vv[j];
+                }
             }
         }
         __syncthreads();
