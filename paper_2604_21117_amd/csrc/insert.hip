@@ -1459,23 +1459,25 @@ __global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v, bool 
             __syncthreads();
             continue;
         }
-        if (static_cast<uint32_t>(lane) < nc) {
-            // all of a child's loads in flight at once (fixed trip count)
-            const uint64_t src = static_cast<uint64_t>(kid[lane]) * kSlots;
-            const uint32_t cn = cnt[lane], at = pre[lane];
-            K kk[kSlots], vv[kSlots];
+        {
+            // 16 lanes per child, slot = lane % 16, four children per round:
+            // every load of the gather in flight at once, few registers
+            const uint32_t j = static_cast<uint32_t>(lane) % kSlots;
+            K kk[4], vv[4];
 #pragma unroll
-            for (uint32_t j = 0; j < kSlots; ++j) {
-                if (j < cn) {
-                    kk[j] = t.lkeys[src + j];
-                    vv[j] = t.lvals[src + j];
+            for (uint32_t r = 0; r < 4; ++r) {
+                const uint32_t c = r * 4 + static_cast<uint32_t>(lane) / kSlots;
+                if (c < nc && j < cnt[c]) {
+                    kk[r] = t.lkeys[static_cast<uint64_t>(kid[c]) * kSlots + j];
+                    vv[r] = t.lvals[static_cast<uint64_t>(kid[c]) * kSlots + j];
                 }
             }
 #pragma unroll
-            for (uint32_t j = 0; j < kSlots; ++j) {
-                if (j < cn) {
-                    mk[at + j] = kk[j];
-                    mv[at + j] = vv[j];
+            for (uint32_t r = 0; r < 4; ++r) {
+                const uint32_t c = r * 4 + static_cast<uint32_t>(lane) / kSlots;
+                if (c < nc && j < cnt[c]) {
+                    mk[pre[c] + j] = kk[r];
+                    mv[pre[c] + j] = vv[r];
                 }
             }
         }
