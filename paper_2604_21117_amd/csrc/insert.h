@@ -1,4 +1,5 @@
-// Insert path (sort, merge, split, parent-split propagation).
+// Insert path (sort, merge, split, parent-split propagation) and delete path
+// (remove in place, merges under the parent and the grandparent, rebuild).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

@@ -1,4 +1,6 @@
-// Insert batches: sort, deduplicate, locate, plan, check, apply.
+// Insert batches: sort, deduplicate, locate, plan, check, apply.  Delete
+// batches (the last section of this file) share the sort, deduplication
+// and locate, then remove keys in place and merge what fell below half full.
 //
 // The paper searches a static tree (Section V-A); inserts are the dynamic
 // counterpart that keeps Section III's invariants: sorted leaves, equal
