@@ -203,6 +203,36 @@ def test_delete_grandparent_merges_and_root_shrink(width):
     t.close()
 
 
+@pytest.mark.parametrize("seed", range(12))
+def test_delete_random_sequences(seed):
+    """Random interleavings of insert and delete batches of random sizes on
+    small trees (fill 0.5 or 1.0, a few hundred to a few thousand keys, u32
+    and u64), so that leaf-parent merges, grandparent merges, root shrinks,
+    rebuilds and regrowth follow each other; statuses, invariants and
+    lookups against the oracle after every step."""
+    rng = np.random.default_rng(2000 + seed)
+    width = 32 if seed % 2 else 64
+    n = int(rng.integers(100, 4000))
+    keys = key_set(n, width, 2100 + seed, edges=(seed % 3 == 0))
+    vals = synth.values_for(keys, 2100 + seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, width // 8, fill=0.5 if seed % 4 < 2 else 1.0, leaf_slack=1 << 14, max_batch=4096)
+    for step in range(10):
+        allk, _ = sa.items()
+        if rng.random() < 0.6 and len(allk):
+            frac = float(rng.choice([0.05, 0.3, 0.9]))
+            B = max(1, min(4096, int(len(allk) * frac) + int(rng.integers(0, 20))))
+            k = _del_batch(allk, B, 2200 + 17 * seed + step, width, float(rng.choice([0.5, 0.95])))
+            assert np.array_equal(t.delete(k), sa.delete(k)), f"seed {seed} step {step}: delete statuses"
+        else:
+            B = int(rng.integers(1, 3000))
+            nk = synth.uniform_keys(B, 2300 + 17 * seed + step, width)
+            nv = synth.values_for(nk, 2400 + step, width)
+            assert np.array_equal(t.insert(nk, nv), sa.insert(nk, nv)), f"seed {seed} step {step}: insert"
+        _check_all(t, sa, width, 2500 + step, f"seed {seed} step {step}")
+    t.close()
+
+
 def test_delete_argument_errors():
     import torch
     import paper_2604_21117_amd as g
