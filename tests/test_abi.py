@@ -26,7 +26,8 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for f in ("tree_build", "tree_lookup_batch", "tree_insert_batch", "tree_range_batch"):
+    for f in ("tree_build", "tree_lookup_batch", "tree_insert_batch", "tree_delete_batch", "tree_range_batch",
+              "tree_lookup_levelwise", "gt_set_sort_spin_limit"):
         assert f in names
 
 
@@ -47,3 +48,17 @@ def test_host_side_errors_without_device():
     assert g.lib().tree_lookup_batch(None, None, 4, None, None, None) == g.GT_ERR_INVALID
     assert g.lib().tree_destroy(None) == g.GT_ERR_INVALID
     assert g.status_str(g.GT_ERR_CAPACITY) == "capacity exceeded"
+    assert g.lib().tree_delete_batch(None, None, 4, None, None) == g.GT_ERR_INVALID
+
+
+def test_sort_spin_limit_hook_is_host_only():
+    """The testing hook sets a host value read at launch: it returns the
+    previous limit (the default 2^20) and touches no device."""
+    import paper_2604_21117_amd as g
+    old = g.set_sort_spin_limit(5)
+    try:
+        assert old == 1 << 20
+        assert g.set_sort_spin_limit(0) == 5
+    finally:
+        assert g.set_sort_spin_limit(old) == 0
+    assert g.set_sort_spin_limit(old) == old
