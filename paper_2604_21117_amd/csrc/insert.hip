@@ -1291,6 +1291,35 @@ __global__ void k_del_unique(Ins<K> v, uint64_t B) {
     }
 }
 
+// Batches up to 2048 keys (after the rank sort, which also cleared the
+// batch state): one workgroup, two sorted positions per thread, finds the
+// distinct keys, writes the statuses of repeats and the batch state.
+template <class K>
+__global__ __launch_bounds__(1024) void k_del_small_prefix(Ins<K> v, const DevHeader* hdr, uint32_t B,
+                                                           uint8_t* __restrict__ status) {
+    __shared__ uint32_t sh[33];
+    const uint32_t t = threadIdx.x, p0 = 2 * t, p1 = p0 + 1;
+    const bool h0 = p0 < B && (p0 == 0 || v.sk[p0] != v.sk[p0 - 1]);
+    const bool h1 = p1 < B && v.sk[p1] != v.sk[p0];
+    if (p0 < B && !h0) status[v.si[p0]] = 0;  // ABSENT: an earlier occurrence deleted it
+    if (p1 < B && !h1) status[v.si[p1]] = 0;
+    uint32_t tot;
+    const uint32_t base = block_excl_scan<uint32_t>((h0 ? 1u : 0u) + (h1 ? 1u : 0u), sh, &tot);
+    if (h0) {
+        v.uk[base] = v.sk[p0];
+        v.upos[base] = p0;
+    }
+    if (h1) {
+        const uint32_t e = base + (h0 ? 1u : 0u);
+        v.uk[e] = v.sk[p1];
+        v.upos[e] = p1;
+    }
+    if (t == 0) {
+        v.st->U = tot;
+        v.st->height = hdr->height;
+    }
+}
+
 // first distinct key of its leaf's run (keys are sorted, so a leaf's keys
 // are consecutive)
 template <class K>
@@ -1696,13 +1725,19 @@ __global__ __launch_bounds__(1024) void k_del_merge2(TreeView<K> t, Ins<K> v) {
     }
 }
 
+// Commit the count and the epoch, then rebuild the top-levels mirror (one
+// launch).
 template <class K>
-__global__ void k_del_commit(TreeView<K> t, Ins<K> v) {
-    if (t.hdr->error & kErrInternal) return;
-    const uint32_t d = v.st->deleted;
-    if (d == 0) return;
-    t.hdr->n_keys -= d;
-    t.hdr->epoch += 1;
+__global__ __launch_bounds__(256) void k_del_commit(TreeView<K> t, Ins<K> v) {
+    if (threadIdx.x == 0 && !(t.hdr->error & kErrInternal)) {
+        const uint32_t d = v.st->deleted;
+        if (d) {
+            t.hdr->n_keys -= d;
+            t.hdr->epoch += 1;
+        }
+    }
+    __syncthreads();
+    mirror_refresh_body<K, 256>(t);
 }
 
 // Copy every pair of the leaves that hold keys (cleared leaves hold none).
@@ -1727,11 +1762,18 @@ const uint32_t* launch_delete(const TreeView<K>& t, const InsertCtx& c, const K*
     Ins<K> v;
     carve<K>(&v, c.scratch, c.max_batch, c.leaf_cap, c.inner_cap);
     const uint32_t gB = grid_for(B, kBlk);
-    hipLaunchKernelGGL(k_init<K>, dim3(1), dim3(kBlk), 0, s, v, t.hdr);
-    sort_from<K>(keys, v.sk, v.si, v.sk2, v.si2, B, v.sort_tmp, s, &t.hdr->error, kErrInternal);
-    hipLaunchKernelGGL(k_del_heads<K>, dim3(gB), dim3(kBlk), 0, s, v, B, status);
-    scan_exclusive<uint32_t>(v.f0, v.f1, &v.st->U, nullptr, B, v.scan_tmp, s);
-    hipLaunchKernelGGL(k_del_unique<K>, dim3(gB), dim3(kBlk), 0, s, v, B);
+    if (B <= kSmallInsert) {
+        rank_sort_small<K>(keys, static_cast<uint32_t>(B), v.sk, v.si, reinterpret_cast<uint32_t*>(v.st),
+                           static_cast<uint32_t>(sizeof(InsState) / 4), s);
+        hipLaunchKernelGGL(k_del_small_prefix<K>, dim3(1), dim3(1024), 0, s, v, t.hdr, static_cast<uint32_t>(B),
+                           status);
+    } else {
+        hipLaunchKernelGGL(k_init<K>, dim3(1), dim3(kBlk), 0, s, v, t.hdr);
+        sort_from<K>(keys, v.sk, v.si, v.sk2, v.si2, B, v.sort_tmp, s, &t.hdr->error, kErrInternal);
+        hipLaunchKernelGGL(k_del_heads<K>, dim3(gB), dim3(kBlk), 0, s, v, B, status);
+        scan_exclusive<uint32_t>(v.f0, v.f1, &v.st->U, nullptr, B, v.scan_tmp, s);
+        hipLaunchKernelGGL(k_del_unique<K>, dim3(gB), dim3(kBlk), 0, s, v, B);
+    }
     launch_locate<K>(t, v, c.cfg, B, status, s);
     const uint64_t gl = grid_for(B * kSlots, kBlk);
     hipLaunchKernelGGL(k_del_leaf<K>, dim3(gl < 65536 ? static_cast<uint32_t>(gl) : 65536u), dim3(kBlk), 0, s, t, v);
@@ -1745,8 +1787,7 @@ const uint32_t* launch_delete(const TreeView<K>& t, const InsertCtx& c, const K*
     const uint32_t gm = B < 16384 ? static_cast<uint32_t>(B) : 16384u;
     hipLaunchKernelGGL(k_del_merge<K>, dim3(gm), dim3(64), 0, s, t, v, ordered);
     hipLaunchKernelGGL(k_del_merge2<K>, dim3(B < 256 ? static_cast<uint32_t>(B) : 256u), dim3(1024), 0, s, t, v);
-    hipLaunchKernelGGL(k_del_commit<K>, dim3(1), dim3(1), 0, s, t, v);
-    launch_mirror_refresh<K>(t, s);
+    hipLaunchKernelGGL(k_del_commit<K>, dim3(1), dim3(256), 0, s, t, v);
     return &v.st->rebuild;
 }
 
