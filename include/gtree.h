@@ -8,7 +8,7 @@
  *   tree_build         bulk load from (key, value) pairs      (Section V-B: the
  *                      one-time build and transfer of the tree)
  *   tree_lookup_batch  root-to-leaf search of a key batch     (Section IV-A,
- *                      IV-E, IV-F: batch search, "key <= node entry" routing,
+ *                      IV-E, IV-F: batch search, routing by key-vs-entry compare,
  *                      -1 for a key that is not found)
  *   tree_lookup_levelwise  the same results by the paper's level-by-level
  *                      walk of a sorted batch (Sections IV-A, IV-F)

@@ -19,8 +19,8 @@
  *      most m children per inner node, at least m/2 for a non-root inner
  *      node), data only in the leaves, leaves chained left to right.  Inner
  *      entry i holds the largest key of child i's subtree, and a search key
- *      goes to the first child whose entry is >= the key (the "less than or
- *      equal to the node entry" test of Section IV-E).  Inserts go one key
+ *      goes to the first child whose entry is >= the key (the routing
+ *      comparison of Section IV-E).  Inserts go one key
  *      at a time with the classic split; bulk load fills leaves evenly.  It
  *      is the timed CPU baseline (the paper times a CPU B+-tree library,
  *      Section V-F), with lookup batches split evenly over threads.
@@ -113,8 +113,9 @@ u64 ora_insert(const u64* keys, const u64* vals, u64 n, const u64* k, const u64*
 }
 
 /*
- * Delete the keys k[i], i = 0..B-1, from S in batch order (the B+-tree's
- * delete of Section III, on the state alone).  status[i] = 1 (DELETED) if
+ * Delete the keys k[i], i = 0..B-1, from S in batch order: sequential
+ * deletion on the state alone (the paper defines no delete; the tree side
+ * keeps the half-full rule of Section III).  status[i] = 1 (DELETED) if
  * k[i] was in S and not earlier in the batch, else 0 (ABSENT).  Each key of
  * S is kept unless some k[i] equals it: a binary search of S per batch key
  * marks the hits, then one pass copies the unmarked pairs.  out_keys and

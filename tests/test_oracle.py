@@ -330,6 +330,88 @@ def test_checker_flags_unequal_depth():
     assert oracle.check_export(b)[0] & oracle.V_DEPTH
 
 
+def _hand_export(shape, width):
+    """A flat export written by hand from a nested shape: an inner node is a
+    list of children, a leaf is an int (its key count).  Keys are 10, 20, 30,
+    ... in leaf order; values are the keys plus one.  The layout follows the
+    export format the library documents (entry i of an inner node is the
+    largest key below child i, unused entries hold the largest key, unused
+    child slots hold 0xFFFFFFFF; leaf slots past the count repeat the last
+    key; the chain links plain leaf indices)."""
+    kb, F, Cc = width // 8, 16, 16
+    maxk = (1 << width) - 1
+    inner, leaves = [], []
+    nxt = [10]
+
+    def depth(s):
+        return 1 if isinstance(s, int) else 1 + depth(s[0])
+
+    def make(s):
+        if isinstance(s, int):
+            ks = [nxt[0] + 10 * i for i in range(s)]
+            nxt[0] += 10 * s
+            leaves.append(ks)
+            return (len(leaves) - 1) | 0x80000000, ks[-1]
+        me = len(inner)
+        inner.append(None)
+        refs, tops = zip(*[make(c) for c in s])
+        inner[me] = (list(refs), list(tops))
+        return me, tops[-1]
+
+    root, _ = make(shape)
+    dt = np.uint32 if width == 32 else np.uint64
+    out = bytearray()
+    nkeys = sum(len(k) for k in leaves)
+    out += np.array([0x58455447, kb, F, Cc, depth(shape), root, 0 if leaves else 0xFFFFFFFF,
+                     len(inner), len(leaves), 0], dtype=np.uint32).tobytes()
+    out += np.array([nkeys], dtype=np.uint64).tobytes()
+    for refs, tops in inner:
+        seps = tops[:-1] + [maxk] * (F - len(tops) + 1)
+        out += np.array(seps, dtype=dt).tobytes()
+        out += np.array(refs + [0xFFFFFFFF] * (F - len(refs)), dtype=np.uint32).tobytes()
+    for j, ks in enumerate(leaves):
+        out += np.array(ks + [ks[-1]] * (Cc - len(ks)), dtype=dt).tobytes()
+        out += np.array([k + 1 for k in ks] + [0] * (Cc - len(ks)), dtype=dt).tobytes()
+        out += np.array([len(ks), j + 1 if j + 1 < len(leaves) else 0xFFFFFFFF],
+                        dtype=np.uint32).tobytes()
+    return np.frombuffer(bytes(out), dtype=np.uint8).copy()
+
+
+@pytest.mark.parametrize("width", [32, 64])
+def test_checker_flags_underfull_inner_node(width):
+    """Section III: every inner node but the root has at least m/2 = 8
+    children.  A parent with 7 leaves under a valid root is flagged (fill
+    only); the same tree with 8 is accepted."""
+    ok = _hand_export([[8] * 8, [8] * 8], width)
+    bits, ek, _ = oracle.check_export(ok)
+    assert bits == 0, oracle.violations(bits)
+    assert len(ek) == 128
+    bad = _hand_export([[8] * 8, [8] * 7], width)
+    assert oracle.check_export(bad)[0] == oracle.V_FILL
+    # a full leaf count does not hide it: 7 children of 16 keys each
+    bad = _hand_export([[16] * 8, [16] * 7], width)
+    assert oracle.check_export(bad)[0] == oracle.V_FILL
+
+
+@pytest.mark.parametrize("width", [32, 64])
+def test_checker_flags_inner_root_with_one_child(width):
+    """The root is exempt from the half-full rule but, when inner, has at
+    least two children: a root over one parent is flagged (fill only); a
+    root over two parents, and a root with exactly 2 leaves, are accepted."""
+    bad = _hand_export([[8] * 8], width)
+    assert oracle.check_export(bad)[0] == oracle.V_FILL
+    assert oracle.check_export(_hand_export([[8] * 8, [8] * 8], width))[0] == 0
+    assert oracle.check_export(_hand_export([8, 8], width))[0] == 0
+    assert oracle.check_export(_hand_export([16], width))[0] == oracle.V_FILL
+
+
+@pytest.mark.parametrize("width", [32, 64])
+def test_checker_flags_overfull_inner_node(width):
+    """No inner node exceeds the order: 16 children is the most an export
+    can even describe; a 16-child parent is valid."""
+    assert oracle.check_export(_hand_export([[8] * 16, [8] * 8], width))[0] == 0
+
+
 # ------------------------------------------------------- random sequences
 
 ops = st.lists(
