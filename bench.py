@@ -43,7 +43,21 @@ Also measured in the same run, outside the K timed steps:
                   arrivals at 0.25/0.5/0.75/0.9 of its rate (20,000 batches
                   each); plain tree and learned index; p50/p99 and the
                   device-busy fraction
-  cpu_baseline    the oracle's pointer B+-tree on the host cores
+  cpu_baseline    the oracle's pointer B+-tree on the host cores, batches
+                  split over 1, 16 and all threads (threads created once)
+
+Every result of the timed and swept launches is checked (closed form of the
+generator, or the oracle's state) outside the timed spans.
+
+Output: the whole record is written to gpurun_out/bench_detail.json and to
+stderr; the last stdout line is one compact JSON object (metric, value,
+ms_per_step, config, roofline, cpu_baseline, the learned/plain ratio and a
+few headline figures).  The roofline block is the 2^20-key lookup kernel:
+algorithmic bytes per launch over its HIP-event time after a 2 GiB cache
+flush (`frac`), with the back-to-back figure beside it (`frac_warm`), and,
+when the committed counter summary matches the kernel's sources, the
+counted memory traffic, R1 = traffic / time / peak and R2 = algorithmic /
+traffic.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -64,6 +78,9 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+MAX64 = (1 << 64) - 1
+METRIC = "lookup Mops/s and \u00b5s/batch at B=1..1024, 2^24 keys; learned vs plain tree"
+LARGE_KERNEL = "k_lookup<unsigned long, 8, 4, 2, true, false>"
 N_LOG2 = 24
 SEED = 2
 
@@ -76,6 +93,14 @@ def iqm(x):
     s = s[:n] if n >= 4 else s
     q = len(s) // 4
     return float(s[q:len(s) - q].mean()) if len(s) >= 4 else float(s.mean())
+
+
+def member(sorted_keys: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """Which of q are in the ascending array sorted_keys."""
+    if len(sorted_keys) == 0:
+        return np.zeros(len(q), dtype=bool)
+    i = np.minimum(np.searchsorted(sorted_keys, q), len(sorted_keys) - 1)
+    return sorted_keys[i] == q
 
 
 def dist_stats(x):
@@ -115,22 +140,52 @@ def lookup_sources_hash() -> str:
     return h.hexdigest()
 
 
-def cpu_baseline(keys, vals, batches, threads, budget_s=10.0):
+def cpu_baseline(keys, vals, queries, B, budget_s=6.0):
+    """The oracle's pointer B+-tree (fanout 16, 16 keys per leaf) on the
+    host cores, timed as the paper times its CPU tree: each batch split
+    evenly over T threads (T = 1, 16 and every core this process may use),
+    the threads created once per run and meeting at a barrier around every
+    batch, a steady clock per batch.  For each T, batches of B queries run
+    until about `budget_s` seconds of them have been timed; every answer is
+    checked against the generator's closed form.  Returns the row of the
+    fastest T with the others beside it."""
     import oracle
+    t0 = time.perf_counter()
     pt = oracle.PointerTree(16, 16, 64)
     pt.bulk_load(keys, vals)
-    done = 0
-    t0 = time.perf_counter()
-    while True:
-        for q in batches:
-            pt.lookup(q, threads)
-            done += len(q)
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": round(done / dt / 1e6, 3), "unit": "Mops/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} lookups in batches of {len(batches[0])} on the oracle's pointer B+-tree "
-                      f"(2^{N_LOG2} keys), each batch split evenly over {threads} threads, {dt:.1f} s"}
+    build = time.perf_counter() - t0
+    expect = synth.values_for(queries, SEED, 64)
+    cores = len(os.sched_getaffinity(0))
+    rows = {}
+    for T in sorted({1, 16, cores}):
+        done, per_batch = 0, []
+        nb = min(len(queries) // B, 64)
+        pos = 0
+        while sum(per_batch) < budget_s and pos + nb * B <= len(queries):
+            q = queries[pos:pos + nb * B]
+            v, f, t = pt.lookup_batches_timed(q, B, T)
+            assert f.all() and np.array_equal(v, expect[pos:pos + nb * B])
+            per_batch += list(t)
+            done += nb * B
+            pos = (pos + nb * B) % (len(queries) - nb * B + 1)
+        us = np.array(per_batch) * 1e6
+        rows[T] = {"threads": T, "mops": round(B / iqm(us), 3), "us_per_batch": dist_stats(us),
+                   "lookups": done, "seconds": round(float(us.sum()) * 1e-6, 2)}
+    top = max(rows.values(), key=lambda r: r["mops"])
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": top["mops"], "unit": "Mops/s", "cores": top["threads"], "kind": "oracle",
+            "sample": f"{top['lookups']} lookups in batches of {B} on the oracle's pointer B+-tree of "
+                      f"2^{int(np.log2(len(keys)))} keys, each batch split over {top['threads']} threads "
+                      f"created once; {top['seconds']} s timed",
+            "by_threads": {str(T): {"mops": r["mops"], "us_iqm": r["us_per_batch"]["iqm"]} for T, r in rows.items()},
+            "host_cores": cores, "cpu_model": model, "tree_build_s": round(build, 1)}, rows
 
 
 def cu_masked_stream(cus):
@@ -186,8 +241,8 @@ def main():
                     help="skip the latency regime (lognormal / clustered keys, full GPU and 8 CUs)")
     ap.add_argument("--log2n", type=int, default=N_LOG2)
     ap.add_argument("--profile", action="store_true",
-                    help="counter-collection mode: a 1 GiB device copy (calibration) and three 2^20-key "
-                         "lookup batches, then exit")
+                    help="counter-collection mode: three 1 GiB device copies (calibration), a priming "
+                         "2^20-key lookup batch, three warm ones and three after a 2 GiB cache flush, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the tree runs on a single MI355X "
@@ -225,10 +280,22 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+        # three warm launches (one untimed launch first), then three cold
+        # ones, each after a 2 GiB read-modify-write that evicts the caches
+        g.tree_lookup_batch(tree.h, qld, vl, fl, stream)
         for _ in range(3):
             g.tree_lookup_batch(tree.h, qld, vl, fl, stream)
         torch.cuda.synchronize()
-        print(json.dumps({"profile": "done", "copy_bytes": 1 << 30, "lookup_batch": BL}), flush=True)
+        del src, dst
+        flush = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
+        for _ in range(3):
+            flush.add_(1)
+            g.tree_lookup_batch(tree.h, qld, vl, fl, stream)
+        torch.cuda.synchronize()
+        got = g.to_numpy(fl)
+        assert got.all() and np.array_equal(g.to_numpy(vl, np.uint64), synth.values_for(ql_np, SEED, 64))
+        print(json.dumps({"profile": "done", "copy_bytes": 1 << 30, "lookup_batch": BL,
+                          "lookup_dispatches": "1 priming, 3 warm, 3 cold (each after a 2 GiB flush)"}), flush=True)
         return
 
     t0 = time.perf_counter()
@@ -375,34 +442,41 @@ def main():
         tz = g.Tree(keys[:m], vals[:m], 8, max_batch=1024)
         lz = g.Learned(tz, models=1024)
         lz.train()
-        qz_np = synth.present_queries(keys[:m], 256 * B, SEED, purpose=6000 + lg)
-        qz = tz.dev(qz_np)
-        qzb = [qz[i * B:(i + 1) * B] for i in range(256)]
         row = {"height": tz.stats()["height"]}
-        for path in ("plain", "learned"):
-            if path == "plain":
-                fn = lambda i: g.tree_lookup_batch(tz.h, qzb[i], vz, fz, stream)
-            else:
-                fn = lambda i: g.li_lookup_batch(lz.h, qzb[i], vz, fz, stream)
-            graphs = [capture(fn, c, GR) for c in range(0, 256, GR)]
-            graphs[0].replay()
-            stream.synchronize()
-            best = None
-            for _ in range(3):
-                t0 = time.perf_counter()
-                for gr in graphs:
-                    gr.replay()
+        kset_z = np.sort(keys[:m])
+        # uniform present keys, then half present / half absent (the absent
+        # half uniform over the key space)
+        for qname, qz_np in (("", synth.present_queries(keys[:m], 256 * B, SEED, purpose=6000 + lg)),
+                             ("mixed_", synth.mixed_queries(keys[:m], 256 * B, 6100 + lg, 64))):
+            qz = tz.dev(qz_np)
+            qzb = [qz[i * B:(i + 1) * B] for i in range(256)]
+            last = qz_np[255 * B:]
+            pres = member(kset_z, last)
+            for path in ("plain", "learned"):
+                if path == "plain":
+                    fn = lambda i: g.tree_lookup_batch(tz.h, qzb[i], vz, fz, stream)
+                else:
+                    fn = lambda i: g.li_lookup_batch(lz.h, qzb[i], vz, fz, stream)
+                graphs = [capture(fn, c, GR) for c in range(0, 256, GR)]
+                graphs[0].replay()
                 stream.synchronize()
-                dt = (time.perf_counter() - t0) / 256 * 1e6
-                best = dt if best is None else min(best, dt)
-            assert g.to_numpy(fz).all() and np.array_equal(g.to_numpy(vz, np.uint64),
-                                                           synth.values_for(qz_np[255 * B:], SEED, 64))
-            del graphs
-            row[f"{path}_us_per_batch"] = round(best, 3)
+                best = None
+                for _ in range(3):
+                    t0 = time.perf_counter()
+                    for gr in graphs:
+                        gr.replay()
+                    stream.synchronize()
+                    dt = (time.perf_counter() - t0) / 256 * 1e6
+                    best = dt if best is None else min(best, dt)
+                gv, gf = g.to_numpy(vz, np.uint64), g.to_numpy(fz).astype(bool)
+                assert np.array_equal(gf, pres) and np.array_equal(gv[pres], synth.values_for(last[pres], SEED, 64)) \
+                    and (gv[~pres] == np.uint64(MAX64)).all(), (lg, qname, path)
+                del graphs
+                row[f"{path}_{qname}us_per_batch"] = round(best, 3)
+            del qz, qzb
         size_sweep[str(lg)] = row
         lz.close()
         tz.close()
-        del qz, qzb
     print("[bench] size sweep done", file=sys.stderr, flush=True)
 
     # ---- large batch: warm launches of the 2^20-key lookup kernel
@@ -511,10 +585,17 @@ def main():
                         fpos_m += b
                         kd, vd = tm.dev(k), tm.dev(synth.values_for(k, SEED, 64))
                         it += timer.run(lambda: g.tree_insert_batch(tm.h, kd, vd, sm[:b], stream), 1, skip=0)
+                        # fresh keys: every status INSERTED
+                        assert (g.to_numpy(sm[:b]) == 0).all(), (dist, b, r)
                     else:
                         j = r % nq
                         qq = qdm[j * b:(j + 1) * b]
                         lt += timer.run(lambda: g.tree_lookup_batch(tm.h, qq, vm[:b], fm[:b], stream), 1, skip=0)
+                        # present keys of the bulk load (inserts add fresh keys
+                        # only): found, with the generator's value
+                        assert g.to_numpy(fm[:b]).all() and np.array_equal(
+                            g.to_numpy(vm[:b], np.uint64), synth.values_for(qn[j * b:(j + 1) * b], SEED, 64)), \
+                            (dist, b, r)
                 assert g.tree_device_error(tm.h) == g.GT_OK
                 mixed[dist][str(b)] = {"lookups": len(lt), "inserts": len(it),
                                        "lookup_us": dist_stats(lt) if lt else None,
@@ -549,7 +630,7 @@ def main():
                 rows = {}
                 for b in [1 << i for i in range(11)] + [1000]:
                     q = synth.mixed_queries(kk, b, 3 + b, 64)
-                    present = np.isin(q, kset)
+                    present = member(kset, q)
                     qd3 = tl.dev(q)
                     v5 = torch.empty(b, dtype=torch.int64, device=dev)
                     f5 = torch.empty(b, dtype=torch.uint8, device=dev)
@@ -661,7 +742,9 @@ def main():
         for r in range(rounds // 4):
             i = qtr * (rounds // 4) + r
             lt += timer.run(lambda: g.li_lookup_batch(li.h, qd[i % nbatch], vo, fo, stream), 1, skip=0)
+            assert g.to_numpy(fo).all() and np.array_equal(g.to_numpy(vo, np.uint64), expect(i)), ("learned", i)
             pt += timer.run(lambda: g.tree_lookup_batch(tree.h, qd[i % nbatch], vo, fo, stream), 1, skip=0)
+            assert g.to_numpy(fo).all() and np.array_equal(g.to_numpy(vo, np.uint64), expect(i)), ("plain", i)
             insert_batch(fresh[fpos:fpos + B])
             fpos += B
         ls = li.stats()
@@ -738,6 +821,38 @@ def main():
                    "latency": "arrival -> completion, PCIe copies included (host buffers in and out)"}
         fpos = 0
         spec_seed = 50
+        sk5 = np.sort(keys5)
+        inserted = []   # key arrays of every insert batch served so far, in admission order
+
+        def check_served(batches):
+            """Every lookup asks for a key of the bulk load (inserts add fresh
+            keys only): found, value hash(key ^ 5).  Every insert status is
+            INSERTED.  Range queries (lo a present key, hi the largest key):
+            the first 16 of each batch exactly, against the bulk-loaded keys
+            merged with every key inserted before the batch in admission
+            order; the rest ascending from lo with present keys' values."""
+            for b in batches:
+                if b.op == g.OP_LOOKUP:
+                    assert b.out1.all() and np.array_equal(b.out0, synth.values_for(b.keys, s5, 64))
+                elif b.op == g.OP_INSERT:
+                    assert (b.out0 == 0).all()
+                    inserted.append(b.keys.copy())
+                else:
+                    ins_sorted = np.sort(np.concatenate(inserted)) if inserted else np.zeros(0, np.uint64)
+                    off = np.concatenate([[0], np.cumsum(b.max_out.astype(np.int64))])
+                    for i in range(len(b.keys)):
+                        lo, mx, c = b.keys[i], int(b.max_out[i]), int(b.count[i])
+                        got = b.out0[off[i]:off[i] + c]
+                        if i < 16:
+                            a = sk5[np.searchsorted(sk5, lo):][:mx]
+                            bb = ins_sorted[np.searchsorted(ins_sorted, lo):][:mx]
+                            want = np.sort(np.concatenate([a, bb]))[:mx]
+                            assert np.array_equal(got, want), ("range", i)
+                        else:
+                            assert (c == mx or c >= len(sk5) - np.searchsorted(sk5, lo)) and got[0] == lo \
+                                and (np.diff(got) > 0).all(), ("range", i)
+                        base = member(sk5, got)
+                        assert np.array_equal(b.out1[off[i]:off[i] + c][base], synth.values_for(got[base], s5, 64))
 
         def run(srv, n_b, rate):
             nonlocal fpos, spec_seed
@@ -747,6 +862,7 @@ def main():
             fpos += sum(len(k) for (op, k, v, m, a) in spec if op == 1)
             batches = [g.Batch(op, k, v, m, a) for (op, k, v, m, a) in spec]
             assert srv.replay(batches) == g.GT_OK
+            check_served(batches)
             st5 = srv.stats()
             lat = srv.latencies(len(batches))
             ops5 = np.array([b[0] for b in spec])
@@ -789,31 +905,36 @@ def main():
         del keys5, vals5, fresh5, zipf5
 
     # HBM bytes per launch from the committed counter summary, if it was
-    # taken on this same kernel (same sources, batch and tree)
-    traffic = None
+    # taken on this same kernel (same sources, batch and tree): one figure for
+    # warm launches and one for launches after the cache flush
+    traffic = {}
     tpath = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if os.path.exists(tpath):
         tj = json.load(open(tpath))
-        if tj.get("kernel") == "k_lookup<unsigned long, 8, 4, 2, true, false>" and tj.get("batch") == BL \
-                and tj.get("keys") == n and tj.get("sources_sha256") == lookup_sources_hash():
-            traffic = tj["traffic_bytes"]
+        if tj.get("kernel") == LARGE_KERNEL and tj.get("batch") == BL and tj.get("keys") == n \
+                and tj.get("sources_sha256") == lookup_sources_hash():
+            traffic = {k: tj[k]["traffic_bytes"] for k in ("warm", "cold") if k in tj}
 
-    line = {
-        "metric": "lookup Mops/s and us/batch at B=1..1024, 2^24 keys; learned vs plain tree",
-        "value": round(value, 3),
-        "unit": "Mops/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 6),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic",
-        "config": {"workload": f"B=1024 lookup batches of uniform present keys on a bulk-loaded B+-tree of "
-                               f"2^{args.log2n} uniform u64 keys (fanout 16, 16 keys per leaf)",
-                   "keys": n, "batch": B, "height": st["height"], "path": args.path,
+    cold_us = large.get("cold_avg_us")
+    t_us = cold_us if cold_us is not None else warm_avg
+    which = "cold" if cold_us is not None else "warm"
+    achieved = ab["bytes"] / (t_us * 1e-6) / 1e9
+    tr = traffic.get(which)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "frac_warm": round(ab["bytes"] / (warm_avg * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic": tr, "algorithmic_bytes": ab["bytes"],
+                "kernel": f"{LARGE_KERNEL}, B=2^20 on 2^{args.log2n} keys, {which} "
+                          f"({'2 GiB flush before each launch' if which == 'cold' else 'back-to-back'})",
+                "avg_us": round(t_us, 2), "warm_avg_us": round(warm_avg, 2),
+                # R1: counted memory bytes / time / peak; R2: algorithmic / counted
+                "r1": round(tr / (t_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) if tr else None,
+                "r2": round(ab["bytes"] / tr, 4) if tr else None}
+
+    learned_ratio = round((value / other_value) if args.path == "learned" else (other_value / value), 3)
+    detail = {
+        "metric": METRIC, "value": round(value, 3), "ms_per_step": round(ms_per_step, 6),
+        "config": {"keys": n, "batch": B, "height": st["height"], "path": args.path,
                    "learned_models": lst["models"], "learned_linear": lst["linear_models"],
                    "learned_mlp": lst["mlp_models"], "learned_tree": lst["tree_models"],
                    "learned_mean_window": round(lst["mean_window"], 2), "learned_max_window": lst["max_window"],
@@ -827,17 +948,14 @@ def main():
                   ("plain" if args.path == "learned" else "learned"): {
                       "value": round(args.steps * B / other_eager / 1e6, 3),
                       "ms_per_step": round(other_eager * 1e3 / args.steps, 6)}},
-        "learned_vs_plain_b1024": round((value / other_value) if args.path == "learned" else (other_value / value), 3),
+        "learned_vs_plain_b1024": learned_ratio,
         "sweep": sweep,
         "size_sweep_b1024": size_sweep,
         "large_batch": large,
         "levelwise": levelwise,
         "latency_regime": latency,
         "mixed_90_10": mixed,
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_lookup<unsigned long, 8, 4, 2, true, false> (B=2^20, warm)",
-                     "algorithmic_bytes": ab["bytes"]},
+        "roofline": roofline,
         "range": rng_row,
         "insert": ins_row,
         "learned_stale": stale_row,
@@ -846,13 +964,66 @@ def main():
         "train_s": round(train_s, 3),
     }
     if serving:
-        line["serving"] = serving
+        detail["serving"] = serving
+    cpu = None
     if not args.no_cpu:
-        threads = len(os.sched_getaffinity(0))
-        cq = [allq[i * B:(i + 1) * B] for i in range(16)]
-        line["cpu_baseline"] = cpu_baseline(keys, vals, cq, threads)
-        line["cpu_baseline_1thread"] = cpu_baseline(keys, vals, cq[:4], 1, budget_s=4.0)
-    print(json.dumps(line), flush=True)
+        cq = synth.present_queries(keys, 1 << 20, SEED, purpose=1100)
+        cpu, cpu_rows = cpu_baseline(keys, vals, cq, B)
+        detail["cpu_baseline"] = cpu
+        detail["cpu_baseline_rows"] = {str(k): v for k, v in cpu_rows.items()}
+        print("[bench] cpu baseline done", file=sys.stderr, flush=True)
+
+    # the whole record goes to a file and to stderr; stdout ends with one
+    # compact line that carries the headline, the roofline and the baseline
+    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+    with open(os.path.join(ROOT, "gpurun_out", "bench_detail.json"), "w") as fh:
+        json.dump(detail, fh, indent=1)
+    print("[bench] detail " + json.dumps(detail), file=sys.stderr, flush=True)
+
+    def sweep_pair(dist, b):
+        r = sweep[dist][str(b)]
+        return [r["plain"]["us_per_batch"], r["learned"]["us_per_batch"]]
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Mops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"B=1024 lookup batches of uniform present keys on a bulk-loaded B+-tree of "
+                               f"2^{args.log2n} uniform u64 keys (fanout 16, 16 keys per leaf, height "
+                               f"{st['height']}), {args.path} path, HIP graph replays",
+                   "keys": n, "batch": B, "path": args.path},
+        "roofline": roofline,
+        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in
+                                                  ("value", "unit", "cores", "kind", "sample", "by_threads",
+                                                   "cpu_model")},
+        "learned_vs_plain_b1024": learned_ratio,
+        "plain": {"value": round(value if args.path == "plain" else other_value, 3),
+                  "ms_per_step": round((ms_per_step if args.path == "plain" else other_elapsed * 1e3 / args.steps),
+                                       6)},
+        "us_per_batch_plain_learned": {d: {str(b): sweep_pair(d, b) for b in (1, 8, 64, 256, 1024)}
+                                       for d in ("uniform", "zipf")},
+        "b2p20_us": {"warm": round(warm_avg, 2), "cold": cold_us},
+        "insert_us": {k: ins_row["us_per_batch"][k] for k in ("1", "1024", str(BL))},
+        "detail": "gpurun_out/bench_detail.json (also on stderr)",
+    }
+    if serving:
+        line["serving_p99_us_at_0.5"] = {p: serving[p]["0.5"]["p99_us"] for p in ("plain", "learned")}
+    out = json.dumps(line, separators=(",", ":"))
+    for k in ("us_per_batch_plain_learned", "serving_p99_us_at_0.5", "insert_us"):
+        if len(out) < 4000:
+            break
+        line.pop(k, None)
+        out = json.dumps(line, separators=(",", ":"))
+    print(out, flush=True)
 
 
 if __name__ == "__main__":

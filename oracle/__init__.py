@@ -78,6 +78,8 @@ def lib():
         L.bpt_bulk_load.restype = i32
         L.bpt_insert_batch.argtypes = [vp, _u64p, _u64p, u64, _u8p]
         L.bpt_lookup_batch.argtypes = [vp, _u64p, u64, _u64p, _u8p, i32]
+        L.bpt_lookup_batches_timed.argtypes = [vp, _u64p, u64, u64, _u64p, _u8p, i32, _u64p]
+        L.bpt_lookup_batches_timed.restype = i32
         L.bpt_range_batch.argtypes = [vp, _u64p, _u64p, _u32p, _u64p, u64, _u64p, _u64p, _u32p]
         L.bpt_stats.argtypes = [vp, _u64p]
         L.bpt_levelwise.argtypes = [vp, _u64p, u64, _u64p, _u8p, _u32p, _u64p, _u64p, _u64p, u64]
@@ -202,6 +204,20 @@ class PointerTree:
         fo = np.empty(len(q), dtype=np.uint8)
         lib().bpt_lookup_batch(self.h, q, len(q), vo, fo, threads)
         return _narrow(vo, self.width), fo
+
+    def lookup_batches_timed(self, q, B: int, threads: int = 1):
+        """len(q) // B batches of B queries, each split evenly over
+        `threads` threads created once (a barrier before and after every
+        batch).  Returns (values, found, seconds per batch)."""
+        q = _w(q)
+        nb = len(q) // B
+        q = np.ascontiguousarray(q[:nb * B])
+        vo = np.empty(max(1, nb * B), dtype=np.uint64)
+        fo = np.empty(max(1, nb * B), dtype=np.uint8)
+        tn = np.zeros(max(1, nb), dtype=np.uint64)
+        if lib().bpt_lookup_batches_timed(self.h, q, nb, B, vo, fo, threads, tn) != 0:
+            raise RuntimeError("could not start the lookup threads")
+        return _narrow(vo[:nb * B], self.width), fo[:nb * B], tn[:nb].astype(np.float64) * 1e-9
 
     def lookup_levelwise(self, sorted_q):
         """Level-wise search of an ascending batch (Sections IV-A, IV-F).

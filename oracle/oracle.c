@@ -36,10 +36,12 @@
  * the caller.  `width` (32 or 64) only decides the all-ones miss value and
  * the largest key.
  */
+#define _POSIX_C_SOURCE 200809L
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #include <pthread.h>
+#include <time.h>
 
 typedef uint64_t u64;
 typedef uint32_t u32;
@@ -379,6 +381,85 @@ void bpt_lookup_batch(const bptree* t, const u64* q, u64 B, u64* vout, uint8_t* 
     }
     for (int i = 0; i < threads; i++) pthread_join(th[i], NULL);
     free(th); free(jobs);
+}
+
+/*
+ * Timed lookup batches for the CPU baseline (the paper times its CPU tree
+ * with the batch split evenly over the threads, Section V-F, and a steady
+ * clock, Section V-C).  nb batches of B queries, q[b*B .. b*B+B), each split
+ * evenly over `threads` threads that are created once: the threads meet at a
+ * barrier before and after every batch, and the calling thread (worker 0)
+ * reads CLOCK_MONOTONIC at both, so times_ns[b] covers exactly batch b's
+ * lookups plus one barrier.  Results as bpt_lookup_batch.  Returns 0, or -1
+ * if the threads could not be started.
+ */
+typedef struct {
+    pthread_mutex_t mu; pthread_cond_t cv; int go;   /* 1 run, -1 abort */
+    pthread_barrier_t bar;
+} pool_gate;
+
+typedef struct {
+    const bptree* t; const u64* q; u64 nb, B; u64* vout; uint8_t* fout;
+    int T, id; pool_gate* g; u64* times;
+} pool_job;
+
+static u64 now_ns(void) {
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (u64)ts.tv_sec * 1000000000ull + (u64)ts.tv_nsec;
+}
+
+static void* pool_worker(void* p) {
+    pool_job* j = p;
+    pthread_mutex_lock(&j->g->mu);
+    while (j->g->go == 0) pthread_cond_wait(&j->g->cv, &j->g->mu);
+    int go = j->g->go;
+    pthread_mutex_unlock(&j->g->mu);
+    if (go < 0) return NULL;
+    for (u64 b = 0; b < j->nb; b++) {
+        u64 t0 = 0;
+        pthread_barrier_wait(&j->g->bar);
+        if (j->id == 0) t0 = now_ns();
+        u64 base = b * j->B;
+        lk_job w = { j->t, j->q + base, (u64)j->id * j->B / j->T, (u64)(j->id + 1) * j->B / j->T,
+                     j->vout + base, j->fout + base };
+        lk_worker(&w);
+        pthread_barrier_wait(&j->g->bar);
+        if (j->id == 0) j->times[b] = now_ns() - t0;
+    }
+    return NULL;
+}
+
+int bpt_lookup_batches_timed(const bptree* t, const u64* q, u64 nb, u64 B, u64* vout, uint8_t* fout,
+                             int threads, u64* times_ns) {
+    if (threads < 1) threads = 1;
+    pool_gate g;
+    pthread_mutex_init(&g.mu, NULL);
+    pthread_cond_init(&g.cv, NULL);
+    g.go = 0;
+    pthread_barrier_init(&g.bar, NULL, (unsigned)threads);
+    pthread_t* th = malloc(sizeof(pthread_t) * threads);
+    pool_job* jobs = malloc(sizeof(pool_job) * threads);
+    int started = 1;
+    for (int i = 0; i < threads; i++)
+        jobs[i] = (pool_job){ t, q, nb, B, vout, fout, threads, i, &g, times_ns };
+    for (int i = 1; i < threads; i++) {
+        if (pthread_create(&th[i], NULL, pool_worker, &jobs[i]) != 0) break;
+        started++;
+    }
+    /* every thread must be running before any reaches the barrier */
+    pthread_mutex_lock(&g.mu);
+    g.go = started == threads ? 1 : -1;
+    pthread_cond_broadcast(&g.cv);
+    pthread_mutex_unlock(&g.mu);
+    if (g.go > 0) pool_worker(&jobs[0]);
+    for (int i = 1; i < started; i++) pthread_join(th[i], NULL);
+    int rc = g.go > 0 ? 0 : -1;
+    pthread_barrier_destroy(&g.bar);
+    pthread_cond_destroy(&g.cv);
+    pthread_mutex_destroy(&g.mu);
+    free(th); free(jobs);
+    return rc;
 }
 
 /* range via the leaf chain; same contract as ora_range */

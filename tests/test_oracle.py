@@ -240,6 +240,23 @@ def test_iqm_iqr():
     assert oracle.iqr([1, 2, 3, 4, 5]) == 2.0
 
 
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_timed_batches_match_plain_lookup(threads):
+    """The timed CPU-baseline path (threads created once, a barrier per
+    batch) answers exactly as the plain definition, present and absent keys
+    alike, and reports one positive time per batch."""
+    keys = np.array(synth.uniform_keys(5000, 11, 64), dtype=np.uint64)
+    vals = synth.values_for(keys, 11, 64)
+    pt = oracle.PointerTree(16, 16, 64)
+    pt.bulk_load(keys, vals)
+    q = synth.mixed_queries(keys, 7 * 100, 12, 64)
+    v, f, t = pt.lookup_batches_timed(q, 100, threads)
+    sa = oracle.SortedArray(keys, vals, 64)
+    ev, ef = sa.lookup(q)
+    assert np.array_equal(f, ef) and np.array_equal(v, ev)
+    assert len(t) == 7 and (t > 0).all()
+
+
 # ---------------------------------------------------------- planted mistakes
 
 def _tree_export(n=3000, width=64):
