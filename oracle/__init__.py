@@ -71,6 +71,12 @@ def lib():
         L.ora_delete.argtypes = [_u64p, _u64p, u64, _u64p, u64, _u64p, _u64p, _u8p]
         L.ora_delete.restype = u64
         L.ora_range.argtypes = [_u64p, _u64p, u64, _u64p, _u64p, _u32p, _u64p, u64, _u64p, _u64p, _u32p]
+        L.orb_sort.argtypes = [_u8p, _u64p, u64, i32, _u8p, _u64p]
+        L.orb_sort.restype = i32
+        L.orb_lookup.argtypes = [_u8p, _u64p, u64, i32, _u8p, u64, _u64p, _u8p]
+        L.orb_range.argtypes = [_u8p, _u64p, u64, i32, _u8p, _u8p, _u32p, _u64p, u64, _u8p, _u64p, _u32p]
+        L.orb_check_export.argtypes = [_u8p, u64, _u8p, _u64p, u64, C.POINTER(u64)]
+        L.orb_check_export.restype = C.c_uint32
         L.bpt_create.argtypes = [i32, i32, i32]
         L.bpt_create.restype = vp
         L.bpt_free.argtypes = [vp]
@@ -111,6 +117,61 @@ def _offsets(maxc) -> np.ndarray:
     if len(m) > 1:
         off[1:] = np.cumsum(m)[:-1]
     return off
+
+
+def _kb_rows(keys, kb: int) -> np.ndarray:
+    """Packed kb-byte keys as a C-contiguous (n, kb) uint8 array."""
+    a = np.ascontiguousarray(np.asarray(keys, dtype=np.uint8))
+    return a.reshape(-1, kb) if a.size else np.zeros((0, kb), dtype=np.uint8)
+
+
+class SortedBytes:
+    """State S over keys of kb bytes (the paper's 32-byte keys) compared as
+    byte strings, byte 0 first, with 8-byte values: sorted distinct keys,
+    lookup by binary search, range as a sorted slice (plain definitions)."""
+
+    def __init__(self, keys=None, vals=(), kb: int = 32):
+        self.kb = kb
+        k = _kb_rows(keys if keys is not None else np.zeros((0, kb), np.uint8), kb)
+        v = np.ascontiguousarray(np.asarray(vals, dtype=np.uint64))
+        n = len(k)
+        self.keys = np.zeros((max(n, 1), kb), dtype=np.uint8)
+        self.vals = np.zeros(max(n, 1), dtype=np.uint64)
+        if lib().orb_sort(k.reshape(-1) if n else np.zeros(1, np.uint8), v if n else np.zeros(1, np.uint64), n, kb,
+                          self.keys.reshape(-1), self.vals):
+            raise ValueError("duplicate keys")
+        self.keys, self.vals = self.keys[:n], self.vals[:n]
+
+    def __len__(self):
+        return len(self.keys)
+
+    def _flat(self):
+        return (self.keys.reshape(-1) if len(self.keys) else np.zeros(1, np.uint8),
+                self.vals if len(self.vals) else np.zeros(1, np.uint64))
+
+    def lookup(self, q):
+        q = _kb_rows(q, self.kb)
+        B = len(q)
+        vo = np.empty(max(B, 1), dtype=np.uint64)
+        fo = np.empty(max(B, 1), dtype=np.uint8)
+        k, v = self._flat()
+        lib().orb_lookup(k, v, len(self.keys), self.kb, q.reshape(-1) if B else np.zeros(1, np.uint8), B, vo, fo)
+        return vo[:B], fo[:B]
+
+    def range(self, lo, hi, maxc):
+        lo, hi = _kb_rows(lo, self.kb), _kb_rows(hi, self.kb)
+        mc = np.ascontiguousarray(np.asarray(maxc, dtype=np.uint32))
+        off = _offsets(mc)
+        tot = int(mc.astype(np.uint64).sum())
+        ok = np.zeros((max(tot, 1), self.kb), dtype=np.uint8)
+        ov = np.zeros(max(tot, 1), dtype=np.uint64)
+        cnt = np.zeros(max(len(mc), 1), dtype=np.uint32)
+        k, v = self._flat()
+        z = np.zeros(1, np.uint8)
+        lib().orb_range(k, v, len(self.keys), self.kb, lo.reshape(-1) if len(lo) else z,
+                        hi.reshape(-1) if len(hi) else z, mc if len(mc) else np.zeros(1, np.uint32),
+                        off if len(off) else np.zeros(1, np.uint64), len(mc), ok.reshape(-1), ov, cnt)
+        return cnt[:len(mc)], off, ok, ov
 
 
 class SortedArray:
@@ -264,13 +325,22 @@ class PointerTree:
 
 def check_export(buf: np.ndarray, expect_n: int | None = None):
     """Check a flat tree export.  Returns (violation_bits, keys, vals) where
-    keys/vals is the in-order sequence (u64)."""
+    keys/vals is the in-order sequence: keys as u64 for 4- and 8-byte keys,
+    as an (n, 32) uint8 array for 32-byte keys; values as u64."""
     buf = np.ascontiguousarray(np.asarray(buf, dtype=np.uint8))
     if len(buf) >= 48:
         nk = int(np.frombuffer(buf[40:48].tobytes(), dtype=np.uint64)[0])
+        kb = int(np.frombuffer(buf[4:8].tobytes(), dtype=np.uint32)[0])
     else:
-        nk = 0
+        nk, kb = 0, 8
     cap = max(nk, expect_n or 0) + 1
+    if kb > 8:
+        okb = np.zeros(cap * kb, dtype=np.uint8)
+        ov = np.zeros(cap, dtype=np.uint64)
+        nout = C.c_uint64(0)
+        v = lib().orb_check_export(buf, len(buf), okb, ov, cap, C.byref(nout))
+        m = min(int(nout.value), cap)
+        return int(v), okb.reshape(cap, kb)[:m], ov[:m]
     ok = np.zeros(cap, dtype=np.uint64)
     ov = np.zeros(cap, dtype=np.uint64)
     nout = C.c_uint64(0)

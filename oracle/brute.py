@@ -80,3 +80,50 @@ class Brute:
     def items(self):
         s = sorted(self.pairs)
         return [p[0] for p in s], [p[1] for p in s]
+
+
+class BruteBytes:
+    """Brute force over byte-string keys (the paper's 32-byte keys) with
+    8-byte values: keys are Python bytes, whose built-in order is the
+    byte-by-byte order with byte 0 first, each byte unsigned."""
+
+    def __init__(self, keys=(), vals=()):
+        self.pairs = []
+        for k, v in zip(keys, vals):
+            k = bytes(k)
+            for p in self.pairs:
+                if p[0] == k:
+                    raise ValueError("duplicate key")
+            self.pairs.append((k, int(v)))
+
+    def lookup(self, q):
+        vals, found = [], []
+        for k in q:
+            k = bytes(k)
+            hit = None
+            for p in self.pairs:
+                if p[0] == k:
+                    hit = p[1]
+            vals.append((1 << 64) - 1 if hit is None else hit)
+            found.append(0 if hit is None else 1)
+        return vals, found
+
+    def range(self, lo, hi, maxc):
+        out = []
+        for a, b, m in zip(lo, hi, maxc):
+            a, b = bytes(a), bytes(b)
+            sel = [p for p in self.pairs if a <= p[0] <= b]
+            # selection sort, so the order owes nothing to a library sort
+            res = []
+            while sel and len(res) < int(m):
+                j = 0
+                for t in range(1, len(sel)):
+                    if sel[t][0] < sel[j][0]:
+                        j = t
+                res.append(sel.pop(j))
+            out.append(res)
+        return out
+
+    def items(self):
+        return sorted(self.pairs)
+

@@ -158,6 +158,95 @@ void ora_range(const u64* keys, const u64* vals, u64 n, const u64* lo, const u64
     }
 }
 
+/* ------------------------------------------------------ O2, byte keys -- */
+
+/*
+ * Keys of kb bytes (the paper's 32-byte search keys, Section IV-C).  Two
+ * keys compare as byte strings: the first byte in which they differ decides,
+ * bytes taken as unsigned and byte 0 first.  That is the order the paper's
+ * 32 per-byte comparators reach once its cascading priority rule has picked
+ * the most significant byte that is not equal (Section IV-E), i.e. memcmp.
+ * Values are 8 bytes, the paper's data entries (Section IV-B).  Keys are
+ * packed kb bytes apart; the oracle keeps them sorted and distinct.
+ */
+
+/* ascending order of n packed keys: idx receives a permutation of 0..n-1,
+ * ties kept in input order (a plain top-down merge sort) */
+static void msort_idx(const uint8_t* keys, int kb, u64* idx, u64* tmp, u64 lo, u64 hi) {
+    if (hi - lo < 2) return;
+    u64 mid = lo + (hi - lo) / 2;
+    msort_idx(keys, kb, idx, tmp, lo, mid);
+    msort_idx(keys, kb, idx, tmp, mid, hi);
+    u64 a = lo, b = mid, o = lo;
+    while (a < mid || b < hi) {
+        if (b >= hi || (a < mid && memcmp(keys + idx[a] * kb, keys + idx[b] * kb, (size_t)kb) <= 0))
+            tmp[o++] = idx[a++];
+        else
+            tmp[o++] = idx[b++];
+    }
+    memcpy(idx + lo, tmp + lo, (hi - lo) * sizeof(u64));
+}
+
+/*
+ * Sort n (key, value) pairs by key into out_keys/out_vals.  Returns 0, or 1
+ * when two keys are equal (a tree holds each key once; the output is then
+ * sorted but not distinct).
+ */
+int orb_sort(const uint8_t* keys, const u64* vals, u64 n, int kb, uint8_t* out_keys, u64* out_vals) {
+    u64* idx = malloc(sizeof(u64) * (n ? n : 1));
+    u64* tmp = malloc(sizeof(u64) * (n ? n : 1));
+    for (u64 i = 0; i < n; i++) idx[i] = i;
+    msort_idx(keys, kb, idx, tmp, 0, n);
+    int dup = 0;
+    for (u64 i = 0; i < n; i++) {
+        memcpy(out_keys + i * kb, keys + idx[i] * kb, (size_t)kb);
+        out_vals[i] = vals[idx[i]];
+        if (i && memcmp(out_keys + (i - 1) * kb, out_keys + i * kb, (size_t)kb) == 0) dup = 1;
+    }
+    free(idx); free(tmp);
+    return dup;
+}
+
+/* index of the first of the n sorted keys that is >= k */
+static u64 lower_bound_b(const uint8_t* keys, u64 n, int kb, const uint8_t* k) {
+    u64 lo = 0, hi = n;
+    while (lo < hi) {
+        u64 mid = lo + (hi - lo) / 2;
+        if (memcmp(keys + mid * kb, k, (size_t)kb) < 0) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+/* lookup: the value of q[i] if present, else all ones, and found 1 / 0 */
+void orb_lookup(const uint8_t* keys, const u64* vals, u64 n, int kb, const uint8_t* q, u64 B,
+                u64* vout, uint8_t* fout) {
+    for (u64 i = 0; i < B; i++) {
+        const uint8_t* k = q + i * kb;
+        u64 p = lower_bound_b(keys, n, kb, k);
+        if (p < n && memcmp(keys + p * kb, k, (size_t)kb) == 0) { vout[i] = vals[p]; fout[i] = 1; }
+        else { vout[i] = ~0ull; fout[i] = 0; }
+    }
+}
+
+/* range: the pairs with lo[i] <= key <= hi[i], ascending, the first maxc[i]
+ * of them, written from position off[i]; count[i] = how many */
+void orb_range(const uint8_t* keys, const u64* vals, u64 n, int kb, const uint8_t* lo, const uint8_t* hi,
+               const u32* maxc, const u64* off, u64 B, uint8_t* out_keys, u64* out_vals, u32* count) {
+    for (u64 i = 0; i < B; i++) {
+        const uint8_t* l = lo + i * kb;
+        const uint8_t* h = hi + i * kb;
+        u64 p = lower_bound_b(keys, n, kb, l);
+        u32 c = 0;
+        if (memcmp(l, h, (size_t)kb) <= 0)
+            while (p < n && memcmp(keys + p * kb, h, (size_t)kb) <= 0 && c < maxc[i]) {
+                memcpy(out_keys + (off[i] + c) * kb, keys + p * kb, (size_t)kb);
+                out_vals[off[i] + c] = vals[p];
+                c++; p++;
+            }
+        count[i] = c;
+    }
+}
+
 /* ------------------------------------------------------------------ O3 -- */
 
 #define MAXF 64 /* largest order supported */
@@ -651,26 +740,45 @@ u64 bpt_export(const bptree* t, uint8_t* buf, u64 bytes) {
 
 typedef struct {
     const uint8_t* inner; const uint8_t* leaves;
-    int kb, F, C; u64 ni, nl, rin, rlf, maxk;
+    int kb, vb, F, C; u64 ni, nl, rin, rlf;
+    uint8_t maxk[32];                  /* the largest key: kb bytes of 0xFF */
     uint8_t* seen_i; uint8_t* seen_l;
-    u32* leaf_order; u64 n_order;   /* leaves in in-order traversal */
-    u64* out_keys; u64* out_vals; u64 out_cap; u64 n_out;
-    u32 viol; int height; u64 n_leaves_reached;
+    u32* leaf_order; u64 n_order;      /* leaves in in-order traversal */
+    /* in-order output: keys as u64 (kb <= 8) or as kb packed bytes */
+    u64* out_keys; uint8_t* out_kbytes; u64* out_vals; u64 out_cap; u64 n_out;
+    const uint8_t* prev_key;           /* last key emitted (I1 across leaves) */
+    u32 viol; int height;
 } chk;
 
-static u64 ik(const chk* c, u64 node, int i) { return get_key(c->inner + node * c->rin + (u64)i * c->kb, c->kb); }
+/* keys of 4 or 8 bytes are little-endian unsigned integers; longer keys
+ * compare as byte strings (the byte-key order above) */
+static int kcmp(const chk* c, const uint8_t* a, const uint8_t* b) {
+    if (c->kb <= 8) { u64 x = get_key(a, c->kb), y = get_key(b, c->kb); return x < y ? -1 : x > y; }
+    return memcmp(a, b, (size_t)c->kb);
+}
+static const uint8_t* ik(const chk* c, u64 node, int i) { return c->inner + node * c->rin + (u64)i * c->kb; }
 static u32 ic(const chk* c, u64 node, int i) { u32 r; memcpy(&r, c->inner + node * c->rin + (u64)c->F * c->kb + (u64)i * 4, 4); return r; }
-static u64 lk(const chk* c, u64 leaf, int i) { return get_key(c->leaves + leaf * c->rlf + (u64)i * c->kb, c->kb); }
-static u64 lv(const chk* c, u64 leaf, int i) { return get_key(c->leaves + leaf * c->rlf + (u64)(c->C + i) * c->kb, c->kb); }
-static u32 lcnt(const chk* c, u64 leaf) { u32 r; memcpy(&r, c->leaves + leaf * c->rlf + (u64)2 * c->C * c->kb, 4); return r; }
-static u32 lnext(const chk* c, u64 leaf) { u32 r; memcpy(&r, c->leaves + leaf * c->rlf + (u64)2 * c->C * c->kb + 4, 4); return r; }
+static const uint8_t* lk(const chk* c, u64 leaf, int i) { return c->leaves + leaf * c->rlf + (u64)i * c->kb; }
+static u64 lv(const chk* c, u64 leaf, int i) { return get_key(c->leaves + leaf * c->rlf + (u64)c->C * c->kb + (u64)i * c->vb, c->vb); }
+static u32 lcnt(const chk* c, u64 leaf) { u32 r; memcpy(&r, c->leaves + leaf * c->rlf + (u64)c->C * (c->kb + c->vb), 4); return r; }
+static u32 lnext(const chk* c, u64 leaf) { u32 r; memcpy(&r, c->leaves + leaf * c->rlf + (u64)c->C * (c->kb + c->vb) + 4, 4); return r; }
+
+static void emit(chk* c, const uint8_t* k, u64 v) {
+    if (c->prev_key && kcmp(c, c->prev_key, k) >= 0) c->viol |= V_SORTED;   /* I1 across leaves */
+    c->prev_key = k;
+    if (c->n_out < c->out_cap) {
+        if (c->out_keys) c->out_keys[c->n_out] = get_key(k, c->kb);
+        else memcpy(c->out_kbytes + c->n_out * c->kb, k, (size_t)c->kb);
+        c->out_vals[c->n_out] = v;
+    }
+    c->n_out++;
+}
 
 /*
  * Visit node `ref` at depth d (root = 1).  Every key below must satisfy
- * lo < key <= hi, where has_lo/has_hi say whether the bound exists.
+ * lo < key <= hi; a null bound is absent.
  */
-static void visit(chk* c, u32 ref, int d, int is_root, int many_leaves,
-                  int has_lo, u64 lo, int has_hi, u64 hi) {
+static void visit(chk* c, u32 ref, int d, int is_root, int many_leaves, const uint8_t* lo, const uint8_t* hi) {
     if (ref == REF_NONE) { c->viol |= V_REACH; return; }
     if (ref & REF_LEAF) {
         u64 id = ref & ~REF_LEAF;
@@ -683,14 +791,13 @@ static void visit(chk* c, u32 ref, int d, int is_root, int many_leaves,
         if (n > (u32)c->C) { c->viol |= V_FILL; n = (u32)c->C; }
         if (many_leaves && n < (u32)((c->C + 1) / 2)) c->viol |= V_FILL;
         for (u32 i = 0; i < n; i++) {
-            u64 k = lk(c, id, (int)i);
-            if (i && lk(c, id, (int)i - 1) >= k) c->viol |= V_SORTED;
-            if ((has_lo && k <= lo) || (has_hi && k > hi)) c->viol |= V_SEPARATOR;
-            if (c->n_out < c->out_cap) { c->out_keys[c->n_out] = k; c->out_vals[c->n_out] = lv(c, id, (int)i); }
-            c->n_out++;
+            const uint8_t* k = lk(c, id, (int)i);
+            if (i && kcmp(c, lk(c, id, (int)i - 1), k) >= 0) c->viol |= V_SORTED;
+            if ((lo && kcmp(c, k, lo) <= 0) || (hi && kcmp(c, k, hi) > 0)) c->viol |= V_SEPARATOR;
+            emit(c, k, lv(c, id, (int)i));
         }
-        u64 pad = n ? lk(c, id, (int)n - 1) : c->maxk;
-        for (u32 i = n; i < (u32)c->C; i++) if (lk(c, id, (int)i) != pad) c->viol |= V_PADDING;
+        const uint8_t* pad = n ? lk(c, id, (int)n - 1) : c->maxk;
+        for (u32 i = n; i < (u32)c->C; i++) if (kcmp(c, lk(c, id, (int)i), pad) != 0) c->viol |= V_PADDING;
         return;
     }
     if (ref >= c->ni) { c->viol |= V_REACH; return; }
@@ -700,50 +807,58 @@ static void visit(chk* c, u32 ref, int d, int is_root, int many_leaves,
     int n = 0;
     while (n < c->F && ic(c, ref, n) != REF_NONE) n++;
     for (int i = n; i < c->F; i++) if (ic(c, ref, i) != REF_NONE) c->viol |= V_PADDING;
+    /* Section III: a non-root inner node has at least m/2 children, an
+       inner root at least two */
     if (is_root ? n < 2 : n < (c->F + 1) / 2) c->viol |= V_FILL;
-    for (int i = n - 1 < 0 ? 0 : n - 1; i < c->F; i++) if (ik(c, ref, i) != c->maxk) c->viol |= V_PADDING;
+    for (int i = n - 1 < 0 ? 0 : n - 1; i < c->F; i++) if (kcmp(c, ik(c, ref, i), c->maxk) != 0) c->viol |= V_PADDING;
     for (int i = 0; i + 1 < n; i++) {
-        u64 s = ik(c, ref, i);
-        if ((has_lo && s <= lo) || (has_hi && s > hi)) c->viol |= V_SEPARATOR;
-        if (i && ik(c, ref, i - 1) >= s) c->viol |= V_SEPARATOR;
+        const uint8_t* sp = ik(c, ref, i);
+        if ((lo && kcmp(c, sp, lo) <= 0) || (hi && kcmp(c, sp, hi) > 0)) c->viol |= V_SEPARATOR;
+        if (i && kcmp(c, ik(c, ref, i - 1), sp) >= 0) c->viol |= V_SEPARATOR;
     }
     for (int i = 0; i < n; i++) {
-        int clo = i ? 1 : has_lo; u64 vlo = i ? ik(c, ref, i - 1) : lo;
-        int chi = (i + 1 < n) ? 1 : has_hi; u64 vhi = (i + 1 < n) ? ik(c, ref, i) : hi;
-        visit(c, ic(c, ref, i), d + 1, 0, many_leaves, clo, vlo, chi, vhi);
+        const uint8_t* clo = i ? ik(c, ref, i - 1) : lo;
+        const uint8_t* chi = (i + 1 < n) ? ik(c, ref, i) : hi;
+        visit(c, ic(c, ref, i), d + 1, 0, many_leaves, clo, chi);
     }
 }
 
 /*
- * Check an exported tree.  Writes the in-order (key, value) sequence into
- * out_keys/out_vals (up to out_cap) and its length into *n_out.
- * Returns the violation bits (0 = all invariants hold).
+ * Check an exported tree whose keys are kb = 4, 8 or 32 bytes.  The header's
+ * last u32 (reserved in the library's 4/8-byte format) gives the value
+ * width: 0 means the key width; 32-byte keys carry 8-byte values.  Leaf
+ * records are key[leaf_cap] (kb each), value[leaf_cap] (vb each), u32 count,
+ * u32 next.  The in-order pairs go to out_keys (u64, when kb <= 8) or
+ * out_kbytes (kb packed bytes each) and out_vals, up to out_cap of them;
+ * *n_out receives how many the tree holds.  Returns the violation bits
+ * (0 = all invariants hold).
  */
-u32 ora_check_export(const uint8_t* buf, u64 bytes, u64* out_keys, u64* out_vals, u64 out_cap,
-                     u64* n_out) {
+static u32 check_export(const uint8_t* buf, u64 bytes, u64* out_keys, uint8_t* out_kbytes, u64* out_vals,
+                        u64 out_cap, u64* n_out, int* kb_out) {
     *n_out = 0;
     if (bytes < 48) return V_FORMAT;
     u32 hdr[10]; u64 nk;
     memcpy(hdr, buf, 40); memcpy(&nk, buf + 40, 8);
-    if (hdr[0] != EX_MAGIC || (hdr[1] != 4 && hdr[1] != 8) || hdr[2] < 4 || hdr[2] > 1024 ||
-        hdr[3] < 2 || hdr[3] > 1024 || hdr[4] < 1) return V_FORMAT;
+    u32 kb = hdr[1], vb = hdr[9] ? hdr[9] : hdr[1];
+    int ok_width = ((kb == 4 || kb == 8) && vb == kb) || (kb == 32 && vb == 8);
+    if (hdr[0] != EX_MAGIC || !ok_width || hdr[2] < 4 || hdr[2] > 1024 || hdr[3] < 2 || hdr[3] > 1024 ||
+        hdr[4] < 1) return V_FORMAT;
+    if (kb_out) *kb_out = (int)kb;
+    if ((kb > 8) != (out_kbytes != NULL)) return V_FORMAT;
     chk c;
     memset(&c, 0, sizeof c);
-    c.kb = (int)hdr[1]; c.F = (int)hdr[2]; c.C = (int)hdr[3]; c.height = (int)hdr[4];
+    c.kb = (int)kb; c.vb = (int)vb; c.F = (int)hdr[2]; c.C = (int)hdr[3]; c.height = (int)hdr[4];
     c.ni = hdr[7]; c.nl = hdr[8];
-    c.rin = (u64)c.F * (c.kb + 4); c.rlf = (u64)c.C * 2 * c.kb + 8;
+    c.rin = (u64)c.F * (c.kb + 4); c.rlf = (u64)c.C * (c.kb + c.vb) + 8;
     if (48 + c.ni * c.rin + c.nl * c.rlf > bytes) return V_FORMAT;
     c.inner = buf + 48; c.leaves = c.inner + c.ni * c.rin;
-    c.maxk = c.kb == 4 ? 0xFFFFFFFFull : ~0ull;
+    memset(c.maxk, 0xFF, sizeof c.maxk);
     c.seen_i = calloc(c.ni + 1, 1); c.seen_l = calloc(c.nl + 1, 1);
     c.leaf_order = malloc(sizeof(u32) * (c.nl + 1));
-    c.out_keys = out_keys; c.out_vals = out_vals; c.out_cap = out_cap;
+    c.out_keys = out_keys; c.out_kbytes = out_kbytes; c.out_vals = out_vals; c.out_cap = out_cap;
     u32 root = hdr[5];
     int many = (root & REF_LEAF) == 0 || root == REF_NONE;
-    visit(&c, root, 1, 1, many, 0, 0, 0, 0);
-    /* I1 across leaves: the in-order sequence must be strictly ascending */
-    u64 lim = c.n_out < c.out_cap ? c.n_out : c.out_cap;
-    for (u64 i = 1; i < lim; i++) if (out_keys[i - 1] >= out_keys[i]) c.viol |= V_SORTED;
+    visit(&c, root, 1, 1, many, NULL, NULL);
     /* I4 */
     if (c.n_out != nk) c.viol |= V_COUNT;
     /* I6: the chain from first_leaf must equal the in-order leaf sequence */
@@ -757,4 +872,16 @@ u32 ora_check_export(const uint8_t* buf, u64 bytes, u64* out_keys, u64* out_vals
     *n_out = c.n_out;
     free(c.seen_i); free(c.seen_l); free(c.leaf_order);
     return c.viol;
+}
+
+/* 4- and 8-byte keys: the in-order keys and values as u64 */
+u32 ora_check_export(const uint8_t* buf, u64 bytes, u64* out_keys, u64* out_vals, u64 out_cap, u64* n_out) {
+    if (bytes >= 8) { u32 kb; memcpy(&kb, buf + 4, 4); if (kb > 8) { *n_out = 0; return V_FORMAT; } }
+    return check_export(buf, bytes, out_keys, NULL, out_vals, out_cap, n_out, NULL);
+}
+
+/* 32-byte keys: the in-order keys as packed bytes, values as u64 */
+u32 orb_check_export(const uint8_t* buf, u64 bytes, uint8_t* out_keys, u64* out_vals, u64 out_cap, u64* n_out) {
+    if (bytes >= 8) { u32 kb; memcpy(&kb, buf + 4, 4); if (kb <= 8) { *n_out = 0; return V_FORMAT; } }
+    return check_export(buf, bytes, NULL, out_keys, out_vals, out_cap, n_out, NULL);
 }
