@@ -822,7 +822,7 @@ def main():
         fpos = 0
         spec_seed = 50
         sk5 = np.sort(keys5)
-        inserted = []   # key arrays of every insert batch served so far, in admission order
+        prev_ins = [np.zeros(0, dtype=np.uint64)]   # sorted keys inserted by earlier runs
 
         def check_served(batches):
             """Every lookup asks for a key of the bulk load (inserts add fresh
@@ -831,28 +831,44 @@ def main():
             the first 16 of each batch exactly, against the bulk-loaded keys
             merged with every key inserted before the batch in admission
             order; the rest ascending from lo with present keys' values."""
-            for b in batches:
+            ins_k = [b.keys for b in batches if b.op == g.OP_INSERT]
+            ins_j = [np.full(len(b.keys), j) for j, b in enumerate(batches) if b.op == g.OP_INSERT]
+            ck = np.concatenate(ins_k) if ins_k else np.zeros(0, np.uint64)
+            cj = np.concatenate(ins_j) if ins_j else np.zeros(0, np.int64)
+            o = np.argsort(ck, kind="stable")
+            ck, cj = ck[o], cj[o]
+            pk = prev_ins[0]
+            for j, b in enumerate(batches):
                 if b.op == g.OP_LOOKUP:
-                    assert b.out1.all() and np.array_equal(b.out0, synth.values_for(b.keys, s5, 64))
+                    assert b.out1.all() and np.array_equal(b.out0, synth.values_for(b.keys, s5, 64)), ("lookup", j)
                 elif b.op == g.OP_INSERT:
-                    assert (b.out0 == 0).all()
-                    inserted.append(b.keys.copy())
+                    assert (b.out0 == 0).all(), ("insert", j)
                 else:
-                    ins_sorted = np.sort(np.concatenate(inserted)) if inserted else np.zeros(0, np.uint64)
                     off = np.concatenate([[0], np.cumsum(b.max_out.astype(np.int64))])
                     for i in range(len(b.keys)):
                         lo, mx, c = b.keys[i], int(b.max_out[i]), int(b.count[i])
                         got = b.out0[off[i]:off[i] + c]
                         if i < 16:
-                            a = sk5[np.searchsorted(sk5, lo):][:mx]
-                            bb = ins_sorted[np.searchsorted(ins_sorted, lo):][:mx]
-                            want = np.sort(np.concatenate([a, bb]))[:mx]
-                            assert np.array_equal(got, want), ("range", i)
+                            # this run's inserts admitted before batch j: a
+                            # window of them from lo, widened until it holds
+                            # mx such keys or reaches the end
+                            p0 = np.searchsorted(ck, lo)
+                            w = mx
+                            while True:
+                                sl = slice(p0, p0 + w)
+                                cur = ck[sl][cj[sl] < j]
+                                if len(cur) >= mx or p0 + w >= len(ck):
+                                    break
+                                w *= 4
+                            want = np.sort(np.concatenate([sk5[np.searchsorted(sk5, lo):][:mx],
+                                                           pk[np.searchsorted(pk, lo):][:mx], cur[:mx]]))[:mx]
+                            assert np.array_equal(got, want), ("range", j, i)
                         else:
                             assert (c == mx or c >= len(sk5) - np.searchsorted(sk5, lo)) and got[0] == lo \
-                                and (np.diff(got) > 0).all(), ("range", i)
+                                and (np.diff(got) > 0).all(), ("range", j, i)
                         base = member(sk5, got)
                         assert np.array_equal(b.out1[off[i]:off[i] + c][base], synth.values_for(got[base], s5, 64))
+            prev_ins[0] = np.sort(np.concatenate([pk, ck]))
 
         def run(srv, n_b, rate):
             nonlocal fpos, spec_seed
