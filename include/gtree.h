@@ -167,6 +167,30 @@ gt_status tree_lookup_levelwise(gt_tree* t, const void* keys, uint64_t B, uint32
                                 hipStream_t stream);
 
 /*
+ * Level-wise lookup that allocates nothing, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, results and
+ * errors as tree_lookup_levelwise, without the workspace: the library keeps
+ * a fixed scratch array of GT_LW_NOALLOC_SCRATCH_BYTES in device memory,
+ * one per GPU it runs on, held until the process ends, and uses it as the
+ * workspace.  A batch is accepted when
+ * tree_lookup_levelwise_workspace_bytes(t, B, flags) fits that size (8-byte
+ * keys: any B <= 2^18 with the library sort, B <= 2^20 presorted; 4-byte
+ * keys: B <= 2^19 and B <= 2^20); a larger one returns GT_ERR_CAPACITY with
+ * nothing enqueued.  The call makes no hipMalloc, hipFree or other
+ * allocating call; the first call on a device resolves that device's array
+ * (the tree's device must be current, as for every call).  Every call on a
+ * GPU shares its one array, whatever the tree or stream: calls that may
+ * overlap on one GPU race and must be ordered by the caller (one stream, or
+ * events).  The array keeps the last call's contents; a call needs none of
+ * them (it clears what it uses with kernels, no memset), so it is
+ * graph-capturable like tree_lookup_levelwise.
+ */
+#define GT_LW_NOALLOC_SCRATCH_BYTES (16ull << 20)
+gt_status tree_lookup_levelwise_noalloc(gt_tree* t, const void* keys, uint64_t B, uint32_t flags,
+                                        void* values_out, uint8_t* found_out, hipStream_t stream);
+
+/*
  * Insert batch.  Equivalent to inserting (keys[i], values[i]) one at a time
  * for i = 0..B-1: a present key gets its value overwritten.  status_out[i]
  * = 0 (INSERTED) when keys[i] was absent before the batch and not earlier in

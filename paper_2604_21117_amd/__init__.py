@@ -102,6 +102,7 @@ def lib():
         L.tree_lookup_levelwise_workspace_bytes.argtypes = [vp, u64, u32]
         L.tree_lookup_levelwise_workspace_bytes.restype = u64
         L.tree_lookup_levelwise.argtypes = [vp, vp, u64, u32, vp, vp, vp, u64, vp]
+        L.tree_lookup_levelwise_noalloc.argtypes = [vp, vp, u64, u32, vp, vp, vp]
         L.tree_insert_batch.argtypes = [vp, vp, vp, u64, vp, vp]
         L.tree_delete_batch.argtypes = [vp, vp, u64, vp, vp]
         L.tree_range_batch.argtypes = [vp, vp, vp, vp, vp, u64, vp, vp, vp, vp]
@@ -216,6 +217,7 @@ def tree_lookup_batch(h, keys, values_out, found_out, stream=None):
 
 
 GT_LW_PRESORTED = 1
+GT_LW_NOALLOC_SCRATCH_BYTES = 16 << 20
 
 
 def tree_lookup_levelwise_workspace_bytes(h, B: int, flags: int = 0) -> int:
@@ -226,6 +228,12 @@ def tree_lookup_levelwise(h, keys, flags, values_out, found_out, workspace, stre
     _check(lib().tree_lookup_levelwise(h, _ptr(keys), keys.numel(), flags, _ptr(values_out), _ptr(found_out),
                                        _ptr(workspace), workspace.numel(), _stream(stream)),
            "tree_lookup_levelwise")
+
+
+def tree_lookup_levelwise_noalloc(h, keys, flags, values_out, found_out, stream=None):
+    _check(lib().tree_lookup_levelwise_noalloc(h, _ptr(keys), keys.numel(), flags, _ptr(values_out),
+                                               _ptr(found_out), _stream(stream)),
+           "tree_lookup_levelwise_noalloc")
 
 
 def tree_insert_batch(h, keys, values, status_out, stream=None):

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include "common.h"
+#include "../../include/gtree.h"
 
 namespace gt {
 
@@ -60,6 +61,12 @@ struct LwLayout {
     uint64_t ha, hb, ra, rb, sk, si, sk2, si2, tmp, total;
 };
 LwLayout lw_layout(uint64_t B, int key_bytes, bool presorted);
+
+// Size of the fixed scratch array of the allocation-free level-wise lookup
+// (per device), and its address on the current device (resolved once per
+// device, then cached).
+constexpr uint64_t kLwScratchBytes = GT_LW_NOALLOC_SCRATCH_BYTES;
+hipError_t lw_scratch(void** out);
 
 // Level-wise lookup: sort the batch (unless presorted), then one kernel per
 // level for `levels` levels (at least the tree's height).

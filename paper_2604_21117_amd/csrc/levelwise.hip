@@ -36,6 +36,8 @@
 // get correct answers: runs are only cut more often.  The host launches one
 // kernel per level up to a bound on the height; a kernel whose level lies
 // below the leaves (per the device header) returns at once.
+#include <mutex>
+
 #include "common.h"
 #include "kernels.h"
 #include "prims.h"
@@ -230,5 +232,38 @@ template void launch_lookup_levelwise<uint32_t>(const TreeView<uint32_t>&, const
                                                 uint32_t, uint32_t*, uint8_t*, void*, hipStream_t);
 template void launch_lookup_levelwise<uint64_t>(const TreeView<uint64_t>&, const uint64_t*, uint64_t, bool,
                                                 uint32_t, uint64_t*, uint8_t*, void*, hipStream_t);
+
+// ---------------------------------------- allocation-free variant's scratch
+
+// The workspace of the allocation-free level-wise lookup: a fixed array in
+// device memory, one copy per GPU the library runs on, held until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on the
+// host the name is only a stand-in for the device symbol); it passes the
+// address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) uint8_t scratch[kLwScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+}  // namespace
+
+hipError_t lw_scratch(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        // the device is current: this resolves its own copy of the array
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 }  // namespace gt

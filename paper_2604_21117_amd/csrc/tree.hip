@@ -338,6 +338,28 @@ gt_status tree_lookup_levelwise(gt_tree* t, const void* keys, uint64_t B, uint32
     return hipGetLastError() == hipSuccess ? GT_OK : GT_ERR_HIP;
 }
 
+gt_status tree_lookup_levelwise_noalloc(gt_tree* t, const void* keys, uint64_t B, uint32_t flags,
+                                        void* values_out, uint8_t* found_out, hipStream_t stream) {
+    if (!t) return GT_ERR_INVALID;
+    if ((flags & ~GT_LW_PRESORTED) != 0) return GT_ERR_INVALID;
+    if (B == 0) return GT_OK;
+    if (!keys || !values_out || !found_out) return GT_ERR_INVALID;
+    if (B >= (1ull << 31)) return GT_ERR_INVALID;
+    const bool presorted = (flags & GT_LW_PRESORTED) != 0;
+    if (lw_layout(B, t->kb, presorted).total > kLwScratchBytes) return GT_ERR_CAPACITY;
+    void* ws = nullptr;
+    if (lw_scratch(&ws) != hipSuccess) return GT_ERR_HIP;
+    if (t->kb == 8)
+        launch_lookup_levelwise<uint64_t>(view<uint64_t>(t), reinterpret_cast<const uint64_t*>(keys), B,
+                                          presorted, t->h_bound, reinterpret_cast<uint64_t*>(values_out),
+                                          found_out, ws, stream);
+    else
+        launch_lookup_levelwise<uint32_t>(view<uint32_t>(t), reinterpret_cast<const uint32_t*>(keys), B,
+                                          presorted, t->h_bound, reinterpret_cast<uint32_t*>(values_out),
+                                          found_out, ws, stream);
+    return hipGetLastError() == hipSuccess ? GT_OK : GT_ERR_HIP;
+}
+
 gt_status tree_delete_batch(gt_tree* t, const void* keys, uint64_t B, uint8_t* status_out, hipStream_t stream) {
     if (!t) return GT_ERR_INVALID;
     if (B == 0) return GT_OK;
