@@ -19,7 +19,8 @@
  * Conventions shared by every call:
  *  - Pointers are DEVICE pointers unless the comment says "host".
  *  - Keys and values have the same width, key_bytes = 4 or 8; keys compare
- *    as unsigned integers.  A NOT-FOUND value is all ones at that width (the
+ *    as unsigned integers (the static tree of 32-byte keys or order 32/64
+ *    described at gt_params has 8-byte values).  A NOT-FOUND value is all ones at that width (the
  *    paper's -1) and the matching found flag is 0; the flag is authoritative
  *    because all ones is also a legal value.
  *  - Every call is asynchronous on `stream`.  Errors that the host can see
@@ -60,11 +61,37 @@ typedef enum {
     GT_ERR_DEVICE = 6     /* device error word set (other than capacity)      */
 } gt_status;
 
-/* Tree parameters (host struct).  Zero fields take the default. */
+/*
+ * Tree parameters (host struct).  Zero fields take the default.
+ *
+ * Two kinds of tree share this ABI:
+ *  - the dynamic tree: key_bytes 4 or 8, fanout 16, 16 keys per leaf;
+ *    every call below applies;
+ *  - the paper's key and node variants (Sections IV-B, IV-C, V-C), a
+ *    static tree built once and searched: key_bytes 32 with fanout 16, 32
+ *    or 64, or key_bytes 8 with fanout 32 or 64.  A node of order m has at
+ *    most m children and, below the root, at least m/2; a leaf holds at
+ *    most m - 1 keys (the paper's k_max) and, when there are two or more
+ *    leaves, at least m/2.  32-byte keys are byte strings compared byte by
+ *    byte, byte 0 most significant, each byte unsigned (the order of the
+ *    paper's bytewise comparators with the cascading priority rule,
+ *    Section IV-E); 8-byte keys are unsigned integers.  Values are 8 bytes
+ *    (the paper's data).  Buffers of 32-byte keys (keys, lo, hi, out_keys)
+ *    and the arena must be 16-byte aligned, else GT_ERR_INVALID.
+ *    tree_build, tree_lookup_batch, tree_range_batch,
+ *    tree_stats, tree_export, tree_device_error and tree_destroy apply, with
+ *    key arrays of key_bytes per key and value arrays of 8 bytes per value;
+ *    tree_insert_batch, tree_delete_batch, the level-wise lookups, li_* and
+ *    srv_create return GT_ERR_INVALID (tree_lookup_levelwise_workspace_bytes
+ *    and li_arena_bytes return 0).  Only key_bytes, fanout, leaf_cap (0 or
+ *    fanout - 1) and fill may be set; tree_arena_bytes ignores leaf_slack.
+ */
 typedef struct {
-    uint32_t key_bytes;       /* 4 or 8 (no default)                          */
-    uint32_t fanout;          /* inner order m; only 16 is supported          */
-    uint32_t leaf_cap;        /* keys per leaf; only 16 is supported          */
+    uint32_t key_bytes;       /* 4, 8 or 32 (no default)                      */
+    uint32_t fanout;          /* inner order m: 16 (default), or 32 / 64 for
+                                 the static tree (above)                      */
+    uint32_t leaf_cap;        /* keys per leaf: 16 for the dynamic tree,
+                                 fanout - 1 for the static one; 0 = that     */
     float fill;               /* bulk-load fill in [0.5, 1]; default 1.0      */
     uint32_t lanes_per_query; /* lookup lanes per query: 4, 8 or 16; 0 = by
                                  batch size (16 below 2^13 queries, else 8);
@@ -259,9 +286,12 @@ gt_status tree_device_error(gt_tree* t, hipStream_t stream);
  * Copy the tree into host memory in the flat export format (synchronises):
  *   header, 48 bytes little endian:
  *     u32 magic 0x58455447, key_bytes, fanout, leaf_cap, height, root,
- *     first_leaf, n_inner, n_leaves, reserved;  u64 n_keys
- *   n_inner inner records:  key[16] (key_bytes each), child[16] (u32)
- *   n_leaves leaf records:  key[16], value[16] (key_bytes each),
+ *     first_leaf, n_inner, n_leaves, value_bytes;  u64 n_keys
+ *     (value_bytes is 0 for the dynamic tree, meaning key_bytes; the static
+ *     tree writes 8)
+ *   n_inner inner records:  key[fanout] (key_bytes each), child[fanout] (u32)
+ *   n_leaves leaf records:  key[leaf_cap] (key_bytes each),
+ *                           value[leaf_cap] (value_bytes each),
  *                           u32 count, u32 next
  * A node reference with bit 31 set is a leaf (index in the low bits),
  * otherwise an inner node index; 0xFFFFFFFF is "none".  Inner entry i < c-1

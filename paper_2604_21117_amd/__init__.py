@@ -427,6 +427,103 @@ class Tree:
         return tree_export(self.h)
 
 
+def make_static_params(key_bytes: int, fanout: int, fill: float = 1.0) -> gt_params:
+    """Parameters of the static tree of the paper's key and node variants:
+    key_bytes 32 with fanout 16, 32 or 64, or key_bytes 8 with fanout 32 or
+    64 (leaves of fanout - 1 keys)."""
+    return gt_params(key_bytes=key_bytes, fanout=fanout, leaf_cap=0, fill=fill, lanes_per_query=0, lds_levels=0,
+                     sorted_mode=0, queries_per_group=0, max_batch=0, value_coload=0, xcd_split=0, leaf_stream=0,
+                     reserved=0)
+
+
+class StaticTree:
+    """A static tree of 32-byte keys (orders 16, 32, 64) or 8-byte keys
+    (orders 32, 64) with 8-byte values, through the same C calls as
+    :class:`Tree`.  32-byte keys are numpy (n, 32) uint8 arrays; 8-byte keys
+    uint64 arrays.  Owns its arena tensor and handle."""
+
+    def __init__(self, keys: np.ndarray, values: np.ndarray, key_bytes: int, fanout: int, fill: float = 1.0,
+                 device="cuda"):
+        torch = _torch()
+        self.kb, self.m, self.device = key_bytes, fanout, device
+        self.params = make_static_params(key_bytes, fanout, fill)
+        k = self._rows(keys)
+        n = len(k)
+        need = tree_arena_bytes(self.params, n)
+        if need == 0:
+            raise GtError(GT_ERR_INVALID, "tree_arena_bytes")
+        self.arena = torch.empty(need, dtype=torch.uint8, device=device)
+        kd = self.dev_keys(k) if n else None
+        vd = to_device(np.asarray(values, dtype=np.uint64), device) if n else None
+        h = C.c_void_p()
+        _check(lib().tree_build(C.byref(self.params), _ptr(kd), _ptr(vd), n, _ptr(self.arena), self.arena.numel(),
+                                _stream(None), C.byref(h)), "tree_build")
+        self.h = h.value
+
+    def _rows(self, a) -> np.ndarray:
+        if self.kb == 8:
+            return np.ascontiguousarray(np.asarray(a, dtype=np.uint64))
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.uint8))
+        return a.reshape(-1, self.kb)
+
+    def dev_keys(self, a):
+        """Keys to a device tensor of len(a) * key_bytes bytes."""
+        r = self._rows(a)
+        return to_device(r.view(np.uint8).reshape(-1) if self.kb == 32 else r, self.device)
+
+    def close(self):
+        h = getattr(self, "h", None)
+        if h:
+            self.h = None
+            tree_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: module globals may be gone
+            pass
+
+    def lookup_dev(self, qd, B: int, stream=None):
+        torch = _torch()
+        vo = torch.empty(B, dtype=torch.int64, device=self.device)
+        fo = torch.empty(B, dtype=torch.uint8, device=self.device)
+        _check(lib().tree_lookup_batch(self.h, _ptr(qd), B, _ptr(vo), _ptr(fo), _stream(stream)), "tree_lookup_batch")
+        return vo, fo
+
+    def lookup(self, q: np.ndarray):
+        r = self._rows(q)
+        vo, fo = self.lookup_dev(self.dev_keys(r), len(r))
+        return to_numpy(vo, np.uint64), to_numpy(fo)
+
+    def range(self, lo: np.ndarray, hi: np.ndarray, maxc: np.ndarray):
+        torch = _torch()
+        lo, hi = self._rows(lo), self._rows(hi)
+        mc = np.asarray(maxc, dtype=np.uint32)
+        B = len(mc)
+        off = np.zeros(B, dtype=np.uint64)
+        if B > 1:
+            off[1:] = np.cumsum(mc.astype(np.uint64))[:-1]
+        tot = int(mc.astype(np.uint64).sum())
+        ok = torch.empty(max(tot, 1) * self.kb, dtype=torch.uint8, device=self.device)
+        ov = torch.empty(max(tot, 1), dtype=torch.int64, device=self.device)
+        cnt = torch.empty(max(B, 1), dtype=torch.int32, device=self.device)
+        # the input tensors stay referenced until the call has enqueued its
+        # kernel (a freed block could be handed to the next allocation)
+        lod, hid = self.dev_keys(lo), self.dev_keys(hi)
+        mcd, offd = to_device(mc, self.device), to_device(off, self.device)
+        _check(lib().tree_range_batch(self.h, _ptr(lod), _ptr(hid), _ptr(mcd), _ptr(offd), B,
+                                      _ptr(ok), _ptr(ov), _ptr(cnt), _stream(None)), "tree_range_batch")
+        keys = to_numpy(ok)[:tot * self.kb]
+        keys = keys.reshape(tot, self.kb) if self.kb == 32 else keys.view(np.uint64)
+        return to_numpy(cnt, np.uint32)[:B], off, keys, to_numpy(ov, np.uint64)[:tot]
+
+    def stats(self):
+        return tree_stats(self.h)
+
+    def export(self):
+        return tree_export(self.h)
+
+
 class Learned:
     """A learned index over a :class:`Tree` (owns its arena tensor)."""
 

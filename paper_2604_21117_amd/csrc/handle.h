@@ -5,6 +5,7 @@
 #include "../../include/gtree.h"
 #include "common.h"
 #include "kernels.h"
+#include "wide.h"
 
 // Changes whenever li_train or li_set_bounds changes what a learned lookup
 // launch captures (kernel arguments, tables); a cached graph of an older
@@ -33,6 +34,9 @@ struct gt_tree {
     uint64_t inserts = 0;   // insert batches enqueued on this tree
     uint64_t deletes = 0;   // delete batches applied to this tree
     uint32_t* h_flag = nullptr;  // pinned host word a delete reads its rebuild flag into
+    gt::WideTree* wide = nullptr;  // set for a tree of 32-byte keys or order 32/64:
+                                   // static, searched by wide.hip; the fields
+                                   // above are then unused
 };
 
 

@@ -1301,12 +1301,12 @@ void launch_li_lookup(gt_learned* li, const void* keys, uint64_t B, void* values
 extern "C" {
 
 uint64_t li_arena_bytes(const gt_tree* t, const gt_li_params* p) {
-    if (!t || params_bad(p)) return 0;
+    if (!t || t->wide || params_bad(p)) return 0;
     return layout_li(nullptr, t->leaf_cap, models_of(p), t->kb);
 }
 
 gt_status li_create(gt_tree* t, const gt_li_params* p, void* arena, uint64_t arena_bytes, gt_learned** out) {
-    if (!t || !arena || !out || params_bad(p)) return GT_ERR_INVALID;
+    if (!t || t->wide || !arena || !out || params_bad(p)) return GT_ERR_INVALID;
     const uint32_t M = models_of(p);
     if (layout_li(nullptr, t->leaf_cap, M, t->kb) > arena_bytes) return GT_ERR_CAPACITY;
     gt_learned* li = new gt_learned();

@@ -477,7 +477,7 @@ gt_status submit_at(gt_server* s, const gt_request* r, double arrival, uint64_t*
 extern "C" {
 
 gt_status srv_create(gt_tree* t, gt_learned* li, const gt_srv_params* p, gt_server** out) {
-    if (!t || !out) return GT_ERR_INVALID;
+    if (!t || t->wide || !out) return GT_ERR_INVALID;
     gt_srv_params q{};
     if (p) q = *p;
     if (q.use_graphs > 2 || q.retrain_log2 > 40) return GT_ERR_INVALID;

@@ -254,6 +254,7 @@ const char* gt_status_str(gt_status s) {
 uint32_t gt_set_sort_spin_limit(uint32_t limit) { return set_sort_spin_limit(limit); }
 
 uint64_t tree_arena_bytes(const gt_params* p, uint64_t n, uint64_t leaf_slack) {
+    if (wide_selected(p)) return wide_arena_bytes(p, n);  // static: no headroom
     if (!params_ok(p)) return 0;
     std::vector<uint64_t> sizes = level_sizes_for(n, fill_of(p));
     return bytes_for_leaf_cap(static_cast<int>(p->key_bytes), max_batch_of(p), sizes[0] + leaf_slack);
@@ -261,6 +262,21 @@ uint64_t tree_arena_bytes(const gt_params* p, uint64_t n, uint64_t leaf_slack) {
 
 gt_status tree_build(const gt_params* p, const void* keys, const void* values, uint64_t n, void* arena,
                      uint64_t arena_bytes, hipStream_t stream, gt_tree** out) {
+    if (wide_selected(p)) {
+        if (!out) return GT_ERR_INVALID;
+        WideTree* w = nullptr;
+        const gt_status st = wide_build(p, keys, values, n, arena, arena_bytes, stream, &w);
+        if (st != GT_OK) return st;
+        gt_tree* t = new gt_tree();
+        t->p = *p;
+        t->kb = static_cast<int>(p->key_bytes);
+        t->arena = reinterpret_cast<uint8_t*>(arena);
+        t->arena_bytes = w->arena_bytes;
+        t->h_bound = w->height;
+        t->wide = w;
+        *out = t;
+        return GT_OK;
+    }
     if (!params_ok(p) || !arena || !out || (n && (!keys || !values))) return GT_ERR_INVALID;
     if (n >= (1ull << 36)) return GT_ERR_INVALID;
     const int kb = static_cast<int>(p->key_bytes);
@@ -304,6 +320,7 @@ gt_status tree_lookup_batch(gt_tree* t, const void* keys, uint64_t B, void* valu
     if (!t) return GT_ERR_INVALID;
     if (B == 0) return GT_OK;
     if (!keys || !values_out || !found_out) return GT_ERR_INVALID;
+    if (t->wide) return wide_lookup(t->wide, keys, B, values_out, found_out, stream);
     if (t->kb == 8)
         launch_lookup<uint64_t>(view<uint64_t>(t), t->cfg, reinterpret_cast<const uint64_t*>(keys), B,
                                 reinterpret_cast<uint64_t*>(values_out), found_out, stream);
@@ -314,13 +331,13 @@ gt_status tree_lookup_batch(gt_tree* t, const void* keys, uint64_t B, void* valu
 }
 
 uint64_t tree_lookup_levelwise_workspace_bytes(const gt_tree* t, uint64_t B, uint32_t flags) {
-    if (!t || (flags & ~GT_LW_PRESORTED) != 0) return 0;
+    if (!t || t->wide || (flags & ~GT_LW_PRESORTED) != 0) return 0;
     return lw_layout(B, t->kb, (flags & GT_LW_PRESORTED) != 0).total;
 }
 
 gt_status tree_lookup_levelwise(gt_tree* t, const void* keys, uint64_t B, uint32_t flags, void* values_out,
                                 uint8_t* found_out, void* workspace, uint64_t workspace_bytes, hipStream_t stream) {
-    if (!t) return GT_ERR_INVALID;
+    if (!t || t->wide) return GT_ERR_INVALID;
     if ((flags & ~GT_LW_PRESORTED) != 0) return GT_ERR_INVALID;
     if (B == 0) return GT_OK;
     if (!keys || !values_out || !found_out || !workspace) return GT_ERR_INVALID;
@@ -340,7 +357,7 @@ gt_status tree_lookup_levelwise(gt_tree* t, const void* keys, uint64_t B, uint32
 
 gt_status tree_lookup_levelwise_noalloc(gt_tree* t, const void* keys, uint64_t B, uint32_t flags,
                                         void* values_out, uint8_t* found_out, hipStream_t stream) {
-    if (!t) return GT_ERR_INVALID;
+    if (!t || t->wide) return GT_ERR_INVALID;
     if ((flags & ~GT_LW_PRESORTED) != 0) return GT_ERR_INVALID;
     if (B == 0) return GT_OK;
     if (!keys || !values_out || !found_out) return GT_ERR_INVALID;
@@ -361,7 +378,7 @@ gt_status tree_lookup_levelwise_noalloc(gt_tree* t, const void* keys, uint64_t B
 }
 
 gt_status tree_delete_batch(gt_tree* t, const void* keys, uint64_t B, uint8_t* status_out, hipStream_t stream) {
-    if (!t) return GT_ERR_INVALID;
+    if (!t || t->wide) return GT_ERR_INVALID;
     if (B == 0) return GT_OK;
     if (!keys || !status_out) return GT_ERR_INVALID;
     if (B > t->max_batch) return GT_ERR_CAPACITY;
@@ -393,6 +410,8 @@ gt_status tree_range_batch(gt_tree* t, const void* lo, const void* hi, const uin
     if (!t) return GT_ERR_INVALID;
     if (B == 0) return GT_OK;
     if (!lo || !hi || !max_out || !out_offsets || !out_keys || !out_values || !count_out) return GT_ERR_INVALID;
+    if (t->wide)
+        return wide_range(t->wide, lo, hi, max_out, out_offsets, B, out_keys, out_values, count_out, stream);
     if (t->kb == 8)
         launch_range<uint64_t>(view<uint64_t>(t), t->cfg, reinterpret_cast<const uint64_t*>(lo),
                                reinterpret_cast<const uint64_t*>(hi), max_out, out_offsets, B,
@@ -408,7 +427,7 @@ gt_status tree_range_batch(gt_tree* t, const void* lo, const void* hi, const uin
 
 gt_status tree_insert_batch(gt_tree* t, const void* keys, const void* values, uint64_t B, uint8_t* status_out,
                             hipStream_t stream) {
-    if (!t) return GT_ERR_INVALID;
+    if (!t || t->wide) return GT_ERR_INVALID;
     if (B == 0) return GT_OK;
     if (!keys || !values || !status_out) return GT_ERR_INVALID;
     if (B > t->max_batch) return GT_ERR_CAPACITY;
@@ -435,12 +454,14 @@ gt_status tree_insert_batch(gt_tree* t, const void* keys, const void* values, ui
 gt_status tree_destroy(gt_tree* t) {
     if (!t) return GT_ERR_INVALID;
     if (t->h_flag) hipHostFree(t->h_flag);
+    delete t->wide;
     delete t;
     return GT_OK;
 }
 
 gt_status tree_stats(gt_tree* t, gt_tree_stats* out, hipStream_t stream) {
     if (!t || !out) return GT_ERR_INVALID;
+    if (t->wide) return wide_stats(t->wide, out, stream);
     DevHeader h;
     HIP_TRY(hipMemcpyAsync(&h, t->hdr, sizeof h, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
@@ -461,6 +482,7 @@ gt_status tree_stats(gt_tree* t, gt_tree_stats* out, hipStream_t stream) {
 
 gt_status tree_device_error(gt_tree* t, hipStream_t stream) {
     if (!t) return GT_ERR_INVALID;
+    if (t->wide) return wide_device_error(t->wide, stream);
     uint32_t e = 0;
     HIP_TRY(hipMemcpyAsync(&e, &t->hdr->error, 4, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
@@ -475,6 +497,7 @@ gt_status tree_device_error(gt_tree* t, hipStream_t stream) {
 
 gt_status tree_export(gt_tree* t, void* host_buf, uint64_t* bytes, hipStream_t stream) {
     if (!t || !bytes) return GT_ERR_INVALID;
+    if (t->wide) return wide_export(t->wide, host_buf, bytes, stream);
     DevHeader h;
     HIP_TRY(hipMemcpyAsync(&h, t->hdr, sizeof h, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
