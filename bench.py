@@ -224,6 +224,143 @@ class Timer:
         return ts
 
 
+def run_probes(torch, g, args):
+    """Memory-system probes (gtree_probe.h), timed with HIP events on one
+    stream: the launch floor (graph-replayed empty kernels), dependent-load
+    latency by region size (one lane chasing a random cycle of 128-byte
+    lines), the random line-read rate, and the per-step time of
+    lookup-shaped B = 1024 batches built from dependent rounds, beside the
+    real B = 1024 lookups (plain tree and learned index on the 2^24-key
+    tree).  Prints one JSON object and writes gpurun_out/probe.json."""
+    dev = "cuda"
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    out = torch.zeros(1 << 20, dtype=torch.int64, device=dev)
+    res = {}
+
+    def ev_time(fn, reps=5):
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return float(np.median(ts))
+
+    def per_step(step, nsteps, gr=64, passes=3):
+        graphs = []
+        for c in range(0, nsteps, gr):
+            g_ = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g_, stream=stream):
+                for i in range(c, c + gr):
+                    step(i)
+            graphs.append(g_)
+        graphs[0].replay()
+        stream.synchronize()
+        best = None
+        for _ in range(passes):
+            t0 = time.perf_counter()
+            for g_ in graphs:
+                g_.replay()
+            stream.synchronize()
+            dt = (time.perf_counter() - t0) / nsteps * 1e6
+            best = dt if best is None else min(best, dt)
+        return round(best, 3)
+
+    # launch floor
+    res["empty_kernel_us_per_launch_graph"] = per_step(lambda i: g.probe_empty(stream), 4096)
+    t0 = time.perf_counter()
+    for _ in range(2000):
+        g.probe_empty(stream)
+    stream.synchronize()
+    res["empty_kernel_us_per_call_eager"] = round((time.perf_counter() - t0) / 2000 * 1e6, 3)
+    print("[probe] launch floor done", file=sys.stderr, flush=True)
+
+    # dependent-load latency: a random cycle over the region's 128-byte
+    # lines.  Warm: the same 4096 steps again (4096 distinct lines, 512 KiB,
+    # which the L2 keeps).  Cold: 4096 steps from a
+    # part of the cycle not visited yet, after a 1 GiB write that evicts the
+    # Infinity Cache and the L2s (from HBM when the region exceeds them).
+    big = torch.empty(1 << 28, dtype=torch.int64, device=dev)       # 2 GiB
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    lat = {}
+    steps = 4096
+    for mb in (1, 4, 16, 64, 128, 512, 2048):
+        L = (mb << 20) // 128
+        perm = torch.randperm(L, device=dev)
+        nxt = big[:L * 16]
+        nxt[perm * 16] = torch.roll(perm, -1) * 16
+        s0 = int(perm[0]) * 16
+        g.probe_chase(nxt, steps, s0, out, stream)
+        warm = ev_time(lambda: g.probe_chase(nxt, steps, s0, out, stream), reps=3)
+        cold = []
+        for rep in range(3):
+            flush.add_(1)
+            start = int(perm[(rep + 1) * L // 4]) * 16 if L >= 4 * steps else s0
+            cold.append(ev_time(lambda: g.probe_chase(nxt, steps, start, out, stream), reps=1))
+        lat[f"{mb}MiB"] = {"warm_ns": round(warm / steps * 1e9, 1), "cold_ns": round(float(np.median(cold)) / steps * 1e9, 1)}
+        del perm
+    del flush
+    res["dependent_load_ns_by_region"] = lat
+    print("[probe] latency done", file=sys.stderr, flush=True)
+
+    # random line reads over 2 GiB
+    big.random_()
+    lines = big.numel() // 16
+    gat = {}
+    n = 1 << 22
+    for pg in (1, 2, 4, 8):
+        dt = ev_time(lambda: g.probe_gather(big, lines, n, pg, 12345, out, stream))
+        gat[str(pg)] = round(n / dt / 1e9, 2)
+    res["random_128B_lines_per_ns_2GiB"] = {"reads_in_flight_per_8_lanes": gat}
+    print("[probe] gather done", file=sys.stderr, flush=True)
+
+    # lookup-shaped batches: B = 1024, 8 lanes per query, 2048 distinct
+    # query batches; table 512 KiB (L2), region 256 MiB
+    B, nb = 1024, 2048
+    qa = torch.randint(0, 1 << 62, (nb * B,), dtype=torch.int64, device=dev)
+    qs = [qa[i * B:(i + 1) * B] for i in range(nb)]
+    table = big[:(512 << 10) // 8]
+    region = big[:(256 << 20) // 8]
+    tl, rl = table.numel() // 16, region.numel() // 16
+    ob = torch.empty(B, dtype=torch.int64, device=dev)
+    shapes = [(0, 0, 0), (1, 0, 0), (2, 0, 0), (4, 0, 0), (0, 1, 1), (1, 1, 1), (1, 1, 2), (1, 1, 4), (1, 1, 8),
+              (4, 1, 1), (4, 2, 1), (4, 2, 2), (1, 2, 2), (0, 1, 2)]
+    bt = {}
+    for tr, rr, lpr in shapes:
+        bt[f"table{tr}_region{rr}x{lpr}"] = per_step(
+            lambda i: g.probe_batch(qs[i % nb], table, tl, tr, region, rl, rr, lpr, ob, stream), nb)
+    res["batch_b1024_us_per_step"] = bt
+    del big
+    print("[probe] batch shapes done", file=sys.stderr, flush=True)
+
+    # the real lookups on the bench's tree, timed the same way
+    n = 1 << args.log2n
+    keys = synth.uniform_keys(n, SEED, 64)
+    vals = synth.values_for(keys, SEED, 64)
+    tree = g.Tree(keys, vals, 8, max_batch=1024)
+    li = g.Learned(tree, models=1024)
+    li.train()
+    allq = synth.present_queries(keys, nb * B, SEED, purpose=1000)
+    qdev = tree.dev(allq)
+    qd = [qdev[i * B:(i + 1) * B] for i in range(nb)]
+    vo = torch.empty(B, dtype=torch.int64, device=dev)
+    fo = torch.empty(B, dtype=torch.uint8, device=dev)
+    res["lookup_b1024_us_per_step"] = {
+        "plain": per_step(lambda i: g.tree_lookup_batch(tree.h, qd[i], vo, fo, stream), nb),
+        "learned": per_step(lambda i: g.li_lookup_batch(li.h, qd[i], vo, fo, stream), nb)}
+    assert g.to_numpy(fo).all() and np.array_equal(g.to_numpy(vo, np.uint64),
+                                                   synth.values_for(allq[(nb - 1) * B:], SEED, 64))
+    li.close()
+    tree.close()
+    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+    with open(os.path.join(ROOT, "gpurun_out", "probe.json"), "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,6 +380,9 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection mode: three 1 GiB device copies (calibration), a priming "
                          "2^20-key lookup batch, three warm ones and three after a 2 GiB cache flush, then exit")
+    ap.add_argument("--probe", action="store_true",
+                    help="memory-system probes (launch floor, load latency, line-read rate, batch chains) and the "
+                         "B = 1024 lookups beside them, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the tree runs on a single MI355X "
@@ -251,6 +391,10 @@ def main():
 
     import torch
     import paper_2604_21117_amd as g
+
+    if args.probe:
+        run_probes(torch, g, args)
+        return
 
     dev = "cuda"
     stream = torch.cuda.Stream()

@@ -103,6 +103,10 @@ def lib():
         L.tree_lookup_levelwise_workspace_bytes.restype = u64
         L.tree_lookup_levelwise.argtypes = [vp, vp, u64, u32, vp, vp, vp, u64, vp]
         L.tree_lookup_levelwise_noalloc.argtypes = [vp, vp, u64, u32, vp, vp, vp]
+        L.gt_probe_empty.argtypes = [vp]
+        L.gt_probe_chase.argtypes = [vp, u64, u64, vp, vp]
+        L.gt_probe_gather.argtypes = [vp, u64, u64, u32, u64, vp, vp]
+        L.gt_probe_batch.argtypes = [vp, u64, vp, u64, u32, vp, u64, u32, u32, vp, vp]
         L.tree_insert_batch.argtypes = [vp, vp, vp, u64, vp, vp]
         L.tree_delete_batch.argtypes = [vp, vp, u64, vp, vp]
         L.tree_range_batch.argtypes = [vp, vp, vp, vp, vp, u64, vp, vp, vp, vp]
@@ -425,6 +429,28 @@ class Tree:
 
     def export(self):
         return tree_export(self.h)
+
+
+# ------------------------------------------------ memory-system probes
+
+def probe_empty(stream=None):
+    _check(lib().gt_probe_empty(_stream(stream)), "gt_probe_empty")
+
+
+def probe_chase(next_idx, steps: int, start: int, out, stream=None):
+    _check(lib().gt_probe_chase(_ptr(next_idx), steps, start, _ptr(out), _stream(stream)), "gt_probe_chase")
+
+
+def probe_gather(region, lines: int, n: int, per_group: int, seed: int, out, stream=None):
+    _check(lib().gt_probe_gather(_ptr(region), lines, n, per_group, seed, _ptr(out), _stream(stream)),
+           "gt_probe_gather")
+
+
+def probe_batch(q, table, table_lines: int, table_rounds: int, region, region_lines: int, region_rounds: int,
+                lines_per_round: int, out, stream=None):
+    _check(lib().gt_probe_batch(_ptr(q), q.numel(), _ptr(table), table_lines, table_rounds, _ptr(region),
+                                region_lines, region_rounds, lines_per_round, _ptr(out), _stream(stream)),
+           "gt_probe_batch")
 
 
 def make_static_params(key_bytes: int, fanout: int, fill: float = 1.0) -> gt_params:
