@@ -452,9 +452,17 @@ typedef struct {
     uint32_t use_graphs;     /* 1 = replay captured graphs, 2 = direct
                                 launches; 0 = default (1)                   */
     uint32_t retrain_log2;   /* with a learned index: after 2^retrain_log2
-                                inserted keys the server pauses admission,
-                                lets in-flight batches finish and retrains
-                                the index (li_train); 0 = never; at most 40 */
+                                inserted (or deleted) keys the server copies
+                                the tree's arena between the writes admitted
+                                before and after that point, trains a second
+                                index on the copy on a thread and stream of
+                                its own while admission goes on, and then
+                                exchanges the two indexes' states (batches
+                                admitted from then on use the new one; a
+                                write after the copy counts as a change since
+                                its training, as for any stale index);
+                                0 = never; at most 40.  The copy and the
+                                second index are allocated by srv_create     */
 } gt_srv_params;
 
 enum { GT_OP_LOOKUP = 0, GT_OP_INSERT = 1, GT_OP_RANGE = 2, GT_OP_DELETE = 3 };
@@ -495,9 +503,12 @@ typedef struct {
 } gt_srv_stats;
 
 /* Create a server over tree t (and learned index li for lookups, or NULL).
- * Allocates its staging buffers (pinned host, device) here, not later.
- * li_train / li_set_bounds on li are allowed while no request is in flight;
- * the server then captures its lookup graphs again. */
+ * Allocates its staging buffers (pinned host, device) here, not later; with
+ * retrain_log2 also a copy of t's arena and a second index like li.
+ * li_train / li_set_bounds on li are allowed while no request is in flight
+ * and no retraining runs (srv_replay returns after the retrainings its
+ * batches started); the server then captures its lookup graphs again.  At
+ * srv_destroy li holds the most recent training, in its own arena. */
 gt_status srv_create(gt_tree* t, gt_learned* li, const gt_srv_params* p /*host*/, gt_server** out);
 /* Queue a batch (non-blocking); *ticket identifies it. */
 gt_status srv_submit(gt_server* s, const gt_request* r /*host*/, uint64_t* ticket /*host*/);

@@ -12,6 +12,32 @@
 // generation must be captured again.
 uint64_t gt_li_generation(const gt_learned* li);
 
+// Serving-runtime support for retraining beside the serving index.
+// Arena bytes of an index like `li` (same tree, parameters and models).
+uint64_t gt_li_arena_bytes_like(const gt_learned* li);
+// A new, untrained index over li's tree with li's parameters.
+gt_status gt_li_create_like(const gt_learned* li, void* arena, uint64_t arena_bytes, gt_learned** out);
+// Point `li` at tree handle `t` (another handle of the same layout, e.g. over
+// a copy of the arena) and record the insert and delete counts of `t` that
+// its training reflects: lookups then read `t`, and treat any later insert
+// or delete as a change since training.
+void gt_li_rebind(gt_learned* li, gt_tree* t, uint64_t inserts_at_train, uint64_t deletes_at_train);
+// Exchange the whole states (arena, models, arguments) of two indexes over
+// the same tree; launches already enqueued keep the state they captured.
+void gt_li_exchange(gt_learned* a, gt_learned* b);
+// The arena an index's state lives in, and the exchange of two indexes'
+// arenas alone (for handing a state back into its owner's arena after a
+// byte copy: the two arenas must then hold the same bytes).
+void* gt_li_arena(const gt_learned* li);
+void gt_li_swap_arenas(gt_learned* a, gt_learned* b);
+// A handle over `arena`, a byte copy of t's arena: the same layout and
+// parameters, no inserts or deletes counted.
+struct gt_tree* gt_tree_clone_handle(const struct gt_tree* t, uint8_t* arena);
+// Enqueue on `s` a copy of what training reads (header, child references of
+// the inner nodes in use, keys and metadata of the leaves in use) from t's
+// arena into the arena of `dst`, a clone handle of t.
+gt_status gt_tree_copy_for_training(const struct gt_tree* t, struct gt_tree* dst, hipStream_t s);
+
 struct gt_tree {
     gt_params p;
     int kb;

@@ -51,6 +51,8 @@
 #include <string.h>
 #include <vector>
 #include <cmath>
+#include <algorithm>
+#include <utility>
 
 #include "../../include/gtree.h"
 #include "common.h"
@@ -1416,3 +1418,35 @@ gt_status li_destroy(gt_learned* li) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------- serving runtime support
+
+uint64_t gt_li_arena_bytes_like(const gt_learned* li) { return layout_li(nullptr, li->leaf_cap, li->M, li->t->kb); }
+
+gt_status gt_li_create_like(const gt_learned* li, void* arena, uint64_t arena_bytes, gt_learned** out) {
+    return li_create(li->t, &li->p, arena, arena_bytes, out);
+}
+
+void gt_li_rebind(gt_learned* li, gt_tree* t, uint64_t inserts_at_train, uint64_t deletes_at_train) {
+    li->t = t;
+    li->inserts_at_train = inserts_at_train;
+    li->deletes_at_train = deletes_at_train;
+    li->generation++;
+}
+
+void* gt_li_arena(const gt_learned* li) { return li->arena; }
+
+void gt_li_swap_arenas(gt_learned* a, gt_learned* b) {
+    std::swap(a->arena, b->arena);
+    a->generation++;
+    b->generation++;
+}
+
+void gt_li_exchange(gt_learned* a, gt_learned* b) {
+    std::swap(*a, *b);
+    // each handle's generation only grows, so graphs captured against either
+    // handle's previous state are captured again
+    const uint64_t g = std::max(a->generation, b->generation) + 1;
+    a->generation = g;
+    b->generation = g;
+}

@@ -5,9 +5,21 @@
 //   1. retires finished batches (event query), copies their outputs from
 //      pinned staging to the caller's buffers and frees slot and bytes;
 //  1b. with a learned index and retrain_log2 set: once 2^retrain_log2 keys
-//      were inserted since training, admission pauses, and when no batch is
-//      in flight the index is retrained (its lookup graphs are captured
-//      again on their next use);
+//      were inserted since training, what training reads of the tree (child
+//      references, leaf keys and metadata in use) is copied on the write
+//      stream (after the writes admitted so far, before any admitted later;
+//      reads go on) and a trainer thread trains a second index against the
+//      copy on its own stream, masked to a few CUs, while admission
+//      continues.  The trained index
+//      is bound to the live tree with the copy's insert and delete counts,
+//      so the lookups treat every later write as a change since training
+//      (a miss is then checked along the leaf chain or the tree, as for any
+//      index that inserts made stale).  At the next pass after training the
+//      worker exchanges its state with the serving index's: batches
+//      admitted from then on use it (their lookup graphs are captured again),
+//      batches already launched keep the state they were launched with, and
+//      the old state is not trained into again until every batch admitted
+//      before the exchange has retired;
 //   2. admits queued batches in arrival order while a slot is free and the
 //      staged bytes in flight stay under the cap (a batch larger than the
 //      cap is refused at once, so admission never deadlocks);
@@ -42,6 +54,12 @@
 namespace {
 
 using clk = std::chrono::steady_clock;
+
+// The trainer's stream runs on 32 of the 256 CUs, four per XCD (bit i of
+// the mask selects a CU of XCD i mod 8), so a retraining leaves the rest of
+// the GPU to the batches being served.
+constexpr uint32_t kTrainCuMaskWords = 8;
+const uint32_t kTrainCuMask[kTrainCuMaskWords] = {0xFFFFFFFFu, 0, 0, 0, 0, 0, 0, 0};
 
 double now_s() {
     return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
@@ -110,8 +128,23 @@ struct gt_server {
     uint32_t inflight = 0;
     uint64_t graph_launches = 0, direct_launches = 0;
     uint64_t inserted_since_train = 0;  // keys of completed insert batches since the last retrain
-    bool retrain_pending = false;       // admission paused until in-flight batches drain
-    bool training = false;              // li_train running on the worker
+    bool retrain_due = false;           // enough keys inserted: retrain when the spare state is free
+    // retraining beside the serving index
+    int device = 0;
+    gt_learned* shadow = nullptr;       // trained on a copy of the tree, then exchanged with li
+    void* shadow_arena = nullptr;
+    uint8_t* snap_arena = nullptr;      // the copy of the tree's arena
+    gt_tree* snap = nullptr;            // a handle over the copy
+    hipStream_t tstream = nullptr;      // the trainer's stream
+    hipEvent_t snap_ev = nullptr;       // recorded after the copy on the write stream
+    std::thread trainer;
+    bool train_running = false;         // copy and training under way
+    bool shadow_ready = false;          // trained: exchange at the next pass
+    gt_status train_status = GT_OK;
+    uint64_t snap_inserts = 0, snap_deletes = 0;
+    uint64_t exchange_ticket = 0;       // batches admitted before the last exchange have smaller tickets
+    void* user_arena = nullptr;         // the caller's index arena (its state returns there at the end)
+    double train_t0 = 0.0;
     uint64_t retrains = 0;
     double retrain_s = 0.0;
     std::vector<uint64_t> last_replay;
@@ -271,6 +304,22 @@ void retire(gt_server* s, Slot& sl, Req& q) {
     }
 }
 
+// The trainer thread: train the shadow index against the copy of the tree
+// on its own stream, bind it to the live tree, and hand it to the worker.
+void trainer_run(gt_server* s) {
+    gt_status st = hipSetDevice(s->device) == hipSuccess ? GT_OK : GT_ERR_HIP;
+    if (st == GT_OK && hipStreamWaitEvent(s->tstream, s->snap_ev, 0) != hipSuccess) st = GT_ERR_HIP;
+    if (st == GT_OK) {
+        gt_li_rebind(s->shadow, s->snap, 0, 0);
+        st = li_train(s->shadow, s->tstream);
+        gt_li_rebind(s->shadow, s->t, s->snap_inserts, s->snap_deletes);
+    }
+    std::lock_guard<std::mutex> g(s->mu);
+    s->train_status = st;
+    s->shadow_ready = true;
+    s->cv_work.notify_all();
+}
+
 void worker_loop(gt_server* s) {
     std::unique_lock<std::mutex> lk(s->mu);
     while (true) {
@@ -284,9 +333,9 @@ void worker_loop(gt_server* s) {
             retire(s, sl, q);
             // deleted keys count too: after a delete the index answers
             // through the tree until it is trained again
-            if ((q.r.op == GT_OP_INSERT || q.r.op == GT_OP_DELETE) && !q.failed && s->li && s->p.retrain_log2) {
+            if ((q.r.op == GT_OP_INSERT || q.r.op == GT_OP_DELETE) && !q.failed && s->shadow) {
                 s->inserted_since_train += q.r.B;
-                if (s->inserted_since_train >= (1ull << s->p.retrain_log2)) s->retrain_pending = true;
+                if (s->inserted_since_train >= (1ull << s->p.retrain_log2)) s->retrain_due = true;
             }
             if (s->ref_set) {
                 float a = 0, b = 0;
@@ -304,27 +353,51 @@ void worker_loop(gt_server* s) {
             did = true;
         }
         if (did) s->cv_done.notify_all();
-        // 1b. retrain the learned index once enough keys were inserted: no
-        //     batch is admitted meanwhile, and training starts when none is in
-        //     flight
-        if (s->retrain_pending && s->inflight == 0 && s->fatal == hipSuccess) {
-            const double t0 = now_s();
-            s->training = true;
-            lk.unlock();
-            const gt_status st = li_train(s->li, s->cstream);
-            lk.lock();
-            s->training = false;
-            if (st != GT_OK) s->fatal = hipErrorUnknown;
-            s->retrains++;
-            s->retrain_s += now_s() - t0;
-            // every inserted key is in the tree the index was trained on
-            s->inserted_since_train = 0;
-            s->retrain_pending = false;
+        // 1b. retraining beside the serving index: exchange a trained shadow
+        //     state, or start the next training once enough keys were
+        //     inserted and no batch still runs on the spare state
+        if (s->shadow_ready) {
+            if (s->trainer.joinable()) s->trainer.join();
+            if (s->train_status == GT_OK) {
+                gt_li_exchange(s->li, s->shadow);
+                s->exchange_ticket = s->queue.empty() ? s->reqs.size() : s->queue.front();
+                s->retrains++;
+            } else {
+                s->fatal = hipErrorUnknown;
+            }
+            s->retrain_s += now_s() - s->train_t0;
+            s->shadow_ready = false;
+            s->train_running = false;
             s->cv_done.notify_all();
             did = true;
         }
+        if (s->retrain_due && !s->train_running && s->fatal == hipSuccess) {
+            bool spare_busy = false;
+            for (const Slot& sl : s->slots)
+                if (sl.busy && sl.ticket < s->exchange_ticket) spare_busy = true;
+            if (!spare_busy) {
+                // the copy reads the tree between the writes admitted so far
+                // and any admitted later (both on the write stream)
+                hipError_t e = gt_tree_copy_for_training(s->t, s->snap, s->wstream) == GT_OK ? hipSuccess
+                                                                                              : hipErrorUnknown;
+                if (e == hipSuccess) e = hipEventRecord(s->snap_ev, s->wstream);
+                if (e != hipSuccess) {
+                    s->fatal = e;
+                } else {
+                    s->snap_inserts = s->t->inserts;
+                    s->snap_deletes = s->t->deletes;
+                    s->inserted_since_train = 0;
+                    s->retrain_due = false;
+                    s->train_running = true;
+                    s->train_t0 = now_s();
+                    if (s->trainer.joinable()) s->trainer.join();
+                    s->trainer = std::thread(trainer_run, s);
+                }
+                did = true;
+            }
+        }
         // 2. admit in arrival order
-        while (!s->queue.empty() && s->fatal == hipSuccess && !s->retrain_pending) {
+        while (!s->queue.empty() && s->fatal == hipSuccess) {
             const uint64_t tk = s->queue.front();
             Req& q = s->reqs[tk];
             const uint32_t bucket = pow2ceil(q.r.B ? q.r.B : 1);
@@ -507,6 +580,18 @@ gt_status srv_create(gt_tree* t, gt_learned* li, const gt_srv_params* p, gt_serv
             hipEventCreate(&s->ref_ev) != hipSuccess)
             st = GT_ERR_HIP;
     }
+    if (st == GT_OK && li && q.retrain_log2) {
+        // the second index and the tree copy it trains on, allocated now
+        const uint64_t lb = gt_li_arena_bytes_like(li);
+        s->user_arena = gt_li_arena(li);
+        if (hipGetDevice(&s->device) != hipSuccess || hipMalloc(&s->shadow_arena, lb) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void**>(&s->snap_arena), t->arena_bytes) != hipSuccess ||
+            hipExtStreamCreateWithCUMask(&s->tstream, kTrainCuMaskWords, kTrainCuMask) != hipSuccess ||
+            hipEventCreateWithFlags(&s->snap_ev, hipEventDisableTiming) != hipSuccess)
+            st = GT_ERR_HIP;
+        if (st == GT_OK) st = gt_li_create_like(li, s->shadow_arena, lb, &s->shadow);
+        if (st == GT_OK) s->snap = gt_tree_clone_handle(t, s->snap_arena);
+    }
     if (st != GT_OK) {
         srv_destroy(s);
         return st;
@@ -572,7 +657,7 @@ gt_status srv_replay(gt_server* s, const gt_request* reqs, uint64_t n) {
     }
     std::unique_lock<std::mutex> lk(s->mu);
     // a retraining these inserts started is part of the replay
-    s->cv_done.wait(lk, [&] { return (!s->retrain_pending && !s->training) || s->fatal != hipSuccess; });
+    s->cv_done.wait(lk, [&] { return (!s->retrain_due && !s->train_running) || s->fatal != hipSuccess; });
     s->last_replay = tickets;
     return res;
 }
@@ -650,7 +735,28 @@ gt_status srv_destroy(gt_server* s) {
         }
         s->worker.join();
     }
+    if (s->trainer.joinable()) s->trainer.join();
     hipDeviceSynchronize();
+    if (s->shadow) {
+        // a training that finished after the last pass is still handed over
+        if (s->shadow_ready && s->train_status == GT_OK) {
+            gt_li_exchange(s->li, s->shadow);
+            s->retrains++;
+        }
+        // the caller's index keeps its own arena: after an odd number of
+        // exchanges its state sits in the server's arena and moves back
+        if (gt_li_arena(s->li) != s->user_arena) {
+            const uint64_t lb = gt_li_arena_bytes_like(s->li);
+            if (hipMemcpy(s->user_arena, gt_li_arena(s->li), lb, hipMemcpyDeviceToDevice) == hipSuccess)
+                gt_li_swap_arenas(s->li, s->shadow);
+        }
+        li_destroy(s->shadow);
+    }
+    if (s->shadow_arena) hipFree(s->shadow_arena);
+    if (s->snap_arena) hipFree(s->snap_arena);
+    delete s->snap;
+    if (s->tstream) hipStreamDestroy(s->tstream);
+    if (s->snap_ev) hipEventDestroy(s->snap_ev);
     for (Slot& sl : s->slots) free_slot(sl);
     for (auto x : s->rstreams)
         if (x) hipStreamDestroy(x);

@@ -236,6 +236,48 @@ gt_status delete_rebuild_t(gt_tree* t, hipStream_t s) {
 
 }  // namespace
 
+namespace {
+
+// Copy what training a learned index reads -- the header, the child
+// references of the inner nodes in use and the keys and {count, next} of
+// the leaves in use -- from one arena layout to another.  The counts in use
+// come from the source header, so the copy follows the tree the stream
+// order leaves it.  16-byte words, grid-stride.
+__global__ void k_train_copy(const DevHeader* __restrict__ sh, DevHeader* __restrict__ dh,
+                             const uint4* __restrict__ sic, uint4* __restrict__ dic,
+                             const uint4* __restrict__ slk, uint4* __restrict__ dlk,
+                             const uint4* __restrict__ slm, uint4* __restrict__ dlm, uint32_t key_bytes) {
+    const uint64_t ni = sh->inner_used, nl = sh->leaf_used;
+    const uint64_t n_ic = ni * kSlots * 4 / 16, n_lk = nl * kSlots * key_bytes / 16, n_lm = (nl * 8 + 15) / 16;
+    const uint64_t tid = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    if (tid == 0) *dh = *sh;
+    for (uint64_t i = tid; i < n_ic; i += stride) dic[i] = sic[i];
+    for (uint64_t i = tid; i < n_lk; i += stride) dlk[i] = slk[i];
+    for (uint64_t i = tid; i < n_lm; i += stride) dlm[i] = slm[i];
+}
+
+}  // namespace
+
+gt_status gt_tree_copy_for_training(const gt_tree* t, gt_tree* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_train_copy, dim3(2048), dim3(256), 0, s, t->hdr, dst->hdr,
+                       reinterpret_cast<const uint4*>(t->ichild), reinterpret_cast<uint4*>(dst->ichild),
+                       reinterpret_cast<const uint4*>(t->lkeys), reinterpret_cast<uint4*>(dst->lkeys),
+                       reinterpret_cast<const uint4*>(t->lmeta), reinterpret_cast<uint4*>(dst->lmeta),
+                       static_cast<uint32_t>(t->kb));
+    return hipGetLastError() == hipSuccess ? GT_OK : GT_ERR_HIP;
+}
+
+gt_tree* gt_tree_clone_handle(const gt_tree* t, uint8_t* arena) {
+    gt_tree* c = new gt_tree(*t);
+    c->h_flag = nullptr;
+    c->wide = nullptr;
+    c->inserts = 0;
+    c->deletes = 0;
+    layout(c, arena, t->leaf_cap);
+    return c;
+}
+
 extern "C" {
 
 const char* gt_status_str(gt_status s) {
