@@ -499,7 +499,12 @@ typedef struct {
                                 at least one batch (copies included), from
                                 timing events around each batch              */
     uint64_t retrains;       /* learned-index retrainings since creation     */
-    double retrain_s;        /* their total time                             */
+    double retrain_s;        /* their total time (copy to exchange)          */
+    uint64_t captures;       /* graphs the worker captured since creation    */
+    double capture_s;        /* worker time spent capturing them             */
+    uint64_t precaptured;    /* lookup graphs captured by the trainer for a
+                                retrained index and installed at the
+                                exchange                                     */
 } gt_srv_stats;
 
 /* Create a server over tree t (and learned index li for lookups, or NULL).

@@ -76,7 +76,8 @@ class gt_srv_stats(C.Structure):
                 ("graph_launches", C.c_uint64), ("direct_launches", C.c_uint64), ("wall_s", C.c_double),
                 ("p50_us", C.c_double), ("p99_us", C.c_double), ("p50_us_op", C.c_double * 4),
                 ("p99_us_op", C.c_double * 4), ("busy_frac", C.c_double), ("retrains", C.c_uint64),
-                ("retrain_s", C.c_double)]
+                ("retrain_s", C.c_double), ("captures", C.c_uint64), ("capture_s", C.c_double),
+                ("precaptured", C.c_uint64)]
 
 
 OP_LOOKUP, OP_INSERT, OP_RANGE, OP_DELETE = 0, 1, 2, 3

@@ -96,6 +96,10 @@ struct Slot {
     uint32_t* h_err = nullptr;
     std::map<uint64_t, hipGraphExec_t> graphs;
     uint64_t li_gen = 0;   // learned-index generation the lookup graphs were captured at
+    // lookup graphs the trainer captured for a retrained index, installed at
+    // the exchange when the index's state still matches (next_flags)
+    std::map<uint64_t, hipGraphExec_t> next_graphs;
+    uint64_t next_flags = 0;
     uint32_t bucket = 0;
     uint64_t out_len = 0;  // staged range output entries
 };
@@ -127,6 +131,9 @@ struct gt_server {
     uint64_t bytes_inflight = 0;
     uint32_t inflight = 0;
     uint64_t graph_launches = 0, direct_launches = 0;
+    uint64_t captures = 0, precaptured = 0;
+    double capture_s = 0.0;
+    hipStream_t tcstream = nullptr;     // the trainer's capture stream
     uint64_t inserted_since_train = 0;  // keys of completed insert batches since the last retrain
     bool retrain_due = false;           // enough keys inserted: retrain when the spare state is free
     // retraining beside the serving index
@@ -206,12 +213,13 @@ void stage_inputs(gt_server* s, Slot& sl, const gt_request& r, uint32_t bucket, 
 }
 
 // Enqueue the whole batch (copies in, kernels, copies out) on stream st.
-hipError_t enqueue_ops(gt_server* s, Slot& sl, uint32_t op, uint32_t bucket, uint64_t outn, hipStream_t st) {
+hipError_t enqueue_ops(gt_server* s, Slot& sl, uint32_t op, uint32_t bucket, uint64_t outn, hipStream_t st,
+                       gt_learned* li) {
     const uint64_t kb = s->kb;
     hipError_t e;
     if ((e = hipMemcpyAsync(sl.d_keys, sl.h_keys, bucket * kb, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
     if (op == GT_OP_LOOKUP) {
-        gt_status g = s->li ? li_lookup_batch(s->li, sl.d_keys, bucket, sl.d_out0, sl.d_flag, st)
+        gt_status g = li ? li_lookup_batch(li, sl.d_keys, bucket, sl.d_out0, sl.d_flag, st)
                             : tree_lookup_batch(s->t, sl.d_keys, bucket, sl.d_out0, sl.d_flag, st);
         if (g != GT_OK) return hipErrorUnknown;
         if ((e = hipMemcpyAsync(sl.h_out0, sl.d_out0, bucket * kb, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
@@ -244,11 +252,30 @@ hipError_t enqueue_ops(gt_server* s, Slot& sl, uint32_t op, uint32_t bucket, uin
     return hipSuccess;
 }
 
+// Capture the batch's work on stream cs (thread-local capture mode, so other
+// threads keep launching) and instantiate it.
+hipError_t capture_ops(gt_server* s, Slot& sl, uint32_t op, uint32_t bucket, uint64_t outn, hipStream_t cs,
+                       gt_learned* li, hipGraphExec_t* out) {
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t e2 = enqueue_ops(s, sl, op, bucket, outn, cs, li);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    if (e2 != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return e2;
+    }
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    return e;
+}
+
 hipError_t launch(gt_server* s, Slot& sl, uint32_t op, uint32_t bucket, uint64_t outn, hipStream_t st) {
     const bool graphs = s->p.use_graphs != 2;
     if (!graphs || op == GT_OP_DELETE) {  // a delete synchronises: never captured
         s->direct_launches++;
-        return enqueue_ops(s, sl, op, bucket, outn, st);
+        return enqueue_ops(s, sl, op, bucket, outn, st, s->li);
     }
     if (op == GT_OP_LOOKUP && s->li) {
         // a retrained (or re-bounded) learned index: its lookup graphs are stale
@@ -268,17 +295,12 @@ hipError_t launch(gt_server* s, Slot& sl, uint32_t op, uint32_t bucket, uint64_t
     const uint64_t key = (static_cast<uint64_t>(op) << 56) | (static_cast<uint64_t>(bucket) << 28) | outn;
     auto it = sl.graphs.find(key);
     if (it == sl.graphs.end()) {
-        hipError_t e = hipStreamBeginCapture(s->cstream, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return e;
-        hipError_t e2 = enqueue_ops(s, sl, op, bucket, outn, s->cstream);
-        hipGraph_t g = nullptr;
-        e = hipStreamEndCapture(s->cstream, &g);
-        if (e2 != hipSuccess) return e2;
-        if (e != hipSuccess) return e;
+        const double t0 = now_s();
         hipGraphExec_t x = nullptr;
-        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        hipError_t e = capture_ops(s, sl, op, bucket, outn, s->cstream, s->li, &x);
         if (e != hipSuccess) return e;
+        s->captures++;
+        s->capture_s += now_s() - t0;
         it = sl.graphs.emplace(key, x).first;
     }
     s->graph_launches++;
@@ -304,6 +326,38 @@ void retire(gt_server* s, Slot& sl, Req& q) {
     }
 }
 
+// Capture, for the retrained index, the lookup graphs every slot holds now,
+// so that the worker does not capture them again after the exchange.  The
+// captures only record the slots' buffers (no work runs); the worker keeps
+// launching meanwhile.  Graphs are tagged with the index's stale / deleted
+// state, which decides the lookup kernel: at the exchange they are used only
+// if that state has not moved on.
+void precapture(gt_server* s) {
+    std::vector<std::vector<uint64_t>> keys(s->slots.size());
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        for (size_t i = 0; i < s->slots.size(); ++i) {
+            for (auto& kv : s->slots[i].next_graphs) hipGraphExecDestroy(kv.second);
+            s->slots[i].next_graphs.clear();
+            for (auto& kv : s->slots[i].graphs)
+                if ((kv.first >> 56) == GT_OP_LOOKUP) keys[i].push_back(kv.first);
+        }
+    }
+    const uint64_t flags = gt_li_generation(s->shadow) & 3u;
+    for (size_t i = 0; i < s->slots.size(); ++i) {
+        std::map<uint64_t, hipGraphExec_t> made;
+        for (uint64_t k : keys[i]) {
+            const uint32_t bucket = static_cast<uint32_t>((k >> 28) & ((1u << 28) - 1));
+            hipGraphExec_t x = nullptr;
+            if (capture_ops(s, s->slots[i], GT_OP_LOOKUP, bucket, 0, s->tcstream, s->shadow, &x) != hipSuccess) break;
+            made.emplace(k, x);
+        }
+        std::lock_guard<std::mutex> g(s->mu);
+        s->slots[i].next_graphs.swap(made);
+        s->slots[i].next_flags = flags;
+    }
+}
+
 // The trainer thread: train the shadow index against the copy of the tree
 // on its own stream, bind it to the live tree, and hand it to the worker.
 void trainer_run(gt_server* s) {
@@ -314,6 +368,7 @@ void trainer_run(gt_server* s) {
         st = li_train(s->shadow, s->tstream);
         gt_li_rebind(s->shadow, s->t, s->snap_inserts, s->snap_deletes);
     }
+    if (st == GT_OK && s->p.use_graphs != 2) precapture(s);
     std::lock_guard<std::mutex> g(s->mu);
     s->train_status = st;
     s->shadow_ready = true;
@@ -362,6 +417,24 @@ void worker_loop(gt_server* s) {
                 gt_li_exchange(s->li, s->shadow);
                 s->exchange_ticket = s->queue.empty() ? s->reqs.size() : s->queue.front();
                 s->retrains++;
+                // the trainer's graphs replace the slots' lookup graphs when
+                // the index's state is the one they were captured for
+                const uint64_t gen = gt_li_generation(s->li);
+                for (Slot& sl : s->slots) {
+                    if (sl.next_graphs.empty() || sl.next_flags != (gen & 3u)) continue;
+                    for (auto g = sl.graphs.begin(); g != sl.graphs.end();) {
+                        if ((g->first >> 56) == GT_OP_LOOKUP) {
+                            hipGraphExecDestroy(g->second);
+                            g = sl.graphs.erase(g);
+                        } else {
+                            ++g;
+                        }
+                    }
+                    for (auto& kv : sl.next_graphs) sl.graphs.emplace(kv.first, kv.second);
+                    s->precaptured += sl.next_graphs.size();
+                    sl.next_graphs.clear();
+                    sl.li_gen = gen;
+                }
             } else {
                 s->fatal = hipErrorUnknown;
             }
@@ -499,6 +572,8 @@ gt_status alloc_slot(gt_server* s, Slot& sl) {
 void free_slot(Slot& sl) {
     for (auto& kv : sl.graphs) hipGraphExecDestroy(kv.second);
     sl.graphs.clear();
+    for (auto& kv : sl.next_graphs) hipGraphExecDestroy(kv.second);
+    sl.next_graphs.clear();
     if (sl.ev) hipEventDestroy(sl.ev);
     if (sl.ev0) hipEventDestroy(sl.ev0);
     void* d[] = {sl.d_keys, sl.d_vals, sl.d_max, sl.d_off, sl.d_out0, sl.d_out1, sl.d_cnt, sl.d_flag};
@@ -587,6 +662,7 @@ gt_status srv_create(gt_tree* t, gt_learned* li, const gt_srv_params* p, gt_serv
         if (hipGetDevice(&s->device) != hipSuccess || hipMalloc(&s->shadow_arena, lb) != hipSuccess ||
             hipMalloc(reinterpret_cast<void**>(&s->snap_arena), t->arena_bytes) != hipSuccess ||
             hipExtStreamCreateWithCUMask(&s->tstream, kTrainCuMaskWords, kTrainCuMask) != hipSuccess ||
+            hipStreamCreateWithFlags(&s->tcstream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&s->snap_ev, hipEventDisableTiming) != hipSuccess)
             st = GT_ERR_HIP;
         if (st == GT_OK) st = gt_li_create_like(li, s->shadow_arena, lb, &s->shadow);
@@ -688,6 +764,9 @@ gt_status srv_stats(gt_server* s, gt_srv_stats* out) {
     }
     out->graph_launches = s->graph_launches;
     out->direct_launches = s->direct_launches;
+    out->captures = s->captures;
+    out->capture_s = s->capture_s;
+    out->precaptured = s->precaptured;
     out->retrains = s->retrains;
     out->retrain_s = s->retrain_s;
     out->wall_s = all.empty() ? 0.0 : last - first;
@@ -756,6 +835,7 @@ gt_status srv_destroy(gt_server* s) {
     if (s->snap_arena) hipFree(s->snap_arena);
     delete s->snap;
     if (s->tstream) hipStreamDestroy(s->tstream);
+    if (s->tcstream) hipStreamDestroy(s->tcstream);
     if (s->snap_ev) hipEventDestroy(s->snap_ev);
     for (Slot& sl : s->slots) free_slot(sl);
     for (auto x : s->rstreams)
