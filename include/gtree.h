@@ -435,8 +435,8 @@ gt_status li_destroy(gt_learned* li);
  * insert admitted before it and none after.  Reads run concurrently on
  * several HIP streams; an insert waits for the reads admitted before it and
  * the reads after it wait for the insert.  Each batch is padded to a power
- * of two with entries that leave the result unchanged (extra lookups, a
- * repeat of the last insert pair, empty ranges) and, once its
+ * of two with entries that leave the result unchanged (repeats of the last
+ * lookup key, insert pair or delete key; empty ranges) and, once its
  * (slot, op, size) shape has been seen, replayed from a captured hipGraph
  * (input copy, kernels, output copy).  Inputs and outputs live in the
  * caller's host memory; the runtime stages them through pinned buffers.

@@ -181,7 +181,10 @@ void stage_inputs(gt_server* s, Slot& sl, const gt_request& r, uint32_t bucket, 
     const uint64_t kb = s->kb;
     memcpy(sl.h_keys, r.keys, r.B * kb);
     if (r.op == GT_OP_LOOKUP) {
-        memset(sl.h_keys + r.B * kb, 0, (bucket - r.B) * kb);
+        // padding repeats the last key: its answers are ignored, and it takes
+        // the path of a real query (an absent filler key would make every
+        // padded batch of a stale learned index descend the tree for it)
+        for (uint32_t i = r.B; i < bucket; ++i) memcpy(sl.h_keys + i * kb, sl.h_keys + (r.B - 1) * kb, kb);
     } else if (r.op == GT_OP_INSERT) {
         memcpy(sl.h_vals, r.values, r.B * kb);
         // padding repeats the last pair: same final value, statuses ignored
