@@ -258,3 +258,36 @@ def test_admission_cap():
         v, f = sa.lookup(b.keys)
         assert np.array_equal(b.out0, v) and np.array_equal(b.out1, f)
     srv.close()
+
+
+def test_padded_lookups_stay_on_the_learned_path():
+    """Served lookup batches are padded to a power of two.  With a learned
+    index made stale by inserts, a padding entry must not be a key that
+    misses its window (such a key goes down the tree): present-key batches
+    of uneven sizes cause no tree descent, and their results are exact."""
+    import paper_2604_21117_amd as g
+    seed = 75
+    keys, vals, fresh = _setup(seed, n=1 << 16)
+    t = mk_tree(keys, vals, 8, leaf_slack=1 << 14, max_batch=1024)
+    li = g.Learned(t, models=128)
+    li.train()
+    for c in range(0, 3000, 1000):
+        k = fresh[c:c + 1000]
+        assert (t.insert(k, synth.values_for(k, seed, 64)) == 0).all()
+    srv = g.Server(t, learned=li, slots=4)
+    f0 = li.stats()["fallbacks"]
+    sa = oracle.SortedArray(np.concatenate([keys, fresh[:3000]]),
+                            np.concatenate([vals, synth.values_for(fresh[:3000], seed, 64)]), 64)
+    for B in (3, 100, 513, 1000):
+        q = synth.present_queries(keys, B, seed + B)
+        b = g.Batch(0, q)
+        assert srv.wait(srv.submit(b)) == g.GT_OK
+        v, f = sa.lookup(q)
+        assert np.array_equal(b.out1, f) and np.array_equal(b.out0, v)
+    srv.close()
+    # padding with an absent key made up to half of a bucket descend the
+    # tree (513 keys pad to 1024); a present key may descend only after a
+    # long chain of splits, which 3000 inserts into 4096 leaves hardly make
+    assert li.stats()["fallbacks"] - f0 <= 0.01 * (3 + 100 + 513 + 1000)
+    li.close()
+    t.close()
