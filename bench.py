@@ -385,6 +385,9 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection mode: three 1 GiB device copies (calibration), a priming "
                          "2^20-key lookup batch, three warm ones and three after a 2 GiB cache flush, then exit")
+    ap.add_argument("--order-probe", action="store_true",
+                    help="the 2^20-key lookup with its queries in random, bucketed and sorted order, cold and "
+                         "warm, then exit")
     ap.add_argument("--probe", action="store_true",
                     help="memory-system probes (launch floor, load latency, line-read rate, batch chains) and the "
                          "B = 1024 lookups beside them, then exit")
@@ -421,6 +424,40 @@ def main():
     qld = tree.dev(ql_np)
     vl = torch.empty(BL, dtype=torch.int64, device=dev)
     fl = torch.empty(BL, dtype=torch.uint8, device=dev)
+
+    if args.order_probe:
+        # the 2^20-key lookup on the same queries in random order, bucketed by
+        # their top 8 / 12 / 16 key bits, and sorted; cold (after a 2 GiB
+        # flush) and warm; and the cost of scattering 9-byte results back to
+        # caller order
+        flush = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
+
+        def ev(fn, cold):
+            ts = []
+            for _ in range(8):
+                if cold:
+                    flush.add_(1)
+                ts += timer.run(fn, 1, skip=0)
+            return round(float(np.median(ts[2:])), 2)
+
+        res = {"batch": BL, "keys": n}
+        for bits in (0, 8, 12, 16, 64):
+            order = np.arange(BL) if bits == 0 else np.argsort(
+                ql_np >> np.uint64(64 - bits) if bits < 64 else ql_np, kind="stable")
+            qo = tree.dev(ql_np[order])
+            name = {0: "random", 64: "sorted"}.get(bits, f"bucketed_{bits}_bits")
+            for cold in (True, False):
+                res[f"{name}_{'cold' if cold else 'warm'}_us"] = ev(
+                    lambda: g.tree_lookup_batch(tree.h, qo, vl, fl, stream), cold)
+            assert g.to_numpy(fl).all() and np.array_equal(g.to_numpy(vl, np.uint64),
+                                                           synth.values_for(ql_np[order], SEED, 64))
+        perm = torch.from_numpy(np.argsort(ql_np >> np.uint64(52), kind="stable").astype(np.int64)).to(dev)
+        ov = torch.empty(BL, dtype=torch.int64, device=dev)
+        of = torch.empty(BL, dtype=torch.uint8, device=dev)
+        res["scatter_results_to_caller_order_cold_us"] = ev(
+            lambda: (ov.index_copy_(0, perm, vl), of.index_copy_(0, perm, fl)), True)
+        print(json.dumps(res), flush=True)
+        return
 
     if args.profile:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
