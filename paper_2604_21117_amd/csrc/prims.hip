@@ -132,7 +132,9 @@ template void scan_exclusive<uint64_t>(const uint64_t*, uint64_t*, uint64_t*, co
 // ------------------------------------------------------------------ sort
 //
 // For n > kBitonicMax: LSD radix sort with 8-bit digits, one scatter kernel
-// per pass (the decoupled look-back scheme of single-pass prefix scans).
+// per pass (the decoupled look-back of single-pass prefix scans, Merrill and
+// Garland, "Single-pass Parallel Prefix Scan with Decoupled Look-back",
+// NVIDIA technical report NVR-2016-002, 2016; written here for wave64 tiles).
 // One kernel clears the pass tickets and tile words, one counts the digits
 // of every pass over the whole input.  In a pass, each workgroup takes the
 // next 4096-element tile from an atomic ticket, ranks its elements by digit

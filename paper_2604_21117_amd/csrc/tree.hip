@@ -13,6 +13,7 @@
 #include <algorithm>
 
 #include "../../include/gtree.h"
+#include "../../include/gtree_testing.h"
 #include "common.h"
 #include "kernels.h"
 #include "prims.h"
