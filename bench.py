@@ -229,6 +229,69 @@ class Timer:
         return ts
 
 
+def run_variants(torch, g, keys, stream, timer, capture, GR):
+    """The paper's key and node variants on the static tree: 32-byte keys at
+    orders 16, 32 and 64 with 1M and 10M entries (the paper's tree sizes),
+    batches of 1000 (the paper's largest) and 2^20; and 8-byte keys at
+    orders 32 and 64 on the 2^24-key set (B = 1024 and 2^20).  Time per batch
+    from graph replays (B <= 2^13) or HIP events; every result of the last
+    batch checked against the generator (values hash(first 8 key bytes ^
+    seed))."""
+    dev = "cuda"
+    variants = {}
+    for kb, m, lgn in ((32, 16, 20), (32, 32, 20), (32, 64, 20), (32, 16, None), (32, 32, None), (32, 64, None),
+                       (8, 32, 24), (8, 64, 24)):
+        nv = 10_000_000 if lgn is None else 1 << lgn
+        if kb == 32:
+            kv = synth.Stream(SEED, 8800).draw(nv * 4).view(np.uint8).reshape(nv, 32)
+            first = kv.view(np.uint64).reshape(nv, 4)[:, 0]
+        else:
+            kv, first = keys[:nv], keys[:nv]
+        vv = synth.values_for(first, SEED, 64)
+        tv = g.StaticTree(kv, vv, kb, m)
+        row = {"keys": nv, "height": tv.stats()["height"]}
+        for bq in ((1000, 1 << 20) if kb == 32 else (1024, 1 << 20)):
+            nbq = 256 if bq <= 8192 else 4
+            idx = synth.Stream(SEED, 8900 + bq).below(nbq * bq, nv)
+            qh = kv[idx]
+            qdev = tv.dev_keys(qh)
+            per = kb if kb == 32 else 1     # tensor elements per key (bytes, or one u64)
+            qb = [qdev[i * bq * per:(i + 1) * bq * per] for i in range(nbq)]
+            vo8 = torch.empty(bq, dtype=torch.int64, device=dev)
+            fo8 = torch.empty(bq, dtype=torch.uint8, device=dev)
+            L = g.lib()
+            fn = lambda i: L.tree_lookup_batch(tv.h, g._ptr(qb[i]), bq, g._ptr(vo8), g._ptr(fo8),  # noqa: E731
+                                               g._stream(stream))
+            if bq <= 8192:
+                graphs = [capture(fn, c, GR) for c in range(0, nbq, GR)]
+                graphs[0].replay()
+                stream.synchronize()
+                best = None
+                for _ in range(3):
+                    t0 = time.perf_counter()
+                    for gr in graphs:
+                        gr.replay()
+                    stream.synchronize()
+                    dt = (time.perf_counter() - t0) / nbq * 1e6
+                    best = dt if best is None else min(best, dt)
+                del graphs
+                us = best
+            else:
+                us = iqm(timer.run(lambda: fn(nbq - 1), 10, skip=2))
+                fn(nbq - 1)
+            stream.synchronize()
+            want = vv[idx[(nbq - 1) * bq:]]
+            assert g.to_numpy(fo8).all() and np.array_equal(g.to_numpy(vo8, np.uint64), want), (kb, m, nv, bq)
+            row[f"b{bq}_us"] = round(us, 3)
+            row[f"b{bq}_mops"] = round(bq / us, 2)
+            del qdev, qb
+        variants[f"k{kb}_m{m}_n{nv}"] = row
+        tv.close()
+        del kv, vv
+    print("[bench] paper variants done", file=sys.stderr, flush=True)
+    return variants
+
+
 def run_probes(torch, g, args):
     """Memory-system probes (gtree_probe.h), timed with HIP events on one
     stream: the launch floor (graph-replayed empty kernels), dependent-load
@@ -385,6 +448,8 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection mode: three 1 GiB device copies (calibration), a priming "
                          "2^20-key lookup batch, three warm ones and three after a 2 GiB cache flush, then exit")
+    ap.add_argument("--variants", action="store_true",
+                    help="only the static tree of the paper's key and node variants, then exit")
     ap.add_argument("--order-probe", action="store_true",
                     help="the 2^20-key lookup with its queries in random, bucketed and sorted order, cold and "
                          "warm, then exit")
@@ -413,6 +478,17 @@ def main():
     vals = synth.values_for(keys, SEED, 64)
     skeys = np.sort(keys)
     print(f"[bench] {n} keys ready", file=sys.stderr, flush=True)
+
+    if args.variants:
+        def cap(step, first, count):
+            gr = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gr, stream=stream):
+                for i in range(first, first + count):
+                    step(i)
+            return gr
+
+        print(json.dumps(run_variants(torch, g, keys, stream, timer, cap, 64)), flush=True)
+        return
 
     t0 = time.perf_counter()
     # room for about 2.1 M inserted keys (a full leaf splits on its first new key)
@@ -753,63 +829,7 @@ def main():
             del ws, wsp, qdn, qds
     print("[bench] level-wise done", file=sys.stderr, flush=True)
 
-    # ---- the paper's key and node variants (static tree): 32-byte keys at
-    # orders 16, 32 and 64 with 1M and 10M entries (the paper's tree sizes),
-    # batches of 1000 (the paper's largest) and 2^20; and 8-byte keys at
-    # orders 32 and 64 on the 2^24-key set.  Time per batch from graph
-    # replays (B <= 2^13) or HIP events; every result of the last batch
-    # checked against the generator (values hash(first 8 key bytes ^ seed)).
-    variants = {}
-    for kb, m, lgn in ((32, 16, 20), (32, 32, 20), (32, 64, 20), (32, 16, None), (32, 32, None), (32, 64, None),
-                       (8, 32, 24), (8, 64, 24)):
-        nv = 10_000_000 if lgn is None else 1 << lgn
-        if kb == 32:
-            kv = synth.Stream(SEED, 8800).draw(nv * 4).view(np.uint8).reshape(nv, 32)
-            first = kv.view(np.uint64).reshape(nv, 4)[:, 0]
-        else:
-            kv, first = keys[:nv], keys[:nv]
-        vv = synth.values_for(first, SEED, 64)
-        tv = g.StaticTree(kv, vv, kb, m)
-        row = {"keys": nv, "height": tv.stats()["height"]}
-        for bq in ((1000, 1 << 20) if kb == 32 else (1024, 1 << 20)):
-            nbq = 256 if bq <= 8192 else 4
-            idx = synth.Stream(SEED, 8900 + bq).below(nbq * bq, nv)
-            qh = kv[idx]
-            qdev = tv.dev_keys(qh)
-            per = kb if kb == 32 else 1     # tensor elements per key (bytes, or one u64)
-            qb = [qdev[i * bq * per:(i + 1) * bq * per] for i in range(nbq)]
-            vo8 = torch.empty(bq, dtype=torch.int64, device=dev)
-            fo8 = torch.empty(bq, dtype=torch.uint8, device=dev)
-            L = g.lib()
-            fn = lambda i: L.tree_lookup_batch(tv.h, g._ptr(qb[i]), bq, g._ptr(vo8), g._ptr(fo8),  # noqa: E731
-                                               g._stream(stream))
-            if bq <= 8192:
-                graphs = [capture(fn, c, GR) for c in range(0, nbq, GR)]
-                graphs[0].replay()
-                stream.synchronize()
-                best = None
-                for _ in range(3):
-                    t0 = time.perf_counter()
-                    for gr in graphs:
-                        gr.replay()
-                    stream.synchronize()
-                    dt = (time.perf_counter() - t0) / nbq * 1e6
-                    best = dt if best is None else min(best, dt)
-                del graphs
-                us = best
-            else:
-                us = iqm(timer.run(lambda: fn(nbq - 1), 10, skip=2))
-                fn(nbq - 1)
-            stream.synchronize()
-            want = vv[idx[(nbq - 1) * bq:]]
-            assert g.to_numpy(fo8).all() and np.array_equal(g.to_numpy(vo8, np.uint64), want), (kb, m, nv, bq)
-            row[f"b{bq}_us"] = round(us, 3)
-            row[f"b{bq}_mops"] = round(bq / us, 2)
-            del qdev, qb
-        variants[f"k{kb}_m{m}_n{nv}"] = row
-        tv.close()
-        del kv, vv
-    print("[bench] paper variants done", file=sys.stderr, flush=True)
+    variants = run_variants(torch, g, keys, stream, timer, capture, GR)
 
     # ---- mixed batches on a restored snapshot: per batch size and query
     # distribution the bulk-loaded tree is restored (a device copy of its
