@@ -6,12 +6,20 @@
 //
 // Layout in the caller's arena (256-byte aligned regions):
 //   WideHeader                     root, height, key count, node counts
-//   ikeys[inner][m]                entry i < c-1: the largest key below
-//                                  child i; entries from c-1 on: the largest
-//                                  key value (all bytes 0xFF)
-//   imeta[inner]                   {first child, children}: a bulk-loaded
+//   ikeys[inner][kw][m]            word-sliced 8-byte words: word w of
+//                                  entry i (w = 0 most significant; a
+//                                  32-byte key's words as big-endian
+//                                  numbers).  Entry i < c-1: the largest key
+//                                  below child i; entries from c-1 on: the
+//                                  largest key value (all bytes 0xFF)
+//   imeta[inner]                   {first child, children, tie mask (2 x
+//                                  32 bits, low first)}: a bulk-loaded
 //                                  node's children are consecutive ids of
-//                                  the level below
+//                                  the level below; bit i of the mask: entry
+//                                  i's leading word equals that of the next
+//                                  key in key order (the first key of child
+//                                  i+1).  One 16-byte record per node, read
+//                                  in one load
 //   lkeys[leaves][m]               up to m-1 keys ascending (the paper's
 //                                  k_max = m - 1); slots from count on
 //                                  repeat the last key
@@ -42,7 +50,7 @@ static_assert(sizeof(WideHeader) == 64, "WideHeader size");
 struct WideView {
     const WideHeader* hdr;
     const uint8_t* ikeys;
-    const uint2* imeta;
+    const uint4* imeta;
     const uint8_t* lkeys;
     const uint64_t* lvals;
     const uint2* lmeta;
@@ -55,7 +63,7 @@ struct WideTree {
     double fill;
     WideHeader* hdr;
     uint8_t* ikeys;
-    uint2* imeta;
+    uint4* imeta;
     uint8_t* lkeys;
     uint64_t* lvals;
     uint2* lmeta;

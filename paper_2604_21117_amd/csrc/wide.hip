@@ -6,9 +6,12 @@
 // significant first (a word decides unless it is equal, as the paper's
 // cascading priority comparison resolves its 32 per-byte comparators), and
 // the group's ballot of "entry < query" counted by popcount is the priority
-// encoder: the child is the first one whose entry is >= the query.  The
-// node's child range comes from one 8-byte record read in the same round as
-// the entries, so a level costs one dependent round.  At the leaf each lane
+// encoder: the child is the first one whose entry is >= the query.  Inner
+// entries are stored word-sliced, so a level first reads only the leading
+// words and goes on to a further word only for entries that tie the query
+// on every word so far.  The node's child range comes from one 8-byte record
+// read in the same round as the leading words, so a level costs one
+// dependent round unless an entry ties.  At the leaf each lane
 // compares its key for equality and reads its value in the same round; the
 // first matching lane answers (the paper's 8-byte data), else the result is
 // all ones with found = 0 (Section IV-D's -1).  Ranges descend with lo and
@@ -119,15 +122,45 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
 // Descend from the root to the leaf whose key range holds `key` (the first
 // child whose entry is >= key at every level).  Every lane of the group
 // takes part; `ref` ends as a leaf id.
-template <int KW, int M>
+// An inner node's entries are word-sliced: word w (0 = most significant,
+// as a big-endian number) of its m entries sits in m consecutive 8-byte
+// words, so a level reads the leading words alone (one 128-byte line at
+// m = 16).  A lane whose leading word ties the query's goes on to the
+// entry's other words (read together, one more round) -- the cascade of the
+// paper's priority comparison, taken through memory -- unless the tie
+// already decides: when the key after the entry in key order (the first of
+// the next child) has a larger leading word, no key of a later child shares
+// the query's leading word, so a present query lies at or below the entry.
+// Exact-match lookups take that shortcut (bit s of the node's mask is set
+// when it does not apply); range descents, which need the exact first key
+// >= lo, compare in full.  Entries below the child count are sorted, so the
+// "entry < query" lanes stay a prefix of the group either way.
+template <int KW, int M, bool Exact>
 __device__ __forceinline__ uint32_t descend(const WideView& v, const Key<KW>& key, bool valid, uint32_t root,
                                             uint32_t height, int s, int gbase) {
-    constexpr uint64_t KB = 8 * KW;
+    const uint64_t* ik = reinterpret_cast<const uint64_t*>(v.ikeys);
     uint32_t ref = root;
     for (uint32_t d = 0; d + 1 < height; ++d) {
-        const Key<KW> e = load_key<KW>(v.ikeys + (static_cast<uint64_t>(ref) * M + s) * KB);
-        const uint2 meta = v.imeta[ref];
-        const bool lt = valid && key_less<KW>(e, key);
+        const uint64_t base = static_cast<uint64_t>(ref) * KW * M + s;
+        const uint64_t e0 = ik[base];
+        const uint4 meta = v.imeta[ref];
+        bool lt = e0 < key.w[0];
+        if constexpr (KW > 1) {
+            const uint64_t mask = Exact ? ~0ull : (static_cast<uint64_t>(meta.w) << 32 | meta.z);
+            const bool need = valid && e0 == key.w[0] && ((mask >> s) & 1ull);
+            if (__ballot(need)) {
+                if (need) {
+                    uint64_t e[KW];
+#pragma unroll
+                    for (int w = 1; w < KW; ++w) e[w] = ik[base + static_cast<uint64_t>(w) * M];
+                    bool l = e[KW - 1] < key.w[KW - 1];
+#pragma unroll
+                    for (int w = KW - 2; w >= 1; --w) l = (e[w] < key.w[w]) || (e[w] == key.w[w] && l);
+                    lt = l;
+                }
+            }
+        }
+        lt = valid && lt;
         const uint32_t ci = static_cast<uint32_t>(__popcll(group_bits<M>(__ballot(lt), gbase)));
         ref = meta.x + ci;
     }
@@ -148,7 +181,7 @@ __global__ __launch_bounds__(kWBlock) void k_wlookup(WideView v, const uint8_t* 
         const uint64_t i = base + lane / M;
         const bool valid = i < B;
         const Key<KW> key = valid ? load_key<KW>(q + i * KB) : max_key<KW>();
-        const uint32_t leaf = descend<KW, M>(v, key, valid, root, height, s, gbase);
+        const uint32_t leaf = descend<KW, M, false>(v, key, valid, root, height, s, gbase);
         const Key<KW> lk = load_key<KW>(v.lkeys + (static_cast<uint64_t>(leaf) * M + s) * KB);
         const uint64_t val = v.lvals[static_cast<uint64_t>(leaf) * M + s];
         // the padding repeats the last key, so the first equal slot is a
@@ -184,7 +217,7 @@ __global__ __launch_bounds__(kWBlock) void k_wrange(WideView v, const uint8_t* _
         const Key<KW> b = valid ? load_key<KW>(hi + i * KB) : max_key<KW>();
         const uint32_t mx = valid ? maxc[i] : 0u;
         const uint64_t o = valid ? off[i] : 0ull;
-        uint32_t leaf = descend<KW, M>(v, a, valid, root, height, s, gbase);
+        uint32_t leaf = descend<KW, M, true>(v, a, valid, root, height, s, gbase);
         uint32_t c = 0;
         bool active = valid && !empty && mx > 0 && !key_less<KW>(b, a);
         // walk the chain; the loop runs while any group of the wave is active
@@ -263,7 +296,7 @@ __global__ void k_wdup(const uint8_t* __restrict__ sk, uint64_t n, uint32_t* fla
 template <int KW, int M>
 __global__ void k_wleaves(uint8_t* __restrict__ lkeys, uint64_t* __restrict__ lvals, uint2* __restrict__ lmeta,
                           const uint8_t* __restrict__ sk, const uint64_t* __restrict__ sv, uint64_t n, uint64_t L,
-                          uint8_t* __restrict__ maxk) {
+                          uint8_t* __restrict__ maxk, uint64_t* __restrict__ succ) {
     constexpr uint64_t KB = 8 * KW;
     for (uint64_t t = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; t < L * M;
          t += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
@@ -275,6 +308,9 @@ __global__ void k_wleaves(uint8_t* __restrict__ lkeys, uint64_t* __restrict__ lv
         if (s == 0) {
             lmeta[j] = make_uint2(static_cast<uint32_t>(c), j + 1 < L ? static_cast<uint32_t>(j + 1) : kNone);
             store_key<KW>(maxk + j * KB, c ? load_key<KW>(sk + (e - 1) * KB) : max_key<KW>());
+            // leading word of the key after the leaf's last one (all ones
+            // past the end)
+            succ[j] = e < n ? load_key<KW>(sk + e * KB).w[0] : ~0ull;
         }
     }
 }
@@ -283,18 +319,31 @@ __global__ void k_wleaves(uint8_t* __restrict__ lkeys, uint64_t* __restrict__ lv
 // node j holds children [j C / P, (j+1) C / P); entry s < c-1 is child s's
 // largest key, later entries the largest key value
 template <int KW, int M>
-__global__ void k_winner(uint8_t* __restrict__ ikeys, uint2* __restrict__ imeta, const uint8_t* __restrict__ cmax,
-                         uint64_t C, uint64_t P, uint32_t node_base, uint8_t* __restrict__ nmax) {
+__global__ void k_winner(uint8_t* __restrict__ ikeys, uint4* __restrict__ imeta,
+                         const uint8_t* __restrict__ cmax, const uint64_t* __restrict__ csucc, uint64_t C, uint64_t P,
+                         uint32_t node_base, uint8_t* __restrict__ nmax, uint64_t* __restrict__ nsucc) {
     constexpr uint64_t KB = 8 * KW;
+    // the stride is a multiple of 64 and M divides 64, so a node's M
+    // entries are M consecutive lanes of one wave in every pass
+    const int lane = threadIdx.x & 63, gbase = lane - lane % M;
     for (uint64_t t = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; t < P * M;
          t += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
         const uint64_t j = t / M, s = t % M;
         const uint64_t b = part_start(j, C, P), e = part_start(j + 1, C, P), c = e - b;
         const Key<KW> k = (s + 1 < c) ? load_key<KW>(cmax + (b + s) * KB) : max_key<KW>();
-        store_key<KW>(ikeys + (node_base + j) * M * KB + s * KB, k);
+        // word-sliced: word w of entry s at ((node * KW) + w) * M + s, as a
+        // big-endian number (the order the search compares in)
+        uint64_t* ik = reinterpret_cast<uint64_t*>(ikeys);
+#pragma unroll
+        for (int w = 0; w < KW; ++w) ik[((node_base + j) * KW + w) * M + s] = k.w[w];
+        // the entry's leading word is shared with the next key in key order
+        const bool shared = s + 1 < c && k.w[0] == csucc[b + s];
+        const uint64_t bits = group_bits<M>(__ballot(shared), gbase);
         if (s == 0) {
-            imeta[node_base + j] = make_uint2(static_cast<uint32_t>(b), static_cast<uint32_t>(c));
+            imeta[node_base + j] = make_uint4(static_cast<uint32_t>(b), static_cast<uint32_t>(c),
+                                              static_cast<uint32_t>(bits), static_cast<uint32_t>(bits >> 32));
             store_key<KW>(nmax + j * KB, load_key<KW>(cmax + (e - 1) * KB));
+            nsucc[j] = csucc[e - 1];
         }
     }
 }
@@ -358,8 +407,8 @@ WSizes wsizes(int kb, int m, uint64_t n, double fill) {
     for (size_t i = 1; i < lv.size(); ++i) z.inner += lv[i];
     z.height = static_cast<int>(lv.size());
     const uint64_t ni = z.inner ? z.inner : 1;
-    z.bytes = al(sizeof(WideHeader)) + al(ni * m * kb) + al(ni * 8) + al(z.leaves * m * kb) + al(z.leaves * m * 8) +
-              al(z.leaves * 8);
+    z.bytes = al(sizeof(WideHeader)) + al(ni * m * kb) + al(ni * 16) + al(z.leaves * m * kb) +
+              al(z.leaves * m * 8) + al(z.leaves * 8);
     return z;
 }
 
@@ -383,21 +432,24 @@ void launch_wrange(const WideView& v, const void* lo, const void* hi, const uint
 
 template <int KW, int M>
 void launch_wpack(WideTree* w, const uint8_t* sk, const uint64_t* sv, uint64_t n, const std::vector<uint64_t>& lv,
-                  uint8_t* maxa, uint8_t* maxb, hipStream_t s) {
+                  uint8_t* maxa, uint8_t* maxb, uint64_t* succa, uint64_t* succb, hipStream_t s) {
     const uint64_t L = lv[0];
     hipLaunchKernelGGL((k_wleaves<KW, M>), dim3(grid_for(L * M, kWBlock)), dim3(kWBlock), 0, s, w->lkeys, w->lvals,
-                       w->lmeta, sk, sv, n, L, maxa);
+                       w->lmeta, sk, sv, n, L, maxa, succa);
     // inner ids top-down: the level just above the leaves gets the last ids
     uint64_t below = L;
     uint64_t base = w->inner_cap;
     uint8_t* cur = maxa;
     uint8_t* nxt = maxb;
+    uint64_t* scur = succa;
+    uint64_t* snxt = succb;
     for (size_t l = 1; l < lv.size(); ++l) {
         const uint64_t P = lv[l];
         base -= P;
         hipLaunchKernelGGL((k_winner<KW, M>), dim3(grid_for(P * M, kWBlock)), dim3(kWBlock), 0, s, w->ikeys, w->imeta,
-                           cur, below, P, static_cast<uint32_t>(base), nxt);
+                           cur, scur, below, P, static_cast<uint32_t>(base), nxt, snxt);
         std::swap(cur, nxt);
+        std::swap(scur, snxt);
         below = P;
     }
 }
@@ -406,7 +458,7 @@ void launch_wpack(WideTree* w, const uint8_t* sk, const uint64_t* sv, uint64_t n
 // inner ids for inner children (leaf children keep their leaf ids)
 void fix_child_bases(WideTree* w, const std::vector<uint64_t>& lv, hipStream_t s);
 
-__global__ void k_rebase(uint2* imeta, uint32_t first, uint32_t count, uint32_t add) {
+__global__ void k_rebase(uint4* imeta, uint32_t first, uint32_t count, uint32_t add) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
         imeta[first + i].x += add;
 }
@@ -504,7 +556,7 @@ gt_status wide_build(const gt_params* p, const void* keys, const void* values, u
     const uint64_t ni = z.inner ? z.inner : 1;
     w->hdr = reinterpret_cast<WideHeader*>(a + o); o += al(sizeof(WideHeader));
     w->ikeys = a + o; o += al(ni * m * kb);
-    w->imeta = reinterpret_cast<uint2*>(a + o); o += al(ni * 8);
+    w->imeta = reinterpret_cast<uint4*>(a + o); o += al(ni * 16);
     w->lkeys = a + o; o += al(z.leaves * m * kb);
     w->lvals = reinterpret_cast<uint64_t*>(a + o); o += al(z.leaves * m * 8);
     w->lmeta = reinterpret_cast<uint2*>(a + o); o += al(z.leaves * 8);
@@ -516,8 +568,8 @@ gt_status wide_build(const gt_params* p, const void* keys, const void* values, u
     // sort-failure flag
     const uint64_t nn = n ? n : 1;
     const uint64_t b_keys = al(nn * kb), b_vals = al(nn * 8), b_idx = al(nn * 4), b_word = al(nn * 8);
-    const uint64_t b_sort = al(sort_tmp_bytes(nn, 8)), b_max = al(z.leaves * kb);
-    const uint64_t total = b_keys + b_vals + 4 * b_idx + 3 * b_word + b_sort + 2 * b_max + kAl;
+    const uint64_t b_sort = al(sort_tmp_bytes(nn, 8)), b_max = al(z.leaves * kb), b_succ = al(z.leaves * 8);
+    const uint64_t total = b_keys + b_vals + 4 * b_idx + 3 * b_word + b_sort + 2 * b_max + 2 * b_succ + kAl;
     uint8_t* tmp = nullptr;
     if (hipMalloc(&tmp, total) != hipSuccess) {
         delete w;
@@ -536,6 +588,8 @@ gt_status wide_build(const gt_params* p, const void* keys, const void* values, u
     void* stmp = q; q += b_sort;
     uint8_t* maxa = q; q += b_max;
     uint8_t* maxb = q; q += b_max;
+    uint64_t* succa = reinterpret_cast<uint64_t*>(q); q += b_succ;
+    uint64_t* succb = reinterpret_cast<uint64_t*>(q); q += b_succ;
     uint32_t* flag = reinterpret_cast<uint32_t*>(q);
 
     gt_status st = GT_OK;
@@ -585,7 +639,7 @@ gt_status wide_build(const gt_params* p, const void* keys, const void* values, u
         if (hflag & 2u) { st = GT_ERR_DEVICE; break; }  // a sort gave up its bounded wait
         if (hflag) { st = GT_ERR_DUPLICATE; break; }
         dispatch(kw, m, [&](auto KWc, auto Mc) {
-            launch_wpack<decltype(KWc)::value, decltype(Mc)::value>(w, sk, sv, n, lv, maxa, maxb, s);
+            launch_wpack<decltype(KWc)::value, decltype(Mc)::value>(w, sk, sv, n, lv, maxa, maxb, succa, succb, s);
         });
         fix_child_bases(w, lv, s);
         hipLaunchKernelGGL(k_wheader, dim3(1), dim3(64), 0, s, w->hdr, static_cast<uint32_t>(z.height), n,
@@ -664,11 +718,12 @@ gt_status wide_export(const WideTree* w, void* host_buf, uint64_t* bytes, hipStr
     }
     if (*bytes < need) return GT_ERR_CAPACITY;
     std::vector<uint8_t> ik(ni * m * kb), lk(nl * m * kb);
-    std::vector<uint2> im(ni), lm(nl);
+    std::vector<uint4> im(ni);
+    std::vector<uint2> lm(nl);
     std::vector<uint64_t> lvv(nl * m);
     if (ni) {
         WHIP(hipMemcpyAsync(ik.data(), w->ikeys, ik.size(), hipMemcpyDeviceToHost, s));
-        WHIP(hipMemcpyAsync(im.data(), w->imeta, ni * 8, hipMemcpyDeviceToHost, s));
+        WHIP(hipMemcpyAsync(im.data(), w->imeta, ni * 16, hipMemcpyDeviceToHost, s));
     }
     if (nl) {
         WHIP(hipMemcpyAsync(lk.data(), w->lkeys, lk.size(), hipMemcpyDeviceToHost, s));
@@ -689,8 +744,17 @@ gt_status wide_export(const WideTree* w, void* host_buf, uint64_t* bytes, hipStr
     memcpy(o, hdr, 40);
     memcpy(o + 40, &h.n_keys, 8);
     o += 48;
+    const uint64_t kw = static_cast<uint64_t>(w->kw);
     for (uint64_t i = 0; i < ni; ++i) {
-        memcpy(o, ik.data() + i * m * kb, m * kb);
+        // inner entries back from word slices to key bytes: a 32-byte key's
+        // words are big-endian numbers, an 8-byte key's word is native
+        for (uint64_t j = 0; j < m; ++j)
+            for (uint64_t wd = 0; wd < kw; ++wd) {
+                uint64_t x;
+                memcpy(&x, ik.data() + ((i * kw + wd) * m + j) * 8, 8);
+                if (kw > 1) x = __builtin_bswap64(x);
+                memcpy(o + j * kb + wd * 8, &x, 8);
+            }
         uint32_t* ch = reinterpret_cast<uint32_t*>(o + m * kb);
         const bool leaf_kids = i >= leaf_parents_first;
         for (uint64_t j = 0; j < m; ++j) {

@@ -129,6 +129,53 @@ def test_static_build_lookup_range(kb, m, n):
     t.close()
 
 
+def _unique_rows(k):
+    u = np.unique(np.ascontiguousarray(k).view(np.dtype((np.void, 32))).ravel())
+    return u.view(np.uint8).reshape(-1, 32)
+
+
+@pytest.mark.parametrize("m", [16, 32, 64])
+def test_static_leading_word_ties(m):
+    """Keys whose first 8 bytes come from a small pool, so that separators
+    tie queries on their leading word both where the next key in order
+    shares it and where it does not; queries are present keys, present keys
+    with the last byte moved up or down (absent, same leading word), and
+    every pool word with all-zero and all-one tails.  Lookups and range
+    lower bounds against the oracle."""
+    s = synth.Stream(901 + m, 1)
+    n = 40000
+    pool = s.draw(5000).view(np.uint8).reshape(5000, 8)
+    k = s.draw(n * 4).view(np.uint8).reshape(n, 32).copy()
+    k[:, :8] = pool[s.below(n, 5000).astype(np.int64)]
+    k = _unique_rows(k)
+    k = k[np.argsort(s.draw(len(k)), kind="stable")]
+    v = synth.values_for(k.view(np.uint64).reshape(len(k), -1)[:, 0], 7, 64)
+    import paper_2604_21117_amd as g
+    t = g.StaticTree(k, v, 32, m)
+    ref = oracle.SortedBytes(k, v)
+    sk = ref.keys
+    up, down = sk.copy(), sk.copy()
+    up[:, 31] += 1
+    down[:, 31] -= 1
+    lo0, hi1 = np.zeros((5000, 32), np.uint8), np.full((5000, 32), 0xFF, np.uint8)
+    lo0[:, :8] = pool
+    hi1[:, :8] = pool
+    q = np.concatenate([sk, up, down, lo0, hi1])
+    q = q[np.argsort(s.draw(len(q)), kind="stable")]
+    check_lookup(t, ref, q)
+    B = 4000
+    lo = q[:B]
+    hi = q[B:2 * B]
+    mc = s.below(B, 40).astype(np.uint32)
+    gc, goff, gk, gv = t.range(lo, hi, mc)
+    oc, ooff, ok, ov = ref.range(lo, hi, mc)
+    assert np.array_equal(gc, oc), f"range counts differ at {np.nonzero(gc != oc)[0][:8]}"
+    for i in np.nonzero(oc)[0]:
+        sl = slice(int(ooff[i]), int(ooff[i] + oc[i]))
+        assert np.array_equal(gk[sl], ok[sl]) and np.array_equal(gv[sl], ov[sl]), f"range {i} differs"
+    t.close()
+
+
 @pytest.mark.parametrize("kb,m", COMBOS)
 @pytest.mark.parametrize("fill", [0.5, 0.75])
 def test_static_partial_fill(kb, m, fill):
