@@ -33,6 +33,17 @@ extern "C" {
  */
 uint32_t gt_set_sort_spin_limit(uint32_t limit);
 
+/*
+ * Testing switch of the one-key insert: a batch of B = 1 runs in one kernel
+ * (descent, leaf and parent rewrites, header, mirror) instead of the batch
+ * path's kernels, with the same resulting tree.  enable = 0 sends B = 1
+ * through the batch path, so that tests can compare the two; any other
+ * value restores the default (on).  Process-wide, read when an insert is
+ * launched (a captured graph keeps the path it was captured with).
+ * Returns the previous setting (1 on, 0 off).
+ */
+int gt_set_single_key_insert(int enable);
+
 #ifdef __cplusplus
 }
 #endif

@@ -117,6 +117,8 @@ def lib():
         L.tree_export.argtypes = [vp, vp, C.POINTER(u64), vp]
         L.gt_set_sort_spin_limit.argtypes = [u32]
         L.gt_set_sort_spin_limit.restype = u32
+        L.gt_set_single_key_insert.argtypes = [C.c_int]
+        L.gt_set_single_key_insert.restype = C.c_int
         L.li_arena_bytes.argtypes = [vp, C.POINTER(gt_li_params)]
         L.li_arena_bytes.restype = u64
         L.li_create.argtypes = [vp, C.POINTER(gt_li_params), vp, u64, C.POINTER(vp)]
@@ -275,6 +277,13 @@ def set_sort_spin_limit(limit: int) -> int:
     """Testing hook: the device sort's look-back limit (0 makes every sort
     of more than 4096 keys fail); returns the previous value."""
     return int(lib().gt_set_sort_spin_limit(limit))
+
+
+def set_single_key_insert(enable: bool) -> bool:
+    """Testing switch: a one-key insert batch runs in its own kernel (True,
+    the default) or through the batch path (False); returns the previous
+    setting."""
+    return bool(lib().gt_set_single_key_insert(1 if enable else 0))
 
 
 def tree_export(h, stream=None) -> np.ndarray:

@@ -20,6 +20,9 @@ struct InsertCtx {
 // node pools of the given capacities.
 uint64_t insert_scratch_bytes(uint64_t max_batch, int key_bytes, uint64_t leaf_cap, uint64_t inner_cap);
 
+// Testing switch of the one-key insert kernel; returns the previous setting.
+int set_single_key_insert(int on);
+
 template <class K>
 void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, const K* vals, uint64_t B,
                    uint8_t* status, hipStream_t s);

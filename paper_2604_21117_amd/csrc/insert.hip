@@ -35,6 +35,8 @@
 //     levels above it, packed with the same even rule.
 //  6. Commit the header (key count, pool cursors, height, root) and refresh
 //     the top-levels mirror.
+#include <atomic>
+
 #include "insert.h"
 #include "mirror.h"
 #include "prims.h"
@@ -858,6 +860,223 @@ __global__ __launch_bounds__(kFusedBlock) void k_small_apply(TreeView<K> t, Ins<
     if (v.st->mirror_dirty) mirror_refresh_body<K, kFusedBlock>(t);
 }
 
+// ------------------------------------------------------ one key (B = 1)
+//
+// A batch of one key in one workgroup.  Wave 0 descends from the root,
+// keeping each inner node's key and child lines (lane s holds slot s, one
+// copy per lane in LDS), and finds the key in its leaf.  A present key gets
+// its value.  A new key goes into its leaf; a leaf that held 16 keys splits
+// evenly into two, and so does every parent, from the leaves up, that held
+// 16 children when a child split; a root that splits grows a new root.
+// Node ids, separators, padding, the capacity check and the header commit
+// are those the batch path (plan, check and apply above) gives a one-key
+// batch, so both leave the same tree.  Every read precedes every write; the
+// whole workgroup then refreshes the mirror if the top levels changed.
+constexpr int kOneBlock = 256;
+
+template <class K>
+__global__ __launch_bounds__(kOneBlock) void k_insert_one(TreeView<K> t, const K* __restrict__ keys,
+                                                          const K* __restrict__ vals, uint8_t* __restrict__ status) {
+    __shared__ K s_sep[kMaxLevels][64];
+    __shared__ uint32_t s_ch[kMaxLevels][64];
+    __shared__ uint32_t s_node[kMaxLevels], s_cnt[kMaxLevels], s_slot[kMaxLevels];
+    __shared__ uint32_t s_dirty;
+    const uint32_t tid = threadIdx.x;
+    if (tid < 64) {
+        const int s = static_cast<int>(tid) & (kSlots - 1);
+        const bool w = tid < static_cast<uint32_t>(kSlots);  // the lanes that write slot s
+        DevHeader* hdr = t.hdr;
+        const K key = keys[0], val = vals[0];
+        const uint32_t h = hdr->height, root = hdr->root, err = hdr->error, epoch = hdr->epoch;
+        const uint64_t n0 = hdr->n_keys;
+        const uint32_t leaf_used = hdr->leaf_used, inner_used = hdr->inner_used;
+
+        // descent: inner level l (0 = root); slot 15 is never a separator
+        uint32_t ref = root;
+        for (uint32_t l = 0; l + 1 < h; ++l) {
+            const uint64_t at = static_cast<uint64_t>(ref) * kSlots + s;
+            const K sp = t.ikeys[at];
+            const uint32_t c = t.ichild[at];
+            const uint32_t ci = static_cast<uint32_t>(__popcll(__ballot(sp < key) & 0x7FFFull));
+            const uint32_t cnt =
+                1u + static_cast<uint32_t>(__popcll(__ballot(s < kFirstSlot && sp != kmax<K>()) & 0xFFFFull));
+            s_sep[l][tid] = sp;
+            s_ch[l][tid] = c;
+            s_node[l] = ref;
+            s_cnt[l] = cnt;
+            s_slot[l] = ci;
+            ref = shfl_u32(c, static_cast<int>(ci));
+        }
+        const uint32_t lf = ref & ~kLeafTag;
+        const uint64_t la = static_cast<uint64_t>(lf) * kSlots;
+        const K lk = t.lkeys[la + s];
+        const K lv = t.lvals[la + s];
+        const uint2 meta = t.lmeta[lf];
+        __threadfence_block();  // every old line is in registers before any write
+        const uint64_t eq = __ballot(lk == key) & 0xFFFFull;
+        bool ok = !(err & kErrInternal);
+        uint32_t dirty = 0;
+        if (eq && n0 != 0) {
+            // present: the value in place (padding repeats the last key, so
+            // the first equal slot is a real one)
+            const uint32_t fs = static_cast<uint32_t>(__builtin_ctzll(eq));
+            if (tid == 0) {
+                status[0] = 1;
+                if (ok) {
+                    t.lvals[la + fs] = val;
+                    hdr->epoch = epoch + 1;
+                    reinterpret_cast<MirrorHeader*>(t.mirror)->n_keys = n0;
+                }
+            }
+        } else {
+            const uint32_t c = meta.x, total = c + 1;
+            const uint32_t pos =
+                static_cast<uint32_t>(__popcll(__ballot(static_cast<uint32_t>(s) < c && lk < key) & 0xFFFFull));
+            // levels that split, counted from the leaves (0) up
+            uint32_t nsplit = total > static_cast<uint32_t>(kSlots) ? 1u : 0u;
+            if (nsplit)
+                for (int l = static_cast<int>(h) - 2; l >= 0 && s_cnt[l] + 1 > static_cast<uint32_t>(kSlots); --l)
+                    ++nsplit;
+            const bool grow = nsplit == h;
+            const uint32_t leaf_new = nsplit ? 1u : 0u;
+            const uint32_t inner_split = nsplit ? nsplit - 1 : 0u;
+            const uint32_t inner_new = inner_split + (grow ? 1u : 0u);
+            if (static_cast<uint64_t>(leaf_used) + leaf_new > t.leaf_cap ||
+                static_cast<uint64_t>(inner_used) + inner_new > t.inner_cap || h + (grow ? 1u : 0u) > kMaxLevels)
+                ok = false;
+            if (tid == 0) status[0] = 0;
+            if (!ok) {
+                if (tid == 0 && !(err & kErrInternal)) atomicOr(&hdr->error, kErrCapacity);
+            } else {
+                // leaf entry e of the c + 1: old keys below pos, the new key,
+                // old keys above
+                auto lentry = [&](uint32_t e, K& ke, K& ve) {
+                    const int src = static_cast<int>(e <= pos ? e : e - 1);
+                    const K ok_ = __shfl(lk, src, 64), ov = __shfl(lv, src, 64);
+                    ke = e == pos ? key : ok_;
+                    ve = e == pos ? val : ov;
+                };
+                K sepup = K(0);
+                uint32_t newref = 0;
+                if (total <= static_cast<uint32_t>(kSlots)) {
+                    const uint32_t e = static_cast<uint32_t>(s) < total ? static_cast<uint32_t>(s) : total - 1;
+                    K ke, ve;
+                    lentry(e, ke, ve);
+                    if (w) {
+                        t.lkeys[la + s] = ke;
+                        t.lvals[la + s] = static_cast<uint32_t>(s) < total ? ve : kmax<K>();
+                    }
+                    if (tid == 0) t.lmeta[lf] = make_uint2(total, meta.y);
+                } else {
+                    // 17 entries: [0, 8) stay, [8, 17) go to leaf_used
+                    const uint64_t nb = static_cast<uint64_t>(leaf_used) * kSlots;
+                    K k0, v0, k1, v1, k7, v7;
+                    lentry(s < 8 ? static_cast<uint32_t>(s) : 7u, k0, v0);
+                    lentry(8u + (s < 9 ? static_cast<uint32_t>(s) : 8u), k1, v1);
+                    lentry(7u, k7, v7);
+                    if (w) {
+                        t.lkeys[la + s] = k0;
+                        t.lvals[la + s] = s < 8 ? v0 : kmax<K>();
+                        t.lkeys[nb + s] = k1;
+                        t.lvals[nb + s] = s < 9 ? v1 : kmax<K>();
+                    }
+                    if (tid == 0) {
+                        t.lmeta[lf] = make_uint2(8u, leaf_used);
+                        t.lmeta[leaf_used] = make_uint2(9u, meta.y);
+                    }
+                    sepup = k7;
+                    newref = kLeafTag | leaf_used;
+                }
+                // parents from the leaf parents up, while a child split
+                uint32_t cursor = inner_used;
+                bool split = nsplit > 0;
+                for (int l = static_cast<int>(h) - 2; l >= 0 && split; --l) {
+                    const uint32_t C = s_cnt[l], cs = s_slot[l], node = s_node[l], E = C + 1;
+                    const K osp = s_sep[l][tid];
+                    const uint32_t och = s_ch[l][tid];
+                    // entry e of the C + 1: the split child's slot holds its
+                    // first piece with the piece separator, the next entry its
+                    // second piece with the child's old separator
+                    auto ientry = [&](uint32_t e, K& se, uint32_t& ce) {
+                        const uint32_t src = e <= cs ? e : e - 1;
+                        const K sv = __shfl(osp, static_cast<int>(src), 64);
+                        const uint32_t cv = shfl_u32(och, static_cast<int>(src));
+                        se = e == cs ? sepup : (src + 1 < C ? sv : kmax<K>());
+                        ce = e == cs + 1 ? newref : cv;
+                    };
+                    const uint64_t na = static_cast<uint64_t>(node) * kSlots;
+                    if (E <= static_cast<uint32_t>(kSlots)) {
+                        K se;
+                        uint32_t ce;
+                        ientry(static_cast<uint32_t>(s) < E ? static_cast<uint32_t>(s) : 0u, se, ce);
+                        if (w) {
+                            const bool in = static_cast<uint32_t>(s) < E;
+                            t.ikeys[na + s] = in && static_cast<uint32_t>(s) + 1 < E ? se : kmax<K>();
+                            t.ichild[na + s] = in ? ce : kNone;
+                        }
+                        split = false;
+                    } else {
+                        // 17 entries: [0, 8) stay, [8, 17) go to a new node
+                        const uint32_t ni = cursor++;
+                        const uint64_t nn = static_cast<uint64_t>(ni) * kSlots;
+                        K s0, s1, s7;
+                        uint32_t c0, c1, c7;
+                        ientry(s < 8 ? static_cast<uint32_t>(s) : 0u, s0, c0);
+                        ientry(8u + (s < 9 ? static_cast<uint32_t>(s) : 0u), s1, c1);
+                        ientry(7u, s7, c7);
+                        if (w) {
+                            t.ikeys[na + s] = s + 1 < 8 ? s0 : kmax<K>();
+                            t.ichild[na + s] = s < 8 ? c0 : kNone;
+                            t.ikeys[nn + s] = s + 1 < 9 ? s1 : kmax<K>();
+                            t.ichild[nn + s] = s < 9 ? c1 : kNone;
+                        }
+                        sepup = s7;
+                        newref = ni;
+                    }
+                }
+                uint32_t new_root = root;
+                if (split) {
+                    // the root split: a new root over its two pieces
+                    new_root = cursor;
+                    const uint32_t oldref = h == 1 ? (kLeafTag | lf) : s_node[0];
+                    const uint64_t ra = static_cast<uint64_t>(new_root) * kSlots;
+                    if (w) {
+                        t.ikeys[ra + s] = s == 0 ? sepup : kmax<K>();
+                        t.ichild[ra + s] = s == 0 ? oldref : (s == 1 ? newref : kNone);
+                    }
+                }
+                if (tid == 0) {
+                    hdr->n_keys = n0 + 1;
+                    hdr->leaf_used = leaf_used + leaf_new;
+                    hdr->inner_used = inner_used + inner_new;
+                    if (grow) {
+                        hdr->height = h + 1;
+                        hdr->root = new_root;
+                    }
+                    hdr->epoch = epoch + 1;
+                    reinterpret_cast<MirrorHeader*>(t.mirror)->n_keys = n0 + 1;
+                }
+                // the mirror's levels change when the tree was empty, the root
+                // grew, or children of its top three levels split
+                bool d = grow || n0 == 0;
+                for (int l = 0; l < 3; ++l) {
+                    const int dc = static_cast<int>(h) - 2 - l;
+                    if (dc >= 0 && static_cast<uint32_t>(dc) < nsplit) d = true;
+                }
+                dirty = d ? 1u : 0u;
+            }
+        }
+        if (tid == 0) s_dirty = dirty;
+    }
+    __syncthreads();
+    if (s_dirty) mirror_refresh_body<K, kOneBlock>(t);
+}
+
+// The testing switch of the one-key kernel (on by default).
+static std::atomic<int> g_single_key{1};
+int set_single_key_insert(int on) { return g_single_key.exchange(on ? 1 : 0, std::memory_order_relaxed); }
+static bool single_key_insert_on() { return g_single_key.load(std::memory_order_relaxed) != 0; }
+
 // ------------------------------------------------- small batches (B <= 2048)
 //
 // A rank sort over many workgroups orders the batch and one workgroup
@@ -1198,6 +1417,10 @@ void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, cons
     const uint32_t gB = grid_for(B, kBlk);
     const int H = height_bound(c.leaf_cap);
 
+    if (B == 1 && single_key_insert_on()) {
+        hipLaunchKernelGGL(k_insert_one<K>, dim3(1), dim3(kOneBlock), 0, s, t, keys, vals, status);
+        return;
+    }
     if (B <= kSmallInsert) {
         rank_sort_small<K>(keys, static_cast<uint32_t>(B), v.sk, v.si, nullptr, 0, s);
         hipLaunchKernelGGL(k_small_prefix<K>, dim3(1), dim3(kSmallBlock), 0, s, v, t.hdr, keys, vals,
