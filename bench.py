@@ -85,7 +85,7 @@ import synth  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 MAX64 = (1 << 64) - 1
 METRIC = "lookup Mops/s and \u00b5s/batch at B=1..1024, 2^24 keys; learned vs plain tree"
-LARGE_KERNEL = "k_lookup<unsigned long, 8, 4, 2, true, false>"
+LARGE_KERNEL = "k_lookup<unsigned long, 8, 4, 2, true, 2>"
 N_LOG2 = 24
 SEED = 2
 
@@ -453,6 +453,9 @@ def main():
     ap.add_argument("--order-probe", action="store_true",
                     help="the 2^20-key lookup with its queries in random, bucketed and sorted order, cold and "
                          "warm, then exit")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="the 2^20-key lookup on trees built with each leaf_stream setting (value lines "
+                         "non-temporal, key and value lines, none): warm, distinct batches, cold; then exit")
     ap.add_argument("--probe", action="store_true",
                     help="memory-system probes (launch floor, load latency, line-read rate, batch chains) and the "
                          "B = 1024 lookups beside them, then exit")
@@ -532,6 +535,39 @@ def main():
         of = torch.empty(BL, dtype=torch.uint8, device=dev)
         res["scatter_results_to_caller_order_cold_us"] = ev(
             lambda: (ov.index_copy_(0, perm, vl), of.index_copy_(0, perm, fl)), True)
+        print(json.dumps(res), flush=True)
+        return
+
+    if args.stream_probe:
+        # the same 2^20-key lookups on trees that read leaf lines with
+        # non-temporal loads or not: warm (one batch back to back), eight
+        # distinct batches back to back, and cold (after a 2 GiB flush)
+        flush = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
+        extra = [synth.present_queries(keys, BL, SEED, purpose=5100 + i) for i in range(8)]
+
+        def med(fn, reps, cold):
+            ts = []
+            for r in range(reps):
+                if cold:
+                    flush.add_(1)
+                ts += timer.run(lambda: fn(r), 1, skip=0)
+            return round(float(np.median(ts[1:])), 2)
+
+        res = {"batch": BL, "keys": n}
+        tree.close()
+        for ls, name in ((0, "value_lines_nt_default"), (1, "key_and_value_lines_nt"), (2, "no_nt")):
+            ts_ = g.Tree(keys, vals, 8, leaf_stream=ls)
+            qx = [ts_.dev(x) for x in extra]
+            q0 = ts_.dev(ql_np)
+            g.tree_lookup_batch(ts_.h, q0, vl, fl, stream)
+            res[f"{name}_warm_us"] = med(lambda r: g.tree_lookup_batch(ts_.h, q0, vl, fl, stream), 9, False)
+            res[f"{name}_distinct_us"] = med(lambda r: g.tree_lookup_batch(ts_.h, qx[r % 8], vl, fl, stream), 9,
+                                             False)
+            res[f"{name}_cold_us"] = med(lambda r: g.tree_lookup_batch(ts_.h, q0, vl, fl, stream), 7, True)
+            assert g.to_numpy(fl).all() and np.array_equal(g.to_numpy(vl, np.uint64),
+                                                           synth.values_for(ql_np, SEED, 64))
+            del qx, q0
+            ts_.close()
         print(json.dumps(res), flush=True)
         return
 

@@ -113,9 +113,12 @@ typedef struct {
                                  range over the 8 XCDs so that each XCD's L2
                                  holds the inner nodes of its own subtrees;
                                  2: off; 0 = default (off)                  */
-    uint32_t leaf_stream;     /* 1: leaf lines are read with non-temporal
-                                 loads (they stream and should not evict
-                                 inner nodes); 2: off; 0 = default (off)    */
+    uint32_t leaf_stream;     /* non-temporal loads of leaf lines in lookups
+                                 (lines that stream should not evict the
+                                 inner nodes other queries reuse from L2):
+                                 1: key and value lines, every batch; 2:
+                                 none; 0 = default: the value line from
+                                 2^15 queries on                            */
     uint32_t reserved;        /* must be 0                                    */
 } gt_params;
 

@@ -13,7 +13,7 @@ struct LaunchCfg {
     int lds_levels;         // top inner levels read from LDS: 0..3
     int value_coload;       // read a leaf's value line together with its key line
     int xcd_split;          // 0 off, 1 on from kXcdMinBatch queries, 2 always
-    int leaf_stream;        // non-temporal leaf loads
+    int leaf_stream;        // non-temporal leaf loads: 0 value lines from kLargeBatch queries, 1 key and value lines, 2 none
     int large_qpg;          // queries per group from kLargeBatch queries on (0 = same)
     int shape_auto;         // lookup shape chosen by batch size: bit 0 lanes, 1 queries per group, 2 LDS levels
 };

@@ -26,8 +26,11 @@ constexpr int kLookupBlock = 256;
 
 // Leaf stage shared by the lookup kernels: match the key line, take the
 // value (from the co-loaded value line, or by one dependent read), write the
-// result of every live query.
-template <class K, int G, int QPG, bool VC, bool NT>
+// result of every live query.  NT selects non-temporal loads: bit 0 the key
+// line, bit 1 the value line (a lookup reads a value line once, so
+// streaming it keeps the lines that are reused -- leaf parents, upper
+// levels -- in L2).
+template <class K, int G, int QPG, bool VC, int NT>
 __device__ __forceinline__ void finish_lookups(const TreeView<K>& t, const K (&key)[QPG], const uint32_t (&leaf)[QPG],
                                                const uint64_t (&qi)[QPG], bool empty, int gl, int gbase,
                                                K* __restrict__ vout, uint8_t* __restrict__ fout) {
@@ -38,12 +41,11 @@ __device__ __forceinline__ void finish_lookups(const TreeView<K>& t, const K (&k
     for (int j = 0; j < QPG; ++j) {
         const K* kl = t.lkeys + static_cast<uint64_t>(leaf[j]) * kSlots;
         const K* vl = t.lvals + static_cast<uint64_t>(leaf[j]) * kSlots;
-        if constexpr (NT) {
-            kv[j] = T::load_keys_nt(kl, gl);
-            if constexpr (VC) vv[j] = T::load_keys_nt(vl, gl);
-        } else {
-            kv[j] = T::load_keys(kl, gl);
-            if constexpr (VC) vv[j] = T::load_keys(vl, gl);
+        if constexpr ((NT & 1) != 0) kv[j] = T::load_keys_nt(kl, gl);
+        else kv[j] = T::load_keys(kl, gl);
+        if constexpr (VC) {
+            if constexpr ((NT & 2) != 0) vv[j] = T::load_keys_nt(vl, gl);
+            else vv[j] = T::load_keys(vl, gl);
         }
     }
     uint32_t slot[QPG];
@@ -59,8 +61,11 @@ __device__ __forceinline__ void finish_lookups(const TreeView<K>& t, const K (&k
             const K x = T::pick_value(vv[j], hit[j] ? slot[j] : 0u, gbase);
             if (hit[j]) val[j] = x;
         } else {
-            if (gl == (j % G) && qi[j] != ~0ull && hit[j])
-                val[j] = t.lvals[static_cast<uint64_t>(leaf[j]) * kSlots + slot[j]];
+            if (gl == (j % G) && qi[j] != ~0ull && hit[j]) {
+                const K* vp = t.lvals + static_cast<uint64_t>(leaf[j]) * kSlots + slot[j];
+                if constexpr ((NT & 2) != 0) val[j] = __builtin_nontemporal_load(vp);
+                else val[j] = *vp;
+            }
         }
     }
 #pragma unroll
@@ -72,7 +77,7 @@ __device__ __forceinline__ void finish_lookups(const TreeView<K>& t, const K (&k
     }
 }
 
-template <class K, int G, int QPG, int LV, bool VC, bool NT>
+template <class K, int G, int QPG, int LV, bool VC, int NT>
 __global__ __launch_bounds__(kLookupBlock) void k_lookup(TreeView<K> t, const K* __restrict__ q, uint64_t B,
                                                           K* __restrict__ vout, uint8_t* __restrict__ fout,
                                                           uint64_t ntiles) {
@@ -133,7 +138,7 @@ __device__ __forceinline__ int nth_set_bit(uint64_t m, uint32_t t) {
 // through a round (the groups' cross-lane reads need their source lanes).
 constexpr int kXcdChunks = 4;  // 64-query chunks a wave reads at once
 
-template <class K, bool VC, bool NT>
+template <class K, bool VC, int NT>
 __global__ __launch_bounds__(kLookupBlock) void k_lookup_xcd(TreeView<K> t, const K* __restrict__ q, uint64_t B,
                                                               K* __restrict__ vout, uint8_t* __restrict__ fout,
                                                               uint64_t nchunks) {
@@ -314,7 +319,7 @@ static uint64_t grid_for(uint64_t ntiles, int lv, int key_bytes) {
     return ntiles < cap ? (ntiles < 1 ? 1 : ntiles) : cap;
 }
 
-template <class K, int G, int QPG, int LV, bool VC, bool NT>
+template <class K, int G, int QPG, int LV, bool VC, int NT>
 static void launch_lookup_t(const TreeView<K>& t, const K* q, uint64_t B, K* vout, uint8_t* fout, hipStream_t s) {
     const uint64_t tile_q = static_cast<uint64_t>(kLookupBlock / G) * QPG;
     const uint64_t ntiles = (B + tile_q - 1) / tile_q;
@@ -323,7 +328,7 @@ static void launch_lookup_t(const TreeView<K>& t, const K* q, uint64_t B, K* vou
                        lds_bytes_for(LV, sizeof(K)), s, t, q, B, vout, fout, ntiles);
 }
 
-template <class K, bool VC, bool NT>
+template <class K, bool VC, int NT>
 static void launch_lookup_xcd(const TreeView<K>& t, const K* q, uint64_t B, K* vout, uint8_t* fout, hipStream_t s) {
     const uint64_t nchunks = (B + 63) / 64;
     // per XCD up to 256 workgroups (8 per CU) of four waves; every XCD reads
@@ -339,22 +344,29 @@ template <class K, int G, int QPG, int LV>
 static void launch_lookup_v(const TreeView<K>& t, const LaunchCfg& cfg, const K* q, uint64_t B, K* vout,
                             uint8_t* fout, hipStream_t s) {
     const bool xcd = cfg.xcd_split == 2 || (cfg.xcd_split == 1 && B >= kXcdMinBatch);
+    // leaf lines read non-temporally: both (leaf_stream 1), none (2), or by
+    // default the value line from kLargeBatch queries on
+    const int nt = cfg.leaf_stream == 1 ? 3 : (cfg.leaf_stream == 0 && B >= kLargeBatch ? 2 : 0);
     if (xcd) {
         if (cfg.value_coload) {
-            if (cfg.leaf_stream) launch_lookup_xcd<K, true, true>(t, q, B, vout, fout, s);
-            else launch_lookup_xcd<K, true, false>(t, q, B, vout, fout, s);
+            if (nt == 3) launch_lookup_xcd<K, true, 3>(t, q, B, vout, fout, s);
+            else if (nt == 2) launch_lookup_xcd<K, true, 2>(t, q, B, vout, fout, s);
+            else launch_lookup_xcd<K, true, 0>(t, q, B, vout, fout, s);
         } else {
-            if (cfg.leaf_stream) launch_lookup_xcd<K, false, true>(t, q, B, vout, fout, s);
-            else launch_lookup_xcd<K, false, false>(t, q, B, vout, fout, s);
+            if (nt == 3) launch_lookup_xcd<K, false, 3>(t, q, B, vout, fout, s);
+            else if (nt == 2) launch_lookup_xcd<K, false, 2>(t, q, B, vout, fout, s);
+            else launch_lookup_xcd<K, false, 0>(t, q, B, vout, fout, s);
         }
         return;
     }
     if (cfg.value_coload) {
-        if (cfg.leaf_stream) launch_lookup_t<K, G, QPG, LV, true, true>(t, q, B, vout, fout, s);
-        else launch_lookup_t<K, G, QPG, LV, true, false>(t, q, B, vout, fout, s);
+        if (nt == 3) launch_lookup_t<K, G, QPG, LV, true, 3>(t, q, B, vout, fout, s);
+        else if (nt == 2) launch_lookup_t<K, G, QPG, LV, true, 2>(t, q, B, vout, fout, s);
+        else launch_lookup_t<K, G, QPG, LV, true, 0>(t, q, B, vout, fout, s);
     } else {
-        if (cfg.leaf_stream) launch_lookup_t<K, G, QPG, LV, false, true>(t, q, B, vout, fout, s);
-        else launch_lookup_t<K, G, QPG, LV, false, false>(t, q, B, vout, fout, s);
+        if (nt == 3) launch_lookup_t<K, G, QPG, LV, false, 3>(t, q, B, vout, fout, s);
+        else if (nt == 2) launch_lookup_t<K, G, QPG, LV, false, 2>(t, q, B, vout, fout, s);
+        else launch_lookup_t<K, G, QPG, LV, false, 0>(t, q, B, vout, fout, s);
     }
 }
 

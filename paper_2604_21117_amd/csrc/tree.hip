@@ -343,7 +343,7 @@ gt_status tree_build(const gt_params* p, const void* keys, const void* values, u
     t->cfg.lds_levels = p->lds_levels == 0 ? 2 : (p->lds_levels == 4 ? 0 : static_cast<int>(p->lds_levels));
     t->cfg.value_coload = p->value_coload == 2 ? 0 : 1;
     t->cfg.xcd_split = p->xcd_split == 1 ? 1 : 0;
-    t->cfg.leaf_stream = p->leaf_stream == 1 ? 1 : 0;
+    t->cfg.leaf_stream = static_cast<int>(p->leaf_stream);  // 0 by batch size, 1 both lines, 2 none
     // an explicit queries_per_group applies to every batch size
     t->cfg.large_qpg = p->queries_per_group ? 0 : 4;
     // lookup shape fields the caller left at 0 follow the batch size

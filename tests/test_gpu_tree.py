@@ -107,11 +107,12 @@ def test_duplicate_queries_and_all_present():
 
 @pytest.mark.parametrize("width", [32, 64])
 @pytest.mark.parametrize("n", [5, 300, 3000, 200000])
-@pytest.mark.parametrize("xcd,stream", [(1, 2), (1, 1), (2, 2)])
+@pytest.mark.parametrize("xcd,stream", [(1, 2), (1, 1), (1, 0), (2, 2), (2, 0), (2, 1)])
 def test_large_batch_paths(width, n, xcd, stream):
-    """Batches above the XCD-split threshold (2^15): the split kernel, with
-    and without streaming leaf loads, agrees bit for bit with the oracle,
-    for trees with and without splitter keys."""
+    """Batches above the XCD-split threshold (2^15): the split and the plain
+    kernel, with streaming loads of both leaf lines, of the value line only
+    (the default) or of neither, agree bit for bit with the oracle, for
+    trees with and without splitter keys."""
     seed = 50 + n
     keys = key_set(n, width, seed, edges=True)
     vals = synth.values_for(keys, seed, width)
