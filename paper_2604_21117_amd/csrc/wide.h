@@ -20,10 +20,12 @@
 //                                  key in key order (the first key of child
 //                                  i+1).  One 16-byte record per node, read
 //                                  in one load
-//   lkeys[leaves][m]               up to m-1 keys ascending (the paper's
-//                                  k_max = m - 1); slots from count on
-//                                  repeat the last key
-//   lvals[leaves][m]               8-byte values; all ones from count on
+//   leaves of 8-byte keys: lkeys[leaves][m] up to m-1 keys ascending (the
+//     paper's k_max = m - 1), slots from count on repeating the last key;
+//     lvals[leaves][m] 8-byte values, all ones from count on
+//   leaves of 32-byte keys (lkeys only, 40 bytes per entry): per leaf the
+//     m leading words, then m 32-byte records {words 1..3, value}, words as
+//     big-endian numbers; the same ordering and padding
 //   lmeta[leaves]                  {count, next leaf}
 // A key is kb = 8 * kw bytes: kw = 1 holds an 8-byte unsigned integer in
 // native (little-endian) order, compared as an integer; kw = 4 holds the

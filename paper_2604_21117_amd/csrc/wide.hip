@@ -9,13 +9,16 @@
 // encoder: the child is the first one whose entry is >= the query.  Inner
 // entries are stored word-sliced, so a level first reads only the leading
 // words and goes on to a further word only for entries that tie the query
-// on every word so far.  The node's child range comes from one 8-byte record
-// read in the same round as the leading words, so a level costs one
-// dependent round unless an entry ties.  At the leaf each lane
-// compares its key for equality and reads its value in the same round; the
-// first matching lane answers (the paper's 8-byte data), else the result is
-// all ones with found = 0 (Section IV-D's -1).  Ranges descend with lo and
-// walk the linked leaves (Section III).
+// (and, for exact-match lookups, only where the node's tie mask says the
+// tie does not decide).  The node's child range comes from one 16-byte
+// record read in the same round as the leading words, so a level costs one
+// dependent round unless an entry ties.  At the leaf each lane compares its
+// key for equality; small batches read every entry's key and value in one
+// round, large ones read the leading words first and only the lanes that
+// tie read the rest of their entry and its value.  The first matching lane
+// answers (the paper's 8-byte data), else the result is all ones with
+// found = 0 (Section IV-D's -1).  Ranges descend with lo and walk the linked
+// leaves (Section III).
 //
 // Build (Section V-B's one-time build, done on the device): the keys are
 // sorted (8-byte keys by the library's radix sort; 32-byte keys by four
@@ -41,6 +44,9 @@ namespace {
 
 constexpr int kWBlock = 256;
 constexpr uint32_t kWGridMax = 8192;
+// batches from this size on are bound by the lines they read, not by the
+// dependent rounds: their leaves are read in two rounds (k_wlookup)
+constexpr uint64_t kWTwoRound = 1u << 13;
 
 // ---------------------------------------------------------------- keys
 
@@ -167,7 +173,54 @@ __device__ __forceinline__ uint32_t descend(const WideView& v, const Key<KW>& ke
     return ref;
 }
 
+// Leaves of 32-byte keys: per leaf, the m leading words (big-endian
+// numbers), then m 32-byte records {words 1..3 as big-endian numbers,
+// value}.  Leaves of 8-byte keys: lkeys[leaf][m] keys, lvals[leaf][m].
+constexpr uint64_t kLeafEntry32 = 40;  // bytes per entry of a 32-byte-key leaf
+
 template <int KW, int M>
+__device__ __forceinline__ const uint64_t* leaf_words(const WideView& v, uint32_t leaf) {
+    return reinterpret_cast<const uint64_t*>(v.lkeys + static_cast<uint64_t>(leaf) * M * (KW == 1 ? 8 : kLeafEntry32));
+}
+
+// words 1..3 and the value of entry s of a 32-byte-key leaf
+template <int M>
+__device__ __forceinline__ void leaf_record(const WideView& v, uint32_t leaf, int s, uint64_t (&w)[3], uint64_t& val) {
+    const uint4* r = reinterpret_cast<const uint4*>(v.lkeys + static_cast<uint64_t>(leaf) * M * kLeafEntry32 + M * 8 +
+                                                    static_cast<uint64_t>(s) * 32);
+    const uint4 a = r[0], b = r[1];
+    w[0] = (static_cast<uint64_t>(a.y) << 32) | a.x;
+    w[1] = (static_cast<uint64_t>(a.w) << 32) | a.z;
+    w[2] = (static_cast<uint64_t>(b.y) << 32) | b.x;
+    val = (static_cast<uint64_t>(b.w) << 32) | b.z;
+}
+
+// entry s of a leaf as a key (and its value)
+template <int KW, int M>
+__device__ __forceinline__ Key<KW> leaf_entry(const WideView& v, uint32_t leaf, int s, uint64_t& val) {
+    Key<KW> k;
+    const uint64_t w0 = leaf_words<KW, M>(v, leaf)[s];
+    if constexpr (KW == 1) {
+        k.w[0] = k.raw[0] = w0;
+        val = v.lvals[static_cast<uint64_t>(leaf) * M + s];
+    } else {
+        uint64_t w[3];
+        leaf_record<M>(v, leaf, s, w, val);
+        k.w[0] = w0;
+#pragma unroll
+        for (int i = 1; i < KW; ++i) k.w[i] = w[i - 1];
+#pragma unroll
+        for (int i = 0; i < KW; ++i) k.raw[i] = __builtin_bswap64(k.w[i]);
+    }
+    return k;
+}
+
+// Lookup.  Small batches (TWO = false) read every entry of the leaf -- key
+// and value -- in one round.  Large batches (TWO = true) are bound by the
+// lines they read: each lane reads its entry's leading word (8-byte keys:
+// the whole key), and only a lane whose leading word equals the query's
+// reads the rest of its entry and the value, one round later.
+template <int KW, int M, bool TWO>
 __global__ __launch_bounds__(kWBlock) void k_wlookup(WideView v, const uint8_t* __restrict__ q, uint64_t B,
                                                      uint64_t* __restrict__ vout, uint8_t* __restrict__ fout) {
     constexpr int QPW = 64 / M;
@@ -182,11 +235,27 @@ __global__ __launch_bounds__(kWBlock) void k_wlookup(WideView v, const uint8_t* 
         const bool valid = i < B;
         const Key<KW> key = valid ? load_key<KW>(q + i * KB) : max_key<KW>();
         const uint32_t leaf = descend<KW, M, false>(v, key, valid, root, height, s, gbase);
-        const Key<KW> lk = load_key<KW>(v.lkeys + (static_cast<uint64_t>(leaf) * M + s) * KB);
-        const uint64_t val = v.lvals[static_cast<uint64_t>(leaf) * M + s];
         // the padding repeats the last key, so the first equal slot is a
         // real one; an empty tree's one leaf holds only padding
-        const bool eq = valid && !empty && key_eq<KW>(lk, key);
+        bool eq;
+        uint64_t val = 0;
+        if constexpr (!TWO) {
+            const Key<KW> lk = leaf_entry<KW, M>(v, leaf, s, val);
+            eq = valid && !empty && key_eq<KW>(lk, key);
+        } else {
+            const uint64_t w0 = leaf_words<KW, M>(v, leaf)[s];
+            eq = valid && !empty && w0 == key.w[0];
+            if (eq) {
+                if constexpr (KW == 1) {
+                    val = v.lvals[static_cast<uint64_t>(leaf) * M + s];
+                } else {
+                    uint64_t w[3];
+                    leaf_record<M>(v, leaf, s, w, val);
+#pragma unroll
+                    for (int x = 1; x < KW; ++x) eq = eq && w[x - 1] == key.w[x];
+                }
+            }
+        }
         const uint64_t gb = group_bits<M>(__ballot(eq), gbase);
         const int f = gb ? __ffsll(static_cast<long long>(gb)) - 1 : 0;
         const uint64_t fv = shfl_u64(val, gbase + f);
@@ -225,8 +294,8 @@ __global__ __launch_bounds__(kWBlock) void k_wrange(WideView v, const uint8_t* _
             bool stop = true;
             if (active) {
                 const uint2 meta = v.lmeta[leaf];
-                const Key<KW> k = load_key<KW>(v.lkeys + (static_cast<uint64_t>(leaf) * M + s) * KB);
-                const uint64_t val = v.lvals[static_cast<uint64_t>(leaf) * M + s];
+                uint64_t val;
+                const Key<KW> k = leaf_entry<KW, M>(v, leaf, s, val);
                 const bool real = static_cast<uint32_t>(s) < meta.x;
                 const bool above = real && key_less<KW>(b, k);
                 const bool in = real && !key_less<KW>(k, a) && !above;
@@ -303,8 +372,19 @@ __global__ void k_wleaves(uint8_t* __restrict__ lkeys, uint64_t* __restrict__ lv
         const uint64_t j = t / M, s = t % M;
         const uint64_t b = part_start(j, n, L), e = part_start(j + 1, n, L), c = e - b;
         Key<KW> k = c ? load_key<KW>(sk + (b + (s < c ? s : c - 1)) * KB) : max_key<KW>();
-        store_key<KW>(lkeys + t * KB, k);
-        lvals[t] = s < c ? sv[b + s] : ~0ull;
+        const uint64_t val = s < c ? sv[b + s] : ~0ull;
+        if constexpr (KW == 1) {
+            store_key<KW>(lkeys + t * KB, k);
+            lvals[t] = val;
+        } else {
+            uint8_t* lb = lkeys + j * M * kLeafEntry32;
+            reinterpret_cast<uint64_t*>(lb)[s] = k.w[0];
+            uint4* r = reinterpret_cast<uint4*>(lb + M * 8 + s * 32);
+            r[0] = make_uint4(static_cast<uint32_t>(k.w[1]), static_cast<uint32_t>(k.w[1] >> 32),
+                              static_cast<uint32_t>(k.w[2]), static_cast<uint32_t>(k.w[2] >> 32));
+            r[1] = make_uint4(static_cast<uint32_t>(k.w[3]), static_cast<uint32_t>(k.w[3] >> 32),
+                              static_cast<uint32_t>(val), static_cast<uint32_t>(val >> 32));
+        }
         if (s == 0) {
             lmeta[j] = make_uint2(static_cast<uint32_t>(c), j + 1 < L ? static_cast<uint32_t>(j + 1) : kNone);
             store_key<KW>(maxk + j * KB, c ? load_key<KW>(sk + (e - 1) * KB) : max_key<KW>());
@@ -407,8 +487,11 @@ WSizes wsizes(int kb, int m, uint64_t n, double fill) {
     for (size_t i = 1; i < lv.size(); ++i) z.inner += lv[i];
     z.height = static_cast<int>(lv.size());
     const uint64_t ni = z.inner ? z.inner : 1;
-    z.bytes = al(sizeof(WideHeader)) + al(ni * m * kb) + al(ni * 16) + al(z.leaves * m * kb) +
-              al(z.leaves * m * 8) + al(z.leaves * 8);
+    // leaves: 8-byte keys and values in two arrays, or 40 bytes per entry
+    // of a 32-byte-key leaf in one
+    const uint64_t lk = kb == 32 ? z.leaves * m * kLeafEntry32 : z.leaves * m * 8;
+    const uint64_t lvb = kb == 32 ? 0 : z.leaves * m * 8;
+    z.bytes = al(sizeof(WideHeader)) + al(ni * m * kb) + al(ni * 16) + al(lk) + al(lvb) + al(z.leaves * 8);
     return z;
 }
 
@@ -416,8 +499,12 @@ template <int KW, int M>
 void launch_wlookup(const WideView& v, const void* keys, uint64_t B, void* vout, uint8_t* fout, hipStream_t s) {
     constexpr uint64_t qpb = kWBlock / M;
     const uint64_t g = std::min<uint64_t>((B + qpb - 1) / qpb, kWGridMax);
-    hipLaunchKernelGGL((k_wlookup<KW, M>), dim3(static_cast<uint32_t>(g)), dim3(kWBlock), 0, s, v,
-                       reinterpret_cast<const uint8_t*>(keys), B, reinterpret_cast<uint64_t*>(vout), fout);
+    if (B >= kWTwoRound)
+        hipLaunchKernelGGL((k_wlookup<KW, M, true>), dim3(static_cast<uint32_t>(g)), dim3(kWBlock), 0, s, v,
+                           reinterpret_cast<const uint8_t*>(keys), B, reinterpret_cast<uint64_t*>(vout), fout);
+    else
+        hipLaunchKernelGGL((k_wlookup<KW, M, false>), dim3(static_cast<uint32_t>(g)), dim3(kWBlock), 0, s, v,
+                           reinterpret_cast<const uint8_t*>(keys), B, reinterpret_cast<uint64_t*>(vout), fout);
 }
 
 template <int KW, int M>
@@ -557,8 +644,13 @@ gt_status wide_build(const gt_params* p, const void* keys, const void* values, u
     w->hdr = reinterpret_cast<WideHeader*>(a + o); o += al(sizeof(WideHeader));
     w->ikeys = a + o; o += al(ni * m * kb);
     w->imeta = reinterpret_cast<uint4*>(a + o); o += al(ni * 16);
-    w->lkeys = a + o; o += al(z.leaves * m * kb);
-    w->lvals = reinterpret_cast<uint64_t*>(a + o); o += al(z.leaves * m * 8);
+    if (kw == 4) {
+        w->lkeys = a + o; o += al(z.leaves * m * kLeafEntry32);
+        w->lvals = nullptr;
+    } else {
+        w->lkeys = a + o; o += al(z.leaves * m * 8);
+        w->lvals = reinterpret_cast<uint64_t*>(a + o); o += al(z.leaves * m * 8);
+    }
     w->lmeta = reinterpret_cast<uint2*>(a + o); o += al(z.leaves * 8);
     w->arena_bytes = o;
 
@@ -717,7 +809,8 @@ gt_status wide_export(const WideTree* w, void* host_buf, uint64_t* bytes, hipStr
         return GT_OK;
     }
     if (*bytes < need) return GT_ERR_CAPACITY;
-    std::vector<uint8_t> ik(ni * m * kb), lk(nl * m * kb);
+    const uint64_t lkb = w->kw == 4 ? nl * m * kLeafEntry32 : nl * m * kb;
+    std::vector<uint8_t> ik(ni * m * kb), lk(lkb);
     std::vector<uint4> im(ni);
     std::vector<uint2> lm(nl);
     std::vector<uint64_t> lvv(nl * m);
@@ -727,7 +820,7 @@ gt_status wide_export(const WideTree* w, void* host_buf, uint64_t* bytes, hipStr
     }
     if (nl) {
         WHIP(hipMemcpyAsync(lk.data(), w->lkeys, lk.size(), hipMemcpyDeviceToHost, s));
-        WHIP(hipMemcpyAsync(lvv.data(), w->lvals, nl * m * 8, hipMemcpyDeviceToHost, s));
+        if (w->kw == 1) WHIP(hipMemcpyAsync(lvv.data(), w->lvals, nl * m * 8, hipMemcpyDeviceToHost, s));
         WHIP(hipMemcpyAsync(lm.data(), w->lmeta, nl * 8, hipMemcpyDeviceToHost, s));
     }
     WHIP(hipStreamSynchronize(s));
@@ -765,8 +858,23 @@ gt_status wide_export(const WideTree* w, void* host_buf, uint64_t* bytes, hipStr
         o += rin;
     }
     for (uint64_t i = 0; i < nl; ++i) {
-        memcpy(o, lk.data() + i * m * kb, C * kb);
-        memcpy(o + C * kb, lvv.data() + i * m, C * 8);
+        if (w->kw == 1) {
+            memcpy(o, lk.data() + i * m * kb, C * kb);
+            memcpy(o + C * kb, lvv.data() + i * m, C * 8);
+        } else {
+            // leading word and record back to key bytes (big-endian words)
+            const uint8_t* lb = lk.data() + i * m * kLeafEntry32;
+            for (uint64_t j = 0; j < C; ++j) {
+                uint64_t x[5];
+                memcpy(&x[0], lb + j * 8, 8);
+                memcpy(&x[1], lb + m * 8 + j * 32, 32);
+                for (int wd = 0; wd < 4; ++wd) {
+                    const uint64_t be = __builtin_bswap64(x[wd]);
+                    memcpy(o + j * kb + wd * 8, &be, 8);
+                }
+                memcpy(o + C * kb + j * 8, &x[4], 8);
+            }
+        }
         memcpy(o + C * (kb + 8), &lm[i], 8);
         o += rlf;
     }

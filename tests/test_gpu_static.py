@@ -121,7 +121,7 @@ def test_static_build_lookup_range(kb, m, n):
     seed = 31 * n + m + kb
     t, ref, k = build(kb, m, n, seed)
     check_export(t, ref, kb)
-    for B in (1, 7, 64, 1000, 4099):
+    for B in (1, 7, 64, 1000, 4099, 9000):
         check_lookup(t, ref, queries(kb, k, B, seed + B))
     check_range(t, ref, kb, k, seed)
     st = t.stats()
