@@ -132,11 +132,6 @@ void launch_mirror_refresh(const TreeView<K>& t, hipStream_t s) {
 }
 
 template <class K>
-void launch_mirror_refresh_if(const TreeView<K>& t, const uint32_t* dirty, hipStream_t s) {
-    hipLaunchKernelGGL(k_mirror_refresh<K>, dim3(1), dim3(256), 0, s, t, dirty);
-}
-
-template <class K>
 void launch_build(const TreeView<K>& t, const K* sk, const K* sv, uint64_t n, const uint64_t* level_sizes,
                   int levels, K* maxbuf, hipStream_t s) {
     const uint64_t L = level_sizes[0];
@@ -173,8 +168,6 @@ template void launch_dup_check<uint32_t>(const uint32_t*, uint64_t, uint32_t*, h
 template void launch_dup_check<uint64_t>(const uint64_t*, uint64_t, uint32_t*, hipStream_t);
 template void launch_mirror_refresh<uint32_t>(const TreeView<uint32_t>&, hipStream_t);
 template void launch_mirror_refresh<uint64_t>(const TreeView<uint64_t>&, hipStream_t);
-template void launch_mirror_refresh_if<uint32_t>(const TreeView<uint32_t>&, const uint32_t*, hipStream_t);
-template void launch_mirror_refresh_if<uint64_t>(const TreeView<uint64_t>&, const uint32_t*, hipStream_t);
 template void launch_build<uint32_t>(const TreeView<uint32_t>&, const uint32_t*, const uint32_t*, uint64_t,
                                      const uint64_t*, int, uint32_t*, hipStream_t);
 template void launch_build<uint64_t>(const TreeView<uint64_t>&, const uint64_t*, const uint64_t*, uint64_t,

@@ -785,14 +785,6 @@ __device__ __forceinline__ void ph_commit(TreeView<K> t, Ins<K> v) {
     reinterpret_cast<MirrorHeader*>(t.mirror)->n_keys = hdr->n_keys;
 }
 
-// growth then commit, one workgroup
-template <class K>
-__global__ __launch_bounds__(1024) void k_grow_commit(TreeView<K> t, Ins<K> v) {
-    grow_body<K>(t, v);
-    __syncthreads();
-    if (threadIdx.x == 0) ph_commit<K>(t, v);
-}
-
 // The upper levels of a large batch's plan in one workgroup: from level d0
 // on, every level below holds at most kTailMax items (the pool's per-level
 // bound), so the phases run back to back with block scans in LDS where the
@@ -849,6 +841,28 @@ __global__ __launch_bounds__(kFusedBlock) void k_small_apply(TreeView<K> t, Ins<
     apply_leaves_body<K>(t, v, grp, ngrp);
     __syncthreads();
     for (int d = 1; d < H; ++d) {
+        if (v.st->lvl_new[d - 1] == 0) break;  // nothing split below: no level above changes
+        apply_inner_body<K>(t, v, d, grp, ngrp);
+        __syncthreads();
+    }
+    grow_body<K>(t, v);
+    __syncthreads();
+    if (threadIdx.x == 0) ph_commit<K>(t, v);
+    __syncthreads();
+    if (v.st->mirror_dirty) mirror_refresh_body<K, kFusedBlock>(t);
+}
+
+// The parent levels from d0 on, the root growth, the commit and the mirror
+// in one workgroup: the host starts it at the first level whose item bound
+// is at most kTailApplyMax, one round of kNodeLanes-lane groups, so the
+// upper levels (and the levels above the tree's current height, which the
+// host cannot see) cost no launch each.
+constexpr uint32_t kTailApplyMax = kFusedMax;
+
+template <class K>
+__global__ __launch_bounds__(kFusedBlock) void k_apply_tail(TreeView<K> t, Ins<K> v, int d0, int H) {
+    const uint64_t grp = threadIdx.x / kNodeLanes, ngrp = kFusedBlock / kNodeLanes;
+    for (int d = d0; d < H; ++d) {
         if (v.st->lvl_new[d - 1] == 0) break;  // nothing split below: no level above changes
         apply_inner_body<K>(t, v, d, grp, ngrp);
         __syncthreads();
@@ -1089,22 +1103,56 @@ constexpr uint32_t kSmallInsert = 2048;
 static_assert(kSmallInsert <= kRankSortMax, "the small path sorts with rank_sort_small");
 constexpr int kSmallBlock = 1024;
 
+// A batch of at most kFusedSortMax keys is ranked here, by the waves that
+// hold its keys, each reading the batch from LDS (about B^2 / 16 cycles of
+// one CU: cheaper than a launch up to this size); a larger one arrives
+// sorted by rank_sort_small, which spreads the comparisons over B / 16 CUs.
+constexpr uint32_t kFusedSortMax = 256;
+
 template <class K>
 __global__ __launch_bounds__(kSmallBlock) void k_small_prefix(Ins<K> v, const DevHeader* hdr,
                                                                const K* __restrict__ keys, const K* __restrict__ vals,
-                                                               uint32_t B, uint8_t* __restrict__ status) {
+                                                               uint32_t B, uint8_t* __restrict__ status,
+                                                               uint32_t presorted) {
+    __shared__ K rk[kSmallInsert];
     __shared__ K sk[kSmallInsert];
     __shared__ uint32_t si[kSmallInsert];
     __shared__ uint32_t sh[33];
     const uint32_t tid = threadIdx.x;
     uint32_t* s = reinterpret_cast<uint32_t*>(v.st);
     for (uint32_t i = tid; i < sizeof(InsState) / 4; i += blockDim.x) s[i] = 0;
-    // the pairs in (key, index) order, from rank_sort_small
-    for (uint32_t i = tid; i < B; i += blockDim.x) {
-        sk[i] = v.sk[i];
-        si[i] = v.si[i];
+    if (presorted) {
+        // the pairs in (key, index) order, from rank_sort_small
+        for (uint32_t i = tid; i < B; i += blockDim.x) {
+            sk[i] = v.sk[i];
+            si[i] = v.si[i];
+        }
+    } else {
+        for (uint32_t i = tid; i < B; i += blockDim.x) rk[i] = keys[i];
+        __syncthreads();
+        // each element's stable rank over the batch in LDS; only the waves
+        // that hold elements count (all lanes of a wave read the same word)
+        if (tid < B) {
+            const K k0 = rk[tid];
+            uint32_t c = 0, j = 0;
+            for (; j + 8 <= B; j += 8) {
+#pragma unroll
+                for (uint32_t u = 0; u < 8; ++u) {
+                    const K kj = rk[j + u];
+                    c += (kj < k0 || (kj == k0 && j + u < tid)) ? 1u : 0u;
+                }
+            }
+            for (; j < B; ++j) c += (rk[j] < k0 || (rk[j] == k0 && j < tid)) ? 1u : 0u;
+            sk[c] = k0;
+            si[c] = tid;
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < B; i += blockDim.x) {
+            v.sk[i] = sk[i];
+            v.si[i] = si[i];  // locate writes each distinct key's status through it
+        }
     }
-    __syncthreads();
+    __syncthreads();  // the pairs in LDS, the batch state cleared
     if (tid == 0) v.st->height = hdr->height;
     uint32_t f[2];
 #pragma unroll
@@ -1398,14 +1446,16 @@ static int height_bound(uint64_t leaf_cap) {
 // apply, grow, commit, mirror: shared by both paths (the small path's plan
 // kernel writes the updates itself)
 template <class K>
-static void launch_apply(const TreeView<K>& t, const Ins<K>& v, uint64_t B, int H, bool updates, hipStream_t s) {
+static void launch_apply(const TreeView<K>& t, const Ins<K>& v, uint64_t B, uint64_t leaf_cap, int H, bool updates,
+                         hipStream_t s) {
     const uint32_t gB = grid_for(B, kBlk);
     if (updates) hipLaunchKernelGGL(k_apply_updates<K>, dim3(gB), dim3(kBlk), 0, s, t, v);
     hipLaunchKernelGGL(k_apply_leaves<K>, dim3(grid_for(B, kBlk / kNodeLanes)), dim3(kBlk), 0, s, t, v);
-    for (int d = 1; d < H; ++d)
+    int d0 = 1;
+    while (d0 < H && level_items_bound(B, leaf_cap, d0) > kTailApplyMax) ++d0;
+    for (int d = 1; d < d0; ++d)
         hipLaunchKernelGGL(k_apply_inner<K>, dim3(grid_for(B, kBlk / kNodeLanes)), dim3(kBlk), 0, s, t, v, d);
-    hipLaunchKernelGGL(k_grow_commit<K>, dim3(1), dim3(1024), 0, s, t, v);
-    launch_mirror_refresh_if<K>(t, &v.st->mirror_dirty, s);
+    hipLaunchKernelGGL(k_apply_tail<K>, dim3(1), dim3(kFusedBlock), 0, s, t, v, d0, H);
 }
 
 template <class K>
@@ -1422,15 +1472,16 @@ void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, cons
         return;
     }
     if (B <= kSmallInsert) {
-        rank_sort_small<K>(keys, static_cast<uint32_t>(B), v.sk, v.si, nullptr, 0, s);
+        const uint32_t presorted = B > kFusedSortMax ? 1u : 0u;
+        if (presorted) rank_sort_small<K>(keys, static_cast<uint32_t>(B), v.sk, v.si, nullptr, 0, s);
         hipLaunchKernelGGL(k_small_prefix<K>, dim3(1), dim3(kSmallBlock), 0, s, v, t.hdr, keys, vals,
-                           static_cast<uint32_t>(B), status);
+                           static_cast<uint32_t>(B), status, presorted);
         launch_locate<K>(t, v, c.cfg, B, status, s);
         if (B <= 128) hipLaunchKernelGGL((k_small_plan<K, 64>), dim3(1), dim3(64), 0, s, t, v, H);
         else if (B <= 512) hipLaunchKernelGGL((k_small_plan<K, 256>), dim3(1), dim3(256), 0, s, t, v, H);
         else hipLaunchKernelGGL((k_small_plan<K, kSmallBlock>), dim3(1), dim3(kSmallBlock), 0, s, t, v, H);
         if (B <= kFusedMax) hipLaunchKernelGGL(k_small_apply<K>, dim3(1), dim3(kFusedBlock), 0, s, t, v, H);
-        else launch_apply<K>(t, v, B, H, false, s);  // the plan wrote the updates
+        else launch_apply<K>(t, v, B, c.leaf_cap, H, false, s);  // the plan wrote the updates
         return;
     }
     hipLaunchKernelGGL(k_init<K>, dim3(1), dim3(kBlk), 0, s, v, t.hdr);
@@ -1462,7 +1513,7 @@ void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, cons
     }
     if (d0 < H) hipLaunchKernelGGL(k_plan_tail<K>, dim3(1), dim3(kTailBlock), 0, s, t, v, d0, H);
     hipLaunchKernelGGL(k_check<K>, dim3(1), dim3(64), 0, s, t, v);
-    launch_apply<K>(t, v, B, H, true, s);
+    launch_apply<K>(t, v, B, c.leaf_cap, H, true, s);
 }
 
 template void launch_insert<uint32_t>(const TreeView<uint32_t>&, const InsertCtx&, const uint32_t*,

@@ -47,9 +47,6 @@ void launch_dup_check(const K* sk, uint64_t n, uint32_t* flag, hipStream_t s);
 template <class K>
 void launch_mirror_refresh(const TreeView<K>& t, hipStream_t s);
 
-// Refresh only if *dirty (device flag) is non-zero when the kernel runs.
-template <class K>
-void launch_mirror_refresh_if(const TreeView<K>& t, const uint32_t* dirty, hipStream_t s);
 
 // Clear the device error word with a kernel (safe inside a captured graph).
 void launch_clear_error(DevHeader* h, hipStream_t s);
