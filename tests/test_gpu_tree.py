@@ -143,3 +143,27 @@ def test_default_shapes_across_batch_sizes(width):
         gv, gf = li.lookup(q)
         ov, of = sa.lookup(q)
         assert np.array_equal(gf, of) and np.array_equal(gv, ov), f"learned, B={B}"
+
+
+@pytest.mark.parametrize("width", [32, 64])
+def test_dense_runs_and_huge_gaps(width):
+    """Lookups on a key set of dense runs of consecutive keys and a few huge
+    gaps (nodes whose separators are a few units apart beside nodes that span
+    half the key space), both edge values, and absent keys on both sides of
+    every present one; batches on both sides of the large-batch shape
+    switch."""
+    top = (1 << width) - 1
+    rng = np.random.default_rng(7 + width)
+    dense = np.arange(1, 30000, dtype=np.uint64)
+    far = np.array([top // 3, top // 3 + 1, top // 2, top - 1, top], dtype=np.uint64)
+    mid = (np.uint64(1) << np.uint64(width - 8)) + rng.integers(0, 1 << 20, 20000).astype(np.uint64)
+    keys = np.unique(np.concatenate([dense, far, mid])).astype(np.uint32 if width == 32 else np.uint64)
+    keys = synth.shuffle(keys, 3)
+    vals = synth.values_for(keys, 9, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    t = mk_tree(keys, vals, width // 8, max_batch=4096)
+    sk = np.sort(keys)
+    q = np.concatenate([sk, sk - 1, sk + 1, np.array([0], dtype=sk.dtype)]).astype(sk.dtype)
+    q = q[rng.permutation(len(q))]
+    assert_lookup_parity(t, sa, q)
+    assert_lookup_parity(t, sa, q[:1000])
