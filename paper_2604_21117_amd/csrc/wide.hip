@@ -15,7 +15,9 @@
 // dependent round unless an entry ties.  At the leaf each lane compares its
 // key for equality; small batches read every entry's key and value in one
 // round, large ones read the leading words first and only the lanes that
-// tie read the rest of their entry and its value.  The first matching lane
+// tie read the rest of their entry and its value.  Large batches also give
+// a query fewer lanes (8 or 16, each holding several entries), so that more
+// queries are in flight per wave.  The first matching lane
 // answers (the paper's 8-byte data), else the result is all ones with
 // found = 0 (Section IV-D's -1).  Ranges descend with lo and walk the linked
 // leaves (Section III).
@@ -44,9 +46,14 @@ namespace {
 
 constexpr int kWBlock = 256;
 constexpr uint32_t kWGridMax = 8192;
-// batches from this size on are bound by the lines they read, not by the
-// dependent rounds: their leaves are read in two rounds (k_wlookup)
+// batches from this size on are bound by the lines they read and by the
+// queries in flight, not by the dependent rounds: fewer lanes per query and
+// their leaves read in two rounds (k_wlookupg)
 constexpr uint64_t kWTwoRound = 1u << 13;
+// lanes per query of a large batch (k_wlookupg), by order: measured best at
+// 2^20 queries, 8 lanes for orders 16 and 32, 16 for order 64
+template <int M>
+constexpr int large_lanes() { return M == 64 ? 16 : 8; }
 
 // ---------------------------------------------------------------- keys
 
@@ -215,12 +222,9 @@ __device__ __forceinline__ Key<KW> leaf_entry(const WideView& v, uint32_t leaf, 
     return k;
 }
 
-// Lookup.  Small batches (TWO = false) read every entry of the leaf -- key
-// and value -- in one round.  Large batches (TWO = true) are bound by the
-// lines they read: each lane reads its entry's leading word (8-byte keys:
-// the whole key), and only a lane whose leading word equals the query's
-// reads the rest of its entry and the value, one round later.
-template <int KW, int M, bool TWO>
+// Lookup of a small batch: M lanes per query, every entry of the leaf --
+// key and value -- read in one round (large batches: k_wlookupg).
+template <int KW, int M>
 __global__ __launch_bounds__(kWBlock) void k_wlookup(WideView v, const uint8_t* __restrict__ q, uint64_t B,
                                                      uint64_t* __restrict__ vout, uint8_t* __restrict__ fout) {
     constexpr int QPW = 64 / M;
@@ -237,29 +241,121 @@ __global__ __launch_bounds__(kWBlock) void k_wlookup(WideView v, const uint8_t* 
         const uint32_t leaf = descend<KW, M, false>(v, key, valid, root, height, s, gbase);
         // the padding repeats the last key, so the first equal slot is a
         // real one; an empty tree's one leaf holds only padding
-        bool eq;
         uint64_t val = 0;
-        if constexpr (!TWO) {
-            const Key<KW> lk = leaf_entry<KW, M>(v, leaf, s, val);
-            eq = valid && !empty && key_eq<KW>(lk, key);
-        } else {
-            const uint64_t w0 = leaf_words<KW, M>(v, leaf)[s];
-            eq = valid && !empty && w0 == key.w[0];
-            if (eq) {
-                if constexpr (KW == 1) {
-                    val = v.lvals[static_cast<uint64_t>(leaf) * M + s];
-                } else {
-                    uint64_t w[3];
-                    leaf_record<M>(v, leaf, s, w, val);
-#pragma unroll
-                    for (int x = 1; x < KW; ++x) eq = eq && w[x - 1] == key.w[x];
-                }
-            }
-        }
+        const Key<KW> lk = leaf_entry<KW, M>(v, leaf, s, val);
+        const bool eq = valid && !empty && key_eq<KW>(lk, key);
         const uint64_t gb = group_bits<M>(__ballot(eq), gbase);
         const int f = gb ? __ffsll(static_cast<long long>(gb)) - 1 : 0;
         const uint64_t fv = shfl_u64(val, gbase + f);
         if (valid && s == 0) {
+            vout[i] = gb ? fv : ~0ull;
+            fout[i] = gb ? 1 : 0;
+        }
+    }
+}
+
+// Large batches: G lanes per query (64 / G queries per wave instead of
+// 64 / M), lane l holding entries [l E, (l + 1) E) of a node, E = M / G.
+// The leading words of a lane's entries are one vector load; the ballots of
+// each entry position add up to the child index.
+// Inner ties and the leaf follow k_wlookup's two-round rules: an inner
+// entry whose leading word ties the query reads its other words only where
+// the node's tie mask says the tie does not decide; at the leaf a lane
+// reads the rest and the value of an entry whose leading word equals the
+// query's; the first equal entry answers.
+template <int KW, int M, int G>
+__global__ __launch_bounds__(kWBlock) void k_wlookupg(WideView v, const uint8_t* __restrict__ q, uint64_t B,
+                                                      uint64_t* __restrict__ vout, uint8_t* __restrict__ fout) {
+    constexpr int E = M / G, QPW = 64 / G;
+    constexpr uint64_t KB = 8 * KW;
+    static_assert(E == 2 || E == 4 || E == 8, "two to eight entries per lane");
+    const int lane = threadIdx.x & 63, gl = lane % G, gbase = lane - gl;
+    const uint64_t wave = (blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x) >> 6;
+    const uint64_t nwaves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
+    const uint32_t root = v.hdr->root, height = v.hdr->height;
+    const bool empty = v.hdr->n_keys == 0;
+    const uint64_t* ik = reinterpret_cast<const uint64_t*>(v.ikeys);
+    for (uint64_t base = wave * QPW; base < B; base += nwaves * QPW) {
+        const uint64_t i = base + lane / G;
+        const bool valid = i < B;
+        const Key<KW> key = valid ? load_key<KW>(q + i * KB) : max_key<KW>();
+        uint32_t ref = root;
+        for (uint32_t d = 0; d + 1 < height; ++d) {
+            const uint64_t nb = static_cast<uint64_t>(ref) * KW * M + static_cast<uint64_t>(gl) * E;
+            uint64_t e0[E];
+            {
+                const uint4* p4 = reinterpret_cast<const uint4*>(ik + nb);
+#pragma unroll
+                for (int h = 0; h < E / 2; ++h) {
+                    const uint4 x = p4[h];
+                    e0[2 * h] = (static_cast<uint64_t>(x.y) << 32) | x.x;
+                    e0[2 * h + 1] = (static_cast<uint64_t>(x.w) << 32) | x.z;
+                }
+            }
+            const uint4 meta = v.imeta[ref];
+            uint32_t ci = 0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                bool lt = e0[e] < key.w[0];
+                if constexpr (KW > 1) {
+                    const uint32_t slot = static_cast<uint32_t>(gl * E + e);
+                    const uint64_t mask = (static_cast<uint64_t>(meta.w) << 32) | meta.z;
+                    const bool need = valid && e0[e] == key.w[0] && ((mask >> slot) & 1ull);
+                    if (need) {
+                        uint64_t w[KW];
+#pragma unroll
+                        for (int x = 1; x < KW; ++x) w[x] = ik[nb + e + static_cast<uint64_t>(x) * M];
+                        bool l = w[KW - 1] < key.w[KW - 1];
+#pragma unroll
+                        for (int x = KW - 2; x >= 1; --x) l = (w[x] < key.w[x]) || (w[x] == key.w[x] && l);
+                        lt = l;
+                    }
+                }
+                ci += static_cast<uint32_t>(__popcll(group_bits<G>(__ballot(valid && lt), gbase)));
+            }
+            ref = meta.x + ci;
+        }
+        // leaf: leading words of this lane's entries, then the rest and the
+        // value of the entries that tie
+        const uint64_t* lw = leaf_words<KW, M>(v, ref) + gl * E;
+        uint64_t w0[E];
+        {
+            const uint4* p4 = reinterpret_cast<const uint4*>(lw);
+#pragma unroll
+            for (int h = 0; h < E / 2; ++h) {
+                const uint4 x = p4[h];
+                w0[2 * h] = (static_cast<uint64_t>(x.y) << 32) | x.x;
+                w0[2 * h + 1] = (static_cast<uint64_t>(x.w) << 32) | x.z;
+            }
+        }
+        int first = -1;
+        uint64_t val = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            bool eq = valid && !empty && first < 0 && w0[e] == key.w[0];
+            if (eq) {
+                const int slot = gl * E + e;
+                uint64_t vv;
+                if constexpr (KW == 1) {
+                    vv = v.lvals[static_cast<uint64_t>(ref) * M + slot];
+                } else {
+                    uint64_t w[3];
+                    leaf_record<M>(v, ref, slot, w, vv);
+#pragma unroll
+                    for (int x = 1; x < KW; ++x) eq = eq && w[x - 1] == key.w[x];
+                }
+                if (eq) {
+                    first = e;
+                    val = vv;
+                }
+            }
+        }
+        // the padding repeats the last key, so the first equal entry is a
+        // real one: the lowest lane with a match holds it
+        const uint64_t gb = group_bits<G>(__ballot(first >= 0), gbase);
+        const int f = gb ? __ffsll(static_cast<long long>(gb)) - 1 : 0;
+        const uint64_t fv = shfl_u64(val, gbase + f);
+        if (valid && gl == 0) {
             vout[i] = gb ? fv : ~0ull;
             fout[i] = gb ? 1 : 0;
         }
@@ -499,12 +595,16 @@ template <int KW, int M>
 void launch_wlookup(const WideView& v, const void* keys, uint64_t B, void* vout, uint8_t* fout, hipStream_t s) {
     constexpr uint64_t qpb = kWBlock / M;
     const uint64_t g = std::min<uint64_t>((B + qpb - 1) / qpb, kWGridMax);
-    if (B >= kWTwoRound)
-        hipLaunchKernelGGL((k_wlookup<KW, M, true>), dim3(static_cast<uint32_t>(g)), dim3(kWBlock), 0, s, v,
+    if (B >= kWTwoRound) {
+        constexpr int G = large_lanes<M>();
+        constexpr uint64_t qpbg = kWBlock / G;
+        const uint64_t gg = std::min<uint64_t>((B + qpbg - 1) / qpbg, kWGridMax);
+        hipLaunchKernelGGL((k_wlookupg<KW, M, G>), dim3(static_cast<uint32_t>(gg)), dim3(kWBlock), 0, s, v,
                            reinterpret_cast<const uint8_t*>(keys), B, reinterpret_cast<uint64_t*>(vout), fout);
-    else
-        hipLaunchKernelGGL((k_wlookup<KW, M, false>), dim3(static_cast<uint32_t>(g)), dim3(kWBlock), 0, s, v,
+    } else {
+        hipLaunchKernelGGL((k_wlookup<KW, M>), dim3(static_cast<uint32_t>(g)), dim3(kWBlock), 0, s, v,
                            reinterpret_cast<const uint8_t*>(keys), B, reinterpret_cast<uint64_t*>(vout), fout);
+    }
 }
 
 template <int KW, int M>
