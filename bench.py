@@ -135,14 +135,107 @@ def algorithmic_bytes(sorted_keys: np.ndarray, q: np.ndarray, height: int, hits:
     return {"distinct_nodes_per_level": per_level, "bytes": int(inner + leaf + io)}
 
 
+def code_tokens(src: str) -> str:
+    """C/HIP source without its comments, runs of whitespace made one space
+    (string and character literals kept as written)."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+            out.append(" ")
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def lookup_sources_hash() -> str:
-    """Hash of the sources the large-batch lookup kernel is built from (a
-    stored HBM traffic figure only applies to the kernel it was taken on)."""
+    """Hash of the code (comments and layout aside) the large-batch lookup
+    kernel is built from: a stored HBM traffic figure only applies to the
+    kernel it was taken on."""
     h = hashlib.sha256()
     for f in ("common.h", "traverse.h", "lookup.hip", "kernels.h"):
-        with open(os.path.join(ROOT, "paper_2604_21117_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2604_21117_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(code_tokens(fh.read()).encode())
+            h.update(b"\0")
     return h.hexdigest()
+
+
+def write_traffic(d: str, log2n: int) -> dict:
+    """Turn the CSVs of the three counter runs of `--profile` (FETCH_SIZE in
+    d/pmc_fetch, WRITE_SIZE in d/pmc_write, the kernel trace in
+    d/ktrace_profile) into profiles/hbm_traffic.json: the counters of the
+    three 1 GiB copies give the scale from KiB read to bytes (the copy reads
+    and writes exactly 1 GiB), the seven lookup dispatches are the priming
+    one, three warm and three cold.  Runs on the host only."""
+    import csv
+
+    def rows(sub, name):
+        with open(os.path.join(d, sub, name), newline="") as fh:
+            return list(csv.DictReader(fh))
+
+    def ours(r):
+        return r["Kernel_Name"].startswith(("void gt::" + LARGE_KERNEL, "gt::" + LARGE_KERNEL))
+
+    f = rows("pmc_fetch", "run_counter_collection.csv")
+    w = rows("pmc_write", "run_counter_collection.csv")
+    t = rows("ktrace_profile", "run_kernel_trace.csv")
+
+    def copies(rs):
+        return [float(r["Counter_Value"]) for r in rs
+                if r["Kernel_Name"] == "__amd_rocclr_copyBuffer" and float(r["Counter_Value"]) > 500000][:3]
+
+    cf, cw = copies(f), copies(w)
+    assert len(cf) == len(cw) == 3, (len(cf), len(cw))
+    fs = (1 << 20) / (sum(cf) / 3)
+    ws = (1 << 20) / (sum(cw) / 3)
+    lf = [float(r["Counter_Value"]) for r in f if ours(r)]
+    lw = [float(r["Counter_Value"]) for r in w if ours(r)]
+    lt = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000 for r in t if ours(r)]
+    assert len(lf) == len(lw) == len(lt) == 7, (len(lf), len(lw), len(lt))
+
+    def summ(idx):
+        fk = sum(lf[i] for i in idx) / len(idx)
+        wk = sum(lw[i] for i in idx) / len(idx)
+        fb, wb = fk * 1024 * fs, wk * 1024 * ws
+        return {"fetch_kib": round(fk, 1), "write_kib": round(wk, 1), "fetch_bytes": int(fb),
+                "write_bytes": int(wb), "traffic_bytes": int(fb + wb),
+                "avg_us_kernel_trace": round(sum(lt[i] for i in idx) / len(idx), 2)}
+
+    # the workload of --profile: the bulk-loaded tree at fill 1.0 (16 keys a
+    # leaf, fanout 16) and the 2^20 present-key queries
+    n = 1 << log2n
+    keys = synth.uniform_keys(n, SEED, 64)
+    ql = synth.present_queries(keys, 1 << 20, SEED, purpose=5000)
+    height, nodes = 1, (n + 15) // 16
+    while nodes > 1:
+        nodes, height = (nodes + 15) // 16, height + 1
+    ab = algorithmic_bytes(np.sort(keys), ql, height, hits=len(ql))
+    out = {"kernel": LARGE_KERNEL, "batch": 1 << 20, "keys": n, "algorithmic_bytes": ab["bytes"],
+           "fetch_scale": round(fs, 4), "write_scale": round(ws, 4), "warm": summ([1, 2, 3]),
+           "cold": summ([4, 5, 6]), "sources_sha256": lookup_sources_hash(),
+           "source": "profiles/hbm_traffic_k_lookup_2p20_on_2p24_u64.md"}
+    with open(os.path.join(ROOT, "profiles", "hbm_traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    for k in ("warm", "cold"):
+        tb, us = out[k]["traffic_bytes"], out[k]["avg_us_kernel_trace"]
+        out[k]["r1"] = round(tb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+        out[k]["r2"] = round(ab["bytes"] / tb, 4)
+        out[k]["r3"] = round(ab["bytes"] / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+    return out
 
 
 def cpu_baseline(keys, vals, queries, B, budget_s=6.0):
@@ -297,8 +390,8 @@ def run_probes(torch, g, args):
     stream: the launch floor (graph-replayed empty kernels), dependent-load
     latency by region size (one lane chasing a random cycle of 128-byte
     lines), the random line-read rate, and the per-step time of
-    lookup-shaped B = 1024 batches built from dependent rounds, beside the
-    real B = 1024 lookups (plain tree and learned index on the 2^24-key
+    lookup-shaped B = 1024 batches built from dependent rounds, which XCC
+    each workgroup runs on, beside the real B = 1024 lookups (plain tree and learned index on the 2^24-key
     tree).  Prints one JSON object and writes gpurun_out/probe.json."""
     dev = "cuda"
     stream = torch.cuda.Stream()
@@ -345,6 +438,41 @@ def run_probes(torch, g, args):
     stream.synchronize()
     res["empty_kernel_us_per_call_eager"] = round((time.perf_counter() - t0) / 2000 * 1e6, 3)
     print("[probe] launch floor done", file=sys.stderr, flush=True)
+
+    # where workgroups run: the fraction of workgroups w on the XCC of
+    # workgroup w % 8 (XCD-aware launches count on it), the XCC of
+    # workgroup 0, and whether one-workgroup launches in between move it
+    def xcc_of(wgs):
+        xo = torch.empty(wgs, dtype=torch.int32, device=dev)
+        g.probe_xcc(xo, wgs, stream)
+        stream.synchronize()
+        ids = xo.to(torch.int64).cpu().numpy()
+        w = np.arange(wgs)
+        return ids, w
+
+    xcc = {}
+    for wgs in (64, 2048, 65536):
+        ids, w = xcc_of(wgs)
+        xcc[str(wgs)] = {"frac_same_xcc_as_w_mod_8": round(float(np.mean(ids == ids[w % 8])), 4),
+                         "xcc_minus_w_mod_8": np.unique((ids - w) % 8).tolist(),
+                         "per_xcc": np.bincount(ids, minlength=8).tolist()}
+    # nothing but these kernels between the probes, all read back after
+    seq = (0, 1, 3, 8, 5)
+    bufs = [torch.empty(64, dtype=torch.int32, device=dev) for _ in seq]
+    for between, b in zip(seq, bufs):
+        for _ in range(between):
+            g.probe_empty(stream)
+        g.probe_xcc(b, 64, stream)
+    stream.synchronize()
+    rot = []
+    w = np.arange(64)
+    for between, b in zip(seq, bufs):
+        ids = b.to(torch.int64).cpu().numpy()
+        rot.append({"one_workgroup_launches_before": between, "xcc_of_workgroup_0": int(ids[0]),
+                    "frac_same_xcc_as_w_mod_8": round(float(np.mean(ids == ids[w % 8])), 4)})
+    xcc["rotation"] = rot
+    res["xcc_of_workgroup"] = xcc
+    print("[probe] xcc mapping done", file=sys.stderr, flush=True)
 
     # dependent-load latency: a random cycle over the region's 128-byte
     # lines.  Warm: the same 4096 steps again (4096 distinct lines, 512 KiB,
@@ -455,15 +583,23 @@ def main():
                          "warm, then exit")
     ap.add_argument("--stream-probe", action="store_true",
                     help="the 2^20-key lookup on trees built with each leaf_stream setting (value lines "
-                         "non-temporal, key and value lines, none): warm, distinct batches, cold; then exit")
+                         "non-temporal, key and value lines, none) and with xcd_split: warm, distinct batches, "
+                         "cold; then exit")
+    ap.add_argument("--write-traffic", metavar="DIR",
+                    help="host only: write profiles/hbm_traffic.json from the CSVs of the FETCH_SIZE, WRITE_SIZE "
+                         "and kernel-trace runs of --profile under DIR (pmc_fetch, pmc_write, ktrace_profile), "
+                         "then exit")
     ap.add_argument("--probe", action="store_true",
                     help="memory-system probes (launch floor, load latency, line-read rate, batch chains) and the "
                          "B = 1024 lookups beside them, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the tree runs on a single MI355X "
-              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              "(sharding over several GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
+    if args.write_traffic:
+        print(json.dumps(write_traffic(args.write_traffic, args.log2n)), flush=True)
+        return
 
     import torch
     import paper_2604_21117_amd as g
@@ -540,7 +676,8 @@ def main():
 
     if args.stream_probe:
         # the same 2^20-key lookups on trees that read leaf lines with
-        # non-temporal loads or not: warm (one batch back to back), eight
+        # non-temporal loads or not, and on one that splits the batch over
+        # the XCDs by key range: warm (one batch back to back), eight
         # distinct batches back to back, and cold (after a 2 GiB flush)
         flush = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
         extra = [synth.present_queries(keys, BL, SEED, purpose=5100 + i) for i in range(8)]
@@ -555,8 +692,9 @@ def main():
 
         res = {"batch": BL, "keys": n}
         tree.close()
-        for ls, name in ((0, "value_lines_nt_default"), (1, "key_and_value_lines_nt"), (2, "no_nt")):
-            ts_ = g.Tree(keys, vals, 8, leaf_stream=ls)
+        for ls, xs, name in ((0, 0, "value_lines_nt_default"), (1, 0, "key_and_value_lines_nt"), (2, 0, "no_nt"),
+                             (0, 1, "xcd_split_value_lines_nt")):
+            ts_ = g.Tree(keys, vals, 8, leaf_stream=ls, xcd_split=xs)
             qx = [ts_.dev(x) for x in extra]
             q0 = ts_.dev(ql_np)
             g.tree_lookup_batch(ts_.h, q0, vl, fl, stream)

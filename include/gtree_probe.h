@@ -25,6 +25,14 @@ extern "C" {
 gt_status gt_probe_empty(hipStream_t stream);
 
 /*
+ * Where workgroups run: `workgroups` workgroups of 256 threads; workgroup w
+ * writes to out[w] the XCC (XCD) it runs on, read from the XCC_ID hardware
+ * register (0..7 on MI355X).  Checks the dealing of workgroups to XCDs in
+ * turn that XCD-aware launches assume (w and w + 8 on one XCD).
+ */
+gt_status gt_probe_xcc(uint32_t* out, uint32_t workgroups, hipStream_t stream);
+
+/*
  * Dependent loads: one lane starts at element `start` of `next` and reads
  * x = next[x] `steps` times, then writes x to out[0].  next holds element
  * indices (u64); the caller lays out a cycle whose elements sit in distinct

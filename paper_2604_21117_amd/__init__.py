@@ -105,6 +105,7 @@ def lib():
         L.tree_lookup_levelwise.argtypes = [vp, vp, u64, u32, vp, vp, vp, u64, vp]
         L.tree_lookup_levelwise_noalloc.argtypes = [vp, vp, u64, u32, vp, vp, vp]
         L.gt_probe_empty.argtypes = [vp]
+        L.gt_probe_xcc.argtypes = [vp, u32, vp]
         L.gt_probe_chase.argtypes = [vp, u64, u64, vp, vp]
         L.gt_probe_gather.argtypes = [vp, u64, u64, u32, u64, vp, vp]
         L.gt_probe_batch.argtypes = [vp, u64, vp, u64, u32, vp, u64, u32, u32, vp, vp]
@@ -445,6 +446,10 @@ class Tree:
 
 def probe_empty(stream=None):
     _check(lib().gt_probe_empty(_stream(stream)), "gt_probe_empty")
+
+
+def probe_xcc(out, workgroups: int, stream=None):
+    _check(lib().gt_probe_xcc(_ptr(out), workgroups, _stream(stream)), "gt_probe_xcc")
 
 
 def probe_chase(next_idx, steps: int, start: int, out, stream=None):

@@ -126,14 +126,16 @@ __device__ __forceinline__ int nth_set_bit(uint64_t m, uint32_t t) {
     return pos;
 }
 
-// XCD-split lookup for large batches.  Workgroup w runs on XCD w % 8 (the
-// dispatcher deals workgroups to XCDs round-robin).  Seven splitter keys cut
-// the key space into eight ranges, and XCD x answers the queries of range x
-// only, so the leaf parents it reads (an eighth of them) stay in its own L2.
-// Every wave of XCD x reads four 64-query chunks of the batch at a time (one
-// coalesced load each), keeps the queries of its range with one ballot per
-// chunk, and deals them to its eight 8-lane groups, four queries per group
-// per round.  Each chunk is read by one wave of every XCD; results go by
+// XCD-split lookup for large batches.  The dispatcher deals the workgroups
+// of a launch to the eight XCDs in turn, so workgroups w and w + 8 share an
+// XCD and its L2 (which XCD takes workgroup 0 varies; only the grouping is
+// used).  Seven splitter keys cut the key space into eight ranges, and the
+// workgroups with w % 8 == x answer the queries of range x only, so the leaf
+// parents they read (an eighth of them) stay in one L2.  Every wave of group
+// x reads four 64-query chunks of the batch at a time (one coalesced load
+// each), keeps the queries of its range with one ballot per chunk, and deals
+// them to its eight 8-lane groups, four queries per group per round.  Each
+// chunk is read by one wave of every XCD; results go by
 // query index, so the output is the plain kernel's.  All lanes stay active
 // through a round (the groups' cross-lane reads need their source lanes).
 constexpr int kXcdChunks = 4;  // 64-query chunks a wave reads at once

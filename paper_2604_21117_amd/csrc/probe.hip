@@ -26,6 +26,11 @@ __device__ __forceinline__ uint64_t shfl_u64p(uint64_t v, int src) {
 
 __global__ void k_probe_empty() {}
 
+// each workgroup's XCC (bits 3:0 of the XCC_ID hardware register)
+__global__ void k_probe_xcc(uint32_t* out, uint32_t n) {
+    if (threadIdx.x == 0 && blockIdx.x < n) out[blockIdx.x] = __builtin_amdgcn_s_getreg((15 << 11) | 20) & 0xFu;
+}
+
 __global__ void k_probe_chase(const uint64_t* __restrict__ next, uint64_t steps, uint64_t start,
                               uint64_t* __restrict__ out) {
     if (threadIdx.x != 0) return;
@@ -109,6 +114,12 @@ extern "C" {
 
 gt_status gt_probe_empty(hipStream_t stream) {
     hipLaunchKernelGGL(k_probe_empty, dim3(1), dim3(64), 0, stream);
+    return done();
+}
+
+gt_status gt_probe_xcc(uint32_t* out, uint32_t workgroups, hipStream_t stream) {
+    if (!out || !workgroups) return GT_ERR_INVALID;
+    hipLaunchKernelGGL(k_probe_xcc, dim3(workgroups), dim3(256), 0, stream, out, workgroups);
     return done();
 }
 
