@@ -60,6 +60,7 @@ struct gt_tree {
     uint64_t inserts = 0;   // insert batches enqueued on this tree
     uint64_t deletes = 0;   // delete batches applied to this tree
     uint32_t* h_flag = nullptr;  // pinned host word a delete reads its rebuild flag into
+    uint32_t* d_flag = nullptr;  // the same word's device address
     gt::WideTree* wide = nullptr;  // set for a tree of 32-byte keys or order 32/64:
                                    // static, searched by wide.hip; the fields
                                    // above are then unused

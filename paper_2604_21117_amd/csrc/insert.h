@@ -20,8 +20,10 @@ struct InsertCtx {
 // node pools of the given capacities.
 uint64_t insert_scratch_bytes(uint64_t max_batch, int key_bytes, uint64_t leaf_cap, uint64_t inner_cap);
 
-// Testing switch of the one-key insert kernel; returns the previous setting.
+// Testing switches of the one-key insert and delete kernels; each returns
+// the previous setting.
 int set_single_key_insert(int on);
+int set_single_key_delete(int on);
 
 template <class K>
 void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, const K* vals, uint64_t B,
@@ -29,9 +31,12 @@ void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, cons
 
 // Delete batch on the same scratch; returns the device word that is nonzero
 // when the tree must be rebuilt from its keys (read after the stream ends).
+// host_flag (optional) is the device address of a pinned host word: a
+// one-key batch then also stores the flag there itself, and *flag_on_host
+// says so (the caller needs no copy).
 template <class K>
 const uint32_t* launch_delete(const TreeView<K>& t, const InsertCtx& c, const K* keys, uint64_t B, uint8_t* status,
-                              hipStream_t s);
+                              uint32_t* host_flag, bool* flag_on_host, hipStream_t s);
 
 // Every pair of the leaves that hold keys, appended at *n (device counter);
 // past `cap` pairs nothing is written, the counter still counts.

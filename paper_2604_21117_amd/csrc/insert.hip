@@ -198,9 +198,9 @@ __global__ void k_unique(Ins<K> v, uint64_t B, const K* __restrict__ vals) {
 }
 
 // Locate every distinct key; G lanes per key, QPG keys in flight per group,
-// the top levels from LDS.
-template <class K, int G, int QPG, int LV>
-__global__ __launch_bounds__(kBlk) void k_locate(TreeView<K> t, Ins<K> v, uint8_t* __restrict__ status) {
+// the top levels from LDS; NT threads per workgroup.
+template <class K, int G, int QPG, int LV, int NT>
+__device__ __forceinline__ void ph_locate(TreeView<K> t, Ins<K> v, uint8_t* __restrict__ status) {
     using T = Trav<K, G>;
     extern __shared__ __align__(16) uint8_t lds[];
     const uint8_t* mir = t.mirror;
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kBlk) void k_locate(TreeView<K> t, Ins<K> v, uint8_
     const int lane = lane_id();
     const int gl = lane % G, gbase = lane - gl;
     const uint64_t group = threadIdx.x / G;
-    const uint64_t per_block = static_cast<uint64_t>(kBlk / G) * QPG;
+    const uint64_t per_block = static_cast<uint64_t>(NT / G) * QPG;
     const uint64_t ntiles = (U + per_block - 1) / per_block;
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         K key[QPG];
@@ -252,6 +252,11 @@ __global__ __launch_bounds__(kBlk) void k_locate(TreeView<K> t, Ins<K> v, uint8_
             }
         }
     }
+}
+
+template <class K, int G, int QPG, int LV>
+__global__ __launch_bounds__(kBlk) void k_locate(TreeView<K> t, Ins<K> v, uint8_t* __restrict__ status) {
+    ph_locate<K, G, QPG, LV, kBlk>(t, v, status);
 }
 
 template <class K>
@@ -1544,6 +1549,22 @@ template void launch_insert<uint64_t>(const TreeView<uint64_t>&, const InsertCtx
 //     keys.
 
 constexpr uint32_t kHalf = kSlots / 2;
+
+// A counter that earlier threads raised with atomics (in the L2), read past
+// the L1, which may still hold its line from before.
+__device__ __forceinline__ uint32_t counter(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Inner nodes at depth < kMirrorDepth (0 = the root) are copied in the
+// top-levels mirror: rewriting one, or moving the root, means the mirror
+// must be refreshed at the commit (otherwise only its key count changes).
+constexpr int kMirrorDepth = 3;
+
+template <class K>
+__device__ __forceinline__ void note_inner_write(const Ins<K>& v, int depth) {
+    if (depth < kMirrorDepth) v.st->mirror_dirty = 1u;
+}
 constexpr uint64_t kDelListScan = 16384;  // above: the merge list comes from a scan, in key order
 
 template <class K>
@@ -1608,7 +1629,7 @@ __device__ __forceinline__ bool leaf_run_head(const Ins<K>& v, uint64_t u) {
 // address would serialise); k_del_list then lists the leaves left below
 // half full, one thread per distinct key.
 template <class K>
-__global__ __launch_bounds__(kBlk) void k_del_leaf(TreeView<K> t, Ins<K> v) {
+__device__ __forceinline__ void ph_del_leaf(TreeView<K> t, Ins<K> v) {
     if (t.hdr->error & kErrInternal) return;  // e.g. the batch's device sort gave up
     const uint64_t U = v.st->U;
     const int h = static_cast<int>(v.st->height);
@@ -1668,6 +1689,7 @@ __global__ __launch_bounds__(kBlk) void k_del_leaf(TreeView<K> t, Ins<K> v) {
                             const uint64_t o2 = static_cast<uint64_t>(l) * v.Bm + u;
                             if (v.pi[o2] + 1u < v.pc[o2]) {
                                 t.ikeys[static_cast<uint64_t>(v.pn[o2]) * kSlots + v.pi[o2]] = pk;
+                                note_inner_write(v, l);
                                 break;
                             }
                         }
@@ -1681,15 +1703,25 @@ __global__ __launch_bounds__(kBlk) void k_del_leaf(TreeView<K> t, Ins<K> v) {
     if (lane == 0 && del) atomicAdd(&v.st->deleted, del);
 }
 
+template <class K>
+__global__ __launch_bounds__(kBlk) void k_del_leaf(TreeView<K> t, Ins<K> v) {
+    ph_del_leaf<K>(t, v);
+}
+
 // The leaf runs left below half full, listed for the merge pass: small
 // batches append with an atomic (any order); large ones place each run at
 // its prefix-scan position, so the list is in key order.
 template <class K>
-__global__ void k_del_list(TreeView<K> t, Ins<K> v) {
+__device__ __forceinline__ void ph_del_list(TreeView<K> t, Ins<K> v) {
     if (t.hdr->error & kErrInternal) return;
     const uint64_t U = v.st->U;
     for (uint64_t u = gtid(); u < U; u += gstride())
         if (v.nu[u]) v.f1[atomicAdd(&v.st->merges, 1u)] = static_cast<uint32_t>(u);
+}
+
+template <class K>
+__global__ void k_del_list(TreeView<K> t, Ins<K> v) {
+    ph_del_list<K>(t, v);
 }
 
 template <class K>
@@ -1700,8 +1732,10 @@ __global__ void k_del_list_ordered(TreeView<K> t, Ins<K> v) {
         if (v.nu[u]) v.f1[v.nleaf[u]] = static_cast<uint32_t>(u);
 }
 
+// One wave per listed parent; a larger workgroup runs the same body with its
+// first wave (the others only meet the barriers).
 template <class K>
-__global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v, bool ordered) {
+__device__ __forceinline__ void ph_del_merge(TreeView<K> t, Ins<K> v, bool ordered) {
     if (t.hdr->error & kErrInternal) return;
     const int h = static_cast<int>(v.st->height);
     if (h < 2) return;
@@ -1711,7 +1745,7 @@ __global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v, bool 
     __shared__ uint32_t s_next;
     const int lane = static_cast<int>(threadIdx.x);
     const uint64_t lp = static_cast<uint64_t>(h - 2) * v.Bm;  // path level of the leaves' parents
-    const uint32_t nlist = v.st->merges;
+    const uint32_t nlist = counter(&v.st->merges);
     for (uint32_t li = blockIdx.x; li < nlist; li += gridDim.x) {
         // a leaf run that left its leaf below half full; the first such run
         // under its parent merges that parent
@@ -1768,11 +1802,12 @@ __global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v, bool 
             // 16 lanes per child, slot = lane % 16, four children per round:
             // every load of the gather in flight at once, few registers
             const uint32_t j = static_cast<uint32_t>(lane) % kSlots;
+            const bool w0 = lane < 64;
             K kk[4], vv[4];
 #pragma unroll
             for (uint32_t r = 0; r < 4; ++r) {
                 const uint32_t c = r * 4 + static_cast<uint32_t>(lane) / kSlots;
-                if (c < nc && j < cnt[c]) {
+                if (w0 && c < nc && j < cnt[c]) {
                     kk[r] = t.lkeys[static_cast<uint64_t>(kid[c]) * kSlots + j];
                     vv[r] = t.lvals[static_cast<uint64_t>(kid[c]) * kSlots + j];
                 }
@@ -1780,7 +1815,7 @@ __global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v, bool 
 #pragma unroll
             for (uint32_t r = 0; r < 4; ++r) {
                 const uint32_t c = r * 4 + static_cast<uint32_t>(lane) / kSlots;
-                if (c < nc && j < cnt[c]) {
+                if (w0 && c < nc && j < cnt[c]) {
                     mk[pre[c] + j] = kk[r];
                     mv[pre[c] + j] = vv[r];
                 }
@@ -1814,6 +1849,7 @@ __global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v, bool 
                 t.lmeta[kid[j]] = make_uint2(0u, kNone);
             }
         }
+        if (lane == 0) note_inner_write(v, h - 2);  // P, or the root it replaces
         if (root && n0 == 1) {
             // the root shrinks to its first leaf
             if (lane == 0) {
@@ -1837,6 +1873,7 @@ __global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v, bool 
                     const uint64_t o2 = static_cast<uint64_t>(l) * v.Bm + u;
                     if (v.pi[o2] + 1u < v.pc[o2]) {
                         t.ikeys[static_cast<uint64_t>(v.pn[o2]) * kSlots + v.pi[o2]] = top;
+                        note_inner_write(v, l);
                         break;
                     }
                 }
@@ -1844,6 +1881,11 @@ __global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v, bool 
         }
         __syncthreads();
     }
+}
+
+template <class K>
+__global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v, bool ordered) {
+    ph_del_merge<K>(t, v, ordered);
 }
 
 // One level up: a leaf parent that would fall below half full (fewer than
@@ -1858,7 +1900,7 @@ __global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v, bool 
 constexpr int kBelowG = kSlots * kSlots * kSlots;
 
 template <class K>
-__global__ __launch_bounds__(1024) void k_del_merge2(TreeView<K> t, Ins<K> v) {
+__device__ __forceinline__ void ph_del_merge2(TreeView<K> t, Ins<K> v) {
     if (t.hdr->error & kErrInternal) return;
     const int h = static_cast<int>(v.st->height);
     if (h < 3) return;
@@ -1870,7 +1912,7 @@ __global__ __launch_bounds__(1024) void k_del_merge2(TreeView<K> t, Ins<K> v) {
     __shared__ uint32_t s_first, s_next;
     const int tid = static_cast<int>(threadIdx.x);
     const uint64_t lg = static_cast<uint64_t>(h - 3) * v.Bm;  // path level of the grandparents
-    const uint32_t nlist = v.st->gmerges;
+    const uint32_t nlist = counter(&v.st->gmerges);
     for (uint32_t li = blockIdx.x; li < nlist; li += gridDim.x) {
         const uint64_t u = v.upos[li];
         const uint32_t G = v.pn[lg + u];
@@ -1978,6 +2020,7 @@ __global__ __launch_bounds__(1024) void k_del_merge2(TreeView<K> t, Ins<K> v) {
                 s2 + 1 < n1 ? mk[leaf_end(par_first(s2 + 1) - 1) - 1] : kmax<K>();
         }
         if (tid == 0) {
+            note_inner_write(v, h - 3);  // G and its parents, or the root that replaces G
             if (root && n1 == 0) {
                 t.hdr->root = lid[0] | kLeafTag;
                 t.hdr->height = 1;
@@ -1990,6 +2033,7 @@ __global__ __launch_bounds__(1024) void k_del_merge2(TreeView<K> t, Ins<K> v) {
                     const uint64_t o2 = static_cast<uint64_t>(l) * v.Bm + u;
                     if (v.pi[o2] + 1u < v.pc[o2]) {
                         t.ikeys[static_cast<uint64_t>(v.pn[o2]) * kSlots + v.pi[o2]] = top;
+                        note_inner_write(v, l);
                         break;
                     }
                 }
@@ -1999,20 +2043,86 @@ __global__ __launch_bounds__(1024) void k_del_merge2(TreeView<K> t, Ins<K> v) {
     }
 }
 
-// Commit the count and the epoch, then rebuild the top-levels mirror (one
-// launch).
 template <class K>
-__global__ __launch_bounds__(256) void k_del_commit(TreeView<K> t, Ins<K> v) {
+__global__ __launch_bounds__(1024) void k_del_merge2(TreeView<K> t, Ins<K> v) {
+    ph_del_merge2<K>(t, v);
+}
+
+// Commit the count and the epoch, then refresh the top-levels mirror if a
+// mirrored node changed, else only its key count (one launch).
+template <class K, int NT>
+__device__ __forceinline__ void ph_del_commit(TreeView<K> t, Ins<K> v) {
     if (threadIdx.x == 0 && !(t.hdr->error & kErrInternal)) {
-        const uint32_t d = v.st->deleted;
+        const uint32_t d = counter(&v.st->deleted);
         if (d) {
             t.hdr->n_keys -= d;
             t.hdr->epoch += 1;
         }
     }
     __syncthreads();
-    mirror_refresh_body<K, 256>(t);
+    if (counter(&v.st->mirror_dirty)) {
+        mirror_refresh_body<K, NT>(t);
+    } else if (threadIdx.x == 0) {
+        reinterpret_cast<MirrorHeader*>(t.mirror)->n_keys = t.hdr->n_keys;
+    }
 }
+
+template <class K>
+__global__ __launch_bounds__(256) void k_del_commit(TreeView<K> t, Ins<K> v) {
+    ph_del_commit<K, 256>(t, v);
+}
+
+// A batch of one key in one launch: the batch path's phases, one after the
+// other in a single 1024-thread workgroup (a grid of one workgroup runs each
+// phase's loops over one workgroup), so the tree it leaves is the batch
+// path's.  The workgroup's waves share one CU and its L1, so a barrier with
+// its workgroup-scope fences orders the phases' plain loads and stores; the
+// counters raised with atomics are read past the L1 (counter()).  A device-
+// scope fence here would write back and invalidate the L2 at every phase.
+constexpr int kDelOneBlock = 1024;
+
+__device__ __forceinline__ void phase_boundary() {
+    __syncthreads();
+}
+
+template <class K>
+__global__ __launch_bounds__(kDelOneBlock) void k_del_one(TreeView<K> t, Ins<K> v, const K* __restrict__ keys,
+                                                          uint8_t* __restrict__ status, uint32_t* host_flag) {
+    const uint32_t tid = threadIdx.x;
+    uint32_t* st = reinterpret_cast<uint32_t*>(v.st);
+    for (uint32_t i = tid; i < sizeof(InsState) / 4; i += kDelOneBlock) st[i] = 0;
+    phase_boundary();
+    // the sort and the distinct keys of a one-key batch
+    if (tid == 0) {
+        const K k = keys[0];
+        v.sk[0] = k;
+        v.si[0] = 0;
+        v.uk[0] = k;
+        v.upos[0] = 0;
+        v.st->U = 1;
+        v.st->height = t.hdr->height;
+    }
+    phase_boundary();
+    ph_locate<K, 16, 1, 2, kDelOneBlock>(t, v, status);
+    phase_boundary();
+    ph_del_leaf<K>(t, v);
+    phase_boundary();
+    ph_del_list<K>(t, v);
+    phase_boundary();
+    ph_del_merge<K>(t, v, false);
+    phase_boundary();
+    ph_del_merge2<K>(t, v);
+    phase_boundary();
+    ph_del_commit<K, kDelOneBlock>(t, v);
+    // the rebuild flag straight into host memory (the merges that raise it
+    // are behind the barriers above)
+    if (host_flag && tid == 0)
+        __hip_atomic_store(host_flag, counter(&v.st->rebuild), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+static std::atomic<int> g_single_key_delete{1};
+int set_single_key_delete(int on) { return g_single_key_delete.exchange(on ? 1 : 0, std::memory_order_relaxed); }
+static bool single_key_delete_on() { return g_single_key_delete.load(std::memory_order_relaxed) != 0; }
 
 // Copy every pair of the leaves that hold keys (cleared leaves hold none).
 template <class K>
@@ -2032,10 +2142,17 @@ __global__ void k_del_collect(TreeView<K> t, uint32_t leaves, K* __restrict__ ok
 
 template <class K>
 const uint32_t* launch_delete(const TreeView<K>& t, const InsertCtx& c, const K* keys, uint64_t B, uint8_t* status,
-                              hipStream_t s) {
+                              uint32_t* host_flag, bool* flag_on_host, hipStream_t s) {
+    *flag_on_host = false;
     Ins<K> v;
     carve<K>(&v, c.scratch, c.max_batch, c.leaf_cap, c.inner_cap);
     const uint32_t gB = grid_for(B, kBlk);
+    if (B == 1 && single_key_delete_on()) {
+        const uint32_t lds = MirrorLayout<K>::bytes(mirror_nodes_for_levels(2));
+        hipLaunchKernelGGL(k_del_one<K>, dim3(1), dim3(kDelOneBlock), lds, s, t, v, keys, status, host_flag);
+        *flag_on_host = host_flag != nullptr;
+        return &v.st->rebuild;
+    }
     if (B <= kSmallInsert) {
         rank_sort_small<K>(keys, static_cast<uint32_t>(B), v.sk, v.si, reinterpret_cast<uint32_t*>(v.st),
                            static_cast<uint32_t>(sizeof(InsState) / 4), s);
@@ -2073,9 +2190,9 @@ void launch_delete_collect(const TreeView<K>& t, uint32_t leaves, K* ok, K* ov, 
 }
 
 template const uint32_t* launch_delete<uint32_t>(const TreeView<uint32_t>&, const InsertCtx&, const uint32_t*,
-                                                 uint64_t, uint8_t*, hipStream_t);
+                                                 uint64_t, uint8_t*, uint32_t*, bool*, hipStream_t);
 template const uint32_t* launch_delete<uint64_t>(const TreeView<uint64_t>&, const InsertCtx&, const uint64_t*,
-                                                 uint64_t, uint8_t*, hipStream_t);
+                                                 uint64_t, uint8_t*, uint32_t*, bool*, hipStream_t);
 template void launch_delete_collect<uint32_t>(const TreeView<uint32_t>&, uint32_t, uint32_t*, uint32_t*, uint64_t,
                                               unsigned long long*, hipStream_t);
 template void launch_delete_collect<uint64_t>(const TreeView<uint64_t>&, uint32_t, uint64_t*, uint64_t*, uint64_t,

@@ -272,6 +272,7 @@ gt_status gt_tree_copy_for_training(const gt_tree* t, gt_tree* dst, hipStream_t 
 gt_tree* gt_tree_clone_handle(const gt_tree* t, uint8_t* arena) {
     gt_tree* c = new gt_tree(*t);
     c->h_flag = nullptr;
+    c->d_flag = nullptr;
     c->wide = nullptr;
     c->inserts = 0;
     c->deletes = 0;
@@ -296,6 +297,7 @@ const char* gt_status_str(gt_status s) {
 
 uint32_t gt_set_sort_spin_limit(uint32_t limit) { return set_sort_spin_limit(limit); }
 int gt_set_single_key_insert(int enable) { return set_single_key_insert(enable); }
+int gt_set_single_key_delete(int enable) { return set_single_key_delete(enable); }
 
 uint64_t tree_arena_bytes(const gt_params* p, uint64_t n, uint64_t leaf_slack) {
     if (wide_selected(p)) return wide_arena_bytes(p, n);  // static: no headroom
@@ -433,16 +435,22 @@ gt_status tree_delete_batch(gt_tree* t, const void* keys, uint64_t B, uint8_t* s
     c.inner_cap = t->inner_cap;
     c.leaf_cap = t->leaf_cap;
     c.cfg = t->cfg;
+    // pinned, so that the flag goes straight to host memory (the first call
+    // allocates it); a one-key batch's kernel stores it there itself
+    if (!t->h_flag) {
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&t->h_flag), 64, hipHostMallocDefault));
+        if (hipHostGetDevicePointer(reinterpret_cast<void**>(&t->d_flag), t->h_flag, 0) != hipSuccess)
+            t->d_flag = nullptr;
+    }
+    bool on_host = false;
     const uint32_t* flag =
         t->kb == 8 ? launch_delete<uint64_t>(view<uint64_t>(t), c, reinterpret_cast<const uint64_t*>(keys), B,
-                                             status_out, stream)
+                                             status_out, t->d_flag, &on_host, stream)
                    : launch_delete<uint32_t>(view<uint32_t>(t), c, reinterpret_cast<const uint32_t*>(keys), B,
-                                             status_out, stream);
+                                             status_out, t->d_flag, &on_host, stream);
     HIP_TRY(hipGetLastError());
     t->deletes++;
-    // pinned, so that the copy goes straight to host memory (first call allocates it)
-    if (!t->h_flag) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&t->h_flag), 64, hipHostMallocDefault));
-    HIP_TRY(hipMemcpyAsync(t->h_flag, flag, 4, hipMemcpyDeviceToHost, stream));
+    if (!on_host) HIP_TRY(hipMemcpyAsync(t->h_flag, flag, 4, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     if (!*t->h_flag) return GT_OK;
     return t->kb == 8 ? delete_rebuild_t<uint64_t>(t, stream) : delete_rebuild_t<uint32_t>(t, stream);
