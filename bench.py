@@ -65,6 +65,13 @@ counted memory traffic, R1 = traffic / time / peak and R2 = algorithmic /
 traffic.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Diagnostic modes (each prints one JSON object and exits): --profile (the
+counter-collection workload), --probe (memory-system probes), --order-probe,
+--stream-probe, --shape-probe (the 2^20-key lookup by query order, leaf
+stream setting and lookup shape), --variants (the static tree only), and
+--write-traffic DIR (host only: the counter CSVs of --profile to
+profiles/hbm_traffic.json).
 """
 from __future__ import annotations
 
@@ -85,7 +92,7 @@ import synth  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 MAX64 = (1 << 64) - 1
 METRIC = "lookup Mops/s and \u00b5s/batch at B=1..1024, 2^24 keys; learned vs plain tree"
-LARGE_KERNEL = "k_lookup<unsigned long, 8, 4, 2, true, 2>"
+LARGE_KERNEL = "k_lookup<unsigned long, 8, 2, 2, true, 2>"
 N_LOG2 = 24
 SEED = 2
 
@@ -585,6 +592,9 @@ def main():
                     help="the 2^20-key lookup on trees built with each leaf_stream setting (value lines "
                          "non-temporal, key and value lines, none) and with xcd_split: warm, distinct batches, "
                          "cold; then exit")
+    ap.add_argument("--shape-probe", action="store_true",
+                    help="the 2^20-key lookup on trees built with fixed lookup shapes (lanes per query, queries "
+                         "per group, LDS levels): warm, distinct batches, cold; then exit")
     ap.add_argument("--write-traffic", metavar="DIR",
                     help="host only: write profiles/hbm_traffic.json from the CSVs of the FETCH_SIZE, WRITE_SIZE "
                          "and kernel-trace runs of --profile under DIR (pmc_fetch, pmc_write, ktrace_profile), "
@@ -704,6 +714,43 @@ def main():
             res[f"{name}_cold_us"] = med(lambda r: g.tree_lookup_batch(ts_.h, q0, vl, fl, stream), 7, True)
             assert g.to_numpy(fl).all() and np.array_equal(g.to_numpy(vl, np.uint64),
                                                            synth.values_for(ql_np, SEED, 64))
+            del qx, q0
+            ts_.close()
+        print(json.dumps(res), flush=True)
+        return
+
+    if args.shape_probe:
+        # the 2^20-key lookup on trees built with fixed lookup shapes (lanes
+        # per query, queries per group, LDS levels; 0 = the default by batch
+        # size): warm, distinct batches, cold (after a 2 GiB flush).  Two
+        # shapes come twice, at the start and at the end, to show the spread.
+        flush = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
+        extra = [synth.present_queries(keys, BL, SEED, purpose=5100 + i) for i in range(4)]
+
+        def med(fn, reps, cold):
+            ts = []
+            for r in range(reps):
+                if cold:
+                    flush.add_(1)
+                ts += timer.run(lambda: fn(r), 1, skip=0)
+            return round(float(np.median(ts[1:])), 2)
+
+        res = {"batch": BL, "keys": n}
+        tree.close()
+        shapes = ((0, 0, 0), (8, 4, 0), (8, 1, 0), (8, 2, 1), (8, 2, 3), (8, 4, 3), (4, 2, 0), (16, 2, 0),
+                  (8, 4, 0), (0, 0, 0))
+        for i, (lanes, qpg, lv) in enumerate(shapes):
+            ts_ = g.Tree(keys, vals, 8, lanes_per_query=lanes, queries_per_group=qpg, lds_levels=lv)
+            qx = [ts_.dev(x) for x in extra]
+            q0 = ts_.dev(ql_np)
+            g.tree_lookup_batch(ts_.h, q0, vl, fl, stream)
+            row = {"warm_us": med(lambda r: g.tree_lookup_batch(ts_.h, q0, vl, fl, stream), 9, False),
+                   "distinct_us": med(lambda r: g.tree_lookup_batch(ts_.h, qx[r % 4], vl, fl, stream), 9, False),
+                   "cold_us": med(lambda r: g.tree_lookup_batch(ts_.h, q0, vl, fl, stream), 7, True)}
+            assert g.to_numpy(fl).all() and np.array_equal(g.to_numpy(vl, np.uint64),
+                                                           synth.values_for(ql_np, SEED, 64))
+            res[f"{i}: lanes {lanes or 'auto'}, per group {qpg or 'auto'}, lds {lv or 'auto'}"] = row
+            print(f"[shape-probe] {i} done", file=sys.stderr, flush=True)
             del qx, q0
             ts_.close()
         print(json.dumps(res), flush=True)

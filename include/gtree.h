@@ -103,7 +103,7 @@ typedef struct {
     uint32_t sorted_mode;     /* reserved, must be 0                          */
     uint32_t queries_per_group; /* queries a lane group walks at once: 1, 2
                                    or 4 for every batch; 0 = by batch size
-                                   (1 below 2^15 queries, else 4)             */
+                                   (1 below 2^15 queries, else 2)             */
     uint64_t max_batch;       /* largest insert batch; default 2^20           */
     uint32_t value_coload;    /* 1: a lookup reads the leaf's value line with
                                  its key line (one dependent load fewer);

@@ -387,14 +387,15 @@ static void launch_lookup_lv(const TreeView<K>& t, const LaunchCfg& cfg, const K
 // (measured on 2^24 u64 keys): small batches are latency-bound and want
 // 16 lanes per query, one query per group and no LDS staging (the top
 // levels are L2 hits, the staging a barrier on the critical path); large
-// batches are bound by the rate of L2 misses and want 8 lanes, four queries
-// in flight per group and the top two levels in LDS.
+// batches are bound by the rate of L2 misses and want 8 lanes, two queries
+// in flight per group (one is too few to hide the misses; four cost more in
+// registers and barriers than they add) and the top two levels in LDS.
 static LaunchCfg shape_for(const LaunchCfg& cfg, uint64_t B) {
     LaunchCfg c = cfg;
     int lanes, qpg, lds;
     if (B < kMidBatch) { lanes = 16; qpg = 1; lds = 0; }
     else if (B < kLargeBatch) { lanes = 8; qpg = 1; lds = 0; }
-    else { lanes = 8; qpg = cfg.large_qpg ? cfg.large_qpg : 4; lds = 2; }
+    else { lanes = 8; qpg = cfg.large_qpg ? cfg.large_qpg : 2; lds = 2; }
     if (cfg.shape_auto & 1) c.lanes = lanes;
     if (cfg.shape_auto & 2) c.queries_per_group = qpg;
     else if (B >= kLargeBatch && cfg.large_qpg) c.queries_per_group = cfg.large_qpg;

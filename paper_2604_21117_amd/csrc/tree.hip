@@ -347,7 +347,7 @@ gt_status tree_build(const gt_params* p, const void* keys, const void* values, u
     t->cfg.xcd_split = p->xcd_split == 1 ? 1 : 0;
     t->cfg.leaf_stream = static_cast<int>(p->leaf_stream);  // 0 by batch size, 1 both lines, 2 none
     // an explicit queries_per_group applies to every batch size
-    t->cfg.large_qpg = p->queries_per_group ? 0 : 4;
+    t->cfg.large_qpg = p->queries_per_group ? 0 : 2;
     // lookup shape fields the caller left at 0 follow the batch size
     t->cfg.shape_auto = (p->lanes_per_query ? 0 : 1) | (p->queries_per_group ? 0 : 2) | (p->lds_levels ? 0 : 4);
     layout(t, reinterpret_cast<uint8_t*>(arena), lo);
