@@ -1341,24 +1341,36 @@ __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int 
     // count (leaves) or sum(k - 1) over its child items (inner levels): a
     // difference of the child level's piece-offset prefix (s_k), taken by
     // the run's first and last keys.
+    // Every LDS read of a step is issued before any of them is used (the
+    // indexes of keys and items past the end are clamped to 0 rather than
+    // branched around), and each key's item at the level below stays in a
+    // register: a single wave otherwise waits out one LDS round trip per read.
     uint32_t psep = 0;
+    uint32_t below[2] = {0u, 0u};  // each key's item index at level d - 1
 #pragma unroll 1
     for (int d = 0; d < hmax; ++d) {
         const uint32_t bd = s_base[d], nd = s_base[d + 1] - bd;
+        uint32_t ixd[2], c[2], e[2];
         for (int j = 0; j < 2; ++j) {
             const uint32_t r = 2 * tid + j;
+            ixd[j] = s_ix[d * kCap + (valid[j] ? r : 0u)];
+            c[j] = d == 0 ? r : s_k[below[j]];
+            e[j] = d == 0 ? r + 1 : s_k[below[j] + 1];
+        }
+        for (int j = 0; j < 2; ++j) {
             if (!valid[j]) continue;
-            const uint32_t ixd = s_ix[d * kCap + r];
-            const uint32_t c = d == 0 ? r : s_k[s_ix[(d - 1) * kCap + r]];
-            if ((hbits >> (2 * d + j)) & 1u) s_a[ixd] = c;
-            if ((lbits >> (2 * d + j)) & 1u) s_b[ixd] = d == 0 ? r + 1 : s_k[s_ix[(d - 1) * kCap + r] + 1];
+            if ((hbits >> (2 * d + j)) & 1u) s_a[ixd[j]] = c[j];
+            if ((lbits >> (2 * d + j)) & 1u) s_b[ixd[j]] = e[j];
+            below[j] = ixd[j];
         }
         __syncthreads();
         uint32_t kk[2], f[2];
         for (int i = 0; i < 2; ++i) {
             const uint32_t jt = 2 * tid + i;
             const bool in = jt < nd && bd + jt < total;
-            kk[i] = in ? split_pieces(static_cast<uint64_t>(s_C[bd + jt]) + (s_b[jt] - s_a[jt])) : 1u;
+            const uint32_t at = in ? jt : 0u;
+            const uint32_t C = s_C[in ? bd + jt : 0u], hi = s_b[at], lo = s_a[at];
+            kk[i] = in ? split_pieces(static_cast<uint64_t>(C) + (hi - lo)) : 1u;
             f[i] = in ? kk[i] - 1u : 0u;
         }
         uint32_t nnew;

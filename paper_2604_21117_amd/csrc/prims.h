@@ -6,15 +6,34 @@
 
 namespace gt {
 
+// Inclusive scan over the 64 lanes of a wave (every lane active).  32-bit
+// integers use DPP moves, which stay in the vector ALU: within each row of
+// 16 lanes, steps adding the value 1, 2, 4 and 8 lanes below (a lane whose
+// source lies outside its row adds 0), then row 0's total into row 1 and
+// row 2's into row 3 (row broadcast of lane 15), then the total of rows 0-1
+// into rows 2 and 3 (row broadcast of lane 31).  Other types shift with
+// cross-lane reads, one LDS-path round trip per step, in the same order as
+// before for floating point.
 template <class T>
 __device__ __forceinline__ T wave_incl_scan(T x) {
-    const int lane = threadIdx.x & 63;
+    if constexpr (sizeof(T) == 4 && static_cast<T>(-1) > static_cast<T>(0)) {
+        int v = static_cast<int>(x);
+        v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);   // row_shr:1
+        v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);   // row_shr:2
+        v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);   // row_shr:4
+        v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);   // row_shr:8
+        v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15, rows 1 and 3
+        v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31, rows 2 and 3
+        return static_cast<T>(v);
+    } else {
+        const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        T y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
+        for (int d = 1; d < 64; d <<= 1) {
+            T y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
+        }
+        return x;
     }
-    return x;
 }
 
 // Exclusive scan across the block (blockDim.x a multiple of 64, <= 2048).
