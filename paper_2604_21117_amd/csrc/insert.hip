@@ -36,6 +36,7 @@
 //  6. Commit the header (key count, pool cursors, height, root) and refresh
 //     the top-levels mirror.
 #include <atomic>
+#include <type_traits>
 
 #include "insert.h"
 #include "mirror.h"
@@ -495,6 +496,32 @@ __device__ __forceinline__ uint32_t lower_bound_dev(const K* a, uint32_t n, K k)
 // Lanes that rebuild one node (a leaf or an inner node): one per slot, four
 // nodes per wave, so a wave keeps four nodes' reads in flight.
 constexpr int kNodeLanes = 16;
+static_assert(kNodeLanes == 16, "a node's lane group is one DPP row (row_lane)");
+
+// The value x holds in lane S of this lane's row of 16 lanes: a DPP row
+// broadcast (row_newbcast), one vector-ALU move where a cross-lane read
+// would make an LDS-path round trip.  The source lane must be active.
+template <int S>
+__device__ __forceinline__ uint32_t row_lane(uint32_t x) {
+    static_assert(S >= 0 && S < 16, "a lane of the row");
+    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x150 + S, 0xf, 0xf, false));
+}
+template <int S>
+__device__ __forceinline__ uint64_t row_lane(uint64_t x) {
+    const uint32_t lo = row_lane<S>(static_cast<uint32_t>(x));
+    const uint32_t hi = row_lane<S>(static_cast<uint32_t>(x >> 32));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// f(std::integral_constant<int, I>) for I = B .. E-1, unrolled at compile
+// time (for cross-lane moves whose lane is part of the instruction).
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
 
 // Merge-split of the touched leaves: kNodeLanes lanes per leaf, group grp
 // of ngrp.
@@ -547,12 +574,13 @@ __device__ __forceinline__ void apply_leaves_body(TreeView<K> t, Ins<K> v, uint6
         uint64_t opos = ~0ull;
         if (one_run) {
             // new keys below this lane's old key, from the group's lanes
+            // (a group is a row of 16 lanes: the moves are row broadcasts)
             const K mine = static_cast<uint32_t>(gl) < r ? nk[gl] : K(0);
             uint32_t below = 0;
-            for (uint32_t s = 0; s < r; ++s) {
-                const K ks = __shfl(mine, gbase + static_cast<int>(s), 64);
-                below += ks < okey ? 1u : 0u;
-            }
+            static_for<0, kNodeLanes>([&](auto S) {
+                const K ks = row_lane<decltype(S)::value>(mine);
+                below += (static_cast<uint32_t>(decltype(S)::value) < r && ks < okey) ? 1u : 0u;
+            });
             if (has_old) opos = gl + below;
         } else if (has_old) {
             opos = gl + lower_bound_dev(nk, r, okey);
@@ -565,10 +593,10 @@ __device__ __forceinline__ void apply_leaves_body(TreeView<K> t, Ins<K> v, uint6
             const bool act = q < r;
             const K key = act ? nk[q] : K(0);
             uint32_t rank = 0;
-            for (uint32_t s = 0; s < c; ++s) {
-                const K ks = __shfl(okey, gbase + static_cast<int>(s), 64);
-                rank += ks < key ? 1u : 0u;
-            }
+            static_for<0, kNodeLanes>([&](auto S) {
+                const K ks = row_lane<decltype(S)::value>(okey);
+                rank += (static_cast<uint32_t>(decltype(S)::value) < c && ks < key) ? 1u : 0u;
+            });
             if (act) {
                 place(q + rank, key, nv[q]);
                 npos = q + rank;
@@ -631,16 +659,18 @@ __device__ __forceinline__ void apply_inner_body(TreeView<K> t, Ins<K> v, int d,
             cks = v.it_k[bc + first + lane];
             cof = v.it_off[bc + first + lane];
         }
-        // per old slot: shift from split children before it, and its own item
+        // per old slot: shift from split children before it, and its own
+        // item (lanes past nci hold no item: slot kNone, one piece, so they
+        // add nothing; the moves are row broadcasts)
         uint32_t shift = 0, myk = 1, myoff = 0;
         uint64_t a = 0;
-        for (uint32_t i = 0; i < nci; ++i) {
-            const int src = gbase + static_cast<int>(i);
-            const uint32_t cs = shfl_u32(ccs, src), ki = shfl_u32(cks, src), oi = shfl_u32(cof, src);
+        static_for<0, kNodeLanes>([&](auto S) {
+            constexpr int i = decltype(S)::value;
+            const uint32_t cs = row_lane<i>(ccs), ki = row_lane<i>(cks), oi = row_lane<i>(cof);
             a += ki - 1;
             if (cs < lane) shift += ki - 1;
             if (cs == lane) { myk = ki; myoff = oi; }
-        }
+        });
         __threadfence_block();  // the old node is in registers before any write
         if (a == 0) continue;   // no child split: the parent is unchanged
         const uint32_t newpos = lane + shift;
@@ -651,10 +681,11 @@ __device__ __forceinline__ void apply_inner_body(TreeView<K> t, Ins<K> v, int d,
             const bool act = e < Cp;
             // old slot whose entries cover e: the last slot with newpos <= e
             uint32_t sf = 0;
-            for (uint32_t s = 0; s < C; ++s) {
-                const uint32_t np = shfl_u32(newpos, gbase + static_cast<int>(s));
-                if (np <= e) sf = s;
-            }
+            static_for<0, kNodeLanes>([&](auto S) {
+                constexpr uint32_t s = decltype(S)::value;
+                const uint32_t np = row_lane<s>(newpos);
+                if (s < C && np <= e) sf = s;
+            });
             const int src = gbase + static_cast<int>(sf);
             const uint32_t np = shfl_u32(newpos, src);
             const uint32_t ks = shfl_u32(myk, src);
