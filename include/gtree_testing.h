@@ -45,15 +45,15 @@ uint32_t gt_set_sort_spin_limit(uint32_t limit);
 int gt_set_single_key_insert(int enable);
 
 /*
- * Testing switch of the one-key delete: a batch of B = 1 runs in one launch
- * (the batch path's phases in one workgroup: locate, leaf removal, the
- * parent and grandparent merges, commit and mirror) instead of the batch
- * path's eight, with the same resulting tree.  enable = 0 sends B = 1
- * through the batch path; any other value restores the default (on).
- * Process-wide, read when a delete is launched.  Returns the previous
- * setting (1 on, 0 off).
+ * Testing switch of the one-launch delete: a batch of at most 64 keys runs
+ * in one launch (the batch path's phases in one workgroup: ranking and
+ * deduplication, locate, leaf removal, the parent and grandparent merges,
+ * commit and mirror) instead of the batch path's eight, with the same
+ * resulting tree.  enable = 0 sends such batches through the batch path;
+ * any other value restores the default (on).  Process-wide, read when a
+ * delete is launched.  Returns the previous setting (1 on, 0 off).
  */
-int gt_set_single_key_delete(int enable);
+int gt_set_one_launch_delete(int enable);
 
 #ifdef __cplusplus
 }

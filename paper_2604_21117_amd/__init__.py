@@ -120,8 +120,8 @@ def lib():
         L.gt_set_sort_spin_limit.restype = u32
         L.gt_set_single_key_insert.argtypes = [C.c_int]
         L.gt_set_single_key_insert.restype = C.c_int
-        L.gt_set_single_key_delete.argtypes = [C.c_int]
-        L.gt_set_single_key_delete.restype = C.c_int
+        L.gt_set_one_launch_delete.argtypes = [C.c_int]
+        L.gt_set_one_launch_delete.restype = C.c_int
         L.li_arena_bytes.argtypes = [vp, C.POINTER(gt_li_params)]
         L.li_arena_bytes.restype = u64
         L.li_create.argtypes = [vp, C.POINTER(gt_li_params), vp, u64, C.POINTER(vp)]
@@ -289,11 +289,11 @@ def set_single_key_insert(enable: bool) -> bool:
     return bool(lib().gt_set_single_key_insert(1 if enable else 0))
 
 
-def set_single_key_delete(enable: bool) -> bool:
-    """Testing switch: a one-key delete batch runs in one launch (True, the
-    default) or through the batch path's kernels (False); returns the
-    previous setting."""
-    return bool(lib().gt_set_single_key_delete(1 if enable else 0))
+def set_one_launch_delete(enable: bool) -> bool:
+    """Testing switch: a delete batch of at most 64 keys runs in one launch
+    (True, the default) or through the batch path's kernels (False); returns
+    the previous setting."""
+    return bool(lib().gt_set_one_launch_delete(1 if enable else 0))
 
 
 def tree_export(h, stream=None) -> np.ndarray:

@@ -1750,21 +1750,42 @@ __global__ void k_del_list_ordered(TreeView<K> t, Ins<K> v) {
         if (v.nu[u]) v.f1[v.nleaf[u]] = static_cast<uint32_t>(u);
 }
 
-// One wave per listed parent; a larger workgroup runs the same body with its
-// first wave (the others only meet the barriers).
+// A wave's LDS for merging one listed parent.
 template <class K>
-__device__ __forceinline__ void ph_del_merge(TreeView<K> t, Ins<K> v, bool ordered) {
+struct MergeLds {
+    K mk[kSlots * kSlots];
+    K mv[kSlots * kSlots];
+    uint32_t kid[kSlots], cnt[kSlots], pre[kSlots + 1];
+    uint32_t next;
+};
+
+// Orders a wave's LDS writes before its lanes' later reads (a wave-level
+// barrier: the body runs in one wave).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wave per listed parent: wave w of nw takes list entries w, w + nw, ...
+// with its own LDS slice (the batch kernel: one wave per workgroup; the
+// one-launch delete: the waves of its workgroup).
+template <class K>
+__device__ __forceinline__ void ph_del_merge(TreeView<K> t, Ins<K> v, bool ordered, uint32_t w, uint32_t nw,
+                                             MergeLds<K>& sm) {
     if (t.hdr->error & kErrInternal) return;
     const int h = static_cast<int>(v.st->height);
     if (h < 2) return;
-    __shared__ K mk[kSlots * kSlots];
-    __shared__ K mv[kSlots * kSlots];
-    __shared__ uint32_t kid[kSlots], cnt[kSlots], pre[kSlots + 1];
-    __shared__ uint32_t s_next;
-    const int lane = static_cast<int>(threadIdx.x);
+    K* const mk = sm.mk;
+    K* const mv = sm.mv;
+    uint32_t* const kid = sm.kid;
+    uint32_t* const cnt = sm.cnt;
+    uint32_t* const pre = sm.pre;
+    uint32_t& s_next = sm.next;
+    const int lane = lane_id();
     const uint64_t lp = static_cast<uint64_t>(h - 2) * v.Bm;  // path level of the leaves' parents
     const uint32_t nlist = counter(&v.st->merges);
-    for (uint32_t li = blockIdx.x; li < nlist; li += gridDim.x) {
+    for (uint32_t li = w; li < nlist; li += nw) {
         // a leaf run that left its leaf below half full; the first such run
         // under its parent merges that parent
         const uint64_t u = v.f1[li];
@@ -1793,7 +1814,7 @@ __device__ __forceinline__ void ph_del_merge(TreeView<K> t, Ins<K> v, bool order
             const uint32_t c = static_cast<uint32_t>(lane) < nc ? t.lmeta[ref & ~kLeafTag].x : 0u;
             cnt[lane] = c < kSlots ? c : kSlots;
         }
-        __syncthreads();
+        wave_sync();
         if (lane == 0) {
             uint32_t a = 0;
             for (int i = 0; i < kSlots; ++i) {
@@ -1803,7 +1824,7 @@ __device__ __forceinline__ void ph_del_merge(TreeView<K> t, Ins<K> v, bool order
             pre[kSlots] = a;
             s_next = t.lmeta[kid[nc - 1]].y;
         }
-        __syncthreads();
+        wave_sync();
         const uint32_t T = pre[kSlots];
         const bool root = h == 2;
         if (!root && T < kHalf * kHalf) {
@@ -1813,19 +1834,18 @@ __device__ __forceinline__ void ph_del_merge(TreeView<K> t, Ins<K> v, bool order
                 v.f0[u] = 2u;
                 v.upos[atomicAdd(&v.st->gmerges, 1u)] = static_cast<uint32_t>(u);
             }
-            __syncthreads();
+            wave_sync();
             continue;
         }
         {
             // 16 lanes per child, slot = lane % 16, four children per round:
             // every load of the gather in flight at once, few registers
             const uint32_t j = static_cast<uint32_t>(lane) % kSlots;
-            const bool w0 = lane < 64;
             K kk[4], vv[4];
 #pragma unroll
             for (uint32_t r = 0; r < 4; ++r) {
                 const uint32_t c = r * 4 + static_cast<uint32_t>(lane) / kSlots;
-                if (w0 && c < nc && j < cnt[c]) {
+                if (c < nc && j < cnt[c]) {
                     kk[r] = t.lkeys[static_cast<uint64_t>(kid[c]) * kSlots + j];
                     vv[r] = t.lvals[static_cast<uint64_t>(kid[c]) * kSlots + j];
                 }
@@ -1833,18 +1853,18 @@ __device__ __forceinline__ void ph_del_merge(TreeView<K> t, Ins<K> v, bool order
 #pragma unroll
             for (uint32_t r = 0; r < 4; ++r) {
                 const uint32_t c = r * 4 + static_cast<uint32_t>(lane) / kSlots;
-                if (w0 && c < nc && j < cnt[c]) {
+                if (c < nc && j < cnt[c]) {
                     mk[pre[c] + j] = kk[r];
                     mv[pre[c] + j] = vv[r];
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
         const uint32_t want = (T + kSlots - 1) / kSlots;
         const uint32_t n0 = root ? (T <= kSlots ? 1u : (want > 2u ? want : 2u)) : (want > kHalf ? want : kHalf);
         if (n0 > nc) {  // cannot happen on a tree whose nodes were at least half full
             if (lane == 0) atomicOr(&v.st->rebuild, 1u);
-            __syncthreads();
+            wave_sync();
             continue;
         }
         const uint32_t q = T / n0, r = T % n0;
@@ -1897,13 +1917,14 @@ __device__ __forceinline__ void ph_del_merge(TreeView<K> t, Ins<K> v, bool order
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
 template <class K>
 __global__ __launch_bounds__(64) void k_del_merge(TreeView<K> t, Ins<K> v, bool ordered) {
-    ph_del_merge<K>(t, v, ordered);
+    __shared__ MergeLds<K> sm;
+    ph_del_merge<K>(t, v, ordered, blockIdx.x, gridDim.x, sm);
 }
 
 // One level up: a leaf parent that would fall below half full (fewer than
@@ -2090,34 +2111,64 @@ __global__ __launch_bounds__(256) void k_del_commit(TreeView<K> t, Ins<K> v) {
     ph_del_commit<K, 256>(t, v);
 }
 
-// A batch of one key in one launch: the batch path's phases, one after the
-// other in a single 1024-thread workgroup (a grid of one workgroup runs each
-// phase's loops over one workgroup), so the tree it leaves is the batch
-// path's.  The workgroup's waves share one CU and its L1, so a barrier with
-// its workgroup-scope fences orders the phases' plain loads and stores; the
-// counters raised with atomics are read past the L1 (counter()).  A device-
-// scope fence here would write back and invalidate the L2 at every phase.
+// A batch of at most kDelFusedMax keys in one launch: the batch path's
+// phases, one after the other in a single 1024-thread workgroup (a grid of
+// one workgroup runs each phase's loops over one workgroup), so the tree it
+// leaves is the batch path's.  The batch is ranked in LDS (by key, then by
+// position, the order of the batch path's sort); the parent merges run one
+// per wave, the grandparent merges one after the other on the whole
+// workgroup.  The workgroup's waves share one CU and its L1, so a barrier
+// with its workgroup-scope fences orders the phases' plain loads and stores;
+// the counters raised with atomics are read past the L1 (counter()).  A
+// device-scope fence here would write back and invalidate the L2 at every
+// phase.
 constexpr int kDelOneBlock = 1024;
+constexpr uint32_t kDelFusedMax = 64;
 
 __device__ __forceinline__ void phase_boundary() {
     __syncthreads();
 }
 
 template <class K>
-__global__ __launch_bounds__(kDelOneBlock) void k_del_one(TreeView<K> t, Ins<K> v, const K* __restrict__ keys,
-                                                          uint8_t* __restrict__ status, uint32_t* host_flag) {
+__global__ __launch_bounds__(kDelOneBlock) void k_del_small(TreeView<K> t, Ins<K> v, const K* __restrict__ keys,
+                                                            uint32_t B, uint8_t* __restrict__ status,
+                                                            uint32_t* host_flag) {
+    __shared__ K s_rk[kDelFusedMax];
+    __shared__ K s_sk[kDelFusedMax];
+    __shared__ uint32_t s_si[kDelFusedMax];
+    __shared__ uint32_t sh[33];
+    __shared__ MergeLds<K> s_merge[kDelOneBlock / 64];
     const uint32_t tid = threadIdx.x;
     uint32_t* st = reinterpret_cast<uint32_t*>(v.st);
     for (uint32_t i = tid; i < sizeof(InsState) / 4; i += kDelOneBlock) st[i] = 0;
+    if (tid < B) s_rk[tid] = keys[tid];
     phase_boundary();
-    // the sort and the distinct keys of a one-key batch
+    // each key's stable rank in the batch
+    if (tid < B) {
+        const K k0 = s_rk[tid];
+        uint32_t c = 0;
+        for (uint32_t j = 0; j < B; ++j) c += (s_rk[j] < k0 || (s_rk[j] == k0 && j < tid)) ? 1u : 0u;
+        s_sk[c] = k0;
+        s_si[c] = tid;
+    }
+    phase_boundary();
+    // the distinct keys; a repeat reports ABSENT (an earlier occurrence
+    // deletes the key)
+    const bool in = tid < B;
+    const bool head = in && (tid == 0 || s_sk[tid] != s_sk[tid - 1]);
+    if (in) {
+        v.sk[tid] = s_sk[tid];
+        v.si[tid] = s_si[tid];  // locate writes each distinct key's status through it
+        if (!head) status[s_si[tid]] = 0;
+    }
+    uint32_t U;
+    const uint32_t pos = block_excl_scan<uint32_t>(head ? 1u : 0u, sh, &U);
+    if (head) {
+        v.uk[pos] = s_sk[tid];
+        v.upos[pos] = tid;
+    }
     if (tid == 0) {
-        const K k = keys[0];
-        v.sk[0] = k;
-        v.si[0] = 0;
-        v.uk[0] = k;
-        v.upos[0] = 0;
-        v.st->U = 1;
+        v.st->U = U;
         v.st->height = t.hdr->height;
     }
     phase_boundary();
@@ -2127,7 +2178,7 @@ __global__ __launch_bounds__(kDelOneBlock) void k_del_one(TreeView<K> t, Ins<K> 
     phase_boundary();
     ph_del_list<K>(t, v);
     phase_boundary();
-    ph_del_merge<K>(t, v, false);
+    ph_del_merge<K>(t, v, false, tid / 64, kDelOneBlock / 64, s_merge[tid / 64]);
     phase_boundary();
     ph_del_merge2<K>(t, v);
     phase_boundary();
@@ -2138,9 +2189,9 @@ __global__ __launch_bounds__(kDelOneBlock) void k_del_one(TreeView<K> t, Ins<K> 
         __hip_atomic_store(host_flag, counter(&v.st->rebuild), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-static std::atomic<int> g_single_key_delete{1};
-int set_single_key_delete(int on) { return g_single_key_delete.exchange(on ? 1 : 0, std::memory_order_relaxed); }
-static bool single_key_delete_on() { return g_single_key_delete.load(std::memory_order_relaxed) != 0; }
+static std::atomic<int> g_one_launch_delete{1};
+int set_one_launch_delete(int on) { return g_one_launch_delete.exchange(on ? 1 : 0, std::memory_order_relaxed); }
+static bool one_launch_delete_on() { return g_one_launch_delete.load(std::memory_order_relaxed) != 0; }
 
 // Copy every pair of the leaves that hold keys (cleared leaves hold none).
 template <class K>
@@ -2165,9 +2216,10 @@ const uint32_t* launch_delete(const TreeView<K>& t, const InsertCtx& c, const K*
     Ins<K> v;
     carve<K>(&v, c.scratch, c.max_batch, c.leaf_cap, c.inner_cap);
     const uint32_t gB = grid_for(B, kBlk);
-    if (B == 1 && single_key_delete_on()) {
+    if (B <= kDelFusedMax && one_launch_delete_on()) {
         const uint32_t lds = MirrorLayout<K>::bytes(mirror_nodes_for_levels(2));
-        hipLaunchKernelGGL(k_del_one<K>, dim3(1), dim3(kDelOneBlock), lds, s, t, v, keys, status, host_flag);
+        hipLaunchKernelGGL(k_del_small<K>, dim3(1), dim3(kDelOneBlock), lds, s, t, v, keys,
+                           static_cast<uint32_t>(B), status, host_flag);
         *flag_on_host = host_flag != nullptr;
         return &v.st->rebuild;
     }
