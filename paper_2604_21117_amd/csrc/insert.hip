@@ -500,20 +500,40 @@ static_assert(kNodeLanes == 16, "a node's lane group is one DPP row (row_lane)")
 
 // Merge-split of the touched leaves: kNodeLanes lanes per leaf, group grp
 // of ngrp.
+// The planned items a rebuild reads: the arrays in device memory, or a copy
+// in LDS that the one-workgroup apply makes of every level's items at its
+// start (the plan wrote them all before; a rebuild only reads them), so
+// that a level's rebuild waits on one round of device memory fewer.
+struct ItemView {
+    const uint32_t* node;
+    const uint32_t* first;
+    const uint32_t* end;
+    const uint32_t* cold;
+    const uint32_t* k;
+    const uint32_t* off;
+    const uint8_t* cs;
+};
+
 template <class K>
-__device__ __forceinline__ void apply_leaves_body(TreeView<K> t, Ins<K> v, uint64_t grp, uint64_t ngrp) {
+__device__ __forceinline__ ItemView items_in(const Ins<K>& v) {
+    return ItemView{v.it_node, v.it_first, v.it_end, v.it_cold, v.it_k, v.it_off, v.it_cs};
+}
+
+template <class K>
+__device__ __forceinline__ void apply_leaves_body(TreeView<K> t, Ins<K> v, uint64_t grp, uint64_t ngrp,
+                                                  const ItemView& iv) {
     const uint32_t ok = v.st->ok;
     const uint64_t T0 = v.st->lvl_count[0];
     if (!ok || T0 == 0) return;
     const int gl = lane_id() % kNodeLanes, gbase = lane_id() - gl;
     const uint32_t alloc = v.st->lvl_alloc[0];
     for (uint64_t it = grp; it < T0; it += ngrp) {
-        const uint32_t leaf = v.it_node[it];
-        const uint32_t first = v.it_first[it];
-        const uint32_t r = v.it_end[it] - first;
-        const uint32_t c = v.it_cold[it];
-        const uint32_t k = v.it_k[it];
-        const uint32_t off = v.it_off[it];
+        const uint32_t leaf = iv.node[it];
+        const uint32_t first = iv.first[it];
+        const uint32_t r = iv.end[it] - first;
+        const uint32_t c = iv.cold[it];
+        const uint32_t k = iv.k[it];
+        const uint32_t off = iv.off[it];
         const uint64_t total = static_cast<uint64_t>(c) + r;
         const uint32_t base_new = alloc + off;
         const K okey = t.lkeys[static_cast<uint64_t>(leaf) * kSlots + gl];
@@ -604,7 +624,8 @@ __device__ __forceinline__ void apply_leaves_body(TreeView<K> t, Ins<K> v, uint6
 // Rebuild the changed parents of level d: kNodeLanes lanes per parent, group
 // grp of ngrp.
 template <class K>
-__device__ __forceinline__ void apply_inner_body(TreeView<K> t, Ins<K> v, int d, uint64_t grp, uint64_t ngrp) {
+__device__ __forceinline__ void apply_inner_body(TreeView<K> t, Ins<K> v, int d, uint64_t grp, uint64_t ngrp,
+                                                 const ItemView& iv) {
     const uint32_t ok = v.st->ok;
     const int h = static_cast<int>(v.st->height);
     const int l = h - 1 - d;
@@ -618,11 +639,11 @@ __device__ __forceinline__ void apply_inner_body(TreeView<K> t, Ins<K> v, int d,
     const int gl = lane_id() % kNodeLanes, gbase = lane_id() - gl;
     const uint32_t lane = static_cast<uint32_t>(gl);  // this lane's old slot
     for (uint64_t j = grp; j < n; j += ngrp) {
-        const uint32_t node = v.it_node[bd + j];
-        const uint32_t first = v.it_first[bd + j], end = v.it_end[bd + j];
-        const uint32_t C = v.it_cold[bd + j];
-        const uint32_t P = v.it_k[bd + j];
-        const uint32_t off = v.it_off[bd + j];
+        const uint32_t node = iv.node[bd + j];
+        const uint32_t first = iv.first[bd + j], end = iv.end[bd + j];
+        const uint32_t C = iv.cold[bd + j];
+        const uint32_t P = iv.k[bd + j];
+        const uint32_t off = iv.off[bd + j];
         const K osep = t.ikeys[static_cast<uint64_t>(node) * kSlots + lane];
         const uint32_t ochild = t.ichild[static_cast<uint64_t>(node) * kSlots + lane];
         // the child items (one per changed child node, so at most kSlots),
@@ -630,9 +651,9 @@ __device__ __forceinline__ void apply_inner_body(TreeView<K> t, Ins<K> v, int d,
         const uint32_t nci = end - first < static_cast<uint32_t>(kNodeLanes) ? end - first : kNodeLanes;
         uint32_t ccs = kNone, cks = 1, cof = 0;
         if (lane < nci) {
-            ccs = v.it_cs[bc + first + lane];
-            cks = v.it_k[bc + first + lane];
-            cof = v.it_off[bc + first + lane];
+            ccs = iv.cs[bc + first + lane];
+            cks = iv.k[bc + first + lane];
+            cof = iv.off[bc + first + lane];
         }
         // per old slot: shift from split children before it, and its own
         // item (lanes past nci hold no item: slot kNone, one piece, so they
@@ -708,12 +729,12 @@ __device__ __forceinline__ void apply_inner_body(TreeView<K> t, Ins<K> v, int d,
 
 template <class K>
 __global__ __launch_bounds__(kBlk) void k_apply_leaves(TreeView<K> t, Ins<K> v) {
-    apply_leaves_body<K>(t, v, gtid() / kNodeLanes, gstride() / kNodeLanes);
+    apply_leaves_body<K>(t, v, gtid() / kNodeLanes, gstride() / kNodeLanes, items_in(v));
 }
 
 template <class K>
 __global__ __launch_bounds__(kBlk) void k_apply_inner(TreeView<K> t, Ins<K> v, int d) {
-    apply_inner_body<K>(t, v, d, gtid() / kNodeLanes, gstride() / kNodeLanes);
+    apply_inner_body<K>(t, v, d, gtid() / kNodeLanes, gstride() / kNodeLanes, items_in(v));
 }
 
 // Root growth: pack the root's pieces into new levels (one workgroup).
@@ -846,14 +867,42 @@ __global__ __launch_bounds__(kTailBlock) void k_plan_tail(TreeView<K> t, Ins<K> 
 constexpr int kFusedBlock = 1024;
 constexpr uint32_t kFusedMax = kFusedBlock / kNodeLanes;  // 64
 
+// every level's items of a batch of at most kFusedMax keys (at most that
+// many runs per level)
+constexpr uint32_t kFusedItems = kFusedMax * kMaxLevels;
+
 template <class K>
 __global__ __launch_bounds__(kFusedBlock) void k_small_apply(TreeView<K> t, Ins<K> v, int H) {
+    __shared__ uint32_t s_node[kFusedItems], s_first[kFusedItems], s_end[kFusedItems];
+    __shared__ uint32_t s_cold[kFusedItems], s_k[kFusedItems], s_off[kFusedItems];
+    __shared__ uint8_t s_cs[kFusedItems];
     const uint64_t grp = threadIdx.x / kNodeLanes, ngrp = kFusedBlock / kNodeLanes;
-    apply_leaves_body<K>(t, v, grp, ngrp);
+    // the planned items of every level, copied once
+    uint32_t total = 0;
+    for (int d = 0; d < H; ++d) {
+        const uint32_t e = v.st->lvl_base[d] + v.st->lvl_count[d];
+        total = e > total ? e : total;
+    }
+    if (total > kFusedItems) {  // cannot happen for at most kFusedMax keys
+        if (threadIdx.x == 0) atomicOr(&t.hdr->error, kErrInternal);
+        return;
+    }
+    for (uint32_t i = threadIdx.x; i < total; i += kFusedBlock) {
+        s_node[i] = v.it_node[i];
+        s_first[i] = v.it_first[i];
+        s_end[i] = v.it_end[i];
+        s_cold[i] = v.it_cold[i];
+        s_k[i] = v.it_k[i];
+        s_off[i] = v.it_off[i];
+        s_cs[i] = v.it_cs[i];
+    }
+    __syncthreads();
+    const ItemView iv{s_node, s_first, s_end, s_cold, s_k, s_off, s_cs};
+    apply_leaves_body<K>(t, v, grp, ngrp, iv);
     __syncthreads();
     for (int d = 1; d < H; ++d) {
         if (v.st->lvl_new[d - 1] == 0) break;  // nothing split below: no level above changes
-        apply_inner_body<K>(t, v, d, grp, ngrp);
+        apply_inner_body<K>(t, v, d, grp, ngrp, iv);
         __syncthreads();
     }
     grow_body<K>(t, v);
@@ -875,7 +924,7 @@ __global__ __launch_bounds__(kFusedBlock) void k_apply_tail(TreeView<K> t, Ins<K
     const uint64_t grp = threadIdx.x / kNodeLanes, ngrp = kFusedBlock / kNodeLanes;
     for (int d = d0; d < H; ++d) {
         if (v.st->lvl_new[d - 1] == 0) break;  // nothing split below: no level above changes
-        apply_inner_body<K>(t, v, d, grp, ngrp);
+        apply_inner_body<K>(t, v, d, grp, ngrp, items_in(v));
         __syncthreads();
     }
     grow_body<K>(t, v);
