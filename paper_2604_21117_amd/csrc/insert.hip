@@ -493,6 +493,29 @@ __device__ __forceinline__ uint32_t lower_bound_dev(const K* a, uint32_t n, K k)
     return lo;
 }
 
+// part_start and part_of for the splits the rebuilds make: below 2^16
+// entries every product j * total fits in 32 bits, and a 32-bit division is
+// a few instructions where a 64-bit one is a long sequence (a rebuild makes
+// several per entry).  Same results; larger counts take the 64-bit forms.
+__device__ __forceinline__ uint32_t pstart(uint64_t j, uint64_t total, uint64_t parts) {
+    if (total < (1u << 16)) {
+        return static_cast<uint32_t>(j) * static_cast<uint32_t>(total) / static_cast<uint32_t>(parts);
+    }
+    return static_cast<uint32_t>(part_start(j, total, parts));
+}
+
+__device__ __forceinline__ uint32_t ppart(uint64_t pos, uint64_t total, uint64_t parts) {
+    if (total < (1u << 16)) {
+        const uint32_t p = static_cast<uint32_t>(pos), t = static_cast<uint32_t>(total),
+                       n = static_cast<uint32_t>(parts);
+        uint32_t j = p * n / t;
+        while (j + 1 < n && (j + 1) * t / n <= p) ++j;
+        while (j > 0 && j * t / n > p) --j;
+        return j;
+    }
+    return static_cast<uint32_t>(part_of(pos, total, parts));
+}
+
 // Lanes that rebuild one node (a leaf or an inner node): one per slot, four
 // nodes per wave, so a wave keeps four nodes' reads in flight.
 constexpr int kNodeLanes = 16;
@@ -534,7 +557,7 @@ __device__ __forceinline__ void apply_leaves_body(TreeView<K> t, Ins<K> v, uint6
         const uint32_t c = iv.cold[it];
         const uint32_t k = iv.k[it];
         const uint32_t off = iv.off[it];
-        const uint64_t total = static_cast<uint64_t>(c) + r;
+        const uint32_t total = c + r;  // r is at most the batch size
         const uint32_t base_new = alloc + off;
         const K okey = t.lkeys[static_cast<uint64_t>(leaf) * kSlots + gl];
         const K oval = t.lvals[static_cast<uint64_t>(leaf) * kSlots + gl];
@@ -545,10 +568,10 @@ __device__ __forceinline__ void apply_leaves_body(TreeView<K> t, Ins<K> v, uint6
         // one run of new keys (the common case): each lane holds at most one
         // old and one new element, and the group pads the pieces together
         const bool one_run = r <= static_cast<uint32_t>(kNodeLanes);
-        auto place = [&](uint64_t pos, K key, K val) {
-            const uint64_t j = part_of(pos, total, k);
-            const uint64_t s0 = part_start(j, total, k), s1 = part_start(j + 1, total, k);
-            const uint64_t slot = pos - s0;
+        auto place = [&](uint32_t pos, K key, K val) {
+            const uint32_t j = ppart(pos, total, k);
+            const uint32_t s0 = pstart(j, total, k), s1 = pstart(j + 1, total, k);
+            const uint32_t slot = pos - s0;
             const uint64_t dest = j == 0 ? leaf : base_new + j - 1;
             t.lkeys[dest * kSlots + slot] = key;
             t.lvals[dest * kSlots + slot] = val;
@@ -603,7 +626,7 @@ __device__ __forceinline__ void apply_leaves_body(TreeView<K> t, Ins<K> v, uint6
             // value: the piece's last element sits on one lane, as an old or
             // a new element; lanes past the count write one slot each
             for (uint32_t j = 0; j < k; ++j) {
-                const uint64_t s0 = part_start(j, total, k), s1 = part_start(j + 1, total, k);
+                const uint64_t s0 = pstart(j, total, k), s1 = pstart(j + 1, total, k);
                 const uint32_t cnt = static_cast<uint32_t>(s1 - s0);
                 if (cnt >= static_cast<uint32_t>(kSlots)) continue;
                 const uint64_t mo = group_bits<kNodeLanes>(__ballot(opos == s1 - 1), gbase);
@@ -659,7 +682,7 @@ __device__ __forceinline__ void apply_inner_body(TreeView<K> t, Ins<K> v, int d,
         // item (lanes past nci hold no item: slot kNone, one piece, so they
         // add nothing; the moves are row broadcasts)
         uint32_t shift = 0, myk = 1, myoff = 0;
-        uint64_t a = 0;
+        uint32_t a = 0;  // below 2^21: at most 16 children of at most 2^17 pieces
         static_for<0, kNodeLanes>([&](auto S) {
             constexpr int i = decltype(S)::value;
             const uint32_t cs = row_lane<i>(ccs), ki = row_lane<i>(cks), oi = row_lane<i>(cof);
@@ -670,10 +693,10 @@ __device__ __forceinline__ void apply_inner_body(TreeView<K> t, Ins<K> v, int d,
         __threadfence_block();  // the old node is in registers before any write
         if (a == 0) continue;   // no child split: the parent is unchanged
         const uint32_t newpos = lane + shift;
-        const uint64_t Cp = C + a;
+        const uint32_t Cp = C + a;
         const uint32_t base_new = alloc + off;
-        for (uint64_t e0 = 0; e0 < Cp; e0 += kNodeLanes) {
-            const uint64_t e = e0 + lane;
+        for (uint32_t e0 = 0; e0 < Cp; e0 += kNodeLanes) {
+            const uint32_t e = e0 + lane;
             const bool act = e < Cp;
             // old slot whose entries cover e: the last slot with newpos <= e
             uint32_t sf = 0;
@@ -688,7 +711,7 @@ __device__ __forceinline__ void apply_inner_body(TreeView<K> t, Ins<K> v, int d,
             const uint32_t ko = shfl_u32(myoff, src);
             const K os = __shfl(osep, src, 64);
             const uint32_t oc = shfl_u32(ochild, src);
-            const uint64_t jj = e - np;
+            const uint32_t jj = e - np;
             const K last_sep = (sf + 1 < C) ? os : kmax<K>();
             K sep;
             uint32_t ch;
@@ -699,29 +722,29 @@ __device__ __forceinline__ void apply_inner_body(TreeView<K> t, Ins<K> v, int d,
                 sep = (jj + 1 < ks) ? v.psep[psep_c + ko + jj] : last_sep;
                 if (jj == 0) ch = oc;
                 else {
-                    const uint32_t id = alloc_c + ko + static_cast<uint32_t>(jj) - 1;
+                    const uint32_t id = alloc_c + ko + jj - 1;
                     ch = child_leaf ? (kLeafTag | id) : id;
                 }
             }
             if (act) {
-                const uint64_t pj = part_of(e, Cp, P);
-                const uint64_t s0 = part_start(pj, Cp, P), s1 = part_start(pj + 1, Cp, P);
-                const uint64_t slot = e - s0;
-                const uint64_t cnt = s1 - s0;
-                const uint64_t dest = pj == 0 ? node : base_new + pj - 1;
-                t.ikeys[dest * kSlots + slot] = (slot + 1 < cnt) ? sep : kmax<K>();
-                t.ichild[dest * kSlots + slot] = ch;
+                const uint32_t pj = ppart(e, Cp, P);
+                const uint32_t s0 = pstart(pj, Cp, P), s1 = pstart(pj + 1, Cp, P);
+                const uint32_t slot = e - s0;
+                const uint32_t cnt = s1 - s0;
+                const uint32_t dest = pj == 0 ? node : base_new + pj - 1;
+                t.ikeys[static_cast<uint64_t>(dest) * kSlots + slot] = (slot + 1 < cnt) ? sep : kmax<K>();
+                t.ichild[static_cast<uint64_t>(dest) * kSlots + slot] = ch;
                 if (e + 1 == s1 && pj + 1 < P) v.psep[psep_d + off + pj] = sep;
             }
         }
         // slots past a piece's count: the largest key and no child, one slot
         // per lane
         for (uint32_t pj = 0; pj < P; ++pj) {
-            const uint64_t cnt = part_start(pj + 1, Cp, P) - part_start(pj, Cp, P);
-            const uint64_t dest = pj == 0 ? node : base_new + pj - 1;
+            const uint32_t cnt = pstart(pj + 1, Cp, P) - pstart(pj, Cp, P);
+            const uint32_t dest = pj == 0 ? node : base_new + pj - 1;
             if (lane >= cnt) {
-                t.ikeys[dest * kSlots + lane] = kmax<K>();
-                t.ichild[dest * kSlots + lane] = kNone;
+                t.ikeys[static_cast<uint64_t>(dest) * kSlots + lane] = kmax<K>();
+                t.ichild[static_cast<uint64_t>(dest) * kSlots + lane] = kNone;
             }
         }
     }
@@ -860,6 +883,15 @@ __global__ __launch_bounds__(kTailBlock) void k_plan_tail(TreeView<K> t, Ins<K> 
     }
 }
 
+// The batch state into LDS, by the workgroup (the caller waits at a barrier
+// before reading it).
+__device__ __forceinline__ void copy_state(InsState* dst, const InsState* src) {
+    static_assert(sizeof(InsState) % 4 == 0, "the state copies as words");
+    uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
+    for (uint32_t i = threadIdx.x; i < sizeof(InsState) / 4; i += blockDim.x) d[i] = s[i];
+}
+
 // Everything after the plan for a batch of at most kFusedMax keys, in one
 // workgroup: every level has at most that many touched nodes, one round of
 // kNodeLanes-lane groups, and barriers stand where the general path has
@@ -871,23 +903,30 @@ constexpr uint32_t kFusedMax = kFusedBlock / kNodeLanes;  // 64
 // many runs per level)
 constexpr uint32_t kFusedItems = kFusedMax * kMaxLevels;
 
+// Besides the items, two things stay on the chip, so that a level waits on
+// fewer rounds of device memory:
+//  - the batch state (per-level counts, bases, allocation cursors), which the
+//    rebuilds only read: from device memory each level would wait on its
+//    fields one read after another;
+//  - the separators a level's splits produce (read by the level above and by
+//    the root growth): a level adds at most one piece per new key below it,
+//    so a batch of at most kFusedMax keys makes at most kFusedItems of them.
 template <class K>
-__global__ __launch_bounds__(kFusedBlock) void k_small_apply(TreeView<K> t, Ins<K> v, int H) {
+__global__ __launch_bounds__(kFusedBlock) void k_small_apply(TreeView<K> t, Ins<K> v0, int H) {
     __shared__ uint32_t s_node[kFusedItems], s_first[kFusedItems], s_end[kFusedItems];
     __shared__ uint32_t s_cold[kFusedItems], s_k[kFusedItems], s_off[kFusedItems];
     __shared__ uint8_t s_cs[kFusedItems];
+    __shared__ K s_psep[kFusedItems];
+    __shared__ InsState s_st;
     const uint64_t grp = threadIdx.x / kNodeLanes, ngrp = kFusedBlock / kNodeLanes;
-    // the planned items of every level, copied once
-    uint32_t total = 0;
-    for (int d = 0; d < H; ++d) {
-        const uint32_t e = v.st->lvl_base[d] + v.st->lvl_count[d];
-        total = e > total ? e : total;
-    }
-    if (total > kFusedItems) {  // cannot happen for at most kFusedMax keys
-        if (threadIdx.x == 0) atomicOr(&t.hdr->error, kErrInternal);
-        return;
-    }
-    for (uint32_t i = threadIdx.x; i < total; i += kFusedBlock) {
+    Ins<K> v = v0;
+    v.psep = s_psep;
+    copy_state(&s_st, v.st);
+    // the planned items of every level, copied once: every slot the plan
+    // may have written, so that the copy need not wait for the level counts
+    // (it and the state arrive in one round of reads)
+    const uint32_t span = v.ip_cap < kFusedItems ? static_cast<uint32_t>(v.ip_cap) : kFusedItems;
+    for (uint32_t i = threadIdx.x; i < span; i += kFusedBlock) {
         s_node[i] = v.it_node[i];
         s_first[i] = v.it_first[i];
         s_end[i] = v.it_end[i];
@@ -897,12 +936,24 @@ __global__ __launch_bounds__(kFusedBlock) void k_small_apply(TreeView<K> t, Ins<
         s_cs[i] = v.it_cs[i];
     }
     __syncthreads();
+    uint32_t total = 0, pieces = 0;
+    for (int d = 0; d < H; ++d) {
+        const uint32_t e = s_st.lvl_base[d] + s_st.lvl_count[d];
+        total = e > total ? e : total;
+        pieces += s_st.lvl_new[d];
+    }
+    if (total > span || pieces > kFusedItems) {  // cannot happen for at most kFusedMax keys
+        if (threadIdx.x == 0) atomicOr(&t.hdr->error, kErrInternal);
+        return;
+    }
     const ItemView iv{s_node, s_first, s_end, s_cold, s_k, s_off, s_cs};
-    apply_leaves_body<K>(t, v, grp, ngrp, iv);
+    Ins<K> vr = v;  // the rebuilds read the state's copy
+    vr.st = &s_st;
+    apply_leaves_body<K>(t, vr, grp, ngrp, iv);
     __syncthreads();
     for (int d = 1; d < H; ++d) {
-        if (v.st->lvl_new[d - 1] == 0) break;  // nothing split below: no level above changes
-        apply_inner_body<K>(t, v, d, grp, ngrp, iv);
+        if (s_st.lvl_new[d - 1] == 0) break;  // nothing split below: no level above changes
+        apply_inner_body<K>(t, vr, d, grp, ngrp, iv);
         __syncthreads();
     }
     grow_body<K>(t, v);
@@ -921,10 +972,15 @@ constexpr uint32_t kTailApplyMax = kFusedMax;
 
 template <class K>
 __global__ __launch_bounds__(kFusedBlock) void k_apply_tail(TreeView<K> t, Ins<K> v, int d0, int H) {
+    __shared__ InsState s_st;
     const uint64_t grp = threadIdx.x / kNodeLanes, ngrp = kFusedBlock / kNodeLanes;
+    copy_state(&s_st, v.st);
+    __syncthreads();
+    Ins<K> vr = v;  // the rebuilds read the state's copy
+    vr.st = &s_st;
     for (int d = d0; d < H; ++d) {
-        if (v.st->lvl_new[d - 1] == 0) break;  // nothing split below: no level above changes
-        apply_inner_body<K>(t, v, d, grp, ngrp, items_in(v));
+        if (s_st.lvl_new[d - 1] == 0) break;  // nothing split below: no level above changes
+        apply_inner_body<K>(t, vr, d, grp, ngrp, items_in(v));
         __syncthreads();
     }
     grow_body<K>(t, v);
