@@ -883,8 +883,8 @@ __global__ __launch_bounds__(kTailBlock) void k_plan_tail(TreeView<K> t, Ins<K> 
     }
 }
 
-// The batch state into LDS, by the workgroup (the caller waits at a barrier
-// before reading it).
+// The batch state from device memory into LDS or back, by the workgroup (a
+// barrier separates the copy from reads of its destination).
 __device__ __forceinline__ void copy_state(InsState* dst, const InsState* src) {
     static_assert(sizeof(InsState) % 4 == 0, "the state copies as words");
     uint32_t* d = reinterpret_cast<uint32_t*>(dst);
@@ -1348,9 +1348,12 @@ __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int 
     __shared__ uint8_t s_C[kL * kCap];         // old entry count of every item
     __shared__ uint32_t s_base[kL + 1];        // first item of each level
     __shared__ uint32_t s_over;
+    __shared__ InsState s_st;  // the batch state, written back at the end
     const uint32_t tid = threadIdx.x;
-    const uint32_t U = v.st->U;
-    const int h = static_cast<int>(v.st->height);
+    copy_state(&s_st, v.st);
+    __syncthreads();
+    const uint32_t U = s_st.U;
+    const int h = static_cast<int>(s_st.height);
     const int hmax = H < h ? H : h;
     if (tid == 0) s_over = 0;
 
@@ -1498,26 +1501,42 @@ __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int 
         }
         if (tid == 0) {
             s_k[nd] = nnew;
-            v.st->lvl_count[d] = nd;
-            v.st->lvl_base[d] = bd;
-            v.st->lvl_new[d] = nnew;
-            v.st->lvl_psep[d] = psep;
+            s_st.lvl_count[d] = nd;
+            s_st.lvl_base[d] = bd;
+            s_st.lvl_new[d] = nnew;
+            s_st.lvl_psep[d] = psep;
         }
         psep += nnew;
         __syncthreads();
     }
     if (tid == 0) {
-        v.st->R = R;
-        if (s_over) v.st->overflow = 1;
+        s_st.R = R;
+        if (s_over) s_st.overflow = 1;
     }
     __syncthreads();
-    ph_check<K>(t, v, tid, NT);
+    // the check reads the level counters one after another: from LDS
+    Ins<K> vs = v;
+    vs.st = &s_st;
+    ph_check<K>(t, vs, tid, NT);
     __syncthreads();
+    copy_state(v.st, &s_st);
     // values of keys already present (the batch passed the capacity check;
     // the leaf rewrites that follow read these values)
-    if (v.st->ok) {
-        for (uint32_t u = tid; u < U; u += NT)
-            if (v.ufound[u]) t.lvals[static_cast<uint64_t>(v.uleaf[u]) * kSlots + v.uslot[u]] = v.uv[u];
+    // (at most 2 NT distinct keys: each thread's two are read before either
+    // is written, so the reads take one round)
+    if (s_st.ok) {
+        uint32_t found[2], leaf[2], slot[2];
+        K val[2];
+        for (int j = 0; j < 2; ++j) {
+            const uint32_t u = tid + j * NT;
+            const bool in = u < U;
+            found[j] = in ? v.ufound[u] : 0u;
+            leaf[j] = in ? v.uleaf[u] : 0u;
+            slot[j] = in ? v.uslot[u] : 0u;
+            val[j] = in ? v.uv[u] : K(0);
+        }
+        for (int j = 0; j < 2; ++j)
+            if (found[j]) t.lvals[static_cast<uint64_t>(leaf[j]) * kSlots + slot[j]] = val[j];
     }
 }
 
