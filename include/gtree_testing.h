@@ -45,6 +45,17 @@ uint32_t gt_set_sort_spin_limit(uint32_t limit);
 int gt_set_single_key_insert(int enable);
 
 /*
+ * Testing switch of the one-launch insert: a batch of 2 to 64 keys runs in
+ * one launch (the small-batch path's phases in one workgroup: ranking and
+ * deduplication, locate, plan, leaf and parent rebuilds, root growth, commit
+ * and mirror) instead of that path's four kernels, with the same resulting
+ * tree and statuses.  enable = 0 sends such batches through the four
+ * kernels; any other value restores the default (on).  Process-wide, read
+ * when an insert is launched.  Returns the previous setting (1 on, 0 off).
+ */
+int gt_set_one_launch_insert(int enable);
+
+/*
  * Testing switch of the one-launch delete: a batch of at most 64 keys runs
  * in one launch (the batch path's phases in one workgroup: ranking and
  * deduplication, locate, leaf removal, the parent and grandparent merges,

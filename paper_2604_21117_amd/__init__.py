@@ -120,6 +120,8 @@ def lib():
         L.gt_set_sort_spin_limit.restype = u32
         L.gt_set_single_key_insert.argtypes = [C.c_int]
         L.gt_set_single_key_insert.restype = C.c_int
+        L.gt_set_one_launch_insert.argtypes = [C.c_int]
+        L.gt_set_one_launch_insert.restype = C.c_int
         L.gt_set_one_launch_delete.argtypes = [C.c_int]
         L.gt_set_one_launch_delete.restype = C.c_int
         L.li_arena_bytes.argtypes = [vp, C.POINTER(gt_li_params)]
@@ -287,6 +289,13 @@ def set_single_key_insert(enable: bool) -> bool:
     the default) or through the batch path (False); returns the previous
     setting."""
     return bool(lib().gt_set_single_key_insert(1 if enable else 0))
+
+
+def set_one_launch_insert(enable: bool) -> bool:
+    """Testing switch: an insert batch of 2 to 64 keys runs in one launch
+    (True, the default) or through the small-batch path's four kernels
+    (False); returns the previous setting."""
+    return bool(lib().gt_set_one_launch_insert(1 if enable else 0))
 
 
 def set_one_launch_delete(enable: bool) -> bool:

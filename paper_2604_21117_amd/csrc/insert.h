@@ -20,9 +20,10 @@ struct InsertCtx {
 // node pools of the given capacities.
 uint64_t insert_scratch_bytes(uint64_t max_batch, int key_bytes, uint64_t leaf_cap, uint64_t inner_cap);
 
-// Testing switches of the one-key insert kernel and the one-launch delete of
-// small batches; each returns the previous setting.
+// Testing switches of the one-key insert kernel and the one-launch insert
+// and delete of small batches; each returns the previous setting.
 int set_single_key_insert(int on);
+int set_one_launch_insert(int on);
 int set_one_launch_delete(int on);
 
 template <class K>

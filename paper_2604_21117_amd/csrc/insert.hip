@@ -883,13 +883,21 @@ __global__ __launch_bounds__(kTailBlock) void k_plan_tail(TreeView<K> t, Ins<K> 
     }
 }
 
-// The batch state from device memory into LDS or back, by the workgroup (a
-// barrier separates the copy from reads of its destination).
-__device__ __forceinline__ void copy_state(InsState* dst, const InsState* src) {
+// The batch state from device memory into LDS or back, by threads tid of nth
+// (a barrier separates the copy from reads of its destination).
+__device__ __forceinline__ void copy_state(InsState* dst, const InsState* src, uint32_t tid, uint32_t nth) {
     static_assert(sizeof(InsState) % 4 == 0, "the state copies as words");
     uint32_t* d = reinterpret_cast<uint32_t*>(dst);
     const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
-    for (uint32_t i = threadIdx.x; i < sizeof(InsState) / 4; i += blockDim.x) d[i] = s[i];
+    for (uint32_t i = tid; i < sizeof(InsState) / 4; i += nth) d[i] = s[i];
+}
+
+// Orders one wave's LDS accesses around a point (a workgroup barrier where
+// the wave works alone).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Everything after the plan for a batch of at most kFusedMax keys, in one
@@ -912,7 +920,7 @@ constexpr uint32_t kFusedItems = kFusedMax * kMaxLevels;
 //    the root growth): a level adds at most one piece per new key below it,
 //    so a batch of at most kFusedMax keys makes at most kFusedItems of them.
 template <class K>
-__global__ __launch_bounds__(kFusedBlock) void k_small_apply(TreeView<K> t, Ins<K> v0, int H) {
+__device__ __forceinline__ void ph_small_apply(TreeView<K> t, Ins<K> v0, int H) {
     __shared__ uint32_t s_node[kFusedItems], s_first[kFusedItems], s_end[kFusedItems];
     __shared__ uint32_t s_cold[kFusedItems], s_k[kFusedItems], s_off[kFusedItems];
     __shared__ uint8_t s_cs[kFusedItems];
@@ -921,7 +929,7 @@ __global__ __launch_bounds__(kFusedBlock) void k_small_apply(TreeView<K> t, Ins<
     const uint64_t grp = threadIdx.x / kNodeLanes, ngrp = kFusedBlock / kNodeLanes;
     Ins<K> v = v0;
     v.psep = s_psep;
-    copy_state(&s_st, v.st);
+    copy_state(&s_st, v.st, threadIdx.x, blockDim.x);
     // the planned items of every level, copied once: every slot the plan
     // may have written, so that the copy need not wait for the level counts
     // (it and the state arrive in one round of reads)
@@ -963,6 +971,11 @@ __global__ __launch_bounds__(kFusedBlock) void k_small_apply(TreeView<K> t, Ins<
     if (v.st->mirror_dirty) mirror_refresh_body<K, kFusedBlock>(t);
 }
 
+template <class K>
+__global__ __launch_bounds__(kFusedBlock) void k_small_apply(TreeView<K> t, Ins<K> v, int H) {
+    ph_small_apply<K>(t, v, H);
+}
+
 // The parent levels from d0 on, the root growth, the commit and the mirror
 // in one workgroup: the host starts it at the first level whose item bound
 // is at most kTailApplyMax, one round of kNodeLanes-lane groups, so the
@@ -974,7 +987,7 @@ template <class K>
 __global__ __launch_bounds__(kFusedBlock) void k_apply_tail(TreeView<K> t, Ins<K> v, int d0, int H) {
     __shared__ InsState s_st;
     const uint64_t grp = threadIdx.x / kNodeLanes, ngrp = kFusedBlock / kNodeLanes;
-    copy_state(&s_st, v.st);
+    copy_state(&s_st, v.st, threadIdx.x, blockDim.x);
     __syncthreads();
     Ins<K> vr = v;  // the rebuilds read the state's copy
     vr.st = &s_st;
@@ -1321,6 +1334,14 @@ __device__ __forceinline__ uint32_t plan_scan(uint32_t x, uint32_t* sh, uint32_t
     }
 }
 
+// The plan's barrier: its workgroup's, or its wave's where one wave of a
+// larger workgroup plans alone (threads 0 .. 63, NT = 64).
+template <bool WAVE>
+__device__ __forceinline__ void plan_sync() {
+    if constexpr (WAVE) wave_sync();
+    else __syncthreads();
+}
+
 // Plan of a small batch, one workgroup of NT threads (NT >= B / 2); thread t
 // owns new keys 2t and 2t+1.  Small NT keeps the barriers cheap (one wave
 // for B <= 128), and the level loops stay rolled so that the kernel's code
@@ -1337,8 +1358,9 @@ __device__ __forceinline__ uint32_t plan_scan(uint32_t x, uint32_t* sh, uint32_t
 // level's piece-offset prefix taken by the run's first and last keys.  Writes
 // the same item arrays and level counters as the general path, and then the
 // values of keys already present.
-template <class K, int NT>
-__global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int H) {
+template <class K, int NT, bool WAVE>
+__device__ __forceinline__ void ph_small_plan(TreeView<K> t, Ins<K> v, int H) {
+    static_assert(!WAVE || NT == 64, "a plan by one wave has 64 threads");
     constexpr int kL = kMaxLevels;
     constexpr uint32_t kCap = 2 * NT;  // new keys, items per level
     __shared__ uint32_t sh[33];
@@ -1350,8 +1372,8 @@ __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int 
     __shared__ uint32_t s_over;
     __shared__ InsState s_st;  // the batch state, written back at the end
     const uint32_t tid = threadIdx.x;
-    copy_state(&s_st, v.st);
-    __syncthreads();
+    copy_state(&s_st, v.st, tid, NT);
+    plan_sync<WAVE>();
     const uint32_t U = s_st.U;
     const int h = static_cast<int>(s_st.height);
     const int hmax = H < h ? H : h;
@@ -1376,7 +1398,7 @@ __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int 
         s_a[r] = u;
         s_b[r] = leaf;
     }
-    __syncthreads();
+    plan_sync<WAVE>();
     bool valid[2];
     // per key and level: node, its old entry count and its slot in its
     // parent (all recorded by locate), the next level's loaded one level ahead
@@ -1402,7 +1424,7 @@ __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int 
                 cs[j] = pix[j];
                 if (valid[j]) s_b[2 * tid + j] = node[j];
             }
-            __syncthreads();
+            plan_sync<WAVE>();
         }
         // the next level's records, in flight through this level
         if (d + 1 < hmax)
@@ -1444,10 +1466,10 @@ __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int 
         }
         if (tid == 0) s_base[d] = items;
         items += n;
-        __syncthreads();  // s_b is rewritten by the next level
+        plan_sync<WAVE>();  // s_b is rewritten by the next level
     }
     if (tid == 0) s_base[hmax] = items;
-    __syncthreads();
+    plan_sync<WAVE>();
 
     const uint32_t total = items < v.ip_cap ? items : static_cast<uint32_t>(v.ip_cap);
 
@@ -1477,7 +1499,7 @@ __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int 
             if ((lbits >> (2 * d + j)) & 1u) s_b[ixd[j]] = e[j];
             below[j] = ixd[j];
         }
-        __syncthreads();
+        plan_sync<WAVE>();
         uint32_t kk[2], f[2];
         for (int i = 0; i < 2; ++i) {
             const uint32_t jt = 2 * tid + i;
@@ -1507,19 +1529,19 @@ __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int 
             s_st.lvl_psep[d] = psep;
         }
         psep += nnew;
-        __syncthreads();
+        plan_sync<WAVE>();
     }
     if (tid == 0) {
         s_st.R = R;
         if (s_over) s_st.overflow = 1;
     }
-    __syncthreads();
+    plan_sync<WAVE>();
     // the check reads the level counters one after another: from LDS
     Ins<K> vs = v;
     vs.st = &s_st;
     ph_check<K>(t, vs, tid, NT);
-    __syncthreads();
-    copy_state(v.st, &s_st);
+    plan_sync<WAVE>();
+    copy_state(v.st, &s_st, tid, NT);
     // values of keys already present (the batch passed the capacity check;
     // the leaf rewrites that follow read these values)
     // (at most 2 NT distinct keys: each thread's two are read before either
@@ -1539,6 +1561,72 @@ __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int 
             if (found[j]) t.lvals[static_cast<uint64_t>(leaf[j]) * kSlots + slot[j]] = val[j];
     }
 }
+
+template <class K, int NT>
+__global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int H) {
+    ph_small_plan<K, NT, false>(t, v, H);
+}
+
+// A batch of at most kFusedMax keys in one launch: the small path's kernels
+// (rank and distinct keys, locate, plan, apply) as phases of one
+// kFusedBlock-thread workgroup, with barriers where the small path has
+// kernel boundaries.  The batch is ranked in LDS (by key, then by position,
+// as the small path ranks it) and one wave plans it (the small path plans up
+// to 128 keys with one wave), so the tree it leaves is the small path's.
+template <class K>
+__global__ __launch_bounds__(kFusedBlock) void k_ins_small(TreeView<K> t, Ins<K> v, const K* __restrict__ keys,
+                                                           const K* __restrict__ vals, uint32_t B,
+                                                           uint8_t* __restrict__ status, int H) {
+    __shared__ K s_rk[kFusedMax];
+    __shared__ K s_sk[kFusedMax];
+    __shared__ uint32_t s_si[kFusedMax];
+    __shared__ uint32_t sh[33];
+    const uint32_t tid = threadIdx.x;
+    uint32_t* st = reinterpret_cast<uint32_t*>(v.st);
+    for (uint32_t i = tid; i < sizeof(InsState) / 4; i += kFusedBlock) st[i] = 0;
+    if (tid < B) s_rk[tid] = keys[tid];
+    __syncthreads();
+    // each key's stable rank in the batch
+    if (tid < B) {
+        const K k0 = s_rk[tid];
+        uint32_t c = 0;
+        for (uint32_t j = 0; j < B; ++j) c += (s_rk[j] < k0 || (s_rk[j] == k0 && j < tid)) ? 1u : 0u;
+        s_sk[c] = k0;
+        s_si[c] = tid;
+    }
+    __syncthreads();
+    // the distinct keys, each with the value of its last occurrence; a
+    // repeat reports UPDATED (an earlier occurrence inserts the key)
+    const bool in = tid < B;
+    const bool head = in && (tid == 0 || s_sk[tid] != s_sk[tid - 1]);
+    const bool last = in && (tid + 1 == B || s_sk[tid + 1] != s_sk[tid]);
+    if (in) {
+        v.sk[tid] = s_sk[tid];
+        v.si[tid] = s_si[tid];  // locate writes each distinct key's status through it
+        if (!head) status[s_si[tid]] = 1;
+    }
+    uint32_t U;
+    const uint32_t pos = block_excl_scan<uint32_t>(head ? 1u : 0u, sh, &U);
+    if (head) {
+        v.uk[pos] = s_sk[tid];
+        v.upos[pos] = tid;
+    }
+    if (last) v.uv[pos + (head ? 1u : 0u) - 1u] = vals[s_si[tid]];
+    if (tid == 0) {
+        v.st->U = U;
+        v.st->height = t.hdr->height;
+    }
+    __syncthreads();
+    ph_locate<K, 16, 1, 2, kFusedBlock>(t, v, status);
+    __syncthreads();
+    if (tid < 64) ph_small_plan<K, 64, true>(t, v, H);
+    __syncthreads();
+    ph_small_apply<K>(t, v, H);
+}
+
+static std::atomic<int> g_one_launch_insert{1};
+int set_one_launch_insert(int on) { return g_one_launch_insert.exchange(on ? 1 : 0, std::memory_order_relaxed); }
+static bool one_launch_insert_on() { return g_one_launch_insert.load(std::memory_order_relaxed) != 0; }
 
 // ------------------------------------------------------------------ launch
 
@@ -1616,6 +1704,12 @@ void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, cons
 
     if (B == 1 && single_key_insert_on()) {
         hipLaunchKernelGGL(k_insert_one<K>, dim3(1), dim3(kOneBlock), 0, s, t, keys, vals, status);
+        return;
+    }
+    if (B <= kFusedMax && one_launch_insert_on()) {
+        const uint32_t lds = MirrorLayout<K>::bytes(mirror_nodes_for_levels(2));
+        hipLaunchKernelGGL(k_ins_small<K>, dim3(1), dim3(kFusedBlock), lds, s, t, v, keys, vals,
+                           static_cast<uint32_t>(B), status, H);
         return;
     }
     if (B <= kSmallInsert) {
@@ -1885,12 +1979,6 @@ struct MergeLds {
 
 // Orders a wave's LDS writes before its lanes' later reads (a wave-level
 // barrier: the body runs in one wave).
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // One wave per listed parent: wave w of nw takes list entries w, w + nw, ...
 // with its own LDS slice (the batch kernel: one wave per workgroup; the
 // one-launch delete: the waves of its workgroup).

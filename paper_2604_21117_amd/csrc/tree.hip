@@ -297,6 +297,7 @@ const char* gt_status_str(gt_status s) {
 
 uint32_t gt_set_sort_spin_limit(uint32_t limit) { return set_sort_spin_limit(limit); }
 int gt_set_single_key_insert(int enable) { return set_single_key_insert(enable); }
+int gt_set_one_launch_insert(int enable) { return set_one_launch_insert(enable); }
 int gt_set_one_launch_delete(int enable) { return set_one_launch_delete(enable); }
 
 uint64_t tree_arena_bytes(const gt_params* p, uint64_t n, uint64_t leaf_slack) {
