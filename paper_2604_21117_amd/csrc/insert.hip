@@ -1334,6 +1334,17 @@ __device__ __forceinline__ uint32_t plan_scan(uint32_t x, uint32_t* sh, uint32_t
     }
 }
 
+// Locate's records of a batch of at most kFusedMax distinct keys, by tree
+// level l (0 = the leaves' parents) and key: the parent, its entry count
+// and the slot taken, and each key's leaf entry count.  The one-launch
+// insert stages them in LDS with all its threads before its one wave plans.
+struct PlanRecs {
+    uint32_t pn[kMaxLevels][kFusedMax];
+    uint8_t pc[kMaxLevels][kFusedMax];
+    uint8_t pi[kMaxLevels][kFusedMax];
+    uint8_t ulc[kFusedMax];
+};
+
 // The plan's barrier: its workgroup's, or its wave's where one wave of a
 // larger workgroup plans alone (threads 0 .. 63, NT = 64).
 template <bool WAVE>
@@ -1358,8 +1369,8 @@ __device__ __forceinline__ void plan_sync() {
 // level's piece-offset prefix taken by the run's first and last keys.  Writes
 // the same item arrays and level counters as the general path, and then the
 // values of keys already present.
-template <class K, int NT, bool WAVE>
-__device__ __forceinline__ void ph_small_plan(TreeView<K> t, Ins<K> v, int H) {
+template <class K, int NT, bool WAVE, bool STAGED = false>
+__device__ __forceinline__ void ph_small_plan(TreeView<K> t, Ins<K> v, int H, const PlanRecs* rec = nullptr) {
     static_assert(!WAVE || NT == 64, "a plan by one wave has 64 threads");
     constexpr int kL = kMaxLevels;
     constexpr uint32_t kCap = 2 * NT;  // new keys, items per level
@@ -1408,8 +1419,13 @@ __device__ __forceinline__ void ph_small_plan(TreeView<K> t, Ins<K> v, int H) {
         valid[j] = r < R;
         nu[j] = valid[j] ? s_a[r] : 0u;
         node[j] = valid[j] ? s_b[r] : 0u;
-        cnt[j] = valid[j] ? v.ulc[nu[j]] : 0u;
-        cs[j] = valid[j] && h >= 2 ? v.pi[static_cast<uint64_t>(h - 2) * v.Bm + nu[j]] : 0u;
+        if constexpr (STAGED) {
+            cnt[j] = valid[j] ? rec->ulc[nu[j]] : 0u;
+            cs[j] = valid[j] && h >= 2 ? rec->pi[h - 2][nu[j]] : 0u;
+        } else {
+            cnt[j] = valid[j] ? v.ulc[nu[j]] : 0u;
+            cs[j] = valid[j] && h >= 2 ? v.pi[static_cast<uint64_t>(h - 2) * v.Bm + nu[j]] : 0u;
+        }
         ixp[j] = r;  // at the leaf level an item's range counts keys
     }
 
@@ -1429,10 +1445,16 @@ __device__ __forceinline__ void ph_small_plan(TreeView<K> t, Ins<K> v, int H) {
         // the next level's records, in flight through this level
         if (d + 1 < hmax)
             for (int j = 0; j < 2; ++j) {
-                const uint64_t at = static_cast<uint64_t>(h - 2 - d) * v.Bm + nu[j];
-                pnx[j] = valid[j] ? v.pn[at] : 0u;
-                pcx[j] = valid[j] ? v.pc[at] : 0u;
-                pix[j] = valid[j] && h - 3 - d >= 0 ? v.pi[at - v.Bm] : 0u;
+                if constexpr (STAGED) {
+                    pnx[j] = valid[j] ? rec->pn[h - 2 - d][nu[j]] : 0u;
+                    pcx[j] = valid[j] ? rec->pc[h - 2 - d][nu[j]] : 0u;
+                    pix[j] = valid[j] && h - 3 - d >= 0 ? rec->pi[h - 3 - d][nu[j]] : 0u;
+                } else {
+                    const uint64_t at = static_cast<uint64_t>(h - 2 - d) * v.Bm + nu[j];
+                    pnx[j] = valid[j] ? v.pn[at] : 0u;
+                    pcx[j] = valid[j] ? v.pc[at] : 0u;
+                    pix[j] = valid[j] && h - 3 - d >= 0 ? v.pi[at - v.Bm] : 0u;
+                }
             }
         uint32_t hd[2], ls[2];
         for (int j = 0; j < 2; ++j) {
@@ -1619,7 +1641,23 @@ __global__ __launch_bounds__(kFusedBlock) void k_ins_small(TreeView<K> t, Ins<K>
     __syncthreads();
     ph_locate<K, 16, 1, 2, kFusedBlock>(t, v, status);
     __syncthreads();
-    if (tid < 64) ph_small_plan<K, 64, true>(t, v, H);
+    // the plan's reads of locate's records, in one round by every thread (a
+    // wave alone would wait on a round of device memory per level)
+    __shared__ PlanRecs s_rec;
+    {
+        const uint32_t h = v.st->height, Ud = v.st->U;
+        const uint32_t nl = h >= 2 ? h - 1 : 0;  // levels 0 .. h-2
+        for (uint32_t i = tid; i < nl * Ud; i += kFusedBlock) {
+            const uint32_t l = i / Ud, u = i % Ud;
+            const uint64_t at = static_cast<uint64_t>(l) * v.Bm + u;
+            s_rec.pn[l][u] = v.pn[at];
+            s_rec.pc[l][u] = v.pc[at];
+            s_rec.pi[l][u] = v.pi[at];
+        }
+        if (tid < Ud) s_rec.ulc[tid] = v.ulc[tid];
+    }
+    __syncthreads();
+    if (tid < 64) ph_small_plan<K, 64, true, true>(t, v, H, &s_rec);
     __syncthreads();
     ph_small_apply<K>(t, v, H);
 }
