@@ -1337,21 +1337,13 @@ __device__ __forceinline__ uint32_t plan_scan(uint32_t x, uint32_t* sh, uint32_t
 // Locate's records of a batch of at most kFusedMax distinct keys, by tree
 // level l (0 = the leaves' parents) and key: the parent, its entry count
 // and the slot taken, and each key's leaf entry count.  The one-launch
-// insert stages them in LDS with all its threads before its one wave plans.
+// insert stages them in LDS with all its threads before it plans.
 struct PlanRecs {
     uint32_t pn[kMaxLevels][kFusedMax];
     uint8_t pc[kMaxLevels][kFusedMax];
     uint8_t pi[kMaxLevels][kFusedMax];
     uint8_t ulc[kFusedMax];
 };
-
-// The plan's barrier: its workgroup's, or its wave's where one wave of a
-// larger workgroup plans alone (threads 0 .. 63, NT = 64).
-template <bool WAVE>
-__device__ __forceinline__ void plan_sync() {
-    if constexpr (WAVE) wave_sync();
-    else __syncthreads();
-}
 
 // Plan of a small batch, one workgroup of NT threads (NT >= B / 2); thread t
 // owns new keys 2t and 2t+1.  Small NT keeps the barriers cheap (one wave
@@ -1369,9 +1361,8 @@ __device__ __forceinline__ void plan_sync() {
 // level's piece-offset prefix taken by the run's first and last keys.  Writes
 // the same item arrays and level counters as the general path, and then the
 // values of keys already present.
-template <class K, int NT, bool WAVE, bool STAGED = false>
-__device__ __forceinline__ void ph_small_plan(TreeView<K> t, Ins<K> v, int H, const PlanRecs* rec = nullptr) {
-    static_assert(!WAVE || NT == 64, "a plan by one wave has 64 threads");
+template <class K, int NT>
+__device__ __forceinline__ void ph_small_plan(TreeView<K> t, Ins<K> v, int H) {
     constexpr int kL = kMaxLevels;
     constexpr uint32_t kCap = 2 * NT;  // new keys, items per level
     __shared__ uint32_t sh[33];
@@ -1384,7 +1375,7 @@ __device__ __forceinline__ void ph_small_plan(TreeView<K> t, Ins<K> v, int H, co
     __shared__ InsState s_st;  // the batch state, written back at the end
     const uint32_t tid = threadIdx.x;
     copy_state(&s_st, v.st, tid, NT);
-    plan_sync<WAVE>();
+    __syncthreads();
     const uint32_t U = s_st.U;
     const int h = static_cast<int>(s_st.height);
     const int hmax = H < h ? H : h;
@@ -1409,7 +1400,7 @@ __device__ __forceinline__ void ph_small_plan(TreeView<K> t, Ins<K> v, int H, co
         s_a[r] = u;
         s_b[r] = leaf;
     }
-    plan_sync<WAVE>();
+    __syncthreads();
     bool valid[2];
     // per key and level: node, its old entry count and its slot in its
     // parent (all recorded by locate), the next level's loaded one level ahead
@@ -1419,13 +1410,8 @@ __device__ __forceinline__ void ph_small_plan(TreeView<K> t, Ins<K> v, int H, co
         valid[j] = r < R;
         nu[j] = valid[j] ? s_a[r] : 0u;
         node[j] = valid[j] ? s_b[r] : 0u;
-        if constexpr (STAGED) {
-            cnt[j] = valid[j] ? rec->ulc[nu[j]] : 0u;
-            cs[j] = valid[j] && h >= 2 ? rec->pi[h - 2][nu[j]] : 0u;
-        } else {
-            cnt[j] = valid[j] ? v.ulc[nu[j]] : 0u;
-            cs[j] = valid[j] && h >= 2 ? v.pi[static_cast<uint64_t>(h - 2) * v.Bm + nu[j]] : 0u;
-        }
+        cnt[j] = valid[j] ? v.ulc[nu[j]] : 0u;
+        cs[j] = valid[j] && h >= 2 ? v.pi[static_cast<uint64_t>(h - 2) * v.Bm + nu[j]] : 0u;
         ixp[j] = r;  // at the leaf level an item's range counts keys
     }
 
@@ -1440,21 +1426,15 @@ __device__ __forceinline__ void ph_small_plan(TreeView<K> t, Ins<K> v, int H, co
                 cs[j] = pix[j];
                 if (valid[j]) s_b[2 * tid + j] = node[j];
             }
-            plan_sync<WAVE>();
+            __syncthreads();
         }
         // the next level's records, in flight through this level
         if (d + 1 < hmax)
             for (int j = 0; j < 2; ++j) {
-                if constexpr (STAGED) {
-                    pnx[j] = valid[j] ? rec->pn[h - 2 - d][nu[j]] : 0u;
-                    pcx[j] = valid[j] ? rec->pc[h - 2 - d][nu[j]] : 0u;
-                    pix[j] = valid[j] && h - 3 - d >= 0 ? rec->pi[h - 3 - d][nu[j]] : 0u;
-                } else {
-                    const uint64_t at = static_cast<uint64_t>(h - 2 - d) * v.Bm + nu[j];
-                    pnx[j] = valid[j] ? v.pn[at] : 0u;
-                    pcx[j] = valid[j] ? v.pc[at] : 0u;
-                    pix[j] = valid[j] && h - 3 - d >= 0 ? v.pi[at - v.Bm] : 0u;
-                }
+                const uint64_t at = static_cast<uint64_t>(h - 2 - d) * v.Bm + nu[j];
+                pnx[j] = valid[j] ? v.pn[at] : 0u;
+                pcx[j] = valid[j] ? v.pc[at] : 0u;
+                pix[j] = valid[j] && h - 3 - d >= 0 ? v.pi[at - v.Bm] : 0u;
             }
         uint32_t hd[2], ls[2];
         for (int j = 0; j < 2; ++j) {
@@ -1488,10 +1468,10 @@ __device__ __forceinline__ void ph_small_plan(TreeView<K> t, Ins<K> v, int H, co
         }
         if (tid == 0) s_base[d] = items;
         items += n;
-        plan_sync<WAVE>();  // s_b is rewritten by the next level
+        __syncthreads();  // s_b is rewritten by the next level
     }
     if (tid == 0) s_base[hmax] = items;
-    plan_sync<WAVE>();
+    __syncthreads();
 
     const uint32_t total = items < v.ip_cap ? items : static_cast<uint32_t>(v.ip_cap);
 
@@ -1521,7 +1501,7 @@ __device__ __forceinline__ void ph_small_plan(TreeView<K> t, Ins<K> v, int H, co
             if ((lbits >> (2 * d + j)) & 1u) s_b[ixd[j]] = e[j];
             below[j] = ixd[j];
         }
-        plan_sync<WAVE>();
+        __syncthreads();
         uint32_t kk[2], f[2];
         for (int i = 0; i < 2; ++i) {
             const uint32_t jt = 2 * tid + i;
@@ -1551,18 +1531,18 @@ __device__ __forceinline__ void ph_small_plan(TreeView<K> t, Ins<K> v, int H, co
             s_st.lvl_psep[d] = psep;
         }
         psep += nnew;
-        plan_sync<WAVE>();
+        __syncthreads();
     }
     if (tid == 0) {
         s_st.R = R;
         if (s_over) s_st.overflow = 1;
     }
-    plan_sync<WAVE>();
+    __syncthreads();
     // the check reads the level counters one after another: from LDS
     Ins<K> vs = v;
     vs.st = &s_st;
     ph_check<K>(t, vs, tid, NT);
-    plan_sync<WAVE>();
+    __syncthreads();
     copy_state(v.st, &s_st, tid, NT);
     // values of keys already present (the batch passed the capacity check;
     // the leaf rewrites that follow read these values)
@@ -1586,15 +1566,175 @@ __device__ __forceinline__ void ph_small_plan(TreeView<K> t, Ins<K> v, int H, co
 
 template <class K, int NT>
 __global__ __launch_bounds__(NT) void k_small_plan(TreeView<K> t, Ins<K> v, int H) {
-    ph_small_plan<K, NT, false>(t, v, H);
+    ph_small_plan<K, NT>(t, v, H);
+}
+
+// The plan of a one-launch insert (at most kFusedMax distinct keys, one per
+// lane of a wave), by the whole workgroup.  The items of every level are cut
+// at once, one wave per level: a level's run heads and each key's item index
+// (a wave scan over the heads) depend only on that level's nodes, which
+// locate recorded (staged in LDS in `rec`).  The item arrays follow once the
+// level bases are known; then one wave takes the piece counts level after
+// level (each level's offsets need the level below), the capacity check and
+// the values of present keys, as the small path's plan does, with the same
+// item arrays and level counters.
+template <class K>
+__device__ __forceinline__ void ph_fused_plan(TreeView<K> t, Ins<K> v, int H, const PlanRecs& rec) {
+    constexpr int kL = kMaxLevels;
+    constexpr uint32_t kCap = kFusedMax;
+    static_assert(kFusedBlock / 64 >= kL, "a wave per level");
+    __shared__ uint32_t s_nu[kCap], s_leaf[kCap];  // new key -> distinct key, leaf
+    __shared__ uint8_t s_ix[kL][kCap];              // item index of each new key, per level
+    __shared__ uint32_t s_n[kL], s_base[kL + 1];    // items per level, first item of each level
+    __shared__ uint32_t s_lo[kCap], s_hi[kCap];     // a level's item bounds in the level below's prefix
+    __shared__ uint32_t s_k[kCap + 1];              // piece-offset prefix of the level below
+    __shared__ uint8_t s_C[kL * kCap];              // old entry count of every item
+    __shared__ uint32_t s_R, s_over;
+    __shared__ InsState s_st;                       // the batch state, written back at the end
+    const uint32_t tid = threadIdx.x, lane = tid % 64, w = tid / 64;
+    copy_state(&s_st, v.st, tid, kFusedBlock);
+    __syncthreads();
+    const uint32_t U = s_st.U;
+    const int h = static_cast<int>(s_st.height);
+    const int hmax = H < h ? H : h;
+
+    // new keys in key order (locate left f0[u] = 1 for a key not in its leaf)
+    if (w == 0) {
+        const uint32_t u = lane;
+        const uint32_t f = u < U ? v.f0[u] : 0u;
+        const uint32_t inc = wave_incl_scan(f);
+        if (f) {
+            const uint32_t r = inc - 1u, leaf = v.uleaf[u];
+            v.nk[r] = v.uk[u];
+            v.nv[r] = v.uv[u];
+            v.nleaf[r] = leaf;
+            v.nu[r] = u;
+            s_nu[r] = u;
+            s_leaf[r] = leaf;
+        }
+        if (lane == 63) {
+            s_R = inc;
+            s_over = 0;
+        }
+    }
+    __syncthreads();
+    const uint32_t R = s_R;
+
+    // each level's items: run heads and ends, item index per key (wave d)
+    const int d = static_cast<int>(w);
+    const uint32_t r = lane;
+    const bool valid = d < hmax && r < R;
+    const uint32_t nu = valid ? s_nu[r] : 0u;
+    auto node_at = [&](uint32_t x) { return d == 0 ? s_leaf[x] : rec.pn[h - 1 - d][s_nu[x]]; };
+    uint32_t node = 0, hd = 0, ls = 0;
+    if (valid) {
+        node = node_at(r);
+        hd = (r == 0 || node_at(r - 1) != node) ? 1u : 0u;
+        ls = (r + 1 == R || node_at(r + 1) != node) ? 1u : 0u;
+    }
+    uint32_t ix = 0;
+    if (d < hmax) {
+        const uint32_t inc = wave_incl_scan(hd);
+        ix = inc - 1u;
+        if (valid) s_ix[d][r] = static_cast<uint8_t>(ix);
+        if (lane == 63) s_n[d] = inc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t items = 0;
+        for (int l = 0; l < hmax; ++l) {
+            s_base[l] = items;
+            items += s_n[l];
+        }
+        s_base[hmax] = items;
+    }
+    __syncthreads();
+    // the item arrays: node, representative key, range of child items (keys
+    // at the leaves), old entry count, slot in the parent
+    if (valid) {
+        const uint64_t e = static_cast<uint64_t>(s_base[d]) + ix;
+        const uint32_t ixp = d == 0 ? r : s_ix[d - 1][r];
+        if (hd) {
+            if (e < v.ip_cap) {
+                const uint32_t cnt = d == 0 ? rec.ulc[nu] : rec.pc[h - 1 - d][nu];
+                const uint32_t cs = h - 2 - d >= 0 ? rec.pi[h - 2 - d][nu] : 0u;
+                v.it_node[e] = node;
+                v.it_rep[e] = nu;
+                v.it_first[e] = ixp;
+                v.it_cold[e] = cnt;
+                v.it_cs[e] = static_cast<uint8_t>(cs);
+                s_C[e] = static_cast<uint8_t>(cnt);
+            } else {
+                s_over = 1;
+            }
+        }
+        if (ls && e < v.ip_cap) v.it_end[e] = ixp + 1u;
+    }
+    __syncthreads();
+    if (w != 0) return;
+
+    // piece counts, level after level (one key and one item per lane): an
+    // item gains its run's key count (leaves) or sum(k - 1) over its child
+    // items, a difference of the level below's piece-offset prefix taken by
+    // the run's first and last keys
+    const uint32_t total_items = s_base[hmax];
+    const uint32_t total = total_items < v.ip_cap ? total_items : static_cast<uint32_t>(v.ip_cap);
+    const bool kv = r < R;
+    uint32_t psep = 0, below = 0;
+#pragma unroll 1
+    for (int l = 0; l < hmax; ++l) {
+        const uint32_t bd = s_base[l], nd = s_base[l + 1] - bd;
+        const uint32_t ixl = kv ? s_ix[l][r] : 0u;
+        const uint32_t lo = l == 0 ? r : s_k[below], hi = l == 0 ? r + 1 : s_k[below + 1];
+        const bool head = kv && (r == 0 || s_ix[l][r - 1] != ixl);
+        const bool end = kv && (r + 1 == R || s_ix[l][r + 1] != ixl);
+        if (head) s_lo[ixl] = lo;
+        if (end) s_hi[ixl] = hi;
+        below = ixl;
+        wave_sync();
+        const uint32_t jt = lane;
+        const bool in = jt < nd && bd + jt < total;
+        const uint32_t C = s_C[in ? bd + jt : 0u], ih = s_hi[in ? jt : 0u], il = s_lo[in ? jt : 0u];
+        const uint32_t kk = in ? split_pieces(static_cast<uint64_t>(C) + (ih - il)) : 1u;
+        const uint32_t f = in ? kk - 1u : 0u;
+        const uint32_t inc = wave_incl_scan(f);
+        const uint32_t nnew = __shfl(inc, 63, 64), o = inc - f;
+        if (jt < nd) s_k[jt] = o;
+        if (in) {
+            v.it_k[bd + jt] = kk;
+            v.it_off[bd + jt] = o;
+        }
+        if (lane == 0) {
+            s_k[nd] = nnew;
+            s_st.lvl_count[l] = nd;
+            s_st.lvl_base[l] = bd;
+            s_st.lvl_new[l] = nnew;
+            s_st.lvl_psep[l] = psep;
+        }
+        psep += nnew;
+        wave_sync();
+    }
+    if (lane == 0) {
+        s_st.R = R;
+        if (s_over) s_st.overflow = 1;
+    }
+    wave_sync();
+    Ins<K> vs = v;
+    vs.st = &s_st;
+    ph_check<K>(t, vs, lane, 64);
+    wave_sync();
+    copy_state(v.st, &s_st, lane, 64);
+    // values of keys already present (one per lane, read before written)
+    if (s_st.ok && lane < U && v.ufound[lane])
+        t.lvals[static_cast<uint64_t>(v.uleaf[lane]) * kSlots + v.uslot[lane]] = v.uv[lane];
 }
 
 // A batch of at most kFusedMax keys in one launch: the small path's kernels
 // (rank and distinct keys, locate, plan, apply) as phases of one
 // kFusedBlock-thread workgroup, with barriers where the small path has
 // kernel boundaries.  The batch is ranked in LDS (by key, then by position,
-// as the small path ranks it) and one wave plans it (the small path plans up
-// to 128 keys with one wave), so the tree it leaves is the small path's.
+// as the small path ranks it) and planned with the small path's item arrays
+// and counters (ph_fused_plan), so the tree it leaves is the small path's.
 template <class K>
 __global__ __launch_bounds__(kFusedBlock) void k_ins_small(TreeView<K> t, Ins<K> v, const K* __restrict__ keys,
                                                            const K* __restrict__ vals, uint32_t B,
@@ -1641,8 +1781,7 @@ __global__ __launch_bounds__(kFusedBlock) void k_ins_small(TreeView<K> t, Ins<K>
     __syncthreads();
     ph_locate<K, 16, 1, 2, kFusedBlock>(t, v, status);
     __syncthreads();
-    // the plan's reads of locate's records, in one round by every thread (a
-    // wave alone would wait on a round of device memory per level)
+    // the plan's reads of locate's records, in one round by every thread
     __shared__ PlanRecs s_rec;
     {
         const uint32_t h = v.st->height, Ud = v.st->U;
@@ -1657,7 +1796,7 @@ __global__ __launch_bounds__(kFusedBlock) void k_ins_small(TreeView<K> t, Ins<K>
         if (tid < Ud) s_rec.ulc[tid] = v.ulc[tid];
     }
     __syncthreads();
-    if (tid < 64) ph_small_plan<K, 64, true, true>(t, v, H, &s_rec);
+    ph_fused_plan<K>(t, v, H, s_rec);
     __syncthreads();
     ph_small_apply<K>(t, v, H);
 }
