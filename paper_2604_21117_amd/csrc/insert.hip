@@ -913,8 +913,8 @@ constexpr uint32_t kFusedItems = kFusedMax * kMaxLevels;
 
 // Besides the items, two things stay on the chip, so that a level waits on
 // fewer rounds of device memory:
-//  - the batch state (per-level counts, bases, allocation cursors), which the
-//    rebuilds only read: from device memory each level would wait on its
+//  - the batch state (per-level counts, bases, allocation cursors): from
+//    device memory each level, the growth and the commit would wait on its
 //    fields one read after another;
 //  - the separators a level's splits produce (read by the level above and by
 //    the root growth): a level adds at most one piece per new key below it,
@@ -955,7 +955,9 @@ __device__ __forceinline__ void ph_small_apply(TreeView<K> t, Ins<K> v0, int H) 
         return;
     }
     const ItemView iv{s_node, s_first, s_end, s_cold, s_k, s_off, s_cs};
-    Ins<K> vr = v;  // the rebuilds read the state's copy
+    // every phase below works on the state's copy (the growth and the
+    // commit write only fields that no later kernel reads)
+    Ins<K> vr = v;
     vr.st = &s_st;
     apply_leaves_body<K>(t, vr, grp, ngrp, iv);
     __syncthreads();
@@ -964,11 +966,11 @@ __device__ __forceinline__ void ph_small_apply(TreeView<K> t, Ins<K> v0, int H) 
         apply_inner_body<K>(t, vr, d, grp, ngrp, iv);
         __syncthreads();
     }
-    grow_body<K>(t, v);
+    grow_body<K>(t, vr);
     __syncthreads();
-    if (threadIdx.x == 0) ph_commit<K>(t, v);
+    if (threadIdx.x == 0) ph_commit<K>(t, vr);
     __syncthreads();
-    if (v.st->mirror_dirty) mirror_refresh_body<K, kFusedBlock>(t);
+    if (s_st.mirror_dirty) mirror_refresh_body<K, kFusedBlock>(t);
 }
 
 template <class K>
