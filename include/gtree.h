@@ -255,8 +255,11 @@ gt_status tree_insert_batch(gt_tree* t, const void* keys, const void* values, ui
  * later inserts (the pools only grow until the next tree_build).  Like an
  * insert, a batch is not applied while the device error word holds
  * GT_DEVERR_INTERNAL.  keys: B keys; status_out: B bytes; B <= max_batch.
- * Synchronises the stream once, to learn whether a rebuild is needed; the
- * rebuild allocates and frees temporary device memory.  A learned index
+ * Waits once on the host, to learn whether a rebuild is needed: up to 64
+ * keys for the flag the batch's kernel stores into pinned host memory (the
+ * kernel may still be finishing its last writes when the call returns;
+ * later work on `stream` is ordered after it), above that for the stream.
+ * The rebuild allocates and frees temporary device memory.  A learned index
  * over the tree answers through the tree after a delete until li_train.
  */
 gt_status tree_delete_batch(gt_tree* t, const void* keys, uint64_t B, uint8_t* status_out, hipStream_t stream);
@@ -461,7 +464,7 @@ enum { GT_REQ_QUEUED = 0, GT_REQ_INFLIGHT = 1, GT_REQ_DONE = 2, GT_REQ_REFUSED =
  * max_out -> out0 (keys), out1 (values) in CSR order of max_out, count_out;
  * delete: keys -> out0 (status, u8).  Inserts and deletes are writes: each
  * sees every batch admitted before it.  A delete batch runs outside the
- * captured graphs (tree_delete_batch synchronises). */
+ * captured graphs (tree_delete_batch waits on the host). */
 typedef struct {
     uint32_t op;
     uint32_t B;

@@ -59,8 +59,10 @@ struct gt_tree {
                             // after an insert, the most the pool sizes allow)
     uint64_t inserts = 0;   // insert batches enqueued on this tree
     uint64_t deletes = 0;   // delete batches applied to this tree
-    uint32_t* h_flag = nullptr;  // pinned host word a delete reads its rebuild flag into
-    uint32_t* d_flag = nullptr;  // the same word's device address
+    // pinned host word a delete reads its rebuild flag into (low half), with
+    // the number of the delete call that stored it (high half)
+    uint64_t* h_flag = nullptr;
+    uint64_t* d_flag = nullptr;  // the same word's device address
     gt::WideTree* wide = nullptr;  // set for a tree of 32-byte keys or order 32/64:
                                    // static, searched by wide.hip; the fields
                                    // above are then unused

@@ -2523,7 +2523,7 @@ __device__ __forceinline__ void phase_boundary() {
 template <class K>
 __global__ __launch_bounds__(kDelOneBlock) void k_del_small(TreeView<K> t, Ins<K> v, const K* __restrict__ keys,
                                                             uint32_t B, uint8_t* __restrict__ status,
-                                                            uint32_t* host_flag) {
+                                                            uint64_t* host_word, uint32_t seq) {
     __shared__ K s_rk[kDelFusedMax];
     __shared__ K s_sk[kDelFusedMax];
     __shared__ uint32_t s_si[kDelFusedMax];
@@ -2574,10 +2574,13 @@ __global__ __launch_bounds__(kDelOneBlock) void k_del_small(TreeView<K> t, Ins<K
     ph_del_merge2<K>(t, v);
     phase_boundary();
     ph_del_commit<K, kDelOneBlock>(t, v);
-    // the rebuild flag straight into host memory (the merges that raise it
-    // are behind the barriers above)
-    if (host_flag && tid == 0)
-        __hip_atomic_store(host_flag, counter(&v.st->rebuild), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    // the call's number and the rebuild flag, in one word, straight into
+    // host memory (the merges that raise the flag are behind the barriers
+    // above): the host waits for this word rather than for the stream
+    if (host_word && tid == 0) {
+        const uint64_t w = (static_cast<uint64_t>(seq) << 32) | (counter(&v.st->rebuild) ? 1u : 0u);
+        __hip_atomic_store(host_word, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 static std::atomic<int> g_one_launch_delete{1};
@@ -2602,7 +2605,7 @@ __global__ void k_del_collect(TreeView<K> t, uint32_t leaves, K* __restrict__ ok
 
 template <class K>
 const uint32_t* launch_delete(const TreeView<K>& t, const InsertCtx& c, const K* keys, uint64_t B, uint8_t* status,
-                              uint32_t* host_flag, bool* flag_on_host, hipStream_t s) {
+                              uint64_t* host_word, uint32_t seq, bool* flag_on_host, hipStream_t s) {
     *flag_on_host = false;
     Ins<K> v;
     carve<K>(&v, c.scratch, c.max_batch, c.leaf_cap, c.inner_cap);
@@ -2610,8 +2613,8 @@ const uint32_t* launch_delete(const TreeView<K>& t, const InsertCtx& c, const K*
     if (B <= kDelFusedMax && one_launch_delete_on()) {
         const uint32_t lds = MirrorLayout<K>::bytes(mirror_nodes_for_levels(2));
         hipLaunchKernelGGL(k_del_small<K>, dim3(1), dim3(kDelOneBlock), lds, s, t, v, keys,
-                           static_cast<uint32_t>(B), status, host_flag);
-        *flag_on_host = host_flag != nullptr;
+                           static_cast<uint32_t>(B), status, host_word, seq);
+        *flag_on_host = host_word != nullptr;
         return &v.st->rebuild;
     }
     if (B <= kSmallInsert) {
@@ -2651,9 +2654,9 @@ void launch_delete_collect(const TreeView<K>& t, uint32_t leaves, K* ok, K* ov, 
 }
 
 template const uint32_t* launch_delete<uint32_t>(const TreeView<uint32_t>&, const InsertCtx&, const uint32_t*,
-                                                 uint64_t, uint8_t*, uint32_t*, bool*, hipStream_t);
+                                                 uint64_t, uint8_t*, uint64_t*, uint32_t, bool*, hipStream_t);
 template const uint32_t* launch_delete<uint64_t>(const TreeView<uint64_t>&, const InsertCtx&, const uint64_t*,
-                                                 uint64_t, uint8_t*, uint32_t*, bool*, hipStream_t);
+                                                 uint64_t, uint8_t*, uint64_t*, uint32_t, bool*, hipStream_t);
 template void launch_delete_collect<uint32_t>(const TreeView<uint32_t>&, uint32_t, uint32_t*, uint32_t*, uint64_t,
                                               unsigned long long*, hipStream_t);
 template void launch_delete_collect<uint64_t>(const TreeView<uint64_t>&, uint32_t, uint64_t*, uint64_t*, uint64_t,

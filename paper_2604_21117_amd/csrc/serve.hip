@@ -276,7 +276,7 @@ hipError_t capture_ops(gt_server* s, Slot& sl, uint32_t op, uint32_t bucket, uin
 
 hipError_t launch(gt_server* s, Slot& sl, uint32_t op, uint32_t bucket, uint64_t outn, hipStream_t st) {
     const bool graphs = s->p.use_graphs != 2;
-    if (!graphs || op == GT_OP_DELETE) {  // a delete synchronises: never captured
+    if (!graphs || op == GT_OP_DELETE) {  // a delete waits on the host: never captured
         s->direct_launches++;
         return enqueue_ops(s, sl, op, bucket, outn, st, s->li);
     }

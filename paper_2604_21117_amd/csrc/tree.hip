@@ -437,23 +437,49 @@ gt_status tree_delete_batch(gt_tree* t, const void* keys, uint64_t B, uint8_t* s
     c.leaf_cap = t->leaf_cap;
     c.cfg = t->cfg;
     // pinned, so that the flag goes straight to host memory (the first call
-    // allocates it); a one-key batch's kernel stores it there itself
+    // allocates it); a one-launch batch's kernel stores it there itself
     if (!t->h_flag) {
         HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&t->h_flag), 64, hipHostMallocDefault));
+        *t->h_flag = 0;  // no call has answered yet (call numbers start at 1)
         if (hipHostGetDevicePointer(reinterpret_cast<void**>(&t->d_flag), t->h_flag, 0) != hipSuccess)
             t->d_flag = nullptr;
     }
     bool on_host = false;
+    const uint32_t seq = static_cast<uint32_t>(t->deletes + 1);
     const uint32_t* flag =
         t->kb == 8 ? launch_delete<uint64_t>(view<uint64_t>(t), c, reinterpret_cast<const uint64_t*>(keys), B,
-                                             status_out, t->d_flag, &on_host, stream)
+                                             status_out, t->d_flag, seq, &on_host, stream)
                    : launch_delete<uint32_t>(view<uint32_t>(t), c, reinterpret_cast<const uint32_t*>(keys), B,
-                                             status_out, t->d_flag, &on_host, stream);
+                                             status_out, t->d_flag, seq, &on_host, stream);
     HIP_TRY(hipGetLastError());
     t->deletes++;
-    if (!on_host) HIP_TRY(hipMemcpyAsync(t->h_flag, flag, 4, hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipStreamSynchronize(stream));
-    if (!*t->h_flag) return GT_OK;
+    bool rebuild;
+    if (on_host) {
+        // the kernel stores (seq << 32 | flag) into the pinned word as its
+        // answer: wait for that word, not for the stream (the stream's end
+        // is checked now and then, so that a kernel that never stores it
+        // cannot hold the call)
+        const volatile uint64_t* w = t->h_flag;
+        uint64_t got = 0;
+        for (uint32_t i = 1;; ++i) {
+            got = __atomic_load_n(w, __ATOMIC_ACQUIRE);
+            if (static_cast<uint32_t>(got >> 32) == seq) break;
+            if (i % 256 == 0) {
+                const hipError_t q = hipStreamQuery(stream);
+                if (q == hipErrorNotReady) continue;
+                if (q != hipSuccess) return GT_ERR_HIP;
+                got = __atomic_load_n(w, __ATOMIC_ACQUIRE);
+                if (static_cast<uint32_t>(got >> 32) != seq) return GT_ERR_HIP;
+                break;
+            }
+        }
+        rebuild = (got & 0xffffffffu) != 0;
+    } else {
+        HIP_TRY(hipMemcpyAsync(t->h_flag, flag, 4, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        rebuild = (*t->h_flag & 0xffffffffu) != 0;
+    }
+    if (!rebuild) return GT_OK;
     return t->kb == 8 ? delete_rebuild_t<uint64_t>(t, stream) : delete_rebuild_t<uint32_t>(t, stream);
 }
 
