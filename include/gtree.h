@@ -255,10 +255,10 @@ gt_status tree_insert_batch(gt_tree* t, const void* keys, const void* values, ui
  * later inserts (the pools only grow until the next tree_build).  Like an
  * insert, a batch is not applied while the device error word holds
  * GT_DEVERR_INTERNAL.  keys: B keys; status_out: B bytes; B <= max_batch.
- * Waits once on the host, to learn whether a rebuild is needed: up to 64
- * keys for the flag the batch's kernel stores into pinned host memory (the
- * kernel may still be finishing its last writes when the call returns;
- * later work on `stream` is ordered after it), above that for the stream.
+ * Waits once on the host, to learn whether a rebuild is needed: for the
+ * flag the batch's last kernel stores into pinned host memory (that kernel
+ * may still be finishing its last writes when the call returns; later work
+ * on `stream` is ordered after it).
  * The rebuild allocates and frees temporary device memory.  A learned index
  * over the tree answers through the tree after a delete until li_train.
  */

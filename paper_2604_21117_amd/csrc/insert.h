@@ -32,10 +32,10 @@ void launch_insert(const TreeView<K>& t, const InsertCtx& c, const K* keys, cons
 
 // Delete batch on the same scratch; returns the device word that is nonzero
 // when the tree must be rebuilt from its keys (read after the stream ends).
-// host_word (optional) is the device address of a pinned host word: a batch
-// of at most 64 keys (one launch) then also stores (seq << 32 | flag) there
-// itself, and *flag_on_host says so (the caller needs no copy and may wait
-// for that word instead of the stream).
+// host_word (optional) is the device address of a pinned host word: the
+// batch's last kernel then also stores (seq << 32 | flag) there itself, and
+// *flag_on_host says so (the caller needs no copy and may wait for that word
+// instead of the stream).
 template <class K>
 const uint32_t* launch_delete(const TreeView<K>& t, const InsertCtx& c, const K* keys, uint64_t B, uint8_t* status,
                               uint64_t* host_word, uint32_t seq, bool* flag_on_host, hipStream_t s);

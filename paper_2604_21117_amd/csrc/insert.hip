@@ -2498,8 +2498,14 @@ __device__ __forceinline__ void ph_del_commit(TreeView<K> t, Ins<K> v) {
 }
 
 template <class K>
-__global__ __launch_bounds__(256) void k_del_commit(TreeView<K> t, Ins<K> v) {
+__global__ __launch_bounds__(256) void k_del_commit(TreeView<K> t, Ins<K> v, uint64_t* host_word, uint32_t seq) {
     ph_del_commit<K, 256>(t, v);
+    // the call's number and the rebuild flag (raised by the merge kernels
+    // before this one), in one word, straight into host memory
+    if (host_word && threadIdx.x == 0) {
+        const uint64_t w = (static_cast<uint64_t>(seq) << 32) | (counter(&v.st->rebuild) ? 1u : 0u);
+        __hip_atomic_store(host_word, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 // A batch of at most kDelFusedMax keys in one launch: the batch path's
@@ -2642,7 +2648,8 @@ const uint32_t* launch_delete(const TreeView<K>& t, const InsertCtx& c, const K*
     const uint32_t gm = B < 16384 ? static_cast<uint32_t>(B) : 16384u;
     hipLaunchKernelGGL(k_del_merge<K>, dim3(gm), dim3(64), 0, s, t, v, ordered);
     hipLaunchKernelGGL(k_del_merge2<K>, dim3(B < 256 ? static_cast<uint32_t>(B) : 256u), dim3(1024), 0, s, t, v);
-    hipLaunchKernelGGL(k_del_commit<K>, dim3(1), dim3(256), 0, s, t, v);
+    hipLaunchKernelGGL(k_del_commit<K>, dim3(1), dim3(256), 0, s, t, v, host_word, seq);
+    *flag_on_host = host_word != nullptr;
     return &v.st->rebuild;
 }
 

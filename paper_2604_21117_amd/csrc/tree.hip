@@ -437,7 +437,7 @@ gt_status tree_delete_batch(gt_tree* t, const void* keys, uint64_t B, uint8_t* s
     c.leaf_cap = t->leaf_cap;
     c.cfg = t->cfg;
     // pinned, so that the flag goes straight to host memory (the first call
-    // allocates it); a one-launch batch's kernel stores it there itself
+    // allocates it); the batch's last kernel stores it there itself
     if (!t->h_flag) {
         HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&t->h_flag), 64, hipHostMallocDefault));
         *t->h_flag = 0;  // no call has answered yet (call numbers start at 1)
