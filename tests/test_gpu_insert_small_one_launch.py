@@ -127,3 +127,28 @@ def test_small_insert_capacity_refusal_matches_four_kernels():
     assert np.array_equal(_insert(g, b, kp, vp, False), want)
     assert np.array_equal(a.export(), b.export())
     assert_export_parity(a, sa)
+
+
+@pytest.mark.parametrize("width", [32, 64])
+def test_small_insert_batches_of_one_repeated_key(width):
+    """Degenerate batches: one key repeated 2..64 times (new, then present,
+    the edge keys 0 and the largest), all keys already present (updates
+    only), and a batch of 64 distinct keys inside one leaf's range."""
+    import paper_2604_21117_amd as g
+    seed = 71
+    keys = key_set(4096, width, seed, edges=True)
+    vals = synth.values_for(keys, seed, width)
+    sa = oracle.SortedArray(keys, vals, width)
+    a = mk_tree(keys, vals, width // 8, leaf_slack=4096, max_batch=64)
+    b = mk_tree(keys, vals, width // 8, leaf_slack=4096, max_batch=64)
+    top = np.iinfo(keys.dtype).max
+    fresh = synth.uniform_keys(8, seed + 3, width, purpose=synth.P_INSERT, exclude=keys)
+    batches = []
+    for k, n in ((fresh[0], 2), (fresh[1], 64), (fresh[1], 17), (keys[5], 33), (0, 64), (top, 64), (fresh[2], 3)):
+        batches.append(np.full(n, k, dtype=keys.dtype))
+    batches.append(keys[100:164].copy())
+    srt = np.sort(keys)
+    lo = int(srt[2000])
+    run = np.arange(lo + 1, lo + 65, dtype=np.uint64).astype(keys.dtype)
+    batches.append(run[~np.isin(run, keys)][:64])
+    _run_batches(g, a, b, sa, [x for x in batches if len(x) >= 2], width, seed, 1, "degenerate")
