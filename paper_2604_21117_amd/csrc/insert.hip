@@ -1731,6 +1731,23 @@ __device__ __forceinline__ void ph_fused_plan(TreeView<K> t, Ins<K> v, int H, co
         t.lvals[static_cast<uint64_t>(v.uleaf[lane]) * kSlots + v.uslot[lane]] = v.uv[lane];
 }
 
+// Stable rank of a[i] = k0 among a[0..n) in LDS (by key, then position):
+// eight reads in flight at a time, where one at a time waits out every
+// read's latency.
+template <class K>
+__device__ __forceinline__ uint32_t stable_rank(const K* a, uint32_t n, K k0, uint32_t i) {
+    uint32_t c = 0, j = 0;
+    for (; j + 8 <= n; j += 8) {
+        K x[8];
+#pragma unroll
+        for (uint32_t q = 0; q < 8; ++q) x[q] = a[j + q];
+#pragma unroll
+        for (uint32_t q = 0; q < 8; ++q) c += (x[q] < k0 || (x[q] == k0 && j + q < i)) ? 1u : 0u;
+    }
+    for (; j < n; ++j) c += (a[j] < k0 || (a[j] == k0 && j < i)) ? 1u : 0u;
+    return c;
+}
+
 // A batch of at most kFusedMax keys in one launch: the small path's kernels
 // (rank and distinct keys, locate, plan, apply) as phases of one
 // kFusedBlock-thread workgroup, with barriers where the small path has
@@ -1753,8 +1770,7 @@ __global__ __launch_bounds__(kFusedBlock) void k_ins_small(TreeView<K> t, Ins<K>
     // each key's stable rank in the batch
     if (tid < B) {
         const K k0 = s_rk[tid];
-        uint32_t c = 0;
-        for (uint32_t j = 0; j < B; ++j) c += (s_rk[j] < k0 || (s_rk[j] == k0 && j < tid)) ? 1u : 0u;
+        const uint32_t c = stable_rank(s_rk, B, k0, tid);
         s_sk[c] = k0;
         s_si[c] = tid;
     }
@@ -2543,8 +2559,7 @@ __global__ __launch_bounds__(kDelOneBlock) void k_del_small(TreeView<K> t, Ins<K
     // each key's stable rank in the batch
     if (tid < B) {
         const K k0 = s_rk[tid];
-        uint32_t c = 0;
-        for (uint32_t j = 0; j < B; ++j) c += (s_rk[j] < k0 || (s_rk[j] == k0 && j < tid)) ? 1u : 0u;
+        const uint32_t c = stable_rank(s_rk, B, k0, tid);
         s_sk[c] = k0;
         s_si[c] = tid;
     }

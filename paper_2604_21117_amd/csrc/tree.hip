@@ -5,6 +5,7 @@
 // checks its arguments on the host, then enqueues kernels on the caller's
 // stream without synchronising (tree_build, tree_stats, tree_export and
 // tree_device_error are the documented exceptions).
+#include <chrono>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -459,19 +460,25 @@ gt_status tree_delete_batch(gt_tree* t, const void* keys, uint64_t B, uint8_t* s
         // answer: wait for that word, not for the stream (the stream's end
         // is checked now and then, so that a kernel that never stores it
         // cannot hold the call)
+        // (the stream is asked at most every 50 us: a query takes the
+        // runtime's locks and costs more than the wait it checks)
         const volatile uint64_t* w = t->h_flag;
         uint64_t got = 0;
+        auto next = std::chrono::steady_clock::now() + std::chrono::microseconds(50);
         for (uint32_t i = 1;; ++i) {
             got = __atomic_load_n(w, __ATOMIC_ACQUIRE);
             if (static_cast<uint32_t>(got >> 32) == seq) break;
-            if (i % 256 == 0) {
-                const hipError_t q = hipStreamQuery(stream);
-                if (q == hipErrorNotReady) continue;
-                if (q != hipSuccess) return GT_ERR_HIP;
-                got = __atomic_load_n(w, __ATOMIC_ACQUIRE);
-                if (static_cast<uint32_t>(got >> 32) != seq) return GT_ERR_HIP;
-                break;
-            }
+            __builtin_ia32_pause();
+            if (i % 64 != 0) continue;
+            const auto now = std::chrono::steady_clock::now();
+            if (now < next) continue;
+            next = now + std::chrono::microseconds(50);
+            const hipError_t q = hipStreamQuery(stream);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) return GT_ERR_HIP;
+            got = __atomic_load_n(w, __ATOMIC_ACQUIRE);
+            if (static_cast<uint32_t>(got >> 32) != seq) return GT_ERR_HIP;
+            break;
         }
         rebuild = (got & 0xffffffffu) != 0;
     } else {
