@@ -1229,6 +1229,8 @@ static bool single_key_insert_on() { return g_single_key.load(std::memory_order_
 // level (k_small_plan), and up to kFusedMax keys one more workgroup applies
 // the whole batch (k_small_apply).  The results are those of the general
 // path: the same item arrays and level counters, the same apply bodies.
+// Batches of 2 to kFusedMax keys run all of it in one launch by default
+// (k_ins_small, below), with the same results.
 
 constexpr uint32_t kSmallInsert = 2048;
 static_assert(kSmallInsert <= kRankSortMax, "the small path sorts with rank_sort_small");
